@@ -1,0 +1,853 @@
+/*
+ * amr_oracle.c -- plain FP64 CPU oracle of one AMR hydro timestep.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the tests, the smoke entry
+ * point and the benchmark's CPU-baseline leg may load it.  It shares no code,
+ * header, table or constant generator with the HIP path; both follow the same
+ * written readings of the paper.
+ *
+ * What the paper fixes (Bordner & Norman, Sec. II-B and II-C):
+ *   - the mesh is an array of octrees; each octree node is a Block of N^3
+ *     cells; leaves carry the solution;
+ *   - before a Method runs on a Block its ghost layer of the stated width is
+ *     refreshed from neighbouring Blocks, with Restrict (fine -> coarse) and
+ *     Prolong (coarse -> fine) across refinement jumps;
+ *   - the hydro Method is a modified piecewise-parabolic method (PPM).
+ * Everything else is a reading, stated at the code that applies it:
+ *   R-order : every formula is evaluated exactly as parenthesised; only
+ *             + - * / sqrt and comparisons; max/min written as selects;
+ *             built with -ffp-contract=off (no fused multiply-add).
+ *   R-mesh  : cubic cells, dx_l = 1 / (Rx * N * 2^l); 2:1 balance across all
+ *             26 neighbour directions; ghost width 3.
+ *   R-order-of-refresh : phase 1 = same-level copies, restriction into
+ *             coarse ghosts, outflow clamps; phase 2 = prolongation into
+ *             fine ghosts (reads the coarse block's active + phase-1 cells).
+ *   R-split : one refresh per step; sweeps x,y,z on even steps, z,y,x on
+ *             odd; sweep s updates cells active along the axes swept so far
+ *             (including this one) and all cells along the others.
+ *   R-dt    : one dt per mesh per step from the CFL condition at step start.
+ *   R-reflux: coarse cells next to a coarse-fine face take the area mean of
+ *             the fine face fluxes, applied after the third sweep.
+ * The oracle is single-threaded in semantics; OpenMP only splits loops over
+ * blocks whose iterations are independent, so results do not depend on the
+ * thread count.
+ */
+#include "amr_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define G ORC_GHOST
+#define NF ORC_NFIELD
+
+enum { ABSENT = 0, LEAF = 1, REFINED = 2 };
+
+/* Published PPM flattening constants (Colella & Woodward 1984): shock
+ * detection threshold and the ramp of the flattening coefficient. */
+static const double EPS_S = 0.33, OMEGA1 = 0.75, OMEGA2 = 10.0;
+
+struct orc_mesh {
+  orc_desc d;
+  int N, M, nlev;
+  int ext[ORC_MAXLEV][3];
+  unsigned char* state[ORC_MAXLEV];
+  int32_t* leaf_at[ORC_MAXLEV];
+  int64_t nleaf;
+  int32_t* key;   /* (level, i, j, k) per leaf */
+  double* U;      /* nleaf * NF * M^3 */
+  double** face;  /* 6 per leaf: coarse-fine face flux buffers or NULL */
+  int64_t floors;
+};
+
+typedef struct {
+  double gamma, gm1, inv_gm1, g_gm1, g1, rho_floor, p_floor, sixth, two3;
+  int iters;
+} consts_t;
+
+static char g_err[256];
+const char* orc_last_error(void) { return g_err; }
+static int fail(const char* msg) {
+  snprintf(g_err, sizeof g_err, "%s", msg);
+  return -1;
+}
+
+/* Gas constants computed once in FP64, in the forms the formulas use. */
+static consts_t make_consts(double gamma, double rho_floor, double p_floor, int iters) {
+  consts_t K;
+  K.gamma = gamma;
+  K.gm1 = gamma - 1.0;
+  K.inv_gm1 = 1.0 / (gamma - 1.0);
+  K.g_gm1 = gamma / (gamma - 1.0);
+  K.g1 = (gamma + 1.0) / (2.0 * gamma);
+  K.rho_floor = rho_floor;
+  K.p_floor = p_floor;
+  K.sixth = 1.0 / 6.0;
+  K.two3 = 2.0 / 3.0;
+  K.iters = iters;
+  return K;
+}
+
+static inline double dmax(double a, double b) { return a < b ? b : a; }
+static inline double dmin(double a, double b) { return a < b ? a : b; }
+
+/* ------------------------------------------------------------------ */
+/* Mesh: dense per-level node state, 2:1 balance                       */
+/* ------------------------------------------------------------------ */
+
+static inline int64_t nidx(const orc_mesh* m, int l, int i, int j, int k) {
+  return ((int64_t)k * m->ext[l][1] + j) * m->ext[l][0] + i;
+}
+static inline int64_t cell(int M, int f, int a, int b, int c) {
+  return (((int64_t)f * M + c) * M + b) * M + a;
+}
+static inline double* block_ptr(const orc_mesh* m, int64_t leaf) {
+  return m->U + leaf * (int64_t)NF * m->M * m->M * m->M;
+}
+/* dx at level l: cubic cells, the x extent of the domain is 1. */
+static inline double dx_level(const orc_mesh* m, int l) {
+  return 1.0 / (double)((int64_t)m->d.root[0] * m->N << l);
+}
+
+static void refine_node(orc_mesh* m, int l, int i, int j, int k) {
+  m->state[l][nidx(m, l, i, j, k)] = REFINED;
+  for (int c = 0; c < 8; c++)
+    m->state[l + 1][nidx(m, l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2))] = LEAF;
+}
+
+/* Map a level-l block coordinate into the domain along axis ax: periodic
+ * axes wrap, outflow axes have no block outside.  Returns 0 if outside. */
+static int wrap_block(const orc_mesh* m, int l, int ax, int* v) {
+  int e = m->ext[l][ax];
+  if (*v >= 0 && *v < e) return 1;
+  if (m->d.bc[ax] != ORC_BC_PERIODIC) return 0;
+  *v = ((*v % e) + e) % e;
+  return 1;
+}
+
+/* Level of the leaf covering level-l block position p (or l if the node at
+ * level l exists, leaf or refined).  p is replaced by that node's position. */
+static int covering_level(const orc_mesh* m, int l, int p[3]) {
+  while (m->state[l][nidx(m, l, p[0], p[1], p[2])] == ABSENT) {
+    l--;
+    p[0] >>= 1; p[1] >>= 1; p[2] >>= 1;
+  }
+  return l;
+}
+
+/* 2:1 balance across faces, edges and corners: refine any leaf that is two
+ * or more levels coarser than a leaf it touches, until none is. */
+static void balance(orc_mesh* m) {
+  int changed = 1;
+  while (changed) {
+    changed = 0;
+    for (int l = 2; l < m->nlev; l++)
+      for (int k = 0; k < m->ext[l][2]; k++)
+        for (int j = 0; j < m->ext[l][1]; j++)
+          for (int i = 0; i < m->ext[l][0]; i++) {
+            if (m->state[l][nidx(m, l, i, j, k)] != LEAF) continue;
+            for (int dz = -1; dz <= 1; dz++)
+              for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                  if (!dx && !dy && !dz) continue;
+                  int p[3] = {i + dx, j + dy, k + dz};
+                  if (!wrap_block(m, l, 0, &p[0]) || !wrap_block(m, l, 1, &p[1]) ||
+                      !wrap_block(m, l, 2, &p[2]))
+                    continue;
+                  int lv = covering_level(m, l, p);
+                  if (l - lv >= 2) {
+                    refine_node(m, lv, p[0], p[1], p[2]);
+                    changed = 1;
+                  }
+                }
+          }
+  }
+}
+
+static int check_desc(const orc_desc* d) {
+  if (d->block_cells < 8 || d->block_cells % 2) return fail("block_cells must be even and >= 8");
+  if (d->max_level < 0 || d->max_level >= ORC_MAXLEV) return fail("max_level out of range");
+  for (int a = 0; a < 3; a++) {
+    if (d->root[a] < 1) return fail("root extent must be >= 1");
+    if (d->bc[a] != ORC_BC_PERIODIC && d->bc[a] != ORC_BC_OUTFLOW) return fail("bad bc");
+  }
+  if (!(d->gamma > 1.0)) return fail("gamma must exceed 1");
+  if (d->riemann_iters < 0) return fail("riemann_iters < 0");
+  return 0;
+}
+
+static orc_mesh* alloc_mesh(const orc_desc* d) {
+  orc_mesh* m = (orc_mesh*)calloc(1, sizeof(orc_mesh));
+  m->d = *d;
+  m->d.refine = NULL;
+  m->d.n_refine = 0;
+  m->N = d->block_cells;
+  m->M = m->N + 2 * G;
+  m->nlev = d->max_level + 1;
+  for (int l = 0; l < m->nlev; l++) {
+    for (int a = 0; a < 3; a++) m->ext[l][a] = d->root[a] << l;
+    int64_t n = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    m->state[l] = (unsigned char*)calloc((size_t)n, 1);
+    m->leaf_at[l] = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  }
+  return m;
+}
+
+void orc_destroy(orc_mesh* m) {
+  if (!m) return;
+  for (int l = 0; l < m->nlev; l++) {
+    free(m->state[l]);
+    free(m->leaf_at[l]);
+  }
+  if (m->face) {
+    for (int64_t s = 0; s < 6 * m->nleaf; s++) free(m->face[s]);
+    free(m->face);
+  }
+  free(m->key);
+  free(m->U);
+  free(m);
+}
+
+/* Number leaves (level, then z, y, x), allocate state and face buffers. */
+static int finish_mesh(orc_mesh* m) {
+  int64_t n = 0;
+  for (int l = 0; l < m->nlev; l++) {
+    int64_t cnt = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    for (int64_t q = 0; q < cnt; q++) {
+      m->leaf_at[l][q] = -1;
+      if (m->state[l][q] == LEAF) n++;
+    }
+  }
+  m->nleaf = n;
+  m->key = (int32_t*)malloc((size_t)(4 * n) * sizeof(int32_t));
+  n = 0;
+  int uniform = 1;
+  for (int l = 0; l < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++)
+          if (m->state[l][nidx(m, l, i, j, k)] == LEAF) {
+            m->leaf_at[l][nidx(m, l, i, j, k)] = (int32_t)n;
+            m->key[4 * n] = l; m->key[4 * n + 1] = i; m->key[4 * n + 2] = j; m->key[4 * n + 3] = k;
+            if (l) uniform = 0;
+            n++;
+          }
+  for (int a = 0; a < 3; a++)
+    if (m->d.bc[a] == ORC_BC_OUTFLOW && !uniform)
+      return fail("outflow boundaries are supported on single-level meshes only");
+  int64_t M3 = (int64_t)m->M * m->M * m->M;
+  m->U = (double*)calloc((size_t)(m->nleaf * NF * M3), sizeof(double));
+  if (!m->U) return fail("out of memory");
+  /* Coarse-fine faces: a face whose same-level neighbour position is refined
+   * (this leaf is the coarse side) or absent (this leaf is the fine side). */
+  m->face = (double**)calloc((size_t)(6 * m->nleaf), sizeof(double*));
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const int32_t* kk = m->key + 4 * s;
+    int l = kk[0];
+    for (int dir = 0; dir < 3; dir++)
+      for (int side = 0; side < 2; side++) {
+        int p[3] = {kk[1], kk[2], kk[3]};
+        p[dir] += side ? 1 : -1;
+        if (!wrap_block(m, l, dir, &p[dir])) continue;
+        unsigned char st = m->state[l][nidx(m, l, p[0], p[1], p[2])];
+        if (st != LEAF)
+          m->face[6 * s + 2 * dir + side] =
+              (double*)calloc((size_t)NF * m->N * m->N, sizeof(double));
+      }
+  }
+  return 0;
+}
+
+int orc_create(const orc_desc* d, orc_mesh** out) {
+  *out = NULL;
+  if (check_desc(d)) return -1;
+  orc_mesh* m = alloc_mesh(d);
+  for (int64_t q = 0; q < (int64_t)m->ext[0][0] * m->ext[0][1] * m->ext[0][2]; q++) m->state[0][q] = LEAF;
+  /* Static refinement list, applied in order; refining a node also refines
+   * any leaf ancestor first. */
+  for (int r = 0; r < d->n_refine; r++) {
+    const int32_t* e = d->refine + 4 * r;
+    int l = e[0];
+    if (l < 0 || l >= d->max_level) { orc_destroy(m); return fail("refine level out of range"); }
+    for (int a = 0; a < 3; a++)
+      if (e[1 + a] < 0 || e[1 + a] >= m->ext[l][a]) { orc_destroy(m); return fail("refine key out of range"); }
+    for (int a = 0; a <= l; a++) {
+      int s = l - a;
+      int i = e[1] >> s, j = e[2] >> s, k = e[3] >> s;
+      if (m->state[a][nidx(m, a, i, j, k)] == LEAF) refine_node(m, a, i, j, k);
+    }
+  }
+  balance(m);
+  if (finish_mesh(m)) { orc_destroy(m); return -1; }
+  *out = m;
+  return 0;
+}
+
+int orc_create_from_leaves(const orc_desc* d, int64_t n, const int32_t* keys, orc_mesh** out) {
+  *out = NULL;
+  if (check_desc(d)) return -1;
+  orc_mesh* m = alloc_mesh(d);
+  for (int64_t s = 0; s < n; s++) {
+    const int32_t* e = keys + 4 * s;
+    int l = e[0];
+    if (l < 0 || l > d->max_level) { orc_destroy(m); return fail("leaf level out of range"); }
+    for (int a = 0; a < 3; a++)
+      if (e[1 + a] < 0 || e[1 + a] >= m->ext[l][a]) { orc_destroy(m); return fail("leaf key out of range"); }
+    unsigned char* st = &m->state[l][nidx(m, l, e[1], e[2], e[3])];
+    if (*st != ABSENT) { orc_destroy(m); return fail("duplicate or overlapping leaf"); }
+    *st = LEAF;
+    for (int a = l - 1; a >= 0; a--) {
+      int s2 = l - a;
+      unsigned char* pa = &m->state[a][nidx(m, a, e[1] >> s2, e[2] >> s2, e[3] >> s2)];
+      if (*pa == LEAF) { orc_destroy(m); return fail("leaf inside another leaf"); }
+      *pa = REFINED;
+    }
+  }
+  /* Every root covered and every refined node has all eight children. */
+  for (int l = 0; l < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++) {
+          unsigned char st = m->state[l][nidx(m, l, i, j, k)];
+          if (l == 0 && st == ABSENT) { orc_destroy(m); return fail("root not covered"); }
+          if (st == REFINED) {
+            if (l + 1 >= m->nlev) { orc_destroy(m); return fail("refined node at max level"); }
+            for (int c = 0; c < 8; c++)
+              if (m->state[l + 1][nidx(m, l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2))] == ABSENT) {
+                orc_destroy(m);
+                return fail("leaves do not tile the domain");
+              }
+          }
+        }
+  /* 2:1 balance must already hold. */
+  for (int l = 2; l < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++) {
+          if (m->state[l][nidx(m, l, i, j, k)] != LEAF) continue;
+          for (int q = 0; q < 27; q++) {
+            if (q == 13) continue;
+            int p[3] = {i + q % 3 - 1, j + (q / 3) % 3 - 1, k + q / 9 - 1};
+            if (!wrap_block(m, l, 0, &p[0]) || !wrap_block(m, l, 1, &p[1]) || !wrap_block(m, l, 2, &p[2]))
+              continue;
+            if (l - covering_level(m, l, p) >= 2) { orc_destroy(m); return fail("leaves violate 2:1 balance"); }
+          }
+        }
+  if (finish_mesh(m)) { orc_destroy(m); return -1; }
+  *out = m;
+  return 0;
+}
+
+int64_t orc_nleaf(const orc_mesh* m) { return m->nleaf; }
+void orc_leaf_keys(const orc_mesh* m, int32_t* out) {
+  memcpy(out, m->key, (size_t)(4 * m->nleaf) * sizeof(int32_t));
+}
+double* orc_state(orc_mesh* m) { return m->U; }
+int64_t orc_floor_count(const orc_mesh* m) { return m->floors; }
+
+/* ------------------------------------------------------------------ */
+/* Ghost refresh (Sec. II-B: ghost layer of width 3 for all 5 fields)  */
+/* ------------------------------------------------------------------ */
+
+/* Boundary condition on a level-l global cell index along axis ax:
+ * periodic wraps, outflow clamps to the nearest domain cell. */
+static int64_t bc_cell(const orc_mesh* m, int l, int ax, int64_t p) {
+  int64_t n = (int64_t)m->ext[l][ax] * m->N;
+  if (p >= 0 && p < n) return p;
+  if (m->d.bc[ax] == ORC_BC_PERIODIC) return ((p % n) + n) % n;
+  return p < 0 ? 0 : n - 1;
+}
+
+static inline int is_active(int N, int a, int b, int c) {
+  return a >= G && a < G + N && b >= G && b < G + N && c >= G && c < G + N;
+}
+
+/* Value of the cell at level-l global index q inside the leaf that holds it
+ * (q's block must be a leaf at level l). */
+static inline double leaf_value(const orc_mesh* m, int l, const int64_t q[3], int f) {
+  int N = m->N;
+  int bx = (int)(q[0] / N), by = (int)(q[1] / N), bz = (int)(q[2] / N);
+  int32_t s = m->leaf_at[l][nidx(m, l, bx, by, bz)];
+  const double* B = block_ptr(m, s);
+  return B[cell(m->M, f, (int)(q[0] - (int64_t)bx * N) + G, (int)(q[1] - (int64_t)by * N) + G,
+                (int)(q[2] - (int64_t)bz * N) + G)];
+}
+
+/* Restrict (Sec. II-B): the coarse value is the mean of its 8 children,
+ * summed pairwise in the fixed order x fastest, then y, then z. */
+static double restrict8(const double v[8]) {
+  return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125;
+}
+
+/* minmod(a,b): the smaller-magnitude argument if both have the same sign,
+ * else 0 (ties take b). */
+static inline double minmod(double a, double b) {
+  return (a * b > 0.0) ? (fabs(a) < fabs(b) ? a : b) : 0.0;
+}
+
+static void refresh_phase(orc_mesh* m, int phase) {
+  const int N = m->N, M = m->M;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const int32_t* kk = m->key + 4 * s;
+    const int l = kk[0];
+    double* B = block_ptr(m, s);
+    for (int c = 0; c < M; c++)
+      for (int b = 0; b < M; b++)
+        for (int a = 0; a < M; a++) {
+          if (is_active(N, a, b, c)) continue;
+          int64_t p[3] = {(int64_t)kk[1] * N + a - G, (int64_t)kk[2] * N + b - G, (int64_t)kk[3] * N + c - G};
+          for (int ax = 0; ax < 3; ax++) p[ax] = bc_cell(m, l, ax, p[ax]);
+          int bp[3] = {(int)(p[0] / N), (int)(p[1] / N), (int)(p[2] / N)};
+          unsigned char st = m->state[l][nidx(m, l, bp[0], bp[1], bp[2])];
+          if (phase == 1 && st == LEAF) {
+            for (int f = 0; f < NF; f++) B[cell(M, f, a, b, c)] = leaf_value(m, l, p, f);
+          } else if (phase == 1 && st == REFINED) {
+            for (int f = 0; f < NF; f++) {
+              double v[8];
+              for (int o = 0; o < 8; o++) {
+                int64_t q[3] = {2 * p[0] + (o & 1), 2 * p[1] + ((o >> 1) & 1), 2 * p[2] + (o >> 2)};
+                v[o] = leaf_value(m, l + 1, q, f);
+              }
+              B[cell(M, f, a, b, c)] = restrict8(v);
+            }
+          } else if (phase == 2 && st == ABSENT) {
+            /* Prolong (Sec. II-B): parent value plus limited slopes times the
+             * octant offsets, U_f = ((U_P + 0.25 o_x s_x) + 0.25 o_y s_y)
+             * + 0.25 o_z s_z, s_d = minmod(U_{P+e_d} - U_P, U_P - U_{P-e_d}),
+             * read from the coarse leaf's active and phase-1 ghost cells. */
+            int64_t pc[3] = {p[0] >> 1, p[1] >> 1, p[2] >> 1};
+            int cb[3] = {(int)(pc[0] / N), (int)(pc[1] / N), (int)(pc[2] / N)};
+            int32_t sc = m->leaf_at[l - 1][nidx(m, l - 1, cb[0], cb[1], cb[2])];
+            const double* C = block_ptr(m, sc);
+            int lc[3];
+            double o[3];
+            for (int ax = 0; ax < 3; ax++) {
+              lc[ax] = (int)(pc[ax] - (int64_t)cb[ax] * N) + G;
+              o[ax] = (p[ax] & 1) ? 1.0 : -1.0;
+            }
+            for (int f = 0; f < NF; f++) {
+              double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
+              double sl[3];
+              sl[0] = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
+              sl[1] = minmod(C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - u0, u0 - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
+              sl[2] = minmod(C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - u0, u0 - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
+              B[cell(M, f, a, b, c)] =
+                  ((u0 + (0.25 * o[0]) * sl[0]) + (0.25 * o[1]) * sl[1]) + (0.25 * o[2]) * sl[2];
+            }
+          }
+        }
+  }
+}
+
+void orc_refresh(orc_mesh* m) {
+  refresh_phase(m, 1);
+  refresh_phase(m, 2);
+}
+
+/* ------------------------------------------------------------------ */
+/* CFL time step                                                        */
+/* ------------------------------------------------------------------ */
+
+/* dt = C_cfl * min over active leaf cells of dx_l / (max_d |u_d| + c); the
+ * min over d of dx/(|u_d|+c) equals this because correctly rounded + and /
+ * are monotone.  Primitive recovery as in the sweeps, x,y,z order. */
+double orc_cfl_dt(const orc_mesh* m) {
+  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  const int N = m->N, M = m->M;
+  double best = INFINITY;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double* B = block_ptr(m, s);
+    const double dx = dx_level(m, m->key[4 * s]);
+    for (int c = G; c < G + N; c++)
+      for (int b = G; b < G + N; b++)
+        for (int a = G; a < G + N; a++) {
+          double rho = B[cell(M, 0, a, b, c)];
+          double ir = 1.0 / rho;
+          double u = B[cell(M, 1, a, b, c)] * ir, v = B[cell(M, 2, a, b, c)] * ir,
+                 w = B[cell(M, 3, a, b, c)] * ir;
+          double p = K.gm1 * (B[cell(M, 4, a, b, c)] - (0.5 * rho) * ((u * u + v * v) + w * w));
+          p = p < K.p_floor ? K.p_floor : p;
+          double cs = sqrt((K.gamma * p) * ir);
+          double vm = dmax(dmax(fabs(u), fabs(v)), fabs(w));
+          double t = dx / (vm + cs);
+          best = t < best ? t : best;
+        }
+  }
+  return m->d.cfl * best;
+}
+
+/* ------------------------------------------------------------------ */
+/* PPM pencil (Sec. II-C, "ppm"; Colella & Woodward 1984 as modified)  */
+/* ------------------------------------------------------------------ */
+
+/* Primitive state of one cell; normal/transverse momenta are the sweep's. */
+typedef struct { double q[5]; double c, ir; } prim_t;  /* q = rho,u,v,w,p */
+
+static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, double mt2, double E) {
+  prim_t P;
+  double ir = 1.0 / rho;
+  double u = mn * ir, v = mt1 * ir, w = mt2 * ir;
+  double p = K->gm1 * (E - (0.5 * rho) * ((u * u + v * v) + w * w));
+  p = p < K->p_floor ? K->p_floor : p;
+  P.q[0] = rho; P.q[1] = u; P.q[2] = v; P.q[3] = w; P.q[4] = p;
+  P.c = sqrt((K->gamma * p) * ir);
+  P.ir = ir;
+  return P;
+}
+
+/* Limited (monotonised central) slope of cell j from q[j-1], q[j], q[j+1]. */
+static double mc_slope(double qm, double q0, double qp) {
+  double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
+  if (!(dl * dr > 0.0)) return 0.0;
+  double mlim = dmin(dmin(fabs(dc), 2.0 * fabs(dl)), 2.0 * fabs(dr));
+  return dc > 0.0 ? mlim : -mlim;
+}
+
+/* Parabola of one cell after flattening and the monotonicity constraint. */
+typedef struct { double qL, qR, dq, q6; } para_t;
+
+static para_t make_parabola(const consts_t* K, double q, double qL, double qR, double f) {
+  para_t P;
+  qL = f * q + (1.0 - f) * qL;
+  qR = f * q + (1.0 - f) * qR;
+  if ((qR - q) * (q - qL) <= 0.0) {
+    qL = q;
+    qR = q;
+  } else {
+    double D = qR - qL, mm = q - 0.5 * (qL + qR);
+    if (D * mm > (D * D) * K->sixth)
+      qL = 3.0 * q - 2.0 * qR;
+    else if (-((D * D) * K->sixth) > D * mm)
+      qR = 3.0 * q - 2.0 * qL;
+  }
+  P.qL = qL;
+  P.qR = qR;
+  P.dq = qR - qL;
+  P.q6 = 6.0 * (q - 0.5 * (qL + qR));
+  return P;
+}
+
+/* Mean of the parabola over the part of the cell a wave of Courant number s
+ * sweeps through in dt, at the right edge (Ip) and at the left edge (Im). */
+static inline double Ip(const consts_t* K, const para_t* P, double s) {
+  return P->qR - (0.5 * s) * (P->dq - (1.0 - K->two3 * s) * P->q6);
+}
+static inline double Im(const consts_t* K, const para_t* P, double s) {
+  return P->qL + (0.5 * s) * (P->dq + (1.0 - K->two3 * s) * P->q6);
+}
+
+/* Characteristic tracing of cell j: the left state at j+1/2 (WL) and the
+ * right state at j-1/2 (WR).  Reference state = the fastest wave towards the
+ * edge; the other waves moving towards it subtract their projections on the
+ * primitive eigenvectors (rho,u,p); v,w ride the contact. */
+static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], double nu,
+                       double WL[5], double WR[5]) {
+  const double rho = C->q[0], u = C->q[1], c = C->c;
+  const double lm = u - c, l0 = u, lp = u + c;
+  const double Ac = rho / (2.0 * c);
+  const double Bc = 1.0 / (rho * c);
+  const double cc = c * c;
+  const double ic2 = 1.0 / cc;
+  const double cor = c * C->ir;
+  /* right edge: waves with positive speed */
+  {
+    double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
+    double rr = Ip(K, &par[0], sp), ur = Ip(K, &par[1], sp), pr = Ip(K, &par[4], sp);
+    double am = (lm > 0.0) ? Ac * ((pr - Ip(K, &par[4], sm)) * Bc - (ur - Ip(K, &par[1], sm))) : 0.0;
+    double a0 = (l0 > 0.0) ? (rr - Ip(K, &par[0], s0)) - (pr - Ip(K, &par[4], s0)) * ic2 : 0.0;
+    WL[0] = (rr - am) - a0;
+    WL[1] = ur + cor * am;
+    WL[4] = pr - cc * am;
+    WL[2] = Ip(K, &par[2], s0);
+    WL[3] = Ip(K, &par[3], s0);
+  }
+  /* left edge: waves with negative speed */
+  {
+    double sm = (lm < 0.0 ? -lm : 0.0) * nu, s0 = (l0 < 0.0 ? -l0 : 0.0) * nu, sp = (lp < 0.0 ? -lp : 0.0) * nu;
+    double rr = Im(K, &par[0], sm), ur = Im(K, &par[1], sm), pr = Im(K, &par[4], sm);
+    double ap = (lp < 0.0) ? Ac * ((pr - Im(K, &par[4], sp)) * Bc + (ur - Im(K, &par[1], sp))) : 0.0;
+    double a0 = (l0 < 0.0) ? (rr - Im(K, &par[0], s0)) - (pr - Im(K, &par[4], s0)) * ic2 : 0.0;
+    WR[0] = (rr - ap) - a0;
+    WR[1] = ur - cor * ap;
+    WR[4] = pr - cc * ap;
+    WR[2] = Im(K, &par[2], s0);
+    WR[3] = Im(K, &par[3], s0);
+  }
+  /* positivity floors on the edge states */
+  WL[0] = WL[0] < K->rho_floor ? K->rho_floor : WL[0];
+  WL[4] = WL[4] < K->p_floor ? K->p_floor : WL[4];
+  WR[0] = WR[0] < K->rho_floor ? K->rho_floor : WR[0];
+  WR[4] = WR[4] < K->p_floor ? K->p_floor : WR[4];
+}
+
+/* Two-shock approximate Riemann solver (the PPM approximation of Colella &
+ * Woodward 1984): a fixed number of Newton steps on p*, both waves treated
+ * as shocks; sampled at x/t = 0 with rarefaction fans interpolated linearly
+ * between head and tail.  Returns the Godunov state and its flux. */
+static void riemann(const consts_t* K, const double WLs[5], const double WRs[5], double Wg[5],
+                    double F[5], double* pstar, double* ustar) {
+  const double rL = WLs[0], uL = WLs[1], pL = WLs[4];
+  const double rR = WRs[0], uR = WRs[1], pR = WRs[4];
+  const double CL = sqrt((K->gamma * pL) * rL), CR = sqrt((K->gamma * pR) * rR);
+  const double CL2 = CL * CL, CR2 = CR * CR;
+  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
+  double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
+  ps = ps < K->p_floor ? K->p_floor : ps;
+  double WLw = 0.0, WRw = 0.0, ZL = 0.0, ZR = 0.0, usL = 0.0, usR = 0.0;
+  for (int it = 0; it <= K->iters; it++) {
+    WLw = CL * sqrt(1.0 + K->g1 * (ps * ipL - 1.0));
+    WRw = CR * sqrt(1.0 + K->g1 * (ps * ipR - 1.0));
+    double W2L = WLw * WLw, W2R = WRw * WRw;
+    ZL = ((2.0 * WLw) * W2L) / (W2L + CL2);
+    ZR = ((2.0 * WRw) * W2R) / (W2R + CR2);
+    usL = uL - (ps - pL) / WLw;
+    usR = uR + (ps - pR) / WRw;
+    if (it == K->iters) break; /* final pass: wave speeds at the last p* */
+    ps = ps - ((ZL * ZR) * (usR - usL)) / (ZL + ZR);
+    ps = ps < K->p_floor ? K->p_floor : ps;
+  }
+  const double us = (ZL * usL + ZR * usR) / (ZL + ZR);
+  /* side of the contact the interface lies on; a tie takes the left side */
+  const int left = us >= 0.0;
+  const double s = left ? 1.0 : -1.0;
+  const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
+  const double WK = left ? WLw : WRw;
+  const double vs = 1.0 / rK - (ps - pK) / (WK * WK); /* 1/rho* on side K */
+  const double rs = 1.0 / vs;
+  double rg, ug, pg;
+  if (ps > pK) {
+    /* shock: S = u_K - s W_K / rho_K */
+    double S = uK - s * (WK / rK);
+    if (s * S >= 0.0) { rg = rK; ug = uK; pg = pK; }
+    else { rg = rs; ug = us; pg = ps; }
+  } else {
+    double cK = sqrt((K->gamma * pK) / rK);
+    double cs = sqrt((K->gamma * ps) * vs);
+    double lh = uK - s * cK, lt = us - s * cs;
+    if (s * lh >= 0.0) { rg = rK; ug = uK; pg = pK; }
+    else if (s * lt <= 0.0) { rg = rs; ug = us; pg = ps; }
+    else {
+      double xi = lh / (lh - lt);
+      rg = rK + xi * (rs - rK);
+      ug = uK + xi * (us - uK);
+      pg = pK + xi * (ps - pK);
+    }
+  }
+  const double vg = left ? WLs[2] : WRs[2], wg = left ? WLs[3] : WRs[3];
+  const double mf = rg * ug;
+  F[0] = mf;
+  F[1] = mf * ug + pg;
+  F[2] = mf * vg;
+  F[3] = mf * wg;
+  F[4] = ug * (pg * K->g_gm1 + (0.5 * rg) * ((ug * ug + vg * vg) + wg * wg));
+  Wg[0] = rg; Wg[1] = ug; Wg[2] = vg; Wg[3] = wg; Wg[4] = pg;
+  if (pstar) *pstar = ps;
+  if (ustar) *ustar = us;
+}
+
+/* Fluxes at interfaces j+1/2, j = 2 .. n-4, of a pencil of n cells; U is
+ * (rho, m_normal, m_t1, m_t2, E) x n, F is 5 x (n-5).  Cell j's update needs
+ * cells j-3 .. j+3, which a ghost width of 3 provides. */
+static void pencil(const consts_t* K, double nu, int n, const double* const U[5], double* const F[5]) {
+  prim_t* P = (prim_t*)malloc((size_t)n * sizeof(prim_t));
+  double(*dl)[5] = malloc((size_t)n * sizeof *dl);   /* slopes */
+  double(*fa)[5] = malloc((size_t)n * sizeof *fa);   /* face values at j+1/2 */
+  double(*WL)[5] = malloc((size_t)n * sizeof *WL);   /* left state at j+1/2 from cell j */
+  double(*WR)[5] = malloc((size_t)n * sizeof *WR);   /* right state at j-1/2 from cell j */
+  for (int j = 0; j < n; j++) P[j] = to_prim(K, U[0][j], U[1][j], U[2][j], U[3][j], U[4][j]);
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
+  /* interface value q_{j+1/2} = 0.5 (q_j + q_{j+1}) - (dq_{j+1} - dq_j) / 6 */
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++)
+      fa[j][v] = 0.5 * (P[j].q[v] + P[j + 1].q[v]) - (dl[j + 1][v] - dl[j][v]) * K->sixth;
+  for (int j = 2; j <= n - 3; j++) {
+    /* local flattening: shock detector on p and u, ramp on the pressure
+     * ratio (the upwind max over neighbours is dropped: it would need a
+     * fourth ghost cell) */
+    double pp = P[j + 1].q[4], pm = P[j - 1].q[4];
+    double dp1 = pp - pm;
+    double pmin = pp < pm ? pp : pm;
+    int shock = (fabs(dp1) > EPS_S * pmin) && (P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
+    double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+    double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    double ft = OMEGA2 * (r - OMEGA1);
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    double f = shock ? ft : 0.0;
+    para_t par[5];
+    for (int v = 0; v < 5; v++) par[v] = make_parabola(K, P[j].q[v], fa[j - 1][v], fa[j][v], f);
+    trace_cell(K, &P[j], par, nu, WL[j], WR[j]);
+  }
+  for (int j = 2; j <= n - 4; j++) {
+    double Wg[5], Fl[5];
+    riemann(K, WL[j], WR[j + 1], Wg, Fl, NULL, NULL);
+    for (int v = 0; v < 5; v++) F[v][j - 2] = Fl[v];
+  }
+  free(P); free(dl); free(fa); free(WL); free(WR);
+}
+
+/* One directional sweep over every leaf.  swept[a] says whether axis a was
+ * already swept this step (then only its active range is updated). */
+static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], double dt) {
+  const int N = m->N, M = m->M;
+  const int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3; /* velocity roles: cyclic */
+  const int a1 = dir == 0 ? 1 : 0, a2 = dir == 2 ? 1 : 2; /* face layout: lower, higher axis */
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; a++) {
+    int act = (a == dir) || swept[a];
+    lo[a] = act ? G : 0;
+    hi[a] = act ? G + N : M;
+  }
+  int64_t nfl_total = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl_total)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    double* B = block_ptr(m, s);
+    const double nu = dt / dx_level(m, m->key[4 * s]);
+    double* in[5];
+    double* fl[5];
+    for (int v = 0; v < 5; v++) {
+      in[v] = (double*)malloc((size_t)M * sizeof(double));
+      fl[v] = (double*)malloc((size_t)M * sizeof(double));
+    }
+    const int fmap[5] = {0, 1 + dir, 1 + t1, 1 + t2, 4};
+    double* flo = m->face[6 * s + 2 * dir];
+    double* fhi = m->face[6 * s + 2 * dir + 1];
+    int64_t nfl = 0;
+    for (int i2 = lo[t2]; i2 < hi[t2]; i2++)
+      for (int i1 = lo[t1]; i1 < hi[t1]; i1++) {
+        int pos[3];
+        pos[t1] = i1;
+        pos[t2] = i2;
+        for (int j = 0; j < M; j++) {
+          pos[dir] = j;
+          for (int v = 0; v < 5; v++) in[v][j] = B[cell(M, fmap[v], pos[0], pos[1], pos[2])];
+        }
+        pencil(K, nu, M, (const double* const*)in, fl);
+        /* flux index k is interface (G-1+k)+1/2 */
+        for (int j = G; j < G + N; j++) {
+          double Un[5];
+          for (int v = 0; v < 5; v++) Un[v] = in[v][j] - nu * (fl[v][j - G + 1] - fl[v][j - G]);
+          /* post-update floors (counted: they break conservation) */
+          if (Un[0] < K->rho_floor) { Un[0] = K->rho_floor; nfl++; }
+          double ir = 1.0 / Un[0];
+          double u = Un[1] * ir, v = Un[2] * ir, w = Un[3] * ir;
+          double ke = (0.5 * Un[0]) * ((u * u + v * v) + w * w);
+          double p = K->gm1 * (Un[4] - ke);
+          if (p < K->p_floor) { Un[4] = K->p_floor * K->inv_gm1 + ke; nfl++; }
+          pos[dir] = j;
+          for (int vv = 0; vv < 5; vv++) B[cell(M, fmap[vv], pos[0], pos[1], pos[2])] = Un[vv];
+        }
+        /* coarse-fine face fluxes, in conserved-field order */
+        int ta1 = (a1 == t1) ? i1 : i2, ta2 = (a2 == t1) ? i1 : i2;
+        if (ta1 >= G && ta1 < G + N && ta2 >= G && ta2 < G + N) {
+          int64_t off = (int64_t)(ta2 - G) * N + (ta1 - G);
+          for (int v = 0; v < 5; v++) {
+            if (flo) flo[(int64_t)fmap[v] * N * N + off] = fl[v][0];
+            if (fhi) fhi[(int64_t)fmap[v] * N * N + off] = fl[v][N];
+          }
+        }
+      }
+    nfl_total += nfl;
+    for (int v = 0; v < 5; v++) { free(in[v]); free(fl[v]); }
+  }
+  m->floors += nfl_total;
+}
+
+/* Reflux at coarse-fine faces (Berger & Colella 1989, cited by the paper for
+ * AMR): the coarse cell's flux at the face is replaced by the area mean of
+ * the 2x2 fine fluxes, F_bar = ((F00 + F10) + (F01 + F11)) * 0.25 (first
+ * index along the lower transverse axis), U_c += s nu_c (F_c - F_bar) with
+ * s = +1 on the coarse cell's high face and -1 on its low face.  Axes are
+ * processed in the order x, y, z. */
+static void reflux(orc_mesh* m, double dt) {
+  const int N = m->N, M = m->M;
+  for (int dir = 0; dir < 3; dir++) {
+    const int a1 = dir == 0 ? 1 : 0, a2 = dir == 2 ? 1 : 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < m->nleaf; s++) {
+      const int32_t* kk = m->key + 4 * s;
+      const int l = kk[0];
+      double* B = block_ptr(m, s);
+      const double nu = dt / dx_level(m, l);
+      for (int side = 0; side < 2; side++) {
+        const double* Fc = m->face[6 * s + 2 * dir + side];
+        if (!Fc) continue;
+        int nb[3] = {kk[1], kk[2], kk[3]};
+        nb[dir] += side ? 1 : -1;
+        wrap_block(m, l, dir, &nb[dir]);
+        if (m->state[l][nidx(m, l, nb[0], nb[1], nb[2])] != REFINED) continue; /* fine side */
+        for (int t2 = 0; t2 < N; t2++)
+          for (int t1 = 0; t1 < N; t1++) {
+            int h1 = t1 >= N / 2, h2 = t2 >= N / 2;
+            int cp[3];
+            cp[dir] = 2 * nb[dir] + (side ? 0 : 1);
+            cp[a1] = 2 * kk[1 + a1] + h1;
+            cp[a2] = 2 * kk[1 + a2] + h2;
+            int32_t fs = m->leaf_at[l + 1][nidx(m, l + 1, cp[0], cp[1], cp[2])];
+            const double* Ff = m->face[6 * (int64_t)fs + 2 * dir + (1 - side)];
+            int f1 = 2 * t1 - h1 * N, f2 = 2 * t2 - h2 * N;
+            int pos[3];
+            pos[dir] = side ? G + N - 1 : G;
+            pos[a1] = G + t1;
+            pos[a2] = G + t2;
+            for (int f = 0; f < NF; f++) {
+              const double* Q = Ff + (int64_t)f * N * N;
+              double fb = ((Q[f2 * N + f1] + Q[f2 * N + f1 + 1]) + (Q[(f2 + 1) * N + f1] + Q[(f2 + 1) * N + f1 + 1])) * 0.25;
+              double corr = nu * (Fc[(int64_t)f * N * N + t2 * N + t1] - fb);
+              double* u = &B[cell(M, f, pos[0], pos[1], pos[2])];
+              *u = side ? *u + corr : *u - corr;
+            }
+          }
+      }
+    }
+  }
+}
+
+/* Test-only switches that plant a known mistake, to show that a pin fails
+ * without the piece it checks. */
+static int g_debug = 0;
+void orc_set_debug(int flags) { g_debug = flags; }
+
+void orc_step_dt(orc_mesh* m, int64_t step_index, double dt) {
+  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  orc_refresh(m);
+  int order[3] = {0, 1, 2};
+  if (step_index & 1) { order[0] = 2; order[2] = 0; }
+  int swept[3] = {0, 0, 0};
+  for (int s = 0; s < 3; s++) {
+    sweep(m, &K, order[s], swept, dt);
+    swept[order[s]] = 1;
+  }
+  if (!(g_debug & ORC_DEBUG_SKIP_REFLUX)) reflux(m, dt);
+}
+
+double orc_step(orc_mesh* m, int64_t step_index) {
+  double dt = orc_cfl_dt(m);
+  orc_step_dt(m, step_index, dt);
+  return dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Test hooks                                                          */
+/* ------------------------------------------------------------------ */
+
+void orc_riemann(const double* gas, int iters, const double* WLs, const double* WRs, double* state_out,
+                 double* flux_out, double* pstar_out, double* ustar_out) {
+  consts_t K = make_consts(gas[0], 0.0, gas[1], iters);
+  riemann(&K, WLs, WRs, state_out, flux_out, pstar_out, ustar_out);
+}
+
+void orc_pencil_flux(const double* gas, int iters, double nu, int n, const double* U, double* flux_out) {
+  consts_t K = make_consts(gas[0], gas[1], gas[2], iters);
+  const double* in[5];
+  double* out[5];
+  for (int v = 0; v < 5; v++) {
+    in[v] = U + (int64_t)v * n;
+    out[v] = flux_out + (int64_t)v * (n - 5);
+  }
+  pencil(&K, nu, n, in, out);
+}

@@ -1,0 +1,94 @@
+/*
+ * amr_oracle.h -- C API of the plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test-suite, the smoke
+ * entry point and the CPU-baseline leg of the benchmark may load this
+ * library.  It shares no code with the HIP path.
+ *
+ * The oracle follows the paper's description of the Enzo-P/Cello timestep
+ * (Bordner & Norman, "Computational Cosmology and Astrophysics on Adaptive
+ * Meshes using Charm++"):
+ *   - array-of-octrees mesh, one Block per octree node (Sec. II-B);
+ *   - ghost-zone refresh of a given width for the named fields, with
+ *     Restrict/Prolong across refinement jumps (Sec. II-B);
+ *   - the "ppm" Method, a modified piecewise-parabolic Euler solver
+ *     (Sec. II-C), here directionally split with a two-shock Riemann solver.
+ * The paper gives no formulas; every arithmetic detail is a stated reading,
+ * written out next to the code that applies it.
+ */
+#ifndef AMR_ORACLE_H
+#define AMR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_GHOST 3
+#define ORC_NFIELD 5
+#define ORC_MAXLEV 8
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
+
+typedef struct {
+  int32_t root[3];        /* octrees (root blocks) per axis                 */
+  int32_t block_cells;    /* N: cells per block edge, even, >= 8            */
+  int32_t max_level;      /* deepest refinement level allowed               */
+  int32_t bc[3];          /* per axis, both faces: ORC_BC_*                 */
+  double gamma, cfl, rho_floor, p_floor;
+  int32_t riemann_iters;  /* fixed number of two-shock Newton iterations    */
+  int32_t n_refine;       /* static refinement list: (level,i,j,k) x n      */
+  const int32_t* refine;
+} orc_desc;
+
+typedef struct orc_mesh orc_mesh;
+
+/* Build the balanced array-of-octrees described by d.  Returns 0 or <0. */
+int orc_create(const orc_desc* d, orc_mesh** out);
+/* Build from an explicit leaf list (level,i,j,k) x n; must tile the domain
+ * and satisfy 2:1 balance (checked). */
+int orc_create_from_leaves(const orc_desc* d, int64_t n, const int32_t* keys,
+                           orc_mesh** out);
+void orc_destroy(orc_mesh* m);
+const char* orc_last_error(void);
+
+int64_t orc_nleaf(const orc_mesh* m);
+void orc_leaf_keys(const orc_mesh* m, int32_t* out /* 4 x nleaf */);
+/* Padded block storage: U[leaf][field][z][y][x], edge M = N + 6. */
+double* orc_state(orc_mesh* m);
+int64_t orc_floor_count(const orc_mesh* m);
+
+void orc_refresh(orc_mesh* m);
+double orc_cfl_dt(const orc_mesh* m);
+/* One full step: dt from CFL, refresh, three sweeps (xyz on even step
+ * index, zyx on odd), reflux.  Returns dt. */
+double orc_step(orc_mesh* m, int64_t step_index);
+/* Same with a given dt (no CFL reduction). */
+void orc_step_dt(orc_mesh* m, int64_t step_index, double dt);
+
+/* Test hooks on the building blocks. */
+#define ORC_DEBUG_SKIP_REFLUX 1
+void orc_set_debug(int flags);
+void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
+                 const double* WL /* rho,u,v,w,p */, const double* WR,
+                 double* state_out /* rho,u,v,w,p Godunov */, double* flux_out,
+                 double* pstar_out, double* ustar_out);
+/* Fluxes of one pencil of n conserved cells (rho, m_normal, m_t1, m_t2, E),
+ * interfaces j+1/2 for j = 2 .. n-4; flux_out is 5 x (n-5). */
+void orc_pencil_flux(const double* gas /* gamma,rho_floor,p_floor */, int iters,
+                     double nu, int n, const double* U /* 5 x n */, double* flux_out);
+
+/* Remesh (density-slope criterion).  Evaluates the per-leaf indicator on
+ * refreshed data, applies refine/coarsen with 2:1 balance and the capacity
+ * policy, and returns a new mesh holding the migrated state.  Counters:
+ * out_stats[0]=refined, [1]=coarsened octets, [2]=refused refinements. */
+int orc_remesh(orc_mesh* m, double refine_slope, double coarsen_slope,
+               int64_t max_blocks, orc_mesh** out, int64_t* out_stats);
+/* Per-leaf indicator S_b (max over active cells and axes of
+ * |rho(+1)-rho(-1)| / (2 rho)).  Requires refreshed ghosts. */
+void orc_indicator(const orc_mesh* m, double* out /* nleaf */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

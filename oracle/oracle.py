@@ -1,0 +1,227 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``amr_oracle.c``).
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only ``tests/``, the smoke entry point
+and the benchmark's CPU-baseline leg may import this module.  It imports
+nothing from the product package; inputs reach it as plain numpy arrays and
+plain mesh parameters.
+
+The oracle follows the paper's description of one Enzo-P/Cello hydro step on
+an array-of-octrees mesh (Sec. II-B: Blocks, ghost refresh of a given width,
+Restrict/Prolong; Sec. II-C: the PPM Method), with every arithmetic detail a
+written reading given in ``amr_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "amr_oracle.c")
+_SO = os.path.join(_HERE, "libamr_oracle.so")
+GHOST = 3
+NFIELD = 5
+BC = {"periodic": 0, "outflow": 1}
+
+# Flags that make the arithmetic exactly the written one: no contraction into
+# fused multiply-add, no value-changing optimisation, SSE2 doubles.
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libamr_oracle.so``."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("root", ctypes.c_int32 * 3),
+        ("block_cells", ctypes.c_int32),
+        ("max_level", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("rho_floor", ctypes.c_double),
+        ("p_floor", ctypes.c_double),
+        ("riemann_iters", ctypes.c_int32),
+        ("n_refine", ctypes.c_int32),
+        ("refine", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        P, D, I64, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        L.orc_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(P)]
+        L.orc_create.restype = I32
+        L.orc_create_from_leaves.argtypes = [ctypes.POINTER(_Desc), I64, P, ctypes.POINTER(P)]
+        L.orc_create_from_leaves.restype = I32
+        L.orc_destroy.argtypes = [P]
+        L.orc_last_error.restype = ctypes.c_char_p
+        L.orc_nleaf.argtypes = [P]
+        L.orc_nleaf.restype = I64
+        L.orc_leaf_keys.argtypes = [P, P]
+        L.orc_state.argtypes = [P]
+        L.orc_state.restype = ctypes.POINTER(ctypes.c_double)
+        L.orc_floor_count.argtypes = [P]
+        L.orc_floor_count.restype = I64
+        L.orc_refresh.argtypes = [P]
+        L.orc_cfl_dt.argtypes = [P]
+        L.orc_cfl_dt.restype = D
+        L.orc_step.argtypes = [P, I64]
+        L.orc_step.restype = D
+        L.orc_step_dt.argtypes = [P, I64, D]
+        L.orc_riemann.argtypes = [P, I32, P, P, P, P, P, P]
+        L.orc_pencil_flux.argtypes = [P, I32, D, I32, P, P]
+        L.orc_set_debug.argtypes = [I32]
+        if hasattr(L, "orc_remesh"):
+            L.orc_remesh.argtypes = [P, D, D, I64, ctypes.POINTER(P), P]
+            L.orc_remesh.restype = I32
+            L.orc_indicator.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_desc(root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
+              rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=()):
+    d = _Desc()
+    d.root[:] = [int(r) for r in root]
+    d.block_cells = int(block_cells)
+    d.max_level = int(max_level)
+    bcs = [bc] * 3 if isinstance(bc, str) else list(bc)
+    d.bc[:] = [BC[b] if isinstance(b, str) else int(b) for b in bcs]
+    d.gamma, d.cfl, d.rho_floor, d.p_floor = float(gamma), float(cfl), float(rho_floor), float(p_floor)
+    d.riemann_iters = int(riemann_iters)
+    ref = np.ascontiguousarray(np.asarray(refine, dtype=np.int32).reshape(-1, 4))
+    d.n_refine = ref.shape[0]
+    d.refine = ref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if ref.size else None
+    return d, ref
+
+
+class OracleMesh:
+    """One mesh of the oracle with its padded FP64 state."""
+
+    def __init__(self, root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
+                 rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), leaves=None,
+                 _handle=None):
+        self._kw = dict(root=root, block_cells=block_cells, max_level=max_level, bc=bc, gamma=gamma,
+                        cfl=cfl, rho_floor=rho_floor, p_floor=p_floor, riemann_iters=riemann_iters)
+        L = lib()
+        h = ctypes.c_void_p()
+        if _handle is not None:
+            h = _handle
+        else:
+            d, keep = make_desc(refine=refine, **self._kw)
+            if leaves is not None:
+                lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+                rc = L.orc_create_from_leaves(ctypes.byref(d), lv.shape[0], _ptr(lv), ctypes.byref(h))
+            else:
+                rc = L.orc_create(ctypes.byref(d), ctypes.byref(h))
+            if rc != 0:
+                raise ValueError("oracle mesh: " + L.orc_last_error().decode())
+        self._h = h
+        self.N = int(block_cells)
+        self.M = self.N + 2 * GHOST
+        self.nleaf = int(L.orc_nleaf(h))
+        keys = np.zeros((self.nleaf, 4), dtype=np.int32)
+        L.orc_leaf_keys(h, _ptr(keys))
+        self.keys = keys
+        n = self.nleaf * NFIELD * self.M ** 3
+        buf = np.ctypeslib.as_array(L.orc_state(h), shape=(n,))
+        self.U = buf.reshape(self.nleaf, NFIELD, self.M, self.M, self.M)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    # state access -----------------------------------------------------
+    def set_active(self, act: np.ndarray) -> None:
+        g, N = GHOST, self.N
+        self.U[...] = 0.0
+        self.U[:, :, g:g + N, g:g + N, g:g + N] = act
+
+    def active(self) -> np.ndarray:
+        g, N = GHOST, self.N
+        return np.array(self.U[:, :, g:g + N, g:g + N, g:g + N])
+
+    @property
+    def floors(self) -> int:
+        return int(lib().orc_floor_count(self._h))
+
+    # method -----------------------------------------------------------
+    def refresh(self) -> None:
+        lib().orc_refresh(self._h)
+
+    def cfl_dt(self) -> float:
+        return float(lib().orc_cfl_dt(self._h))
+
+    def step(self, k: int) -> float:
+        return float(lib().orc_step(self._h, int(k)))
+
+    def step_dt(self, k: int, dt: float) -> None:
+        lib().orc_step_dt(self._h, int(k), float(dt))
+
+    def indicator(self) -> np.ndarray:
+        out = np.zeros(self.nleaf)
+        lib().orc_indicator(self._h, _ptr(out))
+        return out
+
+    def remesh(self, refine_slope, coarsen_slope, max_blocks):
+        """Returns (new OracleMesh, stats[refined, coarsened, refused])."""
+        L = lib()
+        h = ctypes.c_void_p()
+        stats = np.zeros(3, dtype=np.int64)
+        rc = L.orc_remesh(self._h, float(refine_slope), float(coarsen_slope), int(max_blocks),
+                          ctypes.byref(h), _ptr(stats))
+        if rc != 0:
+            raise ValueError("oracle remesh: " + L.orc_last_error().decode())
+        return OracleMesh(_handle=h, **self._kw), stats
+
+
+DEBUG_SKIP_REFLUX = 1
+
+
+def set_debug(flags: int) -> None:
+    """Plant a known mistake in the oracle (tests of the pins' power only)."""
+    lib().orc_set_debug(int(flags))
+
+
+def riemann(WL, WR, gamma=1.4, p_floor=1e-20, iters=5):
+    """Two-shock Riemann solve at one interface: (state, flux, p*, u*)."""
+    gas = np.array([gamma, p_floor])
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    st, fl = np.zeros(5), np.zeros(5)
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    lib().orc_riemann(_ptr(gas), int(iters), _ptr(WL), _ptr(WR), _ptr(st), _ptr(fl),
+                      ctypes.byref(ps), ctypes.byref(us))
+    return st, fl, ps.value, us.value
+
+
+def pencil_flux(U, nu, gamma=1.4, rho_floor=1e-20, p_floor=1e-20, iters=5):
+    """Fluxes of a pencil U[5, n] at interfaces j+1/2, j = 2..n-4."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = U.shape[1]
+    out = np.zeros((5, n - 5))
+    gas = np.array([gamma, rho_floor, p_floor])
+    lib().orc_pencil_flux(_ptr(gas), int(iters), float(nu), int(n), _ptr(U), _ptr(out))
+    return out

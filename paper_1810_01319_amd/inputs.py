@@ -1,0 +1,201 @@
+"""Seeded synthetic inputs: mesh descriptions and initial states.
+
+This module holds no arithmetic of the method (no refresh, no sweep, no
+Riemann solve).  It only states the problems: which blocks are refined, and
+the initial conserved fields at cell centres.  It is the one module shared by
+the HIP path's callers and by the test-suite's oracle runs, so both start from
+byte-identical inputs.
+
+The workloads follow the paper's test problems (Sec. III): an array of blast
+waves (one per root octree, at seeded random offsets instead of the paper's
+letter-shaped sources, for the same purpose of breaking lockstep refinement)
+and, as smaller checks, the Sod shock tube and a single Sedov blast.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+GHOST = 3
+NFIELD = 5  # rho, m_x, m_y, m_z, E
+
+
+@dataclass
+class MeshSpec:
+    """Plain description of one array-of-octrees mesh and its gas."""
+
+    root: Tuple[int, int, int]
+    block_cells: int
+    max_level: int = 0
+    bc: str = "periodic"            # "periodic" or "outflow" (all axes)
+    gamma: float = 1.4
+    cfl: float = 0.4
+    rho_floor: float = 1e-20
+    p_floor: float = 1e-20
+    riemann_iters: int = 5
+    refine: List[Tuple[int, int, int, int]] = field(default_factory=list)
+
+    def kwargs(self) -> dict:
+        return dict(root=tuple(self.root), block_cells=self.block_cells, max_level=self.max_level,
+                    bc=self.bc, gamma=self.gamma, cfl=self.cfl, rho_floor=self.rho_floor,
+                    p_floor=self.p_floor, riemann_iters=self.riemann_iters,
+                    refine=list(self.refine))
+
+    def dx(self, level: int) -> float:
+        return 1.0 / float(self.root[0] * self.block_cells * (1 << level))
+
+
+def cell_centres(spec: MeshSpec, keys: np.ndarray):
+    """x, y, z cell-centre coordinates of the active cells, each [n, N, N, N]
+    (index order z, y, x as in the block storage)."""
+    N = spec.block_cells
+    keys = np.asarray(keys, dtype=np.int64)
+    lev = keys[:, 0]
+    dx = np.array([spec.dx(int(l)) for l in lev])
+    r = np.arange(N, dtype=np.float64) + 0.5
+    out = []
+    for ax in range(3):
+        origin = keys[:, 1 + ax].astype(np.float64) * N
+        c = (origin[:, None] + r[None, :]) * dx[:, None]  # [n, N]
+        shape = [len(keys), 1, 1, 1]
+        shape[3 - ax] = N
+        out.append(np.broadcast_to(c.reshape(shape), (len(keys), N, N, N)))
+    return out
+
+
+def conserved(gamma: float, rho, u, v, w, p) -> np.ndarray:
+    """Conserved fields from primitives at cell centres (the initial state is
+    defined by point values)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    shape = np.broadcast_shapes(np.shape(rho), np.shape(u), np.shape(v), np.shape(w), np.shape(p))
+    out = np.empty((shape[0], NFIELD) + tuple(shape[1:]), dtype=np.float64)
+    rho = np.broadcast_to(rho, shape)
+    u, v, w, p = (np.broadcast_to(np.asarray(a, dtype=np.float64), shape) for a in (u, v, w, p))
+    out[:, 0] = rho
+    out[:, 1] = rho * u
+    out[:, 2] = rho * v
+    out[:, 3] = rho * w
+    out[:, 4] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Sod shock tube along x (uniform level, outflow)
+# ---------------------------------------------------------------------------
+
+def sod_spec(root=(4, 4, 4), block_cells=16) -> MeshSpec:
+    return MeshSpec(root=tuple(root), block_cells=block_cells, max_level=0, bc="outflow",
+                    gamma=1.4, cfl=0.4)
+
+
+def sod_state(spec: MeshSpec, keys) -> np.ndarray:
+    """Left (rho=1, p=1) for x < 0.5, right (rho=0.125, p=0.1); at rest.  The
+    jump lies on a cell face, so the initial state is exact."""
+    x, _, _ = cell_centres(spec, keys)
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    return conserved(spec.gamma, rho, 0.0, 0.0, 0.0, p)
+
+
+# ---------------------------------------------------------------------------
+# Sedov blast on a static two-level refinement around the domain centre
+# ---------------------------------------------------------------------------
+
+def centre_refine_list(root: int, levels: int) -> List[Tuple[int, int, int, int]]:
+    """Refine the 8 blocks touching the domain centre at each level < levels
+    (the centre is a vertex shared by 8 blocks when root is even)."""
+    assert root % 2 == 0
+    out = []
+    for l in range(levels):
+        h = root * (1 << l) // 2
+        for k in (h - 1, h):
+            for j in (h - 1, h):
+                for i in (h - 1, h):
+                    out.append((l, i, j, k))
+    return out
+
+
+def sedov_spec(root=8, block_cells=32, levels=2, gamma=5.0 / 3.0) -> MeshSpec:
+    return MeshSpec(root=(root, root, root), block_cells=block_cells, max_level=levels,
+                    bc="periodic", gamma=gamma, cfl=0.4, refine=centre_refine_list(root, levels))
+
+
+def blast_state(spec: MeshSpec, keys, centres, energy=1.0, rho0=1.0, p0=1e-5, radius_cells=2.0,
+                level=None) -> np.ndarray:
+    """Ambient gas plus, per centre, energy deposited uniformly (as energy
+    density) in the cells of level `level` (default: the finest present)
+    whose centre lies within radius_cells * dx of the blast centre
+    (periodic minimum image).  The deposited total is exactly `energy` per
+    blast in exact arithmetic."""
+    keys = np.asarray(keys)
+    x, y, z = cell_centres(spec, keys)
+    lev = keys[:, 0]
+    lv = int(lev.max()) if level is None else int(level)
+    dx = spec.dx(lv)
+    ext = np.array(spec.root, dtype=np.float64) / spec.root[0]
+    U = conserved(spec.gamma, np.full(x.shape, rho0), 0.0, 0.0, 0.0, np.full(x.shape, p0))
+    on_level = (lev == lv)[:, None, None, None]
+    for c in np.atleast_2d(np.asarray(centres, dtype=np.float64)):
+        d2 = np.zeros(x.shape)
+        for a, X in enumerate((x, y, z)):
+            d = X - c[a]
+            if spec.bc == "periodic":
+                d = d - ext[a] * np.round(d / ext[a])
+            d2 = d2 + d * d
+        sel = (d2 < (radius_cells * dx) ** 2) & on_level
+        n = int(sel.sum())
+        if n == 0:
+            raise ValueError("blast deposit region is empty")
+        U[:, 4][sel] += energy / (n * dx ** 3)
+    return U
+
+
+def sedov_state(spec: MeshSpec, keys) -> np.ndarray:
+    ext = np.array(spec.root, dtype=np.float64) / spec.root[0]
+    return blast_state(spec, keys, [0.5 * ext], energy=1.0, rho0=1.0, p0=1e-5, radius_cells=2.0)
+
+
+# ---------------------------------------------------------------------------
+# Smooth random fields for parity, conservation and symmetry checks
+# ---------------------------------------------------------------------------
+
+def smooth_state(spec: MeshSpec, keys, seed: int, amp=0.2, vel=0.5) -> np.ndarray:
+    """A periodic smooth state: a few random low Fourier modes in rho, u, v,
+    w, p, evaluated at cell centres (seeded, numpy PCG64)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = cell_centres(spec, keys)
+    ext = np.array(spec.root, dtype=np.float64) / spec.root[0]
+
+    def field_(base, a):
+        out = np.full(x.shape, base)
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            c = rng.uniform(-1, 1)
+            out = out + a * c * np.sin(2 * np.pi * (k[0] * x / ext[0] + k[1] * y / ext[1] + k[2] * z / ext[2]) + ph)
+        return out
+
+    rho = field_(1.0, amp)
+    u = field_(0.0, vel)
+    v = field_(0.0, vel)
+    w = field_(0.0, vel)
+    p = field_(1.0, amp)
+    return conserved(spec.gamma, rho, u, v, w, p)
+
+
+def random_refine_list(root, max_level, n, seed) -> List[Tuple[int, int, int, int]]:
+    """n random refinement requests at random levels < max_level."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        l = int(rng.integers(0, max_level))
+        e = [int(r) << l for r in root]
+        out.append((l, int(rng.integers(0, e[0])), int(rng.integers(0, e[1])), int(rng.integers(0, e[2]))))
+    return out
+
+
+def with_(spec: MeshSpec, **kw) -> MeshSpec:
+    return replace(spec, **kw)
