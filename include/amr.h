@@ -1,0 +1,143 @@
+/*
+ * amr.h -- C ABI of the MI355X (gfx950) AMR hydro hot path.
+ *
+ * One timestep over every leaf block of an array-of-octrees mesh, as the
+ * paper describes the Enzo-P/Cello step (Bordner & Norman, "Computational
+ * Cosmology and Astrophysics on Adaptive Meshes using Charm++"):
+ *   - Sec. II-B: the mesh is an array of octrees, one Block per node; a
+ *     Method acting on a Block needs a ghost layer of a stated width for the
+ *     stated fields, refreshed from neighbouring Blocks, with Restrict and
+ *     Prolong across refinement jumps; Boundary supplies physical ghosts;
+ *     Refine decides where blocks split or merge;
+ *   - Sec. II-C: the hydro Method is a modified piecewise-parabolic method.
+ * Here the refresh, the CFL reduction, the three directionally split PPM
+ * sweeps and the coarse-fine reflux run as HIP kernels on one GPU.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (HIP global memory) that the
+ *     caller allocates, owns and keeps alive until the stream work that uses
+ *     them has finished.  The library never allocates device memory; it keeps
+ *     no device pointer beyond a call, except the workspace given to
+ *     amr_mesh_upload, which must stay allocated while the mesh is used.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued asynchronously on it unless stated otherwise.
+ *   - Every call returns an amr_status; on failure amr_last_error() gives a
+ *     message (per thread, valid until the next failing call).
+ *   - Field storage U_dev: n_leaves blocks in the order of amr_mesh_blocks,
+ *     each block = 5 fields (rho, m_x, m_y, m_z, E) of M^3 FP64 values,
+ *     M = N + 6 (ghost width 3 on each side), index (field, z, y, x) with x
+ *     fastest, no padding: block stride 5 M^3 doubles, field stride M^3.
+ *     Only active cells (ghost-free interior N^3) carry state between calls;
+ *     ghosts are scratch that a refresh overwrites.
+ */
+#ifndef AMR_H
+#define AMR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amr_mesh amr_mesh;
+
+typedef int32_t amr_status;
+#define AMR_OK 0
+#define AMR_E_INVALID (-1)  /* bad argument or descriptor */
+#define AMR_E_BALANCE (-2)  /* leaf set violates the 2:1 rule or does not tile */
+#define AMR_E_NOMEM (-3)    /* host allocation failed */
+#define AMR_E_HIP (-4)      /* a HIP call or kernel launch failed */
+#define AMR_E_CAPACITY (-5) /* remesh would exceed max_blocks */
+#define AMR_E_STATE (-6)    /* call out of order (e.g. no workspace uploaded) */
+
+#define AMR_BC_PERIODIC 0
+#define AMR_BC_OUTFLOW 1 /* single-level meshes only */
+
+/* Mesh description (Sec. II-B: array of octrees, Blocks of N^3 cells, ghost
+ * width and fields named by the application).  Cells are cubic:
+ * dx_l = 1 / (root[0] * N * 2^l); the domain is [0,1] x [0, root[1]/root[0]]
+ * x [0, root[2]/root[0]]. */
+typedef struct {
+  int32_t root[3];        /* octrees per axis, >= 1                         */
+  int32_t block_cells;    /* N: 8, 16 or 32                                 */
+  int32_t ghost;          /* ghost width; must be 3                         */
+  int32_t max_level;      /* deepest level, 0..7                            */
+  int32_t bc[3];          /* AMR_BC_* per axis (both faces)                 */
+  double gamma;           /* ratio of specific heats, > 1                   */
+  double cfl;             /* Courant number of the dt reduction             */
+  double rho_floor, p_floor;
+  int32_t riemann_iters;  /* fixed two-shock Newton iterations (e.g. 5)     */
+  int32_t n_refine;       /* static refinement list, borrowed for the call: */
+  const int32_t* refine;  /* n_refine x (level, i, j, k) block keys         */
+} amr_mesh_desc;
+
+typedef struct {
+  int64_t n_leaves;
+  int32_t block_cells;     /* N */
+  int32_t padded;          /* M = N + 6 */
+  int64_t block_stride;    /* doubles per block = 5 M^3 */
+  int64_t field_stride;    /* doubles per field = M^3 */
+  int64_t field_bytes;     /* bytes of U_dev = n_leaves * block_stride * 8 */
+  int64_t workspace_bytes; /* bytes the caller allocates for amr_mesh_upload */
+  int64_t n_cf_faces;      /* coarse-fine block faces (both sides counted) */
+  int32_t levels[8];       /* leaves per level */
+} amr_mesh_info_t;
+
+/* Build the balanced array-of-octrees: roots, then each refine entry in
+ * order (refining a leaf ancestor first when needed), then refinement until
+ * no leaf touches (face, edge or corner, periodic wrap included) a leaf two
+ * or more levels finer.  Sec. II-B (array-of-octrees, Refine).
+ * Errors: AMR_E_INVALID for a bad descriptor (ghost != 3, N not in {8,16,32},
+ * key out of range, outflow on a refined mesh). */
+amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out);
+
+/* Build from an explicit leaf set (n x (level,i,j,k), borrowed for the
+ * call).  Errors: AMR_E_BALANCE if the leaves do not tile the domain or
+ * violate the 2:1 rule. */
+amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n,
+                                       const int32_t* keys, amr_mesh** out);
+
+amr_status amr_mesh_destroy(amr_mesh* mesh);
+amr_status amr_mesh_info(const amr_mesh* mesh, amr_mesh_info_t* out);
+
+/* Leaf keys (level, i, j, k) in storage order (roots x-fastest, Morton order
+ * inside each octree).  keys_out holds cap x 4 int32 (host memory). */
+amr_status amr_mesh_blocks(const amr_mesh* mesh, int32_t* keys_out, int64_t cap);
+
+/* Copy the mesh tables into caller-owned device memory of workspace_bytes
+ * (amr_mesh_info) and bind it to the mesh.  The copy is enqueued on the
+ * stream; the workspace must outlive every later call on this mesh. */
+amr_status amr_mesh_upload(amr_mesh* mesh, void* workspace_dev, void* stream);
+
+/* Ghost refresh (Sec. II-B): fill the width-3 ghost shell of all 5 fields of
+ * every leaf.  Phase 1: same-level copies (faces, edges, corners; periodic
+ * wrap; outflow = nearest domain cell), restriction (mean of the 8 children)
+ * into ghosts covered by finer leaves.  Phase 2: minmod-limited linear
+ * prolongation into ghosts covered by a coarser leaf. */
+amr_status amr_refresh_ghosts(amr_mesh* mesh, double* U_dev, void* stream);
+
+/* CFL dt (device, 1 double): C_cfl * min over active leaf cells of
+ * dx_l / (max_d |u_d| + c).  Exact minimum, order independent. */
+amr_status amr_cfl_dt(amr_mesh* mesh, const double* U_dev, double* dt_dev, void* stream);
+
+/* One hydro step (Sec. II-C "ppm" Method on every Block, after the refresh
+ * its ghosts need): dt from the CFL reduction written to dt_dev, refresh,
+ * PPM sweeps x,y,z on even step_index and z,y,x on odd, then reflux at
+ * coarse-fine faces.  U_dev is updated in place. */
+amr_status amr_hydro_step(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t step_index,
+                          void* stream);
+
+/* The same step with dt given on the device (no CFL reduction). */
+amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,
+                             int64_t step_index, void* stream);
+
+/* Number of post-update floor resets since upload (synchronises the
+ * stream). */
+amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
+
+const char* amr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,259 @@
+// capi.cpp -- extern "C" entry points declared in include/amr.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/amr.h"
+#include "kernels.hpp"
+#include "mesh.hpp"
+
+using namespace amr;
+
+struct amr_mesh {
+  std::unique_ptr<Octree> tree;
+  Plan plan;
+  unsigned char* ws = nullptr;  // caller-owned device workspace
+  LaunchCfg cfg;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+amr_status fail(amr_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+amr_status hip_fail(hipError_t e, const char* where) {
+  return fail(AMR_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+amr_status to_desc(const amr_mesh_desc* d, MeshDesc& m) {
+  if (!d) return fail(AMR_E_INVALID, "null descriptor");
+  if (d->ghost != 3) return fail(AMR_E_INVALID, "ghost width must be 3");
+  if (d->block_cells != 8 && d->block_cells != 16 && d->block_cells != 32)
+    return fail(AMR_E_INVALID, "block_cells must be 8, 16 or 32");
+  if (d->max_level < 0 || d->max_level > 7) return fail(AMR_E_INVALID, "max_level must be in 0..7");
+  for (int a = 0; a < 3; a++) {
+    if (d->root[a] < 1 || (int64_t(d->root[a]) << d->max_level) * d->block_cells >= (int64_t(1) << 30))
+      return fail(AMR_E_INVALID, "root extent out of range");
+    if (d->bc[a] != AMR_BC_PERIODIC && d->bc[a] != AMR_BC_OUTFLOW) return fail(AMR_E_INVALID, "bad boundary code");
+  }
+  if (!(d->gamma > 1.0)) return fail(AMR_E_INVALID, "gamma must exceed 1");
+  if (!(d->cfl > 0.0)) return fail(AMR_E_INVALID, "cfl must be positive");
+  if (d->riemann_iters < 0 || d->riemann_iters > 64) return fail(AMR_E_INVALID, "riemann_iters out of range");
+  if (d->n_refine < 0 || (d->n_refine > 0 && !d->refine)) return fail(AMR_E_INVALID, "bad refine list");
+  for (int a = 0; a < 3; a++) m.root[a] = d->root[a], m.bc[a] = d->bc[a];
+  m.N = d->block_cells;
+  m.max_level = d->max_level;
+  m.gamma = d->gamma;
+  m.cfl = d->cfl;
+  m.rho_floor = d->rho_floor;
+  m.p_floor = d->p_floor;
+  m.iters = d->riemann_iters;
+  return AMR_OK;
+}
+
+amr_status finish(amr_mesh* h, amr_mesh** out) {
+  std::vector<const Octree*> v{h->tree.get()};
+  std::string e = h->plan.build(v);
+  if (!e.empty()) {
+    delete h;
+    return fail(AMR_E_BALANCE, e);
+  }
+  bool outflow = false;
+  for (int a = 0; a < 3; a++) outflow = outflow || h->tree->desc().bc[a] == AMR_BC_OUTFLOW;
+  if (outflow)
+    for (const Key& k : h->plan.keys)
+      if (k.l != 0) {
+        delete h;
+        return fail(AMR_E_INVALID, "outflow boundaries need a single-level mesh");
+      }
+  *out = h;
+  return AMR_OK;
+}
+
+DevPlan dev_plan(const amr_mesh* h) {
+  const Plan& p = h->plan;
+  DevPlan P{};
+  unsigned char* w = h->ws;
+  P.inst = reinterpret_cast<const InstParams*>(w + p.off.inst);
+  P.blocks = reinterpret_cast<const BlockInfo*>(w + p.off.blocks);
+  P.nbr = reinterpret_cast<const Nbr*>(w + p.off.nbr);
+  P.fine = reinterpret_cast<const int32_t*>(w + p.off.fine);
+  P.p2list = reinterpret_cast<const int32_t*>(w + p.off.p2list);
+  P.faceslot = reinterpret_cast<const int32_t*>(w + p.off.faceslot);
+  for (int d = 0; d < 3; d++) {
+    P.reflux[d] = reinterpret_cast<const RefluxTask*>(w + p.off.reflux[d]);
+    P.nreflux[d] = int64_t(p.reflux[d].size());
+  }
+  P.acc = reinterpret_cast<unsigned long long*>(w + p.off.acc);
+  P.counters = reinterpret_cast<unsigned long long*>(w + p.off.counters);
+  P.faces = reinterpret_cast<double*>(w + p.off.faces);
+  P.nleaf = p.nleaf;
+  P.np2 = int64_t(p.p2list.size());
+  P.ninst = int32_t(p.inst.size());
+  P.N = p.N;
+  return P;
+}
+
+amr_status check_ready(const amr_mesh* h, const void* U) {
+  if (!h) return fail(AMR_E_INVALID, "null mesh");
+  if (!h->ws) return fail(AMR_E_STATE, "no workspace uploaded (call amr_mesh_upload first)");
+  if (!U) return fail(AMR_E_INVALID, "null field pointer");
+  return AMR_OK;
+}
+
+amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index, hipStream_t st) {
+  const DevPlan P = dev_plan(h);
+  hipError_t e = launch_refresh(P, U, h->cfg, st);
+  if (e != hipSuccess) return hip_fail(e, "refresh");
+  int order[3] = {0, 1, 2};
+  if (step_index & 1) {
+    order[0] = 2;
+    order[2] = 0;
+  }
+  int swept[3] = {0, 0, 0};
+  for (int s = 0; s < 3; s++) {
+    e = launch_sweep(P, U, dt, order[s], swept, h->cfg, st);
+    if (e != hipSuccess) return hip_fail(e, "sweep");
+    swept[order[s]] = 1;
+  }
+  for (int d = 0; d < 3; d++) {
+    e = launch_reflux(P, U, dt, d, h->cfg, st);
+    if (e != hipSuccess) return hip_fail(e, "reflux");
+  }
+  return AMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out) {
+  if (!out) return fail(AMR_E_INVALID, "null output pointer");
+  *out = nullptr;
+  MeshDesc m{};
+  amr_status rc = to_desc(desc, m);
+  if (rc != AMR_OK) return rc;
+  amr_mesh* h = new (std::nothrow) amr_mesh();
+  if (!h) return fail(AMR_E_NOMEM, "out of host memory");
+  h->tree.reset(new Octree(m));
+  std::string e = h->tree->refine_list(desc->refine, desc->n_refine);
+  if (!e.empty()) {
+    delete h;
+    return fail(AMR_E_INVALID, e);
+  }
+  return finish(h, out);
+}
+
+amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n, const int32_t* keys,
+                                       amr_mesh** out) {
+  if (!out) return fail(AMR_E_INVALID, "null output pointer");
+  *out = nullptr;
+  MeshDesc m{};
+  amr_status rc = to_desc(desc, m);
+  if (rc != AMR_OK) return rc;
+  if (n <= 0 || !keys) return fail(AMR_E_INVALID, "empty leaf list");
+  amr_mesh* h = new (std::nothrow) amr_mesh();
+  if (!h) return fail(AMR_E_NOMEM, "out of host memory");
+  h->tree.reset(new Octree(m));
+  std::string e = h->tree->from_leaves(keys, n);
+  if (!e.empty()) {
+    delete h;
+    return fail(AMR_E_BALANCE, e);
+  }
+  return finish(h, out);
+}
+
+amr_status amr_mesh_destroy(amr_mesh* mesh) {
+  delete mesh;
+  return AMR_OK;
+}
+
+amr_status amr_mesh_info(const amr_mesh* h, amr_mesh_info_t* out) {
+  if (!h || !out) return fail(AMR_E_INVALID, "null argument");
+  std::memset(out, 0, sizeof *out);
+  const Plan& p = h->plan;
+  out->n_leaves = p.nleaf;
+  out->block_cells = p.N;
+  out->padded = p.M;
+  out->field_stride = int64_t(p.M) * p.M * p.M;
+  out->block_stride = kFields * out->field_stride;
+  out->field_bytes = p.nleaf * out->block_stride * 8;
+  out->workspace_bytes = p.off.total;
+  out->n_cf_faces = p.nslots;
+  for (const Key& k : p.keys)
+    if (k.l < 8) out->levels[k.l]++;
+  return AMR_OK;
+}
+
+amr_status amr_mesh_blocks(const amr_mesh* h, int32_t* keys_out, int64_t cap) {
+  if (!h || !keys_out) return fail(AMR_E_INVALID, "null argument");
+  if (cap < h->plan.nleaf) return fail(AMR_E_INVALID, "output too small");
+  for (int64_t s = 0; s < h->plan.nleaf; s++) {
+    const Key& k = h->plan.keys[size_t(s)];
+    keys_out[4 * s] = k.l;
+    keys_out[4 * s + 1] = k.i;
+    keys_out[4 * s + 2] = k.j;
+    keys_out[4 * s + 3] = k.k;
+  }
+  return AMR_OK;
+}
+
+amr_status amr_mesh_upload(amr_mesh* h, void* ws, void* stream) {
+  if (!h || !ws) return fail(AMR_E_INVALID, "null argument");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(AMR_E_INVALID, "workspace must be 256-byte aligned");
+  hipError_t e = hipMemcpyAsync(ws, h->plan.staging.data(), h->plan.staging.size(), hipMemcpyHostToDevice,
+                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "upload");
+  h->ws = static_cast<unsigned char*>(ws);
+  return AMR_OK;
+}
+
+amr_status amr_refresh_ghosts(amr_mesh* h, double* U, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  hipError_t e = launch_refresh(dev_plan(h), U, h->cfg, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "refresh");
+}
+
+amr_status amr_cfl_dt(amr_mesh* h, const double* U, double* dt, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  hipError_t e = launch_cfl(dev_plan(h), U, dt, h->cfg, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "cfl");
+}
+
+amr_status amr_hydro_step(amr_mesh* h, double* U, double* dt, int64_t step_index, void* stream) {
+  amr_status rc = amr_cfl_dt(h, U, dt, stream);
+  if (rc != AMR_OK) return rc;
+  return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_floor_count(amr_mesh* h, int64_t* out, void* stream) {
+  if (!h || !out) return fail(AMR_E_INVALID, "null argument");
+  if (!h->ws) return fail(AMR_E_STATE, "no workspace uploaded");
+  unsigned long long v = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&v, h->ws + h->plan.off.counters, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "floor count");
+  *out = int64_t(v);
+  return AMR_OK;
+}
+
+const char* amr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

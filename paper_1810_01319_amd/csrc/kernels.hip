@@ -1,0 +1,672 @@
+// kernels.hip -- gfx950 kernels of one AMR hydro step.
+//
+// Paper Sec. II-B (ghost refresh of width 3 for the 5 conserved fields,
+// Restrict / Prolong across 2:1 jumps) and Sec. II-C (the PPM Method).
+// Built with -ffp-contract=off: no fused multiply-add, so every formula
+// rounds exactly as written; FP64 '/' and sqrt are IEEE correctly rounded
+// on gfx950.  min/max are selects (a < b ? a : b).
+//
+// Storage: per leaf 5 fields of M^3 doubles, M = N + 6, x fastest.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace amr {
+
+namespace {
+
+constexpr int G = kGhost;
+
+__device__ __forceinline__ double sel_min(double a, double b) { return a < b ? a : b; }
+__device__ __forceinline__ double sel_max(double a, double b) { return a < b ? b : a; }
+
+// dx at level l: cubic cells, x extent 1.
+__device__ __forceinline__ double level_dx(const InstParams& ip, int N, int l) {
+  return 1.0 / (double)((int64_t)ip.root[0] * N << l);
+}
+
+// ---------------------------------------------------------------------------
+// Ghost refresh
+// ---------------------------------------------------------------------------
+
+// Flat ghost index -> padded (a, b, c): 3 full z-layers, N middle layers
+// (3 full rows, N rows of 3+3 cells, 3 full rows), 3 full z-layers.
+template <int N>
+__device__ __forceinline__ void ghost_decode(int g, int& a, int& b, int& c) {
+  constexpr int M = N + 2 * G;
+  constexpr int L2 = M * M;
+  constexpr int SLAB = 3 * L2;
+  constexpr int MID = 6 * M + 6 * N;
+  if (g < SLAB) {
+    c = g / L2;
+    const int r = g - c * L2;
+    b = r / M;
+    a = r - b * M;
+    return;
+  }
+  g -= SLAB;
+  if (g < N * MID) {
+    const int cz = g / MID;
+    int r = g - cz * MID;
+    c = G + cz;
+    if (r < 3 * M) {
+      b = r / M;
+      a = r - b * M;
+      return;
+    }
+    r -= 3 * M;
+    if (r < 6 * N) {
+      const int row = r / 6;
+      const int t = r - row * 6;
+      b = G + row;
+      a = t < 3 ? t : N + t;
+      return;
+    }
+    r -= 6 * N;
+    const int row = r / M;
+    b = N + G + row;
+    a = r - row * M;
+    return;
+  }
+  g -= N * MID;
+  const int cz = g / L2;
+  const int r = g - cz * L2;
+  c = N + G + cz;
+  b = r / M;
+  a = r - b * M;
+}
+
+template <int N>
+__device__ __forceinline__ int dir_code(int a, int b, int c) {
+  const int sx = a < G ? 0 : (a < N + G ? 1 : 2);
+  const int sy = b < G ? 0 : (b < N + G ? 1 : 2);
+  const int sz = c < G ? 0 : (c < N + G ? 1 : 2);
+  return sx + 3 * sy + 9 * sz;
+}
+
+// Global level-l index of a ghost cell after the physical boundary: periodic
+// wraps, outflow clamps to the nearest domain cell.
+template <int N>
+__device__ __forceinline__ int bc_index(const InstParams& ip, int l, int ax, int p) {
+  const int n = (ip.root[ax] << l) * N;
+  if (p >= 0 && p < n) return p;
+  if (ip.bc[ax] == 0) return p < 0 ? p + n : p - n;
+  return p < 0 ? 0 : n - 1;
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  return (a * b > 0.0) ? (fabs(a) < fabs(b) ? a : b) : 0.0;
+}
+
+// Phase 1: same-level copies (incl. outflow clamps) and restriction.
+template <int N>
+__global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int GC = M * M * M - N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * GC) return;
+  const int s = int(t / GC);
+  const int g = int(t - int64_t(s) * GC);
+  int a, b, c;
+  ghost_decode<N>(g, a, b, c);
+  const Nbr e = P.nbr[27 * int64_t(s) + dir_code<N>(a, b, c)];
+  if (e.kind == NBR_COARSE) return;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const int l = bi.level;
+  const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
+  const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
+  const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
+  double* dst = U + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  if (e.kind == NBR_COPY) {
+    const BlockInfo sb = P.blocks[e.id];
+    const int la = px - sb.i * N + G, lb = py - sb.j * N + G, lc = pz - sb.k * N + G;
+    const double* src = U + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) dst[f * M3] = src[f * M3];
+  } else {
+    // mean of the 8 children, summed x fastest then y then z
+    const int qx = 2 * px, qy = 2 * py, qz = 2 * pz;
+    const int cidx = ((qx / N) & 1) + 2 * ((qy / N) & 1) + 4 * ((qz / N) & 1);
+    const int fs = P.fine[8 * int64_t(e.id) + cidx];
+    const int la = qx % N + G, lb = qy % N + G, lc = qz % N + G;
+    const double* src = U + int64_t(fs) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) {
+      const double* q = src + f * M3;
+      const double v0 = q[0], v1 = q[1], v2 = q[M], v3 = q[M + 1];
+      const double v4 = q[M * M], v5 = q[M * M + 1], v6 = q[M * M + M], v7 = q[M * M + M + 1];
+      dst[f * M3] = (((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7))) * 0.125;
+    }
+  }
+}
+
+// Phase 2: limited linear prolongation from the coarser leaf, whose active
+// and phase-1 ghost cells are complete.
+template <int N>
+__global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int GC = M * M * M - N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.np2 * GC) return;
+  const int w = int(t / GC);
+  const int g = int(t - int64_t(w) * GC);
+  const int s = P.p2list[w];
+  int a, b, c;
+  ghost_decode<N>(g, a, b, c);
+  const Nbr e = P.nbr[27 * int64_t(s) + dir_code<N>(a, b, c)];
+  if (e.kind != NBR_COARSE) return;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const int l = bi.level;
+  const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
+  const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
+  const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
+  const BlockInfo cb = P.blocks[e.id];
+  const int la = (px >> 1) - cb.i * N + G, lb = (py >> 1) - cb.j * N + G, lc = (pz >> 1) - cb.k * N + G;
+  const double ox = (px & 1) ? 0.25 : -0.25;
+  const double oy = (py & 1) ? 0.25 : -0.25;
+  const double oz = (pz & 1) ? 0.25 : -0.25;
+  const double* src = U + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+  double* dst = U + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+#pragma unroll
+  for (int f = 0; f < kFields; f++) {
+    const double* q = src + f * M3;
+    const double u0 = q[0];
+    const double sx = minmod(q[1] - u0, u0 - q[-1]);
+    const double sy = minmod(q[M] - u0, u0 - q[-M]);
+    const double sz = minmod(q[M * M] - u0, u0 - q[-M * M]);
+    dst[f * M3] = ((u0 + ox * sx) + oy * sy) + oz * sz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction
+// ---------------------------------------------------------------------------
+
+template <int N>
+__global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, DevPlan P, int chunks) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int N3 = N * N * N;
+  const int s = blockIdx.x / chunks;
+  const int ch = blockIdx.x - s * chunks;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const double dx = level_dx(ip, N, bi.level);
+  const double* B = U + int64_t(s) * kFields * M3;
+  const int per = N3 / chunks;
+  double best = __builtin_huge_val();
+  for (int q = ch * per + threadIdx.x; q < (ch + 1) * per; q += blockDim.x) {
+    const int x = q % N, y = (q / N) % N, z = q / (N * N);
+    const int64_t o = (int64_t(z + G) * M + (y + G)) * M + (x + G);
+    const double rho = B[o];
+    const double ir = 1.0 / rho;
+    const double u = B[o + M3] * ir, v = B[o + 2 * M3] * ir, w = B[o + 3 * M3] * ir;
+    double p = ip.gm1 * (B[o + 4 * M3] - (0.5 * rho) * ((u * u + v * v) + w * w));
+    p = p < ip.p_floor ? ip.p_floor : p;
+    const double cs = sqrt((ip.gamma * p) * ir);
+    const double vm = sel_max(sel_max(fabs(u), fabs(v)), fabs(w));
+    const double dtc = dx / (vm + cs);
+    best = dtc < best ? dtc : best;
+  }
+  // wave64 then workgroup minimum; the minimum is exact in any order
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(best, off, 64);
+    best = o < best ? o : best;
+  }
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < int(blockDim.x >> 6); i++) best = red[i] < best ? red[i] : best;
+    // positive doubles order like their bit patterns
+    atomicMin(&P.acc[bi.inst], (unsigned long long)__double_as_longlong(best));
+  }
+}
+
+__global__ void cfl_finalize(DevPlan P, double* __restrict__ dt) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= P.ninst) return;
+  const double mn = __longlong_as_double((long long)P.acc[m]);
+  dt[m] = P.inst[m].cfl * mn;
+  P.acc[m] = 0x7FF0000000000000ull;
+}
+
+// ---------------------------------------------------------------------------
+// PPM sweep: one lane walks one pencil along the sweep axis with a sliding
+// register window; cells are read once and updated in place three cells
+// behind the read front (the stencil of a cell update is 7 cells wide).
+// ---------------------------------------------------------------------------
+
+struct Par {
+  double qL, qR, dq, q6;
+};
+
+// MC-limited slope of the middle value.
+__device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
+  const double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
+  const double lim = sel_min(sel_min(fabs(dc), 2.0 * fabs(dl)), 2.0 * fabs(dr));
+  const double d = dc > 0.0 ? lim : -lim;
+  return (dl * dr > 0.0) ? d : 0.0;
+}
+
+// Flattened, monotonised parabola of one cell.
+__device__ __forceinline__ Par parabola(double q, double qL, double qR, double f, double sixth) {
+  qL = f * q + (1.0 - f) * qL;
+  qR = f * q + (1.0 - f) * qR;
+  Par P;
+  if ((qR - q) * (q - qL) <= 0.0) {
+    qL = q;
+    qR = q;
+  } else {
+    const double D = qR - qL, mm = q - 0.5 * (qL + qR);
+    const double D26 = (D * D) * sixth;
+    if (D * mm > D26)
+      qL = 3.0 * q - 2.0 * qR;
+    else if (-D26 > D * mm)
+      qR = 3.0 * q - 2.0 * qL;
+  }
+  P.qL = qL;
+  P.qR = qR;
+  P.dq = qR - qL;
+  P.q6 = 6.0 * (q - 0.5 * (qL + qR));
+  return P;
+}
+
+// Mean of the parabola over the fraction s of the cell next to its right
+// (Ip) or left (Im) edge.
+__device__ __forceinline__ double Ip(const Par& P, double s, double two3) {
+  return P.qR - (0.5 * s) * (P.dq - (1.0 - two3 * s) * P.q6);
+}
+__device__ __forceinline__ double Im(const Par& P, double s, double two3) {
+  return P.qL + (0.5 * s) * (P.dq + (1.0 - two3 * s) * P.q6);
+}
+
+// Characteristic tracing of one cell (rho, u, c, 1/rho and its 5 parabolas
+// in the order rho, u, v, w, p) to the left state at its right edge (WL)
+// and the right state at its left edge (WR).
+__device__ __forceinline__ void trace(const InstParams& ip, double rho, double u, double c, double ir,
+                                      const Par* pa, double nu, double* WL, double* WR) {
+  const double two3 = ip.two3;
+  const double lm = u - c, l0 = u, lp = u + c;
+  const double Ac = rho / (2.0 * c);
+  const double Bc = 1.0 / (rho * c);
+  const double cc = c * c;
+  const double ic2 = 1.0 / cc;
+  const double cor = c * ir;
+  {
+    const double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
+    const double rr = Ip(pa[0], sp, two3), ur = Ip(pa[1], sp, two3), pr = Ip(pa[4], sp, two3);
+    const double am = (lm > 0.0) ? Ac * ((pr - Ip(pa[4], sm, two3)) * Bc - (ur - Ip(pa[1], sm, two3))) : 0.0;
+    const double a0 = (l0 > 0.0) ? (rr - Ip(pa[0], s0, two3)) - (pr - Ip(pa[4], s0, two3)) * ic2 : 0.0;
+    const double r = (rr - am) - a0;
+    const double p = pr - cc * am;
+    WL[0] = r < ip.rho_floor ? ip.rho_floor : r;
+    WL[1] = ur + cor * am;
+    WL[2] = Ip(pa[2], s0, two3);
+    WL[3] = Ip(pa[3], s0, two3);
+    WL[4] = p < ip.p_floor ? ip.p_floor : p;
+  }
+  {
+    const double sm = (lm < 0.0 ? -lm : 0.0) * nu, s0 = (l0 < 0.0 ? -l0 : 0.0) * nu, sp = (lp < 0.0 ? -lp : 0.0) * nu;
+    const double rr = Im(pa[0], sm, two3), ur = Im(pa[1], sm, two3), pr = Im(pa[4], sm, two3);
+    const double ap = (lp < 0.0) ? Ac * ((pr - Im(pa[4], sp, two3)) * Bc + (ur - Im(pa[1], sp, two3))) : 0.0;
+    const double a0 = (l0 < 0.0) ? (rr - Im(pa[0], s0, two3)) - (pr - Im(pa[4], s0, two3)) * ic2 : 0.0;
+    const double r = (rr - ap) - a0;
+    const double p = pr - cc * ap;
+    WR[0] = r < ip.rho_floor ? ip.rho_floor : r;
+    WR[1] = ur - cor * ap;
+    WR[2] = Im(pa[2], s0, two3);
+    WR[3] = Im(pa[3], s0, two3);
+    WR[4] = p < ip.p_floor ? ip.p_floor : p;
+  }
+}
+
+// Two-shock Riemann solver (fixed Newton steps on p*), sampled at x/t = 0,
+// linear fan between head and tail; returns the flux.
+__device__ __forceinline__ void riemann_flux(const InstParams& ip, const double* L, const double* R, double* F) {
+  const double rL = L[0], uL = L[1], pL = L[4];
+  const double rR = R[0], uR = R[1], pR = R[4];
+  const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
+  const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
+  const double CL2 = CL * CL, CR2 = CR * CR;
+  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
+  double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
+  ps = ps < pfl ? pfl : ps;
+  double WLw, WRw, ZL, ZR, usL, usR;
+  for (int it = 0;; it++) {
+    WLw = CL * sqrt(1.0 + g1 * (ps * ipL - 1.0));
+    WRw = CR * sqrt(1.0 + g1 * (ps * ipR - 1.0));
+    const double W2L = WLw * WLw, W2R = WRw * WRw;
+    ZL = ((2.0 * WLw) * W2L) / (W2L + CL2);
+    ZR = ((2.0 * WRw) * W2R) / (W2R + CR2);
+    usL = uL - (ps - pL) / WLw;
+    usR = uR + (ps - pR) / WRw;
+    if (it == ip.iters) break;
+    ps = ps - ((ZL * ZR) * (usR - usL)) / (ZL + ZR);
+    ps = ps < pfl ? pfl : ps;
+  }
+  const double us = (ZL * usL + ZR * usR) / (ZL + ZR);
+  const bool left = us >= 0.0;
+  const double s = left ? 1.0 : -1.0;
+  const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
+  const double WK = left ? WLw : WRw;
+  const double vs = 1.0 / rK - (ps - pK) / (WK * WK);
+  const double rs = 1.0 / vs;
+  double rg, ug, pg;
+  if (ps > pK) {
+    const double S = uK - s * (WK / rK);
+    const bool toK = s * S >= 0.0;
+    rg = toK ? rK : rs;
+    ug = toK ? uK : us;
+    pg = toK ? pK : ps;
+  } else {
+    const double cK = sqrt((gam * pK) / rK);
+    const double cs = sqrt((gam * ps) * vs);
+    const double lh = uK - s * cK, lt = us - s * cs;
+    if (s * lh >= 0.0) {
+      rg = rK; ug = uK; pg = pK;
+    } else if (s * lt <= 0.0) {
+      rg = rs; ug = us; pg = ps;
+    } else {
+      const double xi = lh / (lh - lt);
+      rg = rK + xi * (rs - rK);
+      ug = uK + xi * (us - uK);
+      pg = pK + xi * (ps - pK);
+    }
+  }
+  const double vg = left ? L[2] : R[2], wg = left ? L[3] : R[3];
+  const double mf = rg * ug;
+  F[0] = mf;
+  F[1] = mf * ug + pg;
+  F[2] = mf * vg;
+  F[3] = mf * wg;
+  F[4] = ug * (pg * ip.g_gm1 + (0.5 * rg) * ((ug * ug + vg * vg) + wg * wg));
+}
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
+                                                    DevPlan P, int loA, int nA, int loB, int nB) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;  // velocity roles
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  const int64_t npen = int64_t(nA) * nB;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * npen) return;
+  const int s = int(t / npen);
+  const int pp = int(t - int64_t(s) * npen);
+  const int iA = loA + pp % nA, iB = loB + pp / nA;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
+  double* const base = U + int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
+  double* const pr_ = base;
+  double* const pn_ = base + (1 + DIR) * M3;
+  double* const p1_ = base + (1 + T1) * M3;
+  double* const p2_ = base + (1 + T2) * M3;
+  double* const pe_ = base + 4 * M3;
+  const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
+  int slot_lo = -1, slot_hi = -1;
+  if (faces_act) {
+    slot_lo = P.faceslot[6 * int64_t(s) + 2 * DIR];
+    slot_hi = P.faceslot[6 * int64_t(s) + 2 * DIR + 1];
+  }
+  const int64_t face_off = int64_t(iB - G) * N + (iA - G);
+  const double gm1 = ip.gm1, pfl = ip.p_floor, rfl = ip.rho_floor, sixth = ip.sixth;
+
+  // windows: rho, v, w over cells t-2..t; u over t-3..t; p over t-4..t;
+  // c and 1/rho over t-2..t
+  double rw[3], vw[3], ww[3], uw[4], pw[5], cw[3], iw[3];
+  double dl[5][2];   // slopes of cells t-2, t-1
+  double fold[5];    // face value at (t-3)+1/2
+  double WLp[5];     // left state at (t-3)+1/2 from cell t-3
+  double Fp[5];      // flux at (t-4)+1/2
+  unsigned nfl = 0;
+  // prefetch cell 0
+  double nx0 = pr_[0], nx1 = pn_[0], nx2 = p1_[0], nx3 = p2_[0], nx4 = pe_[0];
+  for (int c = 0; c < M; c++) {
+    const double U0 = nx0, U1 = nx1, U2 = nx2, U3 = nx3, U4 = nx4;
+    if (c + 1 < M) {
+      const int64_t o = int64_t(c + 1) * SD;
+      nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
+    }
+    // primitives of cell c
+    const double ir = 1.0 / U0;
+    const double u = U1 * ir, v = U2 * ir, w = U3 * ir;
+    double p = gm1 * (U4 - (0.5 * U0) * ((u * u + v * v) + w * w));
+    p = p < pfl ? pfl : p;
+    const double cs = sqrt((ip.gamma * p) * ir);
+    rw[0] = rw[1]; rw[1] = rw[2]; rw[2] = U0;
+    vw[0] = vw[1]; vw[1] = vw[2]; vw[2] = v;
+    ww[0] = ww[1]; ww[1] = ww[2]; ww[2] = w;
+    uw[0] = uw[1]; uw[1] = uw[2]; uw[2] = uw[3]; uw[3] = u;
+    pw[0] = pw[1]; pw[1] = pw[2]; pw[2] = pw[3]; pw[3] = pw[4]; pw[4] = p;
+    cw[0] = cw[1]; cw[1] = cw[2]; cw[2] = cs;
+    iw[0] = iw[1]; iw[1] = iw[2]; iw[2] = ir;
+    if (c < 2) continue;
+    // slope of cell c-1
+#pragma unroll
+    for (int q = 0; q < 5; q++) dl[q][0] = dl[q][1];
+    dl[0][1] = mc_slope(rw[0], rw[1], rw[2]);
+    dl[1][1] = mc_slope(uw[1], uw[2], uw[3]);
+    dl[2][1] = mc_slope(vw[0], vw[1], vw[2]);
+    dl[3][1] = mc_slope(ww[0], ww[1], ww[2]);
+    dl[4][1] = mc_slope(pw[2], pw[3], pw[4]);
+    if (c < 3) continue;
+    // face value at (c-2)+1/2
+    double fnew[5];
+    fnew[0] = 0.5 * (rw[0] + rw[1]) - (dl[0][1] - dl[0][0]) * sixth;
+    fnew[1] = 0.5 * (uw[1] + uw[2]) - (dl[1][1] - dl[1][0]) * sixth;
+    fnew[2] = 0.5 * (vw[0] + vw[1]) - (dl[2][1] - dl[2][0]) * sixth;
+    fnew[3] = 0.5 * (ww[0] + ww[1]) - (dl[3][1] - dl[3][0]) * sixth;
+    fnew[4] = 0.5 * (pw[2] + pw[3]) - (dl[4][1] - dl[4][0]) * sixth;
+    if (c >= 4) {
+      // cell j = c-2: flattening, parabolas, tracing
+      const double pp1 = pw[3], pm1 = pw[1];
+      const double dp1 = pp1 - pm1;
+      const double pmin = pp1 < pm1 ? pp1 : pm1;
+      const bool shock = (fabs(dp1) > 0.33 * pmin) && (uw[0] - uw[2] > 0.0);
+      const double dp2 = pw[4] - pw[0];
+      const double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+      double ft = 10.0 * (r - 0.75);
+      ft = ft < 1.0 ? ft : 1.0;
+      ft = ft > 0.0 ? ft : 0.0;
+      const double f = shock ? ft : 0.0;
+      Par pa[5];
+      pa[0] = parabola(rw[0], fold[0], fnew[0], f, sixth);
+      pa[1] = parabola(uw[1], fold[1], fnew[1], f, sixth);
+      pa[2] = parabola(vw[0], fold[2], fnew[2], f, sixth);
+      pa[3] = parabola(ww[0], fold[3], fnew[3], f, sixth);
+      pa[4] = parabola(pw[2], fold[4], fnew[4], f, sixth);
+      double WL[5], WR[5];
+      trace(ip, rw[0], uw[1], cw[0], iw[0], pa, nu, WL, WR);
+      if (c >= 5) {
+        // flux at (c-3)+1/2 from cell c-3's right edge and cell c-2's left
+        double F[5];
+        riemann_flux(ip, WLp, WR, F);
+        if (c == G + 2 && slot_lo >= 0) {
+          double* fo = P.faces + int64_t(slot_lo) * kFields * N * N + face_off;
+          fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
+          fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+        }
+        if (c == N + G + 2 && slot_hi >= 0) {
+          double* fo = P.faces + int64_t(slot_hi) * kFields * N * N + face_off;
+          fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
+          fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+        }
+        if (c >= 6) {
+          // conservative update of cell c-3, then the floors
+          const int64_t o = int64_t(c - 3) * SD;
+          double r0 = pr_[o] - nu * (F[0] - Fp[0]);
+          const double m1 = pn_[o] - nu * (F[1] - Fp[1]);
+          const double m2 = p1_[o] - nu * (F[2] - Fp[2]);
+          const double m3 = p2_[o] - nu * (F[3] - Fp[3]);
+          double e = pe_[o] - nu * (F[4] - Fp[4]);
+          if (r0 < rfl) { r0 = rfl; nfl++; }
+          const double jr = 1.0 / r0;
+          const double a1 = m1 * jr, a2 = m2 * jr, a3 = m3 * jr;
+          const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
+          const double pn = gm1 * (e - ke);
+          if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
+          pr_[o] = r0; pn_[o] = m1; p1_[o] = m2; p2_[o] = m3; pe_[o] = e;
+        }
+#pragma unroll
+        for (int q = 0; q < 5; q++) Fp[q] = F[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; q++) WLp[q] = WL[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) fold[q] = fnew[q];
+  }
+  if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+}
+
+// ---------------------------------------------------------------------------
+// Reflux
+// ---------------------------------------------------------------------------
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) reflux_kernel(double* __restrict__ U, const double* __restrict__ dtv,
+                                                     DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nreflux[DIR] * N * N) return;
+  const int k = int(t / (N * N));
+  const int r = int(t - int64_t(k) * N * N);
+  const int tA = r % N, tB = r / N;
+  const RefluxTask T = P.reflux[DIR][k];
+  const BlockInfo bi = P.blocks[T.leaf];
+  const InstParams& ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
+  const int hA = tA >= N / 2, hB = tB >= N / 2;
+  const int fs = T.slot_f[hA + 2 * hB];
+  const int fA = 2 * tA - hA * N, fB = 2 * tB - hB * N;
+  const int d = T.side ? N + G - 1 : G;
+  double* cellp = U + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + tA) * SA + int64_t(G + tB) * SB;
+#pragma unroll
+  for (int f = 0; f < kFields; f++) {
+    const double Fc = P.faces[(int64_t(T.slot_c) * kFields + f) * N * N + int64_t(tB) * N + tA];
+    const double* Q = P.faces + (int64_t(fs) * kFields + f) * N * N;
+    const double fb = ((Q[fB * N + fA] + Q[fB * N + fA + 1]) + (Q[(fB + 1) * N + fA] + Q[(fB + 1) * N + fA + 1])) * 0.25;
+    const double corr = nu * (Fc - fb);
+    const double u = cellp[f * M3];
+    cellp[f * M3] = T.side ? u + corr : u - corr;
+  }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
+
+template <int N>
+hipError_t refresh_n(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
+  if (P.nleaf > 0)
+    hipLaunchKernelGGL(refresh_phase1<N>, dim3(grid_for(P.nleaf * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+  if (P.np2 > 0)
+    hipLaunchKernelGGL(refresh_phase2<N>, dim3(grid_for(P.np2 * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st) {
+  constexpr int N3 = N * N * N;
+  int chunks = N3 / (8 * 256);
+  if (chunks < 1) chunks = 1;
+  if (P.nleaf > 0)
+    hipLaunchKernelGGL(cfl_kernel<N>, dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
+  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt);
+  return hipGetLastError();
+}
+
+template <int N, int DIR>
+hipError_t sweep_nd(const DevPlan& P, double* U, const double* dt, const int swept[3], const LaunchCfg& L,
+                    hipStream_t st) {
+  constexpr int M = N + 2 * G;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  const int loA = swept[A] ? G : 0, nA = swept[A] ? N : M;
+  const int loB = swept[B] ? G : 0, nB = swept[B] ? N : M;
+  const int64_t n = P.nleaf * int64_t(nA) * nB;
+  if (n > 0)
+    hipLaunchKernelGGL((sweep_kernel<N, DIR>), dim3(grid_for(n, L.sweep_block)), dim3(L.sweep_block), 0, st, U, dt, P,
+                       loA, nA, loB, nB);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t sweep_n(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3], const LaunchCfg& L,
+                   hipStream_t st) {
+  if (dir == 0) return sweep_nd<N, 0>(P, U, dt, swept, L, st);
+  if (dir == 1) return sweep_nd<N, 1>(P, U, dt, swept, L, st);
+  return sweep_nd<N, 2>(P, U, dt, swept, L, st);
+}
+
+template <int N>
+hipError_t reflux_n(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L, hipStream_t st) {
+  const int64_t n = P.nreflux[dir] * N * N;
+  if (n == 0) return hipSuccess;
+  const dim3 g(grid_for(n, L.reflux_block)), b(L.reflux_block);
+  if (dir == 0) hipLaunchKernelGGL((reflux_kernel<N, 0>), g, b, 0, st, U, dt, P);
+  else if (dir == 1) hipLaunchKernelGGL((reflux_kernel<N, 1>), g, b, 0, st, U, dt, P);
+  else hipLaunchKernelGGL((reflux_kernel<N, 2>), g, b, 0, st, U, dt, P);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+
+hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
+  switch (P.N) {
+    case 8: return refresh_n<8>(P, U, L, st);
+    case 16: return refresh_n<16>(P, U, L, st);
+    case 32: return refresh_n<32>(P, U, L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st) {
+  switch (P.N) {
+    case 8: return cfl_n<8>(P, U, dt, L, st);
+    case 16: return cfl_n<16>(P, U, dt, L, st);
+    case 32: return cfl_n<32>(P, U, dt, L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
+                        const LaunchCfg& L, hipStream_t st) {
+  switch (P.N) {
+    case 8: return sweep_n<8>(P, U, dt, dir, swept, L, st);
+    case 16: return sweep_n<16>(P, U, dt, dir, swept, L, st);
+    case 32: return sweep_n<32>(P, U, dt, dir, swept, L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,
+                         hipStream_t st) {
+  switch (P.N) {
+    case 8: return reflux_n<8>(P, U, dt, dir, L, st);
+    case 16: return reflux_n<16>(P, U, dt, dir, L, st);
+    case 32: return reflux_n<32>(P, U, dt, dir, L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace amr

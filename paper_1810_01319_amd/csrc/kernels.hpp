@@ -1,0 +1,42 @@
+// kernels.hpp -- launchers of the gfx950 kernels of one hydro step.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.hpp"
+
+namespace amr {
+
+// Device view of a plan's workspace.
+struct DevPlan {
+  const InstParams* inst;
+  const BlockInfo* blocks;
+  const Nbr* nbr;
+  const int32_t* fine;
+  const int32_t* p2list;
+  const int32_t* faceslot;
+  const RefluxTask* reflux[3];
+  unsigned long long* acc;
+  unsigned long long* counters;
+  double* faces;
+  int64_t nleaf, np2, nreflux[3];
+  int32_t ninst, N;
+};
+
+struct LaunchCfg {
+  int refresh_block = 256;
+  int sweep_block = 128;
+  int cfl_block = 256;
+  int reflux_block = 256;
+};
+
+hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st);
+hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st);
+// sweep along dir; swept[a] = axis a already swept this step
+hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
+                        const LaunchCfg& L, hipStream_t st);
+hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,
+                         hipStream_t st);
+
+}  // namespace amr

@@ -1,0 +1,60 @@
+// layout.hpp -- device-visible tables of an execution plan (one or more
+// meshes flattened into one worklist of leaf blocks).
+//
+// Every table lives in one caller-owned device workspace; offsets are
+// 256-byte aligned.  The host builds the same bytes in one staging buffer and
+// uploads them with a single copy.
+#pragma once
+#include <cstdint>
+
+namespace amr {
+
+constexpr int kGhost = 3;
+constexpr int kFields = 5;
+
+// Per mesh instance: gas constants in the exact forms the formulas use
+// (computed once on the host in FP64) and the geometry.
+struct InstParams {
+  double gamma, gm1, inv_gm1, g_gm1, g1;
+  double rho_floor, p_floor, cfl;
+  double sixth, two3;
+  int32_t root[3];
+  int32_t bc[3];
+  int32_t iters;
+  int32_t pad0;
+  int64_t first_leaf;  // first block of this instance in the plan
+  int64_t n_leaf;
+};
+static_assert(sizeof(InstParams) % 8 == 0, "InstParams packing");
+
+struct BlockInfo {
+  int32_t level, i, j, k;
+  int32_t inst;
+  int32_t pad[3];
+};
+
+// Neighbour of a leaf in one of the 26 directions (code = (sx+1) +
+// 3 (sy+1) + 9 (sz+1), code 13 unused): where its ghost box comes from.
+enum NbrKind : int32_t {
+  NBR_COPY = 0,    // same-level leaf `id` (after periodic wrap or outflow clamp)
+  NBR_FINE = 1,    // refined same-level position: children in fine table row `id`
+  NBR_COARSE = 2,  // absent same-level position: covering leaf `id` one level up
+};
+struct Nbr {
+  int32_t kind, id;
+};
+
+// Reflux task: a coarse leaf's face whose same-level neighbour position is
+// refined.  The fine face fluxes of the 4 children touching it correct the
+// coarse face cells.
+struct RefluxTask {
+  int32_t leaf, side, slot_c;
+  int32_t slot_f[4];  // child face slots by quadrant (hA + 2 hB)
+  int32_t pad;
+};
+
+struct PlanOffsets {
+  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, faces, total;
+};
+
+}  // namespace amr

@@ -1,0 +1,342 @@
+// mesh.cpp -- octree, 2:1 balance and plan tables (host side).
+//
+// The array-of-octrees of the paper (Sec. II-B): a root array of octrees, a
+// Block per node, leaves carry data.  Refinement keeps neighbouring leaves
+// (across faces, edges and corners, periodic wrap included) within one level
+// of each other, which bounds every ghost cell's source to one level of
+// difference and lets the two-phase refresh read only copied or restricted
+// values when it prolongs.
+#include "mesh.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace amr {
+
+InstParams make_inst_params(const MeshDesc& d) {
+  InstParams p{};
+  p.gamma = d.gamma;
+  p.gm1 = d.gamma - 1.0;
+  p.inv_gm1 = 1.0 / (d.gamma - 1.0);
+  p.g_gm1 = d.gamma / (d.gamma - 1.0);
+  p.g1 = (d.gamma + 1.0) / (2.0 * d.gamma);
+  p.rho_floor = d.rho_floor;
+  p.p_floor = d.p_floor;
+  p.cfl = d.cfl;
+  p.sixth = 1.0 / 6.0;
+  p.two3 = 2.0 / 3.0;
+  for (int a = 0; a < 3; a++) {
+    p.root[a] = d.root[a];
+    p.bc[a] = d.bc[a];
+  }
+  p.iters = d.iters;
+  return p;
+}
+
+Octree::Octree(const MeshDesc& d) : d_(d) {
+  for (int k = 0; k < d.root[2]; k++)
+    for (int j = 0; j < d.root[1]; j++)
+      for (int i = 0; i < d.root[0]; i++) node_[pack(0, i, j, k)] = LEAF;
+}
+
+uint8_t Octree::state(int l, int i, int j, int k) const {
+  auto it = node_.find(pack(l, i, j, k));
+  return it == node_.end() ? ABSENT : it->second;
+}
+
+bool Octree::wrap(int l, int ax, int& v) const {
+  const int e = ext(l, ax);
+  if (v >= 0 && v < e) return true;
+  if (d_.bc[ax] != 0) return false;
+  v = ((v % e) + e) % e;
+  return true;
+}
+
+void Octree::refine(int l, int i, int j, int k) {
+  node_[pack(l, i, j, k)] = REFINED;
+  for (int c = 0; c < 8; c++)
+    node_[pack(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2))] = LEAF;
+}
+
+std::string Octree::refine_list(const int32_t* keys, int64_t n) {
+  for (int64_t r = 0; r < n; r++) {
+    const int32_t* e = keys + 4 * r;
+    const int l = e[0];
+    if (l < 0 || l >= d_.max_level) return "refine entry level out of range";
+    for (int a = 0; a < 3; a++)
+      if (e[1 + a] < 0 || e[1 + a] >= ext(l, a)) return "refine entry key out of range";
+    // walk down from the root, splitting leaves on the way
+    for (int a = 0; a <= l; a++) {
+      const int s = l - a;
+      const int i = e[1] >> s, j = e[2] >> s, k = e[3] >> s;
+      if (state(a, i, j, k) == LEAF) refine(a, i, j, k);
+    }
+  }
+  balance();
+  return "";
+}
+
+// Level-by-level balance, finest first: a leaf at level l needs every
+// neighbouring position's level-(l-1) node to exist; creating it only adds
+// nodes at levels <= l-1, which are handled when their level comes.
+void Octree::balance() {
+  for (int l = d_.max_level; l >= 2; l--) {
+    std::vector<Key> level_leaves;
+    for (const auto& kv : node_) {
+      if (kv.second != LEAF || int(kv.first >> 60) != l) continue;
+      const uint64_t p = kv.first;
+      level_leaves.push_back({l, int(p & 0xFFFFF), int((p >> 20) & 0xFFFFF), int((p >> 40) & 0xFFFFF)});
+    }
+    for (const Key& lf : level_leaves) {
+      for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dx = -1; dx <= 1; dx++) {
+            if (!dx && !dy && !dz) continue;
+            int q[3] = {lf.i + dx, lf.j + dy, lf.k + dz};
+            bool in = true;
+            for (int a = 0; a < 3; a++) in = in && wrap(l, a, q[a]);
+            if (!in) continue;
+            const int t = l - 1;  // target level that must exist
+            for (int a = 0; a < t; a++) {
+              const int s = l - a;
+              const int i = q[0] >> s, j = q[1] >> s, k = q[2] >> s;
+              if (state(a, i, j, k) == LEAF) refine(a, i, j, k);
+            }
+          }
+    }
+  }
+}
+
+std::string Octree::check_balance() const {
+  for (const auto& kv : node_) {
+    if (kv.second != LEAF) continue;
+    const int l = int(kv.first >> 60);
+    if (l < 2) continue;
+    const int i = int(kv.first & 0xFFFFF), j = int((kv.first >> 20) & 0xFFFFF), k = int((kv.first >> 40) & 0xFFFFF);
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          if (!dx && !dy && !dz) continue;
+          int q[3] = {i + dx, j + dy, k + dz};
+          bool in = true;
+          for (int a = 0; a < 3; a++) in = in && wrap(l, a, q[a]);
+          if (!in) continue;
+          if (state(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1) == ABSENT) return "leaves violate 2:1 balance";
+        }
+  }
+  return "";
+}
+
+std::string Octree::from_leaves(const int32_t* keys, int64_t n) {
+  node_.clear();
+  for (int64_t s = 0; s < n; s++) {
+    const int32_t* e = keys + 4 * s;
+    const int l = e[0];
+    if (l < 0 || l > d_.max_level) return "leaf level out of range";
+    for (int a = 0; a < 3; a++)
+      if (e[1 + a] < 0 || e[1 + a] >= ext(l, a)) return "leaf key out of range";
+    auto& st = node_[pack(l, e[1], e[2], e[3])];
+    if (st != ABSENT) return "duplicate or nested leaf";
+    st = LEAF;
+    for (int a = l - 1; a >= 0; a--) {
+      const int s2 = l - a;
+      auto& pa = node_[pack(a, e[1] >> s2, e[2] >> s2, e[3] >> s2)];
+      if (pa == LEAF) return "leaf inside another leaf";
+      pa = REFINED;
+    }
+  }
+  for (int k = 0; k < d_.root[2]; k++)
+    for (int j = 0; j < d_.root[1]; j++)
+      for (int i = 0; i < d_.root[0]; i++)
+        if (state(0, i, j, k) == ABSENT) return "leaves do not cover the domain";
+  for (const auto& kv : node_) {
+    if (kv.second != REFINED) continue;
+    const int l = int(kv.first >> 60);
+    const int i = int(kv.first & 0xFFFFF), j = int((kv.first >> 20) & 0xFFFFF), k = int((kv.first >> 40) & 0xFFFFF);
+    if (l + 1 > d_.max_level) return "refined node at the deepest level";
+    for (int c = 0; c < 8; c++)
+      if (state(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2)) == ABSENT)
+        return "leaves do not tile the domain";
+  }
+  return check_balance();
+}
+
+void Octree::dfs(int l, int i, int j, int k, std::vector<Key>& out) const {
+  const uint8_t s = state(l, i, j, k);
+  if (s == LEAF) {
+    out.push_back({l, i, j, k});
+    return;
+  }
+  for (int c = 0; c < 8; c++) dfs(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2), out);
+}
+
+std::vector<Key> Octree::leaves() const {
+  std::vector<Key> out;
+  for (int k = 0; k < d_.root[2]; k++)
+    for (int j = 0; j < d_.root[1]; j++)
+      for (int i = 0; i < d_.root[0]; i++) dfs(0, i, j, k, out);
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+
+static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+std::string Plan::build(const std::vector<const Octree*>& meshes) {
+  if (meshes.empty()) return "no meshes";
+  N = meshes[0]->desc().N;
+  M = N + 2 * kGhost;
+  inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); faceslot.clear(); keys.clear();
+  for (auto& r : reflux) r.clear();
+  nslots = 0;
+  std::vector<int64_t> first;
+  for (int m = 0; m < int(meshes.size()); m++) {
+    const Octree& T = *meshes[m];
+    if (T.desc().N != N) return "all meshes of a plan need the same block size";
+    InstParams ip = make_inst_params(T.desc());
+    ip.first_leaf = int64_t(blocks.size());
+    const std::vector<Key> lv = T.leaves();
+    ip.n_leaf = int64_t(lv.size());
+    inst.push_back(ip);
+    for (const Key& k : lv) {
+      BlockInfo b{};
+      b.level = k.l; b.i = k.i; b.j = k.j; b.k = k.k; b.inst = m;
+      blocks.push_back(b);
+      keys.push_back(k);
+    }
+  }
+  nleaf = int64_t(blocks.size());
+  // leaf id lookup per instance
+  std::vector<std::unordered_map<uint64_t, int32_t>> id(meshes.size());
+  auto pk = [](int l, int i, int j, int k) {
+    return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
+  };
+  for (int64_t s = 0; s < nleaf; s++) {
+    const BlockInfo& b = blocks[s];
+    id[b.inst][pk(b.level, b.i, b.j, b.k)] = int32_t(s);
+  }
+  nbr.assign(size_t(27 * nleaf), Nbr{-1, -1});
+  faceslot.assign(size_t(6 * nleaf), -1);
+  for (int64_t s = 0; s < nleaf; s++) {
+    const BlockInfo& b = blocks[s];
+    const Octree& T = *meshes[b.inst];
+    const int l = b.level;
+    const int key[3] = {b.i, b.j, b.k};
+    bool coarse_nbr = false;
+    for (int code = 0; code < 27; code++) {
+      if (code == 13) continue;
+      const int sd[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
+      int q[3];
+      for (int a = 0; a < 3; a++) {
+        q[a] = key[a] + sd[a];
+        if (!T.wrap(l, a, q[a])) q[a] = key[a];  // outflow: clamp to this block's slab
+      }
+      const uint8_t st = T.state(l, q[0], q[1], q[2]);
+      Nbr& e = nbr[size_t(27 * s + code)];
+      if (st == Octree::LEAF) {
+        e.kind = NBR_COPY;
+        e.id = id[b.inst].at(pk(l, q[0], q[1], q[2]));
+      } else if (st == Octree::REFINED) {
+        e.kind = NBR_FINE;
+        e.id = int32_t(fine.size() / 8);
+        for (int c = 0; c < 8; c++) {
+          const int co[3] = {c & 1, (c >> 1) & 1, c >> 2};
+          auto it = id[b.inst].find(pk(l + 1, 2 * q[0] + co[0], 2 * q[1] + co[1], 2 * q[2] + co[2]));
+          fine.push_back(it == id[b.inst].end() ? -1 : it->second);
+          // The ghost box of direction sd reads the children on the near
+          // side along each axis with sd != 0 and both along sd == 0: those
+          // touch this leaf, so balance makes them leaves.  Checked here
+          // because the restriction kernel indexes them without a test.
+          bool read = true;
+          for (int a = 0; a < 3; a++) read = read && (sd[a] == 0 || co[a] == (sd[a] < 0 ? 1 : 0));
+          if (read && fine.back() < 0) return "restriction source is not a leaf: mesh not balanced";
+        }
+      } else {
+        auto it = l > 0 ? id[b.inst].find(pk(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1)) : id[b.inst].end();
+        if (it == id[b.inst].end()) return "neighbour two levels coarser: mesh not balanced";
+        e.kind = NBR_COARSE;
+        e.id = it->second;
+        coarse_nbr = true;
+      }
+    }
+    if (coarse_nbr) p2list.push_back(int32_t(s));
+    // coarse-fine faces get flux slots
+    for (int dir = 0; dir < 3; dir++)
+      for (int side = 0; side < 2; side++) {
+        int q[3] = {key[0], key[1], key[2]};
+        q[dir] += side ? 1 : -1;
+        if (!T.wrap(l, dir, q[dir])) continue;
+        if (T.state(l, q[0], q[1], q[2]) != Octree::LEAF) faceslot[size_t(6 * s + 2 * dir + side)] = int32_t(nslots++);
+      }
+  }
+  has_p2 = !p2list.empty();
+  // reflux tasks: coarse side of each coarse-fine face
+  for (int64_t s = 0; s < nleaf; s++) {
+    const BlockInfo& b = blocks[s];
+    const Octree& T = *meshes[b.inst];
+    const int l = b.level;
+    const int key[3] = {b.i, b.j, b.k};
+    for (int dir = 0; dir < 3; dir++) {
+      const int A = dir == 0 ? 1 : 0, B = dir == 2 ? 1 : 2;
+      for (int side = 0; side < 2; side++) {
+        const int32_t slot = faceslot[size_t(6 * s + 2 * dir + side)];
+        if (slot < 0) continue;
+        int q[3] = {key[0], key[1], key[2]};
+        q[dir] += side ? 1 : -1;
+        T.wrap(l, dir, q[dir]);
+        if (T.state(l, q[0], q[1], q[2]) != Octree::REFINED) continue;
+        RefluxTask t{};
+        t.leaf = int32_t(s);
+        t.side = side;
+        t.slot_c = slot;
+        for (int hB = 0; hB < 2; hB++)
+          for (int hA = 0; hA < 2; hA++) {
+            int c[3];
+            c[dir] = 2 * q[dir] + (side ? 0 : 1);
+            c[A] = 2 * key[A] + hA;
+            c[B] = 2 * key[B] + hB;
+            auto it = id[b.inst].find(pk(l + 1, c[0], c[1], c[2]));
+            if (it == id[b.inst].end()) return "refined face neighbour without leaf children";
+            const int32_t fslot = faceslot[size_t(6 * it->second + 2 * dir + (1 - side))];
+            if (fslot < 0) return "fine face without a flux slot";
+            t.slot_f[hA + 2 * hB] = fslot;
+          }
+        reflux[dir].push_back(t);
+      }
+    }
+  }
+  // workspace layout
+  int64_t o = 0;
+  const int64_t ninst = int64_t(inst.size());
+  off.inst = o; o = align256(o + ninst * int64_t(sizeof(InstParams)));
+  off.blocks = o; o = align256(o + nleaf * int64_t(sizeof(BlockInfo)));
+  off.nbr = o; o = align256(o + int64_t(nbr.size() * sizeof(Nbr)));
+  off.fine = o; o = align256(o + int64_t(fine.size() * sizeof(int32_t)));
+  off.p2list = o; o = align256(o + int64_t(p2list.size() * sizeof(int32_t)));
+  off.faceslot = o; o = align256(o + int64_t(faceslot.size() * sizeof(int32_t)));
+  for (int d = 0; d < 3; d++) {
+    off.reflux[d] = o;
+    o = align256(o + int64_t(reflux[d].size() * sizeof(RefluxTask)));
+  }
+  off.acc = o; o = align256(o + ninst * 8);
+  off.counters = o; o = align256(o + 8);
+  off.faces = o; o = align256(o + nslots * int64_t(kFields) * N * N * 8);
+  off.total = o;
+  staging.assign(size_t(off.faces), 0);
+  auto put = [&](int64_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(staging.data() + at, src, bytes);
+  };
+  put(off.inst, inst.data(), inst.size() * sizeof(InstParams));
+  put(off.blocks, blocks.data(), blocks.size() * sizeof(BlockInfo));
+  put(off.nbr, nbr.data(), nbr.size() * sizeof(Nbr));
+  put(off.fine, fine.data(), fine.size() * sizeof(int32_t));
+  put(off.p2list, p2list.data(), p2list.size() * sizeof(int32_t));
+  put(off.faceslot, faceslot.data(), faceslot.size() * sizeof(int32_t));
+  for (int d = 0; d < 3; d++) put(off.reflux[d], reflux[d].data(), reflux[d].size() * sizeof(RefluxTask));
+  // dt accumulators start at +inf (bit pattern of a positive double)
+  const uint64_t inf_bits = 0x7FF0000000000000ull;
+  for (int64_t m = 0; m < ninst; m++) put(off.acc + 8 * m, &inf_bits, 8);
+  return "";
+}
+
+}  // namespace amr

@@ -1,0 +1,109 @@
+"""Python face of one mesh: the C-ABI calls with torch tensors for device
+memory and the current HIP stream.  Every step of the path runs in the HIP
+library; this module only allocates and passes pointers."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+GHOST = 3
+NFIELD = 5
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """An array-of-octrees mesh with its uploaded tables on one GPU."""
+
+    def __init__(self, root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
+                 rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), leaves=None,
+                 device="cuda"):
+        self.params = dict(root=tuple(root), block_cells=block_cells, max_level=max_level, bc=bc,
+                           gamma=gamma, cfl=cfl, rho_floor=rho_floor, p_floor=p_floor,
+                           riemann_iters=riemann_iters)
+        L = lib()
+        d, keep = _lib.make_desc(refine=refine, **self.params)
+        h = ctypes.c_void_p()
+        if leaves is not None:
+            lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+            check(L.amr_mesh_create_from_leaves(ctypes.byref(d), lv.shape[0],
+                                                lv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        else:
+            check(L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        info = _lib.MeshInfo()
+        check(L.amr_mesh_info(h, ctypes.byref(info)))
+        self.info = info
+        self.nleaf = int(info.n_leaves)
+        self.N = int(info.block_cells)
+        self.M = int(info.padded)
+        keys = np.zeros((self.nleaf, 4), dtype=np.int32)
+        check(L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), self.nleaf))
+        self.keys = keys
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=self.device)
+        check(L.amr_mesh_upload(h, _ptr(self.workspace), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.amr_mesh_destroy(h)
+            self._h = None
+
+    # storage ----------------------------------------------------------
+    def alloc_state(self) -> torch.Tensor:
+        return torch.zeros((self.nleaf, NFIELD, self.M, self.M, self.M), dtype=torch.float64,
+                           device=self.device)
+
+    def state_from_active(self, act: np.ndarray) -> torch.Tensor:
+        U = torch.zeros((self.nleaf, NFIELD, self.M, self.M, self.M), dtype=torch.float64)
+        g, N = GHOST, self.N
+        U[:, :, g:g + N, g:g + N, g:g + N] = torch.from_numpy(np.ascontiguousarray(act))
+        return U.to(self.device)
+
+    def active(self, U: torch.Tensor) -> np.ndarray:
+        g, N = GHOST, self.N
+        return U[:, :, g:g + N, g:g + N, g:g + N].cpu().numpy()
+
+    def _check_state(self, U: torch.Tensor) -> None:
+        if U.dtype != torch.float64 or not U.is_contiguous() or U.device != self.device:
+            raise ValueError("state must be a contiguous float64 tensor on the mesh's device")
+        if U.numel() * 8 != self.info.field_bytes:
+            raise ValueError("state has the wrong size for this mesh")
+
+    # method -----------------------------------------------------------
+    def refresh(self, U: torch.Tensor) -> None:
+        self._check_state(U)
+        check(lib().amr_refresh_ghosts(self._h, _ptr(U), _stream()))
+
+    def cfl_dt(self, U: torch.Tensor, dt: torch.Tensor) -> None:
+        self._check_state(U)
+        check(lib().amr_cfl_dt(self._h, _ptr(U), _ptr(dt), _stream()))
+
+    def step(self, U: torch.Tensor, dt: torch.Tensor, k: int) -> None:
+        """One hydro step; dt (1 double on the device) receives the CFL dt."""
+        self._check_state(U)
+        check(lib().amr_hydro_step(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
+
+    def step_dt(self, U: torch.Tensor, dt: torch.Tensor, k: int) -> None:
+        self._check_state(U)
+        check(lib().amr_hydro_step_dt(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
+
+    def floor_count(self) -> int:
+        out = ctypes.c_int64()
+        check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
+        return int(out.value)
