@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the AMR hydro step on one MI355X.
+
+Workload: the static two-level Sedov blast on an 8^3 array of octrees of
+32^3-cell blocks (624 leaves, 20.4M cells), FP64, periodic, gamma = 5/3,
+refined around the domain centre.  One step = CFL reduction + two-phase ghost
+refresh + three PPM sweeps + reflux over every leaf.  Inputs are generated on
+the host, uploaded once, and resident in HBM for the timed region.
+
+Prints one JSON line: cell-updates/s, the dominant kernel's roofline (live
+HIP-event timing of every kernel over the timed region) and the FP64 CPU
+oracle's throughput on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per PPM step incl. ghost refresh (plain vs batched); adjoint/fwd"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, published
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, published
+
+
+def workload(name):
+    from paper_1810_01319_amd import inputs as I
+
+    if name == "sedov":
+        spec = I.sedov_spec(root=8, block_cells=32, levels=2)
+        desc = ("sedov-static-amr: 8^3 root octrees x 32^3 cells, 2 refinement levels at the centre "
+                "(624 leaves, 20.4M cells), gamma 5/3, periodic, E=1 in r<2 finest cells")
+        return spec, I.sedov_state, desc
+    if name == "sod":
+        spec = I.sod_spec()
+        return spec, I.sod_state, "sod-uniform: 4^3 x 16^3 cells, outflow, gamma 1.4"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(spec, act_fn, steps):
+    """The oracle as it stands, on this host's cores, for `steps` steps of the
+    same workload after one warm-up step."""
+    from oracle import oracle as O
+
+    m = O.OracleMesh(**spec.kwargs())
+    m.set_active(act_fn(spec, m.keys))
+    m.step(0)
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        m.step(k)
+    t = time.perf_counter() - t0
+    cells = m.nleaf * spec.block_cells ** 3
+    return {"value": cells * steps / t, "unit": "cell-updates/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same workload ({m.nleaf} leaves, {cells} cells) after 1 warm-up "
+                      f"step, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sedov")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1810_01319_amd import _lib, costs
+    from paper_1810_01319_amd.mesh import Mesh
+
+    spec, act_fn, desc = workload(args.workload)
+    mesh = Mesh(**spec.kwargs())
+    N = spec.block_cells
+    U = mesh.state_from_active(act_fn(spec, mesh.keys))
+    dt = torch.zeros(1, dtype=torch.float64, device=mesh.device)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=mesh.device)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    for k in range(args.warmup):
+        mesh.step(U, dt, k)
+    torch.cuda.synchronize()
+
+    mesh.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        mesh.step(U, dt, k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = mesh.profile_read()
+    mesh.profile(False)
+    if mesh.floor_count() != 0:
+        print("warning: floors triggered", file=sys.stderr)
+
+    cells = mesh.nleaf * N ** 3
+    K = args.steps
+    value = cells * K / wall
+    # dominant kernel: the three sweeps (FP64 ALU bound)
+    sweep_ms = sum(prof[p][0] for p in ("sweep_x", "sweep_y", "sweep_z"))
+    sweep_launches = sum(prof[p][1] for p in ("sweep_x", "sweep_y", "sweep_z"))
+    flops_step = mesh.nleaf * costs.sweep_flops_per_block_step(N, spec.riemann_iters)
+    launches_per_step = sweep_launches / K
+    flops_per_launch = flops_step / launches_per_step
+    avg_launch_s = sweep_ms * 1e-3 / sweep_launches
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    phases = {p: round(prof[p][0] / K, 4) for p in _lib.PHASES}
+    refresh_bytes = mesh.nleaf * costs.refresh_bytes_per_block(N)
+    refresh_ms = (prof["refresh1"][0] + prof["refresh2"][0]) / K
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "leaves": mesh.nleaf, "cells": cells, "block_cells": N,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "sweep_kernel (x, y, z)", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": None,
+                     "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
+        "phases_ms_per_step": phases,
+        "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
+                        "peak": PEAK_HBM_GBS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

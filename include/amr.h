@@ -135,6 +135,23 @@ amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev
  * stream). */
 amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
 
+/* Per-phase kernel timing with HIP events recorded on the launch stream
+ * around every kernel of refresh, CFL, sweeps and reflux.  Phases: */
+#define AMR_PHASE_CFL 0
+#define AMR_PHASE_REFRESH1 1
+#define AMR_PHASE_REFRESH2 2
+#define AMR_PHASE_SWEEP_X 3
+#define AMR_PHASE_SWEEP_Y 4
+#define AMR_PHASE_SWEEP_Z 5
+#define AMR_PHASE_REFLUX 6
+#define AMR_NPHASE 7
+/* on != 0 starts recording (clearing earlier records); 0 stops. */
+amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
+/* Waits for the recorded events, then writes per phase the summed kernel
+ * milliseconds (ms_out) and the number of launches (launches_out), each of
+ * AMR_NPHASE entries (host memory), and clears the records. */
+amr_status amr_profile_read(amr_mesh* mesh, double* ms_out, int64_t* launches_out);
+
 const char* amr_last_error(void);
 
 #ifdef __cplusplus

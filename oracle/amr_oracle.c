@@ -35,6 +35,7 @@
 #include "amr_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -340,6 +341,7 @@ int orc_create_from_leaves(const orc_desc* d, int64_t n, const int32_t* keys, or
 }
 
 int64_t orc_nleaf(const orc_mesh* m) { return m->nleaf; }
+int orc_num_threads(void) { return omp_get_max_threads(); }
 void orc_leaf_keys(const orc_mesh* m, int32_t* out) {
   memcpy(out, m->key, (size_t)(4 * m->nleaf) * sizeof(int32_t));
 }

@@ -53,6 +53,7 @@ void orc_destroy(orc_mesh* m);
 const char* orc_last_error(void);
 
 int64_t orc_nleaf(const orc_mesh* m);
+int orc_num_threads(void); /* OpenMP threads the oracle's loops use */
 void orc_leaf_keys(const orc_mesh* m, int32_t* out /* 4 x nleaf */);
 /* Padded block storage: U[leaf][field][z][y][x], edge M = N + 6. */
 double* orc_state(orc_mesh* m);

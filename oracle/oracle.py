@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         L.orc_riemann.argtypes = [P, I32, P, P, P, P, P, P]
         L.orc_pencil_flux.argtypes = [P, I32, D, I32, P, P]
         L.orc_set_debug.argtypes = [I32]
+        L.orc_num_threads.restype = I32
         if hasattr(L, "orc_remesh"):
             L.orc_remesh.argtypes = [P, D, D, I64, ctypes.POINTER(P), P]
             L.orc_remesh.restype = I32
@@ -198,6 +199,10 @@ class OracleMesh:
 
 
 DEBUG_SKIP_REFLUX = 1
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def set_debug(flags: int) -> None:

@@ -15,6 +15,7 @@ AMR_OK = 0
 STATUS = {-1: "AMR_E_INVALID", -2: "AMR_E_BALANCE", -3: "AMR_E_NOMEM", -4: "AMR_E_HIP",
           -5: "AMR_E_CAPACITY", -6: "AMR_E_STATE"}
 BC = {"periodic": 0, "outflow": 1}
+PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux"]
 
 
 class AmrError(RuntimeError):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "amr_profile_enable": (_I32, [_P, _I32]),
+    "amr_profile_read": (_I32, [_P, _P, _P]),
     "amr_last_error": (ctypes.c_char_p, []),
 }
 

@@ -11,11 +11,44 @@
 
 using namespace amr;
 
+// Event pairs around kernel phases, recorded while profiling is on.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void release_all() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~Profiler() {
+    release_all();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct amr_mesh {
   std::unique_ptr<Octree> tree;
   Plan plan;
   unsigned char* ws = nullptr;  // caller-owned device workspace
   LaunchCfg cfg;
+  Profiler prof;
 };
 
 namespace {
@@ -107,9 +140,33 @@ amr_status check_ready(const amr_mesh* h, const void* U) {
   return AMR_OK;
 }
 
+// Runs `launch` between two recorded events when profiling is on.
+template <class F>
+hipError_t timed(amr_mesh* h, int phase, hipStream_t st, F&& launch) {
+  if (!h->prof.on) return launch();
+  hipEvent_t a = h->prof.get(), b = h->prof.get();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  h->prof.recs.push_back({phase, a, b});
+  return e;
+}
+
+hipError_t refresh_timed(amr_mesh* h, const DevPlan& P, double* U, hipStream_t st) {
+  LaunchCfg c = h->cfg;
+  DevPlan p1 = P;
+  p1.np2 = 0;  // phase 1 only
+  hipError_t e = timed(h, AMR_PHASE_REFRESH1, st, [&] { return launch_refresh(p1, U, c, st); });
+  if (e != hipSuccess || P.np2 == 0) return e;
+  DevPlan p2 = P;
+  p2.nleaf = 0;  // phase 2 only
+  return timed(h, AMR_PHASE_REFRESH2, st, [&] { return launch_refresh(p2, U, c, st); });
+}
+
 amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index, hipStream_t st) {
   const DevPlan P = dev_plan(h);
-  hipError_t e = launch_refresh(P, U, h->cfg, st);
+  hipError_t e = refresh_timed(h, P, U, st);
   if (e != hipSuccess) return hip_fail(e, "refresh");
   int order[3] = {0, 1, 2};
   if (step_index & 1) {
@@ -118,12 +175,14 @@ amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index
   }
   int swept[3] = {0, 0, 0};
   for (int s = 0; s < 3; s++) {
-    e = launch_sweep(P, U, dt, order[s], swept, h->cfg, st);
+    e = timed(h, AMR_PHASE_SWEEP_X + order[s], st,
+              [&] { return launch_sweep(P, U, dt, order[s], swept, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "sweep");
     swept[order[s]] = 1;
   }
   for (int d = 0; d < 3; d++) {
-    e = launch_reflux(P, U, dt, d, h->cfg, st);
+    if (P.nreflux[d] == 0) continue;
+    e = timed(h, AMR_PHASE_REFLUX, st, [&] { return launch_reflux(P, U, dt, d, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "reflux");
   }
   return AMR_OK;
@@ -217,7 +276,7 @@ amr_status amr_mesh_upload(amr_mesh* h, void* ws, void* stream) {
 amr_status amr_refresh_ghosts(amr_mesh* h, double* U, void* stream) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
-  hipError_t e = launch_refresh(dev_plan(h), U, h->cfg, static_cast<hipStream_t>(stream));
+  hipError_t e = refresh_timed(h, dev_plan(h), U, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "refresh");
 }
 
@@ -225,7 +284,9 @@ amr_status amr_cfl_dt(amr_mesh* h, const double* U, double* dt, void* stream) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
   if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
-  hipError_t e = launch_cfl(dev_plan(h), U, dt, h->cfg, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dt, h->cfg, st); });
   return e == hipSuccess ? AMR_OK : hip_fail(e, "cfl");
 }
 
@@ -251,6 +312,31 @@ amr_status amr_floor_count(amr_mesh* h, int64_t* out, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "floor count");
   *out = int64_t(v);
+  return AMR_OK;
+}
+
+amr_status amr_profile_enable(amr_mesh* h, int32_t on) {
+  if (!h) return fail(AMR_E_INVALID, "null mesh");
+  h->prof.release_all();
+  h->prof.on = on != 0;
+  return AMR_OK;
+}
+
+amr_status amr_profile_read(amr_mesh* h, double* ms_out, int64_t* launches_out) {
+  if (!h || !ms_out || !launches_out) return fail(AMR_E_INVALID, "null argument");
+  for (int p = 0; p < AMR_NPHASE; p++) {
+    ms_out[p] = 0.0;
+    launches_out[p] = 0;
+  }
+  for (auto& r : h->prof.recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    ms_out[r.phase] += double(ms);
+    launches_out[r.phase] += 1;
+  }
+  h->prof.release_all();
   return AMR_OK;
 }
 

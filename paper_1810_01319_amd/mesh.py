@@ -107,3 +107,15 @@ class Mesh:
         out = ctypes.c_int64()
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
         return int(out.value)
+
+    # profiling --------------------------------------------------------
+    def profile(self, on: bool) -> None:
+        check(lib().amr_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """Summed kernel ms and launch counts per phase since profile(True)."""
+        ms = np.zeros(len(_lib.PHASES))
+        n = np.zeros(len(_lib.PHASES), dtype=np.int64)
+        check(lib().amr_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                     n.ctypes.data_as(ctypes.c_void_p)))
+        return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(_lib.PHASES)}
