@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--workload", default="sedov")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -92,6 +93,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    tuned = None
+    if not args.no_tune:
+        from paper_1810_01319_amd import autotune
+
+        tuned = autotune.tune(mesh, U, use_cache=False)
     for k in range(args.warmup):
         mesh.step(U, dt, k)
     torch.cuda.synchronize()
@@ -141,6 +147,7 @@ def main():
                      "traffic": None,
                      "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
         "phases_ms_per_step": phases,
+        "launch": mesh.get_launch(),
         "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
                         "peak": PEAK_HBM_GBS},
     }

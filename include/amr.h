@@ -135,6 +135,19 @@ amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev
  * stream). */
 amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
 
+/* Launch shapes.  Every choice computes bitwise-identical results (each
+ * cell's arithmetic is the same; only the thread mapping changes). */
+typedef struct {
+  int32_t sweep_mode[3];  /* per axis x,y,z: 0 = one lane walks one pencil with
+                             a register window; 1 = LDS-staged tile of whole
+                             pencils, one thread per cell */
+  int32_t sweep_block;    /* workgroup size of mode 0 (64..1024, multiple of 64) */
+  int32_t refresh_block;  /* workgroup size of the refresh kernels */
+  int32_t reflux_block;   /* workgroup size of the reflux kernels */
+} amr_launch_t;
+amr_status amr_mesh_set_launch(amr_mesh* mesh, const amr_launch_t* cfg);
+amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
+
 /* Per-phase kernel timing with HIP events recorded on the launch stream
  * around every kernel of refresh, CFL, sweeps and reflux.  Phases: */
 #define AMR_PHASE_CFL 0

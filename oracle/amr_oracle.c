@@ -549,11 +549,13 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
                        double WL[5], double WR[5]) {
   const double rho = C->q[0], u = C->q[1], c = C->c;
   const double lm = u - c, l0 = u, lp = u + c;
-  const double Ac = rho / (2.0 * c);
-  const double Bc = 1.0 / (rho * c);
+  /* one reciprocal of c serves the three eigenvector weights */
+  const double ic = 1.0 / c;
+  const double Ac = (0.5 * rho) * ic;   /* rho / (2c) */
+  const double Bc = C->ir * ic;         /* 1 / (rho c) */
   const double cc = c * c;
-  const double ic2 = 1.0 / cc;
-  const double cor = c * C->ir;
+  const double ic2 = ic * ic;           /* 1 / c^2 */
+  const double cor = c * C->ir;         /* c / rho */
   /* right edge: waves with positive speed */
   {
     double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
@@ -586,47 +588,55 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
 }
 
 /* Two-shock approximate Riemann solver (the PPM approximation of Colella &
- * Woodward 1984): a fixed number of Newton steps on p*, both waves treated
- * as shocks; sampled at x/t = 0 with rarefaction fans interpolated linearly
- * between head and tail.  Returns the Godunov state and its flux. */
+ * Woodward 1984): both waves treated as shocks, a fixed number of Newton
+ * steps on p*, sampled at x/t = 0 with rarefaction fans interpolated linearly
+ * between head and tail.  Written with reciprocals of the shock mass fluxes
+ * W_K = C_K sqrt(1 + (gamma+1)/(2 gamma) (p* / p_K - 1)) and of the impedances
+ * Z_K = 2 W_K^3 / (W_K^2 + C_K^2), so 1/Z_K = (1 + (C_K/W_K)^2) / (2 W_K):
+ *   u*_L = u_L - (p* - p_L)/W_L,  u*_R = u_R + (p* - p_R)/W_R,
+ *   p*  <- p* - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
+ *   u*   = (u*_L/Z_R + u*_R/Z_L) / (1/Z_L + 1/Z_R)   (= Z-weighted mean).
+ * Returns the Godunov state and its flux. */
 static void riemann(const consts_t* K, const double WLs[5], const double WRs[5], double Wg[5],
                     double F[5], double* pstar, double* ustar) {
   const double rL = WLs[0], uL = WLs[1], pL = WLs[4];
   const double rR = WRs[0], uR = WRs[1], pR = WRs[4];
   const double CL = sqrt((K->gamma * pL) * rL), CR = sqrt((K->gamma * pR) * rR);
-  const double CL2 = CL * CL, CR2 = CR * CR;
   const double ipL = 1.0 / pL, ipR = 1.0 / pR;
   double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
   ps = ps < K->p_floor ? K->p_floor : ps;
-  double WLw = 0.0, WRw = 0.0, ZL = 0.0, ZR = 0.0, usL = 0.0, usR = 0.0;
+  double iWL = 0.0, iWR = 0.0, iZL = 0.0, iZR = 0.0, usL = 0.0, usR = 0.0, WLw = 0.0, WRw = 0.0;
   for (int it = 0; it <= K->iters; it++) {
     WLw = CL * sqrt(1.0 + K->g1 * (ps * ipL - 1.0));
     WRw = CR * sqrt(1.0 + K->g1 * (ps * ipR - 1.0));
-    double W2L = WLw * WLw, W2R = WRw * WRw;
-    ZL = ((2.0 * WLw) * W2L) / (W2L + CL2);
-    ZR = ((2.0 * WRw) * W2R) / (W2R + CR2);
-    usL = uL - (ps - pL) / WLw;
-    usR = uR + (ps - pR) / WRw;
+    iWL = 1.0 / WLw;
+    iWR = 1.0 / WRw;
+    usL = uL - (ps - pL) * iWL;
+    usR = uR + (ps - pR) * iWR;
+    const double qL = CL * iWL, qR = CR * iWR;
+    iZL = (0.5 * iWL) * (1.0 + qL * qL);
+    iZR = (0.5 * iWR) * (1.0 + qR * qR);
     if (it == K->iters) break; /* final pass: wave speeds at the last p* */
-    ps = ps - ((ZL * ZR) * (usR - usL)) / (ZL + ZR);
+    ps = ps - (usR - usL) / (iZL + iZR);
     ps = ps < K->p_floor ? K->p_floor : ps;
   }
-  const double us = (ZL * usL + ZR * usR) / (ZL + ZR);
+  const double us = (iZR * usL + iZL * usR) / (iZL + iZR);
   /* side of the contact the interface lies on; a tie takes the left side */
   const int left = us >= 0.0;
   const double s = left ? 1.0 : -1.0;
   const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
-  const double WK = left ? WLw : WRw;
-  const double vs = 1.0 / rK - (ps - pK) / (WK * WK); /* 1/rho* on side K */
+  const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
+  const double irK = 1.0 / rK;
+  const double vs = irK - (ps - pK) * (iWK * iWK); /* 1/rho* on side K */
   const double rs = 1.0 / vs;
   double rg, ug, pg;
   if (ps > pK) {
     /* shock: S = u_K - s W_K / rho_K */
-    double S = uK - s * (WK / rK);
+    double S = uK - s * (WK * irK);
     if (s * S >= 0.0) { rg = rK; ug = uK; pg = pK; }
     else { rg = rs; ug = us; pg = ps; }
   } else {
-    double cK = sqrt((K->gamma * pK) / rK);
+    double cK = sqrt((K->gamma * pK) * irK);
     double cs = sqrt((K->gamma * ps) * vs);
     double lh = uK - s * cK, lt = us - s * cs;
     if (s * lh >= 0.0) { rg = rK; ug = uK; pg = pK; }

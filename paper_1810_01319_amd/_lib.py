@@ -55,6 +55,15 @@ class MeshInfo(ctypes.Structure):
     ]
 
 
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [
+        ("sweep_mode", ctypes.c_int32 * 3),
+        ("sweep_block", ctypes.c_int32),
+        ("refresh_block", ctypes.c_int32),
+        ("reflux_block", ctypes.c_int32),
+    ]
+
+
 # every entry point declared in include/amr.h: name -> (restype, argtypes)
 _P, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
 SIGNATURES = {
@@ -69,6 +78,8 @@ SIGNATURES = {
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "amr_mesh_set_launch": (_I32, [_P, ctypes.POINTER(LaunchCfg)]),
+    "amr_mesh_get_launch": (_I32, [_P, ctypes.POINTER(LaunchCfg)]),
     "amr_profile_enable": (_I32, [_P, _I32]),
     "amr_profile_read": (_I32, [_P, _P, _P]),
     "amr_last_error": (ctypes.c_char_p, []),

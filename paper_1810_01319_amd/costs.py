@@ -18,16 +18,16 @@ SLOPES = 5 * 7           # MC-limited slope of 5 primitives
 FACE_VALUES = 5 * 5      # fourth-order face value of 5 primitives
 FLATTEN = 7              # shock detector and pressure-ratio ramp
 PARABOLAS = 5 * 24       # flattening blend, monotonicity, dq and q6
-TRACE = 9 + 2 * 63       # eigen-quantities, then both edges (9 parabola means each)
+TRACE = 9 + 2 * 63       # eigen-quantities (one reciprocal of c), then both edges
 TRACED_CELL = FLATTEN + PARABOLAS + TRACE
 
 
 def riemann_flops(iters: int) -> int:
-    """Two-shock solve and flux at one interface: setup 19, (iters+1)
-    evaluations of wave speeds/impedances/star velocities (28 each), iters
-    Newton updates (6 each), u* 5, star density 6, sampling 23 (fan arm),
-    flux 16."""
-    return 19 + (iters + 1) * 28 + iters * 6 + 5 + 6 + 23 + 16
+    """Two-shock solve and flux at one interface: setup 17 (C_K, 1/p_K, first
+    p*), (iters+1) evaluations of mass fluxes, their reciprocals, star
+    velocities and reciprocal impedances (30 each), iters Newton updates (4
+    each), u* 5, star density 6, sampling 23 (fan arm), flux 15."""
+    return 17 + (iters + 1) * 30 + iters * 4 + 5 + 6 + 23 + 15
 
 
 UPDATE = 5 * 3 + 13      # conservative update, post-update floor test

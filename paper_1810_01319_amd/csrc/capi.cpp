@@ -315,6 +315,31 @@ amr_status amr_floor_count(amr_mesh* h, int64_t* out, void* stream) {
   return AMR_OK;
 }
 
+amr_status amr_mesh_set_launch(amr_mesh* h, const amr_launch_t* c) {
+  if (!h || !c) return fail(AMR_E_INVALID, "null argument");
+  for (int a = 0; a < 3; a++)
+    if (c->sweep_mode[a] != 0 && c->sweep_mode[a] != 1) return fail(AMR_E_INVALID, "sweep_mode must be 0 or 1");
+  auto ok = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+  if (!ok(c->sweep_block) || !ok(c->refresh_block) || !ok(c->reflux_block))
+    return fail(AMR_E_INVALID, "workgroup sizes must be multiples of 64 in 64..1024");
+  if (c->sweep_block > 256 || c->refresh_block > 256 || c->reflux_block > 256)
+    return fail(AMR_E_INVALID, "workgroup sizes above 256 exceed the kernels' launch bounds");
+  for (int a = 0; a < 3; a++) h->cfg.sweep_mode[a] = c->sweep_mode[a];
+  h->cfg.sweep_block = c->sweep_block;
+  h->cfg.refresh_block = c->refresh_block;
+  h->cfg.reflux_block = c->reflux_block;
+  return AMR_OK;
+}
+
+amr_status amr_mesh_get_launch(const amr_mesh* h, amr_launch_t* c) {
+  if (!h || !c) return fail(AMR_E_INVALID, "null argument");
+  for (int a = 0; a < 3; a++) c->sweep_mode[a] = h->cfg.sweep_mode[a];
+  c->sweep_block = h->cfg.sweep_block;
+  c->refresh_block = h->cfg.refresh_block;
+  c->reflux_block = h->cfg.reflux_block;
+  return AMR_OK;
+}
+
 amr_status amr_profile_enable(amr_mesh* h, int32_t on) {
   if (!h) return fail(AMR_E_INVALID, "null mesh");
   h->prof.release_all();

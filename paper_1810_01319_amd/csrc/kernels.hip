@@ -293,11 +293,12 @@ __device__ __forceinline__ void trace(const InstParams& ip, double rho, double u
                                       const Par* pa, double nu, double* WL, double* WR) {
   const double two3 = ip.two3;
   const double lm = u - c, l0 = u, lp = u + c;
-  const double Ac = rho / (2.0 * c);
-  const double Bc = 1.0 / (rho * c);
+  const double ic = 1.0 / c;
+  const double Ac = (0.5 * rho) * ic;  // rho / (2c)
+  const double Bc = ir * ic;           // 1 / (rho c)
   const double cc = c * c;
-  const double ic2 = 1.0 / cc;
-  const double cor = c * ir;
+  const double ic2 = ic * ic;          // 1 / c^2
+  const double cor = c * ir;           // c / rho
   {
     const double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
     const double rr = Ip(pa[0], sp, two3), ur = Ip(pa[1], sp, two3), pr = Ip(pa[4], sp, two3);
@@ -327,45 +328,49 @@ __device__ __forceinline__ void trace(const InstParams& ip, double rho, double u
 }
 
 // Two-shock Riemann solver (fixed Newton steps on p*), sampled at x/t = 0,
-// linear fan between head and tail; returns the flux.
+// linear fan between head and tail; returns the flux.  Uses the reciprocal
+// shock mass fluxes 1/W_K and reciprocal impedances
+// 1/Z_K = (1 + (C_K/W_K)^2) / (2 W_K): p* <- p* - (u*_R - u*_L)/(1/Z_L + 1/Z_R).
 __device__ __forceinline__ void riemann_flux(const InstParams& ip, const double* L, const double* R, double* F) {
   const double rL = L[0], uL = L[1], pL = L[4];
   const double rR = R[0], uR = R[1], pR = R[4];
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
   const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
-  const double CL2 = CL * CL, CR2 = CR * CR;
   const double ipL = 1.0 / pL, ipR = 1.0 / pR;
   double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
   ps = ps < pfl ? pfl : ps;
-  double WLw, WRw, ZL, ZR, usL, usR;
+  double WLw, WRw, iWL, iWR, iZL, iZR, usL, usR;
   for (int it = 0;; it++) {
     WLw = CL * sqrt(1.0 + g1 * (ps * ipL - 1.0));
     WRw = CR * sqrt(1.0 + g1 * (ps * ipR - 1.0));
-    const double W2L = WLw * WLw, W2R = WRw * WRw;
-    ZL = ((2.0 * WLw) * W2L) / (W2L + CL2);
-    ZR = ((2.0 * WRw) * W2R) / (W2R + CR2);
-    usL = uL - (ps - pL) / WLw;
-    usR = uR + (ps - pR) / WRw;
+    iWL = 1.0 / WLw;
+    iWR = 1.0 / WRw;
+    usL = uL - (ps - pL) * iWL;
+    usR = uR + (ps - pR) * iWR;
+    const double qL = CL * iWL, qR = CR * iWR;
+    iZL = (0.5 * iWL) * (1.0 + qL * qL);
+    iZR = (0.5 * iWR) * (1.0 + qR * qR);
     if (it == ip.iters) break;
-    ps = ps - ((ZL * ZR) * (usR - usL)) / (ZL + ZR);
+    ps = ps - (usR - usL) / (iZL + iZR);
     ps = ps < pfl ? pfl : ps;
   }
-  const double us = (ZL * usL + ZR * usR) / (ZL + ZR);
+  const double us = (iZR * usL + iZL * usR) / (iZL + iZR);
   const bool left = us >= 0.0;
   const double s = left ? 1.0 : -1.0;
   const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
-  const double WK = left ? WLw : WRw;
-  const double vs = 1.0 / rK - (ps - pK) / (WK * WK);
+  const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
+  const double irK = 1.0 / rK;
+  const double vs = irK - (ps - pK) * (iWK * iWK);
   const double rs = 1.0 / vs;
   double rg, ug, pg;
   if (ps > pK) {
-    const double S = uK - s * (WK / rK);
+    const double S = uK - s * (WK * irK);
     const bool toK = s * S >= 0.0;
     rg = toK ? rK : rs;
     ug = toK ? uK : us;
     pg = toK ? pK : ps;
   } else {
-    const double cK = sqrt((gam * pK) / rK);
+    const double cK = sqrt((gam * pK) * irK);
     const double cs = sqrt((gam * ps) * vs);
     const double lh = uK - s * cK, lt = us - s * cs;
     if (s * lh >= 0.0) {
@@ -532,6 +537,156 @@ __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, cons
 }
 
 // ---------------------------------------------------------------------------
+// PPM sweep, LDS-staged: a workgroup owns a tile of R whole pencils, loaded
+// with coalesced accesses (along x a tile is R consecutive rows, one
+// contiguous run; along y or z it is R consecutive x positions).  Each thread
+// owns one cell of the tile through six stages separated by barriers; its own
+// cell's state stays in registers and only neighbour values go through LDS.
+// ---------------------------------------------------------------------------
+
+template <int N>
+struct StagedShape {
+  static constexpr int M = N + 2 * G;
+  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : 5);  // pencils per tile
+  static constexpr int T = R * M;                               // cells per tile
+  static constexpr int WG = ((T + 63) / 64) * 64;
+};
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged(double* __restrict__ U,
+                                                                    const double* __restrict__ dtv, DevPlan P,
+                                                                    int loA, int nA, int loB, int nB) {
+  using S = StagedShape<N>;
+  constexpr int M = S::M, R = S::R, T = S::T;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  constexpr int NS = DIR == 0 ? 1 : R;  // item stride between neighbouring cells
+  __shared__ double Ps[5][T];           // primitives
+  __shared__ double Xs[5][T];           // slopes, then right states at j-1/2
+  __shared__ double Ys[5][T];           // face values at j+1/2, then fluxes
+  const int tilesA = (nA + R - 1) / R;
+  const int64_t tile = blockIdx.x;
+  const int s = int(tile / (int64_t(nB) * tilesA));
+  const int rem = int(tile - int64_t(s) * nB * tilesA);
+  const int iB = loB + rem / tilesA;
+  const int a0 = (rem % tilesA) * R;
+  const int i = threadIdx.x;
+  const int r = DIR == 0 ? i / M : i % R;
+  const int c = DIR == 0 ? i - r * M : i / R;
+  const bool live = i < T && a0 + r < nA;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
+  const int iA = loA + a0 + r;
+  double* const cellp = U + int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const double gm1 = ip.gm1, pfl = ip.p_floor, rfl = ip.rho_floor, sixth = ip.sixth;
+
+  // A: own cell, primitives
+  double U0 = 0, U1 = 0, U2 = 0, U3 = 0, U4 = 0, q[5] = {0, 0, 0, 0, 0}, cs = 0, ir = 0;
+  if (live) {
+    U0 = cellp[0];
+    U1 = cellp[(1 + DIR) * M3];
+    U2 = cellp[(1 + T1) * M3];
+    U3 = cellp[(1 + T2) * M3];
+    U4 = cellp[4 * M3];
+    ir = 1.0 / U0;
+    q[0] = U0;
+    q[1] = U1 * ir;
+    q[2] = U2 * ir;
+    q[3] = U3 * ir;
+    double p = gm1 * (U4 - (0.5 * U0) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]));
+    q[4] = p < pfl ? pfl : p;
+    cs = sqrt((ip.gamma * q[4]) * ir);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ps[v][i] = q[v];
+  }
+  __syncthreads();
+  // B: limited slopes
+  if (live && c >= 1 && c <= M - 2) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) Xs[v][i] = mc_slope(Ps[v][i - NS], q[v], Ps[v][i + NS]);
+  }
+  __syncthreads();
+  // C: face values at c+1/2
+  if (live && c >= 1 && c <= M - 3) {
+#pragma unroll
+    for (int v = 0; v < 5; v++)
+      Ys[v][i] = 0.5 * (q[v] + Ps[v][i + NS]) - (Xs[v][i + NS] - Xs[v][i]) * sixth;
+  }
+  __syncthreads();
+  // D: flattening, parabolas, characteristic tracing
+  double WL[5] = {0, 0, 0, 0, 0}, WR[5];
+  const bool traced = live && c >= 2 && c <= M - 3;
+  if (traced) {
+    const double pp1 = Ps[4][i + NS], pm1 = Ps[4][i - NS];
+    const double dp1 = pp1 - pm1;
+    const double pmin = pp1 < pm1 ? pp1 : pm1;
+    const bool shock = (fabs(dp1) > 0.33 * pmin) && (Ps[1][i - NS] - Ps[1][i + NS] > 0.0);
+    const double dp2 = Ps[4][i + 2 * NS] - Ps[4][i - 2 * NS];
+    const double rr = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    double ft = 10.0 * (rr - 0.75);
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    const double f = shock ? ft : 0.0;
+    Par pa[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) pa[v] = parabola(q[v], Ys[v][i - NS], Ys[v][i], f, sixth);
+    trace(ip, q[0], q[1], cs, ir, pa, nu, WL, WR);
+  }
+  __syncthreads();
+  if (traced) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) Xs[v][i] = WR[v];
+  }
+  __syncthreads();
+  // E: Riemann flux at c+1/2
+  if (live && c >= 2 && c <= M - 4) {
+    double R5[5], F[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) R5[v] = Xs[v][i + NS];
+    riemann_flux(ip, WL, R5, F);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ys[v][i] = F[v];
+    const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
+    if (faces_act && (c == G - 1 || c == N + G - 1)) {
+      const int slot = P.faceslot[6 * int64_t(s) + 2 * DIR + (c == G - 1 ? 0 : 1)];
+      if (slot >= 0) {
+        double* fo = P.faces + int64_t(slot) * kFields * N * N + int64_t(iB - G) * N + (iA - G);
+        fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
+        fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+      }
+    }
+  }
+  __syncthreads();
+  // F: conservative update of the active cells, floors
+  if (live && c >= G && c < G + N) {
+    double r0 = U0 - nu * (Ys[0][i] - Ys[0][i - NS]);
+    const double m1 = U1 - nu * (Ys[1][i] - Ys[1][i - NS]);
+    const double m2 = U2 - nu * (Ys[2][i] - Ys[2][i - NS]);
+    const double m3 = U3 - nu * (Ys[3][i] - Ys[3][i - NS]);
+    double e = U4 - nu * (Ys[4][i] - Ys[4][i - NS]);
+    unsigned nfl = 0;
+    if (r0 < rfl) { r0 = rfl; nfl++; }
+    const double jr = 1.0 / r0;
+    const double a1 = m1 * jr, a2 = m2 * jr, a3 = m3 * jr;
+    const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
+    const double pn = gm1 * (e - ke);
+    if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
+    cellp[0] = r0;
+    cellp[(1 + DIR) * M3] = m1;
+    cellp[(1 + T1) * M3] = m2;
+    cellp[(1 + T2) * M3] = m3;
+    cellp[4 * M3] = e;
+    if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reflux
 // ---------------------------------------------------------------------------
 
@@ -602,10 +757,16 @@ hipError_t sweep_nd(const DevPlan& P, double* U, const double* dt, const int swe
   constexpr int B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : M;
-  const int64_t n = P.nleaf * int64_t(nA) * nB;
-  if (n > 0)
-    hipLaunchKernelGGL((sweep_kernel<N, DIR>), dim3(grid_for(n, L.sweep_block)), dim3(L.sweep_block), 0, st, U, dt, P,
-                       loA, nA, loB, nB);
+  if (P.nleaf == 0) return hipSuccess;
+  if (L.sweep_mode[DIR] == 1) {
+    using S = StagedShape<N>;
+    const int64_t tiles = P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R);
+    hipLaunchKernelGGL((sweep_staged<N, DIR>), dim3(unsigned(tiles)), dim3(S::WG), 0, st, U, dt, P, loA, nA, loB, nB);
+  } else {
+    const int64_t n = P.nleaf * int64_t(nA) * nB;
+    hipLaunchKernelGGL((sweep_kernel<N, DIR>), dim3(grid_for(n, L.sweep_block)), dim3(L.sweep_block), 0, st, U, dt,
+                       P, loA, nA, loB, nB);
+  }
   return hipGetLastError();
 }
 

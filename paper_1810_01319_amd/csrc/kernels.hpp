@@ -29,6 +29,7 @@ struct LaunchCfg {
   int sweep_block = 128;
   int cfl_block = 256;
   int reflux_block = 256;
+  int sweep_mode[3] = {1, 0, 0};  // per axis: 0 = lane-per-pencil walk, 1 = LDS-staged tile
 };
 
 hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st);

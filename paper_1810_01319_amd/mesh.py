@@ -108,6 +108,23 @@ class Mesh:
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
         return int(out.value)
 
+    # launch shapes ----------------------------------------------------
+    def get_launch(self) -> dict:
+        c = _lib.LaunchCfg()
+        check(lib().amr_mesh_get_launch(self._h, ctypes.byref(c)))
+        return {"sweep_mode": list(c.sweep_mode), "sweep_block": c.sweep_block,
+                "refresh_block": c.refresh_block, "reflux_block": c.reflux_block}
+
+    def set_launch(self, **kw) -> None:
+        cur = self.get_launch()
+        cur.update(kw)
+        c = _lib.LaunchCfg()
+        c.sweep_mode[:] = [int(v) for v in cur["sweep_mode"]]
+        c.sweep_block = int(cur["sweep_block"])
+        c.refresh_block = int(cur["refresh_block"])
+        c.reflux_block = int(cur["reflux_block"])
+        check(lib().amr_mesh_set_launch(self._h, ctypes.byref(c)))
+
     # profiling --------------------------------------------------------
     def profile(self, on: bool) -> None:
         check(lib().amr_profile_enable(self._h, 1 if on else 0))

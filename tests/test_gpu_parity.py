@@ -188,3 +188,38 @@ def test_repeat_runs_are_bitwise_identical():
             gm.step(U, dt, k)
         outs.append(gm.active(U))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("modes", [(0, 0, 0), (1, 1, 1), (1, 0, 1), (0, 1, 0)])
+def test_sweep_variants_are_bitwise_identical_to_oracle(modes):
+    """Both sweep kernels (lane-per-pencil walk, LDS-staged tile) in every
+    per-axis combination give the oracle's result bitwise."""
+    for N in (8, 16, 32):
+        root = (2, 2, 2)
+        spec = I.MeshSpec(root=root, block_cells=N, max_level=2, gamma=5 / 3,
+                          refine=I.random_refine_list(root, 2, 3, 7 + N))
+        say(f"sweep modes {modes} N={N}")
+        om, gm, perm = pair(spec)
+        gm.set_launch(sweep_mode=list(modes))
+        U = load(om, gm, perm, I.smooth_state(spec, gm.keys, seed=N + 1, amp=0.3, vel=0.8))
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for k in range(2):
+            gm.step(U, dt, k)
+            assert float(dt.cpu()[0]) == om.step(k)
+        err, bw = compare_active(gm, U, om, perm)
+        assert bw == 1.0, (modes, N, err)
+
+
+def test_autotuned_launch_is_bitwise_identical():
+    from paper_1810_01319_amd import autotune
+
+    spec = I.sedov_spec(root=4, block_cells=16, levels=2)
+    om, gm, perm = pair(spec)
+    U = load(om, gm, perm, I.sedov_state(spec, gm.keys))
+    cfg = autotune.tune(gm, U, steps=1, use_cache=False)
+    say(f"autotuned {cfg['sweep_mode']} block {cfg['sweep_block']}")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        gm.step(U, dt, k)
+        assert float(dt.cpu()[0]) == om.step(k)
+    assert compare_active(gm, U, om, perm)[1] == 1.0
