@@ -863,3 +863,269 @@ void orc_pencil_flux(const double* gas, int iters, double nu, int n, const doubl
   }
   pencil(&K, nu, n, in, out);
 }
+
+/* ------------------------------------------------------------------ */
+/* Remesh (Sec. II-B "Refine"; the paper's blast runs refine adaptively) */
+/* ------------------------------------------------------------------ */
+
+/* Indicator of one leaf: the largest relative density jump across a cell,
+ * max over active cells and axes of |rho(+1) - rho(-1)| / (2 rho).  Reads
+ * refreshed ghosts at the block boundary. */
+void orc_indicator(const orc_mesh* m, double* out) {
+  const int N = m->N, M = m->M;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double* B = block_ptr(m, s);
+    double best = 0.0;
+    for (int c = G; c < G + N; c++)
+      for (int b = G; b < G + N; b++)
+        for (int a = G; a < G + N; a++) {
+          const double r0 = B[cell(M, 0, a, b, c)];
+          const double sx = fabs(B[cell(M, 0, a + 1, b, c)] - B[cell(M, 0, a - 1, b, c)]) / (2.0 * r0);
+          const double sy = fabs(B[cell(M, 0, a, b + 1, c)] - B[cell(M, 0, a, b - 1, c)]) / (2.0 * r0);
+          const double sz = fabs(B[cell(M, 0, a, b, c + 1)] - B[cell(M, 0, a, b, c - 1)]) / (2.0 * r0);
+          best = sx > best ? sx : best;
+          best = sy > best ? sy : best;
+          best = sz > best ? sz : best;
+        }
+    out[s] = best;
+  }
+}
+
+typedef struct { double S; int32_t key[4]; int64_t leaf; } cand_t;
+
+/* Refinement candidates: larger indicator first; ties by (level, z, y, x). */
+static int cand_cmp(const void* pa, const void* pb) {
+  const cand_t* a = (const cand_t*)pa;
+  const cand_t* b = (const cand_t*)pb;
+  if (a->S != b->S) return a->S > b->S ? -1 : 1;
+  const int order[4] = {0, 3, 2, 1};
+  for (int q = 0; q < 4; q++)
+    if (a->key[order[q]] != b->key[order[q]]) return a->key[order[q]] < b->key[order[q]] ? -1 : 1;
+  return 0;
+}
+
+/* Coarsening candidates (parents): finer first; ties by (z, y, x). */
+static int par_cmp(const void* pa, const void* pb) {
+  const int32_t* a = (const int32_t*)pa;
+  const int32_t* b = (const int32_t*)pb;
+  if (a[0] != b[0]) return a[0] > b[0] ? -1 : 1;
+  for (int q = 3; q >= 1; q--)
+    if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
+  return 0;
+}
+
+static int64_t count_leaves(const orc_mesh* m) {
+  int64_t n = 0;
+  for (int l = 0; l < m->nlev; l++) {
+    int64_t cnt = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    for (int64_t q = 0; q < cnt; q++) n += m->state[l][q] == LEAF;
+  }
+  return n;
+}
+
+static int balanced(const orc_mesh* m) {
+  for (int l = 2; l < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++) {
+          if (m->state[l][nidx(m, l, i, j, k)] != LEAF) continue;
+          for (int q = 0; q < 27; q++) {
+            if (q == 13) continue;
+            int p[3] = {i + q % 3 - 1, j + (q / 3) % 3 - 1, k + q / 9 - 1};
+            if (!wrap_block(m, l, 0, &p[0]) || !wrap_block(m, l, 1, &p[1]) || !wrap_block(m, l, 2, &p[2]))
+              continue;
+            if (l - covering_level(m, l, p) >= 2) return 0;
+          }
+        }
+  return 1;
+}
+
+static void save_states(const orc_mesh* m, unsigned char** dst) {
+  for (int l = 0; l < m->nlev; l++) {
+    size_t n = (size_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    memcpy(dst[l], m->state[l], n);
+  }
+}
+static void load_states(orc_mesh* m, unsigned char** src) {
+  for (int l = 0; l < m->nlev; l++) {
+    size_t n = (size_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    memcpy(m->state[l], src[l], n);
+  }
+}
+
+/* Remesh.  Reading of the refinement rule (the paper names Refine, not its
+ * criterion):
+ *   1. S_b on refreshed data;
+ *   2. every leaf with S_b > refine_slope below the deepest level is a
+ *      candidate; in (S_b descending, key) order a candidate is refined
+ *      together with the minimal refinement that restores 2:1 balance,
+ *      accepted only if every node so refined was a leaf before this remesh
+ *      (at most one level of refinement per remesh) and the leaf count stays
+ *      <= max_blocks; otherwise it is refused and counted;
+ *   3. then, finer first, each octet of leaves that were all leaves before,
+ *      all with S_b < coarsen_slope, is merged if 2:1 balance still holds;
+ *   4. data: kept leaves copy, new children prolong from their parent (the
+ *      refresh prolongation formula, on refreshed parent data), merged
+ *      parents restrict their 8 children. */
+int orc_remesh(orc_mesh* m, double refine_slope, double coarsen_slope, int64_t max_blocks, orc_mesh** out,
+               int64_t* stats) {
+  *out = NULL;
+  stats[0] = stats[1] = stats[2] = 0;
+  orc_refresh(m);
+  double* S = (double*)malloc((size_t)m->nleaf * sizeof(double));
+  orc_indicator(m, S);
+  /* the tree before remesh */
+  unsigned char* orig[ORC_MAXLEV];
+  unsigned char* keep[ORC_MAXLEV];
+  for (int l = 0; l < m->nlev; l++) {
+    size_t n = (size_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    orig[l] = (unsigned char*)malloc(n);
+    keep[l] = (unsigned char*)malloc(n);
+  }
+  save_states(m, orig);
+  /* 2. refinement */
+  cand_t* cand = (cand_t*)malloc((size_t)m->nleaf * sizeof(cand_t));
+  int64_t nc = 0;
+  for (int64_t s = 0; s < m->nleaf; s++)
+    if (S[s] > refine_slope && m->key[4 * s] < m->d.max_level) {
+      cand[nc].S = S[s];
+      memcpy(cand[nc].key, m->key + 4 * s, sizeof cand[nc].key);
+      cand[nc].leaf = s;
+      nc++;
+    }
+  qsort(cand, (size_t)nc, sizeof(cand_t), cand_cmp);
+  for (int64_t q = 0; q < nc; q++) {
+    const int32_t* k = cand[q].key;
+    if (m->state[k[0]][nidx(m, k[0], k[1], k[2], k[3])] != LEAF) continue; /* refined by an earlier closure */
+    save_states(m, keep);
+    refine_node(m, k[0], k[1], k[2], k[3]);
+    balance(m);
+    int ok = count_leaves(m) <= max_blocks;
+    for (int l = 0; l < m->nlev && ok; l++) {
+      int64_t n = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+      for (int64_t p = 0; p < n; p++)
+        if (m->state[l][p] == REFINED && keep[l][p] != REFINED && orig[l][p] != LEAF) { ok = 0; break; }
+    }
+    if (!ok) {
+      load_states(m, keep);
+      stats[2]++;
+    }
+  }
+  for (int l = 0; l < m->nlev; l++) {
+    int64_t n = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+    for (int64_t p = 0; p < n; p++) stats[0] += (m->state[l][p] == REFINED && orig[l][p] != REFINED);
+  }
+  /* 3. coarsening */
+  int64_t npar = 0;
+  int32_t* par = (int32_t*)malloc((size_t)(4 * m->nleaf + 4) * sizeof(int32_t));
+  for (int l = 0; l + 1 < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++) {
+          if (m->state[l][nidx(m, l, i, j, k)] != REFINED) continue;
+          int ok = 1;
+          for (int c = 0; c < 8 && ok; c++) {
+            int ci = 2 * i + (c & 1), cj = 2 * j + ((c >> 1) & 1), ck = 2 * k + (c >> 2);
+            int64_t p = nidx(m, l + 1, ci, cj, ck);
+            if (m->state[l + 1][p] != LEAF || orig[l + 1][p] != LEAF) ok = 0;
+            else if (!(S[m->leaf_at[l + 1][p]] < coarsen_slope)) ok = 0;
+          }
+          if (ok) {
+            par[4 * npar] = l; par[4 * npar + 1] = i; par[4 * npar + 2] = j; par[4 * npar + 3] = k;
+            npar++;
+          }
+        }
+  qsort(par, (size_t)npar, 4 * sizeof(int32_t), par_cmp);
+  for (int64_t q = 0; q < npar; q++) {
+    const int32_t* e = par + 4 * q;
+    int l = e[0];
+    save_states(m, keep);
+    m->state[l][nidx(m, l, e[1], e[2], e[3])] = LEAF;
+    for (int c = 0; c < 8; c++)
+      m->state[l + 1][nidx(m, l + 1, 2 * e[1] + (c & 1), 2 * e[2] + ((c >> 1) & 1), 2 * e[3] + (c >> 2))] = ABSENT;
+    if (balanced(m)) stats[1]++;
+    else load_states(m, keep);
+  }
+  /* 4. new mesh and data migration */
+  int64_t nnew = count_leaves(m);
+  int32_t* keys = (int32_t*)malloc((size_t)(4 * nnew) * sizeof(int32_t));
+  int64_t w = 0;
+  for (int l = 0; l < m->nlev; l++)
+    for (int k = 0; k < m->ext[l][2]; k++)
+      for (int j = 0; j < m->ext[l][1]; j++)
+        for (int i = 0; i < m->ext[l][0]; i++)
+          if (m->state[l][nidx(m, l, i, j, k)] == LEAF) {
+            keys[4 * w] = l; keys[4 * w + 1] = i; keys[4 * w + 2] = j; keys[4 * w + 3] = k;
+            w++;
+          }
+  /* restore the old tree in m (its leaf table still describes its data) */
+  load_states(m, orig);
+  orc_mesh* nm = NULL;
+  int rc = orc_create_from_leaves(&m->d, nnew, keys, &nm);
+  if (rc == 0) {
+    const int N = m->N, M = m->M;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nm->nleaf; s++) {
+      const int32_t* kk = nm->key + 4 * s;
+      const int l = kk[0];
+      double* D = block_ptr(nm, s);
+      if (orig[l][nidx(m, l, kk[1], kk[2], kk[3])] == LEAF) {
+        const double* Sb = block_ptr(m, m->leaf_at[l][nidx(m, l, kk[1], kk[2], kk[3])]);
+        for (int f = 0; f < NF; f++)
+          for (int c = G; c < G + N; c++)
+            for (int b = G; b < G + N; b++)
+              for (int a = G; a < G + N; a++) D[cell(M, f, a, b, c)] = Sb[cell(M, f, a, b, c)];
+      } else if (l > 0 && orig[l - 1][nidx(m, l - 1, kk[1] >> 1, kk[2] >> 1, kk[3] >> 1)] == LEAF) {
+        /* new child of a refined leaf: prolong from the parent */
+        const double* C = block_ptr(m, m->leaf_at[l - 1][nidx(m, l - 1, kk[1] >> 1, kk[2] >> 1, kk[3] >> 1)]);
+        const int co[3] = {kk[1] & 1, kk[2] & 1, kk[3] & 1};
+        for (int c = 0; c < N; c++)
+          for (int b = 0; b < N; b++)
+            for (int a = 0; a < N; a++) {
+              const int fa[3] = {a, b, c};
+              int lc[3];
+              double o[3];
+              for (int ax = 0; ax < 3; ax++) {
+                lc[ax] = (co[ax] * N + fa[ax]) / 2 + G;
+                o[ax] = (fa[ax] & 1) ? 1.0 : -1.0;
+              }
+              for (int f = 0; f < NF; f++) {
+                double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
+                double sx = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
+                double sy = minmod(C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - u0, u0 - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
+                double sz = minmod(C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - u0, u0 - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
+                D[cell(M, f, a + G, b + G, c + G)] =
+                    ((u0 + (0.25 * o[0]) * sx) + (0.25 * o[1]) * sy) + (0.25 * o[2]) * sz;
+              }
+            }
+      } else {
+        /* merged parent: restrict the 8 old children */
+        for (int c = 0; c < N; c++)
+          for (int b = 0; b < N; b++)
+            for (int a = 0; a < N; a++) {
+              const int fa[3] = {a, b, c};
+              for (int f = 0; f < NF; f++) {
+                double v[8];
+                for (int q = 0; q < 8; q++) {
+                  int64_t gq[3];
+                  for (int ax = 0; ax < 3; ax++)
+                    gq[ax] = 2 * ((int64_t)kk[1 + ax] * N + fa[ax]) + ((q >> ax) & 1);
+                  v[q] = leaf_value(m, l + 1, gq, f);
+                }
+                D[cell(M, f, a + G, b + G, c + G)] = restrict8(v);
+              }
+            }
+      }
+    }
+    nm->floors = m->floors;
+  }
+  for (int l = 0; l < m->nlev; l++) {
+    free(orig[l]);
+    free(keep[l]);
+  }
+  free(S); free(cand); free(par); free(keys);
+  if (rc != 0) return rc;
+  *out = nm;
+  return 0;
+}
