@@ -135,6 +135,45 @@ amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev
  * stream). */
 amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
 
+/* Remesh (Sec. II-B "Refine"; the paper's blast test refines adaptively).
+ * Indicator per leaf: S_b = max over active cells and axes of
+ * |rho(+1) - rho(-1)| / (2 rho) on refreshed data.  Rule: leaves with
+ * S_b > refine_slope below max_level are refined in (S_b descending, then
+ * level, z, y, x) order, each with the minimal refinement that keeps 2:1
+ * balance, accepted only if that refines pre-existing leaves only (one level
+ * per remesh) and the leaf count stays <= max_blocks (refused otherwise);
+ * then, finer first, octets of pre-existing leaves all below coarsen_slope
+ * merge if balance allows.  Data: kept leaves copy, new children prolong
+ * (the refresh prolongation), merged parents restrict. */
+typedef struct {
+  double refine_slope, coarsen_slope;
+  int64_t max_blocks;
+} amr_remesh_params;
+typedef struct {
+  int64_t refined;    /* nodes split (including balance refinements) */
+  int64_t coarsened;  /* octets merged */
+  int64_t refused;    /* refinement candidates refused */
+  int64_t n_leaves;   /* leaves of the new mesh */
+} amr_remesh_stats;
+
+/* Refreshes U_dev's ghosts, evaluates the indicator on the GPU, copies it to
+ * the host (synchronises the stream) and builds the new mesh (host-owned,
+ * destroy with amr_mesh_destroy).  U_dev must not change before
+ * amr_remesh_apply. */
+amr_status amr_remesh_plan(amr_mesh* mesh, double* U_dev, const amr_remesh_params* params,
+                           amr_mesh** new_mesh_out, amr_remesh_stats* stats, void* stream);
+/* The same decisions from a caller-supplied indicator (S_host: n_leaves
+ * doubles in host memory, storage order); no GPU work.  The returned mesh
+ * can be uploaded and migrated with amr_remesh_apply like the one above. */
+amr_status amr_remesh_plan_host(amr_mesh* mesh, const double* S_host, const amr_remesh_params* params,
+                                amr_mesh** new_mesh_out, amr_remesh_stats* stats);
+/* Fill the active cells of U_new_dev (new mesh layout) from U_old_dev (the
+ * state given to amr_remesh_plan).  new_mesh must have been uploaded. */
+amr_status amr_remesh_apply(amr_mesh* new_mesh, const double* U_old_dev, double* U_new_dev, void* stream);
+/* The indicator alone into ind_dev (n_leaves doubles, device); ghosts of U_dev
+ * must be refreshed. */
+amr_status amr_indicator(amr_mesh* mesh, const double* U_dev, double* ind_dev, void* stream);
+
 /* Launch shapes.  Every choice computes bitwise-identical results (each
  * cell's arithmetic is the same; only the thread mapping changes). */
 typedef struct {

@@ -64,6 +64,16 @@ class LaunchCfg(ctypes.Structure):
     ]
 
 
+class RemeshParams(ctypes.Structure):
+    _fields_ = [("refine_slope", ctypes.c_double), ("coarsen_slope", ctypes.c_double),
+                ("max_blocks", ctypes.c_int64)]
+
+
+class RemeshStats(ctypes.Structure):
+    _fields_ = [("refined", ctypes.c_int64), ("coarsened", ctypes.c_int64), ("refused", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64)]
+
+
 # every entry point declared in include/amr.h: name -> (restype, argtypes)
 _P, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
 SIGNATURES = {
@@ -78,6 +88,12 @@ SIGNATURES = {
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "amr_remesh_plan": (_I32, [_P, _P, ctypes.POINTER(RemeshParams), ctypes.POINTER(_P),
+                               ctypes.POINTER(RemeshStats), _P]),
+    "amr_remesh_plan_host": (_I32, [_P, _P, ctypes.POINTER(RemeshParams), ctypes.POINTER(_P),
+                                    ctypes.POINTER(RemeshStats)]),
+    "amr_remesh_apply": (_I32, [_P, _P, _P, _P]),
+    "amr_indicator": (_I32, [_P, _P, _P, _P]),
     "amr_mesh_set_launch": (_I32, [_P, ctypes.POINTER(LaunchCfg)]),
     "amr_mesh_get_launch": (_I32, [_P, ctypes.POINTER(LaunchCfg)]),
     "amr_profile_enable": (_I32, [_P, _I32]),

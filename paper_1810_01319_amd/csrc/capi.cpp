@@ -125,6 +125,8 @@ DevPlan dev_plan(const amr_mesh* h) {
   }
   P.acc = reinterpret_cast<unsigned long long*>(w + p.off.acc);
   P.counters = reinterpret_cast<unsigned long long*>(w + p.off.counters);
+  P.ind = reinterpret_cast<double*>(w + p.off.ind);
+  P.migr = reinterpret_cast<const MigrTask*>(w + p.off.migr);
   P.faces = reinterpret_cast<double*>(w + p.off.faces);
   P.nleaf = p.nleaf;
   P.np2 = int64_t(p.p2list.size());
@@ -185,6 +187,23 @@ amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index
     e = timed(h, AMR_PHASE_REFLUX, st, [&] { return launch_reflux(P, U, dt, d, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "reflux");
   }
+  return AMR_OK;
+}
+
+amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_params* prm, amr_mesh** out,
+                  amr_remesh_stats* stats) {
+  RemeshResult r = remesh_decide(*h->tree, h->plan, S, prm->refine_slope, prm->coarsen_slope, prm->max_blocks);
+  amr_mesh* nh = new (std::nothrow) amr_mesh();
+  if (!nh) return fail(AMR_E_NOMEM, "out of host memory");
+  nh->tree = std::move(r.tree);
+  nh->plan.migr = std::move(r.migr);
+  nh->cfg = h->cfg;
+  amr_status rc = finish(nh, out);
+  if (rc != AMR_OK) return rc;
+  stats->refined = r.refined;
+  stats->coarsened = r.coarsened;
+  stats->refused = r.refused;
+  stats->n_leaves = (*out)->plan.nleaf;
   return AMR_OK;
 }
 
@@ -313,6 +332,56 @@ amr_status amr_floor_count(amr_mesh* h, int64_t* out, void* stream) {
   if (e != hipSuccess) return hip_fail(e, "floor count");
   *out = int64_t(v);
   return AMR_OK;
+}
+
+amr_status amr_indicator(amr_mesh* h, const double* U, double* ind, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!ind) return fail(AMR_E_INVALID, "null output");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DevPlan P = dev_plan(h);
+  P.ind = ind;
+  hipError_t e = launch_indicator(P, U, st);
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "indicator");
+}
+
+amr_status amr_remesh_plan(amr_mesh* h, double* U, const amr_remesh_params* prm, amr_mesh** out,
+                           amr_remesh_stats* stats, void* stream) {
+  if (!out || !prm || !stats) return fail(AMR_E_INVALID, "null argument");
+  *out = nullptr;
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (h->plan.inst.size() != 1) return fail(AMR_E_INVALID, "remesh works on single meshes");
+  if (prm->max_blocks < h->plan.nleaf)
+    return fail(AMR_E_CAPACITY, "max_blocks below the current leaf count");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = refresh_timed(h, P, U, st);
+  if (e == hipSuccess) e = launch_indicator(P, U, st);
+  std::vector<double> S(size_t(h->plan.nleaf));
+  if (e == hipSuccess) e = hipMemcpyAsync(S.data(), P.ind, S.size() * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "remesh indicator");
+  return decide(h, S, prm, out, stats);
+}
+
+amr_status amr_remesh_plan_host(amr_mesh* h, const double* S_host, const amr_remesh_params* prm, amr_mesh** out,
+                                amr_remesh_stats* stats) {
+  if (!h || !S_host || !prm || !out || !stats) return fail(AMR_E_INVALID, "null argument");
+  *out = nullptr;
+  if (h->plan.inst.size() != 1) return fail(AMR_E_INVALID, "remesh works on single meshes");
+  if (prm->max_blocks < h->plan.nleaf) return fail(AMR_E_CAPACITY, "max_blocks below the current leaf count");
+  std::vector<double> S(S_host, S_host + h->plan.nleaf);
+  return decide(h, S, prm, out, stats);
+}
+
+amr_status amr_remesh_apply(amr_mesh* nh, const double* Uold, double* Unew, void* stream) {
+  amr_status rc = check_ready(nh, Unew);
+  if (rc != AMR_OK) return rc;
+  if (!Uold) return fail(AMR_E_INVALID, "null old state");
+  if (nh->plan.migr.size() != size_t(nh->plan.nleaf)) return fail(AMR_E_STATE, "mesh was not made by amr_remesh_plan");
+  hipError_t e = launch_migrate(dev_plan(nh), Uold, Unew, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "migrate");
 }
 
 amr_status amr_mesh_set_launch(amr_mesh* h, const amr_launch_t* c) {

@@ -725,6 +725,94 @@ __global__ void __launch_bounds__(256) reflux_kernel(double* __restrict__ U, con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Remesh: indicator and data migration
+// ---------------------------------------------------------------------------
+
+// S_b = max over active cells and axes of |rho(+1) - rho(-1)| / (2 rho); one
+// workgroup per leaf, exact maximum.
+template <int N>
+__global__ void __launch_bounds__(256) indicator_kernel(const double* __restrict__ U, DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int N3 = N * N * N;
+  const int s = blockIdx.x;
+  const double* B = U + int64_t(s) * kFields * M3;
+  double best = 0.0;
+  for (int q = threadIdx.x; q < N3; q += blockDim.x) {
+    const int x = q % N, y = (q / N) % N, z = q / (N * N);
+    const int64_t o = (int64_t(z + G) * M + (y + G)) * M + (x + G);
+    const double r0 = B[o];
+    const double sx = fabs(B[o + 1] - B[o - 1]) / (2.0 * r0);
+    const double sy = fabs(B[o + M] - B[o - M]) / (2.0 * r0);
+    const double sz = fabs(B[o + M * M] - B[o - M * M]) / (2.0 * r0);
+    best = sx > best ? sx : best;
+    best = sy > best ? sy : best;
+    best = sz > best ? sz : best;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(best, off, 64);
+    best = o > best ? o : best;
+  }
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < int(blockDim.x >> 6); i++) best = red[i] > best ? red[i] : best;
+    P.ind[s] = best;
+  }
+}
+
+// One thread per active cell of a new leaf: copy, prolong from the old
+// parent's refreshed block (the refresh prolongation formula), or restrict
+// the 8 old children.
+template <int N>
+__global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__ Uold, double* __restrict__ Unew,
+                                                      DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int N3 = N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const int a = q % N, b = (q / N) % N, c = q / (N * N);
+  const MigrTask T = P.migr[s];
+  double* dst = Unew + int64_t(s) * kFields * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
+  if (T.kind == MIGR_COPY) {
+    const double* src = Uold + int64_t(T.src[0]) * kFields * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
+#pragma unroll
+    for (int f = 0; f < kFields; f++) dst[f * M3] = src[f * M3];
+  } else if (T.kind == MIGR_PROLONG) {
+    const int cx = T.co & 1, cy = (T.co >> 1) & 1, cz = (T.co >> 2) & 1;
+    const int la = (cx * N + a) / 2 + G, lb = (cy * N + b) / 2 + G, lc = (cz * N + c) / 2 + G;
+    const double ox = (a & 1) ? 0.25 : -0.25, oy = (b & 1) ? 0.25 : -0.25, oz = (c & 1) ? 0.25 : -0.25;
+    const double* src = Uold + int64_t(T.src[0]) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) {
+      const double* qq = src + f * M3;
+      const double u0 = qq[0];
+      const double sx = minmod(qq[1] - u0, u0 - qq[-1]);
+      const double sy = minmod(qq[M] - u0, u0 - qq[-M]);
+      const double sz = minmod(qq[M * M] - u0, u0 - qq[-M * M]);
+      dst[f * M3] = ((u0 + ox * sx) + oy * sy) + oz * sz;
+    }
+  } else {
+    const int fx = 2 * a, fy = 2 * b, fz = 2 * c;
+    const int ch = (fx / N) + 2 * (fy / N) + 4 * (fz / N);
+    const int la = fx % N + G, lb = fy % N + G, lc = fz % N + G;
+    const double* src = Uold + int64_t(T.src[ch]) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) {
+      const double* qq = src + f * M3;
+      const double v0 = qq[0], v1 = qq[1], v2 = qq[M], v3 = qq[M + 1];
+      const double v4 = qq[M * M], v5 = qq[M * M + 1], v6 = qq[M * M + M], v7 = qq[M * M + M + 1];
+      dst[f * M3] = (((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7))) * 0.125;
+    }
+  }
+}
+
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
 template <int N>
@@ -818,6 +906,31 @@ hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, 
     case 32: return sweep_n<32>(P, U, dt, dir, swept, L, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_indicator(const DevPlan& P, const double* U, hipStream_t st) {
+  if (P.nleaf == 0) return hipSuccess;
+  const dim3 g(unsigned(P.nleaf)), b(256);
+  switch (P.N) {
+    case 8: hipLaunchKernelGGL(indicator_kernel<8>, g, b, 0, st, U, P); break;
+    case 16: hipLaunchKernelGGL(indicator_kernel<16>, g, b, 0, st, U, P); break;
+    case 32: hipLaunchKernelGGL(indicator_kernel<32>, g, b, 0, st, U, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_migrate(const DevPlan& P, const double* Uold, double* Unew, hipStream_t st) {
+  if (P.nleaf == 0) return hipSuccess;
+  const int64_t n = P.nleaf * int64_t(P.N) * P.N * P.N;
+  const dim3 g(grid_for(n, 256)), b(256);
+  switch (P.N) {
+    case 8: hipLaunchKernelGGL(migrate_kernel<8>, g, b, 0, st, Uold, Unew, P); break;
+    case 16: hipLaunchKernelGGL(migrate_kernel<16>, g, b, 0, st, Uold, Unew, P); break;
+    case 32: hipLaunchKernelGGL(migrate_kernel<32>, g, b, 0, st, Uold, Unew, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,

@@ -19,6 +19,8 @@ struct DevPlan {
   const RefluxTask* reflux[3];
   unsigned long long* acc;
   unsigned long long* counters;
+  double* ind;
+  const MigrTask* migr;
   double* faces;
   int64_t nleaf, np2, nreflux[3];
   int32_t ninst, N;
@@ -39,5 +41,9 @@ hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, 
                         const LaunchCfg& L, hipStream_t st);
 hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,
                          hipStream_t st);
+// per-leaf density-slope indicator into P.ind (needs refreshed ghosts)
+hipError_t launch_indicator(const DevPlan& P, const double* U, hipStream_t st);
+// fill the active cells of every leaf of the new plan P from the old state
+hipError_t launch_migrate(const DevPlan& P, const double* Uold, double* Unew, hipStream_t st);
 
 }  // namespace amr

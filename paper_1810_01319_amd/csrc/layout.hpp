@@ -53,8 +53,17 @@ struct RefluxTask {
   int32_t pad;
 };
 
+// Data migration after a remesh, one task per new leaf: copy the old leaf
+// `src[0]`, prolong from the old parent `src[0]` (child octant `co`), or
+// restrict the 8 old children src[0..7] (x fastest, then y, then z).
+enum MigrKind : int32_t { MIGR_COPY = 0, MIGR_PROLONG = 1, MIGR_RESTRICT = 2 };
+struct MigrTask {
+  int32_t kind, co;
+  int32_t src[8];
+};
+
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, faces, total;
+  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, ind, migr, faces, total;
 };
 
 }  // namespace amr

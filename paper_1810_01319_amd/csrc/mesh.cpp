@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 
 namespace amr {
 
@@ -56,6 +57,11 @@ void Octree::refine(int l, int i, int j, int k) {
   node_[pack(l, i, j, k)] = REFINED;
   for (int c = 0; c < 8; c++)
     node_[pack(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2))] = LEAF;
+}
+
+void Octree::unrefine(int l, int i, int j, int k) {
+  node_[pack(l, i, j, k)] = LEAF;
+  for (int c = 0; c < 8; c++) node_.erase(pack(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2)));
 }
 
 std::string Octree::refine_list(const int32_t* keys, int64_t n) {
@@ -187,6 +193,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   N = meshes[0]->desc().N;
   M = N + 2 * kGhost;
   inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); faceslot.clear(); keys.clear();
+  if (!migr.empty() && meshes.size() != 1) return "migration tables belong to single-mesh plans";
   for (auto& r : reflux) r.clear();
   nslots = 0;
   std::vector<int64_t> first;
@@ -320,6 +327,8 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   }
   off.acc = o; o = align256(o + ninst * 8);
   off.counters = o; o = align256(o + 8);
+  off.ind = o; o = align256(o + nleaf * 8);
+  off.migr = o; o = align256(o + int64_t(migr.size() * sizeof(MigrTask)));
   off.faces = o; o = align256(o + nslots * int64_t(kFields) * N * N * 8);
   off.total = o;
   staging.assign(size_t(off.faces), 0);
@@ -333,10 +342,158 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   put(off.p2list, p2list.data(), p2list.size() * sizeof(int32_t));
   put(off.faceslot, faceslot.data(), faceslot.size() * sizeof(int32_t));
   for (int d = 0; d < 3; d++) put(off.reflux[d], reflux[d].data(), reflux[d].size() * sizeof(RefluxTask));
+  put(off.migr, migr.data(), migr.size() * sizeof(MigrTask));
   // dt accumulators start at +inf (bit pattern of a positive double)
   const uint64_t inf_bits = 0x7FF0000000000000ull;
   for (int64_t m = 0; m < ninst; m++) put(off.acc + 8 * m, &inf_bits, 8);
   return "";
+}
+
+// ---------------------------------------------------------------------------
+// Remesh decisions.  Reading of the refinement rule (the paper names the
+// Refine plug-in, not a criterion): leaves with S > refine_slope below the
+// deepest level are candidates, taken in (S descending, then level, z, y, x)
+// order; each is refined together with the minimal refinement restoring 2:1
+// balance, accepted only if every node that closure refines was a leaf before
+// this remesh (one level per remesh) and the leaf count stays <= max_blocks,
+// else refused.  Then, finer parents first (ties by z, y, x), each octet of
+// leaves that were leaves before and all have S < coarsen_slope merges if the
+// merged leaf touches no leaf two levels finer.  Here the closure is a local
+// ripple from the refined node with an undo journal.
+
+namespace {
+uint64_t pk4(int l, int i, int j, int k) {
+  return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
+}
+}  // namespace
+
+RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<double>& S, double refine_slope,
+                           double coarsen_slope, int64_t max_blocks) {
+  RemeshResult res;
+  res.tree.reset(new Octree(old));
+  Octree& T = *res.tree;
+  const MeshDesc& d = old.desc();
+  std::unordered_map<uint64_t, int32_t> old_id;
+  for (int64_t s = 0; s < op.nleaf; s++) {
+    const Key& k = op.keys[size_t(s)];
+    old_id[pk4(k.l, k.i, k.j, k.k)] = int32_t(s);
+  }
+  int64_t leaves = op.nleaf;
+  struct Cand {
+    double S;
+    Key k;
+  };
+  std::vector<Cand> cand;
+  for (int64_t s = 0; s < op.nleaf; s++)
+    if (S[size_t(s)] > refine_slope && op.keys[size_t(s)].l < d.max_level) cand.push_back({S[size_t(s)], op.keys[size_t(s)]});
+  std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    if (a.S != b.S) return a.S > b.S;
+    if (a.k.l != b.k.l) return a.k.l < b.k.l;
+    if (a.k.k != b.k.k) return a.k.k < b.k.k;
+    if (a.k.j != b.k.j) return a.k.j < b.k.j;
+    return a.k.i < b.k.i;
+  });
+  std::vector<Key> journal, stack;
+  for (const Cand& c : cand) {
+    if (T.state(c.k.l, c.k.i, c.k.j, c.k.k) != Octree::LEAF) continue;
+    journal.clear();
+    stack.assign(1, c.k);
+    bool ok = true;
+    while (ok && !stack.empty()) {
+      const Key n = stack.back();
+      stack.pop_back();
+      if (T.state(n.l, n.i, n.j, n.k) != Octree::LEAF) continue;
+      if (old.state(n.l, n.i, n.j, n.k) != Octree::LEAF) {
+        ok = false;  // would refine a leaf created by this remesh
+        break;
+      }
+      T.refine(n.l, n.i, n.j, n.k);
+      journal.push_back(n);
+      const int lc = n.l + 1;
+      for (int ch = 0; ch < 8; ch++) {
+        const int ci = 2 * n.i + (ch & 1), cj = 2 * n.j + ((ch >> 1) & 1), ck = 2 * n.k + (ch >> 2);
+        for (int q = 0; q < 27; q++) {
+          if (q == 13) continue;
+          int p[3] = {ci + q % 3 - 1, cj + (q / 3) % 3 - 1, ck + q / 9 - 1};
+          bool in = true;
+          for (int a = 0; a < 3; a++) in = in && T.wrap(lc, a, p[a]);
+          if (!in) continue;
+          int lv = lc;
+          while (T.state(lv, p[0], p[1], p[2]) == Octree::ABSENT) {
+            lv--;
+            p[0] >>= 1; p[1] >>= 1; p[2] >>= 1;
+          }
+          if (lc - lv >= 2) stack.push_back({lv, p[0], p[1], p[2]});
+        }
+      }
+    }
+    if (ok && leaves + 7 * int64_t(journal.size()) <= max_blocks) {
+      leaves += 7 * int64_t(journal.size());
+      res.refined += int64_t(journal.size());
+    } else {
+      for (auto it = journal.rbegin(); it != journal.rend(); ++it) T.unrefine(it->l, it->i, it->j, it->k);
+      res.refused++;
+    }
+  }
+  // coarsening
+  std::vector<Key> par;
+  for (int64_t s = 0; s < op.nleaf; s++) {
+    const Key& k = op.keys[size_t(s)];
+    if (k.l == 0 || (k.i & 1) || (k.j & 1) || (k.k & 1)) continue;  // visit each octet once, from its first child
+    const Key P{k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1};
+    if (T.state(P.l, P.i, P.j, P.k) != Octree::REFINED) continue;
+    bool ok = true;
+    for (int ch = 0; ch < 8 && ok; ch++) {
+      const int ci = 2 * P.i + (ch & 1), cj = 2 * P.j + ((ch >> 1) & 1), ck = 2 * P.k + (ch >> 2);
+      auto it = old_id.find(pk4(P.l + 1, ci, cj, ck));
+      if (it == old_id.end() || T.state(P.l + 1, ci, cj, ck) != Octree::LEAF) ok = false;
+      else if (!(S[size_t(it->second)] < coarsen_slope)) ok = false;
+    }
+    if (ok) par.push_back(P);
+  }
+  std::sort(par.begin(), par.end(), [](const Key& a, const Key& b) {
+    if (a.l != b.l) return a.l > b.l;
+    if (a.k != b.k) return a.k < b.k;
+    if (a.j != b.j) return a.j < b.j;
+    return a.i < b.i;
+  });
+  for (const Key& P : par) {
+    const int lc = P.l + 1;
+    bool ok = true;
+    for (int dz = -1; dz <= 2 && ok; dz++)
+      for (int dy = -1; dy <= 2 && ok; dy++)
+        for (int dx = -1; dx <= 2 && ok; dx++) {
+          int p[3] = {2 * P.i + dx, 2 * P.j + dy, 2 * P.k + dz};
+          bool in = true;
+          for (int a = 0; a < 3; a++) in = in && T.wrap(lc, a, p[a]);
+          if (!in) continue;
+          if ((p[0] >> 1) == P.i && (p[1] >> 1) == P.j && (p[2] >> 1) == P.k) continue;  // inside P
+          if (T.state(lc, p[0], p[1], p[2]) == Octree::REFINED) ok = false;
+        }
+    if (!ok) continue;
+    T.unrefine(P.l, P.i, P.j, P.k);
+    res.coarsened++;
+  }
+  // migration tasks in the new storage order
+  for (const Key& k : T.leaves()) {
+    MigrTask t{};
+    for (int q = 0; q < 8; q++) t.src[q] = -1;
+    auto it = old_id.find(pk4(k.l, k.i, k.j, k.k));
+    if (it != old_id.end()) {
+      t.kind = MIGR_COPY;
+      t.src[0] = it->second;
+    } else if (k.l > 0 && old_id.count(pk4(k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1))) {
+      t.kind = MIGR_PROLONG;
+      t.src[0] = old_id.at(pk4(k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1));
+      t.co = (k.i & 1) | ((k.j & 1) << 1) | ((k.k & 1) << 2);
+    } else {
+      t.kind = MIGR_RESTRICT;
+      for (int ch = 0; ch < 8; ch++)
+        t.src[ch] = old_id.at(pk4(k.l + 1, 2 * k.i + (ch & 1), 2 * k.j + ((ch >> 1) & 1), 2 * k.k + (ch >> 2)));
+    }
+    res.migr.push_back(t);
+  }
+  return res;
 }
 
 }  // namespace amr

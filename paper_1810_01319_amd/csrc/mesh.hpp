@@ -3,6 +3,7 @@
 // the plan tables the kernels walk.
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -45,6 +46,8 @@ class Octree {
   // outflow boundary
   bool wrap(int l, int ax, int& v) const;
   void refine(int l, int i, int j, int k);
+  // undo of refine(): the node becomes a leaf again, its children vanish
+  void unrefine(int l, int i, int j, int k);
   // Leaves in storage order: roots x-fastest, Morton (depth-first) inside.
   std::vector<Key> leaves() const;
 
@@ -68,6 +71,7 @@ struct Plan {
   std::vector<int32_t> p2list;   // leaves with a coarser neighbour
   std::vector<int32_t> faceslot; // 6 per leaf
   std::vector<RefluxTask> reflux[3];
+  std::vector<MigrTask> migr;    // set before build() by a remesh
   int64_t nslots = 0;
   PlanOffsets off{};
   std::vector<unsigned char> staging;  // bytes [0, off.faces) as uploaded
@@ -79,5 +83,16 @@ struct Plan {
 };
 
 InstParams make_inst_params(const MeshDesc& d);
+
+struct RemeshResult {
+  std::unique_ptr<Octree> tree;
+  std::vector<MigrTask> migr;  // in the new tree's leaf order
+  int64_t refined = 0, coarsened = 0, refused = 0;
+};
+
+// Refinement decisions of a remesh from the per-leaf indicator S (in the
+// old plan's leaf order); see the reading in mesh.cpp.
+RemeshResult remesh_decide(const Octree& old, const Plan& old_plan, const std::vector<double>& S,
+                           double refine_slope, double coarsen_slope, int64_t max_blocks);
 
 }  // namespace amr

@@ -199,3 +199,40 @@ def random_refine_list(root, max_level, n, seed) -> List[Tuple[int, int, int, in
 
 def with_(spec: MeshSpec, **kw) -> MeshSpec:
     return replace(spec, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Array of blasts, one per root octree (the paper's weak-scaling workload)
+# ---------------------------------------------------------------------------
+
+def blasts_spec(root=24, block_cells=32, levels=3) -> MeshSpec:
+    """Uniform start on root^3 octrees of block_cells^3 cells, refined
+    adaptively up to `levels` levels; gamma = 5/3, periodic."""
+    return MeshSpec(root=(root, root, root), block_cells=block_cells, max_level=levels, bc="periodic",
+                    gamma=5.0 / 3.0, cfl=0.4)
+
+
+def blast_centres(root: int, seed: int = 5) -> np.ndarray:
+    """One blast per root octree at the octree centre plus a uniform random
+    offset in [-1/4, 1/4] of the octree width per axis (numpy PCG64, seeded;
+    octrees in x-fastest order), standing in for the paper's randomly chosen
+    letter-shaped sources that keep the refinement from proceeding in
+    lockstep."""
+    rng = np.random.default_rng(seed)
+    w = 1.0 / root
+    out = np.empty((root ** 3, 3))
+    n = 0
+    for k in range(root):
+        for j in range(root):
+            for i in range(root):
+                out[n] = (np.array([i, j, k]) + 0.5) * w + rng.uniform(-0.25, 0.25, 3) * w
+                n += 1
+    return out
+
+
+def blasts_state(spec: MeshSpec, keys, seed: int = 5) -> np.ndarray:
+    """rho = 1, p = 1e-5 and E = 1 per blast deposited in the root-level cells
+    within 2 dx_0 of its centre.  All blasts sit in their own octree, so the
+    per-blast deposits never overlap."""
+    return blast_state(spec, keys, blast_centres(spec.root[0], seed), energy=1.0, rho0=1.0, p0=1e-5,
+                       radius_cells=2.0, level=0)

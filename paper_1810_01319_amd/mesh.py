@@ -28,14 +28,16 @@ class Mesh:
 
     def __init__(self, root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
                  rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), leaves=None,
-                 device="cuda"):
+                 device="cuda", _handle=None):
         self.params = dict(root=tuple(root), block_cells=block_cells, max_level=max_level, bc=bc,
                            gamma=gamma, cfl=cfl, rho_floor=rho_floor, p_floor=p_floor,
                            riemann_iters=riemann_iters)
         L = lib()
         d, keep = _lib.make_desc(refine=refine, **self.params)
         h = ctypes.c_void_p()
-        if leaves is not None:
+        if _handle is not None:
+            h = _handle
+        elif leaves is not None:
             lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
             check(L.amr_mesh_create_from_leaves(ctypes.byref(d), lv.shape[0],
                                                 lv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
@@ -107,6 +109,30 @@ class Mesh:
         out = ctypes.c_int64()
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
         return int(out.value)
+
+    # remesh -----------------------------------------------------------
+    def indicator(self, U: torch.Tensor) -> torch.Tensor:
+        """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""
+        self._check_state(U)
+        out = torch.empty(self.nleaf, dtype=torch.float64, device=self.device)
+        check(lib().amr_indicator(self._h, _ptr(U), _ptr(out), _stream()))
+        return out
+
+    def remesh(self, U: torch.Tensor, refine_slope: float, coarsen_slope: float, max_blocks: int):
+        """Returns (new Mesh, new state, stats dict).  Refreshes U's ghosts."""
+        self._check_state(U)
+        prm = _lib.RemeshParams(float(refine_slope), float(coarsen_slope), int(max_blocks))
+        st = _lib.RemeshStats()
+        h = ctypes.c_void_p()
+        check(lib().amr_remesh_plan(self._h, _ptr(U), ctypes.byref(prm), ctypes.byref(h), ctypes.byref(st),
+                                    _stream()))
+        new = Mesh(device=self.device, _handle=h, **self.params)
+        new.set_launch(**self.get_launch())
+        Un = new.alloc_state()
+        check(lib().amr_remesh_apply(new._h, _ptr(U), _ptr(Un), _stream()))
+        stats = {"refined": int(st.refined), "coarsened": int(st.coarsened), "refused": int(st.refused),
+                 "n_leaves": int(st.n_leaves)}
+        return new, Un, stats
 
     # launch shapes ----------------------------------------------------
     def get_launch(self) -> dict:

@@ -223,3 +223,49 @@ def test_autotuned_launch_is_bitwise_identical():
         gm.step(U, dt, k)
         assert float(dt.cpu()[0]) == om.step(k)
     assert compare_active(gm, U, om, perm)[1] == 1.0
+
+
+def _oracle_adaptive(om, steps, thr_r, thr_c, cap, interval=4):
+    dts, stats = [], []
+    for k in range(steps):
+        if k > 0 and k % interval == 0:
+            om, st = om.remesh(thr_r, thr_c, cap)
+            stats.append([int(v) for v in st])
+        dts.append(om.step(k))
+    return om, dts, stats
+
+
+@pytest.mark.parametrize("root,N,levels,cap_extra", [(3, 8, 2, 10 ** 6), (3, 16, 3, 10 ** 6), (3, 8, 3, 60)])
+def test_adaptive_blasts_parity(root, N, levels, cap_extra):
+    """Blasts with remesh every 4 steps: indicator, decisions, migrated data
+    and the following steps all bitwise equal to the oracle."""
+    from paper_1810_01319_amd import adaptive
+
+    spec = I.blasts_spec(root=root, block_cells=N, levels=levels)
+    say(f"adaptive blasts root={root} N={N} levels={levels}")
+    om, gm, perm = pair(spec)
+    U = load(om, gm, perm, I.blasts_state(spec, gm.keys))
+    cap = gm.nleaf + cap_extra
+    steps = 13
+    gm2, U2, dts, gst = adaptive.run(gm, U, steps, max_blocks=cap)
+    om2, odts, ost = _oracle_adaptive(om, steps, 0.3, 0.1, cap)
+    assert [float(d.cpu()[0]) for d in dts] == odts
+    assert [[s["refined"], s["coarsened"], s["refused"]] for s in gst] == ost
+    idx = {tuple(k): s for s, k in enumerate(om2.keys)}
+    perm2 = np.array([idx[tuple(k)] for k in gm2.keys])
+    err, bw = compare_active(gm2, U2, om2, perm2)
+    say(f"adaptive: leaves {gm.nleaf} -> {gm2.nleaf}, stats {ost}, bitwise {bw}")
+    assert bw == 1.0, err
+
+
+def test_indicator_bitwise():
+    spec = I.blasts_spec(root=3, block_cells=16, levels=2)
+    om, gm, perm = pair(spec)
+    U = load(om, gm, perm, I.blasts_state(spec, gm.keys))
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        gm.step(U, dt, k)
+        om.step(k)
+    gm.refresh(U)
+    om.refresh()
+    assert np.array_equal(gm.indicator(U).cpu().numpy(), om.indicator()[perm])

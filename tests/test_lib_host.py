@@ -125,3 +125,94 @@ def test_unbalanced_or_gapped_leaf_sets_are_rejected():
     bad += [(2, a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
     rc4, _, _ = host_mesh(root=spec.root, block_cells=8, max_level=2, leaves=bad)
     assert rc4 == -2
+
+
+def _blast_oracle(root, N, levels, seed, steps=4):
+    spec = I.MeshSpec(root=(root,) * 3, block_cells=N, max_level=levels, gamma=5 / 3)
+    m = O.OracleMesh(**spec.kwargs())
+    rng = np.random.default_rng(seed)
+    w = 1.0 / root
+    centres = [np.array([(i + 0.5) * w, (j + 0.5) * w, (k + 0.5) * w]) + rng.uniform(-0.25, 0.25, 3) * w
+               for k in range(root) for j in range(root) for i in range(root)]
+    m.set_active(I.blast_state(spec, m.keys, centres, energy=1.0, rho0=1.0, p0=1e-5, radius_cells=2.0, level=0))
+    for k in range(steps):
+        m.step(k)
+    return spec, m
+
+
+@pytest.mark.parametrize("seed,cap_extra,levels", [(5, 10 ** 6, 2), (6, 40, 2), (7, 10 ** 6, 3), (8, 90, 3)])
+def test_host_remesh_decisions_match_oracle(seed, cap_extra, levels):
+    """Same indicator in, same leaf set and counters out: the library's local
+    ripple closure with an undo journal against the oracle's global
+    fixed-point balance, including refusals at a tight capacity and a second
+    remesh that coarsens."""
+    spec, m = _blast_oracle(3, 8, levels, seed)
+    L = _lib.lib()
+    for rnd in range(2):
+        m.refresh()
+        S_or = m.indicator()
+        d, keep = _lib.make_desc(refine=(), **{k: v for k, v in spec.kwargs().items() if k != "refine"})
+        h = ctypes.c_void_p()
+        lv = np.ascontiguousarray(m.keys)
+        assert L.amr_mesh_create_from_leaves(ctypes.byref(d), lv.shape[0], lv.ctypes.data_as(ctypes.c_void_p),
+                                             ctypes.byref(h)) == 0
+        info = _lib.MeshInfo()
+        L.amr_mesh_info(h, ctypes.byref(info))
+        keys = np.zeros((info.n_leaves, 4), dtype=np.int32)
+        L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+        idx = {tuple(k): s for s, k in enumerate(m.keys)}
+        S = np.ascontiguousarray([S_or[idx[tuple(k)]] for k in keys])
+        cap = m.nleaf + cap_extra
+        prm = _lib.RemeshParams(0.3, 0.1 if rnd else 0.0, cap)
+        st = _lib.RemeshStats()
+        h2 = ctypes.c_void_p()
+        assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
+                                      ctypes.byref(st)) == 0
+        L.amr_mesh_info(h2, ctypes.byref(info))
+        k2 = np.zeros((info.n_leaves, 4), dtype=np.int32)
+        L.amr_mesh_blocks(h2, k2.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+        m2, ost = m.remesh(0.3, 0.1 if rnd else 0.0, cap)
+        assert sorted(map(tuple, k2)) == sorted(map(tuple, m2.keys))
+        assert (st.refined, st.coarsened, st.refused) == tuple(int(v) for v in ost)
+        L.amr_mesh_destroy(h2)
+        L.amr_mesh_destroy(h)
+        m = m2
+        for k in range(3):
+            m.step(k)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_host_coarsening_decisions_match_oracle(seed):
+    root = (3, 2, 2)
+    spec = I.MeshSpec(root=root, block_cells=8, max_level=3, gamma=1.4,
+                      refine=I.random_refine_list(root, 3, 10, seed))
+    m = O.OracleMesh(**spec.kwargs())
+    m.set_active(I.smooth_state(spec, m.keys, seed=seed, amp=0.2, vel=0.3))
+    m.refresh()
+    S_or = m.indicator()
+    thr = float(np.median(S_or))
+    L = _lib.lib()
+    d, keep = _lib.make_desc(**spec.kwargs())
+    h = ctypes.c_void_p()
+    assert L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h)) == 0
+    info = _lib.MeshInfo()
+    L.amr_mesh_info(h, ctypes.byref(info))
+    keys = np.zeros((info.n_leaves, 4), dtype=np.int32)
+    L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+    idx = {tuple(k): s for s, k in enumerate(m.keys)}
+    S = np.ascontiguousarray([S_or[idx[tuple(k)]] for k in keys])
+    for rs in (1e9, thr * 2):
+        prm = _lib.RemeshParams(rs, thr, 10 ** 6)
+        st = _lib.RemeshStats()
+        h2 = ctypes.c_void_p()
+        assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
+                                      ctypes.byref(st)) == 0
+        L.amr_mesh_info(h2, ctypes.byref(info))
+        k2 = np.zeros((info.n_leaves, 4), dtype=np.int32)
+        L.amr_mesh_blocks(h2, k2.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+        m2, ost = m.remesh(rs, thr, 10 ** 6)
+        assert st.coarsened > 0
+        assert sorted(map(tuple, k2)) == sorted(map(tuple, m2.keys))
+        assert (st.refined, st.coarsened, st.refused) == tuple(int(v) for v in ost)
+        L.amr_mesh_destroy(h2)
+    L.amr_mesh_destroy(h)
