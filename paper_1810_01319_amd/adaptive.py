@@ -9,16 +9,38 @@ import torch
 from .mesh import Mesh
 
 
-def capacity_from_memory(mesh: Mesh, reserve_bytes: int = 8 << 30) -> int:
-    """Largest leaf count whose old and new state fit in free HBM together
-    (a remesh holds both while it migrates)."""
-    free, _ = torch.cuda.mem_get_info(mesh.device)
+def capacity_from_memory(mesh: Mesh, reserve_bytes: int = 24 << 30) -> int:
+    """Largest leaf count such that an old and a new state of that size fit in
+    the device's HBM together (a remesh holds both while it migrates)."""
+    total = torch.cuda.get_device_properties(mesh.device).total_memory
     per_block = mesh.info.block_stride * 8
-    return max(mesh.nleaf, int((free - reserve_bytes) // (2 * per_block)))
+    return max(mesh.nleaf, int((total - reserve_bytes) // (2 * per_block)))
+
+
+class StatePool:
+    """Two fixed state arenas of `capacity` blocks each, allocated once: a
+    remesh migrates from the arena holding the current state into the other,
+    so an adaptive run allocates no device memory after start-up and the
+    allocator cannot fragment the 288 GB of HBM."""
+
+    def __init__(self, mesh: Mesh, capacity: int):
+        n = capacity * mesh.info.block_stride
+        self.capacity = capacity
+        self.bufs = [torch.empty(n, dtype=torch.float64, device=mesh.device) for _ in range(2)]
+        self.cur = 0
+
+    def initial(self, mesh: Mesh, fn) -> torch.Tensor:
+        return mesh.state_from_blocks(fn, out=self.bufs[self.cur])
+
+    def other(self) -> torch.Tensor:
+        return self.bufs[1 - self.cur]
+
+    def swap(self) -> None:
+        self.cur = 1 - self.cur
 
 
 def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope=0.1, interval=4,
-        max_blocks=None, start=0, on_remesh=None):
+        max_blocks=None, start=0, on_remesh=None, pool: StatePool = None):
     """Advance `steps` steps from step index `start`, remeshing before every
     step index that is a positive multiple of `interval`.  Returns
     (mesh, U, dt list (device tensors), remesh stats list)."""
@@ -26,7 +48,12 @@ def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope
     for k in range(start, start + steps):
         if interval and k > 0 and k % interval == 0:
             cap = max_blocks if max_blocks is not None else capacity_from_memory(mesh)
-            new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap)
+            if pool is not None:
+                cap = min(cap, pool.capacity)
+                new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap, out=pool.other())
+                pool.swap()
+            else:
+                new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap)
             mesh, U = new, Un
             stats.append(st)
             if on_remesh is not None:

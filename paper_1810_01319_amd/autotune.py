@@ -27,9 +27,13 @@ def _key(mesh) -> str:
     return f"{name}|N{mesh.N}|leaves{mesh.nleaf}|levels{lv}"
 
 
-def _time_axis(mesh, U, dt, axis, steps):
+def _time_axis(mesh, U, dt, axis, steps, scratch=None):
     """Mean ms of the given axis' sweep over `steps` steps (both parities)."""
-    work = U.clone()
+    if scratch is not None:
+        work = scratch[:U.numel()].view(U.shape)
+        work.copy_(U)
+    else:
+        work = U.clone()
     mesh.step(work, dt, 0)  # warm-up
     mesh.profile(True)
     for k in range(steps):
@@ -40,7 +44,7 @@ def _time_axis(mesh, U, dt, axis, steps):
     return ms / max(n, 1)
 
 
-def tune(mesh, U, steps: int = 2, use_cache: bool = True) -> dict:
+def tune(mesh, U, steps: int = 2, use_cache: bool = True, scratch=None) -> dict:
     """Choose per-axis sweep kernels for this mesh; applies and returns the
     launch configuration."""
     key = _key(mesh)
@@ -66,7 +70,7 @@ def tune(mesh, U, steps: int = 2, use_cache: bool = True) -> dict:
             modes = list(best_mode)
             modes[axis] = mode
             mesh.set_launch(sweep_mode=modes, sweep_block=block if mode == 0 else best_block)
-            t = _time_axis(mesh, U, dt, axis, steps)
+            t = _time_axis(mesh, U, dt, axis, steps, scratch)
             timings[f"axis{axis}_mode{mode}_block{block}"] = t
             if best is None or t < best[0]:
                 best = (t, mode, block)

@@ -232,7 +232,28 @@ def blast_centres(root: int, seed: int = 5) -> np.ndarray:
 
 def blasts_state(spec: MeshSpec, keys, seed: int = 5) -> np.ndarray:
     """rho = 1, p = 1e-5 and E = 1 per blast deposited in the root-level cells
-    within 2 dx_0 of its centre.  All blasts sit in their own octree, so the
-    per-blast deposits never overlap."""
-    return blast_state(spec, keys, blast_centres(spec.root[0], seed), energy=1.0, rho0=1.0, p0=1e-5,
-                       radius_cells=2.0, level=0)
+    within 2 dx_0 of its centre.  Each blast lies inside its own octree at
+    least N/4 - 2 cells from the octree's faces, so only that octree's root
+    block receives it; on a uniform level-0 mesh this is evaluated block by
+    block (any subset of the root blocks, in any order)."""
+    keys = np.asarray(keys)
+    R = spec.root[0]
+    centres = blast_centres(R, seed)
+    if not np.all(keys[:, 0] == 0) or spec.block_cells < 16:
+        return blast_state(spec, keys, centres, energy=1.0, rho0=1.0, p0=1e-5, radius_cells=2.0, level=0)
+    N = spec.block_cells
+    dx = spec.dx(0)
+    x, y, z = cell_centres(spec, keys)
+    own = centres[keys[:, 1] + R * (keys[:, 2] + R * keys[:, 3])]  # [n, 3]
+    d2 = np.zeros(x.shape)
+    for a, X in enumerate((x, y, z)):
+        d = X - own[:, a][:, None, None, None]
+        d2 = d2 + d * d
+    sel = d2 < (2.0 * dx) ** 2
+    nsel = sel.reshape(len(keys), -1).sum(axis=1)
+    if np.any(nsel == 0):
+        raise ValueError("blast deposit region is empty")
+    U = conserved(spec.gamma, np.full(x.shape, 1.0), 0.0, 0.0, 0.0, np.full(x.shape, 1e-5))
+    add = (1.0 / (nsel * dx ** 3))[:, None, None, None]
+    U[:, 4] = np.where(sel, U[:, 4] + add, U[:, 4])
+    return U

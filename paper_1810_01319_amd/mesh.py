@@ -77,6 +77,22 @@ class Mesh:
         U[:, :, g:g + N, g:g + N, g:g + N] = torch.from_numpy(np.ascontiguousarray(act))
         return U.to(self.device)
 
+    def state_from_blocks(self, fn, chunk: int = 512, out: torch.Tensor = None) -> torch.Tensor:
+        """Device state filled chunk by chunk from fn(keys) -> active cells
+        [n, 5, N, N, N] (host numpy), for states too large to stage at once;
+        placed at the start of the flat buffer `out` if given."""
+        shape = (self.nleaf, NFIELD, self.M, self.M, self.M)
+        if out is not None:
+            U = out[:self.nleaf * NFIELD * self.M ** 3].view(shape)
+        else:
+            U = torch.empty(shape, dtype=torch.float64, device=self.device)
+        g, N = GHOST, self.N
+        for a in range(0, self.nleaf, chunk):
+            b = min(self.nleaf, a + chunk)
+            act = torch.from_numpy(np.ascontiguousarray(fn(self.keys[a:b])))
+            U[a:b, :, g:g + N, g:g + N, g:g + N] = act.to(self.device)
+        return U
+
     def active(self, U: torch.Tensor) -> np.ndarray:
         g, N = GHOST, self.N
         return U[:, :, g:g + N, g:g + N, g:g + N].cpu().numpy()
@@ -118,8 +134,11 @@ class Mesh:
         check(lib().amr_indicator(self._h, _ptr(U), _ptr(out), _stream()))
         return out
 
-    def remesh(self, U: torch.Tensor, refine_slope: float, coarsen_slope: float, max_blocks: int):
-        """Returns (new Mesh, new state, stats dict).  Refreshes U's ghosts."""
+    def remesh(self, U: torch.Tensor, refine_slope: float, coarsen_slope: float, max_blocks: int,
+               out: torch.Tensor = None):
+        """Returns (new Mesh, new state, stats dict).  Refreshes U's ghosts.
+        `out`, if given, is a flat float64 device buffer of at least
+        max_blocks blocks that receives the new state (no allocation)."""
         self._check_state(U)
         prm = _lib.RemeshParams(float(refine_slope), float(coarsen_slope), int(max_blocks))
         st = _lib.RemeshStats()
@@ -128,7 +147,20 @@ class Mesh:
                                     _stream()))
         new = Mesh(device=self.device, _handle=h, **self.params)
         new.set_launch(**self.get_launch())
-        Un = new.alloc_state()
+        # ghosts are scratch that the next refresh fills; migration writes
+        # every active cell.  Cached free blocks are released first so that
+        # a state near the capacity limit finds contiguous memory.
+        shape = (new.nleaf, NFIELD, new.M, new.M, new.M)
+        if out is not None:
+            n = new.nleaf * NFIELD * new.M ** 3
+            if out.dtype != torch.float64 or out.numel() < n or out.device != self.device:
+                raise ValueError("out buffer too small or of the wrong type")
+            if out.data_ptr() == U.data_ptr():
+                raise ValueError("out must not alias the old state")
+            Un = out[:n].view(shape)
+        else:
+            torch.cuda.empty_cache()
+            Un = torch.empty(shape, dtype=torch.float64, device=self.device)
         check(lib().amr_remesh_apply(new._h, _ptr(U), _ptr(Un), _stream()))
         stats = {"refined": int(st.refined), "coarsened": int(st.coarsened), "refused": int(st.refused),
                  "n_leaves": int(st.n_leaves)}
