@@ -66,6 +66,66 @@ def cpu_baseline(spec, act_fn, steps):
                       f"step, {t:.1f} s"}
 
 
+def batched_compare(steps: int, n_inst: int = 256):
+    """The batched workload: n_inst independent meshes of uneven size in one
+    flat worklist (two steps captured in a HIP graph) against the same
+    meshes stepped one mesh per launch sequence."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    inst = [I.batch_instance(i) for i in range(n_inst)]
+    bm = Mesh.batch([sp.kwargs() for sp, _ in inst])
+    acts = [I.batch_state(sp, bm.keys[bm.first_leaf[i]:bm.first_leaf[i + 1]], c) for i, (sp, c) in enumerate(inst)]
+    cells = bm.nleaf * bm.N ** 3
+    side = torch.cuda.Stream()
+    out = {"instances": n_inst, "leaves": int(bm.nleaf), "cells": int(cells), "steps": steps}
+    with torch.cuda.stream(side):
+        U = torch.empty((bm.nleaf, 5, bm.M, bm.M, bm.M), dtype=torch.float64, device=bm.device)
+        g3 = 3
+        for i, a in enumerate(acts):
+            U[bm.first_leaf[i]:bm.first_leaf[i + 1], :, g3:g3 + bm.N, g3:g3 + bm.N, g3:g3 + bm.N] = \
+                torch.from_numpy(a).to(bm.device)
+        dt = bm.dt_tensor()
+        # eager batched steps
+        bm.step(U, dt, 0)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, steps + 1):
+            bm.step(U, dt, k)
+        side.synchronize()
+        out["batched_eager"] = cells * steps / (time.perf_counter() - t0)
+        # graph of two steps
+        g = bm.graph(U, dt, first_step=0)
+        g.launch()
+        side.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // 2):
+            g.launch()
+        side.synchronize()
+        out["batched_graph"] = cells * 2 * (steps // 2) / (time.perf_counter() - t0)
+        del g
+        # one mesh per launch sequence
+        meshes = []
+        for i, (sp, _) in enumerate(inst):
+            m = Mesh(**sp.kwargs())
+            um = m.state_from_active(acts[i])
+            meshes.append((m, um, torch.zeros(1, dtype=torch.float64, device=m.device)))
+        for m, um, dtm in meshes:
+            m.step(um, dtm, 0)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, steps + 1):
+            for m, um, dtm in meshes:
+                m.step(um, dtm, k)
+        side.synchronize()
+        out["per_mesh_launch"] = cells * steps / (time.perf_counter() - t0)
+    out["speedup_graph_vs_per_mesh"] = out["batched_graph"] / out["per_mesh_launch"]
+    return out
+
+
 def run_adaptive(args, spec, desc):
     """The large adaptive workload: remesh included in the timed region."""
     import torch
@@ -134,6 +194,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--batch-steps", type=int, default=20, help="steps of the batched comparison (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -219,6 +280,9 @@ def main():
         "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
                         "peak": PEAK_HBM_GBS},
     }
+    if args.batch_steps > 0:
+        del U
+        out["batched"] = batched_compare(args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)

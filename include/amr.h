@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 typedef struct amr_mesh amr_mesh;
+typedef struct amr_graph amr_graph;
 
 typedef int32_t amr_status;
 #define AMR_OK 0
@@ -81,6 +82,7 @@ typedef struct {
   int64_t workspace_bytes; /* bytes the caller allocates for amr_mesh_upload */
   int64_t n_cf_faces;      /* coarse-fine block faces (both sides counted) */
   int32_t levels[8];       /* leaves per level */
+  int64_t n_instances;     /* meshes in the handle (1 unless batched) */
 } amr_mesh_info_t;
 
 /* Build the balanced array-of-octrees: roots, then each refine entry in
@@ -96,6 +98,19 @@ amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out);
  * violate the 2:1 rule. */
 amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n,
                                        const int32_t* keys, amr_mesh** out);
+
+/* Batched meshes: n independent meshes (each its own array of octrees, gas,
+ * boundaries and static refinement; all with the same block_cells) in one
+ * handle whose leaves form one flat worklist: instance 0's leaves first,
+ * each instance's in its own storage order.  Every step entry point then
+ * advances all instances in the same launches, each with its own dt:
+ * dt_dev holds n doubles.  This is the paper's "agglomerating work units"
+ * (Sec. IV) applied to many small meshes on one GPU.  Remesh is for
+ * single meshes. */
+amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_mesh** out);
+/* first_leaf[m] = index of instance m's first leaf, first_leaf[n] =
+ * n_leaves (host memory, cap >= n_instances + 1). */
+amr_status amr_mesh_instance_offsets(const amr_mesh* mesh, int64_t* first_leaf, int64_t cap);
 
 amr_status amr_mesh_destroy(amr_mesh* mesh);
 amr_status amr_mesh_info(const amr_mesh* mesh, amr_mesh_info_t* out);
@@ -130,6 +145,15 @@ amr_status amr_hydro_step(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t
 /* The same step with dt given on the device (no CFL reduction). */
 amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,
                              int64_t step_index, void* stream);
+
+/* HIP graph of two consecutive steps (first_step and first_step+1, so one
+ * even and one odd sweep order) bound to U_dev and dt_dev, captured on a
+ * non-null stream; each launch advances the state by two steps.  The
+ * captured kernels read and write the same buffers every launch. */
+amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t first_step, void* stream,
+                            amr_graph** out);
+amr_status amr_graph_launch(amr_graph* graph, void* stream);
+amr_status amr_graph_destroy(amr_graph* graph);
 
 /* Number of post-update floor resets since upload (synchronises the
  * stream). */

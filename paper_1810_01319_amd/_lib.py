@@ -52,6 +52,7 @@ class MeshInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("n_cf_faces", ctypes.c_int64),
         ("levels", ctypes.c_int32 * 8),
+        ("n_instances", ctypes.c_int64),
     ]
 
 
@@ -79,6 +80,11 @@ _P, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
 SIGNATURES = {
     "amr_mesh_create": (_I32, [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)]),
     "amr_mesh_create_from_leaves": (_I32, [ctypes.POINTER(MeshDesc), _I64, _P, ctypes.POINTER(_P)]),
+    "amr_batch_create": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
+    "amr_mesh_instance_offsets": (_I32, [_P, _P, _I64]),
+    "amr_graph_create": (_I32, [_P, _P, _P, _I64, _P, ctypes.POINTER(_P)]),
+    "amr_graph_launch": (_I32, [_P, _P]),
+    "amr_graph_destroy": (_I32, [_P]),
     "amr_mesh_destroy": (_I32, [_P]),
     "amr_mesh_info": (_I32, [_P, ctypes.POINTER(MeshInfo)]),
     "amr_mesh_blocks": (_I32, [_P, _P, _I64]),

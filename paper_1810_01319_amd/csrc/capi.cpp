@@ -44,7 +44,8 @@ struct Profiler {
 };
 
 struct amr_mesh {
-  std::unique_ptr<Octree> tree;
+  std::vector<std::unique_ptr<Octree>> trees;  // one per instance
+  Octree* tree = nullptr;                      // trees[0]
   Plan plan;
   unsigned char* ws = nullptr;  // caller-owned device workspace
   LaunchCfg cfg;
@@ -91,20 +92,25 @@ amr_status to_desc(const amr_mesh_desc* d, MeshDesc& m) {
 }
 
 amr_status finish(amr_mesh* h, amr_mesh** out) {
-  std::vector<const Octree*> v{h->tree.get()};
+  std::vector<const Octree*> v;
+  for (auto& t : h->trees) v.push_back(t.get());
+  h->tree = h->trees[0].get();
   std::string e = h->plan.build(v);
   if (!e.empty()) {
     delete h;
     return fail(AMR_E_BALANCE, e);
   }
-  bool outflow = false;
-  for (int a = 0; a < 3; a++) outflow = outflow || h->tree->desc().bc[a] == AMR_BC_OUTFLOW;
-  if (outflow)
-    for (const Key& k : h->plan.keys)
-      if (k.l != 0) {
+  for (size_t m = 0; m < h->trees.size(); m++) {
+    bool outflow = false;
+    for (int a = 0; a < 3; a++) outflow = outflow || h->trees[m]->desc().bc[a] == AMR_BC_OUTFLOW;
+    if (!outflow) continue;
+    const InstParams& ip = h->plan.inst[m];
+    for (int64_t s = ip.first_leaf; s < ip.first_leaf + ip.n_leaf; s++)
+      if (h->plan.keys[size_t(s)].l != 0) {
         delete h;
         return fail(AMR_E_INVALID, "outflow boundaries need a single-level mesh");
       }
+  }
   *out = h;
   return AMR_OK;
 }
@@ -195,7 +201,7 @@ amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_pa
   RemeshResult r = remesh_decide(*h->tree, h->plan, S, prm->refine_slope, prm->coarsen_slope, prm->max_blocks);
   amr_mesh* nh = new (std::nothrow) amr_mesh();
   if (!nh) return fail(AMR_E_NOMEM, "out of host memory");
-  nh->tree = std::move(r.tree);
+  nh->trees.push_back(std::move(r.tree));
   nh->plan.migr = std::move(r.migr);
   nh->cfg = h->cfg;
   amr_status rc = finish(nh, out);
@@ -219,8 +225,8 @@ amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out) {
   if (rc != AMR_OK) return rc;
   amr_mesh* h = new (std::nothrow) amr_mesh();
   if (!h) return fail(AMR_E_NOMEM, "out of host memory");
-  h->tree.reset(new Octree(m));
-  std::string e = h->tree->refine_list(desc->refine, desc->n_refine);
+  h->trees.emplace_back(new Octree(m));
+  std::string e = h->trees[0]->refine_list(desc->refine, desc->n_refine);
   if (!e.empty()) {
     delete h;
     return fail(AMR_E_INVALID, e);
@@ -238,13 +244,48 @@ amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n, con
   if (n <= 0 || !keys) return fail(AMR_E_INVALID, "empty leaf list");
   amr_mesh* h = new (std::nothrow) amr_mesh();
   if (!h) return fail(AMR_E_NOMEM, "out of host memory");
-  h->tree.reset(new Octree(m));
-  std::string e = h->tree->from_leaves(keys, n);
+  h->trees.emplace_back(new Octree(m));
+  std::string e = h->trees[0]->from_leaves(keys, n);
   if (!e.empty()) {
     delete h;
     return fail(AMR_E_BALANCE, e);
   }
   return finish(h, out);
+}
+
+amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_mesh** out) {
+  if (!out || !descs || n < 1) return fail(AMR_E_INVALID, "need at least one descriptor");
+  *out = nullptr;
+  amr_mesh* h = new (std::nothrow) amr_mesh();
+  if (!h) return fail(AMR_E_NOMEM, "out of host memory");
+  for (int32_t i = 0; i < n; i++) {
+    MeshDesc m{};
+    amr_status rc = to_desc(&descs[i], m);
+    if (rc != AMR_OK) {
+      delete h;
+      return rc;
+    }
+    if (m.N != descs[0].block_cells) {
+      delete h;
+      return fail(AMR_E_INVALID, "all instances of a batch need the same block_cells");
+    }
+    h->trees.emplace_back(new Octree(m));
+    std::string e = h->trees.back()->refine_list(descs[i].refine, descs[i].n_refine);
+    if (!e.empty()) {
+      delete h;
+      return fail(AMR_E_INVALID, "instance " + std::to_string(i) + ": " + e);
+    }
+  }
+  return finish(h, out);
+}
+
+amr_status amr_mesh_instance_offsets(const amr_mesh* h, int64_t* first_leaf, int64_t cap) {
+  if (!h || !first_leaf) return fail(AMR_E_INVALID, "null argument");
+  const int64_t n = int64_t(h->plan.inst.size());
+  if (cap < n + 1) return fail(AMR_E_INVALID, "output too small");
+  for (int64_t m = 0; m < n; m++) first_leaf[m] = h->plan.inst[size_t(m)].first_leaf;
+  first_leaf[n] = h->plan.nleaf;
+  return AMR_OK;
 }
 
 amr_status amr_mesh_destroy(amr_mesh* mesh) {
@@ -264,6 +305,7 @@ amr_status amr_mesh_info(const amr_mesh* h, amr_mesh_info_t* out) {
   out->field_bytes = p.nleaf * out->block_stride * 8;
   out->workspace_bytes = p.off.total;
   out->n_cf_faces = p.nslots;
+  out->n_instances = int64_t(p.inst.size());
   for (const Key& k : p.keys)
     if (k.l < 8) out->levels[k.l]++;
   return AMR_OK;
@@ -431,6 +473,64 @@ amr_status amr_profile_read(amr_mesh* h, double* ms_out, int64_t* launches_out) 
     launches_out[r.phase] += 1;
   }
   h->prof.release_all();
+  return AMR_OK;
+}
+
+struct amr_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+amr_status amr_graph_create(amr_mesh* h, double* U, double* dt, int64_t first_step, void* stream, amr_graph** out) {
+  if (!out) return fail(AMR_E_INVALID, "null output");
+  *out = nullptr;
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  if (!stream) return fail(AMR_E_INVALID, "graph capture needs a non-null stream");
+  if (h->prof.on) return fail(AMR_E_STATE, "turn profiling off before capturing");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  amr_graph* g = new (std::nothrow) amr_graph();
+  if (!g) return fail(AMR_E_NOMEM, "out of host memory");
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "begin capture");
+  }
+  const DevPlan P = dev_plan(h);
+  amr_status srs = AMR_OK;
+  for (int64_t k = first_step; k < first_step + 2 && srs == AMR_OK; k++) {
+    hipError_t e2 = launch_cfl(P, U, dt, h->cfg, st);
+    if (e2 != hipSuccess) srs = hip_fail(e2, "cfl");
+    else srs = run_step(h, U, dt, k, st);
+  }
+  e = hipStreamEndCapture(st, &g->graph);
+  if (srs != AMR_OK || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return srs != AMR_OK ? srs : hip_fail(e, "end capture");
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(e, "instantiate");
+  }
+  *out = g;
+  return AMR_OK;
+}
+
+amr_status amr_graph_launch(amr_graph* g, void* stream) {
+  if (!g) return fail(AMR_E_INVALID, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "graph launch");
+}
+
+amr_status amr_graph_destroy(amr_graph* g) {
+  if (!g) return AMR_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return AMR_OK;
 }
 

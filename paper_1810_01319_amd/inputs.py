@@ -257,3 +257,56 @@ def blasts_state(spec: MeshSpec, keys, seed: int = 5) -> np.ndarray:
     add = (1.0 / (nsel * dx ** 3))[:, None, None, None]
     U[:, 4] = np.where(sel, U[:, 4] + add, U[:, 4])
     return U
+
+
+# ---------------------------------------------------------------------------
+# Batched uneven meshes: Gaussian density blobs, one problem per instance
+# ---------------------------------------------------------------------------
+
+def batch_instance(i: int, block_cells: int = 16, seed0: int = 3000):
+    """Instance i of the batched workload (numpy PCG64 seed seed0 + i): root
+    array n^3 with n drawn from {2,4,6,8}, depth L in {0..3}, 1-3 blobs with
+    centres uniform in [0,1)^3; rho = 1 + 0.5 sum_b exp(-r_b^2/0.01) (periodic
+    minimum image), p = 1, at rest, gamma 5/3, periodic.  Static refinement:
+    at each level l < L every block meeting a sphere of radius 0.1 * 2^-l
+    around a blob centre.  Returns (MeshSpec, blob centres)."""
+    rng = np.random.default_rng(seed0 + i)
+    n = int(rng.choice([2, 4, 6, 8]))
+    L = int(rng.integers(0, 4))
+    nb = int(rng.integers(1, 4))
+    centres = rng.uniform(0.0, 1.0, size=(nb, 3))
+    refine = []
+    for l in range(L):
+        e = n << l
+        w = 1.0 / e
+        rad = 0.1 * 2.0 ** (-l)
+        idx = np.arange(e)
+        lo = idx * w
+        for c in centres:
+            # per-axis distance from the centre to each block interval, periodic
+            dd = []
+            for a in range(3):
+                d = np.maximum(0.0, np.maximum(lo - c[a], c[a] - (lo + w)))
+                d = np.minimum(d, np.maximum(0.0, np.maximum(lo - (c[a] + 1.0), (c[a] + 1.0) - (lo + w))))
+                d = np.minimum(d, np.maximum(0.0, np.maximum(lo - (c[a] - 1.0), (c[a] - 1.0) - (lo + w))))
+                dd.append(d)
+            d2 = dd[0][None, None, :] ** 2 + dd[1][None, :, None] ** 2 + dd[2][:, None, None] ** 2
+            kk, jj, ii = np.nonzero(d2 < rad * rad)
+            refine.extend((l, int(a), int(b), int(c_)) for a, b, c_ in zip(ii, jj, kk))
+    refine = sorted(set(refine))
+    spec = MeshSpec(root=(n, n, n), block_cells=block_cells, max_level=max(L, 0), bc="periodic",
+                    gamma=5.0 / 3.0, cfl=0.4, refine=refine)
+    return spec, centres
+
+
+def batch_state(spec: MeshSpec, keys, centres) -> np.ndarray:
+    x, y, z = cell_centres(spec, keys)
+    rho = np.ones(x.shape)
+    for c in centres:
+        d2 = np.zeros(x.shape)
+        for a, X in enumerate((x, y, z)):
+            d = X - c[a]
+            d = d - np.round(d)
+            d2 = d2 + d * d
+        rho = rho + 0.5 * np.exp(-d2 / 0.01)
+    return conserved(spec.gamma, rho, 0.0, 0.0, 0.0, np.ones(x.shape))

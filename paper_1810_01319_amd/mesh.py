@@ -33,10 +33,22 @@ class Mesh:
                            gamma=gamma, cfl=cfl, rho_floor=rho_floor, p_floor=p_floor,
                            riemann_iters=riemann_iters)
         L = lib()
-        d, keep = _lib.make_desc(refine=refine, **self.params)
         h = ctypes.c_void_p()
+        batch = isinstance(root, (list, tuple)) and len(root) > 0 and isinstance(root[0], dict)
+        if not batch and _handle is None:
+            d, keep = _lib.make_desc(refine=refine, **self.params)
         if _handle is not None:
             h = _handle
+        elif batch:
+            # a batch: root is a list of per-instance parameter dicts
+            descs = (_lib.MeshDesc * len(root))()
+            keeps = []
+            for i, kw in enumerate(root):
+                di, ki = _lib.make_desc(**kw)
+                descs[i] = di
+                keeps.append(ki)
+            check(L.amr_batch_create(descs, len(root), ctypes.byref(h)))
+            self.params = None
         elif leaves is not None:
             lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
             check(L.amr_mesh_create_from_leaves(ctypes.byref(d), lv.shape[0],
@@ -53,6 +65,10 @@ class Mesh:
         keys = np.zeros((self.nleaf, 4), dtype=np.int32)
         check(L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), self.nleaf))
         self.keys = keys
+        self.n_instances = int(info.n_instances)
+        off = np.zeros(self.n_instances + 1, dtype=np.int64)
+        check(L.amr_mesh_instance_offsets(h, off.ctypes.data_as(ctypes.c_void_p), off.size))
+        self.first_leaf = off
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -126,6 +142,24 @@ class Mesh:
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
         return int(out.value)
 
+    @classmethod
+    def batch(cls, specs, device="cuda"):
+        """Many independent meshes (list of parameter dicts, each with its own
+        `refine` list) in one flat worklist; dt tensors hold one double per
+        instance."""
+        return cls(root=list(specs), block_cells=specs[0]["block_cells"], device=device)
+
+    def dt_tensor(self) -> torch.Tensor:
+        return torch.zeros(self.n_instances, dtype=torch.float64, device=self.device)
+
+    def graph(self, U: torch.Tensor, dt: torch.Tensor, first_step: int = 0) -> "Graph":
+        """Capture two consecutive steps into a HIP graph (on the current
+        stream, which must not be the null stream)."""
+        self._check_state(U)
+        g = ctypes.c_void_p()
+        check(lib().amr_graph_create(self._h, _ptr(U), _ptr(dt), int(first_step), _stream(), ctypes.byref(g)))
+        return Graph(g, self, U, dt)
+
     # remesh -----------------------------------------------------------
     def indicator(self, U: torch.Tensor) -> torch.Tensor:
         """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""
@@ -194,3 +228,19 @@ class Mesh:
         check(lib().amr_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
                                      n.ctypes.data_as(ctypes.c_void_p)))
         return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(_lib.PHASES)}
+
+
+class Graph:
+    """Two captured steps; launch() advances the bound state by two steps."""
+
+    def __init__(self, handle, mesh, U, dt):
+        self._h, self._keep = handle, (mesh, U, dt)
+
+    def launch(self) -> None:
+        check(lib().amr_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.amr_graph_destroy(h)
+            self._h = None

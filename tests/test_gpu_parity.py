@@ -269,3 +269,62 @@ def test_indicator_bitwise():
     gm.refresh(U)
     om.refresh()
     assert np.array_equal(gm.indicator(U).cpu().numpy(), om.indicator()[perm])
+
+
+def test_batched_instances_match_oracle_bitwise():
+    """16 uneven instances of the batched workload in one worklist: every
+    instance's dt sequence and state equal its own oracle run bitwise."""
+    specs, cents = zip(*[I.batch_instance(i) for i in range(16)])
+    gm = Mesh.batch([s.kwargs() for s in specs])
+    say(f"batch of 16: {gm.nleaf} leaves")
+    acts = []
+    oms = []
+    for i, (sp, c) in enumerate(zip(specs, cents)):
+        keys = gm.keys[gm.first_leaf[i]:gm.first_leaf[i + 1]]
+        acts.append(I.batch_state(sp, keys, c))
+        om = O.OracleMesh(**sp.kwargs())
+        idx = {tuple(k): s for s, k in enumerate(om.keys)}
+        perm = np.array([idx[tuple(k)] for k in keys])
+        o = np.empty_like(acts[-1])
+        o[perm] = acts[-1]
+        om.set_active(o)
+        oms.append((om, perm))
+    U = gm.state_from_active(np.concatenate(acts))
+    dt = gm.dt_tensor()
+    for k in range(4):
+        gm.step(U, dt, k)
+        dts = dt.cpu().numpy()
+        for i, (om, perm) in enumerate(oms):
+            assert dts[i] == om.step(k), (i, k)
+    act = gm.active(U)
+    for i, (om, perm) in enumerate(oms):
+        a = act[gm.first_leaf[i]:gm.first_leaf[i + 1]]
+        assert np.array_equal(a, om.active()[perm]), i
+
+
+def test_graph_replays_equal_eager_steps():
+    """Two captured steps replayed several times, with eager work and
+    synchronisations in between, equal the same steps run eagerly."""
+    specs, cents = zip(*[I.batch_instance(i) for i in range(6)])
+    gm = Mesh.batch([s.kwargs() for s in specs])
+    acts = [I.batch_state(sp, gm.keys[gm.first_leaf[i]:gm.first_leaf[i + 1]], c)
+            for i, (sp, c) in enumerate(zip(specs, cents))]
+    act = np.concatenate(acts)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        Ue = gm.state_from_active(act)
+        dte = gm.dt_tensor()
+        for k in range(6):
+            gm.step(Ue, dte, k)
+        ref = gm.active(Ue)
+        Ug = gm.state_from_active(act)
+        dtg = gm.dt_tensor()
+        side.synchronize()
+        g = gm.graph(Ug, dtg, first_step=0)
+        for rep in range(3):
+            g.launch()
+            junk = torch.ones(1000, device="cuda").sum()  # eager work between replays
+            side.synchronize()
+            assert float(junk) == 1000.0
+        got = gm.active(Ug)
+    assert np.array_equal(got, ref)

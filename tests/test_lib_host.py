@@ -216,3 +216,35 @@ def test_host_coarsening_decisions_match_oracle(seed):
         assert (st.refined, st.coarsened, st.refused) == tuple(int(v) for v in ost)
         L.amr_mesh_destroy(h2)
     L.amr_mesh_destroy(h)
+
+
+def test_batch_leaf_sets_equal_single_meshes():
+    L = _lib.lib()
+    specs = [I.batch_instance(i)[0] for i in range(12)]
+    descs = (_lib.MeshDesc * len(specs))()
+    keep = []
+    for i, sp in enumerate(specs):
+        d, k = _lib.make_desc(**sp.kwargs())
+        descs[i] = d
+        keep.append(k)
+    h = ctypes.c_void_p()
+    assert L.amr_batch_create(descs, len(specs), ctypes.byref(h)) == 0
+    info = _lib.MeshInfo()
+    L.amr_mesh_info(h, ctypes.byref(info))
+    assert info.n_instances == len(specs)
+    keys = np.zeros((info.n_leaves, 4), dtype=np.int32)
+    L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+    off = np.zeros(len(specs) + 1, dtype=np.int64)
+    assert L.amr_mesh_instance_offsets(h, off.ctypes.data_as(ctypes.c_void_p), off.size) == 0
+    for i, sp in enumerate(specs):
+        rc, inf1, k1 = host_mesh(**sp.kwargs())
+        assert rc == 0
+        assert np.array_equal(keys[off[i]:off[i + 1]], k1)  # same storage order too
+        om = O.OracleMesh(**sp.kwargs())
+        assert sorted(map(tuple, k1)) == sorted(map(tuple, om.keys))
+    L.amr_mesh_destroy(h)
+    # mixed block sizes are rejected
+    d2, k2 = _lib.make_desc(**dict(specs[1].kwargs(), block_cells=8))
+    descs[1] = d2
+    h = ctypes.c_void_p()
+    assert L.amr_batch_create(descs, 2, ctypes.byref(h)) == -1
