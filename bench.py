@@ -126,6 +126,75 @@ def batched_compare(steps: int, n_inst: int = 256):
     return out
 
 
+def adjoint_compare(steps: int = 10, reps: int = 3):
+    """The differentiation workload (4^3 root octrees of 32^3 cells, the
+    central 2^3 roots refined once: 120 leaves, 3.9M cells; density misfit
+    after `steps` steps): wall time of the plain forward, of the
+    checkpointing forward and of the hand-written adjoint, best of `reps`."""
+    import torch
+
+    from paper_1810_01319_amd import adjoint as A
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    spec = I.grf_spec(root=4, block_cells=32)
+    m = Mesh(**spec.kwargs())
+    N, g3 = spec.block_cells, 3
+    base = m.state_from_active(I.grf_state(spec, m.keys, seed=4))
+    target = torch.from_numpy(I.grf_density(spec, m.keys, seed=40)).to(m.device)
+
+    def plain():
+        U = base.clone()
+        for k in range(steps):
+            m.step(U, m.dt_tensor(), k)
+        return U
+
+    def timed(fn):
+        best = None
+        for _ in range(reps + 1):  # first call warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        return best, r
+
+    t_plain, _ = timed(plain)
+    state = {}
+
+    def fwd():
+        r = base[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N].clone().requires_grad_(True)
+        U = base.clone()
+        U[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N] = r
+        L = A.density_misfit(m, A.run_steps(U, m, steps), target)
+        state["L"], state["r"] = L, r
+        return L
+
+    def bwd():
+        state["L"].backward()
+        return state["r"].grad
+
+    best_f = best_b = None
+    for i in range(reps + 1):  # first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bwd()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if i > 0:
+            best_f = t1 - t0 if best_f is None else min(best_f, t1 - t0)
+            best_b = t2 - t1 if best_b is None else min(best_b, t2 - t1)
+    return {"workload": "grf-density-misfit: 4^3 root octrees x 32^3 cells, central 2^3 roots refined once "
+                        f"(120 leaves, 3.9M cells), {steps} steps, gamma 5/3, periodic",
+            "steps": steps, "forward_ms": t_plain * 1e3, "forward_checkpointing_ms": best_f * 1e3,
+            "adjoint_ms": best_b * 1e3, "adjoint_over_forward": best_b / t_plain,
+            "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain}
+
+
 def run_adaptive(args, spec, desc):
     """The large adaptive workload: remesh included in the timed region."""
     import torch
@@ -195,6 +264,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--batch-steps", type=int, default=20, help="steps of the batched comparison (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=10, help="steps of the adjoint comparison (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -283,6 +353,8 @@ def main():
     if args.batch_steps > 0:
         del U
         out["batched"] = batched_compare(args.batch_steps)
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_compare(args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -83,6 +83,7 @@ typedef struct {
   int64_t n_cf_faces;      /* coarse-fine block faces (both sides counted) */
   int32_t levels[8];       /* leaves per level */
   int64_t n_instances;     /* meshes in the handle (1 unless batched) */
+  int64_t adjoint_scratch_bytes; /* scratch of amr_hydro_step_adjoint */
 } amr_mesh_info_t;
 
 /* Build the balanced array-of-octrees: roots, then each refine entry in
@@ -154,6 +155,26 @@ amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64
                             amr_graph** out);
 amr_status amr_graph_launch(amr_graph* graph, void* stream);
 amr_status amr_graph_destroy(amr_graph* graph);
+
+/* Adjoint of one hydro step with its dt frozen (Sec. II-C Method, the
+ * refresh of Sec. II-B): on entry lam_dev holds dL/dU after the step (ghost
+ * entries zero), on exit dL/dU before it (ghost entries zero).  U_in_dev is
+ * the state the forward step started from (a checkpoint), dt_dev the dt it
+ * used, step_index its index (sweep order).  The step's sweep inputs are
+ * recomputed into scratch_dev (adjoint_scratch_bytes of amr_mesh_info); every
+ * limiter, flattening, wave-direction, floor and Riemann branch is taken as
+ * the forward took it, and the result is the exact vector-Jacobian product of
+ * the computed step on those branches.  The refresh transpose scatter-adds
+ * with FP64 atomics (sums in unspecified order).  Post-update floors are
+ * assumed inactive. */
+amr_status amr_hydro_step_adjoint(amr_mesh* mesh, const double* U_in_dev, const double* dt_dev, double* lam_dev,
+                                  void* scratch_dev, int64_t step_index, void* stream);
+
+/* Transpose of amr_refresh_ghosts at the refreshed state U_ref_dev (its
+ * minmod slope choices): on entry lam_dev holds an adjoint on every cell,
+ * ghosts included; on exit the ghost entries are folded into their source
+ * cells and cleared. */
+amr_status amr_refresh_ghosts_adjoint(amr_mesh* mesh, const double* U_ref_dev, double* lam_dev, void* stream);
 
 /* Number of post-update floor resets since upload (synchronises the
  * stream). */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libamr.so")
-SOURCES = ["kernels.hip", "mesh.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "mesh.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
@@ -30,6 +30,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+CORE_SO = os.path.join(HERE, "libamr_core_host.so")
+
+
+def build_core_host() -> str:
+    """Host build of the sweep formulas and their adjoint, for the CPU unit
+    tests of the adjoint (g++, no FMA contraction)."""
+    tmp = CORE_SO + ".tmp"
+    r = subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+                        "-o", tmp, os.path.join(SRC, "core_host.cpp")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed on core_host.cpp:\n" + r.stderr)
+    os.replace(tmp, CORE_SO)
+    return CORE_SO
+
+
 def build(force: bool = True) -> str:
     if not force and os.path.exists(SO):
         return SO
@@ -42,6 +57,7 @@ def build(force: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, SO)
+    build_core_host()
     return SO
 
 

@@ -53,6 +53,7 @@ class MeshInfo(ctypes.Structure):
         ("n_cf_faces", ctypes.c_int64),
         ("levels", ctypes.c_int32 * 8),
         ("n_instances", ctypes.c_int64),
+        ("adjoint_scratch_bytes", ctypes.c_int64),
     ]
 
 
@@ -93,6 +94,8 @@ SIGNATURES = {
     "amr_cfl_dt": (_I32, [_P, _P, _P, _P]),
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
+    "amr_hydro_step_adjoint": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
+    "amr_refresh_ghosts_adjoint": (_I32, [_P, _P, _P, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "amr_remesh_plan": (_I32, [_P, _P, ctypes.POINTER(RemeshParams), ctypes.POINTER(_P),
                                ctypes.POINTER(RemeshStats), _P]),

@@ -1,0 +1,317 @@
+// adjoint.hip -- kernels of the hand-written adjoint of one hydro step:
+// transposes of reflux, of the three sweeps (recomputed from their stored
+// inputs, branches taken from the forward) and of the ghost refresh.
+//
+// The adjoint of the step U_out = Reflux(Sweep3(Sweep2(Sweep1(Refresh(U_in)))))
+// with dt frozen is applied to lam in place: lam enters as dL/dU_out and
+// leaves as dL/dU_in.  Ghost entries of lam are zero on entry and on exit
+// (ghost values of a state are overwritten by the next refresh).
+#include <hip/hip_runtime.h>
+
+#include "adjoint.hpp"
+#include "ghost.hpp"
+#include "ppm_adjoint.hpp"
+
+namespace amr {
+namespace {
+
+constexpr int G = kGhost;
+
+__device__ __forceinline__ double level_dx_a(const InstParams& ip, int N, int l) {
+  return 1.0 / (double)((int64_t)ip.root[0] * N << l);
+}
+
+__global__ void fill_zero(double* __restrict__ p, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0.0;
+}
+
+// Reflux transpose: each coarse face cell's correction
+// U_c += s nu_c (F_c - ((F00 + F10) + (F01 + F11)) / 4) sends s nu_c lam_c to
+// the coarse face flux and -s nu_c lam_c / 4 to each of its four fine fluxes.
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__ lam, const double* __restrict__ dtv,
+                                                      DevPlan P, double* __restrict__ gfaces) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nreflux[DIR] * N * N) return;
+  const int k = int(t / (N * N));
+  const int r = int(t - int64_t(k) * N * N);
+  const int tA = r % N, tB = r / N;
+  const RefluxTask T = P.reflux[DIR][k];
+  const BlockInfo bi = P.blocks[T.leaf];
+  const InstParams& ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
+  const int hA = tA >= N / 2, hB = tB >= N / 2;
+  const int fs = T.slot_f[hA + 2 * hB];
+  const int fA = 2 * tA - hA * N, fB = 2 * tB - hB * N;
+  const int d = T.side ? N + G - 1 : G;
+  const double* cellp = lam + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + tA) * SA +
+                        int64_t(G + tB) * SB;
+  const double s = T.side ? 1.0 : -1.0;
+#pragma unroll
+  for (int f = 0; f < kFields; f++) {
+    const double g = s * nu * cellp[f * M3];
+    gfaces[(int64_t(T.slot_c) * kFields + f) * N * N + int64_t(tB) * N + tA] = g;
+    double* Q = gfaces + (int64_t(fs) * kFields + f) * N * N;
+    const double gf = -0.25 * g;
+    Q[fB * N + fA] = gf;
+    Q[fB * N + fA + 1] = gf;
+    Q[(fB + 1) * N + fA] = gf;
+    Q[(fB + 1) * N + fA + 1] = gf;
+  }
+}
+
+// Sweep transpose: one lane per pencil recomputes the pencil's forward from
+// the sweep's input Uin and applies the pencil's vector-Jacobian product to
+// lam in place.
+template <int N, int DIR>
+__global__ void __launch_bounds__(64) sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam,
+                                                    const double* __restrict__ dtv, DevPlan P,
+                                                    const double* __restrict__ gfaces, int loA, int nA, int loB,
+                                                    int nB) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  const int64_t npen = int64_t(nA) * nB;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * npen) return;
+  const int s = int(t / npen);
+  const int pp = int(t - int64_t(s) * npen);
+  const int iA = loA + pp % nA, iB = loB + pp / nA;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
+  const int64_t base = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
+  const int fmap[5] = {0, 1 + DIR, 1 + T1, 1 + T2, 4};
+  double u[5 * M], l[5 * M];
+  for (int v = 0; v < 5; v++)
+    for (int c = 0; c < M; c++) {
+      u[v * M + c] = Uin[base + fmap[v] * M3 + int64_t(c) * SD];
+      l[v * M + c] = lam[base + fmap[v] * M3 + int64_t(c) * SD];
+    }
+  double glo[5], ghi[5];
+  const double* plo = nullptr;
+  const double* phi = nullptr;
+  if (iA >= G && iA < G + N && iB >= G && iB < G + N) {
+    const int64_t off = int64_t(iB - G) * N + (iA - G);
+    const int sl = P.faceslot[6 * int64_t(s) + 2 * DIR], sh = P.faceslot[6 * int64_t(s) + 2 * DIR + 1];
+    if (sl >= 0) {
+      for (int v = 0; v < 5; v++) glo[v] = gfaces[(int64_t(sl) * kFields + fmap[v]) * N * N + off];
+      plo = glo;
+    }
+    if (sh >= 0) {
+      for (int v = 0; v < 5; v++) ghi[v] = gfaces[(int64_t(sh) * kFields + fmap[v]) * N * N + off];
+      phi = ghi;
+    }
+  }
+  pencil_vjp(ip, nu, M, G, G + N, u, l, plo, phi);
+  for (int v = 0; v < 5; v++)
+    for (int c = 0; c < M; c++) lam[base + fmap[v] * M3 + int64_t(c) * SD] = l[v * M + c];
+}
+
+// Refresh transpose, phase 2 (prolongation): a prolonged ghost's adjoint
+// goes to the coarse parent cell and, through the frozen minmod slopes, to
+// its face neighbours; then the ghost entry is cleared.
+template <int N>
+__global__ void __launch_bounds__(256) refresh2_adjoint(double* __restrict__ lam, const double* __restrict__ Uref,
+                                                        DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int GC = M * M * M - N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.np2 * GC) return;
+  const int w = int(t / GC);
+  const int g = int(t - int64_t(w) * GC);
+  const int s = P.p2list[w];
+  int a, b, c;
+  ghost_decode<N>(g, a, b, c);
+  const Nbr e = P.nbr[27 * int64_t(s) + dir_code<N>(a, b, c)];
+  if (e.kind != NBR_COARSE) return;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const int l = bi.level;
+  const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
+  const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
+  const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
+  const BlockInfo cb = P.blocks[e.id];
+  const int la = (px >> 1) - cb.i * N + G, lb = (py >> 1) - cb.j * N + G, lc = (pz >> 1) - cb.k * N + G;
+  const double o[3] = {(px & 1) ? 0.25 : -0.25, (py & 1) ? 0.25 : -0.25, (pz & 1) ? 0.25 : -0.25};
+  const int64_t cbase = int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+  const int64_t gidx = int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  const int st[3] = {1, M, M * M};
+#pragma unroll
+  for (int f = 0; f < kFields; f++) {
+    double* lg = lam + gidx + f * M3;
+    const double gv = *lg;
+    *lg = 0.0;
+    if (gv == 0.0) continue;
+    const double* q = Uref + cbase + f * M3;
+    const double u0 = q[0];
+    double g0 = gv;
+    for (int d = 0; d < 3; d++) {
+      // s_d = minmod(q[+1] - u0, u0 - q[-1]); the branch the forward took
+      const double aa = q[st[d]] - u0, bb = u0 - q[-st[d]];
+      if (!(aa * bb > 0.0)) continue;
+      const double gs = o[d] * gv;
+      if (fabs(aa) < fabs(bb)) {
+        atomicAdd(lam + cbase + f * M3 + st[d], gs);
+        g0 -= gs;
+      } else {
+        g0 += gs;
+        atomicAdd(lam + cbase + f * M3 - st[d], -gs);
+      }
+    }
+    atomicAdd(lam + cbase + f * M3, g0);
+  }
+}
+
+// Refresh transpose, phase 1 (copies and restriction): a ghost's adjoint goes
+// to its source cell (weight 1) or to its 8 children (weight 1/8); then the
+// ghost entry is cleared.
+template <int N>
+__global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam, DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int GC = M * M * M - N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * GC) return;
+  const int s = int(t / GC);
+  const int g = int(t - int64_t(s) * GC);
+  int a, b, c;
+  ghost_decode<N>(g, a, b, c);
+  const Nbr e = P.nbr[27 * int64_t(s) + dir_code<N>(a, b, c)];
+  if (e.kind == NBR_COARSE) return;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams& ip = P.inst[bi.inst];
+  const int l = bi.level;
+  const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
+  const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
+  const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
+  double* dst = lam + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  if (e.kind == NBR_COPY) {
+    const BlockInfo sb = P.blocks[e.id];
+    const int la = px - sb.i * N + G, lb = py - sb.j * N + G, lc = pz - sb.k * N + G;
+    double* src = lam + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) {
+      const double gv = dst[f * M3];
+      dst[f * M3] = 0.0;
+      if (gv != 0.0) atomicAdd(src + f * M3, gv);
+    }
+  } else {
+    const int qx = 2 * px, qy = 2 * py, qz = 2 * pz;
+    const int cidx = ((qx / N) & 1) + 2 * ((qy / N) & 1) + 4 * ((qz / N) & 1);
+    const int fs = P.fine[8 * int64_t(e.id) + cidx];
+    const int la = qx % N + G, lb = qy % N + G, lc = qz % N + G;
+    double* src = lam + int64_t(fs) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+#pragma unroll
+    for (int f = 0; f < kFields; f++) {
+      const double gv = dst[f * M3];
+      dst[f * M3] = 0.0;
+      if (gv == 0.0) continue;
+      const double g8 = gv * 0.125;
+      double* q = src + f * M3;
+      atomicAdd(q, g8);
+      atomicAdd(q + 1, g8);
+      atomicAdd(q + M, g8);
+      atomicAdd(q + M + 1, g8);
+      atomicAdd(q + M * M, g8);
+      atomicAdd(q + M * M + 1, g8);
+      atomicAdd(q + M * M + M, g8);
+      atomicAdd(q + M * M + M + 1, g8);
+    }
+  }
+}
+
+inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+template <int N>
+hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
+                       int dir, const int swept[3], hipStream_t st) {
+  constexpr int M = N + 2 * G;
+  const int A = dir == 0 ? 1 : 0, B = dir == 2 ? 1 : 2;
+  const int loA = swept[A] ? G : 0, nA = swept[A] ? N : M;
+  const int loB = swept[B] ? G : 0, nB = swept[B] ? N : M;
+  const int64_t n = P.nleaf * int64_t(nA) * nB;
+  if (n == 0) return hipSuccess;
+  const dim3 g(gridn(n, 64)), b(64);
+  if (dir == 0) hipLaunchKernelGGL((sweep_adjoint<N, 0>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
+  else if (dir == 1) hipLaunchKernelGGL((sweep_adjoint<N, 1>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
+  else hipLaunchKernelGGL((sweep_adjoint<N, 2>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t reflux_adj_n(const DevPlan& P, const double* lam, const double* dt, double* gfaces, hipStream_t st) {
+  for (int d = 0; d < 3; d++) {
+    const int64_t n = P.nreflux[d] * N * N;
+    if (n == 0) continue;
+    const dim3 g(gridn(n, 256)), b(256);
+    if (d == 0) hipLaunchKernelGGL((reflux_adjoint<N, 0>), g, b, 0, st, lam, dt, P, gfaces);
+    else if (d == 1) hipLaunchKernelGGL((reflux_adjoint<N, 1>), g, b, 0, st, lam, dt, P, gfaces);
+    else hipLaunchKernelGGL((reflux_adjoint<N, 2>), g, b, 0, st, lam, dt, P, gfaces);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t refresh_adj_n(const DevPlan& P, double* lam, const double* Uref, hipStream_t st) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
+  if (P.np2 > 0)
+    hipLaunchKernelGGL(refresh2_adjoint<N>, dim3(gridn(P.np2 * GC, 256)), dim3(256), 0, st, lam, Uref, P);
+  if (P.nleaf > 0)
+    hipLaunchKernelGGL(refresh1_adjoint<N>, dim3(gridn(P.nleaf * GC, 256)), dim3(256), 0, st, lam, P);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero, dim3(gridn(n, 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const double* dt, double* gfaces,
+                                 hipStream_t st) {
+  switch (P.N) {
+    case 8: return reflux_adj_n<8>(P, lam, dt, gfaces, st);
+    case 16: return reflux_adj_n<16>(P, lam, dt, gfaces, st);
+    case 32: return reflux_adj_n<32>(P, lam, dt, gfaces, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep_adjoint(const DevPlan& P, const double* Uin, double* lam, const double* dt,
+                                const double* gfaces, int dir, const int swept[3], hipStream_t st) {
+  switch (P.N) {
+    case 8: return sweep_adj_n<8>(P, Uin, lam, dt, gfaces, dir, swept, st);
+    case 16: return sweep_adj_n<16>(P, Uin, lam, dt, gfaces, dir, swept, st);
+    case 32: return sweep_adj_n<32>(P, Uin, lam, dt, gfaces, dir, swept, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_refresh_adjoint(const DevPlan& P, double* lam, const double* Uref, hipStream_t st) {
+  switch (P.N) {
+    case 8: return refresh_adj_n<8>(P, lam, Uref, st);
+    case 16: return refresh_adj_n<16>(P, lam, Uref, st);
+    case 32: return refresh_adj_n<32>(P, lam, Uref, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace amr

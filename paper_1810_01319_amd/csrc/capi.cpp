@@ -6,6 +6,7 @@
 #include <string>
 
 #include "../../include/amr.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
 
@@ -113,6 +114,12 @@ amr_status finish(amr_mesh* h, amr_mesh** out) {
   }
   *out = h;
   return AMR_OK;
+}
+
+int64_t adjoint_scratch(const Plan& p) {
+  const int64_t field = p.nleaf * kFields * int64_t(p.M) * p.M * p.M * 8;
+  const int64_t faces = p.nslots * kFields * int64_t(p.N) * p.N * 8;
+  return 3 * field + faces;
 }
 
 DevPlan dev_plan(const amr_mesh* h) {
@@ -306,6 +313,7 @@ amr_status amr_mesh_info(const amr_mesh* h, amr_mesh_info_t* out) {
   out->workspace_bytes = p.off.total;
   out->n_cf_faces = p.nslots;
   out->n_instances = int64_t(p.inst.size());
+  out->adjoint_scratch_bytes = adjoint_scratch(p);
   for (const Key& k : p.keys)
     if (k.l < 8) out->levels[k.l]++;
   return AMR_OK;
@@ -362,6 +370,53 @@ amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t s
   if (rc != AMR_OK) return rc;
   if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* dt, double* lam, void* scratch,
+                                  int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, Uin);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Plan& p = h->plan;
+  const int64_t nfield = p.nleaf * kFields * int64_t(p.M) * p.M * p.M;
+  double* S[3];
+  for (int i = 0; i < 3; i++) S[i] = static_cast<double*>(scratch) + i * nfield;
+  double* gfaces = static_cast<double*>(scratch) + 3 * nfield;
+  const DevPlan P = dev_plan(h);
+  int order[3] = {0, 1, 2};
+  if (step_index & 1) {
+    order[0] = 2;
+    order[2] = 0;
+  }
+  // recompute the inputs of the three sweeps
+  hipError_t e = hipMemcpyAsync(S[0], Uin, size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = launch_refresh(P, S[0], h->cfg, st);
+  int swept[3] = {0, 0, 0};
+  for (int k = 0; k < 2 && e == hipSuccess; k++) {
+    e = hipMemcpyAsync(S[k + 1], S[k], size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_sweep(P, S[k + 1], dt, order[k], swept, h->cfg, st);
+    swept[order[k]] = 1;
+  }
+  if (e != hipSuccess) return hip_fail(e, "adjoint recompute");
+  // transposes in reverse order
+  e = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
+  if (e == hipSuccess) e = launch_reflux_adjoint(P, lam, dt, gfaces, st);
+  for (int k = 2; k >= 0 && e == hipSuccess; k--) {
+    int sw[3] = {0, 0, 0};
+    for (int q = 0; q < k; q++) sw[order[q]] = 1;
+    e = launch_sweep_adjoint(P, S[k], lam, dt, gfaces, order[k], sw, st);
+  }
+  if (e == hipSuccess) e = launch_refresh_adjoint(P, lam, S[0], st);
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
+}
+
+amr_status amr_refresh_ghosts_adjoint(amr_mesh* h, const double* Uref, double* lam, void* stream) {
+  amr_status rc = check_ready(h, Uref);
+  if (rc != AMR_OK) return rc;
+  if (!lam) return fail(AMR_E_INVALID, "null adjoint");
+  hipError_t e = launch_refresh_adjoint(dev_plan(h), lam, Uref, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "refresh adjoint");
 }
 
 amr_status amr_floor_count(amr_mesh* h, int64_t* out, void* stream) {

@@ -1,0 +1,550 @@
+// ppm_adjoint.hpp -- vector-Jacobian products of the PPM sweep's formulas
+// (ppm_core.hpp), for the hand-written adjoint of a hydro step.
+//
+// Every discrete branch (slope limiter choice, monotonicity case, flattening
+// switch and clamps, wave-direction gates, floors, Riemann side / shock /
+// fan) is re-evaluated from the same inputs as the forward and held fixed:
+// each function is the exact derivative of the formula on the branch the
+// forward took.  The time step is a constant.
+#pragma once
+#include "ppm_core.hpp"
+
+namespace amr {
+
+// ---- primitives ----------------------------------------------------------
+
+struct Prim {
+  double q[5];  // rho, u, v, w, p (floored)
+  double c, ir, K;
+  bool pfl;     // pressure floor active
+};
+
+AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
+  Prim P;
+  P.ir = 1.0 / U[0];
+  P.q[0] = U[0];
+  P.q[1] = U[1] * P.ir;
+  P.q[2] = U[2] * P.ir;
+  P.q[3] = U[3] * P.ir;
+  P.K = (P.q[1] * P.q[1] + P.q[2] * P.q[2]) + P.q[3] * P.q[3];
+  const double p = ip.gm1 * (U[4] - (0.5 * U[0]) * P.K);
+  P.pfl = p < ip.p_floor;
+  P.q[4] = P.pfl ? ip.p_floor : p;
+  P.c = sqrt((ip.gamma * P.q[4]) * P.ir);
+  return P;
+}
+
+// g_q[5], g_c, g_ir -> g_U[5] (accumulated)
+AMR_HD inline void prim_vjp(const InstParams& ip, const double* U, const Prim& P, const double* gq, double gc,
+                            double gir, double* gU) {
+  double gp = gq[4] + gc * ((ip.gamma * P.ir) / (2.0 * P.c));
+  gir += gc * ((ip.gamma * P.q[4]) / (2.0 * P.c));
+  if (P.pfl) gp = 0.0;
+  const double gpm = gp * ip.gm1;
+  gU[4] += gpm;
+  const double gK = -gpm * (0.5 * U[0]);
+  double g0 = gq[0] - gpm * (0.5 * P.K);
+  const double gu = gq[1] + gK * (2.0 * P.q[1]);
+  const double gv = gq[2] + gK * (2.0 * P.q[2]);
+  const double gw = gq[3] + gK * (2.0 * P.q[3]);
+  gU[1] += gu * P.ir;
+  gU[2] += gv * P.ir;
+  gU[3] += gw * P.ir;
+  gir += gu * U[1] + gv * U[2] + gw * U[3];
+  g0 -= gir * (P.ir * P.ir);
+  gU[0] += g0;
+}
+
+// ---- MC slope ------------------------------------------------------------
+
+AMR_HD inline void slope_vjp(double qm, double q0, double qp, double g, double* gm, double* g0, double* gp) {
+  const double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
+  if (!(dl * dr > 0.0)) return;
+  const double adc = fabs(dc), a2l = 2.0 * fabs(dl), a2r = 2.0 * fabs(dr);
+  const double sg = dc > 0.0 ? 1.0 : -1.0;
+  // which term the selects min(min(|dc|, 2|dl|), 2|dr|) returned
+  const double m1 = adc < a2l ? adc : a2l;
+  if (!(m1 < a2r)) {  // 2|dr|
+    const double d = sg * 2.0 * (dr > 0.0 ? 1.0 : -1.0) * g;
+    *gp += d;
+    *g0 -= d;
+  } else if (adc < a2l) {  // |dc|
+    const double d = sg * (dc > 0.0 ? 1.0 : -1.0) * 0.5 * g;
+    *gp += d;
+    *gm -= d;
+  } else {  // 2|dl|
+    const double d = sg * 2.0 * (dl > 0.0 ? 1.0 : -1.0) * g;
+    *g0 += d;
+    *gm -= d;
+  }
+}
+
+// ---- parabola ------------------------------------------------------------
+
+struct ParGrad {
+  double qL, qR, dq, q6;
+};
+
+// gradients of the final (qL, qR, dq, q6) -> g of the cell value, of the
+// incoming face values and of the flattening coefficient (accumulated)
+AMR_HD inline void parabola_vjp(double q, double qLi, double qRi, double f, double sixth, const ParGrad& G,
+                                double* gq, double* gqLi, double* gqRi, double* gf) {
+  const double qL1 = f * q + (1.0 - f) * qLi;
+  const double qR1 = f * q + (1.0 - f) * qRi;
+  double gqL = G.qL - G.dq - 3.0 * G.q6;
+  double gqR = G.qR + G.dq - 3.0 * G.q6;
+  double g_q = 6.0 * G.q6;
+  double gqL1 = 0.0, gqR1 = 0.0;
+  if ((qR1 - q) * (q - qL1) <= 0.0) {
+    g_q += gqL + gqR;
+  } else {
+    const double D = qR1 - qL1, mm = q - 0.5 * (qL1 + qR1);
+    const double D26 = (D * D) * sixth;
+    if (D * mm > D26) {
+      g_q += 3.0 * gqL;
+      gqR1 += gqR - 2.0 * gqL;
+    } else if (-D26 > D * mm) {
+      g_q += 3.0 * gqR;
+      gqL1 += gqL - 2.0 * gqR;
+    } else {
+      gqL1 += gqL;
+      gqR1 += gqR;
+    }
+  }
+  g_q += f * (gqL1 + gqR1);
+  *gqLi += (1.0 - f) * gqL1;
+  *gqRi += (1.0 - f) * gqR1;
+  *gf += gqL1 * (q - qLi) + gqR1 * (q - qRi);
+  *gq += g_q;
+}
+
+// ---- parabola means ------------------------------------------------------
+
+// Ip(s) = qR - (0.5 s)(dq - (1 - t s) q6)
+AMR_HD inline void Ip_vjp(const Par& P, double s, double two3, double g, ParGrad* G, double* gs) {
+  G->qR += g;
+  G->dq += -(0.5 * s) * g;
+  G->q6 += (0.5 * s) * (1.0 - two3 * s) * g;
+  *gs += (-0.5 * P.dq + 0.5 * P.q6 - two3 * s * P.q6) * g;
+}
+// Im(s) = qL + (0.5 s)(dq + (1 - t s) q6)
+AMR_HD inline void Im_vjp(const Par& P, double s, double two3, double g, ParGrad* G, double* gs) {
+  G->qL += g;
+  G->dq += (0.5 * s) * g;
+  G->q6 += (0.5 * s) * (1.0 - two3 * s) * g;
+  *gs += (0.5 * P.dq + 0.5 * P.q6 - two3 * s * P.q6) * g;
+}
+
+// ---- characteristic tracing ----------------------------------------------
+
+// gWL (left state at j+1/2), gWR (right state at j-1/2) -> gradients of the
+// 5 parabolas and of rho, u, c, 1/rho of the cell (accumulated)
+AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double c, double ir, const Par* pa, double nu,
+                             const double* gWL, const double* gWR, ParGrad* G, double* grho, double* gu, double* gc,
+                             double* gir) {
+  const double t = ip.two3;
+  const double lm = u - c, l0 = u, lp = u + c;
+  const double ic = 1.0 / c;
+  const double Ac = (0.5 * rho) * ic;
+  const double Bc = ir * ic;
+  const double cc = c * c;
+  const double ic2 = ic * ic;
+  const double cor = c * ir;
+  double gAc = 0, gBc = 0, gcc = 0, gic2 = 0, gcor = 0, glm = 0, gl0 = 0, glp = 0;
+  // ---- right edge (left state at j+1/2) ----
+  {
+    const double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
+    const double rr = Ip(pa[0], sp, t), ur = Ip(pa[1], sp, t), pr = Ip(pa[4], sp, t);
+    const double Ipm = Ip(pa[4], sm, t), Ium = Ip(pa[1], sm, t);
+    const double Ir0 = Ip(pa[0], s0, t), Ip0 = Ip(pa[4], s0, t);
+    const double X = pr - Ipm, Y = ur - Ium;
+    const double am = (lm > 0.0) ? Ac * (X * Bc - Y) : 0.0;
+    const double a0 = (l0 > 0.0) ? (rr - Ir0) - (pr - Ip0) * ic2 : 0.0;
+    const double r = (rr - am) - a0;
+    const double p = pr - cc * am;
+    const double g0 = r < ip.rho_floor ? 0.0 : gWL[0];
+    const double g4 = p < ip.p_floor ? 0.0 : gWL[4];
+    double grr = g0, gur = gWL[1], gpr = g4;
+    double gam = -g0 + cor * gWL[1] - cc * g4;
+    const double ga0 = -g0;
+    gcor += gWL[1] * am;
+    gcc += -g4 * am;
+    double gsm = 0, gs0 = 0, gsp = 0;
+    Ip_vjp(pa[2], s0, t, gWL[2], &G[2], &gs0);
+    Ip_vjp(pa[3], s0, t, gWL[3], &G[3], &gs0);
+    if (l0 > 0.0) {
+      grr += ga0;
+      Ip_vjp(pa[0], s0, t, -ga0, &G[0], &gs0);
+      gpr -= ga0 * ic2;
+      Ip_vjp(pa[4], s0, t, ga0 * ic2, &G[4], &gs0);
+      gic2 -= ga0 * (pr - Ip0);
+    }
+    if (lm > 0.0) {
+      gAc += gam * (X * Bc - Y);
+      const double gX = gam * Ac * Bc, gY = -gam * Ac;
+      gBc += gam * Ac * X;
+      gpr += gX;
+      Ip_vjp(pa[4], sm, t, -gX, &G[4], &gsm);
+      gur += gY;
+      Ip_vjp(pa[1], sm, t, -gY, &G[1], &gsm);
+    }
+    Ip_vjp(pa[0], sp, t, grr, &G[0], &gsp);
+    Ip_vjp(pa[1], sp, t, gur, &G[1], &gsp);
+    Ip_vjp(pa[4], sp, t, gpr, &G[4], &gsp);
+    if (lm > 0.0) glm += nu * gsm;
+    if (l0 > 0.0) gl0 += nu * gs0;
+    if (lp > 0.0) glp += nu * gsp;
+  }
+  // ---- left edge (right state at j-1/2) ----
+  {
+    const double sm = (lm < 0.0 ? -lm : 0.0) * nu, s0 = (l0 < 0.0 ? -l0 : 0.0) * nu, sp = (lp < 0.0 ? -lp : 0.0) * nu;
+    const double rr = Im(pa[0], sm, t), ur = Im(pa[1], sm, t), pr = Im(pa[4], sm, t);
+    const double Imp = Im(pa[4], sp, t), Imu = Im(pa[1], sp, t);
+    const double Ir0 = Im(pa[0], s0, t), Ip0 = Im(pa[4], s0, t);
+    const double X = pr - Imp, Y = ur - Imu;
+    const double ap = (lp < 0.0) ? Ac * (X * Bc + Y) : 0.0;
+    const double a0 = (l0 < 0.0) ? (rr - Ir0) - (pr - Ip0) * ic2 : 0.0;
+    const double r = (rr - ap) - a0;
+    const double p = pr - cc * ap;
+    const double g0 = r < ip.rho_floor ? 0.0 : gWR[0];
+    const double g4 = p < ip.p_floor ? 0.0 : gWR[4];
+    double grr = g0, gur = gWR[1], gpr = g4;
+    const double gap = -g0 - cor * gWR[1] - cc * g4;
+    const double ga0 = -g0;
+    gcor += -gWR[1] * ap;
+    gcc += -g4 * ap;
+    double gsm = 0, gs0 = 0, gsp = 0;
+    Im_vjp(pa[2], s0, t, gWR[2], &G[2], &gs0);
+    Im_vjp(pa[3], s0, t, gWR[3], &G[3], &gs0);
+    if (l0 < 0.0) {
+      grr += ga0;
+      Im_vjp(pa[0], s0, t, -ga0, &G[0], &gs0);
+      gpr -= ga0 * ic2;
+      Im_vjp(pa[4], s0, t, ga0 * ic2, &G[4], &gs0);
+      gic2 -= ga0 * (pr - Ip0);
+    }
+    if (lp < 0.0) {
+      gAc += gap * (X * Bc + Y);
+      const double gX = gap * Ac * Bc, gY = gap * Ac;
+      gBc += gap * Ac * X;
+      gpr += gX;
+      Im_vjp(pa[4], sp, t, -gX, &G[4], &gsp);
+      gur += gY;
+      Im_vjp(pa[1], sp, t, -gY, &G[1], &gsp);
+    }
+    Im_vjp(pa[0], sm, t, grr, &G[0], &gsm);
+    Im_vjp(pa[1], sm, t, gur, &G[1], &gsm);
+    Im_vjp(pa[4], sm, t, gpr, &G[4], &gsm);
+    if (lm < 0.0) glm -= nu * gsm;
+    if (l0 < 0.0) gl0 -= nu * gs0;
+    if (lp < 0.0) glp -= nu * gsp;
+  }
+  // ---- common quantities ----
+  double gic = gAc * (0.5 * rho) + gBc * ir + gic2 * (2.0 * ic);
+  *grho += gAc * (0.5 * ic);
+  *gir += gBc * ic + gcor * c;
+  double g_c = gcc * (2.0 * c) + gcor * ir - gic * (ic * ic);
+  *gu += glm + gl0 + glp;
+  g_c += -glm + glp;
+  *gc += g_c;
+}
+
+// ---- two-shock Riemann solver -------------------------------------------
+
+// gF (flux) -> gL, gR (edge states rho,u,v,w,p; accumulated)
+AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
+                               double* gR) {
+  const double rL = L[0], uL = L[1], pL = L[4];
+  const double rR = R[0], uR = R[1], pR = R[4];
+  const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
+  const int NI = ip.iters;
+  // ---- forward, keeping p* of every Newton step ----
+  const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
+  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
+  const double num0 = (CR * pL + CL * pR) - (CL * CR) * (uR - uL);
+  const double den0 = CL + CR;
+  double ps = num0 / den0;
+  const bool fl0 = ps < pfl;
+  ps = fl0 ? pfl : ps;
+  double psv[65];
+  bool flv[65];
+  double WLw = 0, WRw = 0, iWL = 0, iWR = 0, iZL = 0, iZR = 0, usL = 0, usR = 0;
+  for (int it = 0;; it++) {
+    psv[it] = ps;
+    WLw = CL * sqrt(1.0 + g1 * (ps * ipL - 1.0));
+    WRw = CR * sqrt(1.0 + g1 * (ps * ipR - 1.0));
+    iWL = 1.0 / WLw;
+    iWR = 1.0 / WRw;
+    usL = uL - (ps - pL) * iWL;
+    usR = uR + (ps - pR) * iWR;
+    const double qL = CL * iWL, qR = CR * iWR;
+    iZL = (0.5 * iWL) * (1.0 + qL * qL);
+    iZR = (0.5 * iWR) * (1.0 + qR * qR);
+    if (it == NI) break;
+    ps = ps - (usR - usL) / (iZL + iZR);
+    flv[it] = ps < pfl;
+    ps = flv[it] ? pfl : ps;
+  }
+  const double Dz = iZL + iZR;
+  const double us = (iZR * usL + iZL * usR) / Dz;
+  const bool left = us >= 0.0;
+  const double s = left ? 1.0 : -1.0;
+  const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
+  const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
+  const double irK = 1.0 / rK;
+  const double vs = irK - (ps - pK) * (iWK * iWK);
+  const double rs = 1.0 / vs;
+  // sampled state and its case: 0 = side state, 1 = star, 2 = fan
+  int cse;
+  double xi = 0, lh = 0, lt = 0, cK = 0, csr = 0;
+  if (ps > pK) {
+    const double S = uK - s * (WK * irK);
+    cse = (s * S >= 0.0) ? 0 : 1;
+  } else {
+    cK = sqrt((gam * pK) * irK);
+    csr = sqrt((gam * ps) * vs);
+    lh = uK - s * cK;
+    lt = us - s * csr;
+    if (s * lh >= 0.0) cse = 0;
+    else if (s * lt <= 0.0) cse = 1;
+    else {
+      cse = 2;
+      xi = lh / (lh - lt);
+    }
+  }
+  double rg, ug, pg;
+  if (cse == 0) { rg = rK; ug = uK; pg = pK; }
+  else if (cse == 1) { rg = rs; ug = us; pg = ps; }
+  else { rg = rK + xi * (rs - rK); ug = uK + xi * (us - uK); pg = pK + xi * (ps - pK); }
+  const double vg = left ? L[2] : R[2], wg = left ? L[3] : R[3];
+  const double mf = rg * ug;
+  const double K2 = (ug * ug + vg * vg) + wg * wg;
+  const double H = pg * ip.g_gm1 + (0.5 * rg) * K2;
+  // ---- reverse: flux ----
+  const double gmf = gF[0] + gF[1] * ug + gF[2] * vg + gF[3] * wg;
+  double gug = gF[1] * mf + gF[4] * H;
+  const double gH = gF[4] * ug;
+  double gpg = gF[1] + gH * ip.g_gm1;
+  double grg = gH * (0.5 * K2);
+  const double gK2 = gH * (0.5 * rg);
+  gug += gK2 * (2.0 * ug);
+  const double gvg = gF[2] * mf + gK2 * (2.0 * vg);
+  const double gwg = gF[3] * mf + gK2 * (2.0 * wg);
+  grg += gmf * ug;
+  gug += gmf * rg;
+  if (left) { gL[2] += gvg; gL[3] += gwg; }
+  else { gR[2] += gvg; gR[3] += gwg; }
+  // ---- reverse: sampling ----
+  double grK = 0, guK = 0, gpK = 0, grs = 0, gus = 0, gps = 0, gvs = 0, girK = 0, gWK = 0, giWK = 0;
+  if (cse == 0) { grK += grg; guK += gug; gpK += gpg; }
+  else if (cse == 1) { grs += grg; gus += gug; gps += gpg; }
+  else {
+    grK += grg * (1.0 - xi); grs += grg * xi;
+    guK += gug * (1.0 - xi); gus += gug * xi;
+    gpK += gpg * (1.0 - xi); gps += gpg * xi;
+    const double gxi = grg * (rs - rK) + gug * (us - uK) + gpg * (ps - pK);
+    const double d = lh - lt;
+    const double glh = gxi * (-lt) / (d * d), glt = gxi * lh / (d * d);
+    guK += glh;
+    const double gcK = -s * glh;
+    gus += glt;
+    const double gcs = -s * glt;
+    gpK += gcK * ((gam * irK) / (2.0 * cK));
+    girK += gcK * ((gam * pK) / (2.0 * cK));
+    gps += gcs * ((gam * vs) / (2.0 * csr));
+    gvs += gcs * ((gam * ps) / (2.0 * csr));
+  }
+  (void)gWK;
+  gvs += -grs * (rs * rs);
+  girK += gvs;
+  gps += -gvs * (iWK * iWK);
+  gpK += gvs * (iWK * iWK);
+  giWK += -gvs * (ps - pK) * (2.0 * iWK);
+  grK += -girK * (irK * irK);
+  // star velocity u* = (iZR usL + iZL usR) / (iZL + iZR)
+  double gusL = gus * iZR / Dz, gusR = gus * iZL / Dz;
+  double giZR = gus * (usL - us) / Dz, giZL = gus * (usR - us) / Dz;
+  double giWL = left ? giWK : 0.0, giWR = left ? 0.0 : giWK;
+  // side-K inputs
+  double grL = 0, guL = 0, gpL = 0, grR = 0, guR = 0, gpR = 0;
+  if (left) { grL += grK; guL += guK; gpL += gpK; }
+  else { grR += grK; guR += guK; gpR += gpK; }
+  // ---- reverse through the Newton evaluations ----
+  double gCL = 0, gCR = 0, gipL = 0, gipR = 0;
+  double gps_cur = gps;  // gradient w.r.t. p* of the evaluation being reversed
+  for (int it = NI; it >= 0; it--) {
+    const double p = psv[it];
+    const double aL = p * ipL - 1.0, aR = p * ipR - 1.0;
+    const double sL = sqrt(1.0 + g1 * aL), sR = sqrt(1.0 + g1 * aR);
+    const double Wl = CL * sL, Wr = CR * sR;
+    const double iwl = 1.0 / Wl, iwr = 1.0 / Wr;
+    const double ql = CL * iwl, qr = CR * iwr;
+    // iZ = (0.5 iW)(1 + q^2)
+    giWL += giZL * (0.5 * (1.0 + ql * ql));
+    double gql = giZL * ((0.5 * iwl) * (2.0 * ql));
+    giWR += giZR * (0.5 * (1.0 + qr * qr));
+    double gqr = giZR * ((0.5 * iwr) * (2.0 * qr));
+    gCL += gql * iwl;
+    giWL += gql * CL;
+    gCR += gqr * iwr;
+    giWR += gqr * CR;
+    // usL = uL - (p - pL) iWL ; usR = uR + (p - pR) iWR
+    guL += gusL;
+    gps_cur += -gusL * iwl;
+    gpL += gusL * iwl;
+    giWL += -gusL * (p - pL);
+    guR += gusR;
+    gps_cur += gusR * iwr;
+    gpR += -gusR * iwr;
+    giWR += gusR * (p - pR);
+    // iW = 1/W, W = C s, s = sqrt(1 + g1 a), a = p ip - 1
+    const double gWl = -giWL * (iwl * iwl), gWr = -giWR * (iwr * iwr);
+    gCL += gWl * sL;
+    gCR += gWr * sR;
+    const double gaL = (gWl * CL) / (2.0 * sL) * g1, gaR = (gWr * CR) / (2.0 * sR) * g1;
+    gps_cur += gaL * ipL + gaR * ipR;
+    gipL += gaL * p;
+    gipR += gaR * p;
+    if (it == 0) break;
+    // p_it = p_{it-1} - (usR - usL)/(iZL + iZR) of evaluation it-1
+    double gprev = 0.0;
+    giZL = giZR = gusL = gusR = giWL = giWR = 0.0;
+    if (!flv[it - 1]) {
+      const double pp = psv[it - 1];
+      const double bl = sqrt(1.0 + g1 * (pp * ipL - 1.0)), br = sqrt(1.0 + g1 * (pp * ipR - 1.0));
+      const double wl = 1.0 / (CL * bl), wr = 1.0 / (CR * br);
+      const double uls = uL - (pp - pL) * wl, urs = uR + (pp - pR) * wr;
+      const double zl = (0.5 * wl) * (1.0 + (CL * wl) * (CL * wl));
+      const double zr = (0.5 * wr) * (1.0 + (CR * wr) * (CR * wr));
+      const double D = zl + zr;
+      gprev = gps_cur;
+      gusR = -gps_cur / D;
+      gusL = gps_cur / D;
+      const double gD = gps_cur * (urs - uls) / (D * D);
+      giZL = gD;
+      giZR = gD;
+    }
+    gps_cur = gprev;
+  }
+  // first guess p* = num0 / den0 (unless floored)
+  if (!fl0) {
+    const double gnum = gps_cur / den0;
+    const double gden = -gps_cur * (num0 / den0) / den0;
+    gCR += gnum * (pL - CL * (uR - uL)) + gden;
+    gCL += gnum * (pR - CR * (uR - uL)) + gden;
+    gpL += gnum * CR;
+    gpR += gnum * CL;
+    guR += -gnum * (CL * CR);
+    guL += gnum * (CL * CR);
+  }
+  gpL += -gipL * (ipL * ipL);
+  gpR += -gipR * (ipR * ipR);
+  gpL += gCL * ((gam * rL) / (2.0 * CL));
+  grL += gCL * ((gam * pL) / (2.0 * CL));
+  gpR += gCR * ((gam * rR) / (2.0 * CR));
+  grR += gCR * ((gam * pR) / (2.0 * CR));
+  gL[0] += grL; gL[1] += guL; gL[4] += gpL;
+  gR[0] += grR; gR[1] += guR; gR[4] += gpR;
+}
+
+// ---- one pencil ------------------------------------------------------------
+
+constexpr int kMaxPencil = 38;
+
+// Adjoint of one pencil's sweep update.  U: the sweep's input cells
+// (pencil roles rho, m_n, m_t1, m_t2, E) as U[v * n + j]; lam: on entry the
+// adjoint of the sweep's output on the same cells, on exit the adjoint of
+// its input (cells outside [lo, hi) are not updated by the sweep and keep
+// their identity part).  gface_lo/hi: adjoints of the fluxes at j = lo-1/2
+// and hi-1/2 stored for reflux (nullptr if none).
+AMR_HD inline void pencil_vjp(const InstParams& ip, double nu, int n, int lo, int hi, const double* U, double* lam,
+                              const double* gface_lo, const double* gface_hi) {
+  Prim P[kMaxPencil];
+  double dl[kMaxPencil][5], fa[kMaxPencil][5], fl[kMaxPencil];
+  Par pa[kMaxPencil][5];
+  double WL[kMaxPencil][5], WR[kMaxPencil][5];
+  const double sixth = ip.sixth;
+  for (int j = 0; j < n; j++) {
+    double u5[5] = {U[j], U[n + j], U[2 * n + j], U[3 * n + j], U[4 * n + j]};
+    P[j] = prim_fwd(ip, u5);
+  }
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++)
+      fa[j][v] = 0.5 * (P[j].q[v] + P[j + 1].q[v]) - (dl[j + 1][v] - dl[j][v]) * sixth;
+  bool shk[kMaxPencil], fact[kMaxPencil];
+  double rr_[kMaxPencil];
+  for (int j = 2; j <= n - 3; j++) {
+    const double pp1 = P[j + 1].q[4], pm1 = P[j - 1].q[4];
+    const double dp1 = pp1 - pm1;
+    const double pmin = pp1 < pm1 ? pp1 : pm1;
+    shk[j] = (fabs(dp1) > 0.33 * pmin) && (P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
+    const double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+    const double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    rr_[j] = r;
+    double ft = 10.0 * (r - 0.75);
+    fact[j] = shk[j] && dp2 != 0.0 && ft < 1.0 && ft > 0.0;
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    fl[j] = shk[j] ? ft : 0.0;
+    for (int v = 0; v < 5; v++) pa[j][v] = parabola(P[j].q[v], fa[j - 1][v], fa[j][v], fl[j], sixth);
+    trace(ip, P[j].q[0], P[j].q[1], P[j].c, P[j].ir, pa[j], nu, WL[j], WR[j]);
+  }
+  // adjoint accumulators
+  double gq[kMaxPencil][5] = {}, gc[kMaxPencil] = {}, gir[kMaxPencil] = {};
+  double gdl[kMaxPencil][5] = {}, gfa[kMaxPencil][5] = {}, gfl[kMaxPencil] = {};
+  double gWL[kMaxPencil][5] = {}, gWR[kMaxPencil][5] = {};
+  // update U_j -= nu (F_{j+1/2} - F_{j-1/2}) on [lo, hi); faces for reflux
+  for (int j = lo - 1; j <= hi - 1; j++) {
+    double gF[5];
+    for (int v = 0; v < 5; v++) {
+      const double up = (j + 1 >= lo && j + 1 < hi) ? lam[v * n + j + 1] : 0.0;
+      const double dn = (j >= lo && j < hi) ? lam[v * n + j] : 0.0;
+      gF[v] = nu * (up - dn);
+    }
+    if (j == lo - 1 && gface_lo)
+      for (int v = 0; v < 5; v++) gF[v] += gface_lo[v];
+    if (j == hi - 1 && gface_hi)
+      for (int v = 0; v < 5; v++) gF[v] += gface_hi[v];
+    riemann_vjp(ip, WL[j], WR[j + 1], gF, gWL[j], gWR[j + 1]);
+  }
+  for (int j = 2; j <= n - 3; j++) {
+    ParGrad G[5] = {};
+    double grho = 0, gu = 0;
+    trace_vjp(ip, P[j].q[0], P[j].q[1], P[j].c, P[j].ir, pa[j], nu, gWL[j], gWR[j], G, &grho, &gu, &gc[j], &gir[j]);
+    gq[j][0] += grho;
+    gq[j][1] += gu;
+    for (int v = 0; v < 5; v++)
+      parabola_vjp(P[j].q[v], fa[j - 1][v], fa[j][v], fl[j], sixth, G[v], &gq[j][v], &gfa[j - 1][v], &gfa[j][v],
+                   &gfl[j]);
+    if (fact[j]) {
+      const double gr = 10.0 * gfl[j];
+      const double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+      const double gdp1 = gr / dp2, gdp2 = -gr * rr_[j] / dp2;
+      gq[j + 1][4] += gdp1;
+      gq[j - 1][4] -= gdp1;
+      gq[j + 2][4] += gdp2;
+      gq[j - 2][4] -= gdp2;
+    }
+  }
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++) {
+      const double g = gfa[j][v];
+      gq[j][v] += 0.5 * g;
+      gq[j + 1][v] += 0.5 * g;
+      gdl[j + 1][v] -= sixth * g;
+      gdl[j][v] += sixth * g;
+    }
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++)
+      slope_vjp(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v], gdl[j][v], &gq[j - 1][v], &gq[j][v], &gq[j + 1][v]);
+  for (int j = 0; j < n; j++) {
+    double u5[5] = {U[j], U[n + j], U[2 * n + j], U[3 * n + j], U[4 * n + j]};
+    double gU[5] = {0, 0, 0, 0, 0};
+    prim_vjp(ip, u5, P[j], gq[j], gc[j], gir[j], gU);
+    for (int v = 0; v < 5; v++) lam[v * n + j] += gU[v];
+  }
+}
+
+}  // namespace amr

@@ -310,3 +310,55 @@ def batch_state(spec: MeshSpec, keys, centres) -> np.ndarray:
             d2 = d2 + d * d
         rho = rho + 0.5 * np.exp(-d2 / 0.01)
     return conserved(spec.gamma, rho, 0.0, 0.0, 0.0, np.ones(x.shape))
+
+
+# ---------------------------------------------------------------------------
+# Differentiation workload: density from a power-law Gaussian random field
+# ---------------------------------------------------------------------------
+
+def grf_spec(root=4, block_cells=32) -> MeshSpec:
+    """root^3 octrees with the central 2x2x2 root blocks refined once."""
+    h = root // 2
+    refine = [(0, i, j, k) for k in (h - 1, h) for j in (h - 1, h) for i in (h - 1, h)]
+    return MeshSpec(root=(root, root, root), block_cells=block_cells, max_level=1, bc="periodic",
+                    gamma=5.0 / 3.0, cfl=0.4, refine=refine)
+
+
+def gaussian_random_field(n: int, seed: int, slope: float = -3.0) -> np.ndarray:
+    """Periodic Gaussian random field on an n^3 lattice with power spectrum
+    P(k) ~ k^slope (amplitude ~ k^(slope/2)), k = 0 removed, unit RMS
+    (numpy PCG64, seeded).  Index order (z, y, x)."""
+    rng = np.random.default_rng(seed)
+    white = rng.normal(size=(n, n, n))
+    fk = np.fft.rfftn(white)
+    kx = np.fft.rfftfreq(n) * n
+    ky = np.fft.fftfreq(n) * n
+    kz = np.fft.fftfreq(n) * n
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    amp = np.zeros_like(k2)
+    nz = k2 > 0
+    amp[nz] = k2[nz] ** (slope / 4.0)
+    f = np.fft.irfftn(fk * amp, s=(n, n, n))
+    f -= f.mean()
+    return f / np.sqrt(np.mean(f * f))
+
+
+def grf_density(spec: MeshSpec, keys, seed: int, amplitude: float = 1e-2) -> np.ndarray:
+    """rho = 1 + amplitude * field on the finest lattice (level max_level);
+    coarser leaves take the mean of the lattice cells they cover."""
+    L = spec.max_level
+    N = spec.block_cells
+    n = spec.root[0] * N << L
+    field = 1.0 + amplitude * gaussian_random_field(n, seed)
+    keys = np.asarray(keys)
+    out = np.empty((len(keys), N, N, N))
+    for s, (l, i, j, k) in enumerate(keys):
+        r = 1 << (L - l)
+        sub = field[k * N * r:(k + 1) * N * r, j * N * r:(j + 1) * N * r, i * N * r:(i + 1) * N * r]
+        out[s] = sub.reshape(N, r, N, r, N, r).mean(axis=(1, 3, 5))
+    return out
+
+
+def grf_state(spec: MeshSpec, keys, seed: int = 4) -> np.ndarray:
+    rho = grf_density(spec, keys, seed)
+    return conserved(spec.gamma, rho, 0.0, 0.0, 0.0, np.ones_like(rho))

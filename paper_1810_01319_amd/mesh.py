@@ -160,6 +160,24 @@ class Mesh:
         check(lib().amr_graph_create(self._h, _ptr(U), _ptr(dt), int(first_step), _stream(), ctypes.byref(g)))
         return Graph(g, self, U, dt)
 
+    # adjoint ----------------------------------------------------------
+    def adjoint_scratch(self) -> torch.Tensor:
+        n = (int(self.info.adjoint_scratch_bytes) + 7) // 8
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    def step_adjoint(self, U_in: torch.Tensor, dt: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor,
+                     k: int) -> None:
+        """lam <- (d step_k / d U_in)^T lam, dt frozen, U_in the checkpoint."""
+        self._check_state(U_in)
+        self._check_state(lam)
+        check(lib().amr_hydro_step_adjoint(self._h, _ptr(U_in), _ptr(dt), _ptr(lam), _ptr(scratch), int(k),
+                                           _stream()))
+
+    def refresh_adjoint(self, U_ref: torch.Tensor, lam: torch.Tensor) -> None:
+        self._check_state(U_ref)
+        self._check_state(lam)
+        check(lib().amr_refresh_ghosts_adjoint(self._h, _ptr(U_ref), _ptr(lam), _stream()))
+
     # remesh -----------------------------------------------------------
     def indicator(self, U: torch.Tensor) -> torch.Tensor:
         """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""

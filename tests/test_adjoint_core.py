@@ -1,0 +1,145 @@
+"""CPU unit tests of the hand-written adjoint of the sweep formulas (a host
+build of the same header the gfx950 kernels compile) against central finite
+differences of the forward: the two-shock Riemann flux and a whole pencil
+update including the reflux face fluxes."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(os.path.dirname(HERE), "paper_1810_01319_amd", "libamr_core_host.so")
+P = ctypes.c_void_p
+
+
+@pytest.fixture(scope="module")
+def core():
+    if not os.path.exists(SO):
+        from paper_1810_01319_amd import _build
+
+        _build.build_core_host()
+    L = ctypes.CDLL(SO)
+    L.core_pencil_update.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.core_pencil_vjp.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.core_riemann.argtypes = [P, ctypes.c_int, P, P, P]
+    L.core_riemann_vjp.argtypes = [P, ctypes.c_int, P, P, P, P, P]
+    return L
+
+
+def ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+GAS = np.array([1.4, 1e-20, 1e-20])
+
+
+def riemann(core, L, R):
+    F = np.zeros(5)
+    core.core_riemann(ptr(GAS), 5, ptr(np.ascontiguousarray(L)), ptr(np.ascontiguousarray(R)), ptr(F))
+    return F
+
+
+STATES = [
+    ([1.0, 0.0, 0.1, -0.2, 1.0], [0.125, 0.0, 0.3, 0.1, 0.1]),     # Sod: rarefaction + shock, star left
+    ([1.0, 0.75, 0.0, 0.0, 1.0], [0.125, 0.0, 0.0, 0.0, 0.1]),     # transonic fan
+    ([1.0, 2.3, 0.2, 0.0, 1.0], [1.0, -2.0, -0.1, 0.3, 1.0]),      # two shocks, u* > 0 (off the side tie)
+    ([0.5, -0.3, 0.1, 0.1, 0.4], [1.2, 0.1, 0.0, 0.2, 2.0]),       # star right
+    ([1.0, 3.0, 0.1, 0.0, 1.0], [0.9, 3.1, 0.0, 0.1, 0.9]),        # supersonic: left state
+    ([1.0, -0.2, 0.0, 0.0, 1.0], [1.1, 0.4, 0.0, 0.0, 0.7]),       # diverging, weak
+]
+
+
+@pytest.mark.parametrize("k", range(len(STATES)))
+def test_riemann_vjp_matches_finite_differences(core, k):
+    L0, R0 = (np.array(a, dtype=float) for a in STATES[k])
+    rng = np.random.default_rng(k)
+    for _ in range(6):
+        gF = rng.normal(size=5)
+        dL, dR = rng.normal(size=5), rng.normal(size=5)
+        gL, gR = np.zeros(5), np.zeros(5)
+        core.core_riemann_vjp(ptr(GAS), 5, ptr(L0), ptr(R0), ptr(gF), ptr(gL), ptr(gR))
+        eps = 1e-6
+        fp = gF @ riemann(core, L0 + eps * dL, R0 + eps * dR)
+        fm = gF @ riemann(core, L0 - eps * dL, R0 - eps * dR)
+        fd = (fp - fm) / (2 * eps)
+        ad = gL @ dL + gR @ dR
+        assert abs(ad - fd) <= 2e-7 * max(1.0, abs(fd)), (k, ad, fd)
+
+
+def pencil_state(n, rng, kind):
+    x = np.arange(n, dtype=float)
+    if kind == "smooth":
+        rho = 1 + 0.2 * np.sin(0.4 * x + rng.uniform(0, 6))
+        u = 0.5 * np.cos(0.3 * x + rng.uniform(0, 6))
+        p = 1 + 0.3 * np.sin(0.5 * x + rng.uniform(0, 6))
+    elif kind == "shock":
+        rho = np.where(x < n // 2, 2.0, 1.0) + 0.05 * np.sin(x)
+        u = np.where(x < n // 2, 0.6, -0.2) + 0.01 * np.sin(1.3 * x)  # generic: no exact dL = 0
+        p = np.where(x < n // 2, 3.0, 1.0) + 0.02 * np.cos(x)
+    else:  # supersonic flow to the left with waves
+        rho = 1 + 0.1 * np.sin(0.6 * x)
+        u = -2.5 + 0.2 * np.cos(0.4 * x)
+        p = 0.5 + 0.05 * np.sin(0.7 * x)
+    v = 0.3 * np.sin(0.2 * x)
+    w = -0.2 * np.cos(0.25 * x)
+    E = p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)
+    return np.array([rho, rho * u, rho * v, rho * w, E])
+
+
+@pytest.mark.parametrize("kind", ["smooth", "shock", "supersonic"])
+# kink-free central differences on smooth pencils are checked separately below
+@pytest.mark.parametrize("n,lo,hi", [(22, 3, 19), (38, 3, 35), (14, 3, 11)])
+def test_pencil_vjp_matches_finite_differences(core, kind, n, lo, hi):
+    rng = np.random.default_rng(n + len(kind))
+    U0 = pencil_state(n, rng, kind)
+    nu = 0.35 / 3.0
+    for _ in range(4):
+        lam = rng.normal(size=(5, n))
+        gface = rng.normal(size=10)
+        dU = rng.normal(size=(5, n)) * np.array([1.0, 0.5, 0.5, 0.5, 2.0])[:, None]
+
+        def phi(U):
+            out, faces = np.zeros((5, n)), np.zeros(10)
+            core.core_pencil_update(ptr(GAS), 5, nu, n, lo, hi, ptr(np.ascontiguousarray(U)), ptr(out), ptr(faces))
+            return float(np.sum(lam * out) + gface @ faces)
+
+        adj = np.ascontiguousarray(lam.copy())
+        core.core_pencil_vjp(ptr(GAS), 5, nu, n, lo, hi, ptr(np.ascontiguousarray(U0)), ptr(adj), ptr(gface))
+        ad = float(np.sum(adj * dU))
+        # The limiters make the update continuous but only piecewise smooth:
+        # the adjoint follows the branch the forward took at U0, so it must
+        # equal the one-sided difference on that side of any kink.
+        eps = 1e-7
+        f0 = phi(U0)
+        fp = (phi(U0 + eps * dU) - f0) / eps
+        fm = (f0 - phi(U0 - eps * dU)) / eps
+        err = min(abs(ad - fp), abs(ad - fm))
+        assert err <= 2e-5 * max(1.0, abs(ad)), (kind, ad, fp, fm)
+
+
+def test_pencil_vjp_central_differences_per_cell(core):
+    """Coordinate-wise central differences on smooth sub- and supersonic
+    pencils (no limiter kink within the step): every adjoint entry."""
+    for kind, seed in (("smooth", 3), ("supersonic", 5)):
+        n, lo, hi = 22, 3, 19
+        rng = np.random.default_rng(seed)
+        U0 = pencil_state(n, rng, kind)
+        nu = 0.35 / 3.0
+        lam = rng.normal(size=(5, n))
+        gface = rng.normal(size=10)
+
+        def phi(U):
+            out, faces = np.zeros((5, n)), np.zeros(10)
+            core.core_pencil_update(ptr(GAS), 5, nu, n, lo, hi, ptr(np.ascontiguousarray(U)), ptr(out), ptr(faces))
+            return float(np.sum(lam * out) + gface @ faces)
+
+        adj = np.ascontiguousarray(lam.copy())
+        core.core_pencil_vjp(ptr(GAS), 5, nu, n, lo, hi, ptr(np.ascontiguousarray(U0)), ptr(adj), ptr(gface))
+        for v in range(5):
+            for j in range(n):
+                e = np.zeros((5, n))
+                h = 1e-7 * max(1.0, abs(U0[v, j]))
+                e[v, j] = h
+                fd = (phi(U0 + e) - phi(U0 - e)) / (2 * h)
+                assert abs(fd - adj[v, j]) <= 1e-5 * max(1.0, abs(fd)), (kind, v, j, adj[v, j], fd)

@@ -1,0 +1,228 @@
+"""GPU tests of the hand-written adjoint.
+
+* refresh transpose: <R v, w> = <v, R^T w> to 1e-12 (the refresh is
+  positively homogeneous and piecewise linear, so R v = J_R(v) v exactly);
+* one full step: sampled adjoint entries (all fields, interior and block
+  edges) against coordinate-wise central differences of the forward step
+  with dt fixed, for both sweep orders;
+* the differentiation workload (4^3 roots of 32^3 cells, central octant
+  refined once, 10 steps, density misfit to a target field): the autograd
+  gradient against central differences on 32 random unit directions,
+  |g.v - FD| <= 1e-6 |FD|;
+* a tiny mesh: gradient entries against central differences of the FP64
+  CPU oracle's forward (same dt sequence).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1810_01319_amd import adjoint as A
+from paper_1810_01319_amd import inputs as I
+from paper_1810_01319_amd.mesh import Mesh
+
+pytestmark = pytest.mark.gpu
+G = 3
+
+
+def say(msg):
+    print(f"[gpu-adjoint] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU adjoint tests need an MI355X"
+
+
+def amr_spec(N=8, seed=3):
+    root = (2, 2, 2)
+    return I.MeshSpec(root=root, block_cells=N, max_level=2, gamma=5 / 3,
+                      refine=I.random_refine_list(root, 2, 4, seed))
+
+
+def test_refresh_adjoint_dot_product():
+    for N, seed in ((8, 3), (16, 4)):
+        spec = amr_spec(N, seed)
+        m = Mesh(**spec.kwargs())
+        say(f"refresh dot test N={N} leaves={m.nleaf}")
+        rng = np.random.default_rng(seed)
+        v = rng.normal(size=(m.nleaf, 5, N, N, N))
+        Uv = m.state_from_active(v)
+        m.refresh(Uv)
+        w = torch.from_numpy(rng.normal(size=tuple(Uv.shape))).to(Uv.device)
+        lhs = float((Uv * w).sum())
+        lam = w.clone()
+        m.refresh_adjoint(Uv, lam)
+        act = A.active_mask(m)
+        assert float(lam[:, :, ~act].abs().max()) == 0.0
+        rhs = float((torch.from_numpy(v).to(Uv.device) * lam[:, :, G:G + N, G:G + N, G:G + N]).sum())
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_step_adjoint_matches_differences(k):
+    """Every sampled entry of the one-step adjoint against a coordinate-wise
+    central difference, all five fields, interior and block-edge cells (the
+    latter reach the ghost refresh and the coarse-fine reflux).  Random
+    all-field directions are avoided: on smooth data with u near 0 they
+    cross the tracing's wave-direction switches, where the step is not
+    differentiable and no difference quotient converges."""
+    spec = amr_spec(16, 5)
+    m = Mesh(**spec.kwargs())
+    N = 16
+    U0 = m.state_from_active(I.smooth_state(spec, m.keys, seed=9, amp=0.2, vel=0.4))
+    dt = m.dt_tensor()
+    m.cfl_dt(U0, dt)
+    rng = np.random.default_rng(10 + k)
+    act = A.active_mask(m)
+    lam0 = torch.zeros_like(U0)
+    lam0[:, :, act] = torch.from_numpy(rng.normal(size=(m.nleaf, 5, N ** 3))).to(U0.device)
+    lam = lam0.clone()
+    m.step_adjoint(U0, dt, lam, m.adjoint_scratch(), k)
+
+    def advance(U):
+        W = U.clone()
+        m.step_dt(W, dt, k)
+        return W
+
+    worst = 0.0
+    edge = [0, 1, 2, N - 3, N - 2, N - 1]
+    for t in range(40):
+        f = t % 5
+        s = int(rng.integers(m.nleaf))
+        z, y, x = (int(v) for v in rng.integers(N, size=3))
+        if t % 2:  # pin one coordinate to a block edge
+            c = [z, y, x]
+            c[int(rng.integers(3))] = edge[int(rng.integers(len(edge)))]
+            z, y, x = c
+        z, y, x = z + G, y + G, x + G
+        h = 1e-6 * max(1.0, abs(float(U0[s, f, z, y, x])))
+        Up, Um = U0.clone(), U0.clone()
+        Up[s, f, z, y, x] += h
+        Um[s, f, z, y, x] -= h
+        # <lam0, S(U+h e) - S(U-h e)> summed cell by cell without cancellation
+        fd = float(((advance(Up) - advance(Um)) * lam0).sum()) / (2 * h)
+        ad = float(lam[s, f, z, y, x])
+        err = abs(fd - ad) / max(1.0, abs(fd))
+        worst = max(worst, err)
+        assert err <= 1e-6, (k, f, s, z, y, x, ad, fd)
+    say(f"step k={k}: 40 adjoint entries, worst relative error {worst:.3e}")
+
+
+def test_differentiation_workload_gradient_on_random_directions():
+    spec = I.grf_spec(root=4, block_cells=32)
+    m = Mesh(**spec.kwargs())
+    assert m.nleaf == 120
+    N = spec.block_cells
+    say(f"grf workload: {m.nleaf} leaves")
+    rho0 = torch.from_numpy(I.grf_density(spec, m.keys, seed=4)).to(m.device)
+    target = torch.from_numpy(I.grf_density(spec, m.keys, seed=40)).to(m.device)
+    base = m.state_from_active(I.grf_state(spec, m.keys, seed=4))
+    steps = 10
+
+    def state(rho):
+        U = base.clone()
+        U[:, 0, G:G + N, G:G + N, G:G + N] = rho
+        return U
+
+    r = rho0.clone().requires_grad_(True)
+    UK = A.run_steps(state(r), m, steps)
+    L = A.density_misfit(m, UK, target)
+    L.backward()
+    g = r.grad.detach()
+    say(f"loss {float(L):.6e}, |g| {float(g.norm()):.6e}")
+    # frozen dt sequence of the forward
+    dts = []
+    U = state(rho0)
+    for k in range(steps):
+        dt = m.dt_tensor()
+        m.step(U, dt, k)
+        dts.append(dt)
+    lev = torch.as_tensor(m.keys[:, 0], device=m.device, dtype=torch.float64)
+    w = torch.pow(0.125, lev)[:, None, None, None]
+
+    def run(rho):
+        U = state(rho)
+        for k in range(steps):
+            m.step_dt(U, dts[k], k)
+        return U[:, 0, G:G + N, G:G + N, G:G + N]
+
+    rng = np.random.default_rng(41)
+    # central differences: truncation O(eps^2) is far below the tolerance
+    # at eps = 1e-4, while at 1e-6 the rounding of the ten-step forward
+    # (about an ulp per cell, divided by eps) reaches a few 1e-6 relative
+    # on directions whose projection onto g is small
+    eps = 1e-4
+    worst = 0.0
+    for t in range(32):
+        v = torch.from_numpy(rng.normal(size=tuple(rho0.shape))).to(m.device)
+        v /= v.norm()
+        rp, rm = run(rho0 + eps * v), run(rho0 - eps * v)
+        # L(+) - L(-) summed cell by cell without cancellation
+        fd = float((w * (rp - rm) * (rp + rm - 2 * target)).sum()) / (2 * eps)
+        gv = float((g * v).sum())
+        rel = abs(gv - fd) / max(abs(fd), 1e-30)
+        worst = max(worst, rel)
+        assert rel <= 1e-6, (t, gv, fd, rel)
+    say(f"32 directions: worst relative error {worst:.3e}")
+
+
+def test_tiny_mesh_gradient_against_oracle_differences():
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=1, gamma=5 / 3, refine=[(0, 1, 0, 1)])
+    m = Mesh(**spec.kwargs())
+    N = 8
+    assert m.nleaf == 15
+    act0 = I.smooth_state(spec, m.keys, seed=77, amp=0.2, vel=0.3)
+    target = torch.from_numpy(I.grf_density(spec, m.keys, seed=78, amplitude=0.05)).to(m.device)
+    U0 = m.state_from_active(act0)
+    rho0 = U0[:, 0, G:G + N, G:G + N, G:G + N].clone()
+    steps = 2
+
+    def state(rho):
+        U = U0.clone()
+        U[:, 0, G:G + N, G:G + N, G:G + N] = rho
+        return U
+
+    r = rho0.clone().requires_grad_(True)
+    L = A.density_misfit(m, A.run_steps(state(r), m, steps), target)
+    L.backward()
+    g = r.grad.detach().cpu().numpy()
+    # dt sequence (identical on the oracle: the forward is bitwise equal)
+    dts = []
+    U = state(rho0)
+    for k in range(steps):
+        dt = m.dt_tensor()
+        m.step(U, dt, k)
+        dts.append(float(dt.cpu()[0]))
+    om = O.OracleMesh(**spec.kwargs())
+    idx = {tuple(k): s for s, k in enumerate(om.keys)}
+    perm = np.array([idx[tuple(k)] for k in m.keys])
+    lev = m.keys[:, 0]
+    w = 0.125 ** lev
+    tgt = target.cpu().numpy()
+
+    def oracle_rho(act):
+        o = np.empty_like(act)
+        o[perm] = act
+        om.set_active(o)
+        for k in range(steps):
+            om.step_dt(k, dts[k])
+        return om.active()[perm][:, 0]
+
+    rng = np.random.default_rng(79)
+    cells = [(int(rng.integers(m.nleaf)), *map(int, rng.integers(N, size=3))) for _ in range(48)]
+    h = 1e-6
+    scale = np.abs(g).max()
+    worst = 0.0
+    for (s, z, y, x) in cells:
+        ap, am = act0.copy(), act0.copy()
+        ap[s, 0, z, y, x] += h
+        am[s, 0, z, y, x] -= h
+        rp, rm = oracle_rho(ap), oracle_rho(am)
+        fd = float(np.sum(w[:, None, None, None] * (rp - rm) * (rp + rm - 2 * tgt))) / (2 * h)
+        err = abs(fd - g[s, z, y, x]) / max(abs(fd), 1e-3 * scale)
+        worst = max(worst, err)
+        assert err <= 1e-6, ((s, z, y, x), g[s, z, y, x], fd)
+    say(f"tiny mesh: 48 oracle difference entries, worst relative error {worst:.3e}")
