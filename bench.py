@@ -27,6 +27,37 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, published
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, published
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the sources the sweep kernels are compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ppm_core.hpp", "layout.hpp", "ghost.hpp"):
+        with open(os.path.join(ROOT, "paper_1810_01319_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload_name: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same
+    counters' reading for a copy of known size), or None if there is none
+    or the kernel sources changed since the counters were taken."""
+    name = kernel.replace("<", "_").replace(">", "").replace(",", "_")
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload_name}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def workload(name):
     from paper_1810_01319_amd import inputs as I
 
@@ -188,11 +219,20 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
         if i > 0:
             best_f = t1 - t0 if best_f is None else min(best_f, t1 - t0)
             best_b = t2 - t1 if best_b is None else min(best_b, t2 - t1)
+    # one more adjoint pass with per-phase HIP events
+    fwd()
+    torch.cuda.synchronize()
+    m.profile(True)
+    bwd()
+    prof = m.profile_read()
+    m.profile(False)
+    phases = {p: round(v[0] / steps, 4) for p, v in prof.items() if p.startswith("adj_")}
     return {"workload": "grf-density-misfit: 4^3 root octrees x 32^3 cells, central 2^3 roots refined once "
                         f"(120 leaves, 3.9M cells), {steps} steps, gamma 5/3, periodic",
             "steps": steps, "forward_ms": t_plain * 1e3, "forward_checkpointing_ms": best_f * 1e3,
             "adjoint_ms": best_b * 1e3, "adjoint_over_forward": best_b / t_plain,
-            "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain}
+            "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain,
+            "adjoint_phases_ms_per_step": phases}
 
 
 def run_adaptive(args, spec, desc):
@@ -207,7 +247,7 @@ def run_adaptive(args, spec, desc):
     cap = adaptive.capacity_from_memory(mesh)
     pool = adaptive.StatePool(mesh, cap)
     U = pool.initial(mesh, lambda keys: I.blasts_state(spec, keys))
-    if not args.no_tune:
+    if args.tune:
         # tune on the initial mesh, with the second arena as scratch
         autotune.tune(mesh, U, steps=1, use_cache=False, scratch=pool.other())
     mesh, U, _, _ = adaptive.run(mesh, U, args.warmup, max_blocks=cap, pool=pool)
@@ -262,7 +302,7 @@ def main():
     ap.add_argument("--workload", default="sedov")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tune", action="store_true", help="autotune the sweep launch shapes first")
     ap.add_argument("--batch-steps", type=int, default=20, help="steps of the batched comparison (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="steps of the adjoint comparison (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -293,7 +333,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     tuned = None
-    if not args.no_tune:
+    if args.tune:
         from paper_1810_01319_amd import autotune
 
         tuned = autotune.tune(mesh, U, use_cache=False)
@@ -315,15 +355,28 @@ def main():
     cells = mesh.nleaf * N ** 3
     K = args.steps
     value = cells * K / wall
-    # dominant kernel: the three sweeps (FP64 ALU bound)
-    sweep_ms = sum(prof[p][0] for p in ("sweep_x", "sweep_y", "sweep_z"))
-    sweep_launches = sum(prof[p][1] for p in ("sweep_x", "sweep_y", "sweep_z"))
-    flops_step = mesh.nleaf * costs.sweep_flops_per_block_step(N, spec.riemann_iters)
-    launches_per_step = sweep_launches / K
-    flops_per_launch = flops_step / launches_per_step
-    avg_launch_s = sweep_ms * 1e-3 / sweep_launches
-    achieved = flops_per_launch / avg_launch_s / 1e12
-    phases = {p: round(prof[p][0] / K, 4) for p in _lib.PHASES}
+    # dominant kernel: the sweep axis with the most kernel time (FP64 ALU
+    # bound).  Its pencils per block depend on its place in the step's sweep
+    # order (x, y, z on even steps, z, y, x on odd ones).
+    launch = mesh.get_launch()
+    pen = costs.sweep_pencils_per_block(N)
+    fpp = costs.sweep_flops_per_pencil(N, spec.riemann_iters)
+    axes = ("x", "y", "z")
+    per_axis = {}
+    for a in range(3):
+        pencils = 0
+        for k in range(args.warmup, args.warmup + K):
+            order = (0, 1, 2) if k % 2 == 0 else (2, 1, 0)
+            pencils += (pen["first"], pen["second"], pen["third"])[order.index(a)]
+        ms, n = prof["sweep_" + axes[a]]
+        flops_launch = mesh.nleaf * fpp * pencils / K
+        kname = ("sweep_staged" if launch["sweep_mode"][a] == 1 else "sweep_kernel") + f"<{N},{a}>"
+        per_axis[axes[a]] = {"kernel": kname, "avg_launch_ms": ms / n, "flops_per_launch": flops_launch,
+                             "TFLOP/s": flops_launch / (ms / n * 1e-3) / 1e12}
+    dom = max(per_axis, key=lambda a: per_axis[a]["avg_launch_ms"])
+    achieved = per_axis[dom]["TFLOP/s"]
+    traffic = measured_traffic(per_axis[dom]["kernel"], args.workload)
+    phases = {p: round(prof[p][0] / K, 4) for p in _lib.PHASES if not p.startswith("adj_")}
     refresh_bytes = mesh.nleaf * costs.refresh_bytes_per_block(N)
     refresh_ms = (prof["refresh1"][0] + prof["refresh2"][0]) / K
     out = {
@@ -341,15 +394,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "leaves": mesh.nleaf, "cells": cells, "block_cells": N,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "sweep_kernel (x, y, z)", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": per_axis[dom]["kernel"], "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None,
-                     "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
+                     "traffic": traffic, "flops_per_launch": per_axis[dom]["flops_per_launch"],
+                     "avg_launch_ms": per_axis[dom]["avg_launch_ms"]},
+        "sweeps": per_axis,
         "phases_ms_per_step": phases,
-        "launch": mesh.get_launch(),
+        "launch": launch,
         "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
                         "peak": PEAK_HBM_GBS},
     }
+    if tuned is not None:
+        out["autotune"] = tuned
     if args.batch_steps > 0:
         del U
         out["batched"] = batched_compare(args.batch_steps)

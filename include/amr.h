@@ -164,9 +164,9 @@ amr_status amr_graph_destroy(amr_graph* graph);
  * recomputed into scratch_dev (adjoint_scratch_bytes of amr_mesh_info); every
  * limiter, flattening, wave-direction, floor and Riemann branch is taken as
  * the forward took it, and the result is the exact vector-Jacobian product of
- * the computed step on those branches.  The refresh transpose scatter-adds
- * with FP64 atomics (sums in unspecified order).  Post-update floors are
- * assumed inactive. */
+ * the computed step on those branches (post-update floors included).  The
+ * refresh transpose scatter-adds with FP64 atomics (sums in unspecified
+ * order).  Errors: AMR_E_INVALID if riemann_iters exceeds 8. */
 amr_status amr_hydro_step_adjoint(amr_mesh* mesh, const double* U_in_dev, const double* dt_dev, double* lam_dev,
                                   void* scratch_dev, int64_t step_index, void* stream);
 
@@ -241,7 +241,15 @@ amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 #define AMR_PHASE_SWEEP_Y 4
 #define AMR_PHASE_SWEEP_Z 5
 #define AMR_PHASE_REFLUX 6
-#define AMR_NPHASE 7
+/* amr_hydro_step_adjoint: recompute of the sweep inputs (copies, refresh,
+ * two sweeps), reflux transpose, sweep transposes, refresh transpose */
+#define AMR_PHASE_ADJ_RECOMPUTE 7
+#define AMR_PHASE_ADJ_REFLUX 8
+#define AMR_PHASE_ADJ_SWEEP_X 9
+#define AMR_PHASE_ADJ_SWEEP_Y 10
+#define AMR_PHASE_ADJ_SWEEP_Z 11
+#define AMR_PHASE_ADJ_REFRESH 12
+#define AMR_NPHASE 13
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
 /* Waits for the recorded events, then writes per phase the summed kernel

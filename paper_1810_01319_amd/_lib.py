@@ -15,7 +15,8 @@ AMR_OK = 0
 STATUS = {-1: "AMR_E_INVALID", -2: "AMR_E_BALANCE", -3: "AMR_E_NOMEM", -4: "AMR_E_HIP",
           -5: "AMR_E_CAPACITY", -6: "AMR_E_STATE"}
 BC = {"periodic": 0, "outflow": 1}
-PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux"]
+PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux",
+          "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh"]
 
 
 class AmrError(RuntimeError):

@@ -68,15 +68,28 @@ __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__
   }
 }
 
-// Sweep transpose: one lane per pencil recomputes the pencil's forward from
-// the sweep's input Uin and applies the pencil's vector-Jacobian product to
-// lam in place.
+// Sweep transpose, LDS-staged: a workgroup holds R whole pencils, one thread
+// per cell.  The forward sweep is recomputed phase by phase (primitives,
+// slopes, face values, flattening + parabolas + tracing, Riemann fluxes) and
+// its intermediates kept in LDS; the reverse phases then run in the opposite
+// order, each cell gathering what its neighbours' products send it, so no
+// two threads ever add to the same entry.
+template <int N>
+struct AdjShape {
+  static constexpr int M = N + 2 * G;
+  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : 5);  // pencils per tile
+  static constexpr int T = R * M;                               // cells per tile
+  static constexpr int WG = ((T + 63) / 64) * 64;
+};
+
 template <int N, int DIR>
-__global__ void __launch_bounds__(64) sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam,
-                                                    const double* __restrict__ dtv, DevPlan P,
-                                                    const double* __restrict__ gfaces, int loA, int nA, int loB,
-                                                    int nB) {
-  constexpr int M = N + 2 * G;
+__global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* __restrict__ Uin,
+                                                                  double* __restrict__ lam,
+                                                                  const double* __restrict__ dtv, DevPlan P,
+                                                                  const double* __restrict__ gfaces, int loA,
+                                                                  int nA, int loB, int nB) {
+  using S = AdjShape<N>;
+  constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int A = DIR == 0 ? 1 : 0;
   constexpr int B = DIR == 2 ? 1 : 2;
@@ -84,41 +97,217 @@ __global__ void __launch_bounds__(64) sweep_adjoint(const double* __restrict__ U
   constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
   constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
   constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
-  const int64_t npen = int64_t(nA) * nB;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= P.nleaf * npen) return;
-  const int s = int(t / npen);
-  const int pp = int(t - int64_t(s) * npen);
-  const int iA = loA + pp % nA, iB = loB + pp / nA;
+  constexpr int NS = DIR == 0 ? 1 : R;  // item stride between neighbouring cells
+  constexpr int fmap[5] = {0, 1 + DIR, 1 + T1, 1 + T2, 4};
+  __shared__ double Ps[5][T];  // primitives
+  __shared__ double Xs[5][T];  // slopes; fluxes; adjoint sent to face c-1/2
+  __shared__ double Ys[5][T];  // face values at c+1/2; adjoint sent to cell c-1
+  __shared__ double Ws[5][T];  // right states at c-1/2 and their adjoint; adjoint sent to cell c+1
+  __shared__ double Ls[5][T];  // adjoint of the pre-floor update; adjoint sent to face c+1/2
+  __shared__ double Fl[2][T];  // flattening adjoint sent to p of cells c+-1, c+-2
+  const int tilesA = (nA + R - 1) / R;
+  const int64_t tile = blockIdx.x;
+  const int s = int(tile / (int64_t(nB) * tilesA));
+  const int rem = int(tile - int64_t(s) * nB * tilesA);
+  const int iB = loB + rem / tilesA;
+  const int a0 = (rem % tilesA) * R;
+  const int i = threadIdx.x;
+  const int r = DIR == 0 ? i / M : i % R;
+  const int c = DIR == 0 ? i - r * M : i / R;
+  const bool live = i < T && a0 + r < nA;
   const BlockInfo bi = P.blocks[s];
   const InstParams& ip = P.inst[bi.inst];
   const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
-  const int64_t base = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
-  const int fmap[5] = {0, 1 + DIR, 1 + T1, 1 + T2, 4};
-  double u[5 * M], l[5 * M];
-  for (int v = 0; v < 5; v++)
-    for (int c = 0; c < M; c++) {
-      u[v * M + c] = Uin[base + fmap[v] * M3 + int64_t(c) * SD];
-      l[v * M + c] = lam[base + fmap[v] * M3 + int64_t(c) * SD];
+  const int iA = loA + a0 + r;
+  const int64_t off = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const double* const ucell = Uin + off;
+  double* const lcell = lam + off;
+  const double sixth = ip.sixth;
+  const bool traced = live && c >= 2 && c <= M - 3;
+  const bool faced = live && c >= 2 && c <= M - 4;
+  const bool active = live && c >= G && c < G + N;
+
+  // ---- forward recompute ----
+  double q[5] = {0, 0, 0, 0, 0}, cs = 0, ir = 0;
+  if (live) {
+    double u5[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
+    const Prim Pr = prim_fwd(ip, u5);
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      q[v] = Pr.q[v];
+      Ps[v][i] = q[v];
     }
-  double glo[5], ghi[5];
-  const double* plo = nullptr;
-  const double* phi = nullptr;
-  if (iA >= G && iA < G + N && iB >= G && iB < G + N) {
-    const int64_t off = int64_t(iB - G) * N + (iA - G);
-    const int sl = P.faceslot[6 * int64_t(s) + 2 * DIR], sh = P.faceslot[6 * int64_t(s) + 2 * DIR + 1];
-    if (sl >= 0) {
-      for (int v = 0; v < 5; v++) glo[v] = gfaces[(int64_t(sl) * kFields + fmap[v]) * N * N + off];
-      plo = glo;
-    }
-    if (sh >= 0) {
-      for (int v = 0; v < 5; v++) ghi[v] = gfaces[(int64_t(sh) * kFields + fmap[v]) * N * N + off];
-      phi = ghi;
-    }
+    cs = Pr.c;
+    ir = Pr.ir;
   }
-  pencil_vjp(ip, nu, M, G, G + N, u, l, plo, phi);
-  for (int v = 0; v < 5; v++)
-    for (int c = 0; c < M; c++) lam[base + fmap[v] * M3 + int64_t(c) * SD] = l[v * M + c];
+  __syncthreads();
+  if (live && c >= 1 && c <= M - 2) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) Xs[v][i] = mc_slope(Ps[v][i - NS], q[v], Ps[v][i + NS]);
+  }
+  __syncthreads();
+  if (live && c >= 1 && c <= M - 3) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ys[v][i] = 0.5 * (q[v] + Ps[v][i + NS]) - (Xs[v][i + NS] - Xs[v][i]) * sixth;
+  }
+  __syncthreads();
+  // flattening: coefficient f, whether it is interior to its clamps (fact),
+  // and the pressure-jump ratio
+  double f = 0, rr = 0, dp2 = 0;
+  bool fact = false;
+  double WL[5] = {0, 0, 0, 0, 0};
+  if (traced) {
+    const double pp1 = Ps[4][i + NS], pm1 = Ps[4][i - NS];
+    const double dp1 = pp1 - pm1;
+    const double pmin = pp1 < pm1 ? pp1 : pm1;
+    const bool shock = (fabs(dp1) > 0.33 * pmin) && (Ps[1][i - NS] - Ps[1][i + NS] > 0.0);
+    dp2 = Ps[4][i + 2 * NS] - Ps[4][i - 2 * NS];
+    rr = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    double ft = 10.0 * (rr - 0.75);
+    fact = shock && dp2 != 0.0 && ft < 1.0 && ft > 0.0;
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    f = shock ? ft : 0.0;
+    Par pa[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) pa[v] = parabola(q[v], Ys[v][i - NS], Ys[v][i], f, sixth);
+    double WR[5];
+    trace(ip, q[0], q[1], cs, ir, pa, nu, WL, WR);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ws[v][i] = WR[v];
+  }
+  __syncthreads();
+  if (faced) {
+    double R5[5], F[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) R5[v] = Ws[v][i + NS];
+    riemann_flux(ip, WL, R5, F);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Xs[v][i] = F[v];
+  }
+  __syncthreads();
+
+  // ---- reverse ----
+  // update and floors: li is the adjoint of the cell's own input through the
+  // identity part (pre-floor adjoint on active cells, unchanged elsewhere)
+  double li[5];
+  if (live) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
+    if (active) {
+      double V[5];
+#pragma unroll
+      for (int v = 0; v < 5; v++) V[v] = ucell[fmap[v] * M3] - nu * (Xs[v][i] - Xs[v][i - NS]);
+      floor_vjp(ip, V, li, li);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ls[v][i] = active ? li[v] : 0.0;
+  }
+  __syncthreads();
+  // Riemann flux at c+1/2: adjoint of the left state (own) and of the right
+  // state (cell c+1, through Ws)
+  double gWL[5] = {0, 0, 0, 0, 0};
+  if (faced) {
+    double gF[5], R5[5], gR5[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      gF[v] = nu * (Ls[v][i + NS] - Ls[v][i]);
+      R5[v] = Ws[v][i + NS];
+    }
+    const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
+    if (faces_act && (c == G - 1 || c == N + G - 1)) {
+      const int slot = P.faceslot[6 * int64_t(s) + 2 * DIR + (c == G - 1 ? 0 : 1)];
+      if (slot >= 0) {
+        const double* gf = gfaces + int64_t(slot) * kFields * N * N + int64_t(iB - G) * N + (iA - G);
+#pragma unroll
+        for (int v = 0; v < 5; v++) gF[v] += gf[fmap[v] * N * N];
+      }
+    }
+    riemann_vjp_n<kAdjMaxIters>(ip, WL, R5, gF, gWL, gR5);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Ws[v][i + NS] = gR5[v];
+  }
+  __syncthreads();
+  // tracing, parabolas and flattening of the own cell
+  double gq[5] = {0, 0, 0, 0, 0}, gc = 0, gir = 0;
+  if (live) {
+    double gfa_lo[5] = {0, 0, 0, 0, 0}, gfa_hi[5] = {0, 0, 0, 0, 0};
+    double gd1 = 0, gd2 = 0;
+    if (traced) {
+      double gWR[5];
+#pragma unroll
+      for (int v = 0; v < 5; v++) gWR[v] = c >= 3 ? Ws[v][i] : 0.0;
+      Par pa[5];
+      double fL[5], fR[5];
+#pragma unroll
+      for (int v = 0; v < 5; v++) {
+        fL[v] = Ys[v][i - NS];
+        fR[v] = Ys[v][i];
+        pa[v] = parabola(q[v], fL[v], fR[v], f, sixth);
+      }
+      ParGrad Gp[5] = {};
+      double grho = 0, gu = 0;
+      trace_vjp(ip, q[0], q[1], cs, ir, pa, nu, gWL, gWR, Gp, &grho, &gu, &gc, &gir);
+      gq[0] += grho;
+      gq[1] += gu;
+      double gfl = 0;
+#pragma unroll
+      for (int v = 0; v < 5; v++) parabola_vjp(q[v], fL[v], fR[v], f, sixth, Gp[v], &gq[v], &gfa_lo[v], &gfa_hi[v], &gfl);
+      if (fact) {
+        const double gr = 10.0 * gfl;
+        gd1 = gr / dp2;
+        gd2 = -gr * rr / dp2;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      Xs[v][i] = gfa_lo[v];
+      Ls[v][i] = gfa_hi[v];
+    }
+    Fl[0][i] = gd1;
+    Fl[1][i] = gd2;
+  }
+  __syncthreads();
+  // face values at c+-1/2, flattening, then the own slope
+  if (live) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      const double ghi = (c >= 1 && c <= M - 3) ? Ls[v][i] + Xs[v][i + NS] : 0.0;
+      const double glo = (c >= 2 && c <= M - 2) ? Ls[v][i - NS] + Xs[v][i] : 0.0;
+      gq[v] += 0.5 * (ghi + glo);
+      double gm = 0, gp = 0;
+      if (c >= 1 && c <= M - 2) {
+        const double gdl = sixth * (ghi - glo);
+        slope_vjp(Ps[v][i - NS], q[v], Ps[v][i + NS], gdl, &gm, &gq[v], &gp);
+      }
+      Ys[v][i] = gm;
+      Ws[v][i] = gp;
+    }
+    double gp4 = 0;
+    if (c >= 1) gp4 += Fl[0][i - NS];
+    if (c + 1 < M) gp4 -= Fl[0][i + NS];
+    if (c >= 2) gp4 += Fl[1][i - 2 * NS];
+    if (c + 2 < M) gp4 -= Fl[1][i + 2 * NS];
+    gq[4] += gp4;
+  }
+  __syncthreads();
+  // neighbours' slopes, primitives, and the new adjoint of the cell
+  if (live) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      if (c >= 1) gq[v] += Ws[v][i - NS];
+      if (c + 1 < M) gq[v] += Ys[v][i + NS];
+    }
+    double u5[5], gU[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
+    const Prim Pr = prim_fwd(ip, u5);
+    prim_vjp(ip, u5, Pr, gq, gc, gir, gU);
+#pragma unroll
+    for (int v = 0; v < 5; v++) lcell[fmap[v] * M3] = li[v] + gU[v];
+  }
 }
 
 // Refresh transpose, phase 2 (prolongation): a prolonged ghost's adjoint
@@ -240,13 +429,13 @@ inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 template <int N>
 hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
                        int dir, const int swept[3], hipStream_t st) {
-  constexpr int M = N + 2 * G;
+  using S = AdjShape<N>;
   const int A = dir == 0 ? 1 : 0, B = dir == 2 ? 1 : 2;
-  const int loA = swept[A] ? G : 0, nA = swept[A] ? N : M;
-  const int loB = swept[B] ? G : 0, nB = swept[B] ? N : M;
-  const int64_t n = P.nleaf * int64_t(nA) * nB;
-  if (n == 0) return hipSuccess;
-  const dim3 g(gridn(n, 64)), b(64);
+  const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
+  const int loB = swept[B] ? G : 0, nB = swept[B] ? N : S::M;
+  const int64_t tiles = P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R);
+  if (tiles == 0) return hipSuccess;
+  const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
   if (dir == 0) hipLaunchKernelGGL((sweep_adjoint<N, 0>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
   else if (dir == 1) hipLaunchKernelGGL((sweep_adjoint<N, 1>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
   else hipLaunchKernelGGL((sweep_adjoint<N, 2>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);

@@ -6,6 +6,10 @@
 
 namespace amr {
 
+// Largest riemann_iters the sweep adjoint supports (its Newton history is
+// held in registers).
+constexpr int kAdjMaxIters = 8;
+
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t st);
 // reflux transpose: adjoints of the stored face fluxes into gfaces
 hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const double* dt, double* gfaces,

@@ -379,6 +379,8 @@ amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* 
   if (!dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Plan& p = h->plan;
+  for (const InstParams& ip : p.inst)
+    if (ip.iters > kAdjMaxIters) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
   const int64_t nfield = p.nleaf * kFields * int64_t(p.M) * p.M * p.M;
   double* S[3];
   for (int i = 0; i < 3; i++) S[i] = static_cast<double*>(scratch) + i * nfield;
@@ -390,24 +392,31 @@ amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* 
     order[2] = 0;
   }
   // recompute the inputs of the three sweeps
-  hipError_t e = hipMemcpyAsync(S[0], Uin, size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = launch_refresh(P, S[0], h->cfg, st);
   int swept[3] = {0, 0, 0};
-  for (int k = 0; k < 2 && e == hipSuccess; k++) {
-    e = hipMemcpyAsync(S[k + 1], S[k], size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = launch_sweep(P, S[k + 1], dt, order[k], swept, h->cfg, st);
-    swept[order[k]] = 1;
-  }
+  hipError_t e = timed(h, AMR_PHASE_ADJ_RECOMPUTE, st, [&] {
+    hipError_t r = hipMemcpyAsync(S[0], Uin, size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
+    if (r == hipSuccess) r = launch_refresh(P, S[0], h->cfg, st);
+    for (int k = 0; k < 2 && r == hipSuccess; k++) {
+      r = hipMemcpyAsync(S[k + 1], S[k], size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
+      if (r == hipSuccess) r = launch_sweep(P, S[k + 1], dt, order[k], swept, h->cfg, st);
+      swept[order[k]] = 1;
+    }
+    return r;
+  });
   if (e != hipSuccess) return hip_fail(e, "adjoint recompute");
   // transposes in reverse order
-  e = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
-  if (e == hipSuccess) e = launch_reflux_adjoint(P, lam, dt, gfaces, st);
+  e = timed(h, AMR_PHASE_ADJ_REFLUX, st, [&] {
+    hipError_t r = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
+    if (r == hipSuccess) r = launch_reflux_adjoint(P, lam, dt, gfaces, st);
+    return r;
+  });
   for (int k = 2; k >= 0 && e == hipSuccess; k--) {
     int sw[3] = {0, 0, 0};
     for (int q = 0; q < k; q++) sw[order[q]] = 1;
-    e = launch_sweep_adjoint(P, S[k], lam, dt, gfaces, order[k], sw, st);
+    e = timed(h, AMR_PHASE_ADJ_SWEEP_X + order[k], st,
+              [&] { return launch_sweep_adjoint(P, S[k], lam, dt, gfaces, order[k], sw, st); });
   }
-  if (e == hipSuccess) e = launch_refresh_adjoint(P, lam, S[0], st);
+  if (e == hipSuccess) e = timed(h, AMR_PHASE_ADJ_REFRESH, st, [&] { return launch_refresh_adjoint(P, lam, S[0], st); });
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
 }
 

@@ -25,8 +25,8 @@ static InstParams params(const double* gas, int iters) {
 
 extern "C" {
 
-// Forward update of one pencil (cells [lo,hi) updated); faces_out[10]: the
-// fluxes at lo-1/2 and hi-1/2.
+// Forward update of one pencil (cells [lo,hi) updated, then floored);
+// faces_out[10]: the fluxes at lo-1/2 and hi-1/2.
 void core_pencil_update(const double* gas, int iters, double nu, int n, int lo, int hi, const double* U,
                         double* Uout, double* faces_out) {
   const InstParams ip = params(gas, iters);
@@ -58,8 +58,12 @@ void core_pencil_update(const double* gas, int iters, double nu, int n, int lo, 
   }
   for (int j = lo - 1; j <= hi - 1; j++) riemann_flux(ip, WL[j], WR[j + 1], F[j]);
   std::memcpy(Uout, U, sizeof(double) * 5 * n);
-  for (int j = lo; j < hi; j++)
-    for (int v = 0; v < 5; v++) Uout[v * n + j] = U[v * n + j] - nu * (F[j][v] - F[j - 1][v]);
+  for (int j = lo; j < hi; j++) {
+    double V[5], W[5];
+    for (int v = 0; v < 5; v++) V[v] = U[v * n + j] - nu * (F[j][v] - F[j - 1][v]);
+    floor_apply(ip, V, W);
+    for (int v = 0; v < 5; v++) Uout[v * n + j] = W[v];
+  }
   for (int v = 0; v < 5; v++) {
     faces_out[v] = F[lo - 1][v];
     faces_out[5 + v] = F[hi - 1][v];
@@ -70,6 +74,17 @@ void core_pencil_vjp(const double* gas, int iters, double nu, int n, int lo, int
                      const double* gface /* 10 or null */) {
   const InstParams ip = params(gas, iters);
   pencil_vjp(ip, nu, n, lo, hi, U, lam, gface, gface ? gface + 5 : nullptr);
+}
+
+// post-update floors of one cell (pencil roles) and their adjoint
+void core_floor(const double* gas, const double* V, double* out) {
+  const InstParams ip = params(gas, 5);
+  floor_apply(ip, V, out);
+}
+
+void core_floor_vjp(const double* gas, const double* V, const double* g, double* gV) {
+  const InstParams ip = params(gas, 5);
+  floor_vjp(ip, V, g, gV);
 }
 
 void core_riemann(const double* gas, int iters, const double* L, const double* R, double* F) {

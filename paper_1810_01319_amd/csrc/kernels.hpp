@@ -28,7 +28,7 @@ struct DevPlan {
 
 struct LaunchCfg {
   int refresh_block = 256;
-  int sweep_block = 128;
+  int sweep_block = 256;
   int cfl_block = 256;
   int reflux_block = 256;
   int sweep_mode[3] = {1, 0, 0};  // per axis: 0 = lane-per-pencil walk, 1 = LDS-staged tile

@@ -37,8 +37,10 @@ AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
 // g_q[5], g_c, g_ir -> g_U[5] (accumulated)
 AMR_HD inline void prim_vjp(const InstParams& ip, const double* U, const Prim& P, const double* gq, double gc,
                             double gir, double* gU) {
-  double gp = gq[4] + gc * ((ip.gamma * P.ir) / (2.0 * P.c));
-  gir += gc * ((ip.gamma * P.q[4]) / (2.0 * P.c));
+  // c = sqrt(gamma p / rho): dc = (gamma / 2c)(dp / rho + p d(1/rho))
+  const double h = (0.5 * ip.gamma) * gc / P.c;
+  double gp = gq[4] + h * P.ir;
+  gir += h * P.q[4];
   if (P.pfl) gp = 0.0;
   const double gpm = gp * ip.gm1;
   gU[4] += gpm;
@@ -251,14 +253,20 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
 
 // ---- two-shock Riemann solver -------------------------------------------
 
-// gF (flux) -> gL, gR (edge states rho,u,v,w,p; accumulated)
-AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
-                               double* gR) {
+// gF (flux) -> gL, gR (edge states rho,u,v,w,p; accumulated).  MAXIT bounds
+// ip.iters at compile time: with the loops unrolled the Newton history stays
+// in registers.  The forward part repeats riemann_flux's arithmetic exactly
+// (same branches); the reverse part evaluates each Newton evaluation's square
+// roots and reciprocals once and shares reciprocals between the derivative
+// terms.
+template <int MAXIT>
+AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
+                                 double* gR) {
   const double rL = L[0], uL = L[1], pL = L[4];
   const double rR = R[0], uR = R[1], pR = R[4];
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
   const int NI = ip.iters;
-  // ---- forward, keeping p* of every Newton step ----
+  // ---- forward, keeping p* of every Newton evaluation ----
   const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
   const double ipL = 1.0 / pL, ipR = 1.0 / pR;
   const double num0 = (CR * pL + CL * pR) - (CL * CR) * (uR - uL);
@@ -266,13 +274,16 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
   double ps = num0 / den0;
   const bool fl0 = ps < pfl;
   ps = fl0 ? pfl : ps;
-  double psv[65];
-  bool flv[65];
-  double WLw = 0, WRw = 0, iWL = 0, iWR = 0, iZL = 0, iZR = 0, usL = 0, usR = 0;
-  for (int it = 0;; it++) {
+  double psv[MAXIT + 1];
+  bool flv[MAXIT + 1];
+  double WLw = 0, WRw = 0, iWL = 0, iWR = 0, iZL = 0, iZR = 0, usL = 0, usR = 0, sLf = 1, sRf = 1;
+#pragma unroll
+  for (int it = 0; it <= MAXIT; it++) {
     psv[it] = ps;
-    WLw = CL * sqrt(1.0 + g1 * (ps * ipL - 1.0));
-    WRw = CR * sqrt(1.0 + g1 * (ps * ipR - 1.0));
+    sLf = sqrt(1.0 + g1 * (ps * ipL - 1.0));
+    sRf = sqrt(1.0 + g1 * (ps * ipR - 1.0));
+    WLw = CL * sLf;
+    WRw = CR * sRf;
     iWL = 1.0 / WLw;
     iWR = 1.0 / WRw;
     usL = uL - (ps - pL) * iWL;
@@ -335,7 +346,7 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
   if (left) { gL[2] += gvg; gL[3] += gwg; }
   else { gR[2] += gvg; gR[3] += gwg; }
   // ---- reverse: sampling ----
-  double grK = 0, guK = 0, gpK = 0, grs = 0, gus = 0, gps = 0, gvs = 0, girK = 0, gWK = 0, giWK = 0;
+  double grK = 0, guK = 0, gpK = 0, grs = 0, gus = 0, gps = 0, gvs = 0, girK = 0, giWK = 0;
   if (cse == 0) { grK += grg; guK += gug; gpK += gpg; }
   else if (cse == 1) { grs += grg; gus += gug; gps += gpg; }
   else {
@@ -344,51 +355,54 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
     gpK += gpg * (1.0 - xi); gps += gpg * xi;
     const double gxi = grg * (rs - rK) + gug * (us - uK) + gpg * (ps - pK);
     const double d = lh - lt;
-    const double glh = gxi * (-lt) / (d * d), glt = gxi * lh / (d * d);
+    const double gxd = gxi / (d * d);
+    const double glh = -gxd * lt, glt = gxd * lh;
     guK += glh;
     const double gcK = -s * glh;
     gus += glt;
     const double gcs = -s * glt;
-    gpK += gcK * ((gam * irK) / (2.0 * cK));
-    girK += gcK * ((gam * pK) / (2.0 * cK));
-    gps += gcs * ((gam * vs) / (2.0 * csr));
-    gvs += gcs * ((gam * ps) / (2.0 * csr));
+    // c = sqrt(gam p / rho): dc = (gam / 2c) (dp / rho + p d(1/rho))
+    const double hK = (0.5 * gam) * gcK / cK, hs = (0.5 * gam) * gcs / csr;
+    gpK += hK * irK;
+    girK += hK * pK;
+    gps += hs * vs;
+    gvs += hs * ps;
   }
-  (void)gWK;
   gvs += -grs * (rs * rs);
   girK += gvs;
-  gps += -gvs * (iWK * iWK);
-  gpK += gvs * (iWK * iWK);
+  const double iWK2 = iWK * iWK;
+  gps += -gvs * iWK2;
+  gpK += gvs * iWK2;
   giWK += -gvs * (ps - pK) * (2.0 * iWK);
   grK += -girK * (irK * irK);
   // star velocity u* = (iZR usL + iZL usR) / (iZL + iZR)
-  double gusL = gus * iZR / Dz, gusR = gus * iZL / Dz;
-  double giZR = gus * (usL - us) / Dz, giZL = gus * (usR - us) / Dz;
+  const double iDz = 1.0 / Dz;
+  double gusL = gus * iZR * iDz, gusR = gus * iZL * iDz;
+  double giZR = gus * (usL - us) * iDz, giZL = gus * (usR - us) * iDz;
   double giWL = left ? giWK : 0.0, giWR = left ? 0.0 : giWK;
   // side-K inputs
   double grL = 0, guL = 0, gpL = 0, grR = 0, guR = 0, gpR = 0;
   if (left) { grL += grK; guL += guK; gpL += gpK; }
   else { grR += grK; guR += guK; gpR += gpK; }
-  // ---- reverse through the Newton evaluations ----
+  // ---- reverse through the Newton evaluations, last first ----
+  // Evaluation at p: s = sqrt(1 + g1 (p/pK - 1)), 1/W = 1/(C s), q = C/W,
+  // 1/Z = (1/(2W))(1 + q^2), u*_K = u_K -+ (p - p_K)/W_K.
   double gCL = 0, gCR = 0, gipL = 0, gipR = 0;
-  double gps_cur = gps;  // gradient w.r.t. p* of the evaluation being reversed
-  for (int it = NI; it >= 0; it--) {
+  double gps_cur = gps;  // adjoint of the p* the evaluation being reversed used
+  double sl = sLf, sr = sRf, iwl = iWL, iwr = iWR;  // that evaluation's values
+#pragma unroll
+  for (int it = MAXIT; it >= 0; it--) {
+    if (it > NI) continue;
     const double p = psv[it];
-    const double aL = p * ipL - 1.0, aR = p * ipR - 1.0;
-    const double sL = sqrt(1.0 + g1 * aL), sR = sqrt(1.0 + g1 * aR);
-    const double Wl = CL * sL, Wr = CR * sR;
-    const double iwl = 1.0 / Wl, iwr = 1.0 / Wr;
     const double ql = CL * iwl, qr = CR * iwr;
-    // iZ = (0.5 iW)(1 + q^2)
     giWL += giZL * (0.5 * (1.0 + ql * ql));
-    double gql = giZL * ((0.5 * iwl) * (2.0 * ql));
+    const double gql = giZL * (iwl * ql);
     giWR += giZR * (0.5 * (1.0 + qr * qr));
-    double gqr = giZR * ((0.5 * iwr) * (2.0 * qr));
+    const double gqr = giZR * (iwr * qr);
     gCL += gql * iwl;
     giWL += gql * CL;
     gCR += gqr * iwr;
     giWR += gqr * CR;
-    // usL = uL - (p - pL) iWL ; usR = uR + (p - pR) iWR
     guL += gusL;
     gps_cur += -gusL * iwl;
     gpL += gusL * iwl;
@@ -397,39 +411,41 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
     gps_cur += gusR * iwr;
     gpR += -gusR * iwr;
     giWR += gusR * (p - pR);
-    // iW = 1/W, W = C s, s = sqrt(1 + g1 a), a = p ip - 1
+    // W = C s: dW = s dC + C ds; ds = g1 da / (2 s) with 1/s = C/W
     const double gWl = -giWL * (iwl * iwl), gWr = -giWR * (iwr * iwr);
-    gCL += gWl * sL;
-    gCR += gWr * sR;
-    const double gaL = (gWl * CL) / (2.0 * sL) * g1, gaR = (gWr * CR) / (2.0 * sR) * g1;
+    gCL += gWl * sl;
+    gCR += gWr * sr;
+    const double gaL = (0.5 * g1) * gWl * (CL * CL * iwl), gaR = (0.5 * g1) * gWr * (CR * CR * iwr);
     gps_cur += gaL * ipL + gaR * ipR;
     gipL += gaL * p;
     gipR += gaR * p;
     if (it == 0) break;
-    // p_it = p_{it-1} - (usR - usL)/(iZL + iZR) of evaluation it-1
+    // the previous evaluation, and the Newton update that produced p:
+    // p = p_prev - (u*_R - u*_L) / (1/Z_L + 1/Z_R)
+    const double pp = psv[it - 1];
+    sl = sqrt(1.0 + g1 * (pp * ipL - 1.0));
+    sr = sqrt(1.0 + g1 * (pp * ipR - 1.0));
+    iwl = 1.0 / (CL * sl);
+    iwr = 1.0 / (CR * sr);
     double gprev = 0.0;
     giZL = giZR = gusL = gusR = giWL = giWR = 0.0;
     if (!flv[it - 1]) {
-      const double pp = psv[it - 1];
-      const double bl = sqrt(1.0 + g1 * (pp * ipL - 1.0)), br = sqrt(1.0 + g1 * (pp * ipR - 1.0));
-      const double wl = 1.0 / (CL * bl), wr = 1.0 / (CR * br);
-      const double uls = uL - (pp - pL) * wl, urs = uR + (pp - pR) * wr;
-      const double zl = (0.5 * wl) * (1.0 + (CL * wl) * (CL * wl));
-      const double zr = (0.5 * wr) * (1.0 + (CR * wr) * (CR * wr));
-      const double D = zl + zr;
+      const double uls = uL - (pp - pL) * iwl, urs = uR + (pp - pR) * iwr;
+      const double zl = (0.5 * iwl) * (1.0 + (CL * iwl) * (CL * iwl));
+      const double zr = (0.5 * iwr) * (1.0 + (CR * iwr) * (CR * iwr));
+      const double iD = 1.0 / (zl + zr);
+      const double gD = gps_cur * iD;
       gprev = gps_cur;
-      gusR = -gps_cur / D;
-      gusL = gps_cur / D;
-      const double gD = gps_cur * (urs - uls) / (D * D);
-      giZL = gD;
-      giZR = gD;
+      gusR = -gD;
+      gusL = gD;
+      giZL = giZR = gD * (urs - uls) * iD;
     }
     gps_cur = gprev;
   }
   // first guess p* = num0 / den0 (unless floored)
   if (!fl0) {
     const double gnum = gps_cur / den0;
-    const double gden = -gps_cur * (num0 / den0) / den0;
+    const double gden = -gnum * (num0 / den0);
     gCR += gnum * (pL - CL * (uR - uL)) + gden;
     gCL += gnum * (pR - CR * (uR - uL)) + gden;
     gpL += gnum * CR;
@@ -439,12 +455,66 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
   }
   gpL += -gipL * (ipL * ipL);
   gpR += -gipR * (ipR * ipR);
-  gpL += gCL * ((gam * rL) / (2.0 * CL));
-  grL += gCL * ((gam * pL) / (2.0 * CL));
-  gpR += gCR * ((gam * rR) / (2.0 * CR));
-  grR += gCR * ((gam * pR) / (2.0 * CR));
+  // C = sqrt(gam p rho): dC = (gam / 2C)(rho dp + p drho)
+  const double hL = (0.5 * gam) * gCL / CL, hR = (0.5 * gam) * gCR / CR;
+  gpL += hL * rL;
+  grL += hL * pL;
+  gpR += hR * rR;
+  grR += hR * pR;
   gL[0] += grL; gL[1] += guL; gL[4] += gpL;
   gR[0] += grR; gR[1] += guR; gR[4] += gpR;
+}
+
+AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
+                               double* gR) {
+  riemann_vjp_n<64>(ip, L, R, gF, gL, gR);
+}
+
+// ---- post-update floors ----------------------------------------------------
+
+// The floors the update applies to a cell's new conserved values V (pencil
+// roles rho, m_n, m_t1, m_t2, E): rho is raised to the density floor, then E
+// is reset to the floor pressure's energy if the pressure fell below it.
+AMR_HD inline void floor_apply(const InstParams& ip, const double* V, double* out) {
+  double r0 = V[0];
+  if (r0 < ip.rho_floor) r0 = ip.rho_floor;
+  const double jr = 1.0 / r0;
+  const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
+  const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
+  double e = V[4];
+  if (ip.gm1 * (e - ke) < ip.p_floor) e = ip.p_floor * ip.inv_gm1 + ke;
+  out[0] = r0;
+  out[1] = V[1];
+  out[2] = V[2];
+  out[3] = V[3];
+  out[4] = e;
+}
+
+// g (adjoint of the floored values) -> gV (adjoint of V); may alias g.
+// With the pressure floor active E = const + |m|^2 / (2 rho).
+AMR_HD inline void floor_vjp(const InstParams& ip, const double* V, const double* g, double* gV) {
+  const bool rfl = V[0] < ip.rho_floor;
+  const double r0 = rfl ? ip.rho_floor : V[0];
+  const double jr = 1.0 / r0;
+  const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
+  const double K = (a1 * a1 + a2 * a2) + a3 * a3;
+  const double ke = (0.5 * r0) * K;
+  const bool pfl = ip.gm1 * (V[4] - ke) < ip.p_floor;
+  const double g4 = g[4];
+  double gr = g[0];
+  if (pfl) {
+    gV[1] = g[1] + g4 * a1;
+    gV[2] = g[2] + g4 * a2;
+    gV[3] = g[3] + g4 * a3;
+    gr += -0.5 * K * g4;
+    gV[4] = 0.0;
+  } else {
+    gV[1] = g[1];
+    gV[2] = g[2];
+    gV[3] = g[3];
+    gV[4] = g4;
+  }
+  gV[0] = rfl ? 0.0 : gr;
 }
 
 // ---- one pencil ------------------------------------------------------------
@@ -456,7 +526,9 @@ constexpr int kMaxPencil = 38;
 // adjoint of the sweep's output on the same cells, on exit the adjoint of
 // its input (cells outside [lo, hi) are not updated by the sweep and keep
 // their identity part).  gface_lo/hi: adjoints of the fluxes at j = lo-1/2
-// and hi-1/2 stored for reflux (nullptr if none).
+// and hi-1/2 stored for reflux (nullptr if none).  Reference composition for
+// the host tests: the gfx950 kernel applies the same element products in
+// LDS-staged phases.
 AMR_HD inline void pencil_vjp(const InstParams& ip, double nu, int n, int lo, int hi, const double* U, double* lam,
                               const double* gface_lo, const double* gface_hi) {
   Prim P[kMaxPencil];
@@ -495,7 +567,20 @@ AMR_HD inline void pencil_vjp(const InstParams& ip, double nu, int n, int lo, in
   double gq[kMaxPencil][5] = {}, gc[kMaxPencil] = {}, gir[kMaxPencil] = {};
   double gdl[kMaxPencil][5] = {}, gfa[kMaxPencil][5] = {}, gfl[kMaxPencil] = {};
   double gWL[kMaxPencil][5] = {}, gWR[kMaxPencil][5] = {};
-  // update U_j -= nu (F_{j+1/2} - F_{j-1/2}) on [lo, hi); faces for reflux
+  // update U_j -= nu (F_{j+1/2} - F_{j-1/2}) on [lo, hi), then floors: the
+  // adjoint of the pre-floor values replaces lam there
+  for (int j = lo; j < hi; j++) {
+    double F0[5], F1[5], V[5], g[5];
+    riemann_flux(ip, WL[j - 1], WR[j], F0);
+    riemann_flux(ip, WL[j], WR[j + 1], F1);
+    for (int v = 0; v < 5; v++) {
+      V[v] = U[v * n + j] - nu * (F1[v] - F0[v]);
+      g[v] = lam[v * n + j];
+    }
+    floor_vjp(ip, V, g, g);
+    for (int v = 0; v < 5; v++) lam[v * n + j] = g[v];
+  }
+  // faces for reflux
   for (int j = lo - 1; j <= hi - 1; j++) {
     double gF[5];
     for (int v = 0; v < 5; v++) {

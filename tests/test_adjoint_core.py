@@ -143,3 +143,44 @@ def test_pencil_vjp_central_differences_per_cell(core):
                 e[v, j] = h
                 fd = (phi(U0 + e) - phi(U0 - e)) / (2 * h)
                 assert abs(fd - adj[v, j]) <= 1e-5 * max(1.0, abs(fd)), (kind, v, j, adj[v, j], fd)
+
+
+FLOOR_GAS = np.array([1.4, 0.1, 0.05])
+FLOOR_CASES = [
+    ("none", [1.0, 0.3, -0.2, 0.1, 2.0]),
+    ("density", [0.05, 0.02, 0.01, -0.03, 0.5]),
+    ("pressure", [1.0, 0.9, 0.4, -0.3, 0.6]),
+    ("both", [0.07, 0.2, -0.1, 0.15, 0.3]),
+]
+
+
+@pytest.mark.parametrize("k", range(len(FLOOR_CASES)))
+def test_floor_vjp_matches_finite_differences(core, k):
+    """Post-update floors of one cell: which floor is active is checked from
+    the forward's output, then every adjoint entry against a central
+    difference (the cases sit away from the floors' switch points)."""
+    name, V0 = FLOOR_CASES[k]
+    V0 = np.array(V0)
+    core.core_floor.argtypes = [P, P, P]
+    core.core_floor_vjp.argtypes = [P, P, P, P]
+
+    def fwd(V):
+        out = np.zeros(5)
+        core.core_floor(ptr(FLOOR_GAS), ptr(np.ascontiguousarray(V)), ptr(out))
+        return out
+
+    out = fwd(V0)
+    rfl = out[0] == FLOOR_GAS[1]
+    ke = 0.5 * (out[1] ** 2 + out[2] ** 2 + out[3] ** 2) / out[0]
+    pfl = abs(0.4 * (out[4] - ke) - FLOOR_GAS[2]) < 1e-14
+    assert (rfl, pfl) == {"none": (False, False), "density": (True, False),
+                          "pressure": (False, True), "both": (True, True)}[name]
+    rng = np.random.default_rng(k)
+    g = rng.normal(size=5)
+    gV = np.zeros(5)
+    core.core_floor_vjp(ptr(FLOOR_GAS), ptr(V0), ptr(g), ptr(gV))
+    for v in range(5):
+        e = np.zeros(5)
+        e[v] = 1e-7
+        fd = g @ (fwd(V0 + e) - fwd(V0 - e)) / 2e-7
+        assert abs(fd - gV[v]) <= 1e-7 * max(1.0, abs(fd)), (name, v, gV[v], fd)
