@@ -120,14 +120,15 @@ def batched_compare(steps: int, n_inst: int = 256):
             U[bm.first_leaf[i]:bm.first_leaf[i + 1], :, g3:g3 + bm.N, g3:g3 + bm.N, g3:g3 + bm.N] = \
                 torch.from_numpy(a).to(bm.device)
         dt = bm.dt_tensor()
-        # eager batched steps
+        # eager batched steps (fewer: for reference only)
+        eager = min(steps, 20)
         bm.step(U, dt, 0)
         side.synchronize()
         t0 = time.perf_counter()
-        for k in range(1, steps + 1):
+        for k in range(1, eager + 1):
             bm.step(U, dt, k)
         side.synchronize()
-        out["batched_eager"] = cells * steps / (time.perf_counter() - t0)
+        out["batched_eager"] = cells * eager / (time.perf_counter() - t0)
         # graph of two steps
         g = bm.graph(U, dt, first_step=0)
         g.launch()
@@ -235,11 +236,40 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
             "adjoint_phases_ms_per_step": phases}
 
 
+def step_bytes_per_block(N: int) -> int:
+    """Algorithmic HBM bytes of one step of one block: CFL read, refresh,
+    three sweeps (reflux is negligible)."""
+    from paper_1810_01319_amd import costs
+
+    return costs.cfl_bytes_per_block(N) + costs.refresh_bytes_per_block(N) + costs.sweep_bytes_per_block_step(N)
+
+
+def cpu_baseline_adaptive(spec_tile, steps: int = 9):
+    """The oracle on a 4^3-octree tile of the adaptive workload (same block
+    size, levels, thresholds and interval; remesh before steps 4 and 8)."""
+    from oracle import oracle as O
+    from paper_1810_01319_amd import inputs as I
+
+    m = O.OracleMesh(**spec_tile.kwargs())
+    m.set_active(I.blasts_state(spec_tile, m.keys))
+    cells = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if k > 0 and k % 4 == 0:
+            m, _ = m.remesh(0.3, 0.1, 10 ** 9)
+        m.step(k)
+        cells += m.nleaf * spec_tile.block_cells ** 3
+    t = time.perf_counter() - t0
+    return {"value": cells / t, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} steps incl. 2 remeshes of a 4^3-octree tile of the same workload "
+                      f"({cells} cell-updates), {t:.1f} s"}
+
+
 def run_adaptive(args, spec, desc):
     """The large adaptive workload: remesh included in the timed region."""
     import torch
 
-    from paper_1810_01319_amd import adaptive, autotune, costs
+    from paper_1810_01319_amd import _lib, adaptive, autotune
     from paper_1810_01319_amd.mesh import Mesh
     from paper_1810_01319_amd import inputs as I
 
@@ -254,44 +284,66 @@ def run_adaptive(args, spec, desc):
     torch.cuda.synchronize()
     leaves_start = int(mesh.nleaf)
     cells_per_step = []
+    bytes_per_step = []
     stats = []
+    phases = {p: 0.0 for p in _lib.PHASES if not p.startswith("adj_")}
 
-    t_remesh = [0.0]
+    def collect(mm):
+        prof = mm.profile_read()
+        mm.profile(False)
+        for p in phases:
+            phases[p] += prof[p][0]
 
-    t0 = time.perf_counter()
-    step_ms = 0.0
+    t_remesh = 0.0
     N = spec.block_cells
     m, u = mesh, U
     del mesh, U  # a remesh may hold only the old and the new state
+    m.profile(True)
+    t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         if k > 0 and k % 4 == 0:
             torch.cuda.synchronize()
             tr = time.perf_counter()
             new, un, st = m.remesh(u, 0.3, 0.1, cap, out=pool.other())
-            pool.swap()
+            if new is not m:
+                pool.swap()
+                collect(m)
+                new.profile(True)
             m, u = new, un
             stats.append(st)
             torch.cuda.synchronize()
-            t_remesh[0] += time.perf_counter() - tr
+            t_remesh += time.perf_counter() - tr
         dt = torch.zeros(1, dtype=torch.float64, device=m.device)
         m.step(u, dt, k)
         cells_per_step.append(m.nleaf * N ** 3)
+        bytes_per_step.append(m.nleaf * step_bytes_per_block(N))
         if (k - args.warmup) % 10 == 0:
             print(f"[bench] step {k} leaves {m.nleaf}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    collect(m)
     total = float(sum(cells_per_step))
-    return {
+    hydro_s = wall - t_remesh
+    out = {
         "metric": METRIC, "value": total / wall, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "leaves_start": leaves_start, "leaves_end": int(m.nleaf),
                    "max_blocks": cap, "parallelism": "single GPU"},
-        "without_remesh": total / (wall - t_remesh[0]),
-        "remesh_s": t_remesh[0],
+        "without_remesh": total / hydro_s,
+        "remesh_s": t_remesh,
+        "remeshes": len(stats),
         "remesh_stats_last": stats[-1] if stats else None,
         "refused_total": int(sum(s["refused"] for s in stats)),
+        "phases_ms_per_step": {p: round(v / args.steps, 3) for p, v in phases.items()},
+        "step_hbm_algorithmic": {"GB/s": sum(bytes_per_step) / hydro_s / 1e9, "peak": PEAK_HBM_GBS,
+                                 "frac": sum(bytes_per_step) / hydro_s / 1e9 / PEAK_HBM_GBS},
     }
+    if not args.no_cpu_baseline:
+        del u, pool
+        tile = I.blasts_spec(root=4, block_cells=spec.block_cells, levels=spec.max_level)
+        out["cpu_baseline"] = cpu_baseline_adaptive(tile)
+    return out
 
 
 def main():
@@ -303,7 +355,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the sweep launch shapes first")
-    ap.add_argument("--batch-steps", type=int, default=20, help="steps of the batched comparison (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="steps of the batched comparison, graph and one-mesh-per-launch (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="steps of the adjoint comparison (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")

@@ -51,7 +51,8 @@ def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope
             if pool is not None:
                 cap = min(cap, pool.capacity)
                 new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap, out=pool.other())
-                pool.swap()
+                if new is not mesh:
+                    pool.swap()
             else:
                 new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap)
             mesh, U = new, Un

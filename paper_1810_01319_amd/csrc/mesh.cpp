@@ -396,6 +396,10 @@ RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<
   std::vector<Key> journal, stack;
   for (const Cand& c : cand) {
     if (T.state(c.k.l, c.k.i, c.k.j, c.k.k) != Octree::LEAF) continue;
+    if (leaves + 7 > max_blocks) {  // any closure adds >= 7 leaves: refused without trying
+      res.refused++;
+      continue;
+    }
     journal.clear();
     stack.assign(1, c.k);
     bool ok = true;

@@ -190,13 +190,20 @@ class Mesh:
                out: torch.Tensor = None):
         """Returns (new Mesh, new state, stats dict).  Refreshes U's ghosts.
         `out`, if given, is a flat float64 device buffer of at least
-        max_blocks blocks that receives the new state (no allocation)."""
+        max_blocks blocks that receives the new state (no allocation).  When
+        nothing is refined or coarsened the leaf set and its order are
+        unchanged: this mesh and U itself are returned (no migration)."""
         self._check_state(U)
         prm = _lib.RemeshParams(float(refine_slope), float(coarsen_slope), int(max_blocks))
         st = _lib.RemeshStats()
         h = ctypes.c_void_p()
         check(lib().amr_remesh_plan(self._h, _ptr(U), ctypes.byref(prm), ctypes.byref(h), ctypes.byref(st),
                                     _stream()))
+        stats = {"refined": int(st.refined), "coarsened": int(st.coarsened), "refused": int(st.refused),
+                 "n_leaves": int(st.n_leaves)}
+        if stats["refined"] == 0 and stats["coarsened"] == 0:
+            lib().amr_mesh_destroy(h)
+            return self, U, stats
         new = Mesh(device=self.device, _handle=h, **self.params)
         new.set_launch(**self.get_launch())
         # ghosts are scratch that the next refresh fills; migration writes
@@ -214,8 +221,6 @@ class Mesh:
             torch.cuda.empty_cache()
             Un = torch.empty(shape, dtype=torch.float64, device=self.device)
         check(lib().amr_remesh_apply(new._h, _ptr(U), _ptr(Un), _stream()))
-        stats = {"refined": int(st.refined), "coarsened": int(st.coarsened), "refused": int(st.refused),
-                 "n_leaves": int(st.n_leaves)}
         return new, Un, stats
 
     # launch shapes ----------------------------------------------------

@@ -235,18 +235,20 @@ def _oracle_adaptive(om, steps, thr_r, thr_c, cap, interval=4):
     return om, dts, stats
 
 
-@pytest.mark.parametrize("root,N,levels,cap_extra", [(3, 8, 2, 10 ** 6), (3, 16, 3, 10 ** 6), (3, 8, 3, 60)])
-def test_adaptive_blasts_parity(root, N, levels, cap_extra):
+@pytest.mark.parametrize("root,N,levels,cap_extra,steps", [
+    (3, 8, 2, 10 ** 6, 13), (3, 16, 3, 10 ** 6, 13), (3, 8, 3, 60, 13),
+    (4, 32, 3, 10 ** 6, 9),  # the large adaptive workload's 4^3-octree tile: remesh before steps 4 and 8
+])
+def test_adaptive_blasts_parity(root, N, levels, cap_extra, steps):
     """Blasts with remesh every 4 steps: indicator, decisions, migrated data
     and the following steps all bitwise equal to the oracle."""
     from paper_1810_01319_amd import adaptive
 
     spec = I.blasts_spec(root=root, block_cells=N, levels=levels)
-    say(f"adaptive blasts root={root} N={N} levels={levels}")
+    say(f"adaptive blasts root={root} N={N} levels={levels} steps={steps}")
     om, gm, perm = pair(spec)
     U = load(om, gm, perm, I.blasts_state(spec, gm.keys))
     cap = gm.nleaf + cap_extra
-    steps = 13
     gm2, U2, dts, gst = adaptive.run(gm, U, steps, max_blocks=cap)
     om2, odts, ost = _oracle_adaptive(om, steps, 0.3, 0.1, cap)
     assert [float(d.cpu()[0]) for d in dts] == odts
