@@ -161,8 +161,10 @@ def batched_compare(steps: int, n_inst: int = 256):
 def adjoint_compare(steps: int = 10, reps: int = 3):
     """The differentiation workload (4^3 root octrees of 32^3 cells, the
     central 2^3 roots refined once: 120 leaves, 3.9M cells; density misfit
-    after `steps` steps): wall time of the plain forward, of the
-    checkpointing forward and of the hand-written adjoint, best of `reps`."""
+    after `steps` steps): wall time of the plain forward, and of the
+    differentiable forward and the hand-written adjoint in both modes
+    (recording the sweep inputs, or checkpointing and recomputing them),
+    best of `reps`."""
     import torch
 
     from paper_1810_01319_amd import adjoint as A
@@ -193,47 +195,53 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
         return best, r
 
     t_plain, _ = timed(plain)
-    state = {}
+    out = {"workload": "grf-density-misfit: 4^3 root octrees x 32^3 cells, central 2^3 roots refined once "
+                       f"(120 leaves, 3.9M cells), {steps} steps, gamma 5/3, periodic",
+           "steps": steps, "forward_ms": t_plain * 1e3}
+    for record in (True, False):
+        state = {}
 
-    def fwd():
-        r = base[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N].clone().requires_grad_(True)
-        U = base.clone()
-        U[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N] = r
-        L = A.density_misfit(m, A.run_steps(U, m, steps), target)
-        state["L"], state["r"] = L, r
-        return L
+        def fwd():
+            r = base[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N].clone().requires_grad_(True)
+            U = base.clone()
+            U[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N] = r
+            L = A.density_misfit(m, A.run_steps(U, m, steps, record=record), target)
+            state["L"], state["r"] = L, r
+            return L
 
-    def bwd():
-        state["L"].backward()
-        return state["r"].grad
-
-    best_f = best_b = None
-    for i in range(reps + 1):  # first pass warms up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        best_f = best_b = None
+        for i in range(reps + 1):  # first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fwd()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            state["L"].backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if i > 0:
+                best_f = t1 - t0 if best_f is None else min(best_f, t1 - t0)
+                best_b = t2 - t1 if best_b is None else min(best_b, t2 - t1)
+        # one more adjoint pass with per-phase events
         fwd()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        bwd()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        if i > 0:
-            best_f = t1 - t0 if best_f is None else min(best_f, t1 - t0)
-            best_b = t2 - t1 if best_b is None else min(best_b, t2 - t1)
-    # one more adjoint pass with per-phase HIP events
-    fwd()
-    torch.cuda.synchronize()
-    m.profile(True)
-    bwd()
-    prof = m.profile_read()
-    m.profile(False)
-    phases = {p: round(v[0] / steps, 4) for p, v in prof.items() if p.startswith("adj_")}
-    return {"workload": "grf-density-misfit: 4^3 root octrees x 32^3 cells, central 2^3 roots refined once "
-                        f"(120 leaves, 3.9M cells), {steps} steps, gamma 5/3, periodic",
-            "steps": steps, "forward_ms": t_plain * 1e3, "forward_checkpointing_ms": best_f * 1e3,
-            "adjoint_ms": best_b * 1e3, "adjoint_over_forward": best_b / t_plain,
-            "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain,
-            "adjoint_phases_ms_per_step": phases}
+        m.profile(True)
+        state["L"].backward()
+        prof = m.profile_read()
+        m.profile(False)
+        res = {"forward_ms": best_f * 1e3, "adjoint_ms": best_b * 1e3,
+               "adjoint_over_forward": best_b / t_plain,
+               "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain,
+               "adjoint_phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items()
+                                              if p.startswith("adj_")}}
+        if record:
+            out["adjoint_ms"] = res["adjoint_ms"]
+            out["adjoint_over_forward"] = res["adjoint_over_forward"]
+            out["recording"] = res
+        else:
+            out["recomputing"] = res
+        del state
+    return out
 
 
 def step_bytes_per_block(N: int) -> int:

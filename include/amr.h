@@ -84,6 +84,7 @@ typedef struct {
   int32_t levels[8];       /* leaves per level */
   int64_t n_instances;     /* meshes in the handle (1 unless batched) */
   int64_t adjoint_scratch_bytes; /* scratch of amr_hydro_step_adjoint */
+  int64_t adjoint_face_bytes;    /* scratch of amr_hydro_step_adjoint_recorded */
 } amr_mesh_info_t;
 
 /* Build the balanced array-of-octrees: roots, then each refine entry in
@@ -156,19 +157,40 @@ amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64
 amr_status amr_graph_launch(amr_graph* graph, void* stream);
 amr_status amr_graph_destroy(amr_graph* graph);
 
+/* One hydro step (as amr_hydro_step, bitwise the same result) that keeps
+ * what its adjoint needs, for reverse-mode differentiation without
+ * recomputation: U_dev's ghosts are refreshed in place and U_dev is otherwise
+ * not modified (it becomes the first sweep's input S0); the first and second
+ * sweeps write their results to S1_dev and S2_dev, the third sweep and the
+ * reflux write the new state to U_out_dev (field_bytes each, all distinct;
+ * ghost cells of U_out_dev are unspecified: the next step's refresh fills
+ * them); floors_dev (one uint64 on the device) receives the number of
+ * post-update floor resets of this step.  dt_dev receives the CFL dt. */
+amr_status amr_hydro_step_record(amr_mesh* mesh, double* U_dev, double* dt_dev, double* S1_dev, double* S2_dev,
+                                 double* U_out_dev, uint64_t* floors_dev, int64_t step_index, void* stream);
+
 /* Adjoint of one hydro step with its dt frozen (Sec. II-C Method, the
  * refresh of Sec. II-B): on entry lam_dev holds dL/dU after the step (ghost
  * entries zero), on exit dL/dU before it (ghost entries zero).  U_in_dev is
  * the state the forward step started from (a checkpoint), dt_dev the dt it
  * used, step_index its index (sweep order).  The step's sweep inputs are
- * recomputed into scratch_dev (adjoint_scratch_bytes of amr_mesh_info); every
- * limiter, flattening, wave-direction, floor and Riemann branch is taken as
- * the forward took it, and the result is the exact vector-Jacobian product of
- * the computed step on those branches (post-update floors included).  The
- * refresh transpose scatter-adds with FP64 atomics (sums in unspecified
- * order).  Errors: AMR_E_INVALID if riemann_iters exceeds 8. */
+ * recomputed into scratch_dev (adjoint_scratch_bytes of amr_mesh_info; the
+ * mesh's floor-reset count is left unchanged); every limiter, flattening,
+ * wave-direction, floor and Riemann branch is taken as the forward took it,
+ * and the result is the exact vector-Jacobian product of the computed step
+ * on those branches (post-update floors included).  The refresh transpose
+ * scatter-adds with FP64 atomics (sums in unspecified order).
+ * Errors: AMR_E_INVALID if riemann_iters exceeds 8. */
 amr_status amr_hydro_step_adjoint(amr_mesh* mesh, const double* U_in_dev, const double* dt_dev, double* lam_dev,
                                   void* scratch_dev, int64_t step_index, void* stream);
+
+/* The same adjoint from what amr_hydro_step_record kept: S0_dev (its U_dev
+ * after the call), S1_dev, S2_dev, dt_dev and floors_dev (zero resets lets
+ * the sweeps' transposes skip the floors).  scratch_dev: adjoint_face_bytes
+ * of amr_mesh_info.  Nothing is recomputed. */
+amr_status amr_hydro_step_adjoint_recorded(amr_mesh* mesh, const double* S0_dev, const double* S1_dev,
+                                           const double* S2_dev, const double* dt_dev, const uint64_t* floors_dev,
+                                           double* lam_dev, void* scratch_dev, int64_t step_index, void* stream);
 
 /* Transpose of amr_refresh_ghosts at the refreshed state U_ref_dev (its
  * minmod slope choices): on entry lam_dev holds an adjoint on every cell,

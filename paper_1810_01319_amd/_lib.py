@@ -55,6 +55,7 @@ class MeshInfo(ctypes.Structure):
         ("levels", ctypes.c_int32 * 8),
         ("n_instances", ctypes.c_int64),
         ("adjoint_scratch_bytes", ctypes.c_int64),
+        ("adjoint_face_bytes", ctypes.c_int64),
     ]
 
 
@@ -96,6 +97,8 @@ SIGNATURES = {
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_adjoint": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
+    "amr_hydro_step_record": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I64, _P]),
+    "amr_hydro_step_adjoint_recorded": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P]),
     "amr_refresh_ghosts_adjoint": (_I32, [_P, _P, _P, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "amr_remesh_plan": (_I32, [_P, _P, ctypes.POINTER(RemeshParams), ctypes.POINTER(_P),

@@ -1,8 +1,8 @@
 """Differentiable hydro steps: a torch.autograd.Function whose forward runs K
-steps of the HIP path keeping a checkpoint of the state before every step,
-and whose backward runs the hand-written adjoint of each step (HIP kernels,
-dt of every step frozen at its forward value) from the last step to the
-first."""
+steps of the HIP path keeping what each step's adjoint needs (the step's
+sweep inputs, or a checkpoint of the state before it), and whose backward
+runs the hand-written adjoint of each step (HIP kernels, dt of every step
+frozen at its forward value) from the last step to the first."""
 from __future__ import annotations
 
 import torch
@@ -18,18 +18,32 @@ def active_mask(mesh) -> torch.Tensor:
 
 
 class HydroSteps(torch.autograd.Function):
-    """U_K = step_{K-1}(... step_0(U_0)); gradients flow to U_0's active cells."""
+    """U_K = step_{K-1}(... step_0(U_0)); gradients flow to U_0's active cells.
+
+    record=True keeps, for every step, its refreshed input and the inputs of
+    its second and third sweeps (three states per step, no copies: the
+    forward writes them as it goes) and the step's floor-reset count; the
+    backward then recomputes nothing.  record=False keeps one checkpoint per
+    step and recomputes the refresh and the first two sweeps in the backward.
+    Ghost cells of the returned state are unspecified with record=True."""
 
     @staticmethod
-    def forward(ctx, U0, mesh, steps: int, start: int = 0):
+    def forward(ctx, U0, mesh, steps: int, start: int = 0, record: bool = True):
         U = U0.detach().clone()
-        ckpts, dts = [], []
+        saved, dts = [], []
         for k in range(start, start + steps):
-            ckpts.append(U.clone())
             dt = mesh.dt_tensor()
-            mesh.step(U, dt, k)
+            if record:
+                S1, S2, Uo = (torch.empty_like(U) for _ in range(3))
+                floors = torch.empty(1, dtype=torch.int64, device=U.device)
+                mesh.step_record(U, dt, S1, S2, Uo, floors, k)
+                saved.append((U, S1, S2, floors))
+                U = Uo
+            else:
+                saved.append(U.clone())
+                mesh.step(U, dt, k)
             dts.append(dt)
-        ctx.mesh, ctx.ckpts, ctx.dts, ctx.start = mesh, ckpts, dts, start
+        ctx.mesh, ctx.saved, ctx.dts, ctx.start, ctx.record = mesh, saved, dts, start, record
         return U
 
     @staticmethod
@@ -37,14 +51,20 @@ class HydroSteps(torch.autograd.Function):
         mesh = ctx.mesh
         lam = gU.detach().clone().contiguous()
         lam[:, :, ~active_mask(mesh)] = 0.0  # ghost values of U_K influence nothing
-        scratch = mesh.adjoint_scratch()
-        for i in range(len(ctx.ckpts) - 1, -1, -1):
-            mesh.step_adjoint(ctx.ckpts[i], ctx.dts[i], lam, scratch, ctx.start + i)
-        return lam, None, None, None
+        if ctx.record:
+            scratch = mesh.adjoint_face_scratch()
+            for i in range(len(ctx.saved) - 1, -1, -1):
+                S0, S1, S2, floors = ctx.saved[i]
+                mesh.step_adjoint_recorded(S0, S1, S2, ctx.dts[i], floors, lam, scratch, ctx.start + i)
+        else:
+            scratch = mesh.adjoint_scratch()
+            for i in range(len(ctx.saved) - 1, -1, -1):
+                mesh.step_adjoint(ctx.saved[i], ctx.dts[i], lam, scratch, ctx.start + i)
+        return lam, None, None, None, None
 
 
-def run_steps(U0: torch.Tensor, mesh, steps: int, start: int = 0) -> torch.Tensor:
-    return HydroSteps.apply(U0, mesh, steps, start)
+def run_steps(U0: torch.Tensor, mesh, steps: int, start: int = 0, record: bool = True) -> torch.Tensor:
+    return HydroSteps.apply(U0, mesh, steps, start, record)
 
 
 def density_misfit(mesh, U: torch.Tensor, target_rho: torch.Tensor) -> torch.Tensor:

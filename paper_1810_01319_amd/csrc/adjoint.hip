@@ -74,21 +74,27 @@ __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__
 // its intermediates kept in LDS; the reverse phases then run in the opposite
 // order, each cell gathering what its neighbours' products send it, so no
 // two threads ever add to the same entry.
-template <int N>
+// Tile shape per block size and axis (measured on gfx950: x sweeps, whose
+// tiles are contiguous rows, run best with smaller tiles).
+template <int N, int DIR>
 struct AdjShape {
   static constexpr int M = N + 2 * G;
-  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : 5);  // pencils per tile
-  static constexpr int T = R * M;                               // cells per tile
+  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : (DIR == 0 ? 3 : 5));  // pencils per tile
+  static constexpr int T = R * M;                                              // cells per tile
   static constexpr int WG = ((T + 63) / 64) * 64;
 };
 
-template <int N, int DIR>
-__global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* __restrict__ Uin,
-                                                                  double* __restrict__ lam,
-                                                                  const double* __restrict__ dtv, DevPlan P,
-                                                                  const double* __restrict__ gfaces, int loA,
-                                                                  int nA, int loB, int nB) {
-  using S = AdjShape<N>;
+// FLOORS: the variant with the post-update floors' products (and the flux
+// recompute that detects them).  Both variants are launched; each returns at
+// once unless the forward step's floor-reset count (null: unknown) selects it.
+// Registers are capped for 3 waves per SIMD (a few bytes of spill cost less
+// than the lost occupancy).
+template <int N, int DIR, bool FLOORS>
+__global__ void __launch_bounds__((AdjShape<N, DIR>::WG)) __attribute__((amdgpu_waves_per_eu(3)))
+sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const double* __restrict__ dtv, DevPlan P,
+              const double* __restrict__ gfaces, const unsigned long long* __restrict__ floors, int loA, int nA,
+              int loB, int nB) {
+  using S = AdjShape<N, DIR>;
   constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int A = DIR == 0 ? 1 : 0;
@@ -126,39 +132,39 @@ __global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* _
   const bool traced = live && c >= 2 && c <= M - 3;
   const bool faced = live && c >= 2 && c <= M - 4;
   const bool active = live && c >= G && c < G + N;
+  if ((floors == nullptr || *floors != 0) != FLOORS) return;  // uniform over the grid
 
   // ---- forward recompute ----
-  double q[5] = {0, 0, 0, 0, 0}, cs = 0, ir = 0;
+  // Between phases only adjoint accumulators stay in registers: primitives
+  // are read back from Ps, c and 1/rho wait in Fl until the trace adjoint,
+  // the flattening is recomputed where needed, and the floor-free variant
+  // keeps the left states in Xs (free between the face values and the trace
+  // adjoint).
   if (live) {
     double u5[5];
 #pragma unroll
     for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
     const Prim Pr = prim_fwd(ip, u5);
 #pragma unroll
-    for (int v = 0; v < 5; v++) {
-      q[v] = Pr.q[v];
-      Ps[v][i] = q[v];
-    }
-    cs = Pr.c;
-    ir = Pr.ir;
+    for (int v = 0; v < 5; v++) Ps[v][i] = Pr.q[v];
+    Fl[0][i] = Pr.c;
+    Fl[1][i] = Pr.ir;
   }
   __syncthreads();
   if (live && c >= 1 && c <= M - 2) {
 #pragma unroll
-    for (int v = 0; v < 5; v++) Xs[v][i] = mc_slope(Ps[v][i - NS], q[v], Ps[v][i + NS]);
+    for (int v = 0; v < 5; v++) Xs[v][i] = mc_slope(Ps[v][i - NS], Ps[v][i], Ps[v][i + NS]);
   }
   __syncthreads();
   if (live && c >= 1 && c <= M - 3) {
 #pragma unroll
-    for (int v = 0; v < 5; v++) Ys[v][i] = 0.5 * (q[v] + Ps[v][i + NS]) - (Xs[v][i + NS] - Xs[v][i]) * sixth;
+    for (int v = 0; v < 5; v++)
+      Ys[v][i] = 0.5 * (Ps[v][i] + Ps[v][i + NS]) - (Xs[v][i + NS] - Xs[v][i]) * sixth;
   }
   __syncthreads();
-  // flattening: coefficient f, whether it is interior to its clamps (fact),
-  // and the pressure-jump ratio
-  double f = 0, rr = 0, dp2 = 0;
-  bool fact = false;
-  double WL[5] = {0, 0, 0, 0, 0};
-  if (traced) {
+  // flattening of the own cell: coefficient f, whether it is interior to its
+  // clamps (fact), the pressure-jump ratio and its denominator
+  auto flattening = [&](double& f, double& rr, double& dp2, bool& fact) {
     const double pp1 = Ps[4][i + NS], pm1 = Ps[4][i - NS];
     const double dp1 = pp1 - pm1;
     const double pmin = pp1 < pm1 ? pp1 : pm1;
@@ -170,50 +176,68 @@ __global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* _
     ft = ft < 1.0 ? ft : 1.0;
     ft = ft > 0.0 ? ft : 0.0;
     f = shock ? ft : 0.0;
+  };
+  double WL[5] = {0, 0, 0, 0, 0};  // held in registers by the floor variant only
+  if (traced) {
+    double f, rr, dp2;
+    bool fact;
+    flattening(f, rr, dp2, fact);
     Par pa[5];
 #pragma unroll
-    for (int v = 0; v < 5; v++) pa[v] = parabola(q[v], Ys[v][i - NS], Ys[v][i], f, sixth);
+    for (int v = 0; v < 5; v++) pa[v] = parabola(Ps[v][i], Ys[v][i - NS], Ys[v][i], f, sixth);
     double WR[5];
-    trace(ip, q[0], q[1], cs, ir, pa, nu, WL, WR);
+    trace(ip, Ps[0][i], Ps[1][i], Fl[0][i], Fl[1][i], pa, nu, WL, WR);
 #pragma unroll
-    for (int v = 0; v < 5; v++) Ws[v][i] = WR[v];
+    for (int v = 0; v < 5; v++) {
+      Ws[v][i] = WR[v];
+      if (!FLOORS) Xs[v][i] = WL[v];
+    }
   }
   __syncthreads();
-  if (faced) {
-    double R5[5], F[5];
+  if (FLOORS) {
+    if (faced) {
+      double R5[5], F[5];
 #pragma unroll
-    for (int v = 0; v < 5; v++) R5[v] = Ws[v][i + NS];
-    riemann_flux(ip, WL, R5, F);
+      for (int v = 0; v < 5; v++) R5[v] = Ws[v][i + NS];
+      riemann_flux(ip, WL, R5, F);
 #pragma unroll
-    for (int v = 0; v < 5; v++) Xs[v][i] = F[v];
+      for (int v = 0; v < 5; v++) Xs[v][i] = F[v];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- reverse ----
   // update and floors: li is the adjoint of the cell's own input through the
-  // identity part (pre-floor adjoint on active cells, unchanged elsewhere)
-  double li[5];
+  // identity part (pre-floor adjoint on active cells, unchanged elsewhere);
+  // the floor-free variant rereads it from lam at the end
+  double li[5] = {0, 0, 0, 0, 0};
   if (live) {
+    if (FLOORS) {
 #pragma unroll
-    for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
-    if (active) {
-      double V[5];
+      for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
+      if (active) {
+        double V[5];
 #pragma unroll
-      for (int v = 0; v < 5; v++) V[v] = ucell[fmap[v] * M3] - nu * (Xs[v][i] - Xs[v][i - NS]);
-      floor_vjp(ip, V, li, li);
+        for (int v = 0; v < 5; v++) V[v] = ucell[fmap[v] * M3] - nu * (Xs[v][i] - Xs[v][i - NS]);
+        floor_vjp(ip, V, li, li);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; v++) Ls[v][i] = active ? li[v] : 0.0;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; v++) Ls[v][i] = active ? lcell[fmap[v] * M3] : 0.0;
     }
-#pragma unroll
-    for (int v = 0; v < 5; v++) Ls[v][i] = active ? li[v] : 0.0;
   }
   __syncthreads();
   // Riemann flux at c+1/2: adjoint of the left state (own) and of the right
   // state (cell c+1, through Ws)
   double gWL[5] = {0, 0, 0, 0, 0};
   if (faced) {
-    double gF[5], R5[5], gR5[5] = {0, 0, 0, 0, 0};
+    double gF[5], L5[5], R5[5], gR5[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       gF[v] = nu * (Ls[v][i + NS] - Ls[v][i]);
+      L5[v] = FLOORS ? WL[v] : Xs[v][i];
       R5[v] = Ws[v][i + NS];
     }
     const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
@@ -225,46 +249,72 @@ __global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* _
         for (int v = 0; v < 5; v++) gF[v] += gf[fmap[v] * N * N];
       }
     }
-    riemann_vjp_n<kAdjMaxIters>(ip, WL, R5, gF, gWL, gR5);
+    riemann_vjp_n<kAdjMaxIters>(ip, L5, R5, gF, gWL, gR5);
 #pragma unroll
     for (int v = 0; v < 5; v++) Ws[v][i + NS] = gR5[v];
   }
   __syncthreads();
-  // tracing, parabolas and flattening of the own cell
+  // tracing, parabolas and flattening of the own cell; the adjoints sent to
+  // the faces c-1/2 and c+1/2 go to Xs and Ls field by field
   double gq[5] = {0, 0, 0, 0, 0}, gc = 0, gir = 0;
   if (live) {
-    double gfa_lo[5] = {0, 0, 0, 0, 0}, gfa_hi[5] = {0, 0, 0, 0, 0};
     double gd1 = 0, gd2 = 0;
     if (traced) {
+      double f;
+      {
+        double rr, dp2;
+        bool fact;
+        flattening(f, rr, dp2, fact);
+      }
+      const double cs = Fl[0][i], ir = Fl[1][i];
+      double gfl = 0;
+      // transverse fields, one at a time
+#pragma unroll
+      for (int v = 2; v <= 3; v++) {
+        const double qv = Ps[v][i], fL = Ys[v][i - NS], fR = Ys[v][i];
+        const Par pv = parabola(qv, fL, fR, f, sixth);
+        ParGrad Gv = {0, 0, 0, 0};
+        trace_vjp_transverse(Ps[1][i], nu, ip.two3, pv, gWL[v], c >= 3 ? Ws[v][i] : 0.0, &Gv, &gq[1]);
+        double glo = 0, ghi = 0;
+        parabola_vjp(qv, fL, fR, f, sixth, Gv, &gq[v], &glo, &ghi, &gfl);
+        Xs[v][i] = glo;
+        Ls[v][i] = ghi;
+      }
+      // rho, u, p
+      constexpr int cf[3] = {0, 1, 4};
       double gWR[5];
 #pragma unroll
       for (int v = 0; v < 5; v++) gWR[v] = c >= 3 ? Ws[v][i] : 0.0;
-      Par pa[5];
-      double fL[5], fR[5];
+      Par pc[3];
 #pragma unroll
-      for (int v = 0; v < 5; v++) {
-        fL[v] = Ys[v][i - NS];
-        fR[v] = Ys[v][i];
-        pa[v] = parabola(q[v], fL[v], fR[v], f, sixth);
-      }
-      ParGrad Gp[5] = {};
+      for (int k = 0; k < 3; k++) pc[k] = parabola(Ps[cf[k]][i], Ys[cf[k]][i - NS], Ys[cf[k]][i], f, sixth);
+      ParGrad Gc[3] = {};
       double grho = 0, gu = 0;
-      trace_vjp(ip, q[0], q[1], cs, ir, pa, nu, gWL, gWR, Gp, &grho, &gu, &gc, &gir);
+      trace_vjp_rup(ip, Ps[0][i], Ps[1][i], cs, ir, pc[0], pc[1], pc[2], nu, gWL, gWR, &Gc[0], &Gc[1], &Gc[2],
+                    &grho, &gu, &gc, &gir);
       gq[0] += grho;
       gq[1] += gu;
-      double gfl = 0;
 #pragma unroll
-      for (int v = 0; v < 5; v++) parabola_vjp(q[v], fL[v], fR[v], f, sixth, Gp[v], &gq[v], &gfa_lo[v], &gfa_hi[v], &gfl);
+      for (int k = 0; k < 3; k++) {
+        double glo = 0, ghi = 0;
+        parabola_vjp(Ps[cf[k]][i], Ys[cf[k]][i - NS], Ys[cf[k]][i], f, sixth, Gc[k], &gq[cf[k]], &glo, &ghi, &gfl);
+        Xs[cf[k]][i] = glo;
+        Ls[cf[k]][i] = ghi;
+      }
+      double f2, rr, dp2;  // recomputed here rather than held across the trace adjoint
+      bool fact;
+      flattening(f2, rr, dp2, fact);
       if (fact) {
         const double gr = 10.0 * gfl;
         gd1 = gr / dp2;
         gd2 = -gr * rr / dp2;
       }
-    }
+    } else {
 #pragma unroll
-    for (int v = 0; v < 5; v++) {
-      Xs[v][i] = gfa_lo[v];
-      Ls[v][i] = gfa_hi[v];
+      for (int v = 0; v < 5; v++) {
+        Xs[v][i] = 0.0;
+        Ls[v][i] = 0.0;
+      }
     }
     Fl[0][i] = gd1;
     Fl[1][i] = gd2;
@@ -280,7 +330,7 @@ __global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* _
       double gm = 0, gp = 0;
       if (c >= 1 && c <= M - 2) {
         const double gdl = sixth * (ghi - glo);
-        slope_vjp(Ps[v][i - NS], q[v], Ps[v][i + NS], gdl, &gm, &gq[v], &gp);
+        slope_vjp(Ps[v][i - NS], Ps[v][i], Ps[v][i + NS], gdl, &gm, &gq[v], &gp);
       }
       Ys[v][i] = gm;
       Ws[v][i] = gp;
@@ -305,6 +355,10 @@ __global__ void __launch_bounds__(AdjShape<N>::WG) sweep_adjoint(const double* _
     for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
     const Prim Pr = prim_fwd(ip, u5);
     prim_vjp(ip, u5, Pr, gq, gc, gir, gU);
+    if (!FLOORS) {
+#pragma unroll
+      for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
+    }
 #pragma unroll
     for (int v = 0; v < 5; v++) lcell[fmap[v] * M3] = li[v] + gU[v];
   }
@@ -426,20 +480,28 @@ __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam
 
 inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-template <int N>
-hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
-                       int dir, const int swept[3], hipStream_t st) {
-  using S = AdjShape<N>;
-  const int A = dir == 0 ? 1 : 0, B = dir == 2 ? 1 : 2;
+template <int N, int DIR>
+hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
+                        const unsigned long long* floors, const int swept[3], hipStream_t st) {
+  using S = AdjShape<N, DIR>;
+  constexpr int A = DIR == 0 ? 1 : 0, B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : S::M;
   const int64_t tiles = P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R);
   if (tiles == 0) return hipSuccess;
   const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
-  if (dir == 0) hipLaunchKernelGGL((sweep_adjoint<N, 0>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
-  else if (dir == 1) hipLaunchKernelGGL((sweep_adjoint<N, 1>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
-  else hipLaunchKernelGGL((sweep_adjoint<N, 2>), g, b, 0, st, Uin, lam, dt, P, gfaces, loA, nA, loB, nB);
+  if (floors != nullptr)
+    hipLaunchKernelGGL((sweep_adjoint<N, DIR, false>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, loA, nA, loB, nB);
+  hipLaunchKernelGGL((sweep_adjoint<N, DIR, true>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, loA, nA, loB, nB);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
+                       const unsigned long long* floors, int dir, const int swept[3], hipStream_t st) {
+  if (dir == 0) return sweep_adj_nd<N, 0>(P, Uin, lam, dt, gfaces, floors, swept, st);
+  if (dir == 1) return sweep_adj_nd<N, 1>(P, Uin, lam, dt, gfaces, floors, swept, st);
+  return sweep_adj_nd<N, 2>(P, Uin, lam, dt, gfaces, floors, swept, st);
 }
 
 template <int N>
@@ -485,11 +547,12 @@ hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const doub
 }
 
 hipError_t launch_sweep_adjoint(const DevPlan& P, const double* Uin, double* lam, const double* dt,
-                                const double* gfaces, int dir, const int swept[3], hipStream_t st) {
+                                const double* gfaces, const unsigned long long* floors, int dir, const int swept[3],
+                                hipStream_t st) {
   switch (P.N) {
-    case 8: return sweep_adj_n<8>(P, Uin, lam, dt, gfaces, dir, swept, st);
-    case 16: return sweep_adj_n<16>(P, Uin, lam, dt, gfaces, dir, swept, st);
-    case 32: return sweep_adj_n<32>(P, Uin, lam, dt, gfaces, dir, swept, st);
+    case 8: return sweep_adj_n<8>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
+    case 16: return sweep_adj_n<16>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
+    case 32: return sweep_adj_n<32>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
     default: return hipErrorInvalidValue;
   }
 }

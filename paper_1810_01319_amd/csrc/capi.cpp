@@ -116,10 +116,16 @@ amr_status finish(amr_mesh* h, amr_mesh** out) {
   return AMR_OK;
 }
 
+// Adjoint scratch: face-flux adjoints (256-B rounded), then for the
+// recomputing entry three states and one counter slot.
+int64_t adjoint_face_bytes(const Plan& p) {
+  const int64_t faces = p.nslots * kFields * int64_t(p.N) * p.N * 8;
+  return (faces + 255) / 256 * 256;
+}
+
 int64_t adjoint_scratch(const Plan& p) {
   const int64_t field = p.nleaf * kFields * int64_t(p.M) * p.M * p.M * 8;
-  const int64_t faces = p.nslots * kFields * int64_t(p.N) * p.N * 8;
-  return 3 * field + faces;
+  return adjoint_face_bytes(p) + 3 * field + 256;
 }
 
 DevPlan dev_plan(const amr_mesh* h) {
@@ -179,7 +185,10 @@ hipError_t refresh_timed(amr_mesh* h, const DevPlan& P, double* U, hipStream_t s
   return timed(h, AMR_PHASE_REFRESH2, st, [&] { return launch_refresh(p2, U, c, st); });
 }
 
-amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index, hipStream_t st) {
+// One step: refresh U in place, then sweep k reads the previous result and
+// writes out[k] (all equal to U for the in-place step), then reflux out[2].
+amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const double* dt, int64_t step_index,
+                         hipStream_t st) {
   const DevPlan P = dev_plan(h);
   hipError_t e = refresh_timed(h, P, U, st);
   if (e != hipSuccess) return hip_fail(e, "refresh");
@@ -189,18 +198,58 @@ amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index
     order[2] = 0;
   }
   int swept[3] = {0, 0, 0};
+  const double* in = U;
   for (int s = 0; s < 3; s++) {
     e = timed(h, AMR_PHASE_SWEEP_X + order[s], st,
-              [&] { return launch_sweep(P, U, dt, order[s], swept, h->cfg, st); });
+              [&] { return launch_sweep_oop(P, in, out[s], dt, order[s], swept, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "sweep");
     swept[order[s]] = 1;
+    in = out[s];
   }
   for (int d = 0; d < 3; d++) {
     if (P.nreflux[d] == 0) continue;
-    e = timed(h, AMR_PHASE_REFLUX, st, [&] { return launch_reflux(P, U, dt, d, h->cfg, st); });
+    e = timed(h, AMR_PHASE_REFLUX, st, [&] { return launch_reflux(P, out[2], dt, d, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "reflux");
   }
   return AMR_OK;
+}
+
+amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index, hipStream_t st) {
+  double* const out[3] = {U, U, U};
+  return run_step_into(h, U, out, dt, step_index, st);
+}
+
+// The transposes of one step in reverse order, given the inputs S[k] of its
+// three sweeps (S[0] the refreshed input state).
+hipError_t adjoint_transposes(amr_mesh* h, const DevPlan& P, const double* const S[3], const double* dt,
+                              const unsigned long long* floors, double* lam, double* gfaces, int64_t step_index,
+                              hipStream_t st) {
+  const Plan& p = h->plan;
+  int order[3] = {0, 1, 2};
+  if (step_index & 1) {
+    order[0] = 2;
+    order[2] = 0;
+  }
+  hipError_t e = timed(h, AMR_PHASE_ADJ_REFLUX, st, [&] {
+    hipError_t r = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
+    if (r == hipSuccess) r = launch_reflux_adjoint(P, lam, dt, gfaces, st);
+    return r;
+  });
+  for (int k = 2; k >= 0 && e == hipSuccess; k--) {
+    int sw[3] = {0, 0, 0};
+    for (int q = 0; q < k; q++) sw[order[q]] = 1;
+    e = timed(h, AMR_PHASE_ADJ_SWEEP_X + order[k], st,
+              [&] { return launch_sweep_adjoint(P, S[k], lam, dt, gfaces, floors, order[k], sw, st); });
+  }
+  if (e == hipSuccess)
+    e = timed(h, AMR_PHASE_ADJ_REFRESH, st, [&] { return launch_refresh_adjoint(P, lam, S[0], st); });
+  return e;
+}
+
+bool adjoint_iters_ok(const Plan& p) {
+  for (const InstParams& ip : p.inst)
+    if (ip.iters > kAdjMaxIters) return false;
+  return true;
 }
 
 amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_params* prm, amr_mesh** out,
@@ -314,6 +363,7 @@ amr_status amr_mesh_info(const amr_mesh* h, amr_mesh_info_t* out) {
   out->n_cf_faces = p.nslots;
   out->n_instances = int64_t(p.inst.size());
   out->adjoint_scratch_bytes = adjoint_scratch(p);
+  out->adjoint_face_bytes = adjoint_face_bytes(p);
   for (const Key& k : p.keys)
     if (k.l < 8) out->levels[k.l]++;
   return AMR_OK;
@@ -372,51 +422,77 @@ amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t s
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
 }
 
+amr_status amr_hydro_step_record(amr_mesh* h, double* U, double* dt, double* S1, double* S2, double* Uout,
+                                 uint64_t* floors, int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !S1 || !S2 || !Uout || !floors) return fail(AMR_E_INVALID, "null argument");
+  if (S1 == U || S2 == U || Uout == U || S1 == S2 || S1 == Uout || S2 == Uout)
+    return fail(AMR_E_INVALID, "U, S1, S2 and U_out must be distinct buffers");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  unsigned long long* mark = reinterpret_cast<unsigned long long*>(floors);
+  hipError_t e = launch_floor_mark(P, mark, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "floor mark");
+  rc = amr_cfl_dt(h, U, dt, stream);
+  if (rc != AMR_OK) return rc;
+  double* const out[3] = {S1, S2, Uout};
+  rc = run_step_into(h, U, out, dt, step_index, st);
+  if (rc != AMR_OK) return rc;
+  e = launch_floor_mark(P, mark, 1, st);
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "floor mark");
+}
+
 amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* dt, double* lam, void* scratch,
                                   int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, Uin);
   if (rc != AMR_OK) return rc;
   if (!dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const Plan& p = h->plan;
-  for (const InstParams& ip : p.inst)
-    if (ip.iters > kAdjMaxIters) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
+  if (!adjoint_iters_ok(p)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
+  hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nfield = p.nleaf * kFields * int64_t(p.M) * p.M * p.M;
+  unsigned char* sc = static_cast<unsigned char*>(scratch);
+  double* gfaces = reinterpret_cast<double*>(sc);
   double* S[3];
-  for (int i = 0; i < 3; i++) S[i] = static_cast<double*>(scratch) + i * nfield;
-  double* gfaces = static_cast<double*>(scratch) + 3 * nfield;
+  for (int i = 0; i < 3; i++) S[i] = reinterpret_cast<double*>(sc + adjoint_face_bytes(p)) + i * nfield;
+  unsigned long long* mark = reinterpret_cast<unsigned long long*>(S[2] + nfield);
   const DevPlan P = dev_plan(h);
   int order[3] = {0, 1, 2};
   if (step_index & 1) {
     order[0] = 2;
     order[2] = 0;
   }
-  // recompute the inputs of the three sweeps
+  // recompute the inputs of the three sweeps; the floor-reset counter is
+  // restored afterwards so that recomputation does not count twice
   int swept[3] = {0, 0, 0};
   hipError_t e = timed(h, AMR_PHASE_ADJ_RECOMPUTE, st, [&] {
-    hipError_t r = hipMemcpyAsync(S[0], Uin, size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
+    hipError_t r = launch_floor_mark(P, mark, 0, st);
+    if (r == hipSuccess) r = hipMemcpyAsync(S[0], Uin, size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
     if (r == hipSuccess) r = launch_refresh(P, S[0], h->cfg, st);
     for (int k = 0; k < 2 && r == hipSuccess; k++) {
-      r = hipMemcpyAsync(S[k + 1], S[k], size_t(nfield) * 8, hipMemcpyDeviceToDevice, st);
-      if (r == hipSuccess) r = launch_sweep(P, S[k + 1], dt, order[k], swept, h->cfg, st);
+      r = launch_sweep_oop(P, S[k], S[k + 1], dt, order[k], swept, h->cfg, st);
       swept[order[k]] = 1;
     }
+    if (r == hipSuccess) r = launch_floor_mark(P, mark, 2, st);
     return r;
   });
   if (e != hipSuccess) return hip_fail(e, "adjoint recompute");
-  // transposes in reverse order
-  e = timed(h, AMR_PHASE_ADJ_REFLUX, st, [&] {
-    hipError_t r = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
-    if (r == hipSuccess) r = launch_reflux_adjoint(P, lam, dt, gfaces, st);
-    return r;
-  });
-  for (int k = 2; k >= 0 && e == hipSuccess; k--) {
-    int sw[3] = {0, 0, 0};
-    for (int q = 0; q < k; q++) sw[order[q]] = 1;
-    e = timed(h, AMR_PHASE_ADJ_SWEEP_X + order[k], st,
-              [&] { return launch_sweep_adjoint(P, S[k], lam, dt, gfaces, order[k], sw, st); });
-  }
-  if (e == hipSuccess) e = timed(h, AMR_PHASE_ADJ_REFRESH, st, [&] { return launch_refresh_adjoint(P, lam, S[0], st); });
+  const double* const Sc[3] = {S[0], S[1], S[2]};
+  e = adjoint_transposes(h, P, Sc, dt, nullptr, lam, gfaces, step_index, st);
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
+}
+
+amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const double* S1, const double* S2,
+                                           const double* dt, const uint64_t* floors, double* lam, void* scratch,
+                                           int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, S0);
+  if (rc != AMR_OK) return rc;
+  if (!S1 || !S2 || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
+  if (!adjoint_iters_ok(h->plan)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
+  const double* const S[3] = {S0, S1, S2};
+  hipError_t e = adjoint_transposes(h, dev_plan(h), S, dt, reinterpret_cast<const unsigned long long*>(floors), lam,
+                                    static_cast<double*>(scratch), step_index, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
 }
 

@@ -159,6 +159,16 @@ __global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, 
   }
 }
 
+// Floor-reset counter bookkeeping, one lane: mode 0 copies the counter to
+// *mark, mode 1 replaces *mark by the resets since (counter - *mark), mode 2
+// copies *mark back into the counter.
+__global__ void floor_mark(DevPlan P, unsigned long long* __restrict__ mark, int mode) {
+  if (blockIdx.x * blockDim.x + threadIdx.x != 0) return;
+  if (mode == 0) mark[threadIdx.x] = P.counters[threadIdx.x];
+  else if (mode == 1) mark[threadIdx.x] = P.counters[threadIdx.x] - mark[threadIdx.x];
+  else P.counters[threadIdx.x] = mark[threadIdx.x];
+}
+
 __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= P.ninst) return;
@@ -173,9 +183,9 @@ __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt) {
 // behind the read front (the stencil of a cell update is 7 cells wide).
 // ---------------------------------------------------------------------------
 
-template <int N, int DIR>
-__global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
-                                                    DevPlan P, int loA, int nA, int loB, int nB) {
+template <int N, int DIR, bool OOP>
+__device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
+                                                const DevPlan& P, int loA, int nA, int loB, int nB) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int A = DIR == 0 ? 1 : 0;
@@ -193,12 +203,17 @@ __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, cons
   const BlockInfo bi = P.blocks[s];
   const InstParams& ip = P.inst[bi.inst];
   const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
-  double* const base = U + int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
-  double* const pr_ = base;
-  double* const pn_ = base + (1 + DIR) * M3;
-  double* const p1_ = base + (1 + T1) * M3;
-  double* const p2_ = base + (1 + T2) * M3;
-  double* const pe_ = base + 4 * M3;
+  const int64_t boff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
+  const double* const pr_ = Uin + boff;
+  const double* const pn_ = pr_ + (1 + DIR) * M3;
+  const double* const p1_ = pr_ + (1 + T1) * M3;
+  const double* const p2_ = pr_ + (1 + T2) * M3;
+  const double* const pe_ = pr_ + 4 * M3;
+  double* const qr_ = Uout + boff;
+  double* const qn_ = qr_ + (1 + DIR) * M3;
+  double* const q1_ = qr_ + (1 + T1) * M3;
+  double* const q2_ = qr_ + (1 + T2) * M3;
+  double* const qe_ = qr_ + 4 * M3;
   const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
   int slot_lo = -1, slot_hi = -1;
   if (faces_act) {
@@ -223,6 +238,10 @@ __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, cons
     if (c + 1 < M) {
       const int64_t o = int64_t(c + 1) * SD;
       nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
+    }
+    if (OOP && (c < G || c >= G + N)) {  // cells the sweep does not update pass through
+      const int64_t o = int64_t(c) * SD;
+      qr_[o] = U0; qn_[o] = U1; q1_[o] = U2; q2_[o] = U3; qe_[o] = U4;
     }
     // primitives of cell c
     const double ir = 1.0 / U0;
@@ -302,7 +321,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, cons
           const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
           const double pn = gm1 * (e - ke);
           if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
-          pr_[o] = r0; pn_[o] = m1; p1_[o] = m2; p2_[o] = m3; pe_[o] = e;
+          qr_[o] = r0; qn_[o] = m1; q1_[o] = m2; q2_[o] = m3; qe_[o] = e;
         }
 #pragma unroll
         for (int q = 0; q < 5; q++) Fp[q] = F[q];
@@ -314,6 +333,21 @@ __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, cons
     for (int q = 0; q < 5; q++) fold[q] = fnew[q];
   }
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+}
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
+                                                    DevPlan P, int loA, int nA, int loB, int nB) {
+  sweep_walk_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB);
+}
+
+// Out of place: every cell of the swept pencils is written to Uout (updated
+// or passed through); Uin is not modified.
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) sweep_kernel_oop(const double* __restrict__ Uin, double* __restrict__ Uout,
+                                                        const double* __restrict__ dtv, DevPlan P, int loA, int nA,
+                                                        int loB, int nB) {
+  sweep_walk_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,10 +366,9 @@ struct StagedShape {
   static constexpr int WG = ((T + 63) / 64) * 64;
 };
 
-template <int N, int DIR>
-__global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged(double* __restrict__ U,
-                                                                    const double* __restrict__ dtv, DevPlan P,
-                                                                    int loA, int nA, int loB, int nB) {
+template <int N, int DIR, bool OOP>
+__device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
+                                                  const DevPlan& P, int loA, int nA, int loB, int nB) {
   using S = StagedShape<N>;
   constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -363,7 +396,9 @@ __global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged(double* __res
   const InstParams& ip = P.inst[bi.inst];
   const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
   const int iA = loA + a0 + r;
-  double* const cellp = U + int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const int64_t coff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const double* const cellp = Uin + coff;
+  double* const outp = Uout + coff;
   const double gm1 = ip.gm1, pfl = ip.p_floor, rfl = ip.rho_floor, sixth = ip.sixth;
 
   // A: own cell, primitives
@@ -457,13 +492,34 @@ __global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged(double* __res
     const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
     const double pn = gm1 * (e - ke);
     if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
-    cellp[0] = r0;
-    cellp[(1 + DIR) * M3] = m1;
-    cellp[(1 + T1) * M3] = m2;
-    cellp[(1 + T2) * M3] = m3;
-    cellp[4 * M3] = e;
+    outp[0] = r0;
+    outp[(1 + DIR) * M3] = m1;
+    outp[(1 + T1) * M3] = m2;
+    outp[(1 + T2) * M3] = m3;
+    outp[4 * M3] = e;
     if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+  } else if (OOP && live) {  // cells the sweep does not update pass through
+    outp[0] = U0;
+    outp[(1 + DIR) * M3] = U1;
+    outp[(1 + T1) * M3] = U2;
+    outp[(1 + T2) * M3] = U3;
+    outp[4 * M3] = U4;
   }
+}
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged(double* __restrict__ U,
+                                                                    const double* __restrict__ dtv, DevPlan P,
+                                                                    int loA, int nA, int loB, int nB) {
+  sweep_staged_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB);
+}
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(StagedShape<N>::WG) sweep_staged_oop(const double* __restrict__ Uin,
+                                                                        double* __restrict__ Uout,
+                                                                        const double* __restrict__ dtv, DevPlan P,
+                                                                        int loA, int nA, int loB, int nB) {
+  sweep_staged_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,32 +674,39 @@ hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg&
 }
 
 template <int N, int DIR>
-hipError_t sweep_nd(const DevPlan& P, double* U, const double* dt, const int swept[3], const LaunchCfg& L,
-                    hipStream_t st) {
+hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const double* dt, const int swept[3],
+                    const LaunchCfg& L, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int A = DIR == 0 ? 1 : 0;
   constexpr int B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : M;
   if (P.nleaf == 0) return hipSuccess;
+  const bool oop = Uin != Uout;
   if (L.sweep_mode[DIR] == 1) {
     using S = StagedShape<N>;
-    const int64_t tiles = P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R);
-    hipLaunchKernelGGL((sweep_staged<N, DIR>), dim3(unsigned(tiles)), dim3(S::WG), 0, st, U, dt, P, loA, nA, loB, nB);
+    const dim3 g(static_cast<unsigned>(P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R))), b(S::WG);
+    if (oop)
+      hipLaunchKernelGGL((sweep_staged_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
+    else
+      hipLaunchKernelGGL((sweep_staged<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB);
   } else {
     const int64_t n = P.nleaf * int64_t(nA) * nB;
-    hipLaunchKernelGGL((sweep_kernel<N, DIR>), dim3(grid_for(n, L.sweep_block)), dim3(L.sweep_block), 0, st, U, dt,
-                       P, loA, nA, loB, nB);
+    const dim3 g(grid_for(n, L.sweep_block)), b(L.sweep_block);
+    if (oop)
+      hipLaunchKernelGGL((sweep_kernel_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
+    else
+      hipLaunchKernelGGL((sweep_kernel<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB);
   }
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t sweep_n(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3], const LaunchCfg& L,
-                   hipStream_t st) {
-  if (dir == 0) return sweep_nd<N, 0>(P, U, dt, swept, L, st);
-  if (dir == 1) return sweep_nd<N, 1>(P, U, dt, swept, L, st);
-  return sweep_nd<N, 2>(P, U, dt, swept, L, st);
+hipError_t sweep_n(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir, const int swept[3],
+                   const LaunchCfg& L, hipStream_t st) {
+  if (dir == 0) return sweep_nd<N, 0>(P, Uin, Uout, dt, swept, L, st);
+  if (dir == 1) return sweep_nd<N, 1>(P, Uin, Uout, dt, swept, L, st);
+  return sweep_nd<N, 2>(P, Uin, Uout, dt, swept, L, st);
 }
 
 template <int N>
@@ -680,12 +743,22 @@ hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const Launc
 
 hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
                         const LaunchCfg& L, hipStream_t st) {
+  return launch_sweep_oop(P, U, U, dt, dir, swept, L, st);
+}
+
+hipError_t launch_sweep_oop(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir,
+                            const int swept[3], const LaunchCfg& L, hipStream_t st) {
   switch (P.N) {
-    case 8: return sweep_n<8>(P, U, dt, dir, swept, L, st);
-    case 16: return sweep_n<16>(P, U, dt, dir, swept, L, st);
-    case 32: return sweep_n<32>(P, U, dt, dir, swept, L, st);
+    case 8: return sweep_n<8>(P, Uin, Uout, dt, dir, swept, L, st);
+    case 16: return sweep_n<16>(P, Uin, Uout, dt, dir, swept, L, st);
+    case 32: return sweep_n<32>(P, Uin, Uout, dt, dir, swept, L, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_floor_mark(const DevPlan& P, unsigned long long* mark, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(floor_mark, dim3(1), dim3(64), 0, st, P, mark, mode);
+  return hipGetLastError();
 }
 
 hipError_t launch_indicator(const DevPlan& P, const double* U, hipStream_t st) {

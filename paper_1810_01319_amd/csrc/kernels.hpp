@@ -39,8 +39,15 @@ hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const Launc
 // sweep along dir; swept[a] = axis a already swept this step
 hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
                         const LaunchCfg& L, hipStream_t st);
+// the same sweep reading Uin and writing every cell of the swept pencils to
+// Uout (updated cells, and the others passed through); in place if equal
+hipError_t launch_sweep_oop(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir,
+                            const int swept[3], const LaunchCfg& L, hipStream_t st);
 hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,
                          hipStream_t st);
+// floor-reset counter: mode 0 mark = counter; 1 mark = counter - mark;
+// 2 counter = mark
+hipError_t launch_floor_mark(const DevPlan& P, unsigned long long* mark, int mode, hipStream_t st);
 // per-leaf density-slope indicator into P.ind (needs refreshed ghosts)
 hipError_t launch_indicator(const DevPlan& P, const double* U, hipStream_t st);
 // fill the active cells of every leaf of the new plan P from the old state

@@ -139,11 +139,13 @@ AMR_HD inline void Im_vjp(const Par& P, double s, double two3, double g, ParGrad
 
 // ---- characteristic tracing ----------------------------------------------
 
-// gWL (left state at j+1/2), gWR (right state at j-1/2) -> gradients of the
-// 5 parabolas and of rho, u, c, 1/rho of the cell (accumulated)
-AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double c, double ir, const Par* pa, double nu,
-                             const double* gWL, const double* gWR, ParGrad* G, double* grho, double* gu, double* gc,
-                             double* gir) {
+// The tracing's coupled part: gWL, gWR (adjoints of the edge states; only
+// their rho, u, p entries are used) -> gradients of the rho, u and p
+// parabolas (G0, G1, G4) and of rho, u, c, 1/rho of the cell (accumulated).
+AMR_HD inline void trace_vjp_rup(const InstParams& ip, double rho, double u, double c, double ir, const Par& p0,
+                                 const Par& p1, const Par& p4, double nu, const double* gWL, const double* gWR,
+                                 ParGrad* G0, ParGrad* G1, ParGrad* G4, double* grho, double* gu, double* gc,
+                                 double* gir) {
   const double t = ip.two3;
   const double lm = u - c, l0 = u, lp = u + c;
   const double ic = 1.0 / c;
@@ -156,9 +158,9 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
   // ---- right edge (left state at j+1/2) ----
   {
     const double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
-    const double rr = Ip(pa[0], sp, t), ur = Ip(pa[1], sp, t), pr = Ip(pa[4], sp, t);
-    const double Ipm = Ip(pa[4], sm, t), Ium = Ip(pa[1], sm, t);
-    const double Ir0 = Ip(pa[0], s0, t), Ip0 = Ip(pa[4], s0, t);
+    const double rr = Ip(p0, sp, t), ur = Ip(p1, sp, t), pr = Ip(p4, sp, t);
+    const double Ipm = Ip(p4, sm, t), Ium = Ip(p1, sm, t);
+    const double Ir0 = Ip(p0, s0, t), Ip0 = Ip(p4, s0, t);
     const double X = pr - Ipm, Y = ur - Ium;
     const double am = (lm > 0.0) ? Ac * (X * Bc - Y) : 0.0;
     const double a0 = (l0 > 0.0) ? (rr - Ir0) - (pr - Ip0) * ic2 : 0.0;
@@ -172,13 +174,11 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
     gcor += gWL[1] * am;
     gcc += -g4 * am;
     double gsm = 0, gs0 = 0, gsp = 0;
-    Ip_vjp(pa[2], s0, t, gWL[2], &G[2], &gs0);
-    Ip_vjp(pa[3], s0, t, gWL[3], &G[3], &gs0);
     if (l0 > 0.0) {
       grr += ga0;
-      Ip_vjp(pa[0], s0, t, -ga0, &G[0], &gs0);
+      Ip_vjp(p0, s0, t, -ga0, G0, &gs0);
       gpr -= ga0 * ic2;
-      Ip_vjp(pa[4], s0, t, ga0 * ic2, &G[4], &gs0);
+      Ip_vjp(p4, s0, t, ga0 * ic2, G4, &gs0);
       gic2 -= ga0 * (pr - Ip0);
     }
     if (lm > 0.0) {
@@ -186,13 +186,13 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
       const double gX = gam * Ac * Bc, gY = -gam * Ac;
       gBc += gam * Ac * X;
       gpr += gX;
-      Ip_vjp(pa[4], sm, t, -gX, &G[4], &gsm);
+      Ip_vjp(p4, sm, t, -gX, G4, &gsm);
       gur += gY;
-      Ip_vjp(pa[1], sm, t, -gY, &G[1], &gsm);
+      Ip_vjp(p1, sm, t, -gY, G1, &gsm);
     }
-    Ip_vjp(pa[0], sp, t, grr, &G[0], &gsp);
-    Ip_vjp(pa[1], sp, t, gur, &G[1], &gsp);
-    Ip_vjp(pa[4], sp, t, gpr, &G[4], &gsp);
+    Ip_vjp(p0, sp, t, grr, G0, &gsp);
+    Ip_vjp(p1, sp, t, gur, G1, &gsp);
+    Ip_vjp(p4, sp, t, gpr, G4, &gsp);
     if (lm > 0.0) glm += nu * gsm;
     if (l0 > 0.0) gl0 += nu * gs0;
     if (lp > 0.0) glp += nu * gsp;
@@ -200,9 +200,9 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
   // ---- left edge (right state at j-1/2) ----
   {
     const double sm = (lm < 0.0 ? -lm : 0.0) * nu, s0 = (l0 < 0.0 ? -l0 : 0.0) * nu, sp = (lp < 0.0 ? -lp : 0.0) * nu;
-    const double rr = Im(pa[0], sm, t), ur = Im(pa[1], sm, t), pr = Im(pa[4], sm, t);
-    const double Imp = Im(pa[4], sp, t), Imu = Im(pa[1], sp, t);
-    const double Ir0 = Im(pa[0], s0, t), Ip0 = Im(pa[4], s0, t);
+    const double rr = Im(p0, sm, t), ur = Im(p1, sm, t), pr = Im(p4, sm, t);
+    const double Imp = Im(p4, sp, t), Imu = Im(p1, sp, t);
+    const double Ir0 = Im(p0, s0, t), Ip0 = Im(p4, s0, t);
     const double X = pr - Imp, Y = ur - Imu;
     const double ap = (lp < 0.0) ? Ac * (X * Bc + Y) : 0.0;
     const double a0 = (l0 < 0.0) ? (rr - Ir0) - (pr - Ip0) * ic2 : 0.0;
@@ -216,13 +216,11 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
     gcor += -gWR[1] * ap;
     gcc += -g4 * ap;
     double gsm = 0, gs0 = 0, gsp = 0;
-    Im_vjp(pa[2], s0, t, gWR[2], &G[2], &gs0);
-    Im_vjp(pa[3], s0, t, gWR[3], &G[3], &gs0);
     if (l0 < 0.0) {
       grr += ga0;
-      Im_vjp(pa[0], s0, t, -ga0, &G[0], &gs0);
+      Im_vjp(p0, s0, t, -ga0, G0, &gs0);
       gpr -= ga0 * ic2;
-      Im_vjp(pa[4], s0, t, ga0 * ic2, &G[4], &gs0);
+      Im_vjp(p4, s0, t, ga0 * ic2, G4, &gs0);
       gic2 -= ga0 * (pr - Ip0);
     }
     if (lp < 0.0) {
@@ -230,13 +228,13 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
       const double gX = gap * Ac * Bc, gY = gap * Ac;
       gBc += gap * Ac * X;
       gpr += gX;
-      Im_vjp(pa[4], sp, t, -gX, &G[4], &gsp);
+      Im_vjp(p4, sp, t, -gX, G4, &gsp);
       gur += gY;
-      Im_vjp(pa[1], sp, t, -gY, &G[1], &gsp);
+      Im_vjp(p1, sp, t, -gY, G1, &gsp);
     }
-    Im_vjp(pa[0], sm, t, grr, &G[0], &gsm);
-    Im_vjp(pa[1], sm, t, gur, &G[1], &gsm);
-    Im_vjp(pa[4], sm, t, gpr, &G[4], &gsm);
+    Im_vjp(p0, sm, t, grr, G0, &gsm);
+    Im_vjp(p1, sm, t, gur, G1, &gsm);
+    Im_vjp(p4, sm, t, gpr, G4, &gsm);
     if (lm < 0.0) glm -= nu * gsm;
     if (l0 < 0.0) gl0 -= nu * gs0;
     if (lp < 0.0) glp -= nu * gsp;
@@ -249,6 +247,29 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
   *gu += glm + gl0 + glp;
   g_c += -glm + glp;
   *gc += g_c;
+}
+
+// A transverse field of the tracing (v or w): its edge states are the
+// parabola's means over the entropy wave's reach, WL_t = Ip(s0) at j+1/2 and
+// WR_t = Im(s0') at j-1/2 -> gradient of its parabola and of u (accumulated).
+AMR_HD inline void trace_vjp_transverse(double u, double nu, double two3, const Par& pa, double gWLt, double gWRt,
+                                        ParGrad* G, double* gu) {
+  const double sR = (u > 0.0 ? u : 0.0) * nu, sL = (u < 0.0 ? -u : 0.0) * nu;
+  double gsR = 0, gsL = 0;
+  Ip_vjp(pa, sR, two3, gWLt, G, &gsR);
+  Im_vjp(pa, sL, two3, gWRt, G, &gsL);
+  if (u > 0.0) *gu += nu * gsR;
+  if (u < 0.0) *gu -= nu * gsL;
+}
+
+// The whole tracing: gWL, gWR -> gradients of the 5 parabolas and of rho, u,
+// c, 1/rho of the cell (accumulated).
+AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double c, double ir, const Par* pa, double nu,
+                             const double* gWL, const double* gWR, ParGrad* G, double* grho, double* gu, double* gc,
+                             double* gir) {
+  trace_vjp_rup(ip, rho, u, c, ir, pa[0], pa[1], pa[4], nu, gWL, gWR, &G[0], &G[1], &G[4], grho, gu, gc, gir);
+  trace_vjp_transverse(u, nu, ip.two3, pa[2], gWL[2], gWR[2], &G[2], gu);
+  trace_vjp_transverse(u, nu, ip.two3, pa[3], gWL[3], gWR[3], &G[3], gu);
 }
 
 // ---- two-shock Riemann solver -------------------------------------------

@@ -165,13 +165,44 @@ class Mesh:
         n = (int(self.info.adjoint_scratch_bytes) + 7) // 8
         return torch.empty(n, dtype=torch.float64, device=self.device)
 
+    def adjoint_face_scratch(self) -> torch.Tensor:
+        n = (int(self.info.adjoint_face_bytes) + 7) // 8
+        return torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+
+    @staticmethod
+    def _check_scratch(scratch: torch.Tensor, nbytes: int) -> None:
+        if scratch.dtype != torch.float64 or not scratch.is_contiguous() or scratch.numel() * 8 < nbytes:
+            raise ValueError("adjoint scratch too small or of the wrong type")
+
     def step_adjoint(self, U_in: torch.Tensor, dt: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor,
                      k: int) -> None:
         """lam <- (d step_k / d U_in)^T lam, dt frozen, U_in the checkpoint."""
         self._check_state(U_in)
         self._check_state(lam)
+        self._check_scratch(scratch, int(self.info.adjoint_scratch_bytes))
         check(lib().amr_hydro_step_adjoint(self._h, _ptr(U_in), _ptr(dt), _ptr(lam), _ptr(scratch), int(k),
                                            _stream()))
+
+    def step_record(self, U: torch.Tensor, dt: torch.Tensor, S1: torch.Tensor, S2: torch.Tensor,
+                    U_out: torch.Tensor, floors: torch.Tensor, k: int) -> None:
+        """Step k from U (ghosts refreshed in place, otherwise unchanged) into
+        U_out, keeping the second and third sweeps' inputs in S1, S2 and the
+        step's floor-reset count in floors (one int64 on the device)."""
+        for X in (U, S1, S2, U_out):
+            self._check_state(X)
+        if floors.dtype != torch.int64 or floors.numel() < 1 or floors.device != self.device:
+            raise ValueError("floors must be an int64 device tensor")
+        check(lib().amr_hydro_step_record(self._h, _ptr(U), _ptr(dt), _ptr(S1), _ptr(S2), _ptr(U_out),
+                                          _ptr(floors), int(k), _stream()))
+
+    def step_adjoint_recorded(self, S0: torch.Tensor, S1: torch.Tensor, S2: torch.Tensor, dt: torch.Tensor,
+                              floors: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor, k: int) -> None:
+        """lam <- (d step_k / d U)^T lam from what step_record kept."""
+        for X in (S0, S1, S2, lam):
+            self._check_state(X)
+        self._check_scratch(scratch, int(self.info.adjoint_face_bytes))
+        check(lib().amr_hydro_step_adjoint_recorded(self._h, _ptr(S0), _ptr(S1), _ptr(S2), _ptr(dt),
+                                                    _ptr(floors), _ptr(lam), _ptr(scratch), int(k), _stream()))
 
     def refresh_adjoint(self, U_ref: torch.Tensor, lam: torch.Tensor) -> None:
         self._check_state(U_ref)

@@ -111,7 +111,8 @@ def test_step_adjoint_matches_differences(k):
     say(f"step k={k}: 40 adjoint entries, worst relative error {worst:.3e}")
 
 
-def test_differentiation_workload_gradient_on_random_directions():
+@pytest.mark.parametrize("record", [True, False])
+def test_differentiation_workload_gradient_on_random_directions(record):
     spec = I.grf_spec(root=4, block_cells=32)
     m = Mesh(**spec.kwargs())
     assert m.nleaf == 120
@@ -128,11 +129,11 @@ def test_differentiation_workload_gradient_on_random_directions():
         return U
 
     r = rho0.clone().requires_grad_(True)
-    UK = A.run_steps(state(r), m, steps)
+    UK = A.run_steps(state(r), m, steps, record=record)
     L = A.density_misfit(m, UK, target)
     L.backward()
     g = r.grad.detach()
-    say(f"loss {float(L):.6e}, |g| {float(g.norm()):.6e}")
+    say(f"record={record}: loss {float(L.detach()):.6e}, |g| {float(g.norm()):.6e}")
     # frozen dt sequence of the forward
     dts = []
     U = state(rho0)
@@ -226,3 +227,48 @@ def test_tiny_mesh_gradient_against_oracle_differences():
         worst = max(worst, err)
         assert err <= 1e-6, ((s, z, y, x), g[s, z, y, x], fd)
     say(f"tiny mesh: 48 oracle difference entries, worst relative error {worst:.3e}")
+
+
+@pytest.mark.parametrize("case", ["smooth", "floors"])
+def test_recorded_adjoint_equals_recomputing_adjoint(case):
+    """Adjoint from the recorded sweep inputs against the adjoint that
+    recomputes them from a checkpoint (which always handles floors), on a
+    smooth AMR state and on a state whose steps reset floors; the recompute
+    leaves the mesh's floor-reset count unchanged."""
+    if case == "smooth":
+        spec = amr_spec(16, 6)
+        m = Mesh(**spec.kwargs())
+        act = I.smooth_state(spec, m.keys, seed=12, amp=0.2, vel=0.4)
+    else:
+        spec = I.MeshSpec(root=(4, 1, 1), block_cells=8, gamma=1.4, p_floor=1e-3, rho_floor=1e-6)
+        m = Mesh(**spec.kwargs())
+        x = I.cell_centres(spec, m.keys)[0]
+        u = np.where(x < 0.5, -4.0, 4.0)
+        act = I.conserved(1.4, np.ones_like(x), u, 0.0, 0.0, np.full(x.shape, 2e-3))
+    N = spec.block_cells
+    say(f"recorded vs recomputing adjoint: {case}, {m.nleaf} leaves")
+    U = m.state_from_active(act)
+    rng = np.random.default_rng(13)
+    act_mask = A.active_mask(m)
+    total = 0
+    for k in range(3):
+        ck = U.clone()
+        dt = m.dt_tensor()
+        S1, S2, Uo = (torch.empty_like(U) for _ in range(3))
+        floors = torch.empty(1, dtype=torch.int64, device=U.device)
+        m.step_record(U, dt, S1, S2, Uo, floors, k)
+        total += int(floors.cpu()[0])
+        lam0 = torch.zeros_like(U)
+        lam0[:, :, act_mask] = torch.from_numpy(rng.normal(size=(m.nleaf, 5, N ** 3))).to(U.device)
+        la, lb = lam0.clone(), lam0.clone()
+        m.step_adjoint_recorded(U, S1, S2, dt, floors, la, m.adjoint_face_scratch(), k)
+        before = m.floor_count()
+        m.step_adjoint(ck, dt, lb, m.adjoint_scratch(), k)
+        assert m.floor_count() == before
+        scale = float(lb.abs().max())
+        err = float((la - lb).abs().max()) / scale
+        say(f"step {k}: floors {int(floors.cpu()[0])}, max |recorded - recomputed| / max {err:.3e}")
+        assert err <= 1e-13, (k, err)
+        U = Uo
+    if case == "floors":
+        assert total > 0

@@ -330,3 +330,49 @@ def test_graph_replays_equal_eager_steps():
             assert float(junk) == 1000.0
         got = gm.active(Ug)
     assert np.array_equal(got, ref)
+
+
+def _floor_spec_state():
+    spec = I.MeshSpec(root=(4, 1, 1), block_cells=8, gamma=1.4, p_floor=1e-3, rho_floor=1e-6)
+    m = Mesh(**spec.kwargs())
+    x = I.cell_centres(spec, m.keys)[0]
+    u = np.where(x < 0.5, -4.0, 4.0)
+    act = I.conserved(1.4, np.ones_like(x), u, 0.0, 0.0, np.full(x.shape, 2e-3))
+    return spec, m, act
+
+
+@pytest.mark.parametrize("case", ["random-amr", "floors"])
+def test_recorded_steps_equal_plain_steps(case):
+    """The recording step (out-of-place sweeps into S1, S2 and a new state)
+    gives bitwise the plain step's dt and active cells, leaves its input's
+    active cells unchanged, and counts the step's floor resets."""
+    if case == "random-amr":
+        spec = I.MeshSpec(root=(2, 2, 2), block_cells=16, max_level=2, gamma=5 / 3,
+                          refine=I.random_refine_list((2, 2, 2), 2, 4, 7))
+        m = Mesh(**spec.kwargs())
+        act = I.smooth_state(spec, m.keys, seed=8, amp=0.2, vel=0.4)
+    else:
+        spec, m, act = _floor_spec_state()
+    say(f"recorded steps: {case}, {m.nleaf} leaves")
+    Up = m.state_from_active(act)
+    dtp = m.dt_tensor()
+    U = m.state_from_active(act)
+    dt = m.dt_tensor()
+    total = 0
+    for k in range(5):
+        before = m.floor_count()
+        m.step(Up, dtp, k)
+        plain_resets = m.floor_count() - before
+        S1, S2, Uo = (torch.empty_like(U) for _ in range(3))
+        floors = torch.empty(1, dtype=torch.int64, device=U.device)
+        a0 = m.active(U)
+        before = m.floor_count()
+        m.step_record(U, dt, S1, S2, Uo, floors, k)
+        assert int(floors.cpu()[0]) == m.floor_count() - before == plain_resets
+        total += plain_resets
+        assert np.array_equal(m.active(U), a0)
+        assert float(dt.cpu()[0]) == float(dtp.cpu()[0])
+        assert np.array_equal(m.active(Uo), m.active(Up)), k
+        U = Uo
+    if case == "floors":
+        assert total > 0
