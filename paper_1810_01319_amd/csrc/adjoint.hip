@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__
 template <int N, int DIR>
 struct AdjShape {
   static constexpr int M = N + 2 * G;
-  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : (DIR == 0 ? 3 : 5));  // pencils per tile
+  static constexpr int R = N == 8 ? 9 : (N == 16 ? 11 : (DIR == 0 ? 3 : 6));  // pencils per tile
   static constexpr int T = R * M;                                              // cells per tile
   static constexpr int WG = ((T + 63) / 64) * 64;
 };
