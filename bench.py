@@ -38,15 +38,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload_name: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same
-    counters' reading for a copy of known size), or None if there is none
-    or the kernel sources changed since the counters were taken."""
+def committed_counters(kernel: str, workload_name: str, what: str) -> dict:
+    """key: value lines of the committed rocprofv3 counter summary
+    profiles/<kernel>_<workload>_<what>.txt, or {} if there is none or the
+    kernel sources changed since the counters were taken."""
     name = kernel.replace("<", "_").replace(">", "").replace(",", "_")
-    path = os.path.join(ROOT, "profiles", f"{name}_{workload_name}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload_name}_{what}.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     kv = {}
     with open(path) as f:
         for line in f:
@@ -54,8 +53,16 @@ def measured_traffic(kernel: str, workload_name: str):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+        return {}
+    return kv
+
+
+def measured_traffic(kernel: str, workload_name: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE per
+    dispatch, scaled by the same counters' reading for a copy of known size),
+    or None."""
+    kv = committed_counters(kernel, workload_name, "traffic")
+    return float(kv["hbm_bytes_per_launch"]) if kv else None
 
 
 def workload(name):
@@ -437,6 +444,7 @@ def main():
     dom = max(per_axis, key=lambda a: per_axis[a]["avg_launch_ms"])
     achieved = per_axis[dom]["TFLOP/s"]
     traffic = measured_traffic(per_axis[dom]["kernel"], args.workload)
+    valu = committed_counters(per_axis[dom]["kernel"], args.workload, "valu")
     phases = {p: round(prof[p][0] / K, 4) for p in _lib.PHASES if not p.startswith("adj_")}
     refresh_bytes = mesh.nleaf * costs.refresh_bytes_per_block(N)
     refresh_ms = (prof["refresh1"][0] + prof["refresh2"][0]) / K
@@ -458,7 +466,12 @@ def main():
         "roofline": {"bound": "alu", "kernel": per_axis[dom]["kernel"], "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "flops_per_launch": per_axis[dom]["flops_per_launch"],
-                     "avg_launch_ms": per_axis[dom]["avg_launch_ms"]},
+                     "avg_launch_ms": per_axis[dom]["avg_launch_ms"],
+                     # rocprofv3 VALUBusy and VALU instructions of the same kernel (committed
+                     # counter summary; None once the kernel sources change)
+                     "valu_busy": float(valu["valu_busy"]) if valu else None,
+                     "valu_issue_frac": (float(valu["valu_insts_per_launch"]) * 4
+                                         / (per_axis[dom]["avg_launch_ms"] * 1e-3 * 1024 * 2.4e9)) if valu else None},
         "sweeps": per_axis,
         "phases_ms_per_step": phases,
         "launch": launch,
