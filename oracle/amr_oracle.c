@@ -844,6 +844,109 @@ double orc_step(orc_mesh* m, int64_t step_index) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Tracer particles (Sec. II-B: Lagrangian particles live on Blocks and  */
+/* move between them; Sec. III: the blast workload carries tracers)      */
+/* ------------------------------------------------------------------ */
+/* Readings: a position is stored in level-0 cell units, X in [0, Rx*N),
+ * so a particle's level-l cell is floor(X * 2^l) (an exact scaling) and
+ * wrapping adds or subtracts the integer extent exactly.  A particle belongs
+ * to the leaf holding that cell.  The drift uses the velocity of the state at
+ * the start of the step with refreshed ghosts: per cell u = m * (1/rho), then
+ * trilinear interpolation between the 8 cell centres around the particle,
+ * X += (dt * u) * (Rx * N); periodic axes wrap, particles leaving through an
+ * outflow face are removed. */
+
+int64_t orc_locate(const orc_mesh* m, const double P[3]) {
+  const int N = m->N;
+  for (int l = 0; l < m->nlev; l++) {
+    int b[3];
+    for (int a = 0; a < 3; a++) {
+      const double c = floor(ldexp(P[a], l));
+      if (!(c >= 0.0)) return -1;
+      b[a] = (int)((int64_t)c / N);
+      if (b[a] >= m->ext[l][a]) return -1;
+    }
+    const int64_t q = nidx(m, l, b[0], b[1], b[2]);
+    if (m->state[l][q] == LEAF) return m->leaf_at[l][q];
+    if (m->state[l][q] != REFINED) return -1;
+  }
+  return -1;
+}
+
+/* Velocity at P inside leaf s (refreshed ghosts), trilinear between the 8
+ * surrounding cell centres, summed x, then y, then z. */
+static void tracer_velocity(const orc_mesh* m, int64_t s, const double P[3], double v[3]) {
+  const int N = m->N, M = m->M;
+  const int32_t* kk = m->key + 4 * s;
+  const int l = kk[0];
+  int i0[3];
+  double w[3][2];
+  for (int a = 0; a < 3; a++) {
+    const double sa = (ldexp(P[a], l) - (double)((int64_t)kk[1 + a] * N)) - 0.5;
+    const double fl = floor(sa);
+    i0[a] = (int)fl + G;
+    const double f = sa - fl;
+    w[a][0] = 1.0 - f;
+    w[a][1] = f;
+  }
+  const double* B = block_ptr(m, s);
+  double c[3][2][2][2];  /* component, dz, dy, dx */
+  for (int dz = 0; dz < 2; dz++)
+    for (int dy = 0; dy < 2; dy++)
+      for (int dx = 0; dx < 2; dx++) {
+        const int a = i0[0] + dx, b = i0[1] + dy, cc = i0[2] + dz;
+        const double ir = 1.0 / B[cell(M, 0, a, b, cc)];
+        for (int d = 0; d < 3; d++) c[d][dz][dy][dx] = B[cell(M, 1 + d, a, b, cc)] * ir;
+      }
+  for (int d = 0; d < 3; d++) {
+    const double z0 = (c[d][0][0][0] * w[0][0] + c[d][0][0][1] * w[0][1]) * w[1][0] +
+                      (c[d][0][1][0] * w[0][0] + c[d][0][1][1] * w[0][1]) * w[1][1];
+    const double z1 = (c[d][1][0][0] * w[0][0] + c[d][1][0][1] * w[0][1]) * w[1][0] +
+                      (c[d][1][1][0] * w[0][0] + c[d][1][1][1] * w[0][1]) * w[1][1];
+    v[d] = z0 * w[2][0] + z1 * w[2][1];
+  }
+}
+
+int64_t orc_tracers_drift(const orc_mesh* m, double dt, int64_t n, double* X, double* Y, double* Z,
+                          int32_t* alive) {
+  const double n0 = (double)((int64_t)m->d.root[0] * m->N);
+  int64_t removed = 0;
+#pragma omp parallel for reduction(+ : removed) schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    if (!alive[i]) continue;
+    double P[3] = {X[i], Y[i], Z[i]};
+    const int64_t s = orc_locate(m, P);
+    if (s < 0) { alive[i] = 0; removed++; continue; }
+    double v[3];
+    tracer_velocity(m, s, P, v);
+    int out = 0;
+    for (int a = 0; a < 3; a++) {
+      const double E = (double)((int64_t)m->d.root[a] * m->N);
+      double x = P[a] + (dt * v[a]) * n0;
+      if (m->d.bc[a] == ORC_BC_PERIODIC) {
+        if (x < 0.0) x += E;
+        if (x >= E) x -= E;
+      } else if (x < 0.0 || x >= E) {
+        out = 1;
+      }
+      P[a] = x;
+    }
+    if (out) { alive[i] = 0; removed++; continue; }
+    X[i] = P[0]; Y[i] = P[1]; Z[i] = P[2];
+  }
+  return removed;
+}
+
+double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, double* Y, double* Z,
+                        int32_t* alive) {
+  const double dt = orc_cfl_dt(m);
+  orc_refresh(m);
+  orc_tracers_drift(m, dt, n, X, Y, Z, alive);
+  orc_step_dt(m, step_index, dt);  /* refreshes again: the same ghosts */
+  return dt;
+}
+
+/* ------------------------------------------------------------------ */
 /* Test hooks                                                          */
 /* ------------------------------------------------------------------ */
 

@@ -67,7 +67,21 @@ double orc_step(orc_mesh* m, int64_t step_index);
 /* Same with a given dt (no CFL reduction). */
 void orc_step_dt(orc_mesh* m, int64_t step_index, double dt);
 
-/* Test hooks on the building blocks. */
+/* Tracer particles.  Positions in level-0 cell units: X in [0, root[0]*N)
+ * etc.; a particle belongs to the leaf holding level-l cell floor(X * 2^l).
+ * orc_locate: that leaf, or -1 outside the domain.  orc_tracers_drift: one
+ * drift of the alive particles with the velocity of the current state (its
+ * ghosts must be refreshed) by trilinear interpolation of u = m / rho between
+ * cell centres, X += (dt * u) * root[0] * N, periodic wrap; particles leaving
+ * through an outflow face get alive = 0.  Returns how many were removed.
+ * orc_step_tracers: dt from CFL, refresh, drift, then the hydro step. */
+int64_t orc_locate(const orc_mesh* m, const double P[3]);
+int64_t orc_tracers_drift(const orc_mesh* m, double dt, int64_t n, double* X, double* Y, double* Z,
+                          int32_t* alive);
+double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, double* Y, double* Z,
+                        int32_t* alive);
+
+/* Test hooks on the building blocks. *//* Test hooks on the building blocks. */
 #define ORC_DEBUG_SKIP_REFLUX 1
 void orc_set_debug(int flags);
 void orc_riemann(const double* gas /* gamma,p_floor */, int iters,

@@ -92,6 +92,12 @@ def lib() -> ctypes.CDLL:
             L.orc_remesh.argtypes = [P, D, D, I64, ctypes.POINTER(P), P]
             L.orc_remesh.restype = I32
             L.orc_indicator.argtypes = [P, P]
+        L.orc_locate.argtypes = [P, P]
+        L.orc_locate.restype = I64
+        L.orc_tracers_drift.argtypes = [P, D, I64, P, P, P, P]
+        L.orc_tracers_drift.restype = I64
+        L.orc_step_tracers.argtypes = [P, I64, I64, P, P, P, P]
+        L.orc_step_tracers.restype = D
         _lib = L
     return _lib
 
@@ -186,6 +192,25 @@ class OracleMesh:
         lib().orc_indicator(self._h, _ptr(out))
         return out
 
+    # tracer particles (positions in level-0 cell units) ----------------
+    def locate(self, P: np.ndarray) -> np.ndarray:
+        """Leaf index holding each position P[n, 3] (-1 outside)."""
+        P = np.ascontiguousarray(P, dtype=np.float64).reshape(-1, 3)
+        out = np.empty(P.shape[0], dtype=np.int64)
+        for i in range(P.shape[0]):
+            out[i] = lib().orc_locate(self._h, _ptr(P[i]))
+        return out
+
+    def tracers_drift(self, dt: float, tr: "Tracers") -> int:
+        """One drift of the alive tracers (ghosts must be refreshed)."""
+        return int(lib().orc_tracers_drift(self._h, float(dt), tr.n, _ptr(tr.X), _ptr(tr.Y), _ptr(tr.Z),
+                                            _ptr(tr.alive)))
+
+    def step_tracers(self, k: int, tr: "Tracers") -> float:
+        """dt from CFL, refresh, tracer drift, hydro step; returns dt."""
+        return float(lib().orc_step_tracers(self._h, int(k), tr.n, _ptr(tr.X), _ptr(tr.Y), _ptr(tr.Z),
+                                            _ptr(tr.alive)))
+
     def remesh(self, refine_slope, coarsen_slope, max_blocks):
         """Returns (new OracleMesh, stats[refined, coarsened, refused])."""
         L = lib()
@@ -196,6 +221,22 @@ class OracleMesh:
         if rc != 0:
             raise ValueError("oracle remesh: " + L.orc_last_error().decode())
         return OracleMesh(_handle=h, **self._kw), stats
+
+
+class Tracers:
+    """Flat particle arrays of the oracle: positions in level-0 cell units,
+    ids, alive flags."""
+
+    def __init__(self, X, Y, Z, ids):
+        self.X = np.ascontiguousarray(X, dtype=np.float64).copy()
+        self.Y = np.ascontiguousarray(Y, dtype=np.float64).copy()
+        self.Z = np.ascontiguousarray(Z, dtype=np.float64).copy()
+        self.ids = np.ascontiguousarray(ids, dtype=np.int64).copy()
+        self.alive = np.ones(self.X.size, dtype=np.int32)
+        self.n = int(self.X.size)
+
+    def positions(self) -> np.ndarray:
+        return np.stack([self.X, self.Y, self.Z], axis=1)
 
 
 DEBUG_SKIP_REFLUX = 1

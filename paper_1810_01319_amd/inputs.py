@@ -362,3 +362,31 @@ def grf_density(spec: MeshSpec, keys, seed: int, amplitude: float = 1e-2) -> np.
 def grf_state(spec: MeshSpec, keys, seed: int = 4) -> np.ndarray:
     rho = grf_density(spec, keys, seed)
     return conserved(spec.gamma, rho, 0.0, 0.0, 0.0, np.ones_like(rho))
+
+
+# ---------------------------------------------------------------------------
+# Tracer particles: positions in level-0 cell units (X in [0, Rx*N) etc.)
+# ---------------------------------------------------------------------------
+
+def tracer_positions(spec: MeshSpec, keys, per_axis: int = 1, jitter_seed=None):
+    """per_axis^3 particles in every active cell of every leaf, at the centres
+    of a per_axis^3 sub-grid of the cell, optionally moved by a seeded uniform
+    offset of up to half a sub-cell (numpy PCG64).  Returns (pos, ids):
+    pos[leaf, n, 3] and ids[leaf, n] with n = (per_axis * N)^3, ids numbered
+    in storage order."""
+    keys = np.asarray(keys)
+    N = spec.block_cells
+    n1 = per_axis * N
+    sub = (np.arange(n1) + 0.5) / per_axis  # sub-cell centres in cells
+    z, y, x = np.meshgrid(sub, sub, sub, indexing="ij")
+    local = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)  # [n, 3] in cells of the leaf's level
+    pos = np.empty((len(keys), n1 ** 3, 3))
+    rng = np.random.default_rng(jitter_seed) if jitter_seed is not None else None
+    for s, (l, i, j, k) in enumerate(keys):
+        q = local.copy()
+        if rng is not None:
+            q += rng.uniform(-0.5, 0.5, size=q.shape) / per_axis
+        q += np.array([i, j, k], dtype=np.float64) * N
+        pos[s] = q / float(1 << int(l))
+    ids = np.arange(len(keys) * n1 ** 3, dtype=np.int64).reshape(len(keys), n1 ** 3)
+    return pos, ids
