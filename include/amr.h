@@ -198,6 +198,50 @@ amr_status amr_hydro_step_adjoint_recorded(amr_mesh* mesh, const double* S0_dev,
  * cells and cleared. */
 amr_status amr_refresh_ghosts_adjoint(amr_mesh* mesh, const double* U_ref_dev, double* lam_dev, void* stream);
 
+/* Tracer particles (Sec. II-B: particles live on Blocks, are allocated in
+ * fixed-size batches and move between Blocks; Sec. III: the blast workload
+ * carries tracers).  Positions are in level-0 cell units: X in
+ * [0, root[0] N), Y in [0, root[1] N), Z in [0, root[2] N); a particle belongs
+ * to the leaf holding its level-l cell floor(X 2^l).  A set stores
+ * `capacity` slots per leaf (a multiple of the 256-slot batch), device
+ * memory owned by the caller:
+ *   pos   3 x n_leaves x capacity doubles: every slot's X, then Y, then Z
+ *         (slot s of leaf b at b * capacity + s);
+ *   id    n_leaves x capacity int64, carried along;
+ *   count n_leaves int32: leaf b holds slots 0 .. count[b]-1. */
+typedef struct {
+  double* pos;
+  int64_t* id;
+  int32_t* count;
+} amr_tracer_set_t;
+/* Bytes of the scratch the tracer calls need for this capacity; the scratch
+ * must be zero-filled before its first use and is then kept by the caller
+ * from call to call. */
+amr_status amr_tracer_scratch_bytes(const amr_mesh* mesh, int64_t capacity, int64_t* bytes);
+/* Advance every particle of `in` by one step into `out` (a distinct set):
+ * drift with the velocity of U_dev (ghosts refreshed) -- per cell
+ * u = m (1/rho), trilinear between the 8 cell centres around the particle --
+ * X += (dt u) (root[0] N) with the instance's dt_dev entry; periodic axes wrap,
+ * particles leaving through an outflow face are removed; then each particle
+ * is written to the leaf holding its new position: those that stay keep
+ * their order, arrivals are appended in no particular order.  The input
+ * positions are overwritten.  Particles beyond a leaf's capacity are dropped
+ * and counted (amr_tracer_counters). */
+amr_status amr_tracers_advance(amr_mesh* mesh, const double* U_dev, const double* dt_dev,
+                               const amr_tracer_set_t* in, amr_tracer_set_t* out, int64_t capacity,
+                               void* scratch_dev, void* stream);
+/* A hydro step (as amr_hydro_step) that advances the tracers of `in` into
+ * `out` between the ghost refresh and the sweeps. */
+amr_status amr_hydro_step_tracers(amr_mesh* mesh, double* U_dev, double* dt_dev, const amr_tracer_set_t* in,
+                                  amr_tracer_set_t* out, int64_t capacity, void* scratch_dev, int64_t step_index,
+                                  void* stream);
+/* Cumulative counters of the scratch (synchronises the stream): out3[0]
+ * particles dropped for lack of capacity, [1] removed through outflow faces,
+ * [2] lost (moved more than a leaf in one step: never under a CFL number
+ * below 1).  reset != 0 zeroes them afterwards. */
+amr_status amr_tracer_counters(amr_mesh* mesh, void* scratch_dev, int64_t capacity, int64_t* out3, int32_t reset,
+                               void* stream);
+
 /* Number of post-update floor resets since upload (synchronises the
  * stream). */
 amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
@@ -271,7 +315,9 @@ amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 #define AMR_PHASE_ADJ_SWEEP_Y 10
 #define AMR_PHASE_ADJ_SWEEP_Z 11
 #define AMR_PHASE_ADJ_REFRESH 12
-#define AMR_NPHASE 13
+/* tracer drift and migration (amr_hydro_step_tracers, amr_tracers_advance) */
+#define AMR_PHASE_TRACERS 13
+#define AMR_NPHASE 14
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
 /* Waits for the recorded events, then writes per phase the summed kernel

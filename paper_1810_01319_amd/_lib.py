@@ -16,7 +16,7 @@ STATUS = {-1: "AMR_E_INVALID", -2: "AMR_E_BALANCE", -3: "AMR_E_NOMEM", -4: "AMR_
           -5: "AMR_E_CAPACITY", -6: "AMR_E_STATE"}
 BC = {"periodic": 0, "outflow": 1}
 PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux",
-          "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh"]
+          "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh", "tracers"]
 
 
 class AmrError(RuntimeError):
@@ -40,6 +40,10 @@ class MeshDesc(ctypes.Structure):
         ("n_refine", ctypes.c_int32),
         ("refine", ctypes.POINTER(ctypes.c_int32)),
     ]
+
+
+class TracerSet(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("id", ctypes.c_void_p), ("count", ctypes.c_void_p)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -98,6 +102,10 @@ SIGNATURES = {
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_adjoint": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
     "amr_hydro_step_record": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I64, _P]),
+    "amr_tracer_scratch_bytes": (_I32, [_P, _I64, _P]),
+    "amr_tracers_advance": (_I32, [_P, _P, _P, _P, _P, _I64, _P, _P]),
+    "amr_hydro_step_tracers": (_I32, [_P, _P, _P, _P, _P, _I64, _P, _I64, _P]),
+    "amr_tracer_counters": (_I32, [_P, _P, _I64, _P, _I32, _P]),
     "amr_hydro_step_adjoint_recorded": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P]),
     "amr_refresh_ghosts_adjoint": (_I32, [_P, _P, _P, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),

@@ -9,6 +9,7 @@
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
+#include "tracers.hpp"
 
 using namespace amr;
 
@@ -188,10 +189,14 @@ hipError_t refresh_timed(amr_mesh* h, const DevPlan& P, double* U, hipStream_t s
 // One step: refresh U in place, then sweep k reads the previous result and
 // writes out[k] (all equal to U for the in-place step), then reflux out[2].
 amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const double* dt, int64_t step_index,
-                         hipStream_t st) {
+                         hipStream_t st, const TracerDev* tracers = nullptr) {
   const DevPlan P = dev_plan(h);
   hipError_t e = refresh_timed(h, P, U, st);
   if (e != hipSuccess) return hip_fail(e, "refresh");
+  if (tracers) {  // drift with the refreshed start-of-step state, then migrate
+    e = timed(h, AMR_PHASE_TRACERS, st, [&] { return launch_tracers_advance(P, U, dt, *tracers, st); });
+    if (e != hipSuccess) return hip_fail(e, "tracers");
+  }
   int order[3] = {0, 1, 2};
   if (step_index & 1) {
     order[0] = 2;
@@ -494,6 +499,96 @@ amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const 
   hipError_t e = adjoint_transposes(h, dev_plan(h), S, dt, reinterpret_cast<const unsigned long long*>(floors), lam,
                                     static_cast<double*>(scratch), step_index, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
+}
+
+// ---- tracer particles ------------------------------------------------------
+
+amr_status tracer_dev(amr_mesh* h, const amr_tracer_set_t* in, amr_tracer_set_t* out, int64_t cap, void* scratch,
+                      TracerDev* T) {
+  if (!in || !scratch) return fail(AMR_E_INVALID, "null argument");
+  if (!in->pos || !in->id || !in->count) return fail(AMR_E_INVALID, "null input tracer array");
+  if (cap <= 0 || cap % kTracerBatch != 0 || cap > (int64_t(1) << 30))
+    return fail(AMR_E_INVALID, "capacity must be a positive multiple of 256");
+  if (out) {
+    if (!out->pos || !out->id || !out->count) return fail(AMR_E_INVALID, "null output tracer array");
+    if (out->pos == in->pos || out->id == in->id || out->count == in->count)
+      return fail(AMR_E_INVALID, "input and output tracer sets must be distinct");
+  }
+  const int64_t nleaf = h->plan.nleaf;
+  const TracerScratch L = tracer_scratch_layout(nleaf, cap);
+  unsigned char* sc = static_cast<unsigned char*>(scratch);
+  T->pos_in = in->pos;
+  T->id_in = in->id;
+  T->count_in = in->count;
+  T->pos_out = out ? out->pos : nullptr;
+  T->id_out = out ? out->id : nullptr;
+  T->count_out = out ? out->count : nullptr;
+  T->dest = reinterpret_cast<int32_t*>(sc + L.dest);
+  T->stay_batch = reinterpret_cast<int32_t*>(sc + L.stay_batch);
+  T->stay = reinterpret_cast<int32_t*>(sc + L.stay);
+  T->arrive = reinterpret_cast<int32_t*>(sc + L.arrive);
+  T->flags = reinterpret_cast<unsigned long long*>(sc + L.flags);
+  T->cap = cap;
+  T->plane = nleaf * cap;
+  T->nbatch = int32_t(cap / kTracerBatch);
+  return AMR_OK;
+}
+
+amr_status amr_tracer_scratch_bytes(const amr_mesh* h, int64_t capacity, int64_t* bytes) {
+  if (!h || !bytes) return fail(AMR_E_INVALID, "null argument");
+  if (capacity <= 0 || capacity % kTracerBatch != 0) return fail(AMR_E_INVALID, "capacity must be a multiple of 256");
+  *bytes = tracer_scratch_layout(h->plan.nleaf, capacity).total;
+  return AMR_OK;
+}
+
+amr_status amr_tracers_advance(amr_mesh* h, const double* U, const double* dt, const amr_tracer_set_t* in,
+                               amr_tracer_set_t* out, int64_t capacity, void* scratch, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !out) return fail(AMR_E_INVALID, "null argument");
+  TracerDev T;
+  rc = tracer_dev(h, in, out, capacity, scratch, &T);
+  if (rc != AMR_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = timed(h, AMR_PHASE_TRACERS, st, [&] { return launch_tracers_advance(dev_plan(h), U, dt, T, st); });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "tracers");
+}
+
+amr_status amr_hydro_step_tracers(amr_mesh* h, double* U, double* dt, const amr_tracer_set_t* in,
+                                  amr_tracer_set_t* out, int64_t capacity, void* scratch, int64_t step_index,
+                                  void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!out) return fail(AMR_E_INVALID, "null argument");
+  TracerDev T;
+  rc = tracer_dev(h, in, out, capacity, scratch, &T);
+  if (rc != AMR_OK) return rc;
+  rc = amr_cfl_dt(h, U, dt, stream);
+  if (rc != AMR_OK) return rc;
+  double* const o[3] = {U, U, U};
+  return run_step_into(h, U, o, dt, step_index, static_cast<hipStream_t>(stream), &T);
+}
+
+amr_status amr_tracer_counters(amr_mesh* h, void* scratch, int64_t capacity, int64_t* out3, int32_t reset,
+                               void* stream) {
+  if (!h || !scratch || !out3) return fail(AMR_E_INVALID, "null argument");
+  if (capacity <= 0 || capacity % kTracerBatch != 0) return fail(AMR_E_INVALID, "capacity must be a multiple of 256");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const TracerScratch L = tracer_scratch_layout(h->plan.nleaf, capacity);
+  unsigned long long f[TRACER_NFLAGS];
+  hipError_t e = hipMemcpyAsync(f, static_cast<unsigned char*>(scratch) + L.flags, sizeof f, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "tracer counters");
+  out3[0] = int64_t(f[TRACER_OVERFLOW]);
+  out3[1] = int64_t(f[TRACER_REMOVED]);
+  out3[2] = int64_t(f[TRACER_LOST]);
+  if (reset) {
+    TracerDev T{};
+    T.flags = reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(scratch) + L.flags);
+    e = launch_tracer_zero_flags(T, st);
+    if (e != hipSuccess) return hip_fail(e, "tracer counters");
+  }
+  return AMR_OK;
 }
 
 amr_status amr_refresh_ghosts_adjoint(amr_mesh* h, const double* Uref, double* lam, void* stream) {
