@@ -251,6 +251,50 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
     return out
 
 
+def tracer_compare(steps: int = 20):
+    """Tracer particles on the Sedov workload: one particle per active cell
+    (20.4M, jittered inside the cell), hydro steps that also advance them,
+    against plain steps of the same mesh.  The tracer phase (drift and
+    migration kernels) is timed with HIP events."""
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+    from paper_1810_01319_amd.tracers import Tracers
+
+    spec = I.sedov_spec(root=8, block_cells=32, levels=2)
+    m = Mesh(**spec.kwargs())
+    U = m.state_from_active(I.sedov_state(spec, m.keys))
+    pos, ids = I.tracer_positions(spec, m.keys, 1, jitter_seed=9)
+    n = int(ids.size)
+    tr = Tracers.from_positions(m, pos, ids, capacity=2 * spec.block_cells ** 3)
+    del pos, ids
+    dt = m.dt_tensor()
+    tr.step(U, dt, 0)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        tr.step(U, dt, k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = m.profile_read()
+    m.profile(False)
+    tr_ms = prof["tracers"][0] / steps
+    c = tr.counters()
+    # algorithmic bytes per particle and step: drift reads X, Y, Z and writes
+    # them and the destination (52 B); migration reads destination, position,
+    # id and writes position and id (68 B); the interpolation reads 4 fields of
+    # the cells around it, about one cell per particle at this density (32 B)
+    bytes_pp = 52 + 68 + 32
+    return {"workload": "sedov-static-amr with one tracer per active cell (20.4M particles)",
+            "particles": n, "steps": steps, "ms_per_step_with_tracers": wall * 1e3 / steps,
+            "tracer_ms_per_step": tr_ms, "particle_updates_per_s": n / (tr_ms * 1e-3),
+            "tracer_hbm": {"algorithmic_bytes_per_particle": bytes_pp,
+                           "GB/s": n * bytes_pp / (tr_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS},
+            "counters": c, "particles_end": tr.count}
+
+
 def step_bytes_per_block(N: int) -> int:
     """Algorithmic HBM bytes of one step of one block: CFL read, refresh,
     three sweeps (reflux is negligible)."""
@@ -373,6 +417,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the batched comparison, graph and one-mesh-per-launch (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="steps of the adjoint comparison (0: skip)")
+    ap.add_argument("--tracer-steps", type=int, default=20, help="steps of the tracer measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -485,6 +530,8 @@ def main():
         out["batched"] = batched_compare(args.batch_steps)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_compare(args.adjoint_steps)
+    if args.tracer_steps > 0:
+        out["tracers"] = tracer_compare(args.tracer_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)
