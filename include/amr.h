@@ -235,6 +235,15 @@ amr_status amr_tracers_advance(amr_mesh* mesh, const double* U_dev, const double
 amr_status amr_hydro_step_tracers(amr_mesh* mesh, double* U_dev, double* dt_dev, const amr_tracer_set_t* in,
                                   amr_tracer_set_t* out, int64_t capacity, void* scratch_dev, int64_t step_index,
                                   void* stream);
+/* After a remesh: move every particle of old_set (the set of the mesh given
+ * to amr_remesh_plan, old_leaves leaves) into new_set on new_mesh (made by
+ * amr_remesh_plan and uploaded): particles of a kept leaf stay with it, those
+ * of a split leaf go to the child holding their position, those of merged
+ * leaves to the new parent; the order inside a leaf is not specified.
+ * Positions are unchanged.  scratch_dev: the scratch of new_mesh for this
+ * capacity (zero-filled before its first use). */
+amr_status amr_tracers_remesh(amr_mesh* new_mesh, int64_t old_leaves, const amr_tracer_set_t* old_set,
+                              amr_tracer_set_t* new_set, int64_t capacity, void* scratch_dev, void* stream);
 /* Cumulative counters of the scratch (synchronises the stream): out3[0]
  * particles dropped for lack of capacity, [1] removed through outflow faces,
  * [2] lost (moved more than a leaf in one step: never under a CFL number

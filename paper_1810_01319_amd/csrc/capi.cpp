@@ -147,6 +147,8 @@ DevPlan dev_plan(const amr_mesh* h) {
   P.counters = reinterpret_cast<unsigned long long*>(w + p.off.counters);
   P.ind = reinterpret_cast<double*>(w + p.off.ind);
   P.migr = reinterpret_cast<const MigrTask*>(w + p.off.migr);
+  P.reloc = reinterpret_cast<const Reloc*>(w + p.off.reloc);
+  P.reloc_child = reinterpret_cast<const int32_t*>(w + p.off.reloc_child);
   P.faces = reinterpret_cast<double*>(w + p.off.faces);
   P.nleaf = p.nleaf;
   P.np2 = int64_t(p.p2list.size());
@@ -263,6 +265,38 @@ amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_pa
   amr_mesh* nh = new (std::nothrow) amr_mesh();
   if (!nh) return fail(AMR_E_NOMEM, "out of host memory");
   nh->trees.push_back(std::move(r.tree));
+  // where the particles of each old leaf go: the inverse of the migration tasks
+  std::vector<Reloc> reloc(size_t(h->plan.nleaf), Reloc{-1, -1});
+  std::vector<int32_t> child;
+  std::vector<int32_t> row(size_t(h->plan.nleaf), -1);
+  for (size_t n = 0; n < r.migr.size(); n++) {
+    const MigrTask& t = r.migr[n];
+    if (t.kind == MIGR_COPY) {
+      reloc[size_t(t.src[0])] = Reloc{RELOC_KEEP, int32_t(n)};
+    } else if (t.kind == MIGR_PROLONG) {
+      int32_t& rw = row[size_t(t.src[0])];
+      if (rw < 0) {
+        rw = int32_t(child.size() / 8);
+        child.resize(child.size() + 8, -1);
+      }
+      reloc[size_t(t.src[0])] = Reloc{RELOC_SPLIT, rw};
+      child[size_t(8 * rw + t.co)] = int32_t(n);
+    } else {
+      for (int q = 0; q < 8; q++) reloc[size_t(t.src[q])] = Reloc{RELOC_MERGE, int32_t(n)};
+    }
+  }
+  for (const Reloc& x : reloc)
+    if (x.kind < 0) {
+      delete nh;
+      return fail(AMR_E_STATE, "remesh left an old leaf without a successor");
+    }
+  for (int32_t c : child)
+    if (c < 0) {
+      delete nh;
+      return fail(AMR_E_STATE, "remesh split a leaf into fewer than 8 children");
+    }
+  nh->plan.reloc = std::move(reloc);
+  nh->plan.reloc_child = std::move(child);
   nh->plan.migr = std::move(r.migr);
   nh->cfg = h->cfg;
   amr_status rc = finish(nh, out);
@@ -530,6 +564,7 @@ amr_status tracer_dev(amr_mesh* h, const amr_tracer_set_t* in, amr_tracer_set_t*
   T->flags = reinterpret_cast<unsigned long long*>(sc + L.flags);
   T->cap = cap;
   T->plane = nleaf * cap;
+  T->plane_out = nleaf * cap;
   T->nbatch = int32_t(cap / kTracerBatch);
   return AMR_OK;
 }
@@ -567,6 +602,20 @@ amr_status amr_hydro_step_tracers(amr_mesh* h, double* U, double* dt, const amr_
   if (rc != AMR_OK) return rc;
   double* const o[3] = {U, U, U};
   return run_step_into(h, U, o, dt, step_index, static_cast<hipStream_t>(stream), &T);
+}
+
+amr_status amr_tracers_remesh(amr_mesh* nh, int64_t old_leaves, const amr_tracer_set_t* old_set,
+                              amr_tracer_set_t* new_set, int64_t capacity, void* scratch, void* stream) {
+  if (!nh || !new_set) return fail(AMR_E_INVALID, "null argument");
+  if (!nh->ws) return fail(AMR_E_STATE, "mesh not uploaded");
+  if (nh->plan.reloc.size() != size_t(old_leaves))
+    return fail(AMR_E_STATE, "mesh was not made by amr_remesh_plan from a mesh of old_leaves leaves");
+  TracerDev T;
+  amr_status rc = tracer_dev(nh, old_set, new_set, capacity, scratch, &T);
+  if (rc != AMR_OK) return rc;
+  T.plane = old_leaves * capacity;  // the input set belongs to the old mesh
+  hipError_t e = launch_tracers_relocate(dev_plan(nh), old_leaves, T, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "tracer relocation");
 }
 
 amr_status amr_tracer_counters(amr_mesh* h, void* scratch, int64_t capacity, int64_t* out3, int32_t reset,

@@ -21,6 +21,8 @@ struct DevPlan {
   unsigned long long* counters;
   double* ind;
   const MigrTask* migr;
+  const Reloc* reloc;
+  const int32_t* reloc_child;
   double* faces;
   int64_t nleaf, np2, nreflux[3];
   int32_t ninst, N;

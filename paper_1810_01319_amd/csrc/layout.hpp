@@ -62,8 +62,16 @@ struct MigrTask {
   int32_t src[8];
 };
 
+// Where the particles of an old leaf go in a remeshed mesh.
+enum RelocKind : int32_t { RELOC_KEEP = 0, RELOC_SPLIT = 1, RELOC_MERGE = 2 };
+struct Reloc {
+  int32_t kind;  // RELOC_*
+  int32_t id;    // KEEP/MERGE: new leaf; SPLIT: row of 8 children (x fastest) in reloc_child
+};
+
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, ind, migr, faces, total;
+  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, ind, migr, reloc, reloc_child, faces,
+      total;
 };
 
 }  // namespace amr

@@ -329,6 +329,8 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   off.counters = o; o = align256(o + 8);
   off.ind = o; o = align256(o + nleaf * 8);
   off.migr = o; o = align256(o + int64_t(migr.size() * sizeof(MigrTask)));
+  off.reloc = o; o = align256(o + int64_t(reloc.size() * sizeof(Reloc)));
+  off.reloc_child = o; o = align256(o + int64_t(reloc_child.size() * sizeof(int32_t)));
   off.faces = o; o = align256(o + nslots * int64_t(kFields) * N * N * 8);
   off.total = o;
   staging.assign(size_t(off.faces), 0);
@@ -343,6 +345,8 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   put(off.faceslot, faceslot.data(), faceslot.size() * sizeof(int32_t));
   for (int d = 0; d < 3; d++) put(off.reflux[d], reflux[d].data(), reflux[d].size() * sizeof(RefluxTask));
   put(off.migr, migr.data(), migr.size() * sizeof(MigrTask));
+  put(off.reloc, reloc.data(), reloc.size() * sizeof(Reloc));
+  put(off.reloc_child, reloc_child.data(), reloc_child.size() * sizeof(int32_t));
   // dt accumulators start at +inf (bit pattern of a positive double)
   const uint64_t inf_bits = 0x7FF0000000000000ull;
   for (int64_t m = 0; m < ninst; m++) put(off.acc + 8 * m, &inf_bits, 8);

@@ -72,6 +72,8 @@ struct Plan {
   std::vector<int32_t> faceslot; // 6 per leaf
   std::vector<RefluxTask> reflux[3];
   std::vector<MigrTask> migr;    // set before build() by a remesh
+  std::vector<Reloc> reloc;      // per leaf of the previous mesh; set before build() by a remesh
+  std::vector<int32_t> reloc_child;  // 8 per split leaf
   int64_t nslots = 0;
   PlanOffsets off{};
   std::vector<unsigned char> staging;  // bytes [0, off.faces) as uploaded

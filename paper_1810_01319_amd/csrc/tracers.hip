@@ -203,8 +203,40 @@ __global__ void __launch_bounds__(B) tracer_scatter(TracerDev T) {
   }
   const int64_t d = int64_t(dest) * T.cap + to;
   T.pos_out[d] = T.pos_in[at];
-  T.pos_out[T.plane + d] = T.pos_in[T.plane + at];
-  T.pos_out[2 * T.plane + d] = T.pos_in[2 * T.plane + at];
+  T.pos_out[T.plane_out + d] = T.pos_in[T.plane + at];
+  T.pos_out[2 * T.plane_out + d] = T.pos_in[2 * T.plane + at];
+  T.id_out[d] = T.id_in[at];
+}
+
+// After a remesh: the particles of old leaf s go to the leaf that kept it, to
+// the child holding their position, or to the merged parent.
+__global__ void __launch_bounds__(B) tracer_relocate(DevPlan P, TracerDev T) {
+  const int64_t s = blockIdx.x / T.nbatch;
+  const int b = int(blockIdx.x - s * T.nbatch);
+  const int n = T.count_in[s];
+  const int slot = b * B + threadIdx.x;
+  if (slot >= n) return;
+  const int64_t at = s * T.cap + slot;
+  const Reloc r = P.reloc[s];
+  const double X[3] = {T.pos_in[at], T.pos_in[T.plane + at], T.pos_in[2 * T.plane + at]};
+  int dest = r.id;
+  if (r.kind == RELOC_SPLIT) {
+    const int32_t* ch = P.reloc_child + 8 * int64_t(r.id);
+    const int lc = P.blocks[ch[0]].level;
+    int c = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) c |= int(((int64_t)floor(ldexp(X[a], lc)) / P.N) & 1) << a;
+    dest = ch[c];
+  }
+  const int k = atomicAdd(&T.arrive[dest], 1);
+  if (k >= T.cap) {
+    atomicAdd(&T.flags[TRACER_OVERFLOW], 1ull);
+    return;
+  }
+  const int64_t d = int64_t(dest) * T.cap + k;
+  T.pos_out[d] = X[0];
+  T.pos_out[T.plane_out + d] = X[1];
+  T.pos_out[2 * T.plane_out + d] = X[2];
   T.id_out[d] = T.id_in[at];
 }
 
@@ -236,6 +268,15 @@ hipError_t launch_tracers_advance(const DevPlan& P, const double* U, const doubl
   hipLaunchKernelGGL(tracer_scatter, g, b, 0, st, T);
   hipLaunchKernelGGL(tracer_counts, dim3(static_cast<unsigned>((P.nleaf + 255) / 256)), dim3(256), 0, st, T,
                      P.nleaf);
+  return hipGetLastError();
+}
+
+hipError_t launch_tracers_relocate(const DevPlan& P, int64_t old_nleaf, const TracerDev& T, hipStream_t st) {
+  if (old_nleaf > 0)
+    hipLaunchKernelGGL(tracer_relocate, dim3(static_cast<unsigned>(old_nleaf * T.nbatch)), dim3(B), 0, st, P, T);
+  if (P.nleaf > 0)
+    hipLaunchKernelGGL(tracer_counts, dim3(static_cast<unsigned>((P.nleaf + 255) / 256)), dim3(256), 0, st, T,
+                       P.nleaf);
   return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ struct TracerDev {
   int32_t* stay;            // nleaf (zero between advances)
   int32_t* arrive;          // nleaf (zero between advances)
   unsigned long long* flags;  // TRACER_NFLAGS cumulative counters
-  int64_t cap, plane;       // slots per leaf; nleaf * cap
+  int64_t cap, plane;       // slots per leaf; nleaf * cap of the input set
+  int64_t plane_out;        // nleaf * cap of the output set (differs after a remesh)
   int32_t nbatch;           // cap / kTracerBatch
 };
 
@@ -52,5 +53,8 @@ inline TracerScratch tracer_scratch_layout(int64_t nleaf, int64_t cap) {
 hipError_t launch_tracers_advance(const DevPlan& P, const double* U, const double* dt, const TracerDev& T,
                                   hipStream_t st);
 hipError_t launch_tracer_zero_flags(const TracerDev& T, hipStream_t st);
+// move every particle of T.in (sets of the mesh before a remesh, old_nleaf
+// leaves) to its leaf of the remeshed mesh P (its relocation table) in T.out
+hipError_t launch_tracers_relocate(const DevPlan& P, int64_t old_nleaf, const TracerDev& T, hipStream_t st);
 
 }  // namespace amr

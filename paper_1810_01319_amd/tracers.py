@@ -65,6 +65,17 @@ class Tracers:
                                         self.cap, _ptr(self.scratch), _stream()))
         self.cur = 1 - self.cur
 
+    def remesh(self, new_mesh) -> "Tracers":
+        """The tracers moved onto `new_mesh`, the result of this mesh's remesh
+        (itself if the remesh kept the mesh)."""
+        if new_mesh is self.mesh:
+            return self
+        t = Tracers(new_mesh, self.cap)
+        a, b = self._set(self.cur), t._set(0)
+        check(lib().amr_tracers_remesh(new_mesh._h, self.mesh.nleaf, ctypes.byref(a), ctypes.byref(b), self.cap,
+                                       _ptr(t.scratch), _stream()))
+        return t
+
     def counters(self, reset: bool = False) -> dict:
         out = np.zeros(3, dtype=np.int64)
         check(lib().amr_tracer_counters(self.mesh._h, _ptr(self.scratch), self.cap,

@@ -178,3 +178,39 @@ def test_capacity_overflow_is_counted():
     assert c["overflow"] > 0 and c["lost"] == 0
     assert tr.count == 2 * n - c["overflow"]
     assert int(tr.sets[tr.cur][2].max()) <= 256
+
+
+@pytest.mark.parametrize("root,N,levels,cap_extra", [(3, 8, 2, 10 ** 6), (3, 8, 3, 60)])
+def test_tracers_through_remesh(root, N, levels, cap_extra):
+    """Blast tiles with a remesh every 4 steps: the tracers follow their
+    leaves through refinement and coarsening (and refusals at a tight
+    capacity) and stay bitwise equal to the oracle, whose particles are
+    located by position in whatever mesh it holds."""
+    spec = I.blasts_spec(root=root, block_cells=N, levels=levels)
+    gm = Mesh(**spec.kwargs())
+    act = I.blasts_state(spec, gm.keys)
+    om, perm = oracle_pair(spec, gm, act)
+    pos, ids = I.tracer_positions(spec, gm.keys, 1, jitter_seed=31)
+    tr = Tracers.from_positions(gm, pos, ids, capacity=8 * N ** 3)
+    otr = O.Tracers(*pos.reshape(-1, 3).T, ids.ravel())
+    U = gm.state_from_active(act)
+    cap = gm.nleaf + cap_extra
+    say(f"tracers through remesh: root={root} N={N} levels={levels}, {gm.nleaf} leaves")
+    remeshes = 0
+    for k in range(13):
+        if k > 0 and k % 4 == 0:
+            new, U, st = gm.remesh(U, 0.3, 0.1, cap)
+            tr = tr.remesh(new)
+            remeshes += new is not gm
+            gm = new
+            om, _ = om.remesh(0.3, 0.1, cap)
+        dt = gm.dt_tensor()
+        tr.step(U, dt, k)
+        assert float(dt.cpu()[0]) == om.step_tracers(k, otr), k
+    assert remeshes > 0
+    idx = {tuple(kk): s for s, kk in enumerate(om.keys)}
+    perm = np.array([idx[tuple(kk)] for kk in gm.keys])
+    assert np.array_equal(gm.active(U), om.active()[perm])
+    compare(gm, tr, om, otr, perm)
+    assert tr.counters() == {"overflow": 0, "removed": 0, "lost": 0}
+    say(f"tracers through remesh: {remeshes} remeshes, now {gm.nleaf} leaves, {tr.count} particles")
