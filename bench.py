@@ -353,6 +353,14 @@ def run_adaptive(args, spec, desc):
         for p in phases:
             phases[p] += prof[p][0]
 
+    def total_mass(mm, uu):
+        # sum over leaves of the cell volumes (root-cell units) times rho
+        g, n = 3, spec.block_cells
+        lev = torch.as_tensor(mm.keys[:, 0], device=uu.device, dtype=torch.float64)
+        per_leaf = uu[:mm.nleaf, 0, g:g + n, g:g + n, g:g + n].sum(dim=(1, 2, 3))
+        return float((per_leaf * torch.pow(0.125, lev)).sum())
+
+    mass0 = total_mass(mesh, U)
     t_remesh = 0.0
     N = spec.block_cells
     m, u = mesh, U
@@ -381,6 +389,7 @@ def run_adaptive(args, spec, desc):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     collect(m)
+    mass1 = total_mass(m, u)
     total = float(sum(cells_per_step))
     hydro_s = wall - t_remesh
     out = {
@@ -394,6 +403,7 @@ def run_adaptive(args, spec, desc):
         "remeshes": len(stats),
         "remesh_stats_last": stats[-1] if stats else None,
         "refused_total": int(sum(s["refused"] for s in stats)),
+        "mass_relative_change": (mass1 - mass0) / mass0,
         "phases_ms_per_step": {p: round(v / args.steps, 3) for p, v in phases.items()},
         "step_hbm_algorithmic": {"GB/s": sum(bytes_per_step) / hydro_s / 1e9, "peak": PEAK_HBM_GBS,
                                  "frac": sum(bytes_per_step) / hydro_s / 1e9 / PEAK_HBM_GBS},
