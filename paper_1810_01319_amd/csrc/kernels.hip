@@ -9,6 +9,8 @@
 // Storage: per leaf 5 fields of M^3 doubles, M = N + 6, x fastest.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "ppm_core.hpp"
 #include "ghost.hpp"
@@ -179,8 +181,9 @@ __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt) {
 
 // ---------------------------------------------------------------------------
 // PPM sweep: one lane walks one pencil along the sweep axis with a sliding
-// register window; cells are read once and updated in place three cells
-// behind the read front (the stencil of a cell update is 7 cells wide).
+// register window; the next cell is prefetched one step ahead, and each cell
+// is updated three cells behind the read front (the stencil of a cell update
+// is 7 cells wide), re-read from cache for its conserved values.
 // ---------------------------------------------------------------------------
 
 template <int N, int DIR, bool OOP>
@@ -194,14 +197,17 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
   constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
   constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
-  const int64_t npen = int64_t(nA) * nB;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= P.nleaf * npen) return;
-  const int s = int(t / npen);
-  const int pp = int(t - int64_t(s) * npen);
+  // waves never straddle two leaves: the leaf index is wave-uniform, so the
+  // leaf's and the instance's parameters are scalar loads
+  const int npen = nA * nB;
+  const unsigned wpl = unsigned(npen + 63) / 64u;
+  const unsigned w = blockIdx.x * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  const int s = int(w / wpl);
+  const int pp = int(w - unsigned(s) * wpl) * 64 + int(threadIdx.x & 63u);
+  if (s >= P.nleaf || pp >= npen) return;
   const int iA = loA + pp % nA, iB = loB + pp / nA;
   const BlockInfo bi = P.blocks[s];
-  const InstParams& ip = P.inst[bi.inst];
+  const InstParams ip = P.inst[bi.inst];  // by value: read once, before any store
   const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
   const int64_t boff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
   const double* const pr_ = Uin + boff;
@@ -223,6 +229,14 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   const int64_t face_off = int64_t(iB - G) * N + (iA - G);
   const double gm1 = ip.gm1, pfl = ip.p_floor, rfl = ip.rho_floor, sixth = ip.sixth;
 
+  if (OOP) {  // cells the sweep does not update pass through
+#pragma unroll
+    for (int k = 0; k < 2 * G; k++) {
+      const int64_t o = int64_t(k < G ? k : N + k) * SD;
+      qr_[o] = pr_[o]; qn_[o] = pn_[o]; q1_[o] = p1_[o]; q2_[o] = p2_[o]; qe_[o] = pe_[o];
+    }
+  }
+
   // windows: rho, v, w over cells t-2..t; u over t-3..t; p over t-4..t;
   // c and 1/rho over t-2..t
   double rw[3], vw[3], ww[3], uw[4], pw[5], cw[3], iw[3];
@@ -233,15 +247,22 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   unsigned nfl = 0;
   // prefetch cell 0
   double nx0 = pr_[0], nx1 = pn_[0], nx2 = p1_[0], nx3 = p2_[0], nx4 = pe_[0];
-  for (int c = 0; c < M; c++) {
+  // One cell of the walk.  The walk is split into a head (cells 0..5: no
+  // update yet; the lower coarse-fine face flux), a body in which every cell
+  // issues the same loads and stores (so that waiting for the prefetched cell
+  // never waits for the previous cell's stores) and the last cell (the upper
+  // face flux).
+  auto cell = [&](const int c, auto phase) __attribute__((always_inline)) {
+    constexpr int PH = decltype(phase)::value;
+    double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;
+    if (PH > 0) {  // the cell updated here, c-3, loaded ahead of the prefetch
+      const int64_t o = int64_t(c - 3) * SD;
+      h0 = pr_[o]; h1 = pn_[o]; h2 = p1_[o]; h3 = p2_[o]; h4 = pe_[o];
+    }
     const double U0 = nx0, U1 = nx1, U2 = nx2, U3 = nx3, U4 = nx4;
-    if (c + 1 < M) {
+    if (PH < 2) {
       const int64_t o = int64_t(c + 1) * SD;
       nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
-    }
-    if (OOP && (c < G || c >= G + N)) {  // cells the sweep does not update pass through
-      const int64_t o = int64_t(c) * SD;
-      qr_[o] = U0; qn_[o] = U1; q1_[o] = U2; q2_[o] = U3; qe_[o] = U4;
     }
     // primitives of cell c
     const double ir = 1.0 / U0;
@@ -256,7 +277,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
     pw[0] = pw[1]; pw[1] = pw[2]; pw[2] = pw[3]; pw[3] = pw[4]; pw[4] = p;
     cw[0] = cw[1]; cw[1] = cw[2]; cw[2] = cs;
     iw[0] = iw[1]; iw[1] = iw[2]; iw[2] = ir;
-    if (c < 2) continue;
+    if (PH == 0 && c < 2) return;
     // slope of cell c-1
 #pragma unroll
     for (int q = 0; q < 5; q++) dl[q][0] = dl[q][1];
@@ -265,7 +286,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
     dl[2][1] = mc_slope(vw[0], vw[1], vw[2]);
     dl[3][1] = mc_slope(ww[0], ww[1], ww[2]);
     dl[4][1] = mc_slope(pw[2], pw[3], pw[4]);
-    if (c < 3) continue;
+    if (PH == 0 && c < 3) return;
     // face value at (c-2)+1/2
     double fnew[5];
     fnew[0] = 0.5 * (rw[0] + rw[1]) - (dl[0][1] - dl[0][0]) * sixth;
@@ -273,7 +294,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
     fnew[2] = 0.5 * (vw[0] + vw[1]) - (dl[2][1] - dl[2][0]) * sixth;
     fnew[3] = 0.5 * (ww[0] + ww[1]) - (dl[3][1] - dl[3][0]) * sixth;
     fnew[4] = 0.5 * (pw[2] + pw[3]) - (dl[4][1] - dl[4][0]) * sixth;
-    if (c >= 4) {
+    if (PH > 0 || c >= 4) {
       // cell j = c-2: flattening, parabolas, tracing
       const double pp1 = pw[3], pm1 = pw[1];
       const double dp1 = pp1 - pm1;
@@ -293,28 +314,28 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
       pa[4] = parabola(pw[2], fold[4], fnew[4], f, sixth);
       double WL[5], WR[5];
       trace(ip, rw[0], uw[1], cw[0], iw[0], pa, nu, WL, WR);
-      if (c >= 5) {
+      if (PH > 0 || c >= 5) {
         // flux at (c-3)+1/2 from cell c-3's right edge and cell c-2's left
         double F[5];
         riemann_flux(ip, WLp, WR, F);
-        if (c == G + 2 && slot_lo >= 0) {
+        if (PH == 0 && slot_lo >= 0) {  // c = G+2: lower face of the active cells
           double* fo = P.faces + int64_t(slot_lo) * kFields * N * N + face_off;
           fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
           fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
         }
-        if (c == N + G + 2 && slot_hi >= 0) {
+        if (PH == 2 && slot_hi >= 0) {  // c = N+G+2: upper face
           double* fo = P.faces + int64_t(slot_hi) * kFields * N * N + face_off;
           fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
           fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
         }
-        if (c >= 6) {
+        if (PH > 0) {
           // conservative update of cell c-3, then the floors
           const int64_t o = int64_t(c - 3) * SD;
-          double r0 = pr_[o] - nu * (F[0] - Fp[0]);
-          const double m1 = pn_[o] - nu * (F[1] - Fp[1]);
-          const double m2 = p1_[o] - nu * (F[2] - Fp[2]);
-          const double m3 = p2_[o] - nu * (F[3] - Fp[3]);
-          double e = pe_[o] - nu * (F[4] - Fp[4]);
+          double r0 = h0 - nu * (F[0] - Fp[0]);
+          const double m1 = h1 - nu * (F[1] - Fp[1]);
+          const double m2 = h2 - nu * (F[2] - Fp[2]);
+          const double m3 = h3 - nu * (F[3] - Fp[3]);
+          double e = h4 - nu * (F[4] - Fp[4]);
           if (r0 < rfl) { r0 = rfl; nfl++; }
           const double jr = 1.0 / r0;
           const double a1 = m1 * jr, a2 = m2 * jr, a3 = m3 * jr;
@@ -331,7 +352,14 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
     }
 #pragma unroll
     for (int q = 0; q < 5; q++) fold[q] = fnew[q];
-  }
+  };
+  static_assert(G == 3, "the walk's head covers cells 0..2G-1");
+  for (int c = 0; c < 2 * G; c++) cell(c, std::integral_constant<int, 0>{});
+  // one full wait on entry to the body: its loop then starts from the same
+  // outstanding-memory state on every pass
+  __builtin_amdgcn_s_waitcnt(0);
+  for (int c = 2 * G; c < M - 1; c++) cell(c, std::integral_constant<int, 1>{});
+  cell(M - 1, std::integral_constant<int, 2>{});
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
@@ -693,7 +721,7 @@ hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const dou
     else
       hipLaunchKernelGGL((sweep_staged<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB);
   } else {
-    const int64_t n = P.nleaf * int64_t(nA) * nB;
+    const int64_t n = P.nleaf * ((int64_t(nA) * nB + 63) / 64) * 64;  // whole waves per leaf
     const dim3 g(grid_for(n, L.sweep_block)), b(L.sweep_block);
     if (oop)
       hipLaunchKernelGGL((sweep_kernel_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);

@@ -61,24 +61,31 @@ AMR_HD inline void prim_vjp(const InstParams& ip, const double* U, const Prim& P
 
 AMR_HD inline void slope_vjp(double qm, double q0, double qp, double g, double* gm, double* g0, double* gp) {
   const double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
-  if (!(dl * dr > 0.0)) return;
-  const double adc = fabs(dc), a2l = 2.0 * fabs(dl), a2r = 2.0 * fabs(dr);
-  const double sg = dc > 0.0 ? 1.0 : -1.0;
-  // which term the selects min(min(|dc|, 2|dl|), 2|dr|) returned
-  const double m1 = adc < a2l ? adc : a2l;
-  if (!(m1 < a2r)) {  // 2|dr|
-    const double d = sg * 2.0 * (dr > 0.0 ? 1.0 : -1.0) * g;
-    *gp += d;
-    *g0 -= d;
-  } else if (adc < a2l) {  // |dc|
-    const double d = sg * (dc > 0.0 ? 1.0 : -1.0) * 0.5 * g;
-    *gp += d;
-    *gm -= d;
-  } else {  // 2|dl|
-    const double d = sg * 2.0 * (dl > 0.0 ? 1.0 : -1.0) * g;
-    *g0 += d;
-    *gm -= d;
+  // every branch sets all three increments and the adds are unconditional,
+  // so the accumulators stay in registers (no store through a chosen pointer)
+  double em = 0.0, e0 = 0.0, ep = 0.0;
+  if (dl * dr > 0.0) {
+    const double adc = fabs(dc), a2l = 2.0 * fabs(dl), a2r = 2.0 * fabs(dr);
+    const double sg = dc > 0.0 ? 1.0 : -1.0;
+    // which term the selects min(min(|dc|, 2|dl|), 2|dr|) returned
+    const double m1 = adc < a2l ? adc : a2l;
+    if (!(m1 < a2r)) {  // 2|dr|
+      const double d = sg * 2.0 * (dr > 0.0 ? 1.0 : -1.0) * g;
+      ep = d;
+      e0 = -d;
+    } else if (adc < a2l) {  // |dc|
+      const double d = sg * (dc > 0.0 ? 1.0 : -1.0) * 0.5 * g;
+      ep = d;
+      em = -d;
+    } else {  // 2|dl|
+      const double d = sg * 2.0 * (dl > 0.0 ? 1.0 : -1.0) * g;
+      e0 = d;
+      em = -d;
+    }
   }
+  *gm += em;
+  *g0 += e0;
+  *gp += ep;
 }
 
 // ---- parabola ------------------------------------------------------------
