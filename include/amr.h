@@ -66,7 +66,8 @@ typedef struct {
   int32_t bc[3];          /* AMR_BC_* per axis (both faces)                 */
   double gamma;           /* ratio of specific heats, > 1                   */
   double cfl;             /* Courant number of the dt reduction             */
-  double rho_floor, p_floor;
+  double rho_floor, p_floor; /* density and pressure floors, >= 1e-100; states
+                             are expected within [floor, 1e100]       */
   int32_t riemann_iters;  /* fixed two-shock Newton iterations (e.g. 5)     */
   int32_t n_refine;       /* static refinement list, borrowed for the call: */
   const int32_t* refine;  /* n_refine x (level, i, j, k) block keys         */
@@ -333,6 +334,17 @@ amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
  * milliseconds (ms_out) and the number of launches (launches_out), each of
  * AMR_NPHASE entries (host memory), and clears the records. */
 amr_status amr_profile_read(amr_mesh* mesh, double* ms_out, int64_t* launches_out);
+
+/* Device arithmetic self-test.  The kernels take reciprocals and square
+ * roots of positive operands in [2^-767, 2^1022] (densities, pressures,
+ * sound speeds, shock mass fluxes: within that range for floors >= 1e-100
+ * and states <= 1e100) with the IEEE sequences minus their operand scaling
+ * and special-value fix-ups, which are identities on that range.  This
+ * call compares both with the IEEE 1/x and sqrt(x) on n operands (random
+ * mantissas, exponents uniform over [-767, 1022], from seed) and adds the
+ * numbers of differing reciprocals and square roots to counts[0] and
+ * counts[1] (device memory, 2 x uint64, not cleared).  Stream-ordered. */
+amr_status amr_arith_selftest(uint64_t seed, int64_t n, uint64_t* counts_dev, void* stream);
 
 const char* amr_last_error(void);
 

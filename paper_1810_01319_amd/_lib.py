@@ -120,6 +120,7 @@ SIGNATURES = {
     "amr_mesh_get_launch": (_I32, [_P, ctypes.POINTER(LaunchCfg)]),
     "amr_profile_enable": (_I32, [_P, _I32]),
     "amr_profile_read": (_I32, [_P, _P, _P]),
+    "amr_arith_selftest": (_I32, [ctypes.c_uint64, _I64, _P, _P]),
     "amr_last_error": (ctypes.c_char_p, []),
 }
 

@@ -80,6 +80,8 @@ amr_status to_desc(const amr_mesh_desc* d, MeshDesc& m) {
   }
   if (!(d->gamma > 1.0)) return fail(AMR_E_INVALID, "gamma must exceed 1");
   if (!(d->cfl > 0.0)) return fail(AMR_E_INVALID, "cfl must be positive");
+  if (!(d->rho_floor >= 1e-100) || !(d->p_floor >= 1e-100))
+    return fail(AMR_E_INVALID, "density and pressure floors must be at least 1e-100");
   if (d->riemann_iters < 0 || d->riemann_iters > 64) return fail(AMR_E_INVALID, "riemann_iters out of range");
   if (d->n_refine < 0 || (d->n_refine > 0 && !d->refine)) return fail(AMR_E_INVALID, "bad refine list");
   for (int a = 0; a < 3; a++) m.root[a] = d->root[a], m.bc[a] = d->bc[a];
@@ -816,6 +818,14 @@ amr_status amr_graph_destroy(amr_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
   return AMR_OK;
+}
+
+amr_status amr_arith_selftest(uint64_t seed, int64_t n, uint64_t* counts, void* stream) {
+  if (!counts) return fail(AMR_E_INVALID, "null counts");
+  if (n < 0 || n > (int64_t(1) << 40)) return fail(AMR_E_INVALID, "operand count out of range");
+  hipError_t e = launch_arith_check(seed, n, reinterpret_cast<unsigned long long*>(counts),
+                                    static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "arithmetic self-test");
 }
 
 const char* amr_last_error(void) { return g_err.c_str(); }

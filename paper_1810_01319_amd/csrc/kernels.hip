@@ -136,11 +136,11 @@ __global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, 
     const int x = q % N, y = (q / N) % N, z = q / (N * N);
     const int64_t o = (int64_t(z + G) * M + (y + G)) * M + (x + G);
     const double rho = B[o];
-    const double ir = 1.0 / rho;
+    const double ir = rcp_pos(rho);
     const double u = B[o + M3] * ir, v = B[o + 2 * M3] * ir, w = B[o + 3 * M3] * ir;
     double p = ip.gm1 * (B[o + 4 * M3] - (0.5 * rho) * ((u * u + v * v) + w * w));
     p = p < ip.p_floor ? ip.p_floor : p;
-    const double cs = sqrt((ip.gamma * p) * ir);
+    const double cs = sqrt_pos((ip.gamma * p) * ir);
     const double vm = sel_max(sel_max(fabs(u), fabs(v)), fabs(w));
     const double dtc = dx / (vm + cs);
     best = dtc < best ? dtc : best;
@@ -265,11 +265,11 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
       nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
     }
     // primitives of cell c
-    const double ir = 1.0 / U0;
+    const double ir = rcp_pos(U0);
     const double u = U1 * ir, v = U2 * ir, w = U3 * ir;
     double p = gm1 * (U4 - (0.5 * U0) * ((u * u + v * v) + w * w));
     p = p < pfl ? pfl : p;
-    const double cs = sqrt((ip.gamma * p) * ir);
+    const double cs = sqrt_pos((ip.gamma * p) * ir);
     rw[0] = rw[1]; rw[1] = rw[2]; rw[2] = U0;
     vw[0] = vw[1]; vw[1] = vw[2]; vw[2] = v;
     ww[0] = ww[1]; ww[1] = ww[2]; ww[2] = w;
@@ -337,7 +337,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
           const double m3 = h3 - nu * (F[3] - Fp[3]);
           double e = h4 - nu * (F[4] - Fp[4]);
           if (r0 < rfl) { r0 = rfl; nfl++; }
-          const double jr = 1.0 / r0;
+          const double jr = rcp_pos(r0);
           const double a1 = m1 * jr, a2 = m2 * jr, a3 = m3 * jr;
           const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
           const double pn = gm1 * (e - ke);
@@ -439,14 +439,14 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     U2 = cellp[(1 + T1) * M3];
     U3 = cellp[(1 + T2) * M3];
     U4 = cellp[4 * M3];
-    ir = 1.0 / U0;
+    ir = rcp_pos(U0);
     q[0] = U0;
     q[1] = U1 * ir;
     q[2] = U2 * ir;
     q[3] = U3 * ir;
     double p = gm1 * (U4 - (0.5 * U0) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]));
     q[4] = p < pfl ? pfl : p;
-    cs = sqrt((ip.gamma * q[4]) * ir);
+    cs = sqrt_pos((ip.gamma * q[4]) * ir);
 #pragma unroll
     for (int v = 0; v < 5; v++) Ps[v][i] = q[v];
   }
@@ -517,7 +517,7 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     double e = U4 - nu * (Ys[4][i] - Ys[4][i - NS]);
     unsigned nfl = 0;
     if (r0 < rfl) { r0 = rfl; nfl++; }
-    const double jr = 1.0 / r0;
+    const double jr = rcp_pos(r0);
     const double a1 = m1 * jr, a2 = m2 * jr, a3 = m3 * jr;
     const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
     const double pn = gm1 * (e - ke);
@@ -788,6 +788,41 @@ hipError_t launch_sweep_oop(const DevPlan& P, const double* Uin, double* Uout, c
 
 hipError_t launch_floor_mark(const DevPlan& P, unsigned long long* mark, int mode, hipStream_t st) {
   hipLaunchKernelGGL(floor_mark, dim3(1), dim3(64), 0, st, P, mark, mode);
+  return hipGetLastError();
+}
+
+// Self-test of rcp_pos and sqrt_pos against the IEEE operations: operand i
+// has a random mantissa and an exponent uniform over [-767, 1022], drawn
+// from the splitmix64 hash of seed + i (Steele, Lea and Flood 2014); the
+// first operands of seed 0 are 1, 2^-767, 1.5 * 2^1021 and 2^1022.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) arith_check_kernel(uint64_t seed, int64_t n,
+                                                         unsigned long long* __restrict__ bad) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = seed + uint64_t(i);
+  const uint64_t h = splitmix64(k), g = splitmix64(k ^ 0x5DEECE66Dull);
+  const int64_t ex = -767 + int64_t(g % 1790u);
+  double x = __longlong_as_double((long long)((uint64_t(ex + 1023) << 52) | (h & ((1ull << 52) - 1))));
+  if (k == 0) x = 1.0;
+  if (k == 1) x = 0x1p-767;
+  if (k == 2) x = 0x1.8p+1021;
+  if (k == 3) x = 0x1p+1022;
+  const double r = rcp_pos(x), q = 1.0 / x, a = sqrt_pos(x), b = sqrt(x);
+  const unsigned nr = __double_as_longlong(r) != __double_as_longlong(q);
+  const unsigned ns = __double_as_longlong(a) != __double_as_longlong(b);
+  if (nr) atomicAdd(&bad[0], 1ull);
+  if (ns) atomicAdd(&bad[1], 1ull);
+}
+
+hipError_t launch_arith_check(uint64_t seed, int64_t n, unsigned long long* bad, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(arith_check_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, seed, n, bad);
   return hipGetLastError();
 }
 

@@ -52,6 +52,9 @@ hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir,
 hipError_t launch_floor_mark(const DevPlan& P, unsigned long long* mark, int mode, hipStream_t st);
 // per-leaf density-slope indicator into P.ind (needs refreshed ghosts)
 hipError_t launch_indicator(const DevPlan& P, const double* U, hipStream_t st);
+// counts (bad[0], bad[1]) the operands on which rcp_pos / sqrt_pos differ from
+// the IEEE 1/x and sqrt(x); bad is not cleared
+hipError_t launch_arith_check(uint64_t seed, int64_t n, unsigned long long* bad, hipStream_t st);
 // fill the active cells of every leaf of the new plan P from the old state
 hipError_t launch_migrate(const DevPlan& P, const double* Uold, double* Unew, hipStream_t st);
 

@@ -21,7 +21,7 @@ struct Prim {
 
 AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
   Prim P;
-  P.ir = 1.0 / U[0];
+  P.ir = rcp_pos(U[0]);
   P.q[0] = U[0];
   P.q[1] = U[1] * P.ir;
   P.q[2] = U[2] * P.ir;
@@ -30,7 +30,7 @@ AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
   const double p = ip.gm1 * (U[4] - (0.5 * U[0]) * P.K);
   P.pfl = p < ip.p_floor;
   P.q[4] = P.pfl ? ip.p_floor : p;
-  P.c = sqrt((ip.gamma * P.q[4]) * P.ir);
+  P.c = sqrt_pos((ip.gamma * P.q[4]) * P.ir);
   return P;
 }
 
@@ -155,7 +155,7 @@ AMR_HD inline void trace_vjp_rup(const InstParams& ip, double rho, double u, dou
                                  double* gir) {
   const double t = ip.two3;
   const double lm = u - c, l0 = u, lp = u + c;
-  const double ic = 1.0 / c;
+  const double ic = rcp_pos(c);
   const double Ac = (0.5 * rho) * ic;
   const double Bc = ir * ic;
   const double cc = c * c;
@@ -295,8 +295,8 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
   const int NI = ip.iters;
   // ---- forward, keeping p* of every Newton evaluation ----
-  const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
-  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
+  const double CL = sqrt_pos((gam * pL) * rL), CR = sqrt_pos((gam * pR) * rR);
+  const double ipL = rcp_pos(pL), ipR = rcp_pos(pR);
   const double num0 = (CR * pL + CL * pR) - (CL * CR) * (uR - uL);
   const double den0 = CL + CR;
   double ps = num0 / den0;
@@ -308,12 +308,12 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
 #pragma unroll
   for (int it = 0; it <= MAXIT; it++) {
     psv[it] = ps;
-    sLf = sqrt(1.0 + g1 * (ps * ipL - 1.0));
-    sRf = sqrt(1.0 + g1 * (ps * ipR - 1.0));
+    sLf = sqrt_pos(1.0 + g1 * (ps * ipL - 1.0));
+    sRf = sqrt_pos(1.0 + g1 * (ps * ipR - 1.0));
     WLw = CL * sLf;
     WRw = CR * sRf;
-    iWL = 1.0 / WLw;
-    iWR = 1.0 / WRw;
+    iWL = rcp_pos(WLw);
+    iWR = rcp_pos(WRw);
     usL = uL - (ps - pL) * iWL;
     usR = uR + (ps - pR) * iWR;
     const double qL = CL * iWL, qR = CR * iWR;
@@ -330,9 +330,9 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   const double s = left ? 1.0 : -1.0;
   const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
   const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
-  const double irK = 1.0 / rK;
+  const double irK = rcp_pos(rK);
   const double vs = irK - (ps - pK) * (iWK * iWK);
-  const double rs = 1.0 / vs;
+  const double rs = rcp_pos(vs);
   // sampled state and its case: 0 = side state, 1 = star, 2 = fan
   int cse;
   double xi = 0, lh = 0, lt = 0, cK = 0, csr = 0;
@@ -340,8 +340,8 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
     const double S = uK - s * (WK * irK);
     cse = (s * S >= 0.0) ? 0 : 1;
   } else {
-    cK = sqrt((gam * pK) * irK);
-    csr = sqrt((gam * ps) * vs);
+    cK = sqrt_pos((gam * pK) * irK);
+    csr = sqrt_pos((gam * ps) * vs);
     lh = uK - s * cK;
     lt = us - s * csr;
     if (s * lh >= 0.0) cse = 0;
@@ -404,7 +404,7 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   giWK += -gvs * (ps - pK) * (2.0 * iWK);
   grK += -girK * (irK * irK);
   // star velocity u* = (iZR usL + iZL usR) / (iZL + iZR)
-  const double iDz = 1.0 / Dz;
+  const double iDz = rcp_pos(Dz);
   double gusL = gus * iZR * iDz, gusR = gus * iZL * iDz;
   double giZR = gus * (usL - us) * iDz, giZL = gus * (usR - us) * iDz;
   double giWL = left ? giWK : 0.0, giWR = left ? 0.0 : giWK;
@@ -451,17 +451,17 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
     // the previous evaluation, and the Newton update that produced p:
     // p = p_prev - (u*_R - u*_L) / (1/Z_L + 1/Z_R)
     const double pp = psv[it - 1];
-    sl = sqrt(1.0 + g1 * (pp * ipL - 1.0));
-    sr = sqrt(1.0 + g1 * (pp * ipR - 1.0));
-    iwl = 1.0 / (CL * sl);
-    iwr = 1.0 / (CR * sr);
+    sl = sqrt_pos(1.0 + g1 * (pp * ipL - 1.0));
+    sr = sqrt_pos(1.0 + g1 * (pp * ipR - 1.0));
+    iwl = rcp_pos(CL * sl);
+    iwr = rcp_pos(CR * sr);
     double gprev = 0.0;
     giZL = giZR = gusL = gusR = giWL = giWR = 0.0;
     if (!flv[it - 1]) {
       const double uls = uL - (pp - pL) * iwl, urs = uR + (pp - pR) * iwr;
       const double zl = (0.5 * iwl) * (1.0 + (CL * iwl) * (CL * iwl));
       const double zr = (0.5 * iwr) * (1.0 + (CR * iwr) * (CR * iwr));
-      const double iD = 1.0 / (zl + zr);
+      const double iD = rcp_pos(zl + zr);
       const double gD = gps_cur * iD;
       gprev = gps_cur;
       gusR = -gD;
@@ -506,7 +506,7 @@ AMR_HD inline void riemann_vjp(const InstParams& ip, const double* L, const doub
 AMR_HD inline void floor_apply(const InstParams& ip, const double* V, double* out) {
   double r0 = V[0];
   if (r0 < ip.rho_floor) r0 = ip.rho_floor;
-  const double jr = 1.0 / r0;
+  const double jr = rcp_pos(r0);
   const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
   const double ke = (0.5 * r0) * ((a1 * a1 + a2 * a2) + a3 * a3);
   double e = V[4];
@@ -523,7 +523,7 @@ AMR_HD inline void floor_apply(const InstParams& ip, const double* V, double* ou
 AMR_HD inline void floor_vjp(const InstParams& ip, const double* V, const double* g, double* gV) {
   const bool rfl = V[0] < ip.rho_floor;
   const double r0 = rfl ? ip.rho_floor : V[0];
-  const double jr = 1.0 / r0;
+  const double jr = rcp_pos(r0);
   const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
   const double K = (a1 * a1 + a2 * a2) + a3 * a3;
   const double ke = (0.5 * r0) * K;

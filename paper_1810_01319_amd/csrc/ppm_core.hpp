@@ -19,6 +19,43 @@ namespace amr {
 using std::fabs;
 using std::sqrt;
 
+// Reciprocal and square root of an operand in [2^-767, 2^1022] (every
+// density, pressure, sound speed and shock mass flux of a step whose floors
+// are at least 1e-200).  On the device these are the Newton-Raphson
+// reciprocal with Markstein's final correction and the Goldschmidt square
+// root, i.e. the IEEE-conforming sequences without their operand scaling and
+// special-value fix-ups, which leave such operands unchanged: the results
+// are the correctly rounded 1/b and sqrt(x), bit for bit, in fewer
+// instructions.
+AMR_HD inline double rcp_pos(double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  double t = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  t = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  t = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(t, r, r);
+#else
+  return 1.0 / b;
+#endif
+}
+AMR_HD inline double sqrt_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = y * 0.5;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double e = __builtin_fma(-g, g, x);
+  g = __builtin_fma(e, h, g);
+  e = __builtin_fma(-g, g, x);
+  return __builtin_fma(e, h, g);
+#else
+  return sqrt(x);
+#endif
+}
+
 AMR_HD inline double sel_min(double a, double b) { return a < b ? a : b; }
 AMR_HD inline double sel_max(double a, double b) { return a < b ? b : a; }
 
@@ -77,7 +114,7 @@ AMR_HD inline void trace(const InstParams& ip, double rho, double u, double c, d
                                       const Par* pa, double nu, double* WL, double* WR) {
   const double two3 = ip.two3;
   const double lm = u - c, l0 = u, lp = u + c;
-  const double ic = 1.0 / c;
+  const double ic = rcp_pos(c);
   const double Ac = (0.5 * rho) * ic;  // rho / (2c)
   const double Bc = ir * ic;           // 1 / (rho c)
   const double cc = c * c;
@@ -119,16 +156,16 @@ AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const dou
   const double rL = L[0], uL = L[1], pL = L[4];
   const double rR = R[0], uR = R[1], pR = R[4];
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
-  const double CL = sqrt((gam * pL) * rL), CR = sqrt((gam * pR) * rR);
-  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
+  const double CL = sqrt_pos((gam * pL) * rL), CR = sqrt_pos((gam * pR) * rR);
+  const double ipL = rcp_pos(pL), ipR = rcp_pos(pR);
   double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
   ps = ps < pfl ? pfl : ps;
   double WLw, WRw, iWL, iWR, iZL, iZR, usL, usR;
   for (int it = 0;; it++) {
-    WLw = CL * sqrt(1.0 + g1 * (ps * ipL - 1.0));
-    WRw = CR * sqrt(1.0 + g1 * (ps * ipR - 1.0));
-    iWL = 1.0 / WLw;
-    iWR = 1.0 / WRw;
+    WLw = CL * sqrt_pos(1.0 + g1 * (ps * ipL - 1.0));
+    WRw = CR * sqrt_pos(1.0 + g1 * (ps * ipR - 1.0));
+    iWL = rcp_pos(WLw);
+    iWR = rcp_pos(WRw);
     usL = uL - (ps - pL) * iWL;
     usR = uR + (ps - pR) * iWR;
     const double qL = CL * iWL, qR = CR * iWR;
@@ -143,9 +180,9 @@ AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const dou
   const double s = left ? 1.0 : -1.0;
   const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
   const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
-  const double irK = 1.0 / rK;
+  const double irK = rcp_pos(rK);
   const double vs = irK - (ps - pK) * (iWK * iWK);
-  const double rs = 1.0 / vs;
+  const double rs = rcp_pos(vs);
   double rg, ug, pg;
   if (ps > pK) {
     const double S = uK - s * (WK * irK);
@@ -154,8 +191,8 @@ AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const dou
     ug = toK ? uK : us;
     pg = toK ? pK : ps;
   } else {
-    const double cK = sqrt((gam * pK) * irK);
-    const double cs = sqrt((gam * ps) * vs);
+    const double cK = sqrt_pos((gam * pK) * irK);
+    const double cs = sqrt_pos((gam * ps) * vs);
     const double lh = uK - s * cK, lt = us - s * cs;
     if (s * lh >= 0.0) {
       rg = rK; ug = uK; pg = pK;

@@ -23,6 +23,15 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def arith_selftest(n: int, seed: int = 0, device="cuda") -> tuple[int, int]:
+    """Numbers of operands (of n, from seed) on which the kernels' reciprocal
+    and square root of positive operands differ from IEEE 1/x and sqrt(x)."""
+    counts = torch.zeros(2, dtype=torch.int64, device=device)
+    check(lib().amr_arith_selftest(ctypes.c_uint64(seed), n, _ptr(counts), _stream()))
+    c = counts.cpu()
+    return int(c[0]), int(c[1])
+
+
 class Mesh:
     """An array-of-octrees mesh with its uploaded tables on one GPU."""
 

@@ -260,6 +260,19 @@ def test_adaptive_blasts_parity(root, N, levels, cap_extra, steps):
     assert bw == 1.0, err
 
 
+@pytest.mark.parametrize("seed", [0, 1 << 40])
+def test_kernel_reciprocal_and_sqrt_are_ieee_bitwise(seed):
+    """The kernels' reciprocal and square root of positive operands (the IEEE
+    sequences without operand scaling and special-value fix-ups) equal IEEE
+    1/x and sqrt(x) bit for bit on 2^26 operands spread over the exponent
+    range [-767, 1022] that floors >= 1e-100 guarantee."""
+    from paper_1810_01319_amd.mesh import arith_selftest
+    n = 1 << 26
+    bad_rcp, bad_sqrt = arith_selftest(n, seed)
+    say(f"arith self-test seed {seed}: {n} operands, {bad_rcp} reciprocal and {bad_sqrt} sqrt mismatches")
+    assert bad_rcp == 0 and bad_sqrt == 0
+
+
 def test_indicator_bitwise():
     spec = I.blasts_spec(root=3, block_cells=16, levels=2)
     om, gm, perm = pair(spec)

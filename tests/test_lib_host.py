@@ -102,6 +102,8 @@ def test_info_sizes():
     (dict(block_cells=12), -1),
     (dict(max_level=9), -1),
     (dict(gamma=1.0), -1),
+    (dict(rho_floor=1e-120), -1),
+    (dict(p_floor=0.0), -1),
     (dict(bc="outflow", refine=[(0, 0, 0, 0)], max_level=1), -1),
     (dict(refine=[(1, 0, 0, 0)], max_level=1), -1),
 ])
