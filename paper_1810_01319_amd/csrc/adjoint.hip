@@ -88,7 +88,9 @@ struct AdjShape {
 // recompute that detects them).  Both variants are launched; each returns at
 // once unless the forward step's floor-reset count (null: unknown) selects it.
 // Registers are capped for 3 waves per SIMD (a few bytes of spill cost less
-// than the lost occupancy).
+// than the lost occupancy).  The cell's state and adjoint are read together
+// at the start (the adjoint parked in LDS until the reverse pass) and again
+// one phase before the end, so that their latency overlaps computation.
 template <int N, int DIR, bool FLOORS>
 __global__ void __launch_bounds__((AdjShape<N, DIR>::WG)) __attribute__((amdgpu_waves_per_eu(3)))
 sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const double* __restrict__ dtv, DevPlan P,
@@ -122,7 +124,7 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   const int c = DIR == 0 ? i - r * M : i / R;
   const bool live = i < T && a0 + r < nA;
   const BlockInfo bi = P.blocks[s];
-  const InstParams& ip = P.inst[bi.inst];
+  const InstParams ip = P.inst[bi.inst];  // by value: read once, before any store
   const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
   const int iA = loA + a0 + r;
   const int64_t off = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
@@ -141,12 +143,20 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   // keeps the left states in Xs (free between the face values and the trace
   // adjoint).
   if (live) {
-    double u5[5];
+    // the cell's adjoint is read with its state (one memory round trip) and
+    // waits in Ls, which the forward recompute does not use
+    double u5[5], l5[5];
 #pragma unroll
-    for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
+    for (int v = 0; v < 5; v++) {
+      u5[v] = ucell[fmap[v] * M3];
+      l5[v] = lcell[fmap[v] * M3];
+    }
     const Prim Pr = prim_fwd(ip, u5);
 #pragma unroll
-    for (int v = 0; v < 5; v++) Ps[v][i] = Pr.q[v];
+    for (int v = 0; v < 5; v++) {
+      Ps[v][i] = Pr.q[v];
+      Ls[v][i] = l5[v];
+    }
     Fl[0][i] = Pr.c;
     Fl[1][i] = Pr.ir;
   }
@@ -214,7 +224,7 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   if (live) {
     if (FLOORS) {
 #pragma unroll
-      for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
+      for (int v = 0; v < 5; v++) li[v] = Ls[v][i];
       if (active) {
         double V[5];
 #pragma unroll
@@ -223,9 +233,9 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
       }
 #pragma unroll
       for (int v = 0; v < 5; v++) Ls[v][i] = active ? li[v] : 0.0;
-    } else {
+    } else if (!active) {
 #pragma unroll
-      for (int v = 0; v < 5; v++) Ls[v][i] = active ? lcell[fmap[v] * M3] : 0.0;
+      for (int v = 0; v < 5; v++) Ls[v][i] = 0.0;
     }
   }
   __syncthreads();
@@ -320,8 +330,17 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
     Fl[1][i] = gd2;
   }
   __syncthreads();
-  // face values at c+-1/2, flattening, then the own slope
+  // face values at c+-1/2, flattening, then the own slope; the state and
+  // (floor-free variant) the adjoint of the cell, needed at the end, are
+  // read here so that the two phases hide their latency
+  double u5e[5] = {0, 0, 0, 0, 0};
   if (live) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) u5e[v] = ucell[fmap[v] * M3];
+    if (!FLOORS) {
+#pragma unroll
+      for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
+    }
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       const double ghi = (c >= 1 && c <= M - 3) ? Ls[v][i] + Xs[v][i + NS] : 0.0;
@@ -350,15 +369,9 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
       if (c >= 1) gq[v] += Ws[v][i - NS];
       if (c + 1 < M) gq[v] += Ys[v][i + NS];
     }
-    double u5[5], gU[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int v = 0; v < 5; v++) u5[v] = ucell[fmap[v] * M3];
-    const Prim Pr = prim_fwd(ip, u5);
-    prim_vjp(ip, u5, Pr, gq, gc, gir, gU);
-    if (!FLOORS) {
-#pragma unroll
-      for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
-    }
+    double gU[5] = {0, 0, 0, 0, 0};
+    const Prim Pr = prim_fwd(ip, u5e);
+    prim_vjp(ip, u5e, Pr, gq, gc, gir, gU);
 #pragma unroll
     for (int v = 0; v < 5; v++) lcell[fmap[v] * M3] = li[v] + gU[v];
   }
