@@ -455,7 +455,7 @@ void orc_refresh(orc_mesh* m) {
 /* dt = C_cfl * min over active leaf cells of dx_l / (max_d |u_d| + c); the
  * min over d of dx/(|u_d|+c) equals this because correctly rounded + and /
  * are monotone.  Primitive recovery as in the sweeps, x,y,z order. */
-double orc_cfl_dt(const orc_mesh* m) {
+static double cfl_min(const orc_mesh* m) {
   const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
   const int N = m->N, M = m->M;
   double best = INFINITY;
@@ -478,8 +478,10 @@ double orc_cfl_dt(const orc_mesh* m) {
           best = t < best ? t : best;
         }
   }
-  return m->d.cfl * best;
+  return best;
 }
+
+double orc_cfl_dt(const orc_mesh* m) { return m->d.cfl * cfl_min(m); }
 
 /* ------------------------------------------------------------------ */
 /* PPM pencil (Sec. II-C, "ppm"; Colella & Woodward 1984 as modified)  */
@@ -841,6 +843,68 @@ double orc_step(orc_mesh* m, int64_t step_index) {
   double dt = orc_cfl_dt(m);
   orc_step_dt(m, step_index, dt);
   return dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Comoving coordinates (Sec. II-C: the ppm Method with cosmological     */
+/* comoving expansion terms, Bryan et al. 1995)                          */
+/* ------------------------------------------------------------------ */
+/* Readings: x is the comoving position, v the peculiar velocity and a(t)
+ * the expansion factor.  The flux divergence carries 1/a, so a step with dt
+ * runs the plain sweeps and reflux with the effective dt / a (nu = (dt / a)
+ * / dx), and a signal crosses a comoving cell in a dx / (|v| + c): the CFL
+ * dt is (C_cfl * a) * min dx / (max_d |v_d| + c).  The expansion sources
+ * dv/dt = -H v and d(rho e)/dt = -3 (gamma - 1) H rho e (H = adot / a; rho
+ * is the comoving density and does not change) are applied after the reflux
+ * with Crank-Nicolson factors at the step's mid time, c = (dt / 2) H:
+ * momenta times fv = (1 - c) / (1 + c); internal energy times
+ * fe = (1 - 3 (gamma - 1) c) / (1 + 3 (gamma - 1) c); the total energy
+ * takes the two changes as E + ((ie' - ie) + ke (fv fv - 1)), so that H = 0
+ * leaves the state bit for bit.  Where the source lowered the internal
+ * energy below the pressure floor it is raised to it (counted). */
+
+double orc_cfl_dt_comoving(const orc_mesh* m, double a) { return (m->d.cfl * a) * cfl_min(m); }
+
+static void expansion(orc_mesh* m, double dt, double hubble) {
+  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  const int N = m->N, M = m->M;
+  const double c = (0.5 * dt) * hubble;
+  const double g3 = 3.0 * K.gm1;
+  const double fv = (1.0 - c) / (1.0 + c);
+  const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
+  int64_t nfl = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    double* B = block_ptr(m, s);
+    for (int z = G; z < G + N; z++)
+      for (int y = G; y < G + N; y++)
+        for (int x = G; x < G + N; x++) {
+          double* rho = &B[cell(M, 0, x, y, z)];
+          double* mx = &B[cell(M, 1, x, y, z)];
+          double* my = &B[cell(M, 2, x, y, z)];
+          double* mz = &B[cell(M, 3, x, y, z)];
+          double* E = &B[cell(M, 4, x, y, z)];
+          const double ir = 1.0 / *rho;
+          const double u = *mx * ir, v = *my * ir, w = *mz * ir;
+          const double ke = (0.5 * *rho) * ((u * u + v * v) + w * w);
+          const double ie = *E - ke;
+          double ie2 = ie * fe;
+          if (ie2 < ie && K.gm1 * ie2 < K.p_floor) {
+            ie2 = K.p_floor * K.inv_gm1;
+            nfl++;
+          }
+          *mx = *mx * fv;
+          *my = *my * fv;
+          *mz = *mz * fv;
+          *E = *E + ((ie2 - ie) + ke * (fv * fv - 1.0));
+        }
+  }
+  m->floors += nfl;
+}
+
+void orc_step_comoving(orc_mesh* m, int64_t step_index, double dt, double a, double hubble) {
+  orc_step_dt(m, step_index, dt / a);
+  expansion(m, dt, hubble);
 }
 
 /* ------------------------------------------------------------------ */

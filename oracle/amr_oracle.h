@@ -66,6 +66,11 @@ double orc_cfl_dt(const orc_mesh* m);
 double orc_step(orc_mesh* m, int64_t step_index);
 /* Same with a given dt (no CFL reduction). */
 void orc_step_dt(orc_mesh* m, int64_t step_index, double dt);
+/* Comoving coordinates (expansion factor a, H = adot / a at the step's mid
+ * time): CFL dt = (C_cfl * a) * min dx / (|v| + c); the step runs the plain
+ * step with dt / a, then the Crank-Nicolson expansion sources over dt. */
+double orc_cfl_dt_comoving(const orc_mesh* m, double a);
+void orc_step_comoving(orc_mesh* m, int64_t step_index, double dt, double a, double hubble);
 
 /* Tracer particles.  Positions in level-0 cell units: X in [0, root[0]*N)
  * etc.; a particle belongs to the leaf holding level-l cell floor(X * 2^l).

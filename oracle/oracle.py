@@ -84,6 +84,9 @@ def lib() -> ctypes.CDLL:
         L.orc_step.argtypes = [P, I64]
         L.orc_step.restype = D
         L.orc_step_dt.argtypes = [P, I64, D]
+        L.orc_cfl_dt_comoving.argtypes = [P, D]
+        L.orc_cfl_dt_comoving.restype = D
+        L.orc_step_comoving.argtypes = [P, I64, D, D, D]
         L.orc_riemann.argtypes = [P, I32, P, P, P, P, P, P]
         L.orc_pencil_flux.argtypes = [P, I32, D, I32, P, P]
         L.orc_set_debug.argtypes = [I32]
@@ -186,6 +189,15 @@ class OracleMesh:
 
     def step_dt(self, k: int, dt: float) -> None:
         lib().orc_step_dt(self._h, int(k), float(dt))
+
+    def cfl_dt_comoving(self, a: float) -> float:
+        """CFL dt in comoving coordinates with expansion factor a."""
+        return float(lib().orc_cfl_dt_comoving(self._h, float(a)))
+
+    def step_comoving(self, k: int, dt: float, a: float, hubble: float) -> None:
+        """One comoving step: the plain step with dt / a, then the expansion
+        sources over dt with H = hubble (a and H at the step's mid time)."""
+        lib().orc_step_comoving(self._h, int(k), float(dt), float(a), float(hubble))
 
     def indicator(self) -> np.ndarray:
         out = np.zeros(self.nleaf)
