@@ -145,6 +145,25 @@ amr_status amr_cfl_dt(amr_mesh* mesh, const double* U_dev, double* dt_dev, void*
 amr_status amr_hydro_step(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t step_index,
                           void* stream);
 
+/* Comoving coordinates (Sec. II-C: the ppm Method with cosmological
+ * comoving expansion terms; the terms of Bryan et al. 1995).  x is the
+ * comoving position, v the peculiar velocity, a the expansion factor and
+ * H = adot / a.  amr_cfl_dt_comoving: dt = (C_cfl * a) * min over active
+ * leaf cells of dx_l / (max_d |v_d| + c) (a > 0, finite).
+ * amr_hydro_step_comoving: with dt given on the device (e.g. from the CFL
+ * call) and a, H taken at the step's mid time, runs the plain step with
+ * dt / a (the flux divergence carries 1/a; the per-instance dt / a is kept in
+ * the workspace), then the expansion sources on every active cell with
+ * Crank-Nicolson factors, c = (dt / 2) H: momenta times (1 - c) / (1 + c),
+ * internal energy times (1 - 3 (gamma - 1) c) / (1 + 3 (gamma - 1) c), the
+ * total energy updated by both changes (H = 0 leaves the state bit for bit;
+ * where the source lowers the internal energy below the pressure floor it is
+ * raised to it and counted in amr_floor_count).  Stream-ordered; U_dev is
+ * updated in place; AMR_E_INVALID for a <= 0 or non-finite a, H. */
+amr_status amr_cfl_dt_comoving(amr_mesh* mesh, const double* U_dev, double a, double* dt_dev, void* stream);
+amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* dt_dev, int64_t step_index,
+                                   double a, double hubble, void* stream);
+
 /* The same step with dt given on the device (no CFL reduction). */
 amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,
                              int64_t step_index, void* stream);
@@ -327,7 +346,9 @@ amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 #define AMR_PHASE_ADJ_REFRESH 12
 /* tracer drift and migration (amr_hydro_step_tracers, amr_tracers_advance) */
 #define AMR_PHASE_TRACERS 13
-#define AMR_NPHASE 14
+/* expansion sources of amr_hydro_step_comoving */
+#define AMR_PHASE_EXPANSION 14
+#define AMR_NPHASE 15
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
 /* Waits for the recorded events, then writes per phase the summed kernel

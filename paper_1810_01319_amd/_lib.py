@@ -16,7 +16,8 @@ STATUS = {-1: "AMR_E_INVALID", -2: "AMR_E_BALANCE", -3: "AMR_E_NOMEM", -4: "AMR_
           -5: "AMR_E_CAPACITY", -6: "AMR_E_STATE"}
 BC = {"periodic": 0, "outflow": 1}
 PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux",
-          "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh", "tracers"]
+          "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh", "tracers",
+          "expansion"]
 
 
 class AmrError(RuntimeError):
@@ -121,6 +122,8 @@ SIGNATURES = {
     "amr_profile_enable": (_I32, [_P, _I32]),
     "amr_profile_read": (_I32, [_P, _P, _P]),
     "amr_arith_selftest": (_I32, [ctypes.c_uint64, _I64, _P, _P]),
+    "amr_cfl_dt_comoving": (_I32, [_P, _P, ctypes.c_double, _P, _P]),
+    "amr_hydro_step_comoving": (_I32, [_P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, _P]),
     "amr_last_error": (ctypes.c_char_p, []),
 }
 

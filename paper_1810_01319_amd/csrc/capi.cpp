@@ -1,6 +1,7 @@
 // capi.cpp -- extern "C" entry points declared in include/amr.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -146,6 +147,7 @@ DevPlan dev_plan(const amr_mesh* h) {
     P.nreflux[d] = int64_t(p.reflux[d].size());
   }
   P.acc = reinterpret_cast<unsigned long long*>(w + p.off.acc);
+  P.dte = reinterpret_cast<double*>(w + p.off.dte);
   P.counters = reinterpret_cast<unsigned long long*>(w + p.off.counters);
   P.ind = reinterpret_cast<double*>(w + p.off.ind);
   P.migr = reinterpret_cast<const MigrTask*>(w + p.off.migr);
@@ -461,6 +463,34 @@ amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t s
   if (rc != AMR_OK) return rc;
   if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_cfl_dt_comoving(amr_mesh* h, const double* U, double a, double* dt, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factor must be positive and finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dt, h->cfg, st, a); });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "cfl");
+}
+
+amr_status amr_hydro_step_comoving(amr_mesh* h, double* U, const double* dt, int64_t step_index, double a,
+                                   double hubble, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factor must be positive and finite");
+  if (!std::isfinite(hubble)) return fail(AMR_E_INVALID, "expansion rate must be finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = launch_scale_dt(P, dt, a, st);
+  if (e != hipSuccess) return hip_fail(e, "comoving dt");
+  rc = run_step(h, U, P.dte, step_index, st);
+  if (rc != AMR_OK) return rc;
+  e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, dt, hubble, st); });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "expansion");
 }
 
 amr_status amr_hydro_step_record(amr_mesh* h, double* U, double* dt, double* S1, double* S2, double* Uout,

@@ -171,11 +171,11 @@ __global__ void floor_mark(DevPlan P, unsigned long long* __restrict__ mark, int
   else P.counters[threadIdx.x] = mark[threadIdx.x];
 }
 
-__global__ void cfl_finalize(DevPlan P, double* __restrict__ dt) {
+__global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= P.ninst) return;
   const double mn = __longlong_as_double((long long)P.acc[m]);
-  dt[m] = P.inst[m].cfl * mn;
+  dt[m] = (P.inst[m].cfl * a) * mn;  // a = 1 leaves cfl * mn bit for bit
   P.acc[m] = 0x7FF0000000000000ull;
 }
 
@@ -693,13 +693,13 @@ hipError_t refresh_n(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_
 }
 
 template <int N>
-hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st) {
+hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a) {
   constexpr int N3 = N * N * N;
   int chunks = N3 / (8 * 256);
   if (chunks < 1) chunks = 1;
   if (P.nleaf > 0)
     hipLaunchKernelGGL(cfl_kernel<N>, dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
-  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt);
+  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt, a);
   return hipGetLastError();
 }
 
@@ -762,11 +762,11 @@ hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipSt
   }
 }
 
-hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st) {
+hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a) {
   switch (P.N) {
-    case 8: return cfl_n<8>(P, U, dt, L, st);
-    case 16: return cfl_n<16>(P, U, dt, L, st);
-    case 32: return cfl_n<32>(P, U, dt, L, st);
+    case 8: return cfl_n<8>(P, U, dt, L, st, a);
+    case 16: return cfl_n<16>(P, U, dt, L, st, a);
+    case 32: return cfl_n<32>(P, U, dt, L, st, a);
     default: return hipErrorInvalidValue;
   }
 }

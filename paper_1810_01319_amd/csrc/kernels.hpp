@@ -18,6 +18,7 @@ struct DevPlan {
   const int32_t* faceslot;
   const RefluxTask* reflux[3];
   unsigned long long* acc;
+  double* dte;  // per instance: dt / a of a comoving step
   unsigned long long* counters;
   double* ind;
   const MigrTask* migr;
@@ -37,7 +38,12 @@ struct LaunchCfg {
 };
 
 hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st);
-hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st);
+// dt = (C_cfl * a) * min ...; a = 1 outside comoving steps
+hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st,
+                      double a = 1.0);
+// comoving steps (comoving.hip): P.dte = dt / a; the expansion sources
+hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStream_t st);
+hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st);
 // sweep along dir; swept[a] = axis a already swept this step
 hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
                         const LaunchCfg& L, hipStream_t st);

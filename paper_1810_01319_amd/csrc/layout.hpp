@@ -70,8 +70,8 @@ struct Reloc {
 };
 
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, counters, ind, migr, reloc, reloc_child, faces,
-      total;
+  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, dte, counters, ind, migr, reloc, reloc_child,
+      faces, total;
 };
 
 }  // namespace amr

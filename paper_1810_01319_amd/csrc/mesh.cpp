@@ -326,6 +326,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
     o = align256(o + int64_t(reflux[d].size() * sizeof(RefluxTask)));
   }
   off.acc = o; o = align256(o + ninst * 8);
+  off.dte = o; o = align256(o + ninst * 8);
   off.counters = o; o = align256(o + 8);
   off.ind = o; o = align256(o + nleaf * 8);
   off.migr = o; o = align256(o + int64_t(migr.size() * sizeof(MigrTask)));

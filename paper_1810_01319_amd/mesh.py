@@ -146,6 +146,18 @@ class Mesh:
         self._check_state(U)
         check(lib().amr_hydro_step_dt(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
 
+    def cfl_dt_comoving(self, U: torch.Tensor, a: float, dt: torch.Tensor) -> None:
+        """CFL dt in comoving coordinates with expansion factor a."""
+        self._check_state(U)
+        check(lib().amr_cfl_dt_comoving(self._h, _ptr(U), ctypes.c_double(a), _ptr(dt), _stream()))
+
+    def step_comoving(self, U: torch.Tensor, dt: torch.Tensor, k: int, a: float, hubble: float) -> None:
+        """One comoving step with the given dt (device): fluxes with dt / a,
+        then the expansion sources with H = hubble (a, H at the mid time)."""
+        self._check_state(U)
+        check(lib().amr_hydro_step_comoving(self._h, _ptr(U), _ptr(dt), int(k), ctypes.c_double(a),
+                                            ctypes.c_double(hubble), _stream()))
+
     def floor_count(self) -> int:
         out = ctypes.c_int64()
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))
