@@ -295,6 +295,53 @@ def tracer_compare(steps: int = 20):
             "counters": c, "particles_end": tr.count}
 
 
+def comoving_compare(steps: int = 20):
+    """Comoving steps on the Sedov workload in an Einstein-de Sitter expansion
+    (a = t^(2/3), H = 2 / (3 t), from t = 1e-3, a = 0.01): each step takes its dt from the
+    comoving CFL (read back to the host, as a cosmology driver does to place
+    a and H at the step's mid time), then runs the step.  Reports the time per
+    step and the expansion-source kernel's HBM rate (per active cell: 5
+    fields read, 4 written)."""
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    spec = I.sedov_spec(root=8, block_cells=32, levels=2)
+    m = Mesh(**spec.kwargs())
+    U = m.state_from_active(I.sedov_state(spec, m.keys))
+    dt = m.dt_tensor()
+    cells = m.nleaf * spec.block_cells ** 3
+
+    def run(k0, n, t):
+        for k in range(k0, k0 + n):
+            a = t ** (2.0 / 3.0)
+            m.cfl_dt_comoving(U, a, dt)
+            d = float(dt.cpu()[0])
+            tm = t + 0.5 * d
+            m.step_comoving(U, dt, k, tm ** (2.0 / 3.0), 2.0 / (3.0 * tm))
+            t += d
+        return t
+
+    t = run(0, 2, 1e-3)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t0 = time.perf_counter()
+    t = run(2, steps, t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = m.profile_read()
+    m.profile(False)
+    ex_ms = prof["expansion"][0] / steps
+    bytes_pc = 72
+    return {"workload": "sedov-static-amr, comoving, Einstein-de Sitter expansion from a = 0.01",
+            "steps": steps, "a_end": t ** (2.0 / 3.0), "ms_per_step": wall * 1e3 / steps,
+            "cell_updates_per_s": cells * steps / wall, "expansion_ms_per_step": ex_ms,
+            "expansion_hbm": {"algorithmic_bytes_per_cell": bytes_pc,
+                              "GB/s": cells * bytes_pc / (ex_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS},
+            "phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items() if v[1] > 0}}
+
+
 def step_bytes_per_block(N: int) -> int:
     """Algorithmic HBM bytes of one step of one block: CFL read, refresh,
     three sweeps (reflux is negligible)."""
@@ -428,6 +475,8 @@ def main():
                     help="steps of the batched comparison, graph and one-mesh-per-launch (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="steps of the adjoint comparison (0: skip)")
     ap.add_argument("--tracer-steps", type=int, default=20, help="steps of the tracer measurement (0: skip)")
+    ap.add_argument("--comoving-steps", type=int, default=20,
+                    help="steps of the comoving measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -542,6 +591,8 @@ def main():
         out["adjoint"] = adjoint_compare(args.adjoint_steps)
     if args.tracer_steps > 0:
         out["tracers"] = tracer_compare(args.tracer_steps)
+    if args.comoving_steps > 0:
+        out["comoving"] = comoving_compare(args.comoving_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)
