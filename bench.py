@@ -298,7 +298,7 @@ def tracer_compare(steps: int = 20):
 def comoving_compare(steps: int = 20):
     """Comoving steps on the Sedov workload in an Einstein-de Sitter expansion
     (a = t^(2/3), H = 2 / (3 t), from t = 1e-3, a = 0.01): each step takes its dt from the
-    comoving CFL (read back to the host, as a cosmology driver does to place
+    comoving CFL (read back to the host, as a cosmology code does to place
     a and H at the step's mid time), then runs the step.  Reports the time per
     step and the expansion-source kernel's HBM rate (per active cell: 5
     fields read, 4 written)."""
@@ -481,7 +481,7 @@ def main():
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path; "
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
               "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -1,7 +1,7 @@
 """ctypes declarations of the C ABI in include/amr.h (argument marshalling only).
 
-The HIP library must have been built (``__graft_entry__.build()`` or
-``python -m paper_1810_01319_amd._build``); there is no fallback path.
+The HIP library must have been built (``python -m paper_1810_01319_amd._build``);
+there is no fallback path.
 """
 from __future__ import annotations
 
@@ -134,7 +134,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(SO):
-            raise ImportError(f"HIP library {SO} is not built; run __graft_entry__.build()")
+            raise ImportError(f"HIP library {SO} is not built; run python -m paper_1810_01319_amd._build")
         L = ctypes.CDLL(SO)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

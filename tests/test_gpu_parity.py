@@ -2,7 +2,7 @@
 the same seeded inputs.
 
 Bar: dt sequences bitwise equal; every active cell within 1e-12 of the oracle
-relative to max(|b|, ||b_field||_inf) (the benchmark spec's tolerance; momenta
+relative to max(|b|, ||b_field||_inf) (the FP64 parity tolerance; momenta
 cross zero so the field max-norm scales it).  Refresh is compared on every
 cell, ghosts included, bitwise.  The design target is bitwise equality, and
 the tests report the fraction of bitwise-equal values.
