@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__
 // order, each cell gathering what its neighbours' products send it, so no
 // two threads ever add to the same entry.
 // Tile shape per block size and axis (measured on gfx950: x sweeps, whose
-// tiles are contiguous rows, run best with smaller tiles).
+// tiles are contiguous rows, run best with smaller tiles; y and z best with
+// 6 pencils, 4 waves per workgroup).
 template <int N, int DIR>
 struct AdjShape {
   static constexpr int M = N + 2 * G;
@@ -113,20 +114,21 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   __shared__ double Ws[5][T];  // right states at c-1/2 and their adjoint; adjoint sent to cell c+1
   __shared__ double Ls[5][T];  // adjoint of the pre-floor update; adjoint sent to face c+1/2
   __shared__ double Fl[2][T];  // flattening adjoint sent to p of cells c+-1, c+-2
-  const int tilesA = (nA + R - 1) / R;
-  const int64_t tile = blockIdx.x;
-  const int s = int(tile / (int64_t(nB) * tilesA));
-  const int rem = int(tile - int64_t(s) * nB * tilesA);
-  const int iB = loB + rem / tilesA;
-  const int a0 = (rem % tilesA) * R;
+  // a tile is R consecutive pencils of the leaf's nA x nB plane (numbered
+  // along A, then B), so only the leaf's last tile is partial
+  const int npen = nA * nB;
+  const int tpl = (npen + R - 1) / R;
+  const int s = int(blockIdx.x / unsigned(tpl));
   const int i = threadIdx.x;
   const int r = DIR == 0 ? i / M : i % R;
   const int c = DIR == 0 ? i - r * M : i / R;
-  const bool live = i < T && a0 + r < nA;
+  const int pp = (int(blockIdx.x) - s * tpl) * R + r;
+  const bool live = i < T && pp < npen;
+  const int iB = loB + pp / nA;
   const BlockInfo bi = P.blocks[s];
   const InstParams ip = P.inst[bi.inst];  // by value: read once, before any store
   const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
-  const int iA = loA + a0 + r;
+  const int iA = loA + pp % nA;
   const int64_t off = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
   const double* const ucell = Uin + off;
   double* const lcell = lam + off;
@@ -500,7 +502,7 @@ hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const 
   constexpr int A = DIR == 0 ? 1 : 0, B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : S::M;
-  const int64_t tiles = P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R);
+  const int64_t tiles = P.nleaf * ((int64_t(nA) * nB + S::R - 1) / S::R);
   if (tiles == 0) return hipSuccess;
   const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
   if (floors != nullptr)

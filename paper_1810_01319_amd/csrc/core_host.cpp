@@ -99,6 +99,14 @@ void core_riemann_vjp(const double* gas, int iters, const double* L, const doubl
   riemann_vjp(ip, L, R, gF, gL, gR);
 }
 
+// the same transpose with every Newton evaluation reversed one by one
+void core_riemann_vjp_stepwise(const double* gas, int iters, const double* L, const double* R, const double* gF,
+                               double* gL, double* gR) {
+  const InstParams ip = params(gas, iters);
+  for (int v = 0; v < 5; v++) gL[v] = gR[v] = 0.0;
+  riemann_vjp_n<64, false>(ip, L, R, gF, gL, gR);
+}
+
 }  // extern "C"
 
 extern "C" {

@@ -287,7 +287,9 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
 // (same branches); the reverse part evaluates each Newton evaluation's square
 // roots and reciprocals once and shares reciprocals between the derivative
 // terms.
-template <int MAXIT>
+// FIXSTOP = false reverses every evaluation one by one (a host-side check of
+// the closed form used at a fixed point).
+template <int MAXIT, bool FIXSTOP = true>
 AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
                                  double* gR) {
   const double rL = L[0], uL = L[1], pL = L[4];
@@ -305,6 +307,10 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   double psv[MAXIT + 1];
   bool flv[MAXIT + 1];
   double WLw = 0, WRw = 0, iWL = 0, iWR = 0, iZL = 0, iZR = 0, usL = 0, usR = 0, sLf = 1, sRf = 1;
+  // evaluations kfix..NI all take place at the same p* once a Newton step
+  // leaves p* unchanged (a fixed point: the forward stops there with the
+  // same bits); their reverse is done in closed form below
+  int kfix = NI;
 #pragma unroll
   for (int it = 0; it <= MAXIT; it++) {
     psv[it] = ps;
@@ -320,9 +326,14 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
     iZL = (0.5 * iWL) * (1.0 + qL * qL);
     iZR = (0.5 * iWR) * (1.0 + qR * qR);
     if (it == NI) break;
-    ps = ps - (usR - usL) / (iZL + iZR);
-    flv[it] = ps < pfl;
-    ps = flv[it] ? pfl : ps;
+    double pn = ps - (usR - usL) / (iZL + iZR);
+    flv[it] = pn < pfl;
+    pn = flv[it] ? pfl : pn;
+    if (FIXSTOP && pn == ps) {
+      kfix = it;
+      break;
+    }
+    ps = pn;
   }
   const double Dz = iZL + iZR;
   const double us = (iZR * usL + iZL * usR) / Dz;
@@ -418,10 +429,9 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   double gCL = 0, gCR = 0, gipL = 0, gipR = 0;
   double gps_cur = gps;  // adjoint of the p* the evaluation being reversed used
   double sl = sLf, sr = sRf, iwl = iWL, iwr = iWR;  // that evaluation's values
-#pragma unroll
-  for (int it = MAXIT; it >= 0; it--) {
-    if (it > NI) continue;
-    const double p = psv[it];
+  // reverse of one evaluation at p (inputs giZL, giZR, gusL, gusR, giWL,
+  // giWR; output added to gps_cur and the accumulators)
+  auto eval_rev = [&](double p) {
     const double ql = CL * iwl, qr = CR * iwr;
     giWL += giZL * (0.5 * (1.0 + ql * ql));
     const double gql = giZL * (iwl * ql);
@@ -447,17 +457,13 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
     gps_cur += gaL * ipL + gaR * ipR;
     gipL += gaL * p;
     gipR += gaR * p;
-    if (it == 0) break;
-    // the previous evaluation, and the Newton update that produced p:
-    // p = p_prev - (u*_R - u*_L) / (1/Z_L + 1/Z_R)
-    const double pp = psv[it - 1];
-    sl = sqrt_pos(1.0 + g1 * (pp * ipL - 1.0));
-    sr = sqrt_pos(1.0 + g1 * (pp * ipR - 1.0));
-    iwl = rcp_pos(CL * sl);
-    iwr = rcp_pos(CR * sr);
+  };
+  // reverse of the Newton update p = p_prev - (u*_R - u*_L) / (1/Z_L + 1/Z_R)
+  // into the evaluation at p_prev (whose values are in sl, sr, iwl, iwr)
+  auto update_rev = [&](double pp, bool floored) {
     double gprev = 0.0;
     giZL = giZR = gusL = gusR = giWL = giWR = 0.0;
-    if (!flv[it - 1]) {
+    if (!floored) {
       const double uls = uL - (pp - pL) * iwl, urs = uR + (pp - pR) * iwr;
       const double zl = (0.5 * iwl) * (1.0 + (CL * iwl) * (CL * iwl));
       const double zr = (0.5 * iwr) * (1.0 + (CR * iwr) * (CR * iwr));
@@ -469,6 +475,52 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
       giZL = giZR = gD * (urs - uls) * iD;
     }
     gps_cur = gprev;
+  };
+  eval_rev(ps);  // the last evaluation (at the final p*, psv[kfix] = ... = psv[NI])
+  if (kfix < NI) {
+    // m = NI - kfix identical (update, evaluation) pairs at p*: each maps the
+    // adjoint g of p* to J g and adds g a to the accumulators (a, J constants
+    // at p*).  One pair run with g (1 + J + ... + J^(m-1)) adds exactly the m
+    // pairs' sum; the adjoint leaving them is J^m g.
+    const double p = ps;
+    const int m = NI - kfix;
+    double J = 0.0;
+    if (!flv[kfix]) {
+      const double uls = usL, urs = usR;
+      const double iD = rcp_pos(iZL + iZR);
+      const double z = (urs - uls) * iD * iD;  // giZ per unit g
+      const double ql = CL * iwl, qr = CR * iwr;
+      const double wl = z * (0.5 * (1.0 + ql * ql)) + z * (iwl * ql) * CL - iD * (p - pL);
+      const double wr = z * (0.5 * (1.0 + qr * qr)) + z * (iwr * qr) * CR - iD * (p - pR);
+      const double aL = (0.5 * g1) * (-wl * (iwl * iwl)) * (CL * CL * iwl);
+      const double aR = (0.5 * g1) * (-wr * (iwr * iwr)) * (CR * CR * iwr);
+      J = 1.0 + ((-iD * iwl - iD * iwr) + (aL * ipL + aR * ipR));
+    }
+    double S = 0.0, Jm = 1.0;
+#pragma unroll
+    for (int i = 0; i < MAXIT; i++) {
+      if (i < m) {
+        S += Jm;
+        Jm *= J;
+      }
+    }
+    const double g = gps_cur;
+    gps_cur = g * S;
+    update_rev(p, flv[kfix]);
+    eval_rev(p);
+    gps_cur = g * Jm;
+  }
+  // the evaluations before the fixed point, last first
+#pragma unroll
+  for (int it = MAXIT; it >= 1; it--) {
+    if (it > kfix) continue;
+    const double pp = psv[it - 1];
+    sl = sqrt_pos(1.0 + g1 * (pp * ipL - 1.0));
+    sr = sqrt_pos(1.0 + g1 * (pp * ipR - 1.0));
+    iwl = rcp_pos(CL * sl);
+    iwr = rcp_pos(CR * sr);
+    update_rev(pp, flv[it - 1]);
+    eval_rev(pp);
   }
   // first guess p* = num0 / den0 (unless floored)
   if (!fl0) {

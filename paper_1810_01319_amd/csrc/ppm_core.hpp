@@ -148,8 +148,9 @@ AMR_HD inline void trace(const InstParams& ip, double rho, double u, double c, d
   }
 }
 
-// Two-shock Riemann solver (fixed Newton steps on p*), sampled at x/t = 0,
-// linear fan between head and tail; returns the flux.  Uses the reciprocal
+// Two-shock Riemann solver (a fixed number of Newton steps on p*, ending
+// early only at an exact fixed point, which gives the same bits), sampled at
+// x/t = 0, linear fan between head and tail; returns the flux.  Uses the reciprocal
 // shock mass fluxes 1/W_K and reciprocal impedances
 // 1/Z_K = (1 + (C_K/W_K)^2) / (2 W_K): p* <- p* - (u*_R - u*_L)/(1/Z_L + 1/Z_R).
 AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const double* R, double* F) {
@@ -172,8 +173,12 @@ AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const dou
     iZL = (0.5 * iWL) * (1.0 + qL * qL);
     iZR = (0.5 * iWR) * (1.0 + qR * qR);
     if (it == ip.iters) break;
-    ps = ps - (usR - usL) / (iZL + iZR);
-    ps = ps < pfl ? pfl : ps;
+    double pn = ps - (usR - usL) / (iZL + iZR);
+    pn = pn < pfl ? pfl : pn;
+    // a step that leaves p* unchanged has reached a fixed point: every later
+    // step would recompute exactly these values, so stopping is exact
+    if (pn == ps) break;
+    ps = pn;
   }
   const double us = (iZR * usL + iZL * usR) / (iZL + iZR);
   const bool left = us >= 0.0;

@@ -67,6 +67,40 @@ def test_riemann_vjp_matches_finite_differences(core, k):
         assert abs(ad - fd) <= 2e-7 * max(1.0, abs(fd)), (k, ad, fd)
 
 
+# states whose Newton iteration reaches an exact fixed point before the last
+# step (equal states, tiny and weak jumps, an asymmetric cavitation with a
+# floored star pressure; a symmetric one would put u* on the star/fan kink)
+FIXED = [
+    ([1.0, 0.3, 0.1, 0.0, 1.0], [1.0, 0.3, -0.2, 0.4, 1.0]),
+    ([1.0, 0.3, 0.0, 0.0, 1.0], [1.0000001, 0.3000001, 0.0, 0.0, 1.0000002]),
+    ([1.0, 0.1, 0.0, 0.0, 1.0], [1.02, 0.08, 0.0, 0.0, 1.03]),
+    ([1.0, -4.0, 0.0, 0.0, 0.01], [0.8, 3.0, 0.0, 0.0, 0.012]),
+]
+
+
+@pytest.mark.parametrize("k", range(len(FIXED)))
+def test_riemann_vjp_at_a_fixed_point_equals_the_stepwise_transpose(core, k):
+    """At an exact Newton fixed point the transpose of the identical remaining
+    evaluations is taken in closed form; it must equal reversing them one by
+    one (up to rounding) and match finite differences."""
+    core.core_riemann_vjp_stepwise.argtypes = core.core_riemann_vjp.argtypes
+    L0, R0 = (np.array(a, dtype=float) for a in FIXED[k])
+    rng = np.random.default_rng(40 + k)
+    for _ in range(6):
+        gF = rng.normal(size=5)
+        a = [np.zeros(5), np.zeros(5)]
+        b = [np.zeros(5), np.zeros(5)]
+        core.core_riemann_vjp(ptr(GAS), 5, ptr(L0), ptr(R0), ptr(gF), ptr(a[0]), ptr(a[1]))
+        core.core_riemann_vjp_stepwise(ptr(GAS), 5, ptr(L0), ptr(R0), ptr(gF), ptr(b[0]), ptr(b[1]))
+        scale = max(1.0, float(np.max(np.abs(np.concatenate(b)))))
+        assert np.max(np.abs(np.concatenate(a) - np.concatenate(b))) <= 1e-13 * scale, (k, a, b)
+        dL, dR = rng.normal(size=5), rng.normal(size=5)
+        eps = 1e-6
+        fd = (gF @ riemann(core, L0 + eps * dL, R0 + eps * dR) - gF @ riemann(core, L0 - eps * dL, R0 - eps * dR)) / (2 * eps)
+        ad = a[0] @ dL + a[1] @ dR
+        assert abs(ad - fd) <= 2e-7 * max(1.0, abs(fd)), (k, ad, fd)
+
+
 def pencil_state(n, rng, kind):
     x = np.arange(n, dtype=float)
     if kind == "smooth":
