@@ -171,7 +171,9 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
     after `steps` steps): wall time of the plain forward, and of the
     differentiable forward and the hand-written adjoint in both modes
     (recording the sweep inputs, or checkpointing and recomputing them),
-    best of `reps`."""
+    best of `reps`.  adjoint_over_forward divides the adjoint by the plain
+    forward; adjoint_over_own_forward by the differentiable forward it
+    follows."""
     import torch
 
     from paper_1810_01319_amd import adjoint as A
@@ -238,12 +240,14 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
         m.profile(False)
         res = {"forward_ms": best_f * 1e3, "adjoint_ms": best_b * 1e3,
                "adjoint_over_forward": best_b / t_plain,
+               "adjoint_over_own_forward": best_b / best_f,
                "forward_and_adjoint_over_forward": (best_f + best_b) / t_plain,
                "adjoint_phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items()
                                               if p.startswith("adj_")}}
         if record:
             out["adjoint_ms"] = res["adjoint_ms"]
             out["adjoint_over_forward"] = res["adjoint_over_forward"]
+            out["adjoint_over_own_forward"] = res["adjoint_over_own_forward"]
             out["recording"] = res
         else:
             out["recomputing"] = res
