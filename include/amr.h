@@ -164,6 +164,19 @@ amr_status amr_cfl_dt_comoving(amr_mesh* mesh, const double* U_dev, double a, do
 amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* dt_dev, int64_t step_index,
                                    double a, double hubble, void* stream);
 
+/* nsteps consecutive hydro steps (step indices first_step, first_step + 1,
+ * ...; U_dev updated in place): the same results as that many
+ * amr_hydro_step calls, bit for bit, with step i's dt (one per instance) in
+ * dt_dev[i * n_instances ...] (device, nsteps * n_instances doubles).  Only
+ * the first step runs the CFL reduction over the state; each later step's dt
+ * comes from its predecessor, whose last sweep adds the candidates of the
+ * cells it updates and no reflux changes, and a kernel after the reflux
+ * those of the refluxed cells (the minimum is exact in any order).  The
+ * caller must not change U_dev between the steps of one call.
+ * Stream-ordered; AMR_E_INVALID for nsteps < 0 or a null dt_dev. */
+amr_status amr_hydro_steps(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps, int64_t first_step,
+                           void* stream);
+
 /* The same step with dt given on the device (no CFL reduction). */
 amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,
                              int64_t step_index, void* stream);

@@ -123,6 +123,7 @@ SIGNATURES = {
     "amr_profile_read": (_I32, [_P, _P, _P]),
     "amr_arith_selftest": (_I32, [ctypes.c_uint64, _I64, _P, _P]),
     "amr_cfl_dt_comoving": (_I32, [_P, _P, ctypes.c_double, _P, _P]),
+    "amr_hydro_steps": (_I32, [_P, _P, _P, _I64, _I64, _P]),
     "amr_hydro_step_comoving": (_I32, [_P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, _P]),
     "amr_last_error": (ctypes.c_char_p, []),
 }

@@ -147,6 +147,7 @@ DevPlan dev_plan(const amr_mesh* h) {
     P.nreflux[d] = int64_t(p.reflux[d].size());
   }
   P.acc = reinterpret_cast<unsigned long long*>(w + p.off.acc);
+  P.lacc = reinterpret_cast<unsigned long long*>(w + p.off.lacc);
   P.dte = reinterpret_cast<double*>(w + p.off.dte);
   P.counters = reinterpret_cast<unsigned long long*>(w + p.off.counters);
   P.ind = reinterpret_cast<double*>(w + p.off.ind);
@@ -194,8 +195,11 @@ hipError_t refresh_timed(amr_mesh* h, const DevPlan& P, double* U, hipStream_t s
 
 // One step: refresh U in place, then sweep k reads the previous result and
 // writes out[k] (all equal to U for the in-place step), then reflux out[2].
+// cfl_next (in place only): the step also accumulates the next step's CFL
+// candidates (last sweep, then the refluxed cells) into the instance
+// accumulators, for cfl_finalize.
 amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const double* dt, int64_t step_index,
-                         hipStream_t st, const TracerDev* tracers = nullptr) {
+                         hipStream_t st, const TracerDev* tracers = nullptr, int cfl_next = 0) {
   const DevPlan P = dev_plan(h);
   hipError_t e = refresh_timed(h, P, U, st);
   if (e != hipSuccess) return hip_fail(e, "refresh");
@@ -211,8 +215,9 @@ amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const dou
   int swept[3] = {0, 0, 0};
   const double* in = U;
   for (int s = 0; s < 3; s++) {
+    const int last = s == 2 ? cfl_next : 0;
     e = timed(h, AMR_PHASE_SWEEP_X + order[s], st,
-              [&] { return launch_sweep_oop(P, in, out[s], dt, order[s], swept, h->cfg, st); });
+              [&] { return launch_sweep_oop(P, in, out[s], dt, order[s], swept, h->cfg, st, last); });
     if (e != hipSuccess) return hip_fail(e, "sweep");
     swept[order[s]] = 1;
     in = out[s];
@@ -221,6 +226,10 @@ amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const dou
     if (P.nreflux[d] == 0) continue;
     e = timed(h, AMR_PHASE_REFLUX, st, [&] { return launch_reflux(P, out[2], dt, d, h->cfg, st); });
     if (e != hipSuccess) return hip_fail(e, "reflux");
+  }
+  if (cfl_next) {
+    e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_reflux_cfl(P, out[2], st); });
+    if (e != hipSuccess) return hip_fail(e, "cfl");
   }
   return AMR_OK;
 }
@@ -456,6 +465,29 @@ amr_status amr_hydro_step(amr_mesh* h, double* U, double* dt, int64_t step_index
   amr_status rc = amr_cfl_dt(h, U, dt, stream);
   if (rc != AMR_OK) return rc;
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_hydro_steps(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
+  if (nsteps < 0) return fail(AMR_E_INVALID, "negative step count");
+  if (nsteps == 0) return AMR_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dt, h->cfg, st); });
+  if (e != hipSuccess) return hip_fail(e, "cfl");
+  double* const out[3] = {U, U, U};
+  for (int64_t i = 0; i < nsteps; i++) {
+    double* const dti = dt + i * P.ninst;
+    if (i > 0) {
+      e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl_finalize(P, dti, st); });
+      if (e != hipSuccess) return hip_fail(e, "cfl");
+    }
+    rc = run_step_into(h, U, out, dti, first_step + i, st, nullptr, i + 1 < nsteps ? 1 : 0);
+    if (rc != AMR_OK) return rc;
+  }
+  return AMR_OK;
 }
 
 amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t step_index, void* stream) {

@@ -179,6 +179,79 @@ __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a) {
   P.acc[m] = 0x7FF0000000000000ull;
 }
 
+// Signal speed max_d |u_d| + c of one cell from its conserved values
+// (momenta in x, y, z order), in exactly the CFL kernel's arithmetic; ir =
+// 1/rho.  A run of steps keeps each leaf's maximum: correctly rounded
+// division is monotone, so dx / (leaf maximum) is the leaf's minimum of
+// dx / speed bit for bit, and the per-cell division is saved.
+__device__ __forceinline__ double cfl_speed(const InstParams& ip, double rho, double ir, double mx, double my,
+                                            double mz, double E) {
+  const double u = mx * ir, v = my * ir, w = mz * ir;
+  double p = ip.gm1 * (E - (0.5 * rho) * ((u * u + v * v) + w * w));
+  p = p < ip.p_floor ? ip.p_floor : p;
+  const double cs = sqrt_pos((ip.gamma * p) * ir);
+  const double vm = sel_max(sel_max(fabs(u), fabs(v)), fabs(w));
+  return vm + cs;
+}
+
+// dt of each instance from the per-leaf maximum signal speeds a run of steps
+// accumulated: min over leaves of dx / speed (one workgroup per instance;
+// exact), C_cfl times it; the speeds are reset to 0.
+__global__ void __launch_bounds__(256) cfl_finalize_leaves(DevPlan P, double* __restrict__ dt) {
+  const int m = blockIdx.x;
+  const InstParams& ip = P.inst[m];
+  unsigned long long best = 0x7FF0000000000000ull;
+  for (int64_t s = ip.first_leaf + threadIdx.x; s < ip.first_leaf + ip.n_leaf; s += blockDim.x) {
+    unsigned long long sb = 0ull;
+    for (int k = 0; k < kCflSlots; k++) {
+      const unsigned long long v = P.lacc[s * kCflSlots + k];
+      sb = v > sb ? v : sb;
+      P.lacc[s * kCflSlots + k] = 0ull;
+    }
+    const double sp = __longlong_as_double((long long)sb);
+    const double t = level_dx(ip, P.N, P.blocks[s].level) / sp;
+    const unsigned long long v = (unsigned long long)__double_as_longlong(t);
+    best = v < best ? v : best;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off, 64);
+    best = o < best ? o : best;
+  }
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; w++) best = red[w] < best ? red[w] : best;
+    dt[m] = ip.cfl * __longlong_as_double((long long)best);
+  }
+}
+
+// Whether the reflux will still correct cell (x, y, z) of a leaf whose
+// corrected faces are the bits 2 d + side of rflx.
+__device__ __forceinline__ bool in_reflux_layer(int rflx, int N, int x, int y, int z) {
+  const int q[3] = {x, y, z};
+  bool in = false;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    in = in || (((rflx >> (2 * a)) & 1) && q[a] == G) || (((rflx >> (2 * a + 1)) & 1) && q[a] == G + N - 1);
+  }
+  return in;
+}
+
+// Maximum over a full wave, then one atomic per wave (non-negative doubles
+// order like their bit patterns); partial waves add lane by lane.
+__device__ __forceinline__ void cfl_commit(unsigned long long* acc, double best) {
+  if (__ballot(1) == ~0ull) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off, 64);
+      best = o > best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(acc, (unsigned long long)__double_as_longlong(best));
+  } else {
+    atomicMax(acc, (unsigned long long)__double_as_longlong(best));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // PPM sweep: one lane walks one pencil along the sweep axis with a sliding
 // register window; the next cell is prefetched one step ahead, and each cell
@@ -186,9 +259,12 @@ __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a) {
 // is 7 cells wide), re-read from cache for its conserved values.
 // ---------------------------------------------------------------------------
 
+// cfl_next (the last sweep of a step in a run of steps): every updated cell
+// that no reflux will change adds its CFL candidate for the next step to the
+// instance's accumulator.
 template <int N, int DIR, bool OOP>
 __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
-                                                const DevPlan& P, int loA, int nA, int loB, int nB) {
+                                                const DevPlan& P, int loA, int nA, int loB, int nB, int cfl_next) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int A = DIR == 0 ? 1 : 0;
@@ -208,7 +284,9 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   const int iA = loA + pp % nA, iB = loB + pp / nA;
   const BlockInfo bi = P.blocks[s];
   const InstParams ip = P.inst[bi.inst];  // by value: read once, before any store
-  const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
+  const double dxl = level_dx(ip, N, bi.level);
+  const double nu = dtv[bi.inst] / dxl;
+  double cfl_best = 0.0;  // maximum signal speed (cfl_next)
   const int64_t boff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
   const double* const pr_ = Uin + boff;
   const double* const pn_ = pr_ + (1 + DIR) * M3;
@@ -343,6 +421,20 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
           const double pn = gm1 * (e - ke);
           if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
           qr_[o] = r0; qn_[o] = m1; q1_[o] = m2; q2_[o] = m3; qe_[o] = e;
+          if (cfl_next) {
+            int q[3];
+            q[DIR] = c - 3;
+            q[A] = iA;
+            q[B] = iB;
+            if (!in_reflux_layer(bi.rflx, N, q[0], q[1], q[2])) {
+              double mv[3];
+              mv[DIR] = m1;
+              mv[T1] = m2;
+              mv[T2] = m3;
+              const double t = cfl_speed(ip, r0, jr, mv[0], mv[1], mv[2], e);
+              cfl_best = t > cfl_best ? t : cfl_best;
+            }
+          }
         }
 #pragma unroll
         for (int q = 0; q < 5; q++) Fp[q] = F[q];
@@ -361,12 +453,13 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   for (int c = 2 * G; c < M - 1; c++) cell(c, std::integral_constant<int, 1>{});
   cell(M - 1, std::integral_constant<int, 2>{});
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+  if (cfl_next) cfl_commit(&P.lacc[int64_t(s) * kCflSlots + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCflSlots)], cfl_best);
 }
 
 template <int N, int DIR>
 __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
-                                                    DevPlan P, int loA, int nA, int loB, int nB) {
-  sweep_walk_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB);
+                                                    DevPlan P, int loA, int nA, int loB, int nB, int cfl_next) {
+  sweep_walk_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
 }
 
 // Out of place: every cell of the swept pencils is written to Uout (updated
@@ -375,7 +468,7 @@ template <int N, int DIR>
 __global__ void __launch_bounds__(256) sweep_kernel_oop(const double* __restrict__ Uin, double* __restrict__ Uout,
                                                         const double* __restrict__ dtv, DevPlan P, int loA, int nA,
                                                         int loB, int nB) {
-  sweep_walk_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB);
+  sweep_walk_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,7 +491,8 @@ struct StagedShape {
 
 template <int N, int DIR, bool OOP>
 __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
-                                                  const DevPlan& P, int loA, int nA, int loB, int nB) {
+                                                  const DevPlan& P, int loA, int nA, int loB, int nB,
+                                                  int cfl_next) {
   using S = StagedShape<N, DIR>;
   constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -509,6 +603,7 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   }
   __syncthreads();
   // F: conservative update of the active cells, floors
+  double cfl_best = 0.0;  // signal speed (cfl_next)
   if (live && c >= G && c < G + N) {
     double r0 = U0 - nu * (Ys[0][i] - Ys[0][i - NS]);
     const double m1 = U1 - nu * (Ys[1][i] - Ys[1][i - NS]);
@@ -528,6 +623,19 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     outp[(1 + T2) * M3] = m3;
     outp[4 * M3] = e;
     if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
+    if (cfl_next) {  // the next step's CFL candidate (see the walk)
+      int q[3];
+      q[DIR] = c;
+      q[A] = iA;
+      q[B] = iB;
+      if (!in_reflux_layer(bi.rflx, N, q[0], q[1], q[2])) {
+        double mv[3];
+        mv[DIR] = m1;
+        mv[T1] = m2;
+        mv[T2] = m3;
+        cfl_best = cfl_speed(ip, r0, jr, mv[0], mv[1], mv[2], e);
+      }
+    }
   } else if (OOP && live) {  // cells the sweep does not update pass through
     outp[0] = U0;
     outp[(1 + DIR) * M3] = U1;
@@ -535,13 +643,15 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     outp[(1 + T2) * M3] = U3;
     outp[4 * M3] = U4;
   }
+  if (cfl_next) cfl_commit(&P.lacc[int64_t(s) * kCflSlots + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCflSlots)], cfl_best);
 }
 
 template <int N, int DIR>
 __global__ void __launch_bounds__((StagedShape<N, DIR>::WG)) sweep_staged(double* __restrict__ U,
                                                                     const double* __restrict__ dtv, DevPlan P,
-                                                                    int loA, int nA, int loB, int nB) {
-  sweep_staged_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB);
+                                                                    int loA, int nA, int loB, int nB,
+                                                                    int cfl_next) {
+  sweep_staged_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
 }
 
 template <int N, int DIR>
@@ -549,7 +659,7 @@ __global__ void __launch_bounds__((StagedShape<N, DIR>::WG)) sweep_staged_oop(co
                                                                         double* __restrict__ Uout,
                                                                         const double* __restrict__ dtv, DevPlan P,
                                                                         int loA, int nA, int loB, int nB) {
-  sweep_staged_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB);
+  sweep_staged_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,7 +815,7 @@ hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg&
 
 template <int N, int DIR>
 hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const double* dt, const int swept[3],
-                    const LaunchCfg& L, hipStream_t st) {
+                    const LaunchCfg& L, hipStream_t st, int cfl_next) {
   constexpr int M = N + 2 * G;
   constexpr int A = DIR == 0 ? 1 : 0;
   constexpr int B = DIR == 2 ? 1 : 2;
@@ -719,24 +829,64 @@ hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const dou
     if (oop)
       hipLaunchKernelGGL((sweep_staged_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
-      hipLaunchKernelGGL((sweep_staged<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB);
+      hipLaunchKernelGGL((sweep_staged<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
   } else {
     const int64_t n = P.nleaf * ((int64_t(nA) * nB + 63) / 64) * 64;  // whole waves per leaf
     const dim3 g(grid_for(n, L.sweep_block)), b(L.sweep_block);
     if (oop)
       hipLaunchKernelGGL((sweep_kernel_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
-      hipLaunchKernelGGL((sweep_kernel<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB);
+      hipLaunchKernelGGL((sweep_kernel<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
   }
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t sweep_n(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir, const int swept[3],
-                   const LaunchCfg& L, hipStream_t st) {
-  if (dir == 0) return sweep_nd<N, 0>(P, Uin, Uout, dt, swept, L, st);
-  if (dir == 1) return sweep_nd<N, 1>(P, Uin, Uout, dt, swept, L, st);
-  return sweep_nd<N, 2>(P, Uin, Uout, dt, swept, L, st);
+                   const LaunchCfg& L, hipStream_t st, int cfl_next) {
+  if (dir == 0) return sweep_nd<N, 0>(P, Uin, Uout, dt, swept, L, st, cfl_next);
+  if (dir == 1) return sweep_nd<N, 1>(P, Uin, Uout, dt, swept, L, st, cfl_next);
+  return sweep_nd<N, 2>(P, Uin, Uout, dt, swept, L, st, cfl_next);
+}
+
+// The next step's CFL candidates of the cells the reflux corrected (one
+// thread per cell of each task's face layer; cells on two corrected faces
+// are counted twice, which a minimum ignores).
+template <int N, int DIR>
+__global__ void __launch_bounds__(256) reflux_cfl_kernel(const double* __restrict__ U, DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nreflux[DIR] * N * N) return;  // N * N is a multiple of 64: whole waves
+  const int k = int(t / (N * N));
+  const int r = int(t - int64_t(k) * N * N);
+  const RefluxTask T = P.reflux[DIR][k];
+  const BlockInfo bi = P.blocks[T.leaf];
+  const InstParams ip = P.inst[bi.inst];
+  const int d = T.side ? N + G - 1 : G;
+  const double* B0 = U + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + r % N) * SA +
+                     int64_t(G + r / N) * SB;
+  const double rho = B0[0];
+  const double c = cfl_speed(ip, rho, rcp_pos(rho), B0[M3], B0[2 * M3], B0[3 * M3], B0[4 * M3]);
+  cfl_commit(&P.lacc[int64_t(T.leaf) * kCflSlots + ((t >> 6) % kCflSlots)], c);
+}
+
+template <int N>
+hipError_t reflux_cfl_n(const DevPlan& P, const double* U, hipStream_t st) {
+  for (int d = 0; d < 3; d++) {
+    const int64_t n = P.nreflux[d] * N * N;
+    if (n == 0) continue;
+    const dim3 g(grid_for(n, 256)), b(256);
+    if (d == 0) hipLaunchKernelGGL((reflux_cfl_kernel<N, 0>), g, b, 0, st, U, P);
+    else if (d == 1) hipLaunchKernelGGL((reflux_cfl_kernel<N, 1>), g, b, 0, st, U, P);
+    else hipLaunchKernelGGL((reflux_cfl_kernel<N, 2>), g, b, 0, st, U, P);
+  }
+  return hipGetLastError();
 }
 
 template <int N>
@@ -777,13 +927,29 @@ hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, 
 }
 
 hipError_t launch_sweep_oop(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir,
-                            const int swept[3], const LaunchCfg& L, hipStream_t st) {
+                            const int swept[3], const LaunchCfg& L, hipStream_t st, int cfl_next) {
+  if (cfl_next && Uin != Uout) return hipErrorInvalidValue;  // only the in-place sweeps feed the next CFL
   switch (P.N) {
-    case 8: return sweep_n<8>(P, Uin, Uout, dt, dir, swept, L, st);
-    case 16: return sweep_n<16>(P, Uin, Uout, dt, dir, swept, L, st);
-    case 32: return sweep_n<32>(P, Uin, Uout, dt, dir, swept, L, st);
+    case 8: return sweep_n<8>(P, Uin, Uout, dt, dir, swept, L, st, cfl_next);
+    case 16: return sweep_n<16>(P, Uin, Uout, dt, dir, swept, L, st, cfl_next);
+    case 32: return sweep_n<32>(P, Uin, Uout, dt, dir, swept, L, st, cfl_next);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_reflux_cfl(const DevPlan& P, const double* U, hipStream_t st) {
+  switch (P.N) {
+    case 8: return reflux_cfl_n<8>(P, U, st);
+    case 16: return reflux_cfl_n<16>(P, U, st);
+    case 32: return reflux_cfl_n<32>(P, U, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cfl_finalize(const DevPlan& P, double* dt, hipStream_t st) {
+  if (P.ninst > 0)
+    hipLaunchKernelGGL(cfl_finalize_leaves, dim3(static_cast<unsigned>(P.ninst)), dim3(256), 0, st, P, dt);
+  return hipGetLastError();
 }
 
 hipError_t launch_floor_mark(const DevPlan& P, unsigned long long* mark, int mode, hipStream_t st) {

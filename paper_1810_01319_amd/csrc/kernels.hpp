@@ -18,6 +18,7 @@ struct DevPlan {
   const int32_t* faceslot;
   const RefluxTask* reflux[3];
   unsigned long long* acc;
+  unsigned long long* lacc;  // kCflSlots per leaf: next-step signal-speed maxima of a run of steps
   double* dte;  // per instance: dt / a of a comoving step
   unsigned long long* counters;
   double* ind;
@@ -49,8 +50,15 @@ hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, 
                         const LaunchCfg& L, hipStream_t st);
 // the same sweep reading Uin and writing every cell of the swept pencils to
 // Uout (updated cells, and the others passed through); in place if equal
+// cfl_next (in place only): the sweep is a step's last, and its updated cells
+// outside the reflux layers add their CFL candidates for the next step to the
+// instance accumulators
 hipError_t launch_sweep_oop(const DevPlan& P, const double* Uin, double* Uout, const double* dt, int dir,
-                            const int swept[3], const LaunchCfg& L, hipStream_t st);
+                            const int swept[3], const LaunchCfg& L, hipStream_t st, int cfl_next = 0);
+// after the reflux: the corrected cells' CFL candidates for the next step
+hipError_t launch_reflux_cfl(const DevPlan& P, const double* U, hipStream_t st);
+// dt = C_cfl * min of the accumulated candidates; resets the accumulators
+hipError_t launch_cfl_finalize(const DevPlan& P, double* dt, hipStream_t st);
 hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L,
                          hipStream_t st);
 // floor-reset counter: mode 0 mark = counter; 1 mark = counter - mark;

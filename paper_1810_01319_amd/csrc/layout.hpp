@@ -11,6 +11,9 @@ namespace amr {
 
 constexpr int kGhost = 3;
 constexpr int kFields = 5;
+// slots per leaf of the next-step signal-speed maxima of a run of steps (spread
+// so that a leaf's waves do not all update one word)
+constexpr int kCflSlots = 16;
 
 // Per mesh instance: gas constants in the exact forms the formulas use
 // (computed once on the host in FP64) and the geometry.
@@ -30,7 +33,8 @@ static_assert(sizeof(InstParams) % 8 == 0, "InstParams packing");
 struct BlockInfo {
   int32_t level, i, j, k;
   int32_t inst;
-  int32_t pad[3];
+  int32_t rflx;  // bit 2 d + side: the reflux corrects this leaf's face (d, side)
+  int32_t pad[2];
 };
 
 // Neighbour of a leaf in one of the 26 directions (code = (sx+1) +
@@ -70,8 +74,8 @@ struct Reloc {
 };
 
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, dte, counters, ind, migr, reloc, reloc_child,
-      faces, total;
+  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, lacc, dte, counters, ind, migr, reloc,
+      reloc_child, faces, total;
 };
 
 }  // namespace amr

@@ -309,6 +309,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
             t.slot_f[hA + 2 * hB] = fslot;
           }
         reflux[dir].push_back(t);
+        blocks[size_t(s)].rflx |= 1 << (2 * dir + side);
       }
     }
   }
@@ -326,6 +327,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
     o = align256(o + int64_t(reflux[d].size() * sizeof(RefluxTask)));
   }
   off.acc = o; o = align256(o + ninst * 8);
+  off.lacc = o; o = align256(o + nleaf * kCflSlots * 8);
   off.dte = o; o = align256(o + ninst * 8);
   off.counters = o; o = align256(o + 8);
   off.ind = o; o = align256(o + nleaf * 8);

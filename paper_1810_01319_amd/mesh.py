@@ -142,6 +142,15 @@ class Mesh:
         self._check_state(U)
         check(lib().amr_hydro_step(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
 
+    def steps(self, U: torch.Tensor, dt: torch.Tensor, n: int, first: int = 0) -> None:
+        """n consecutive steps in one call (the same results as n step calls);
+        dt holds n * n_instances doubles, step i's in row i.  Each step's CFL
+        reduction is fused into its predecessor."""
+        self._check_state(U)
+        if dt.numel() < n * self.n_instances:
+            raise ValueError("dt holds fewer than n * n_instances values")
+        check(lib().amr_hydro_steps(self._h, _ptr(U), _ptr(dt), int(n), int(first), _stream()))
+
     def step_dt(self, U: torch.Tensor, dt: torch.Tensor, k: int) -> None:
         self._check_state(U)
         check(lib().amr_hydro_step_dt(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
