@@ -349,11 +349,13 @@ def comoving_compare(steps: int = 20):
 
 
 def step_bytes_per_block(N: int) -> int:
-    """Algorithmic HBM bytes of one step of one block: CFL read, refresh,
-    three sweeps (reflux is negligible)."""
+    """Algorithmic HBM bytes of one step of one block in a run of steps:
+    refresh and three sweeps (the CFL candidates are taken from the values
+    the last sweep writes, so the CFL reads nothing of its own; reflux is
+    negligible)."""
     from paper_1810_01319_amd import costs
 
-    return costs.cfl_bytes_per_block(N) + costs.refresh_bytes_per_block(N) + costs.sweep_bytes_per_block_step(N)
+    return costs.refresh_bytes_per_block(N) + costs.sweep_bytes_per_block_step(N)
 
 
 def cpu_baseline_adaptive(spec_tile, steps: int = 9):
