@@ -108,8 +108,9 @@ def cpu_baseline(spec, act_fn, steps):
 
 def batched_compare(steps: int, n_inst: int = 256):
     """The batched workload: n_inst independent meshes of uneven size in one
-    flat worklist (two steps captured in a HIP graph) against the same
-    meshes stepped one mesh per launch sequence."""
+    flat worklist (two steps, the second's CFL fused into the first,
+    captured in a HIP graph) against the same meshes stepped one mesh per
+    launch sequence (two fused steps per call)."""
     import numpy as np
     import torch
 
@@ -129,13 +130,14 @@ def batched_compare(steps: int, n_inst: int = 256):
             U[bm.first_leaf[i]:bm.first_leaf[i + 1], :, g3:g3 + bm.N, g3:g3 + bm.N, g3:g3 + bm.N] = \
                 torch.from_numpy(a).to(bm.device)
         dt = bm.dt_tensor()
-        # eager batched steps (fewer: for reference only)
-        eager = min(steps, 20)
-        bm.step(U, dt, 0)
+        dt2 = torch.zeros(2 * bm.n_instances, dtype=torch.float64, device=bm.device)
+        # eager batched steps, two per call as in the graph (fewer: for reference only)
+        eager = max(2, min(steps, 20)) // 2 * 2
+        bm.steps(U, dt2, 2, 0)
         side.synchronize()
         t0 = time.perf_counter()
-        for k in range(1, eager + 1):
-            bm.step(U, dt, k)
+        for k in range(2, eager + 2, 2):
+            bm.steps(U, dt2, 2, k)
         side.synchronize()
         out["batched_eager"] = cells * eager / (time.perf_counter() - t0)
         # graph of two steps
@@ -148,21 +150,21 @@ def batched_compare(steps: int, n_inst: int = 256):
         side.synchronize()
         out["batched_graph"] = cells * 2 * (steps // 2) / (time.perf_counter() - t0)
         del g
-        # one mesh per launch sequence
+        # one mesh per launch sequence, two fused steps per call
         meshes = []
         for i, (sp, _) in enumerate(inst):
             m = Mesh(**sp.kwargs())
             um = m.state_from_active(acts[i])
-            meshes.append((m, um, torch.zeros(1, dtype=torch.float64, device=m.device)))
+            meshes.append((m, um, torch.zeros(2, dtype=torch.float64, device=m.device)))
         for m, um, dtm in meshes:
-            m.step(um, dtm, 0)
+            m.steps(um, dtm, 2, 0)
         side.synchronize()
         t0 = time.perf_counter()
-        for k in range(1, steps + 1):
+        for k in range(2, 2 * (steps // 2) + 2, 2):
             for m, um, dtm in meshes:
-                m.step(um, dtm, k)
+                m.steps(um, dtm, 2, k)
         side.synchronize()
-        out["per_mesh_launch"] = cells * steps / (time.perf_counter() - t0)
+        out["per_mesh_launch"] = cells * 2 * (steps // 2) / (time.perf_counter() - t0)
     out["speedup_graph_vs_per_mesh"] = out["batched_graph"] / out["per_mesh_launch"]
     return out
 

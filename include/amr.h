@@ -184,7 +184,10 @@ amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev
 /* HIP graph of two consecutive steps (first_step and first_step+1, so one
  * even and one odd sweep order) bound to U_dev and dt_dev, captured on a
  * non-null stream; each launch advances the state by two steps.  The
- * captured kernels read and write the same buffers every launch. */
+ * second step's CFL reduction is fused into the first step, as in
+ * amr_hydro_steps, and both steps use the ninst doubles at dt_dev (after a
+ * launch they hold the second step's dt).  The captured kernels read and
+ * write the same buffers every launch. */
 amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t first_step, void* stream,
                             amr_graph** out);
 amr_status amr_graph_launch(amr_graph* graph, void* stream);

@@ -846,12 +846,15 @@ amr_status amr_graph_create(amr_mesh* h, double* U, double* dt, int64_t first_st
     return hip_fail(e, "begin capture");
   }
   const DevPlan P = dev_plan(h);
+  // The first step's CFL reduction reads the state; the second step's is
+  // accumulated by the first step and only finalized (as in amr_hydro_steps).
+  double* const inplace[3] = {U, U, U};
   amr_status srs = AMR_OK;
-  for (int64_t k = first_step; k < first_step + 2 && srs == AMR_OK; k++) {
-    hipError_t e2 = launch_cfl(P, U, dt, h->cfg, st);
-    if (e2 != hipSuccess) srs = hip_fail(e2, "cfl");
-    else srs = run_step(h, U, dt, k, st);
-  }
+  hipError_t e2 = launch_cfl(P, U, dt, h->cfg, st);
+  if (e2 != hipSuccess) srs = hip_fail(e2, "cfl");
+  if (srs == AMR_OK) srs = run_step_into(h, U, inplace, dt, first_step, st, nullptr, 1);
+  if (srs == AMR_OK && (e2 = launch_cfl_finalize(P, dt, st)) != hipSuccess) srs = hip_fail(e2, "cfl");
+  if (srs == AMR_OK) srs = run_step(h, U, dt, first_step + 1, st);
   e = hipStreamEndCapture(st, &g->graph);
   if (srs != AMR_OK || e != hipSuccess) {
     if (g->graph) (void)hipGraphDestroy(g->graph);

@@ -318,8 +318,9 @@ def test_batched_instances_match_oracle_bitwise():
 
 
 def test_graph_replays_equal_eager_steps():
-    """Two captured steps replayed several times, with eager work and
-    synchronisations in between, equal the same steps run eagerly."""
+    """Two captured steps (the second's CFL fused into the first) replayed
+    several times, with eager work and synchronisations in between, equal
+    the same steps run eagerly one by one, state and dt."""
     specs, cents = zip(*[I.batch_instance(i) for i in range(6)])
     gm = Mesh.batch([s.kwargs() for s in specs])
     acts = [I.batch_state(sp, gm.keys[gm.first_leaf[i]:gm.first_leaf[i + 1]], c)
@@ -343,6 +344,7 @@ def test_graph_replays_equal_eager_steps():
             assert float(junk) == 1000.0
         got = gm.active(Ug)
     assert np.array_equal(got, ref)
+    assert torch.equal(dtg, dte)  # both hold the sixth step's dt
 
 
 def _floor_spec_state():
