@@ -41,7 +41,6 @@
 #include <string.h>
 
 #define G ORC_GHOST
-#define NF ORC_NFIELD
 
 enum { ABSENT = 0, LEAF = 1, REFINED = 2 };
 
@@ -57,7 +56,8 @@ struct orc_mesh {
   int32_t* leaf_at[ORC_MAXLEV];
   int64_t nleaf;
   int32_t* key;   /* (level, i, j, k) per leaf */
-  double* U;      /* nleaf * NF * M^3 */
+  int nf;         /* fields per cell: 5, or 6 with the dual-energy field */
+  double* U;      /* nleaf * nf * M^3 */
   double** face;  /* 6 per leaf: coarse-fine face flux buffers or NULL */
   int64_t floors;
 };
@@ -65,9 +65,14 @@ struct orc_mesh {
 typedef struct {
   double gamma, gm1, inv_gm1, g_gm1, g1, rho_floor, p_floor, sixth, two3;
   int iters;
+  int de;             /* dual-energy field present */
+  double eta1, eta2;  /* its pressure-selection and resynchronisation thresholds */
 } consts_t;
 
 static char g_err[256];
+/* Test-only switches that plant a known mistake, to show that a pin fails
+ * without the piece it checks (ORC_DEBUG_*). */
+static int g_debug = 0;
 const char* orc_last_error(void) { return g_err; }
 static int fail(const char* msg) {
   snprintf(g_err, sizeof g_err, "%s", msg);
@@ -87,6 +92,19 @@ static consts_t make_consts(double gamma, double rho_floor, double p_floor, int 
   K.sixth = 1.0 / 6.0;
   K.two3 = 2.0 / 3.0;
   K.iters = iters;
+  K.de = 0;
+  K.eta1 = 0.0;
+  K.eta2 = 0.0;
+  return K;
+}
+
+static double cell_pressure(const consts_t* K, double rho, double u, double v, double w, double E, double ge);
+
+static consts_t mesh_consts(const orc_mesh* m) {
+  consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  K.de = m->d.dual_energy != 0;
+  K.eta1 = m->d.eta1;
+  K.eta2 = m->d.eta2;
   return K;
 }
 
@@ -104,7 +122,7 @@ static inline int64_t cell(int M, int f, int a, int b, int c) {
   return (((int64_t)f * M + c) * M + b) * M + a;
 }
 static inline double* block_ptr(const orc_mesh* m, int64_t leaf) {
-  return m->U + leaf * (int64_t)NF * m->M * m->M * m->M;
+  return m->U + leaf * (int64_t)m->nf * m->M * m->M * m->M;
 }
 /* dx at level l: cubic cells, the x extent of the domain is 1. */
 static inline double dx_level(const orc_mesh* m, int l) {
@@ -175,6 +193,9 @@ static int check_desc(const orc_desc* d) {
   }
   if (!(d->gamma > 1.0)) return fail("gamma must exceed 1");
   if (d->riemann_iters < 0) return fail("riemann_iters < 0");
+  if (d->dual_energy != 0 && d->dual_energy != 1) return fail("dual_energy must be 0 or 1");
+  if (d->dual_energy && !(d->eta1 >= 0.0 && d->eta1 <= 1.0 && d->eta2 >= 0.0 && d->eta2 <= 1.0))
+    return fail("eta1 and eta2 must lie in [0, 1]");
   return 0;
 }
 
@@ -185,6 +206,7 @@ static orc_mesh* alloc_mesh(const orc_desc* d) {
   m->d.n_refine = 0;
   m->N = d->block_cells;
   m->M = m->N + 2 * G;
+  m->nf = d->dual_energy ? ORC_NFIELD + 1 : ORC_NFIELD;
   m->nlev = d->max_level + 1;
   for (int l = 0; l < m->nlev; l++) {
     for (int a = 0; a < 3; a++) m->ext[l][a] = d->root[a] << l;
@@ -238,7 +260,7 @@ static int finish_mesh(orc_mesh* m) {
     if (m->d.bc[a] == ORC_BC_OUTFLOW && !uniform)
       return fail("outflow boundaries are supported on single-level meshes only");
   int64_t M3 = (int64_t)m->M * m->M * m->M;
-  m->U = (double*)calloc((size_t)(m->nleaf * NF * M3), sizeof(double));
+  m->U = (double*)calloc((size_t)(m->nleaf * m->nf * M3), sizeof(double));
   if (!m->U) return fail("out of memory");
   /* Coarse-fine faces: a face whose same-level neighbour position is refined
    * (this leaf is the coarse side) or absent (this leaf is the fine side). */
@@ -254,7 +276,7 @@ static int finish_mesh(orc_mesh* m) {
         unsigned char st = m->state[l][nidx(m, l, p[0], p[1], p[2])];
         if (st != LEAF)
           m->face[6 * s + 2 * dir + side] =
-              (double*)calloc((size_t)NF * m->N * m->N, sizeof(double));
+              (double*)calloc((size_t)m->nf * m->N * m->N, sizeof(double));
       }
   }
   return 0;
@@ -347,6 +369,7 @@ void orc_leaf_keys(const orc_mesh* m, int32_t* out) {
 }
 double* orc_state(orc_mesh* m) { return m->U; }
 int64_t orc_floor_count(const orc_mesh* m) { return m->floors; }
+int orc_nfields(const orc_mesh* m) { return m->nf; }
 
 /* ------------------------------------------------------------------ */
 /* Ghost refresh (Sec. II-B: ghost layer of width 3 for all 5 fields)  */
@@ -404,9 +427,9 @@ static void refresh_phase(orc_mesh* m, int phase) {
           int bp[3] = {(int)(p[0] / N), (int)(p[1] / N), (int)(p[2] / N)};
           unsigned char st = m->state[l][nidx(m, l, bp[0], bp[1], bp[2])];
           if (phase == 1 && st == LEAF) {
-            for (int f = 0; f < NF; f++) B[cell(M, f, a, b, c)] = leaf_value(m, l, p, f);
+            for (int f = 0; f < m->nf; f++) B[cell(M, f, a, b, c)] = leaf_value(m, l, p, f);
           } else if (phase == 1 && st == REFINED) {
-            for (int f = 0; f < NF; f++) {
+            for (int f = 0; f < m->nf; f++) {
               double v[8];
               for (int o = 0; o < 8; o++) {
                 int64_t q[3] = {2 * p[0] + (o & 1), 2 * p[1] + ((o >> 1) & 1), 2 * p[2] + (o >> 2)};
@@ -429,7 +452,7 @@ static void refresh_phase(orc_mesh* m, int phase) {
               lc[ax] = (int)(pc[ax] - (int64_t)cb[ax] * N) + G;
               o[ax] = (p[ax] & 1) ? 1.0 : -1.0;
             }
-            for (int f = 0; f < NF; f++) {
+            for (int f = 0; f < m->nf; f++) {
               double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
               double sl[3];
               sl[0] = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
@@ -456,7 +479,7 @@ void orc_refresh(orc_mesh* m) {
  * min over d of dx/(|u_d|+c) equals this because correctly rounded + and /
  * are monotone.  Primitive recovery as in the sweeps, x,y,z order. */
 static double cfl_min(const orc_mesh* m) {
-  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  const consts_t K = mesh_consts(m);
   const int N = m->N, M = m->M;
   double best = INFINITY;
 #pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
@@ -470,7 +493,8 @@ static double cfl_min(const orc_mesh* m) {
           double ir = 1.0 / rho;
           double u = B[cell(M, 1, a, b, c)] * ir, v = B[cell(M, 2, a, b, c)] * ir,
                  w = B[cell(M, 3, a, b, c)] * ir;
-          double p = K.gm1 * (B[cell(M, 4, a, b, c)] - (0.5 * rho) * ((u * u + v * v) + w * w));
+          double p = cell_pressure(&K, rho, u, v, w, B[cell(M, 4, a, b, c)],
+                                   K.de ? B[cell(M, 5, a, b, c)] : 0.0);
           p = p < K.p_floor ? K.p_floor : p;
           double cs = sqrt((K.gamma * p) * ir);
           double vm = dmax(dmax(fabs(u), fabs(v)), fabs(w));
@@ -490,11 +514,22 @@ double orc_cfl_dt(const orc_mesh* m) { return m->d.cfl * cfl_min(m); }
 /* Primitive state of one cell; normal/transverse momenta are the sweep's. */
 typedef struct { double q[5]; double c, ir; } prim_t;  /* q = rho,u,v,w,p */
 
-static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, double mt2, double E) {
+/* Pressure (before the floor) of a cell with density rho, velocity u, v, w,
+ * total energy E and (dual energy) internal energy density ge.  Dual-energy
+ * reading (Bryan et al. 1995): the internal energy is E - ke where it exceeds
+ * eta1 E, else the separately advected rho e. */
+static double cell_pressure(const consts_t* K, double rho, double u, double v, double w, double E, double ge) {
+  const double ie = E - (0.5 * rho) * ((u * u + v * v) + w * w);
+  const int use_ge = (g_debug & ORC_DEBUG_DE_ETA1_FLIP) ? (ie > K->eta1 * E) : !(ie > K->eta1 * E);
+  if (K->de && use_ge) return K->gm1 * ge;
+  return K->gm1 * ie;
+}
+
+static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, double mt2, double E, double ge) {
   prim_t P;
   double ir = 1.0 / rho;
   double u = mn * ir, v = mt1 * ir, w = mt2 * ir;
-  double p = K->gm1 * (E - (0.5 * rho) * ((u * u + v * v) + w * w));
+  double p = cell_pressure(K, rho, u, v, w, E, ge);
   p = p < K->p_floor ? K->p_floor : p;
   P.q[0] = rho; P.q[1] = u; P.q[2] = v; P.q[3] = w; P.q[4] = p;
   P.c = sqrt((K->gamma * p) * ir);
@@ -598,9 +633,14 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
  *   u*_L = u_L - (p* - p_L)/W_L,  u*_R = u_R + (p* - p_R)/W_R,
  *   p*  <- p* - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
  *   u*   = (u*_L/Z_R + u*_R/Z_L) / (1/Z_L + 1/Z_R)   (= Z-weighted mean).
- * Returns the Godunov state and its flux. */
+ * Returns the Godunov state and its flux; with the dual-energy field also
+ * the flux of rho e, the internal-energy flux of the Godunov state,
+ * u_g p_g / (gamma - 1) (rho e and p are the same variable up to the factor
+ * gamma - 1, so its interface value is the characteristic-traced p_g; a
+ * value carried along the contact alone would miss the acoustic waves and
+ * drop to first order in time). */
 static void riemann(const consts_t* K, const double WLs[5], const double WRs[5], double Wg[5],
-                    double F[5], double* pstar, double* ustar) {
+                    double F[], double* pstar, double* ustar) {
   const double rL = WLs[0], uL = WLs[1], pL = WLs[4];
   const double rR = WRs[0], uR = WRs[1], pR = WRs[4];
   const double CL = sqrt((K->gamma * pL) * rL), CR = sqrt((K->gamma * pR) * rR);
@@ -657,21 +697,25 @@ static void riemann(const consts_t* K, const double WLs[5], const double WRs[5],
   F[2] = mf * vg;
   F[3] = mf * wg;
   F[4] = ug * (pg * K->g_gm1 + (0.5 * rg) * ((ug * ug + vg * vg) + wg * wg));
+  if (K->de) F[5] = ug * (pg * ((g_debug & ORC_DEBUG_DE_ENTHALPY) ? K->g_gm1 : K->inv_gm1));
   Wg[0] = rg; Wg[1] = ug; Wg[2] = vg; Wg[3] = wg; Wg[4] = pg;
   if (pstar) *pstar = ps;
   if (ustar) *ustar = us;
 }
 
 /* Fluxes at interfaces j+1/2, j = 2 .. n-4, of a pencil of n cells; U is
- * (rho, m_normal, m_t1, m_t2, E) x n, F is 5 x (n-5).  Cell j's update needs
- * cells j-3 .. j+3, which a ghost width of 3 provides. */
-static void pencil(const consts_t* K, double nu, int n, const double* const U[5], double* const F[5]) {
+ * (rho, m_normal, m_t1, m_t2, E [, rho e]) x n, F is nv x (n-5) and, with the
+ * dual-energy field, ug (n-5) the Godunov velocity at each interface.  Cell
+ * j's update needs cells j-3 .. j+3, which a ghost width of 3 provides. */
+static void pencil(const consts_t* K, double nu, int n, const double* const U[], double* const F[], double* ug) {
+  const int nf = K->de ? 6 : 5;
   prim_t* P = (prim_t*)malloc((size_t)n * sizeof(prim_t));
   double(*dl)[5] = malloc((size_t)n * sizeof *dl);   /* slopes */
   double(*fa)[5] = malloc((size_t)n * sizeof *fa);   /* face values at j+1/2 */
   double(*WL)[5] = malloc((size_t)n * sizeof *WL);   /* left state at j+1/2 from cell j */
   double(*WR)[5] = malloc((size_t)n * sizeof *WR);   /* right state at j-1/2 from cell j */
-  for (int j = 0; j < n; j++) P[j] = to_prim(K, U[0][j], U[1][j], U[2][j], U[3][j], U[4][j]);
+  for (int j = 0; j < n; j++)
+    P[j] = to_prim(K, U[0][j], U[1][j], U[2][j], U[3][j], U[4][j], K->de ? U[5][j] : 0.0);
   for (int j = 1; j <= n - 2; j++)
     for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
   /* interface value q_{j+1/2} = 0.5 (q_j + q_{j+1}) - (dq_{j+1} - dq_j) / 6 */
@@ -697,9 +741,10 @@ static void pencil(const consts_t* K, double nu, int n, const double* const U[5]
     trace_cell(K, &P[j], par, nu, WL[j], WR[j]);
   }
   for (int j = 2; j <= n - 4; j++) {
-    double Wg[5], Fl[5];
+    double Wg[5], Fl[6];
     riemann(K, WL[j], WR[j + 1], Wg, Fl, NULL, NULL);
-    for (int v = 0; v < 5; v++) F[v][j - 2] = Fl[v];
+    for (int v = 0; v < nf; v++) F[v][j - 2] = Fl[v];
+    if (ug) ug[j - 2] = Wg[1];
   }
   free(P); free(dl); free(fa); free(WL); free(WR);
 }
@@ -721,13 +766,15 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
   for (int64_t s = 0; s < m->nleaf; s++) {
     double* B = block_ptr(m, s);
     const double nu = dt / dx_level(m, m->key[4 * s]);
-    double* in[5];
-    double* fl[5];
-    for (int v = 0; v < 5; v++) {
+    const int nv = m->nf;
+    double* in[6];
+    double* fl[6];
+    for (int v = 0; v < nv; v++) {
       in[v] = (double*)malloc((size_t)M * sizeof(double));
       fl[v] = (double*)malloc((size_t)M * sizeof(double));
     }
-    const int fmap[5] = {0, 1 + dir, 1 + t1, 1 + t2, 4};
+    double* ug = (double*)malloc((size_t)M * sizeof(double));
+    const int fmap[6] = {0, 1 + dir, 1 + t1, 1 + t2, 4, 5};
     double* flo = m->face[6 * s + 2 * dir];
     double* fhi = m->face[6 * s + 2 * dir + 1];
     int64_t nfl = 0;
@@ -738,13 +785,20 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
         pos[t2] = i2;
         for (int j = 0; j < M; j++) {
           pos[dir] = j;
-          for (int v = 0; v < 5; v++) in[v][j] = B[cell(M, fmap[v], pos[0], pos[1], pos[2])];
+          for (int v = 0; v < nv; v++) in[v][j] = B[cell(M, fmap[v], pos[0], pos[1], pos[2])];
         }
-        pencil(K, nu, M, (const double* const*)in, fl);
+        pencil(K, nu, M, (const double* const*)in, fl, ug);
         /* flux index k is interface (G-1+k)+1/2 */
         for (int j = G; j < G + N; j++) {
-          double Un[5];
-          for (int v = 0; v < 5; v++) Un[v] = in[v][j] - nu * (fl[v][j - G + 1] - fl[v][j - G]);
+          double Un[6];
+          for (int v = 0; v < nv; v++) Un[v] = in[v][j] - nu * (fl[v][j - G + 1] - fl[v][j - G]);
+          if (K->de) {
+            /* the -p div(v) work on rho e: the cell's pressure (as in its
+             * primitives) times the difference of the Godunov velocities */
+            const prim_t Pj = to_prim(K, in[0][j], in[1][j], in[2][j], in[3][j], in[4][j], in[5][j]);
+            const double work = Pj.q[4] * (ug[j - G + 1] - ug[j - G]);
+            Un[5] = (g_debug & ORC_DEBUG_DE_PDV_SIGN) ? Un[5] + nu * work : Un[5] - nu * work;
+          }
           /* post-update floors (counted: they break conservation) */
           if (Un[0] < K->rho_floor) { Un[0] = K->rho_floor; nfl++; }
           double ir = 1.0 / Un[0];
@@ -752,21 +806,29 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
           double ke = (0.5 * Un[0]) * ((u * u + v * v) + w * w);
           double p = K->gm1 * (Un[4] - ke);
           if (p < K->p_floor) { Un[4] = K->p_floor * K->inv_gm1 + ke; nfl++; }
+          if (K->de) {
+            /* resynchronise rho e from the total energy where E - ke > eta2 E,
+             * then its own floor (counted) */
+            const double ie = Un[4] - ke;
+            if (ie > K->eta2 * Un[4]) Un[5] = ie;
+            if (K->gm1 * Un[5] < K->p_floor) { Un[5] = K->p_floor * K->inv_gm1; nfl++; }
+          }
           pos[dir] = j;
-          for (int vv = 0; vv < 5; vv++) B[cell(M, fmap[vv], pos[0], pos[1], pos[2])] = Un[vv];
+          for (int vv = 0; vv < nv; vv++) B[cell(M, fmap[vv], pos[0], pos[1], pos[2])] = Un[vv];
         }
         /* coarse-fine face fluxes, in conserved-field order */
         int ta1 = (a1 == t1) ? i1 : i2, ta2 = (a2 == t1) ? i1 : i2;
         if (ta1 >= G && ta1 < G + N && ta2 >= G && ta2 < G + N) {
           int64_t off = (int64_t)(ta2 - G) * N + (ta1 - G);
-          for (int v = 0; v < 5; v++) {
+          for (int v = 0; v < nv; v++) {
             if (flo) flo[(int64_t)fmap[v] * N * N + off] = fl[v][0];
             if (fhi) fhi[(int64_t)fmap[v] * N * N + off] = fl[v][N];
           }
         }
       }
     nfl_total += nfl;
-    for (int v = 0; v < 5; v++) { free(in[v]); free(fl[v]); }
+    for (int v = 0; v < nv; v++) { free(in[v]); free(fl[v]); }
+    free(ug);
   }
   m->floors += nfl_total;
 }
@@ -808,7 +870,7 @@ static void reflux(orc_mesh* m, double dt) {
             pos[dir] = side ? G + N - 1 : G;
             pos[a1] = G + t1;
             pos[a2] = G + t2;
-            for (int f = 0; f < NF; f++) {
+            for (int f = 0; f < m->nf; f++) {
               const double* Q = Ff + (int64_t)f * N * N;
               double fb = ((Q[f2 * N + f1] + Q[f2 * N + f1 + 1]) + (Q[(f2 + 1) * N + f1] + Q[(f2 + 1) * N + f1 + 1])) * 0.25;
               double corr = nu * (Fc[(int64_t)f * N * N + t2 * N + t1] - fb);
@@ -821,13 +883,10 @@ static void reflux(orc_mesh* m, double dt) {
   }
 }
 
-/* Test-only switches that plant a known mistake, to show that a pin fails
- * without the piece it checks. */
-static int g_debug = 0;
 void orc_set_debug(int flags) { g_debug = flags; }
 
 void orc_step_dt(orc_mesh* m, int64_t step_index, double dt) {
-  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  const consts_t K = mesh_consts(m);
   orc_refresh(m);
   int order[3] = {0, 1, 2};
   if (step_index & 1) { order[0] = 2; order[2] = 0; }
@@ -866,7 +925,7 @@ double orc_step(orc_mesh* m, int64_t step_index) {
 double orc_cfl_dt_comoving(const orc_mesh* m, double a) { return (m->d.cfl * a) * cfl_min(m); }
 
 static void expansion(orc_mesh* m, double dt, double hubble) {
-  const consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  const consts_t K = mesh_consts(m);
   const int N = m->N, M = m->M;
   const double c = (0.5 * dt) * hubble;
   const double g3 = 3.0 * K.gm1;
@@ -897,6 +956,15 @@ static void expansion(orc_mesh* m, double dt, double hubble) {
           *my = *my * fv;
           *mz = *mz * fv;
           *E = *E + ((ie2 - ie) + ke * (fv * fv - 1.0));
+          if (K.de) { /* the dual-energy field takes the same factor and floor rule */
+            double* ge = &B[cell(M, 5, x, y, z)];
+            double ge2 = *ge * fe;
+            if (ge2 < *ge && K.gm1 * ge2 < K.p_floor) {
+              ge2 = K.p_floor * K.inv_gm1;
+              nfl++;
+            }
+            *ge = ge2;
+          }
         }
   }
   m->floors += nfl;
@@ -1028,7 +1096,7 @@ void orc_pencil_flux(const double* gas, int iters, double nu, int n, const doubl
     in[v] = U + (int64_t)v * n;
     out[v] = flux_out + (int64_t)v * (n - 5);
   }
-  pencil(&K, nu, n, in, out);
+  pencil(&K, nu, n, in, out, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1239,7 +1307,7 @@ int orc_remesh(orc_mesh* m, double refine_slope, double coarsen_slope, int64_t m
       double* D = block_ptr(nm, s);
       if (orig[l][nidx(m, l, kk[1], kk[2], kk[3])] == LEAF) {
         const double* Sb = block_ptr(m, m->leaf_at[l][nidx(m, l, kk[1], kk[2], kk[3])]);
-        for (int f = 0; f < NF; f++)
+        for (int f = 0; f < m->nf; f++)
           for (int c = G; c < G + N; c++)
             for (int b = G; b < G + N; b++)
               for (int a = G; a < G + N; a++) D[cell(M, f, a, b, c)] = Sb[cell(M, f, a, b, c)];
@@ -1257,7 +1325,7 @@ int orc_remesh(orc_mesh* m, double refine_slope, double coarsen_slope, int64_t m
                 lc[ax] = (co[ax] * N + fa[ax]) / 2 + G;
                 o[ax] = (fa[ax] & 1) ? 1.0 : -1.0;
               }
-              for (int f = 0; f < NF; f++) {
+              for (int f = 0; f < m->nf; f++) {
                 double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
                 double sx = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
                 double sy = minmod(C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - u0, u0 - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
@@ -1272,7 +1340,7 @@ int orc_remesh(orc_mesh* m, double refine_slope, double coarsen_slope, int64_t m
           for (int b = 0; b < N; b++)
             for (int a = 0; a < N; a++) {
               const int fa[3] = {a, b, c};
-              for (int f = 0; f < NF; f++) {
+              for (int f = 0; f < m->nf; f++) {
                 double v[8];
                 for (int q = 0; q < 8; q++) {
                   int64_t gq[3];

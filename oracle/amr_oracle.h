@@ -25,7 +25,7 @@ extern "C" {
 #endif
 
 #define ORC_GHOST 3
-#define ORC_NFIELD 5
+#define ORC_NFIELD 5     /* rho, m_x, m_y, m_z, E; dual energy adds rho e */
 #define ORC_MAXLEV 8
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
@@ -39,6 +39,12 @@ typedef struct {
   int32_t riemann_iters;  /* fixed number of two-shock Newton iterations    */
   int32_t n_refine;       /* static refinement list: (level,i,j,k) x n      */
   const int32_t* refine;
+  /* Dual-energy formalism (Bryan et al. 1995): a sixth field rho e (internal
+   * energy density) advected with the flow and given the -p div(v) work; the
+   * pressure comes from E - ke where (E - ke) > eta1 E, else from rho e; after
+   * each sweep's update rho e is reset to E - ke where (E - ke) > eta2 E. */
+  int32_t dual_energy;    /* 0: five fields; 1: six fields                  */
+  double eta1, eta2;
 } orc_desc;
 
 typedef struct orc_mesh orc_mesh;
@@ -55,7 +61,9 @@ const char* orc_last_error(void);
 int64_t orc_nleaf(const orc_mesh* m);
 int orc_num_threads(void); /* OpenMP threads the oracle's loops use */
 void orc_leaf_keys(const orc_mesh* m, int32_t* out /* 4 x nleaf */);
-/* Padded block storage: U[leaf][field][z][y][x], edge M = N + 6. */
+/* Padded block storage: U[leaf][field][z][y][x], edge M = N + 6; 5 fields,
+ * or 6 with the dual-energy field (orc_nfields). */
+int orc_nfields(const orc_mesh* m);
 double* orc_state(orc_mesh* m);
 int64_t orc_floor_count(const orc_mesh* m);
 
@@ -88,6 +96,9 @@ double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, d
 
 /* Test hooks on the building blocks. *//* Test hooks on the building blocks. */
 #define ORC_DEBUG_SKIP_REFLUX 1
+#define ORC_DEBUG_DE_PDV_SIGN 2   /* rho e takes +p div(v) */
+#define ORC_DEBUG_DE_ENTHALPY 4   /* rho e flux with gamma / (gamma - 1) */
+#define ORC_DEBUG_DE_ETA1_FLIP 8  /* pressure source selection reversed */
 void orc_set_debug(int flags);
 void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
                  const double* WL /* rho,u,v,w,p */, const double* WR,

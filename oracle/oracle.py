@@ -52,6 +52,9 @@ class _Desc(ctypes.Structure):
         ("riemann_iters", ctypes.c_int32),
         ("n_refine", ctypes.c_int32),
         ("refine", ctypes.POINTER(ctypes.c_int32)),
+        ("dual_energy", ctypes.c_int32),
+        ("eta1", ctypes.c_double),
+        ("eta2", ctypes.c_double),
     ]
 
 
@@ -78,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.orc_state.restype = ctypes.POINTER(ctypes.c_double)
         L.orc_floor_count.argtypes = [P]
         L.orc_floor_count.restype = I64
+        L.orc_nfields.argtypes = [P]
+        L.orc_nfields.restype = I32
         L.orc_refresh.argtypes = [P]
         L.orc_cfl_dt.argtypes = [P]
         L.orc_cfl_dt.restype = D
@@ -110,7 +115,8 @@ def _ptr(a: np.ndarray):
 
 
 def make_desc(root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
-              rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=()):
+              rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), dual_energy=False,
+              eta1=1e-3, eta2=0.1):
     d = _Desc()
     d.root[:] = [int(r) for r in root]
     d.block_cells = int(block_cells)
@@ -119,6 +125,8 @@ def make_desc(root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
     d.bc[:] = [BC[b] if isinstance(b, str) else int(b) for b in bcs]
     d.gamma, d.cfl, d.rho_floor, d.p_floor = float(gamma), float(cfl), float(rho_floor), float(p_floor)
     d.riemann_iters = int(riemann_iters)
+    d.dual_energy = 1 if dual_energy else 0
+    d.eta1, d.eta2 = float(eta1), float(eta2)
     ref = np.ascontiguousarray(np.asarray(refine, dtype=np.int32).reshape(-1, 4))
     d.n_refine = ref.shape[0]
     d.refine = ref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if ref.size else None
@@ -130,9 +138,10 @@ class OracleMesh:
 
     def __init__(self, root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
                  rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), leaves=None,
-                 _handle=None):
+                 dual_energy=False, eta1=1e-3, eta2=0.1, _handle=None):
         self._kw = dict(root=root, block_cells=block_cells, max_level=max_level, bc=bc, gamma=gamma,
-                        cfl=cfl, rho_floor=rho_floor, p_floor=p_floor, riemann_iters=riemann_iters)
+                        cfl=cfl, rho_floor=rho_floor, p_floor=p_floor, riemann_iters=riemann_iters,
+                        dual_energy=dual_energy, eta1=eta1, eta2=eta2)
         L = lib()
         h = ctypes.c_void_p()
         if _handle is not None:
@@ -153,9 +162,10 @@ class OracleMesh:
         keys = np.zeros((self.nleaf, 4), dtype=np.int32)
         L.orc_leaf_keys(h, _ptr(keys))
         self.keys = keys
-        n = self.nleaf * NFIELD * self.M ** 3
+        self.nf = int(L.orc_nfields(h))  # 5, or 6 with the dual-energy field rho e
+        n = self.nleaf * self.nf * self.M ** 3
         buf = np.ctypeslib.as_array(L.orc_state(h), shape=(n,))
-        self.U = buf.reshape(self.nleaf, NFIELD, self.M, self.M, self.M)
+        self.U = buf.reshape(self.nleaf, self.nf, self.M, self.M, self.M)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -252,6 +262,9 @@ class Tracers:
 
 
 DEBUG_SKIP_REFLUX = 1
+DEBUG_DE_PDV_SIGN = 2
+DEBUG_DE_ENTHALPY = 4
+DEBUG_DE_ETA1_FLIP = 8
 
 
 def num_threads() -> int:

@@ -36,12 +36,22 @@ class MeshSpec:
     p_floor: float = 1e-20
     riemann_iters: int = 5
     refine: List[Tuple[int, int, int, int]] = field(default_factory=list)
+    dual_energy: bool = False       # sixth field rho e (internal energy density)
+    eta1: float = 1e-3              # its pressure-selection threshold
+    eta2: float = 0.1               # its resynchronisation threshold
 
     def kwargs(self) -> dict:
-        return dict(root=tuple(self.root), block_cells=self.block_cells, max_level=self.max_level,
-                    bc=self.bc, gamma=self.gamma, cfl=self.cfl, rho_floor=self.rho_floor,
-                    p_floor=self.p_floor, riemann_iters=self.riemann_iters,
-                    refine=list(self.refine))
+        kw = dict(root=tuple(self.root), block_cells=self.block_cells, max_level=self.max_level,
+                  bc=self.bc, gamma=self.gamma, cfl=self.cfl, rho_floor=self.rho_floor,
+                  p_floor=self.p_floor, riemann_iters=self.riemann_iters,
+                  refine=list(self.refine))
+        if self.dual_energy:
+            kw.update(dual_energy=True, eta1=self.eta1, eta2=self.eta2)
+        return kw
+
+    @property
+    def nfields(self) -> int:
+        return 6 if self.dual_energy else 5
 
     def dx(self, level: int) -> float:
         return 1.0 / float(self.root[0] * self.block_cells * (1 << level))
@@ -79,6 +89,15 @@ def conserved(gamma: float, rho, u, v, w, p) -> np.ndarray:
     out[:, 3] = rho * w
     out[:, 4] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
     return out
+
+
+def with_internal_energy(act: np.ndarray) -> np.ndarray:
+    """Append the dual-energy field rho e = E - |m|^2 / (2 rho) to a state of
+    five conserved fields (an initial internal energy consistent with E)."""
+    act = np.asarray(act, dtype=np.float64)
+    rho, m, E = act[:, 0], act[:, 1:4], act[:, 4]
+    ge = E - 0.5 * (m[:, 0] ** 2 + m[:, 1] ** 2 + m[:, 2] ** 2) / rho
+    return np.concatenate([act, ge[:, None]], axis=1)
 
 
 # ---------------------------------------------------------------------------
