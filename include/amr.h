@@ -24,9 +24,11 @@
  *   - Every call returns an amr_status; on failure amr_last_error() gives a
  *     message (per thread, valid until the next failing call).
  *   - Field storage U_dev: n_leaves blocks in the order of amr_mesh_blocks,
- *     each block = 5 fields (rho, m_x, m_y, m_z, E) of M^3 FP64 values,
+ *     each block = 5 fields (rho, m_x, m_y, m_z, E), 6 with the dual-energy
+ *     field rho e (amr_mesh_desc.dual_energy), of M^3 FP64 values,
  *     M = N + 6 (ghost width 3 on each side), index (field, z, y, x) with x
- *     fastest, no padding: block stride 5 M^3 doubles, field stride M^3.
+ *     fastest, no padding: block stride n_fields M^3 doubles, field stride
+ *     M^3.
  *     Only active cells (ghost-free interior N^3) carry state between calls;
  *     ghosts are scratch that a refresh overwrites.
  */
@@ -71,13 +73,26 @@ typedef struct {
   int32_t riemann_iters;  /* fixed two-shock Newton iterations (e.g. 5)     */
   int32_t n_refine;       /* static refinement list, borrowed for the call: */
   const int32_t* refine;  /* n_refine x (level, i, j, k) block keys         */
+  /* Dual-energy formalism (Bryan et al. 1995, the PPM variant the paper's
+   * Sec. II-C Method derives from, for flows whose kinetic energy dwarfs the
+   * thermal one): 1 adds a sixth field rho e (internal energy density) to
+   * every cell.  A cell's pressure is (gamma-1)(E - ke) where E - ke > eta1 E,
+   * else (gamma-1) rho e; rho e is carried by the internal-energy flux of the
+   * Godunov state u_g p_g / (gamma-1) and takes the work -p div(v) (the cell
+   * pressure times the difference of the Godunov velocities); after each
+   * sweep's update rho e = E - ke where E - ke > eta2 E, then rho e is
+   * floored at p_floor / (gamma-1) (counted).  The refresh, reflux, remesh
+   * and comoving expansion treat rho e like the other fields; the adjoint
+   * entries reject such meshes.  All instances of a batch must agree. */
+  int32_t dual_energy;    /* 0 or 1                                         */
+  double eta1, eta2;      /* in [0, 1]; typically 1e-3 and 0.1              */
 } amr_mesh_desc;
 
 typedef struct {
   int64_t n_leaves;
   int32_t block_cells;     /* N */
   int32_t padded;          /* M = N + 6 */
-  int64_t block_stride;    /* doubles per block = 5 M^3 */
+  int64_t block_stride;    /* doubles per block = n_fields M^3 */
   int64_t field_stride;    /* doubles per field = M^3 */
   int64_t field_bytes;     /* bytes of U_dev = n_leaves * block_stride * 8 */
   int64_t workspace_bytes; /* bytes the caller allocates for amr_mesh_upload */
@@ -86,6 +101,8 @@ typedef struct {
   int64_t n_instances;     /* meshes in the handle (1 unless batched) */
   int64_t adjoint_scratch_bytes; /* scratch of amr_hydro_step_adjoint */
   int64_t adjoint_face_bytes;    /* scratch of amr_hydro_step_adjoint_recorded */
+  int32_t n_fields;        /* 5 (rho, m_x, m_y, m_z, E), or 6 with rho e */
+  int32_t pad0;
 } amr_mesh_info_t;
 
 /* Build the balanced array-of-octrees: roots, then each refine entry in
@@ -127,7 +144,7 @@ amr_status amr_mesh_blocks(const amr_mesh* mesh, int32_t* keys_out, int64_t cap)
  * stream; the workspace must outlive every later call on this mesh. */
 amr_status amr_mesh_upload(amr_mesh* mesh, void* workspace_dev, void* stream);
 
-/* Ghost refresh (Sec. II-B): fill the width-3 ghost shell of all 5 fields of
+/* Ghost refresh (Sec. II-B): fill the width-3 ghost shell of all fields of
  * every leaf.  Phase 1: same-level copies (faces, edges, corners; periodic
  * wrap; outflow = nearest domain cell), restriction (mean of the 8 children)
  * into ghosts covered by finer leaves.  Phase 2: minmod-limited linear
@@ -193,7 +210,10 @@ amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64
 amr_status amr_graph_launch(amr_graph* graph, void* stream);
 amr_status amr_graph_destroy(amr_graph* graph);
 
-/* One hydro step (as amr_hydro_step, bitwise the same result) that keeps
+/* The recording step and the three adjoint entries below need a five-field
+ * mesh: they return AMR_E_INVALID for a mesh with the dual-energy field.
+ *
+ * One hydro step (as amr_hydro_step, bitwise the same result) that keeps
  * what its adjoint needs, for reverse-mode differentiation without
  * recomputation: U_dev's ghosts are refreshed in place and U_dev is otherwise
  * not modified (it becomes the first sweep's input S0); the first and second

@@ -40,6 +40,9 @@ class MeshDesc(ctypes.Structure):
         ("riemann_iters", ctypes.c_int32),
         ("n_refine", ctypes.c_int32),
         ("refine", ctypes.POINTER(ctypes.c_int32)),
+        ("dual_energy", ctypes.c_int32),
+        ("eta1", ctypes.c_double),
+        ("eta2", ctypes.c_double),
     ]
 
 
@@ -61,6 +64,8 @@ class MeshInfo(ctypes.Structure):
         ("n_instances", ctypes.c_int64),
         ("adjoint_scratch_bytes", ctypes.c_int64),
         ("adjoint_face_bytes", ctypes.c_int64),
+        ("n_fields", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
     ]
 
 
@@ -151,7 +156,7 @@ def check(rc: int) -> None:
 
 
 def make_desc(root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4, rho_floor=1e-20,
-              p_floor=1e-20, riemann_iters=5, refine=(), ghost=3):
+              p_floor=1e-20, riemann_iters=5, refine=(), ghost=3, dual_energy=False, eta1=1e-3, eta2=0.1):
     import numpy as np
 
     d = MeshDesc()
@@ -164,6 +169,8 @@ def make_desc(root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
     d.gamma, d.cfl = float(gamma), float(cfl)
     d.rho_floor, d.p_floor = float(rho_floor), float(p_floor)
     d.riemann_iters = int(riemann_iters)
+    d.dual_energy = int(dual_energy)
+    d.eta1, d.eta2 = float(eta1), float(eta2)
     ref = np.ascontiguousarray(np.asarray(refine, dtype=np.int32).reshape(-1, 4))
     d.n_refine = ref.shape[0]
     d.refine = ref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if ref.size else None

@@ -93,6 +93,12 @@ amr_status to_desc(const amr_mesh_desc* d, MeshDesc& m) {
   m.rho_floor = d->rho_floor;
   m.p_floor = d->p_floor;
   m.iters = d->riemann_iters;
+  if (d->dual_energy != 0 && d->dual_energy != 1) return fail(AMR_E_INVALID, "dual_energy must be 0 or 1");
+  if (d->dual_energy && !(d->eta1 >= 0.0 && d->eta1 <= 1.0 && d->eta2 >= 0.0 && d->eta2 <= 1.0))
+    return fail(AMR_E_INVALID, "eta1 and eta2 must lie in [0, 1]");
+  m.de = d->dual_energy;
+  m.eta1 = d->dual_energy ? d->eta1 : 0.0;
+  m.eta2 = d->dual_energy ? d->eta2 : 0.0;
   return AMR_OK;
 }
 
@@ -159,6 +165,7 @@ DevPlan dev_plan(const amr_mesh* h) {
   P.np2 = int64_t(p.p2list.size());
   P.ninst = int32_t(p.inst.size());
   P.N = p.N;
+  P.nf = p.nf;
   return P;
 }
 
@@ -409,7 +416,8 @@ amr_status amr_mesh_info(const amr_mesh* h, amr_mesh_info_t* out) {
   out->block_cells = p.N;
   out->padded = p.M;
   out->field_stride = int64_t(p.M) * p.M * p.M;
-  out->block_stride = kFields * out->field_stride;
+  out->block_stride = p.nf * out->field_stride;
+  out->n_fields = p.nf;
   out->field_bytes = p.nleaf * out->block_stride * 8;
   out->workspace_bytes = p.off.total;
   out->n_cf_faces = p.nslots;
@@ -529,6 +537,7 @@ amr_status amr_hydro_step_record(amr_mesh* h, double* U, double* dt, double* S1,
                                  uint64_t* floors, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!dt || !S1 || !S2 || !Uout || !floors) return fail(AMR_E_INVALID, "null argument");
   if (S1 == U || S2 == U || Uout == U || S1 == S2 || S1 == Uout || S2 == Uout)
     return fail(AMR_E_INVALID, "U, S1, S2 and U_out must be distinct buffers");
@@ -550,6 +559,7 @@ amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* 
                                   int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, Uin);
   if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   const Plan& p = h->plan;
   if (!adjoint_iters_ok(p)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
@@ -591,6 +601,7 @@ amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const 
                                            int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, S0);
   if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!S1 || !S2 || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   if (!adjoint_iters_ok(h->plan)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
   const double* const S[3] = {S0, S1, S2};
@@ -707,6 +718,7 @@ amr_status amr_tracer_counters(amr_mesh* h, void* scratch, int64_t capacity, int
 amr_status amr_refresh_ghosts_adjoint(amr_mesh* h, const double* Uref, double* lam, void* stream) {
   amr_status rc = check_ready(h, Uref);
   if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!lam) return fail(AMR_E_INVALID, "null adjoint");
   hipError_t e = launch_refresh_adjoint(dev_plan(h), lam, Uref, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "refresh adjoint");

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   const double g3 = 3.0 * ip.gm1;
   const double fv = (1.0 - c) / (1.0 + c);
   const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
-  double* const B = U + int64_t(s) * kFields * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
+  double* const B = U + int64_t(s) * P.nf * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
   const double rho = B[0], mx = B[M3], my = B[2 * M3], mz = B[3 * M3], E = B[4 * M3];
   const double ir = rcp_pos(rho);
   const double u = mx * ir, v = my * ir, w = mz * ir;
@@ -58,7 +58,17 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   B[2 * M3] = my * fv;
   B[3 * M3] = mz * fv;
   B[4 * M3] = E + ((ie2 - ie) + ke * (fv * fv - 1.0));
-  if (fl) atomicAdd(P.counters, 1ull);
+  unsigned long long nfl = fl ? 1ull : 0ull;
+  if (P.nf == kFieldsDE) {  // the dual-energy field: the same factor and floor rule
+    const double ge = B[5 * M3];
+    double ge2 = ge * fe;
+    if (ge2 < ge && ip.gm1 * ge2 < ip.p_floor) {
+      ge2 = ip.p_floor * ip.inv_gm1;
+      nfl++;
+    }
+    B[5 * M3] = ge2;
+  }
+  if (nfl) atomicAdd(P.counters, nfl);
 }
 
 template <int N>

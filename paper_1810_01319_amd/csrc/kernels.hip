@@ -32,7 +32,7 @@ __device__ __forceinline__ double level_dx(const InstParams& ip, int N, int l) {
 // ---------------------------------------------------------------------------
 
 // Phase 1: same-level copies (incl. outflow clamps) and restriction.
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -51,22 +51,22 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
   const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
   const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
   const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
-  double* dst = U + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  double* dst = U + int64_t(s) * NF * M3 + (int64_t(c) * M + b) * M + a;
   if (e.kind == NBR_COPY) {
     const BlockInfo sb = P.blocks[e.id];
     const int la = px - sb.i * N + G, lb = py - sb.j * N + G, lc = pz - sb.k * N + G;
-    const double* src = U + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) dst[f * M3] = src[f * M3];
+    for (int f = 0; f < NF; f++) dst[f * M3] = src[f * M3];
   } else {
     // mean of the 8 children, summed x fastest then y then z
     const int qx = 2 * px, qy = 2 * py, qz = 2 * pz;
     const int cidx = ((qx / N) & 1) + 2 * ((qy / N) & 1) + 4 * ((qz / N) & 1);
     const int fs = P.fine[8 * int64_t(e.id) + cidx];
     const int la = qx % N + G, lb = qy % N + G, lc = qz % N + G;
-    const double* src = U + int64_t(fs) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    const double* src = U + int64_t(fs) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) {
+    for (int f = 0; f < NF; f++) {
       const double* q = src + f * M3;
       const double v0 = q[0], v1 = q[1], v2 = q[M], v3 = q[M + 1];
       const double v4 = q[M * M], v5 = q[M * M + 1], v6 = q[M * M + M], v7 = q[M * M + M + 1];
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
 // and phase-1 ghost cells are complete.
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -102,10 +102,10 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
   const double ox = (px & 1) ? 0.25 : -0.25;
   const double oy = (py & 1) ? 0.25 : -0.25;
   const double oz = (pz & 1) ? 0.25 : -0.25;
-  const double* src = U + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
-  double* dst = U + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
+  double* dst = U + int64_t(s) * NF * M3 + (int64_t(c) * M + b) * M + a;
 #pragma unroll
-  for (int f = 0; f < kFields; f++) {
+  for (int f = 0; f < NF; f++) {
     const double* q = src + f * M3;
     const double u0 = q[0];
     const double sx = minmod(q[1] - u0, u0 - q[-1]);
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
 // CFL reduction
 // ---------------------------------------------------------------------------
 
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, DevPlan P, int chunks) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, 
   const BlockInfo bi = P.blocks[s];
   const InstParams& ip = P.inst[bi.inst];
   const double dx = level_dx(ip, N, bi.level);
-  const double* B = U + int64_t(s) * kFields * M3;
+  const double* B = U + int64_t(s) * NF * M3;
   const int per = N3 / chunks;
   double best = __builtin_huge_val();
   for (int q = ch * per + threadIdx.x; q < (ch + 1) * per; q += blockDim.x) {
@@ -138,7 +138,9 @@ __global__ void __launch_bounds__(256) cfl_kernel(const double* __restrict__ U, 
     const double rho = B[o];
     const double ir = rcp_pos(rho);
     const double u = B[o + M3] * ir, v = B[o + 2 * M3] * ir, w = B[o + 3 * M3] * ir;
-    double p = ip.gm1 * (B[o + 4 * M3] - (0.5 * rho) * ((u * u + v * v) + w * w));
+    double ge = 0.0;
+    if constexpr (NF == kFieldsDE) ge = B[o + 5 * M3];
+    double p = gas_pressure<NF == kFieldsDE>(ip, rho, u, v, w, B[o + 4 * M3], ge);
     p = p < ip.p_floor ? ip.p_floor : p;
     const double cs = sqrt_pos((ip.gamma * p) * ir);
     const double vm = sel_max(sel_max(fabs(u), fabs(v)), fabs(w));
@@ -184,10 +186,11 @@ __global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a) {
 // 1/rho.  A run of steps keeps each leaf's maximum: correctly rounded
 // division is monotone, so dx / (leaf maximum) is the leaf's minimum of
 // dx / speed bit for bit, and the per-cell division is saved.
+template <bool DE = false>
 __device__ __forceinline__ double cfl_speed(const InstParams& ip, double rho, double ir, double mx, double my,
-                                            double mz, double E) {
+                                            double mz, double E, double ge = 0.0) {
   const double u = mx * ir, v = my * ir, w = mz * ir;
-  double p = ip.gm1 * (E - (0.5 * rho) * ((u * u + v * v) + w * w));
+  double p = gas_pressure<DE>(ip, rho, u, v, w, E, ge);
   p = p < ip.p_floor ? ip.p_floor : p;
   const double cs = sqrt_pos((ip.gamma * p) * ir);
   const double vm = sel_max(sel_max(fabs(u), fabs(v)), fabs(w));
@@ -262,9 +265,10 @@ __device__ __forceinline__ void cfl_commit(unsigned long long* acc, double best)
 // cfl_next (the last sweep of a step in a run of steps): every updated cell
 // that no reflux will change adds its CFL candidate for the next step to the
 // instance's accumulator.
-template <int N, int DIR, bool OOP>
+template <int N, int DIR, bool OOP, int NF>
 __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
                                                 const DevPlan& P, int loA, int nA, int loB, int nB, int cfl_next) {
+  constexpr bool DE = NF == kFieldsDE;  // dual-energy field rho e (field 5)
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int A = DIR == 0 ? 1 : 0;
@@ -287,7 +291,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   const double dxl = level_dx(ip, N, bi.level);
   const double nu = dtv[bi.inst] / dxl;
   double cfl_best = 0.0;  // maximum signal speed (cfl_next)
-  const int64_t boff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
+  const int64_t boff = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
   const double* const pr_ = Uin + boff;
   const double* const pn_ = pr_ + (1 + DIR) * M3;
   const double* const p1_ = pr_ + (1 + T1) * M3;
@@ -298,6 +302,8 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   double* const q1_ = qr_ + (1 + T1) * M3;
   double* const q2_ = qr_ + (1 + T2) * M3;
   double* const qe_ = qr_ + 4 * M3;
+  const double* const pg_ = pr_ + 5 * M3;  // rho e: dereferenced only with DE
+  double* const qg_ = qr_ + 5 * M3;
   const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
   int slot_lo = -1, slot_hi = -1;
   if (faces_act) {
@@ -312,6 +318,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
     for (int k = 0; k < 2 * G; k++) {
       const int64_t o = int64_t(k < G ? k : N + k) * SD;
       qr_[o] = pr_[o]; qn_[o] = pn_[o]; q1_[o] = p1_[o]; q2_[o] = p2_[o]; qe_[o] = pe_[o];
+      if constexpr (DE) qg_[o] = pg_[o];
     }
   }
 
@@ -321,10 +328,12 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   double dl[5][2];   // slopes of cells t-2, t-1
   double fold[5];    // face value at (t-3)+1/2
   double WLp[5];     // left state at (t-3)+1/2 from cell t-3
-  double Fp[5];      // flux at (t-4)+1/2
+  double Fp[NF];     // flux at (t-4)+1/2
+  double ugp = 0.0;  // Godunov velocity at (t-4)+1/2 (DE)
   unsigned nfl = 0;
   // prefetch cell 0
-  double nx0 = pr_[0], nx1 = pn_[0], nx2 = p1_[0], nx3 = p2_[0], nx4 = pe_[0];
+  double nx0 = pr_[0], nx1 = pn_[0], nx2 = p1_[0], nx3 = p2_[0], nx4 = pe_[0], nx5 = 0.0;
+  if constexpr (DE) nx5 = pg_[0];
   // One cell of the walk.  The walk is split into a head (cells 0..5: no
   // update yet; the lower coarse-fine face flux), a body in which every cell
   // issues the same loads and stores (so that waiting for the prefetched cell
@@ -332,20 +341,22 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   // face flux).
   auto cell = [&](const int c, auto phase) __attribute__((always_inline)) {
     constexpr int PH = decltype(phase)::value;
-    double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;
+    double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
     if (PH > 0) {  // the cell updated here, c-3, loaded ahead of the prefetch
       const int64_t o = int64_t(c - 3) * SD;
       h0 = pr_[o]; h1 = pn_[o]; h2 = p1_[o]; h3 = p2_[o]; h4 = pe_[o];
+      if constexpr (DE) h5 = pg_[o];
     }
-    const double U0 = nx0, U1 = nx1, U2 = nx2, U3 = nx3, U4 = nx4;
+    const double U0 = nx0, U1 = nx1, U2 = nx2, U3 = nx3, U4 = nx4, U5 = nx5;
     if (PH < 2) {
       const int64_t o = int64_t(c + 1) * SD;
       nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
+      if constexpr (DE) nx5 = pg_[o];
     }
     // primitives of cell c
     const double ir = rcp_pos(U0);
     const double u = U1 * ir, v = U2 * ir, w = U3 * ir;
-    double p = gm1 * (U4 - (0.5 * U0) * ((u * u + v * v) + w * w));
+    double p = gas_pressure<DE>(ip, U0, u, v, w, U4, U5);
     p = p < pfl ? pfl : p;
     const double cs = sqrt_pos((ip.gamma * p) * ir);
     rw[0] = rw[1]; rw[1] = rw[2]; rw[2] = U0;
@@ -394,17 +405,19 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
       trace(ip, rw[0], uw[1], cw[0], iw[0], pa, nu, WL, WR);
       if (PH > 0 || c >= 5) {
         // flux at (c-3)+1/2 from cell c-3's right edge and cell c-2's left
-        double F[5];
-        riemann_flux(ip, WLp, WR, F);
+        double F[NF], ugn = 0.0;
+        riemann_flux<DE>(ip, WLp, WR, F, &ugn);
         if (PH == 0 && slot_lo >= 0) {  // c = G+2: lower face of the active cells
-          double* fo = P.faces + int64_t(slot_lo) * kFields * N * N + face_off;
+          double* fo = P.faces + int64_t(slot_lo) * NF * N * N + face_off;
           fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
           fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+          if constexpr (DE) fo[5 * N * N] = F[5];
         }
         if (PH == 2 && slot_hi >= 0) {  // c = N+G+2: upper face
-          double* fo = P.faces + int64_t(slot_hi) * kFields * N * N + face_off;
+          double* fo = P.faces + int64_t(slot_hi) * NF * N * N + face_off;
           fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
           fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+          if constexpr (DE) fo[5 * N * N] = F[5];
         }
         if (PH > 0) {
           // conservative update of cell c-3, then the floors
@@ -421,6 +434,18 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
           const double pn = gm1 * (e - ke);
           if (pn < pfl) { e = pfl * ip.inv_gm1 + ke; nfl++; }
           qr_[o] = r0; qn_[o] = m1; q1_[o] = m2; q2_[o] = m3; qe_[o] = e;
+          double ge = 0.0;
+          if constexpr (DE) {
+            // rho e: its flux difference, the work of cell c-3's pressure
+            // (pw[1]) on the Godunov velocities, then the resynchronisation
+            // from E where E - ke > eta2 E and the floor
+            ge = h5 - nu * (F[5] - Fp[5]);
+            ge = ge - nu * (pw[1] * (ugn - ugp));
+            const double ie = e - ke;
+            if (ie > ip.eta2 * e) ge = ie;
+            if (gm1 * ge < pfl) { ge = pfl * ip.inv_gm1; nfl++; }
+            qg_[o] = ge;
+          }
           if (cfl_next) {
             int q[3];
             q[DIR] = c - 3;
@@ -431,13 +456,14 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
               mv[DIR] = m1;
               mv[T1] = m2;
               mv[T2] = m3;
-              const double t = cfl_speed(ip, r0, jr, mv[0], mv[1], mv[2], e);
+              const double t = cfl_speed<DE>(ip, r0, jr, mv[0], mv[1], mv[2], e, ge);
               cfl_best = t > cfl_best ? t : cfl_best;
             }
           }
         }
 #pragma unroll
-        for (int q = 0; q < 5; q++) Fp[q] = F[q];
+        for (int q = 0; q < NF; q++) Fp[q] = F[q];
+        ugp = ugn;
       }
 #pragma unroll
       for (int q = 0; q < 5; q++) WLp[q] = WL[q];
@@ -456,19 +482,19 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   if (cfl_next) cfl_commit(&P.lacc[int64_t(s) * kCflSlots + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCflSlots)], cfl_best);
 }
 
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
                                                     DevPlan P, int loA, int nA, int loB, int nB, int cfl_next) {
-  sweep_walk_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
+  sweep_walk_body<N, DIR, false, NF>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
 }
 
 // Out of place: every cell of the swept pencils is written to Uout (updated
 // or passed through); Uin is not modified.
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__(256) sweep_kernel_oop(const double* __restrict__ Uin, double* __restrict__ Uout,
                                                         const double* __restrict__ dtv, DevPlan P, int loA, int nA,
                                                         int loB, int nB) {
-  sweep_walk_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
+  sweep_walk_body<N, DIR, true, NF>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,10 +515,11 @@ struct StagedShape {
   static constexpr int WG = ((T + 63) / 64) * 64;
 };
 
-template <int N, int DIR, bool OOP>
+template <int N, int DIR, bool OOP, int NF>
 __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
                                                   const DevPlan& P, int loA, int nA, int loB, int nB,
                                                   int cfl_next) {
+  constexpr bool DE = NF == kFieldsDE;  // dual-energy field rho e (field 5)
   using S = StagedShape<N, DIR>;
   constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -506,6 +533,8 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   __shared__ double Ps[5][T];           // primitives
   __shared__ double Xs[5][T];           // slopes, then right states at j-1/2
   __shared__ double Ys[5][T];           // face values at j+1/2, then fluxes
+  __shared__ double Fg[DE ? T : 1];     // DE: rho e flux at j+1/2
+  __shared__ double Ug[DE ? T : 1];     // DE: Godunov velocity at j+1/2
   const int tilesA = (nA + R - 1) / R;
   const int64_t tile = blockIdx.x;
   const int s = int(tile / (int64_t(nB) * tilesA));
@@ -520,25 +549,26 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   const InstParams& ip = P.inst[bi.inst];
   const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
   const int iA = loA + a0 + r;
-  const int64_t coff = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const int64_t coff = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
   const double* const cellp = Uin + coff;
   double* const outp = Uout + coff;
   const double gm1 = ip.gm1, pfl = ip.p_floor, rfl = ip.rho_floor, sixth = ip.sixth;
 
   // A: own cell, primitives
-  double U0 = 0, U1 = 0, U2 = 0, U3 = 0, U4 = 0, q[5] = {0, 0, 0, 0, 0}, cs = 0, ir = 0;
+  double U0 = 0, U1 = 0, U2 = 0, U3 = 0, U4 = 0, U5 = 0, q[5] = {0, 0, 0, 0, 0}, cs = 0, ir = 0;
   if (live) {
     U0 = cellp[0];
     U1 = cellp[(1 + DIR) * M3];
     U2 = cellp[(1 + T1) * M3];
     U3 = cellp[(1 + T2) * M3];
     U4 = cellp[4 * M3];
+    if constexpr (DE) U5 = cellp[5 * M3];
     ir = rcp_pos(U0);
     q[0] = U0;
     q[1] = U1 * ir;
     q[2] = U2 * ir;
     q[3] = U3 * ir;
-    double p = gm1 * (U4 - (0.5 * U0) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]));
+    double p = gas_pressure<DE>(ip, U0, q[1], q[2], q[3], U4, U5);
     q[4] = p < pfl ? pfl : p;
     cs = sqrt_pos((ip.gamma * q[4]) * ir);
 #pragma unroll
@@ -585,19 +615,24 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   __syncthreads();
   // E: Riemann flux at c+1/2
   if (live && c >= 2 && c <= M - 4) {
-    double R5[5], F[5];
+    double R5[5], F[NF], ugn = 0.0;
 #pragma unroll
     for (int v = 0; v < 5; v++) R5[v] = Xs[v][i + NS];
-    riemann_flux(ip, WL, R5, F);
+    riemann_flux<DE>(ip, WL, R5, F, &ugn);
 #pragma unroll
     for (int v = 0; v < 5; v++) Ys[v][i] = F[v];
+    if constexpr (DE) {
+      Fg[i] = F[5];
+      Ug[i] = ugn;
+    }
     const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
     if (faces_act && (c == G - 1 || c == N + G - 1)) {
       const int slot = P.faceslot[6 * int64_t(s) + 2 * DIR + (c == G - 1 ? 0 : 1)];
       if (slot >= 0) {
-        double* fo = P.faces + int64_t(slot) * kFields * N * N + int64_t(iB - G) * N + (iA - G);
+        double* fo = P.faces + int64_t(slot) * NF * N * N + int64_t(iB - G) * N + (iA - G);
         fo[0] = F[0]; fo[(1 + DIR) * N * N] = F[1]; fo[(1 + T1) * N * N] = F[2];
         fo[(1 + T2) * N * N] = F[3]; fo[4 * N * N] = F[4];
+        if constexpr (DE) fo[5 * N * N] = F[5];
       }
     }
   }
@@ -622,6 +657,15 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     outp[(1 + T1) * M3] = m2;
     outp[(1 + T2) * M3] = m3;
     outp[4 * M3] = e;
+    double ge = 0.0;
+    if constexpr (DE) {  // rho e: flux difference, work, resynchronisation, floor (as in the walk)
+      ge = U5 - nu * (Fg[i] - Fg[i - NS]);
+      ge = ge - nu * (q[4] * (Ug[i] - Ug[i - NS]));
+      const double ie = e - ke;
+      if (ie > ip.eta2 * e) ge = ie;
+      if (gm1 * ge < pfl) { ge = pfl * ip.inv_gm1; nfl++; }
+      outp[5 * M3] = ge;
+    }
     if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
     if (cfl_next) {  // the next step's CFL candidate (see the walk)
       int q[3];
@@ -633,7 +677,7 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
         mv[DIR] = m1;
         mv[T1] = m2;
         mv[T2] = m3;
-        cfl_best = cfl_speed(ip, r0, jr, mv[0], mv[1], mv[2], e);
+        cfl_best = cfl_speed<DE>(ip, r0, jr, mv[0], mv[1], mv[2], e, ge);
       }
     }
   } else if (OOP && live) {  // cells the sweep does not update pass through
@@ -642,31 +686,32 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
     outp[(1 + T1) * M3] = U2;
     outp[(1 + T2) * M3] = U3;
     outp[4 * M3] = U4;
+    if constexpr (DE) outp[5 * M3] = U5;
   }
   if (cfl_next) cfl_commit(&P.lacc[int64_t(s) * kCflSlots + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCflSlots)], cfl_best);
 }
 
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__((StagedShape<N, DIR>::WG)) sweep_staged(double* __restrict__ U,
                                                                     const double* __restrict__ dtv, DevPlan P,
                                                                     int loA, int nA, int loB, int nB,
                                                                     int cfl_next) {
-  sweep_staged_body<N, DIR, false>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
+  sweep_staged_body<N, DIR, false, NF>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
 }
 
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__((StagedShape<N, DIR>::WG)) sweep_staged_oop(const double* __restrict__ Uin,
                                                                         double* __restrict__ Uout,
                                                                         const double* __restrict__ dtv, DevPlan P,
                                                                         int loA, int nA, int loB, int nB) {
-  sweep_staged_body<N, DIR, true>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
+  sweep_staged_body<N, DIR, true, NF>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
 }
 
 // ---------------------------------------------------------------------------
 // Reflux
 // ---------------------------------------------------------------------------
 
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__(256) reflux_kernel(double* __restrict__ U, const double* __restrict__ dtv,
                                                      DevPlan P) {
   constexpr int M = N + 2 * G;
@@ -689,11 +734,11 @@ __global__ void __launch_bounds__(256) reflux_kernel(double* __restrict__ U, con
   const int fs = T.slot_f[hA + 2 * hB];
   const int fA = 2 * tA - hA * N, fB = 2 * tB - hB * N;
   const int d = T.side ? N + G - 1 : G;
-  double* cellp = U + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + tA) * SA + int64_t(G + tB) * SB;
+  double* cellp = U + int64_t(T.leaf) * NF * M3 + int64_t(d) * SD + int64_t(G + tA) * SA + int64_t(G + tB) * SB;
 #pragma unroll
-  for (int f = 0; f < kFields; f++) {
-    const double Fc = P.faces[(int64_t(T.slot_c) * kFields + f) * N * N + int64_t(tB) * N + tA];
-    const double* Q = P.faces + (int64_t(fs) * kFields + f) * N * N;
+  for (int f = 0; f < NF; f++) {
+    const double Fc = P.faces[(int64_t(T.slot_c) * NF + f) * N * N + int64_t(tB) * N + tA];
+    const double* Q = P.faces + (int64_t(fs) * NF + f) * N * N;
     const double fb = ((Q[fB * N + fA] + Q[fB * N + fA + 1]) + (Q[(fB + 1) * N + fA] + Q[(fB + 1) * N + fA + 1])) * 0.25;
     const double corr = nu * (Fc - fb);
     const double u = cellp[f * M3];
@@ -713,7 +758,7 @@ __global__ void __launch_bounds__(256) indicator_kernel(const double* __restrict
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int N3 = N * N * N;
   const int s = blockIdx.x;
-  const double* B = U + int64_t(s) * kFields * M3;
+  const double* B = U + int64_t(s) * P.nf * M3;
   double best = 0.0;
   for (int q = threadIdx.x; q < N3; q += blockDim.x) {
     const int x = q % N, y = (q / N) % N, z = q / (N * N);
@@ -743,7 +788,7 @@ __global__ void __launch_bounds__(256) indicator_kernel(const double* __restrict
 // One thread per active cell of a new leaf: copy, prolong from the old
 // parent's refreshed block (the refresh prolongation formula), or restrict
 // the 8 old children.
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__ Uold, double* __restrict__ Unew,
                                                       DevPlan P) {
   constexpr int M = N + 2 * G;
@@ -755,18 +800,18 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
   const int q = int(t - int64_t(s) * N3);
   const int a = q % N, b = (q / N) % N, c = q / (N * N);
   const MigrTask T = P.migr[s];
-  double* dst = Unew + int64_t(s) * kFields * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
+  double* dst = Unew + int64_t(s) * NF * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
   if (T.kind == MIGR_COPY) {
-    const double* src = Uold + int64_t(T.src[0]) * kFields * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
+    const double* src = Uold + int64_t(T.src[0]) * NF * M3 + (int64_t(c + G) * M + (b + G)) * M + (a + G);
 #pragma unroll
-    for (int f = 0; f < kFields; f++) dst[f * M3] = src[f * M3];
+    for (int f = 0; f < NF; f++) dst[f * M3] = src[f * M3];
   } else if (T.kind == MIGR_PROLONG) {
     const int cx = T.co & 1, cy = (T.co >> 1) & 1, cz = (T.co >> 2) & 1;
     const int la = (cx * N + a) / 2 + G, lb = (cy * N + b) / 2 + G, lc = (cz * N + c) / 2 + G;
     const double ox = (a & 1) ? 0.25 : -0.25, oy = (b & 1) ? 0.25 : -0.25, oz = (c & 1) ? 0.25 : -0.25;
-    const double* src = Uold + int64_t(T.src[0]) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    const double* src = Uold + int64_t(T.src[0]) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) {
+    for (int f = 0; f < NF; f++) {
       const double* qq = src + f * M3;
       const double u0 = qq[0];
       const double sx = minmod(qq[1] - u0, u0 - qq[-1]);
@@ -778,9 +823,9 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
     const int fx = 2 * a, fy = 2 * b, fz = 2 * c;
     const int ch = (fx / N) + 2 * (fy / N) + 4 * (fz / N);
     const int la = fx % N + G, lb = fy % N + G, lc = fz % N + G;
-    const double* src = Uold + int64_t(T.src[ch]) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    const double* src = Uold + int64_t(T.src[ch]) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) {
+    for (int f = 0; f < NF; f++) {
       const double* qq = src + f * M3;
       const double v0 = qq[0], v1 = qq[1], v2 = qq[M], v3 = qq[M + 1];
       const double v4 = qq[M * M], v5 = qq[M * M + 1], v6 = qq[M * M + M], v7 = qq[M * M + M + 1];
@@ -791,15 +836,20 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
-template <int N>
-hipError_t refresh_n(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
+template <int N, int NF>
+hipError_t refresh_nf(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
   if (P.nleaf > 0)
-    hipLaunchKernelGGL(refresh_phase1<N>, dim3(grid_for(P.nleaf * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+    hipLaunchKernelGGL((refresh_phase1<N, NF>), dim3(grid_for(P.nleaf * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
   if (P.np2 > 0)
-    hipLaunchKernelGGL(refresh_phase2<N>, dim3(grid_for(P.np2 * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+    hipLaunchKernelGGL((refresh_phase2<N, NF>), dim3(grid_for(P.np2 * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t refresh_n(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
+  return P.nf == kFieldsDE ? refresh_nf<N, kFieldsDE>(P, U, L, st) : refresh_nf<N, kFields>(P, U, L, st);
 }
 
 template <int N>
@@ -807,15 +857,19 @@ hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg&
   constexpr int N3 = N * N * N;
   int chunks = N3 / (8 * 256);
   if (chunks < 1) chunks = 1;
-  if (P.nleaf > 0)
-    hipLaunchKernelGGL(cfl_kernel<N>, dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
+  if (P.nleaf > 0) {
+    if (P.nf == kFieldsDE)
+      hipLaunchKernelGGL((cfl_kernel<N, kFieldsDE>), dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
+    else
+      hipLaunchKernelGGL((cfl_kernel<N, kFields>), dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
+  }
   hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt, a);
   return hipGetLastError();
 }
 
-template <int N, int DIR>
-hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const double* dt, const int swept[3],
-                    const LaunchCfg& L, hipStream_t st, int cfl_next) {
+template <int N, int DIR, int NF>
+hipError_t sweep_ndf(const DevPlan& P, const double* Uin, double* Uout, const double* dt, const int swept[3],
+                     const LaunchCfg& L, hipStream_t st, int cfl_next) {
   constexpr int M = N + 2 * G;
   constexpr int A = DIR == 0 ? 1 : 0;
   constexpr int B = DIR == 2 ? 1 : 2;
@@ -827,18 +881,25 @@ hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const dou
     using S = StagedShape<N, DIR>;
     const dim3 g(static_cast<unsigned>(P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R))), b(S::WG);
     if (oop)
-      hipLaunchKernelGGL((sweep_staged_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
+      hipLaunchKernelGGL((sweep_staged_oop<N, DIR, NF>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
-      hipLaunchKernelGGL((sweep_staged<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
+      hipLaunchKernelGGL((sweep_staged<N, DIR, NF>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
   } else {
     const int64_t n = P.nleaf * ((int64_t(nA) * nB + 63) / 64) * 64;  // whole waves per leaf
     const dim3 g(grid_for(n, L.sweep_block)), b(L.sweep_block);
     if (oop)
-      hipLaunchKernelGGL((sweep_kernel_oop<N, DIR>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
+      hipLaunchKernelGGL((sweep_kernel_oop<N, DIR, NF>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
-      hipLaunchKernelGGL((sweep_kernel<N, DIR>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
+      hipLaunchKernelGGL((sweep_kernel<N, DIR, NF>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
   }
   return hipGetLastError();
+}
+
+template <int N, int DIR>
+hipError_t sweep_nd(const DevPlan& P, const double* Uin, double* Uout, const double* dt, const int swept[3],
+                    const LaunchCfg& L, hipStream_t st, int cfl_next) {
+  if (P.nf == kFieldsDE) return sweep_ndf<N, DIR, kFieldsDE>(P, Uin, Uout, dt, swept, L, st, cfl_next);
+  return sweep_ndf<N, DIR, kFields>(P, Uin, Uout, dt, swept, L, st, cfl_next);
 }
 
 template <int N>
@@ -852,7 +913,7 @@ hipError_t sweep_n(const DevPlan& P, const double* Uin, double* Uout, const doub
 // The next step's CFL candidates of the cells the reflux corrected (one
 // thread per cell of each task's face layer; cells on two corrected faces
 // are counted twice, which a minimum ignores).
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__(256) reflux_cfl_kernel(const double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -869,35 +930,47 @@ __global__ void __launch_bounds__(256) reflux_cfl_kernel(const double* __restric
   const BlockInfo bi = P.blocks[T.leaf];
   const InstParams ip = P.inst[bi.inst];
   const int d = T.side ? N + G - 1 : G;
-  const double* B0 = U + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + r % N) * SA +
+  const double* B0 = U + int64_t(T.leaf) * NF * M3 + int64_t(d) * SD + int64_t(G + r % N) * SA +
                      int64_t(G + r / N) * SB;
   const double rho = B0[0];
-  const double c = cfl_speed(ip, rho, rcp_pos(rho), B0[M3], B0[2 * M3], B0[3 * M3], B0[4 * M3]);
+  double ge = 0.0;
+  if constexpr (NF == kFieldsDE) ge = B0[5 * M3];
+  const double c = cfl_speed<NF == kFieldsDE>(ip, rho, rcp_pos(rho), B0[M3], B0[2 * M3], B0[3 * M3], B0[4 * M3], ge);
   cfl_commit(&P.lacc[int64_t(T.leaf) * kCflSlots + ((t >> 6) % kCflSlots)], c);
 }
 
-template <int N>
-hipError_t reflux_cfl_n(const DevPlan& P, const double* U, hipStream_t st) {
+template <int N, int NF>
+hipError_t reflux_cfl_nf(const DevPlan& P, const double* U, hipStream_t st) {
   for (int d = 0; d < 3; d++) {
     const int64_t n = P.nreflux[d] * N * N;
     if (n == 0) continue;
     const dim3 g(grid_for(n, 256)), b(256);
-    if (d == 0) hipLaunchKernelGGL((reflux_cfl_kernel<N, 0>), g, b, 0, st, U, P);
-    else if (d == 1) hipLaunchKernelGGL((reflux_cfl_kernel<N, 1>), g, b, 0, st, U, P);
-    else hipLaunchKernelGGL((reflux_cfl_kernel<N, 2>), g, b, 0, st, U, P);
+    if (d == 0) hipLaunchKernelGGL((reflux_cfl_kernel<N, 0, NF>), g, b, 0, st, U, P);
+    else if (d == 1) hipLaunchKernelGGL((reflux_cfl_kernel<N, 1, NF>), g, b, 0, st, U, P);
+    else hipLaunchKernelGGL((reflux_cfl_kernel<N, 2, NF>), g, b, 0, st, U, P);
   }
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t reflux_n(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L, hipStream_t st) {
+hipError_t reflux_cfl_n(const DevPlan& P, const double* U, hipStream_t st) {
+  return P.nf == kFieldsDE ? reflux_cfl_nf<N, kFieldsDE>(P, U, st) : reflux_cfl_nf<N, kFields>(P, U, st);
+}
+
+template <int N, int NF>
+hipError_t reflux_nf(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L, hipStream_t st) {
   const int64_t n = P.nreflux[dir] * N * N;
   if (n == 0) return hipSuccess;
   const dim3 g(grid_for(n, L.reflux_block)), b(L.reflux_block);
-  if (dir == 0) hipLaunchKernelGGL((reflux_kernel<N, 0>), g, b, 0, st, U, dt, P);
-  else if (dir == 1) hipLaunchKernelGGL((reflux_kernel<N, 1>), g, b, 0, st, U, dt, P);
-  else hipLaunchKernelGGL((reflux_kernel<N, 2>), g, b, 0, st, U, dt, P);
+  if (dir == 0) hipLaunchKernelGGL((reflux_kernel<N, 0, NF>), g, b, 0, st, U, dt, P);
+  else if (dir == 1) hipLaunchKernelGGL((reflux_kernel<N, 1, NF>), g, b, 0, st, U, dt, P);
+  else hipLaunchKernelGGL((reflux_kernel<N, 2, NF>), g, b, 0, st, U, dt, P);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t reflux_n(const DevPlan& P, double* U, const double* dt, int dir, const LaunchCfg& L, hipStream_t st) {
+  return P.nf == kFieldsDE ? reflux_nf<N, kFieldsDE>(P, U, dt, dir, L, st) : reflux_nf<N, kFields>(P, U, dt, dir, L, st);
 }
 
 }  // namespace
@@ -1008,10 +1081,20 @@ hipError_t launch_migrate(const DevPlan& P, const double* Uold, double* Unew, hi
   if (P.nleaf == 0) return hipSuccess;
   const int64_t n = P.nleaf * int64_t(P.N) * P.N * P.N;
   const dim3 g(grid_for(n, 256)), b(256);
+  const bool de = P.nf == kFieldsDE;
   switch (P.N) {
-    case 8: hipLaunchKernelGGL(migrate_kernel<8>, g, b, 0, st, Uold, Unew, P); break;
-    case 16: hipLaunchKernelGGL(migrate_kernel<16>, g, b, 0, st, Uold, Unew, P); break;
-    case 32: hipLaunchKernelGGL(migrate_kernel<32>, g, b, 0, st, Uold, Unew, P); break;
+    case 8:
+      if (de) hipLaunchKernelGGL((migrate_kernel<8, kFieldsDE>), g, b, 0, st, Uold, Unew, P);
+      else hipLaunchKernelGGL((migrate_kernel<8, kFields>), g, b, 0, st, Uold, Unew, P);
+      break;
+    case 16:
+      if (de) hipLaunchKernelGGL((migrate_kernel<16, kFieldsDE>), g, b, 0, st, Uold, Unew, P);
+      else hipLaunchKernelGGL((migrate_kernel<16, kFields>), g, b, 0, st, Uold, Unew, P);
+      break;
+    case 32:
+      if (de) hipLaunchKernelGGL((migrate_kernel<32, kFieldsDE>), g, b, 0, st, Uold, Unew, P);
+      else hipLaunchKernelGGL((migrate_kernel<32, kFields>), g, b, 0, st, Uold, Unew, P);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -28,6 +28,7 @@ struct DevPlan {
   double* faces;
   int64_t nleaf, np2, nreflux[3];
   int32_t ninst, N;
+  int32_t nf;  // fields per cell: kFields, or kFieldsDE with the dual-energy field
 };
 
 struct LaunchCfg {

@@ -10,7 +10,8 @@
 namespace amr {
 
 constexpr int kGhost = 3;
-constexpr int kFields = 5;
+constexpr int kFields = 5;    // rho, m_x, m_y, m_z, E
+constexpr int kFieldsDE = 6;  // with the dual-energy field rho e
 // slots per leaf of the next-step signal-speed maxima of a run of steps (spread
 // so that a leaf's waves do not all update one word)
 constexpr int kCflSlots = 16;
@@ -21,10 +22,11 @@ struct InstParams {
   double gamma, gm1, inv_gm1, g_gm1, g1;
   double rho_floor, p_floor, cfl;
   double sixth, two3;
+  double eta1, eta2;  // dual-energy thresholds (pressure selection, resynchronisation)
   int32_t root[3];
   int32_t bc[3];
   int32_t iters;
-  int32_t pad0;
+  int32_t de;  // the plan carries the dual-energy field
   int64_t first_leaf;  // first block of this instance in the plan
   int64_t n_leaf;
 };

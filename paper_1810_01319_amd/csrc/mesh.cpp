@@ -31,6 +31,9 @@ InstParams make_inst_params(const MeshDesc& d) {
     p.bc[a] = d.bc[a];
   }
   p.iters = d.iters;
+  p.de = d.de;
+  p.eta1 = d.eta1;
+  p.eta2 = d.eta2;
   return p;
 }
 
@@ -192,6 +195,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   if (meshes.empty()) return "no meshes";
   N = meshes[0]->desc().N;
   M = N + 2 * kGhost;
+  nf = meshes[0]->desc().de ? kFieldsDE : kFields;
   inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); faceslot.clear(); keys.clear();
   if (!migr.empty() && meshes.size() != 1) return "migration tables belong to single-mesh plans";
   for (auto& r : reflux) r.clear();
@@ -200,6 +204,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   for (int m = 0; m < int(meshes.size()); m++) {
     const Octree& T = *meshes[m];
     if (T.desc().N != N) return "all meshes of a plan need the same block size";
+    if ((T.desc().de ? kFieldsDE : kFields) != nf) return "all meshes of a plan need the same fields (dual energy on or off)";
     InstParams ip = make_inst_params(T.desc());
     ip.first_leaf = int64_t(blocks.size());
     const std::vector<Key> lv = T.leaves();
@@ -334,7 +339,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   off.migr = o; o = align256(o + int64_t(migr.size() * sizeof(MigrTask)));
   off.reloc = o; o = align256(o + int64_t(reloc.size() * sizeof(Reloc)));
   off.reloc_child = o; o = align256(o + int64_t(reloc_child.size() * sizeof(int32_t)));
-  off.faces = o; o = align256(o + nslots * int64_t(kFields) * N * N * 8);
+  off.faces = o; o = align256(o + nslots * int64_t(nf) * N * N * 8);
   off.total = o;
   staging.assign(size_t(off.faces), 0);
   auto put = [&](int64_t at, const void* src, size_t bytes) {

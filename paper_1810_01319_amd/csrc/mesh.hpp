@@ -21,6 +21,8 @@ struct MeshDesc {
   int32_t bc[3];
   double gamma, cfl, rho_floor, p_floor;
   int32_t iters;
+  int32_t de;  // dual-energy field
+  double eta1, eta2;
 };
 
 struct Key {
@@ -63,6 +65,7 @@ class Octree {
 // Flattened tables of one or more meshes.
 struct Plan {
   int N = 0, M = 0;
+  int nf = kFields;  // fields per cell: kFields, or kFieldsDE with the dual-energy field
   int64_t nleaf = 0;
   std::vector<InstParams> inst;
   std::vector<BlockInfo> blocks;

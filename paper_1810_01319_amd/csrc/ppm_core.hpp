@@ -148,12 +148,29 @@ AMR_HD inline void trace(const InstParams& ip, double rho, double u, double c, d
   }
 }
 
+// Pressure before the floor from the total energy E and, with the
+// dual-energy field (DE), its internal energy density ge: (gamma-1)(E - ke)
+// where E - ke > eta1 E, else (gamma-1) ge; ke = (0.5 rho)((u u + v v) + w w).
+template <bool DE>
+AMR_HD inline double gas_pressure(const InstParams& ip, double rho, double u, double v, double w, double E,
+                                  double ge) {
+  const double ie = E - (0.5 * rho) * ((u * u + v * v) + w * w);
+  if constexpr (DE) {
+    if (!(ie > ip.eta1 * E)) return ip.gm1 * ge;
+  }
+  return ip.gm1 * ie;
+}
+
 // Two-shock Riemann solver (a fixed number of Newton steps on p*, ending
 // early only at an exact fixed point, which gives the same bits), sampled at
 // x/t = 0, linear fan between head and tail; returns the flux.  Uses the reciprocal
 // shock mass fluxes 1/W_K and reciprocal impedances
 // 1/Z_K = (1 + (C_K/W_K)^2) / (2 W_K): p* <- p* - (u*_R - u*_L)/(1/Z_L + 1/Z_R).
-AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const double* R, double* F) {
+// DE (dual-energy field): also F[5], the internal-energy flux of the Godunov
+// state u_g p_g / (gamma - 1), and *ug = u_g.
+template <bool DE = false>
+AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const double* R, double* F,
+                                double* ug_out = nullptr) {
   const double rL = L[0], uL = L[1], pL = L[4];
   const double rR = R[0], uR = R[1], pR = R[4];
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
@@ -217,6 +234,10 @@ AMR_HD inline void riemann_flux(const InstParams& ip, const double* L, const dou
   F[2] = mf * vg;
   F[3] = mf * wg;
   F[4] = ug * (pg * ip.g_gm1 + (0.5 * rg) * ((ug * ug + vg * vg) + wg * wg));
+  if constexpr (DE) {
+    F[5] = ug * (pg * ip.inv_gm1);
+    *ug_out = ug;
+  }
 }
 
 

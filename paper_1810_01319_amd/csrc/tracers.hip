@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(B) tracer_drift(const double* __restrict__ U, 
       w[a][0] = 1.0 - f;
       w[a][1] = f;
     }
-    const double* Bk = U + s * kFields * M3;
+    const double* Bk = U + s * P.nf * M3;
     double c[3][2][2][2];
 #pragma unroll
     for (int dz = 0; dz < 2; dz++)

@@ -12,7 +12,6 @@ from . import _lib
 from ._lib import check, lib
 
 GHOST = 3
-NFIELD = 5
 
 
 def _stream():
@@ -37,10 +36,10 @@ class Mesh:
 
     def __init__(self, root, block_cells, max_level=0, bc="periodic", gamma=1.4, cfl=0.4,
                  rho_floor=1e-20, p_floor=1e-20, riemann_iters=5, refine=(), leaves=None,
-                 device="cuda", _handle=None):
+                 dual_energy=False, eta1=1e-3, eta2=0.1, device="cuda", _handle=None):
         self.params = dict(root=tuple(root), block_cells=block_cells, max_level=max_level, bc=bc,
                            gamma=gamma, cfl=cfl, rho_floor=rho_floor, p_floor=p_floor,
-                           riemann_iters=riemann_iters)
+                           riemann_iters=riemann_iters, dual_energy=dual_energy, eta1=eta1, eta2=eta2)
         L = lib()
         h = ctypes.c_void_p()
         batch = isinstance(root, (list, tuple)) and len(root) > 0 and isinstance(root[0], dict)
@@ -71,6 +70,7 @@ class Mesh:
         self.nleaf = int(info.n_leaves)
         self.N = int(info.block_cells)
         self.M = int(info.padded)
+        self.nf = int(info.n_fields)  # 5, or 6 with the dual-energy field rho e
         keys = np.zeros((self.nleaf, 4), dtype=np.int32)
         check(L.amr_mesh_blocks(h, keys.ctypes.data_as(ctypes.c_void_p), self.nleaf))
         self.keys = keys
@@ -93,22 +93,22 @@ class Mesh:
 
     # storage ----------------------------------------------------------
     def alloc_state(self) -> torch.Tensor:
-        return torch.zeros((self.nleaf, NFIELD, self.M, self.M, self.M), dtype=torch.float64,
+        return torch.zeros((self.nleaf, self.nf, self.M, self.M, self.M), dtype=torch.float64,
                            device=self.device)
 
     def state_from_active(self, act: np.ndarray) -> torch.Tensor:
-        U = torch.zeros((self.nleaf, NFIELD, self.M, self.M, self.M), dtype=torch.float64)
+        U = torch.zeros((self.nleaf, self.nf, self.M, self.M, self.M), dtype=torch.float64)
         g, N = GHOST, self.N
         U[:, :, g:g + N, g:g + N, g:g + N] = torch.from_numpy(np.ascontiguousarray(act))
         return U.to(self.device)
 
     def state_from_blocks(self, fn, chunk: int = 512, out: torch.Tensor = None) -> torch.Tensor:
         """Device state filled chunk by chunk from fn(keys) -> active cells
-        [n, 5, N, N, N] (host numpy), for states too large to stage at once;
+        [n, nf, N, N, N] (host numpy), for states too large to stage at once;
         placed at the start of the flat buffer `out` if given."""
-        shape = (self.nleaf, NFIELD, self.M, self.M, self.M)
+        shape = (self.nleaf, self.nf, self.M, self.M, self.M)
         if out is not None:
-            U = out[:self.nleaf * NFIELD * self.M ** 3].view(shape)
+            U = out[:self.nleaf * self.nf * self.M ** 3].view(shape)
         else:
             U = torch.empty(shape, dtype=torch.float64, device=self.device)
         g, N = GHOST, self.N
@@ -270,9 +270,9 @@ class Mesh:
         # ghosts are scratch that the next refresh fills; migration writes
         # every active cell.  Cached free blocks are released first so that
         # a state near the capacity limit finds contiguous memory.
-        shape = (new.nleaf, NFIELD, new.M, new.M, new.M)
+        shape = (new.nleaf, new.nf, new.M, new.M, new.M)
         if out is not None:
-            n = new.nleaf * NFIELD * new.M ** 3
+            n = new.nleaf * new.nf * new.M ** 3
             if out.dtype != torch.float64 or out.numel() < n or out.device != self.device:
                 raise ValueError("out buffer too small or of the wrong type")
             if out.data_ptr() == U.data_ptr():

@@ -95,6 +95,12 @@ def test_info_sizes():
     assert info.field_bytes == 624 * 5 * 38 ** 3 * 8
     assert info.workspace_bytes % 256 == 0
     assert info.n_cf_faces > 0
+    assert info.n_fields == 5
+    rc, de, _ = host_mesh(**I.with_(spec, dual_energy=True).kwargs())
+    assert rc == 0 and de.n_fields == 6
+    assert de.block_stride == 6 * 38 ** 3
+    assert de.field_bytes == 624 * 6 * 38 ** 3 * 8
+    assert de.workspace_bytes > info.workspace_bytes  # six face fluxes per coarse-fine face cell
 
 
 @pytest.mark.parametrize("bad,code", [
@@ -106,6 +112,9 @@ def test_info_sizes():
     (dict(p_floor=0.0), -1),
     (dict(bc="outflow", refine=[(0, 0, 0, 0)], max_level=1), -1),
     (dict(refine=[(1, 0, 0, 0)], max_level=1), -1),
+    (dict(dual_energy=2), -1),
+    (dict(dual_energy=True, eta1=-0.1), -1),
+    (dict(dual_energy=True, eta2=1.5), -1),
 ])
 def test_invalid_descriptors_are_rejected(bad, code):
     kw = dict(root=(2, 2, 2), block_cells=8)
