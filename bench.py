@@ -350,6 +350,65 @@ def comoving_compare(steps: int = 20):
             "phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items() if v[1] > 0}}
 
 
+def dual_energy_compare(steps: int = 50):
+    """The dual-energy variant: (1) the Sedov workload with the sixth field
+    rho e (thresholds 1e-3, 0.1), fused runs of steps as in the main line,
+    against the same run without it; (2) accuracy on a cold stream: a
+    density wave on a Mach 1e5 flow at uniform pressure (E - ke keeps about
+    six of the thermal energy's sixteen digits), 20 steps, maximum relative
+    deviation of the pressure from the exact uniform value, plain (from E -
+    ke) against dual energy (from rho e)."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    out = {}
+    spec = I.sedov_spec(root=8, block_cells=32, levels=2)
+    for name, sp in (("plain", spec), ("dual_energy", I.with_(spec, dual_energy=True))):
+        m = Mesh(**sp.kwargs())
+        act = I.sedov_state(sp, m.keys)
+        U = m.state_from_active(I.with_internal_energy(act) if sp.dual_energy else act)
+        cells = m.nleaf * sp.block_cells ** 3
+        dt = torch.zeros(steps * m.n_instances, dtype=torch.float64, device=m.device)
+        m.steps(U, dt, 2, 0)
+        torch.cuda.synchronize()
+        m.profile(True)
+        t0 = time.perf_counter()
+        m.steps(U, dt, steps, 2)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = m.profile_read()
+        m.profile(False)
+        out[name] = {"ms_per_step": wall * 1e3 / steps, "cell_updates_per_s": cells * steps / wall,
+                     "phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items() if v[1] > 0}}
+        del U, m
+        torch.cuda.empty_cache()
+    out["workload"] = "sedov-static-amr (624 leaves x 32^3), gamma 5/3, eta1 1e-3, eta2 0.1"
+    out["steps"] = steps
+    out["dual_over_plain_time"] = out["dual_energy"]["ms_per_step"] / out["plain"]["ms_per_step"]
+    # cold stream accuracy
+    cs = I.MeshSpec(root=(4, 4, 1), block_cells=32, gamma=5.0 / 3.0)
+    acc = {}
+    for name, sp in (("plain", cs), ("dual_energy", I.with_(cs, dual_energy=True))):
+        m = Mesh(**sp.kwargs())
+        act = I.cold_stream_state(sp, m.keys, mach=1e5)
+        U = m.state_from_active(act if sp.dual_energy else act[:, :5])
+        dt = torch.zeros(1, dtype=torch.float64, device=m.device)
+        for k in range(20):
+            m.step(U, dt, k)
+        a = m.active(U)
+        rho, mom, E = a[:, 0], a[:, 1:4], a[:, 4]
+        ke = 0.5 * (mom ** 2).sum(axis=1) / rho
+        p = (sp.gamma - 1.0) * (a[:, 5] if sp.dual_energy else E - ke)
+        acc[name] = float(np.max(np.abs(p - 1.0)))
+        del U, m
+    out["cold_stream"] = {"workload": "density wave on a uniform Mach 1e5 stream, 16 leaves x 32^3, 20 steps",
+                          "max_rel_pressure_error": acc}
+    return out
+
+
 def step_bytes_per_block(N: int) -> int:
     """Algorithmic HBM bytes of one step of one block in a run of steps:
     refresh and three sweeps (the CFL candidates are taken from the values
@@ -492,6 +551,8 @@ def main():
     ap.add_argument("--tracer-steps", type=int, default=20, help="steps of the tracer measurement (0: skip)")
     ap.add_argument("--comoving-steps", type=int, default=20,
                     help="steps of the comoving measurement (0: skip)")
+    ap.add_argument("--dual-steps", type=int, default=50,
+                    help="steps of the dual-energy measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -559,7 +620,7 @@ def main():
             pencils += (pen["first"], pen["second"], pen["third"])[order.index(a)]
         ms, n = prof["sweep_" + axes[a]]
         flops_launch = mesh.nleaf * fpp * pencils / K
-        kname = ("sweep_staged" if launch["sweep_mode"][a] == 1 else "sweep_kernel") + f"<{N},{a}>"
+        kname = ("sweep_staged" if launch["sweep_mode"][a] == 1 else "sweep_kernel") + f"<{N},{a},{mesh.nf}>"
         per_axis[axes[a]] = {"kernel": kname, "avg_launch_ms": ms / n, "flops_per_launch": flops_launch,
                              "TFLOP/s": flops_launch / (ms / n * 1e-3) / 1e12}
     dom = max(per_axis, key=lambda a: per_axis[a]["avg_launch_ms"])
@@ -610,6 +671,8 @@ def main():
         out["tracers"] = tracer_compare(args.tracer_steps)
     if args.comoving_steps > 0:
         out["comoving"] = comoving_compare(args.comoving_steps)
+    if args.dual_steps > 0:
+        out["dual_energy"] = dual_energy_compare(args.dual_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -91,6 +91,18 @@ def conserved(gamma: float, rho, u, v, w, p) -> np.ndarray:
     return out
 
 
+def cold_stream_state(spec: MeshSpec, keys, mach: float, amp: float = 0.2, p0: float = 1.0) -> np.ndarray:
+    """A density wave riding a uniform stream along x at Mach `mach` (sound
+    speed of the mean density) at uniform pressure p0; six fields, rho e =
+    p0 / (gamma - 1) (not E - ke, which has lost the thermal digits)."""
+    x, y, z = cell_centres(spec, keys)
+    rho = 1.0 + amp * np.sin(2.0 * np.pi * x) * np.cos(2.0 * np.pi * y)
+    u0 = mach * np.sqrt(spec.gamma * p0)
+    act = conserved(spec.gamma, rho, u0, 0.0, 0.0, np.full(rho.shape, p0))
+    ge = np.full(rho.shape, p0 / (spec.gamma - 1.0))
+    return np.concatenate([act, ge[:, None]], axis=1)
+
+
 def with_internal_energy(act: np.ndarray) -> np.ndarray:
     """Append the dual-energy field rho e = E - |m|^2 / (2 rho) to a state of
     five conserved fields (an initial internal energy consistent with E)."""
