@@ -109,6 +109,26 @@ void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
 void orc_pencil_flux(const double* gas /* gamma,rho_floor,p_floor */, int iters,
                      double nu, int n, const double* U /* 5 x n */, double* flux_out);
 
+/* mg0 Poisson solver (mg_oracle.c): the 7-point Laplacian of phi equals f
+ * on a uniform periodic nx x ny x nz grid of spacing h (arrays x fastest).
+ * f is made mean-free; ncycles V(nu1, nu2) cycles of red-black Gauss-Seidel
+ * with residual restriction (8-child mean) and trilinear prolongation,
+ * starting from phi; phi is returned with zero mean; resid (ncycles + 1
+ * values, may be NULL) receives the residual L2 norm before and after each
+ * cycle.  Returns the number of levels, or -1 for odd or too small sizes. */
+#define ORC_MG_DEBUG_INJECT 1        /* piecewise-constant prolongation */
+#define ORC_MG_DEBUG_RESTRICT_SUM 2  /* restriction sums instead of averaging */
+#define ORC_MG_DEBUG_SMOOTH_SIGN 4   /* smoother adds h^2 f */
+void orc_mg_set_debug(int flags);
+int orc_mg_levels(int nx, int ny, int nz);
+/* Building blocks: fine (2nxc x 2nyc x 2nzc) += prolongation of coarse;
+ * coarse_f = restriction of the residual f - lap(phi) of a grid. */
+void orc_mg_prolong_add(int nxc, int nyc, int nzc, const double* coarse, double* fine);
+void orc_mg_restrict_residual(int nx, int ny, int nz, double h, const double* f, const double* phi,
+                              double* coarse_f);
+int orc_mg_solve(int nx, int ny, int nz, double h, const double* f, double* phi, int ncycles, int nu1, int nu2,
+                 double* resid);
+
 /* Remesh (density-slope criterion).  Evaluates the per-leaf indicator on
  * refreshed data, applies refine/coarsen with 2:1 balance and the capacity
  * policy, and returns a new mesh holding the migrated state.  Counters:

@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amr_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "mg_oracle.c")]
 _SO = os.path.join(_HERE, "libamr_oracle.so")
 GHOST = 3
 NFIELD = 5
@@ -34,7 +35,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/libamr_oracle.so``."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -64,7 +65,7 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = ctypes.CDLL(_SO)
         P, D, I64, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
@@ -106,6 +107,13 @@ def lib() -> ctypes.CDLL:
         L.orc_tracers_drift.restype = I64
         L.orc_step_tracers.argtypes = [P, I64, I64, P, P, P, P]
         L.orc_step_tracers.restype = D
+        L.orc_mg_set_debug.argtypes = [I32]
+        L.orc_mg_prolong_add.argtypes = [I32, I32, I32, P, P]
+        L.orc_mg_restrict_residual.argtypes = [I32, I32, I32, D, P, P, P]
+        L.orc_mg_levels.argtypes = [I32, I32, I32]
+        L.orc_mg_levels.restype = I32
+        L.orc_mg_solve.argtypes = [I32, I32, I32, D, P, P, I32, I32, I32, P]
+        L.orc_mg_solve.restype = I32
         _lib = L
     return _lib
 
@@ -295,4 +303,52 @@ def pencil_flux(U, nu, gamma=1.4, rho_floor=1e-20, p_floor=1e-20, iters=5):
     out = np.zeros((5, n - 5))
     gas = np.array([gamma, rho_floor, p_floor])
     lib().orc_pencil_flux(_ptr(gas), int(iters), float(nu), int(n), _ptr(U), _ptr(out))
+    return out
+
+
+def mg_levels(shape) -> int:
+    """Number of mg0 levels of a grid of shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    return int(lib().orc_mg_levels(nx, ny, nz))
+
+
+def mg_solve(f, h, ncycles, nu1=2, nu2=2, phi0=None):
+    """mg0 solve of lap(phi) = f on a periodic grid f[nz, ny, nx] of spacing
+    h: returns (phi, residual norms before and after each cycle)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nz, ny, nx = f.shape
+    phi = np.zeros_like(f) if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64).copy()
+    res = np.zeros(ncycles + 1)
+    nl = lib().orc_mg_solve(nx, ny, nz, float(h), _ptr(f), _ptr(phi), int(ncycles), int(nu1), int(nu2), _ptr(res))
+    if nl < 0:
+        raise ValueError("mg0 needs even sizes >= 2 and h > 0")
+    return phi, res
+
+
+MG_DEBUG_INJECT = 1
+MG_DEBUG_RESTRICT_SUM = 2
+MG_DEBUG_SMOOTH_SIGN = 4
+
+
+def mg_set_debug(flags: int) -> None:
+    """Plant a known mistake in the mg0 oracle (tests of the pins' power only)."""
+    lib().orc_mg_set_debug(int(flags))
+
+
+def mg_prolong(coarse):
+    """The mg0 prolongation of a coarse grid [nz, ny, nx] onto the doubled grid."""
+    c = np.ascontiguousarray(coarse, dtype=np.float64)
+    nz, ny, nx = c.shape
+    fine = np.zeros((2 * nz, 2 * ny, 2 * nx))
+    lib().orc_mg_prolong_add(nx, ny, nz, _ptr(c), _ptr(fine))
+    return fine
+
+
+def mg_restrict_residual(f, phi, h):
+    """The mg0 restriction of the residual f - lap(phi) (grid [nz, ny, nx], spacing h)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    nz, ny, nx = f.shape
+    out = np.zeros((nz // 2, ny // 2, nx // 2))
+    lib().orc_mg_restrict_residual(nx, ny, nz, float(h), _ptr(f), _ptr(phi), _ptr(out))
     return out
