@@ -409,6 +409,54 @@ def dual_energy_compare(steps: int = 50):
     return out
 
 
+def mg0_compare(cycles: int = 10):
+    """The mg0 Poisson solver on a uniform periodic mesh of 16^3 root octrees x
+    32^3 cells (512^3 cells; the paper's uniform-mesh self-gravity shape on
+    one GPU): V(2,2) cycles on a seeded standard-normal right-hand side, time
+    per cycle and residual reduction per cycle.  Algorithmic HBM bytes per
+    cycle and finest cell: 4 red-black sweeps x 2 colour passes x 12 B (read
+    the other colour's phi and the own f, write the own phi, half the cells
+    each), residual restriction 18 B, prolongation 17 B, all levels
+    (x 8/7): 150 B."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    spec = I.MeshSpec(root=(16, 16, 16), block_cells=32)
+    m = Mesh(**spec.kwargs())
+    shape = (m.nleaf, m.N, m.N, m.N)
+    g = torch.Generator(device=m.device)
+    g.manual_seed(1234)
+    f = torch.randn(shape, generator=g, dtype=torch.float64, device=m.device)
+    phi = torch.zeros_like(f)
+    work = m.poisson_workspace()
+    m.poisson_solve(f, phi, 1, work=work, resid=False)  # warm-up
+    phi.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.poisson_solve(f, phi, cycles, work=work, resid=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phi.zero_()
+    res = m.poisson_solve(f, phi, cycles, work=work).cpu().tolist()
+    n = m.nleaf * m.N ** 3
+    fac = [res[i + 1] / res[i] for i in range(1, len(res) - 1)]
+    ms = wall * 1e3 / cycles
+    bytes_pc = 150
+    out = {"workload": "uniform periodic mesh, 16^3 root octrees x 32^3 cells (512^3), V(2,2) cycles, "
+                       "seeded standard-normal right-hand side",
+           "cells": n, "cycles": cycles, "ms_per_vcycle": ms, "cell_vcycles_per_s": n * cycles / wall,
+           "residual_factor_per_cycle": float(np.exp(np.mean(np.log(fac)))) if fac else None,
+           "residual_first_last": [res[0], res[-1]],
+           "hbm": {"algorithmic_bytes_per_cell_per_vcycle": bytes_pc, "GB/s": n * bytes_pc / (ms * 1e-3) / 1e9,
+                   "peak": PEAK_HBM_GBS}}
+    del f, phi, work, m
+    torch.cuda.empty_cache()
+    return out
+
+
 def step_bytes_per_block(N: int) -> int:
     """Algorithmic HBM bytes of one step of one block in a run of steps:
     refresh and three sweeps (the CFL candidates are taken from the values
@@ -553,6 +601,8 @@ def main():
                     help="steps of the comoving measurement (0: skip)")
     ap.add_argument("--dual-steps", type=int, default=50,
                     help="steps of the dual-energy measurement (0: skip)")
+    ap.add_argument("--mg-cycles", type=int, default=10,
+                    help="V-cycles of the mg0 Poisson measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -673,6 +723,8 @@ def main():
         out["comoving"] = comoving_compare(args.comoving_steps)
     if args.dual_steps > 0:
         out["dual_energy"] = dual_energy_compare(args.dual_steps)
+    if args.mg_cycles > 0:
+        out["mg0"] = mg0_compare(args.mg_cycles)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)

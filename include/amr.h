@@ -384,7 +384,40 @@ amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 #define AMR_PHASE_TRACERS 13
 /* expansion sources of amr_hydro_step_comoving */
 #define AMR_PHASE_EXPANSION 14
-#define AMR_NPHASE 15
+/* amr_poisson_solve (one record per solve) */
+#define AMR_PHASE_POISSON 15
+#define AMR_NPHASE 16
+/* mg0 Poisson solver: the gravity Method's geometric multigrid V-cycle
+ * (Sec. II-C; the self-gravity solver of the uniform-mesh cosmology test of
+ * Sec. III).  Solves the 7-point Laplacian (sum of the 6 neighbours -
+ * 6 phi) / dx^2 = f on a uniform periodic mesh: one instance, every leaf at
+ * level 0, periodic on every axis, grid (root[0] N) x (root[1] N) x
+ * (root[2] N) of spacing dx = dx_0.  Levels: level l+1 halves every axis of
+ * level l while all of level l's axes are multiples of 4; the coarsest level
+ * must hold at most 4096 cells.  A V(nu1, nu2) cycle: nu1 red-black
+ * Gauss-Seidel sweeps (red = (i + j + k) even first; phi = (S - dx^2 f) / 6,
+ * S = ((W + E) + (S + N)) + (B + T)), the coarse right-hand side = mean of
+ * the 8 children's residuals, the coarse correction from 0 (64 red-black
+ * sweeps on the coarsest level), trilinear prolongation of the correction
+ * (weights 27, 9, 3, 1 over 64), nu2 sweeps.
+ *   f_dev, phi_dev: n_leaves x N^3 doubles on the device, per leaf its cells
+ *     x fastest, leaves in the order of amr_mesh_blocks (f_dev is read only;
+ *     they may be the same buffer).  f is made mean-free first (periodic
+ *     solvability); phi_dev holds the initial guess on entry and, after
+ *     ncycles cycles, the mean-free result.
+ *   resid_dev: null, or ncycles + 1 doubles on the device that receive the
+ *     residual L2 norm sqrt(sum r^2) before the first cycle and after each.
+ *   work_dev: amr_poisson_workspace_bytes bytes of device memory (the level
+ *     arrays and reduction scratch), owned by the caller, contents ignored.
+ * Means and norms are fixed-order two-stage sums (results are reproducible
+ * from run to run; they differ from a sequential sum in the last bits).
+ * Errors: AMR_E_INVALID for a batch, a refined mesh, a non-periodic axis, a
+ * coarsest level above 4096 cells, ncycles < 0 or nu outside [0, 64], null
+ * pointers (resid_dev excepted); AMR_E_STATE before amr_mesh_upload. */
+amr_status amr_poisson_workspace_bytes(const amr_mesh* mesh, int64_t* bytes);
+amr_status amr_poisson_solve(amr_mesh* mesh, const double* f_dev, double* phi_dev, int32_t ncycles, int32_t nu1,
+                             int32_t nu2, double* resid_dev, void* work_dev, void* stream);
+
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
 /* Waits for the recorded events, then writes per phase the summed kernel

@@ -17,7 +17,7 @@ STATUS = {-1: "AMR_E_INVALID", -2: "AMR_E_BALANCE", -3: "AMR_E_NOMEM", -4: "AMR_
 BC = {"periodic": 0, "outflow": 1}
 PHASES = ["cfl", "refresh1", "refresh2", "sweep_x", "sweep_y", "sweep_z", "reflux",
           "adj_recompute", "adj_reflux", "adj_sweep_x", "adj_sweep_y", "adj_sweep_z", "adj_refresh", "tracers",
-          "expansion"]
+          "expansion", "poisson"]
 
 
 class AmrError(RuntimeError):
@@ -127,6 +127,8 @@ SIGNATURES = {
     "amr_profile_enable": (_I32, [_P, _I32]),
     "amr_profile_read": (_I32, [_P, _P, _P]),
     "amr_arith_selftest": (_I32, [ctypes.c_uint64, _I64, _P, _P]),
+    "amr_poisson_workspace_bytes": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "amr_poisson_solve": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P]),
     "amr_cfl_dt_comoving": (_I32, [_P, _P, ctypes.c_double, _P, _P]),
     "amr_hydro_steps": (_I32, [_P, _P, _P, _I64, _I64, _P]),
     "amr_hydro_step_comoving": (_I32, [_P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, _P]),

@@ -10,6 +10,7 @@
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
+#include "poisson.hpp"
 #include "tracers.hpp"
 
 using namespace amr;
@@ -895,6 +896,57 @@ amr_status amr_graph_destroy(amr_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
   return AMR_OK;
+}
+
+namespace {
+
+// The mg0 solver's grid: one instance whose leaves are all at level 0, periodic
+// on every axis, with a coarsest level that fits one workgroup.
+amr_status poisson_grid(const amr_mesh* h, int n[3]) {
+  const Plan& p = h->plan;
+  if (p.inst.size() != 1) return fail(AMR_E_INVALID, "the Poisson solver takes one mesh, not a batch");
+  for (const Key& k : p.keys)
+    if (k.l != 0) return fail(AMR_E_INVALID, "the Poisson solver needs a uniform mesh (all leaves at level 0)");
+  const InstParams& ip = p.inst[0];
+  for (int a = 0; a < 3; a++) {
+    if (ip.bc[a] != AMR_BC_PERIODIC) return fail(AMR_E_INVALID, "the Poisson solver needs periodic boundaries");
+    n[a] = ip.root[a] * p.N;
+  }
+  int sz[kMgMaxLevels][3];
+  const int nl = mg_levels(n[0], n[1], n[2], sz);
+  if (int64_t(sz[nl - 1][0]) * sz[nl - 1][1] * sz[nl - 1][2] > kMgCoarseMax)
+    return fail(AMR_E_INVALID, "the Poisson solver's coarsest level exceeds 4096 cells (odd parts of the root extents too large)");
+  return AMR_OK;
+}
+
+}  // namespace
+
+amr_status amr_poisson_workspace_bytes(const amr_mesh* h, int64_t* bytes) {
+  if (!h || !bytes) return fail(AMR_E_INVALID, "null argument");
+  int n[3];
+  amr_status rc = poisson_grid(h, n);
+  if (rc != AMR_OK) return rc;
+  *bytes = mg_workspace_bytes(n[0], n[1], n[2]);
+  return AMR_OK;
+}
+
+amr_status amr_poisson_solve(amr_mesh* h, const double* f, double* phi, int32_t ncycles, int32_t nu1, int32_t nu2,
+                             double* resid, void* work, void* stream) {
+  if (!h) return fail(AMR_E_INVALID, "null mesh");
+  if (!h->ws) return fail(AMR_E_STATE, "no workspace uploaded");
+  if (!f || !phi || !work) return fail(AMR_E_INVALID, "null argument");
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
+    return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
+  int n[3];
+  amr_status rc = poisson_grid(h, n);
+  if (rc != AMR_OK) return rc;
+  const Plan& p = h->plan;
+  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = timed(h, AMR_PHASE_POISSON, st, [&] {
+    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, phi, ncycles, nu1, nu2, resid, work, st);
+  });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
 }
 
 amr_status amr_arith_selftest(uint64_t seed, int64_t n, uint64_t* counts, void* stream) {

@@ -1,0 +1,300 @@
+// poisson.hip -- gfx950 kernels of the mg0 Poisson solver.
+//
+// The gravity Method's geometric multigrid V-cycle (paper Sec. II-C; the
+// self-gravity solver of its uniform-mesh cosmology test, Sec. III): the
+// 7-point Laplacian of phi equals f on a uniform periodic mesh.  Each level
+// is one global array (x fastest); level l+1 halves every axis of level l
+// and exists while all of level l's axes are multiples of 4.  Red-black
+// Gauss-Seidel smoothing (red = (i + j + k) even first), residual restriction
+// by the mean of the 8 children, trilinear prolongation of the correction,
+// 64 red-black sweeps on the coarsest level in one workgroup's LDS.  Every
+// cell update is a fixed expression, so the smoothing, transfer and coarse
+// kernels give the same bits in any launch shape; the means and residual
+// norms are two-stage reductions in a fixed order.
+//
+// Built with -ffp-contract=off: each formula rounds exactly as written.
+#include <hip/hip_runtime.h>
+
+#include "poisson.hpp"
+
+namespace amr {
+
+namespace {
+
+constexpr int kRedBlock = 256;     // threads of a reduction workgroup
+constexpr int kRedParts = 1024;    // workgroups of the first reduction stage
+constexpr int kCoarseThreads = 1024;
+
+struct Lvl {
+  double* phi;
+  double* f;
+  int nx, ny, nz;
+  double h;
+};
+
+__device__ __forceinline__ int wrap_dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wrap_up(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+
+__device__ __forceinline__ int64_t lidx(const Lvl& L, int i, int j, int k) {
+  return (int64_t(k) * L.ny + j) * L.nx + i;
+}
+
+// ((W + E) + (S + N)) + (B + T) of phi around (i, j, k), periodic.
+__device__ __forceinline__ double nbr_sum(const Lvl& L, const double* p, int i, int j, int k) {
+  const int64_t row = int64_t(L.nx);
+  const int64_t pln = row * L.ny;
+  const int64_t c = lidx(L, i, j, k);
+  const double w = p[c - i + wrap_dn(i, L.nx)], e = p[c - i + wrap_up(i, L.nx)];
+  const double s = p[c + (wrap_dn(j, L.ny) - j) * row], n = p[c + (wrap_up(j, L.ny) - j) * row];
+  const double b = p[c + (wrap_dn(k, L.nz) - k) * pln], t = p[c + (wrap_up(k, L.nz) - k) * pln];
+  return ((w + e) + (s + n)) + (b + t);
+}
+
+// One colour of a red-black sweep: thread -> (m, j, k), i = 2m + parity.
+__global__ void __launch_bounds__(256) mg_rbgs(Lvl L, int color) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int hx = L.nx >> 1;
+  if (t >= int64_t(hx) * L.ny * L.nz) return;
+  const int m = int(t % hx);
+  const int64_t r = t / hx;
+  const int j = int(r % L.ny), k = int(r / L.ny);
+  const int i = 2 * m + ((j + k + color) & 1);
+  const double h2 = L.h * L.h, sixth = 1.0 / 6.0;
+  const int64_t c = lidx(L, i, j, k);
+  L.phi[c] = (nbr_sum(L, L.phi, i, j, k) - h2 * L.f[c]) * sixth;
+}
+
+__device__ __forceinline__ double residual_at(const Lvl& L, int i, int j, int k) {
+  const int64_t c = lidx(L, i, j, k);
+  const double ih2 = 1.0 / (L.h * L.h);
+  return L.f[c] - (nbr_sum(L, L.phi, i, j, k) - 6.0 * L.phi[c]) * ih2;
+}
+
+// Coarse right-hand side = mean of the 8 children's residuals (x fastest,
+// then y, then z, in pairs); the coarse correction starts from 0.
+__global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(C.nx) * C.ny * C.nz) return;
+  const int i = int(t % C.nx);
+  const int64_t q = t / C.nx;
+  const int j = int(q % C.ny), k = int(q / C.ny);
+  double r[8];
+#pragma unroll
+  for (int o = 0; o < 8; o++) r[o] = residual_at(F, 2 * i + (o & 1), 2 * j + ((o >> 1) & 1), 2 * k + (o >> 2));
+  C.f[t] = (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * 0.125;
+  C.phi[t] = 0.0;
+}
+
+// Trilinear prolongation of the coarse correction, added to the fine phi.
+__global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(F.nx) * F.ny * F.nz) return;
+  const int i = int(t % F.nx);
+  const int64_t q = t / F.nx;
+  const int j = int(q % F.ny), k = int(q / F.ny);
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  const int I2 = (i & 1) ? wrap_up(I, C.nx) : wrap_dn(I, C.nx);
+  const int J2 = (j & 1) ? wrap_up(J, C.ny) : wrap_dn(J, C.ny);
+  const int K2 = (k & 1) ? wrap_up(K, C.nz) : wrap_dn(K, C.nz);
+  const double* p = C.phi;
+  const double c0 = p[lidx(C, I, J, K)];
+  const double cx = p[lidx(C, I2, J, K)], cy = p[lidx(C, I, J2, K)], cz = p[lidx(C, I, J, K2)];
+  const double cxy = p[lidx(C, I2, J2, K)], cxz = p[lidx(C, I2, J, K2)], cyz = p[lidx(C, I, J2, K2)];
+  const double cxyz = p[lidx(C, I2, J2, K2)];
+  const double w64 = 1.0 / 64.0;
+  const double v = ((27.0 * c0 + 9.0 * ((cx + cy) + cz)) + (3.0 * ((cxy + cxz) + cyz) + cxyz)) * w64;
+  F.phi[t] = F.phi[t] + v;
+}
+
+// Coarsest level: 64 red-black sweeps in one workgroup's LDS (at most
+// kMgCoarseMax cells), from its phi (0 below the finest level, which is set
+// by the restriction; the iterate itself on a one-level grid).
+__global__ void __launch_bounds__(kCoarseThreads) mg_coarse_solve(Lvl L) {
+  __shared__ double ph[kMgCoarseMax];
+  __shared__ double rhs[kMgCoarseMax];
+  const int n = L.nx * L.ny * L.nz;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    ph[c] = L.phi[c];
+    rhs[c] = L.f[c];
+  }
+  __syncthreads();
+  Lvl S = L;
+  S.phi = ph;
+  const double h2 = L.h * L.h, sixth = 1.0 / 6.0;
+  for (int sweep = 0; sweep < kMgCoarseSweeps; sweep++)
+    for (int color = 0; color < 2; color++) {
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+        if (((i + j + k) & 1) != color) continue;
+        ph[c] = (nbr_sum(S, ph, i, j, k) - h2 * rhs[c]) * sixth;
+      }
+      __syncthreads();
+    }
+  for (int c = threadIdx.x; c < n; c += blockDim.x) L.phi[c] = ph[c];
+}
+
+// Level 0 from the block layout (per leaf N^3 active cells, x fastest).
+template <int N>
+__global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, const double* __restrict__ pb,
+                                                 Lvl L, DevPlan P) {
+  constexpr int N3 = N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const BlockInfo bi = P.blocks[s];
+  const int64_t g = lidx(L, bi.i * N + q % N, bi.j * N + (q / N) % N, bi.k * N + q / (N * N));
+  L.f[g] = fb[t];
+  L.phi[g] = pb[t];
+}
+
+// Block layout from level 0, minus the mean held at *mean.
+template <int N>
+__global__ void __launch_bounds__(256) mg_scatter(Lvl L, DevPlan P, const double* __restrict__ mean,
+                                                  double* __restrict__ pb) {
+  constexpr int N3 = N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const BlockInfo bi = P.blocks[s];
+  const int64_t g = lidx(L, bi.i * N + q % N, bi.j * N + (q / N) % N, bi.k * N + q / (N * N));
+  pb[t] = L.phi[g] - *mean;
+}
+
+__global__ void __launch_bounds__(256) mg_sub_mean(double* __restrict__ a, int64_t n, const double* __restrict__ mean) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = a[t] - *mean;
+}
+
+// Workgroup sum in a fixed tree order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kRedBlock];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// First stage: part b sums the elements b, b + kRedParts kRedBlock, ... of
+// each of its lanes' strided sequences (MODE 0: a; MODE 1: the squared
+// residual of level L).
+template <int MODE>
+__global__ void __launch_bounds__(kRedBlock) mg_sum_parts(const double* __restrict__ a, Lvl L, int64_t n,
+                                                          double* __restrict__ parts) {
+  double s = 0.0;
+  for (int64_t t = int64_t(blockIdx.x) * kRedBlock + threadIdx.x; t < n; t += int64_t(kRedParts) * kRedBlock) {
+    if (MODE == 0) {
+      s += a[t];
+    } else {
+      const int i = int(t % L.nx);
+      const int64_t q = t / L.nx;
+      const double r = residual_at(L, i, int(q % L.ny), int(q / L.ny));
+      s += r * r;
+    }
+  }
+  const double b = block_sum(s);
+  if (threadIdx.x == 0) parts[blockIdx.x] = b;
+}
+
+// Second stage: *out = sum of the parts times scale (MODE 0), or its square
+// root (MODE 1).
+template <int MODE>
+__global__ void __launch_bounds__(kRedBlock) mg_sum_final(const double* __restrict__ parts, double scale,
+                                                          double* __restrict__ out) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < kRedParts; b += kRedBlock) s += parts[b];
+  const double tot = block_sum(s);
+  if (threadIdx.x == 0) *out = MODE == 0 ? tot * scale : sqrt(tot);
+}
+
+inline unsigned grid_for(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+int mg_levels(int nx, int ny, int nz, int sizes[][3]) {
+  int n[3] = {nx, ny, nz}, nl = 0;
+  while (true) {
+    for (int a = 0; a < 3; a++) sizes[nl][a] = n[a];
+    nl++;
+    if (nl >= kMgMaxLevels || n[0] % 4 || n[1] % 4 || n[2] % 4) break;
+    for (int a = 0; a < 3; a++) n[a] /= 2;
+  }
+  return nl;
+}
+
+int64_t mg_workspace_bytes(int nx, int ny, int nz) {
+  int sz[kMgMaxLevels][3];
+  const int nl = mg_levels(nx, ny, nz, sz);
+  int64_t o = 0;
+  for (int l = 0; l < nl; l++) o += 2 * ((int64_t(sz[l][0]) * sz[l][1] * sz[l][2] * 8 + 255) / 256 * 256);
+  return o + (kRedParts + 64) * 8;
+}
+
+hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, double* phi_blocks,
+                    int ncycles, int nu1, int nu2, double* resid, void* work, hipStream_t st) {
+  int sz[kMgMaxLevels][3];
+  const int nl = mg_levels(nx, ny, nz, sz);
+  Lvl Ls[kMgMaxLevels];
+  unsigned char* w = static_cast<unsigned char*>(work);
+  double hl = h;
+  for (int l = 0; l < nl; l++) {
+    const int64_t bytes = (int64_t(sz[l][0]) * sz[l][1] * sz[l][2] * 8 + 255) / 256 * 256;
+    Ls[l] = Lvl{reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + bytes), sz[l][0], sz[l][1], sz[l][2], hl};
+    w += 2 * bytes;
+    hl = 2.0 * hl;
+  }
+  double* parts = reinterpret_cast<double*>(w);
+  double* scal = parts + kRedParts;  // [0] mean of f, [1] mean of phi
+  const int64_t n0 = int64_t(nx) * ny * nz;
+  const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
+  const dim3 b(256);
+  switch (P.N) {
+    case 8: hipLaunchKernelGGL(mg_gather<8>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
+    case 16: hipLaunchKernelGGL(mg_gather<16>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
+    case 32: hipLaunchKernelGGL(mg_gather<32>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(mg_sum_parts<0>, dim3(kRedParts), dim3(kRedBlock), 0, st, Ls[0].f, Ls[0], n0, parts);
+  hipLaunchKernelGGL(mg_sum_final<0>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0 / double(n0), scal);
+  hipLaunchKernelGGL(mg_sub_mean, dim3(grid_for(n0, 256)), b, 0, st, Ls[0].f, n0, scal);
+  auto norm = [&](int c) {
+    if (!resid) return;
+    hipLaunchKernelGGL(mg_sum_parts<1>, dim3(kRedParts), dim3(kRedBlock), 0, st, nullptr, Ls[0], n0, parts);
+    hipLaunchKernelGGL(mg_sum_final<1>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0, resid + c);
+  };
+  auto smooth = [&](const Lvl& L, int sweeps) {
+    const int64_t half = int64_t(L.nx / 2) * L.ny * L.nz;
+    for (int s = 0; s < sweeps; s++)
+      for (int color = 0; color < 2; color++)
+        hipLaunchKernelGGL(mg_rbgs, dim3(grid_for(half, 256)), b, 0, st, L, color);
+  };
+  norm(0);
+  for (int c = 0; c < ncycles; c++) {
+    for (int l = 0; l < nl - 1; l++) {
+      smooth(Ls[l], nu1);
+      const int64_t ncell = int64_t(Ls[l + 1].nx) * Ls[l + 1].ny * Ls[l + 1].nz;
+      hipLaunchKernelGGL(mg_restrict, dim3(grid_for(ncell, 256)), b, 0, st, Ls[l], Ls[l + 1]);
+    }
+    hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
+    for (int l = nl - 2; l >= 0; l--) {
+      const int64_t ncell = int64_t(Ls[l].nx) * Ls[l].ny * Ls[l].nz;
+      hipLaunchKernelGGL(mg_prolong_add, dim3(grid_for(ncell, 256)), b, 0, st, Ls[l + 1], Ls[l]);
+      smooth(Ls[l], nu2);
+    }
+    norm(c + 1);
+  }
+  hipLaunchKernelGGL(mg_sum_parts<0>, dim3(kRedParts), dim3(kRedBlock), 0, st, Ls[0].phi, Ls[0], n0, parts);
+  hipLaunchKernelGGL(mg_sum_final<0>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0 / double(n0), scal + 1);
+  switch (P.N) {
+    case 8: hipLaunchKernelGGL(mg_scatter<8>, dim3(grid_for(nb, 256)), b, 0, st, Ls[0], P, scal + 1, phi_blocks); break;
+    case 16: hipLaunchKernelGGL(mg_scatter<16>, dim3(grid_for(nb, 256)), b, 0, st, Ls[0], P, scal + 1, phi_blocks); break;
+    default: hipLaunchKernelGGL(mg_scatter<32>, dim3(grid_for(nb, 256)), b, 0, st, Ls[0], P, scal + 1, phi_blocks); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace amr

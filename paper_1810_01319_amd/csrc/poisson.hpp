@@ -1,0 +1,27 @@
+// poisson.hpp -- the mg0 Poisson solver's launcher (poisson.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace amr {
+
+constexpr int kMgMaxLevels = 24;
+constexpr int kMgCoarseMax = 4096;  // cells of the coarsest level (one workgroup's LDS)
+constexpr int kMgCoarseSweeps = 64;
+
+// Level sizes (x, y, z) of a uniform nx x ny x nz grid: level l+1 halves
+// level l while every axis of level l is a multiple of 4.  Returns the count.
+int mg_levels(int nx, int ny, int nz, int sizes[][3]);
+// Workspace of mg_solve: phi and f of every level (256-byte aligned), then
+// the reduction scratch.
+int64_t mg_workspace_bytes(int nx, int ny, int nz);
+// ncycles V(nu1, nu2) cycles on the uniform periodic grid of the plan's
+// level-0 leaves (spacing h), f and phi in the block layout (per leaf N^3
+// active cells, x fastest); resid (device, ncycles + 1 doubles) or null.
+hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, double* phi_blocks,
+                    int ncycles, int nu1, int nu2, double* resid, void* work, hipStream_t st);
+
+}  // namespace amr

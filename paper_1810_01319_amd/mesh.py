@@ -239,6 +239,30 @@ class Mesh:
         self._check_state(lam)
         check(lib().amr_refresh_ghosts_adjoint(self._h, _ptr(U_ref), _ptr(lam), _stream()))
 
+    # mg0 Poisson solver ---------------------------------------------
+    def poisson_workspace(self) -> torch.Tensor:
+        """Device workspace of poisson_solve (the level arrays)."""
+        n = ctypes.c_int64()
+        check(lib().amr_poisson_workspace_bytes(self._h, ctypes.byref(n)))
+        return torch.empty((int(n.value) + 7) // 8, dtype=torch.float64, device=self.device)
+
+    def poisson_solve(self, f: torch.Tensor, phi: torch.Tensor, ncycles: int, nu1: int = 2, nu2: int = 2,
+                      work: torch.Tensor = None, resid: bool = True):
+        """ncycles mg0 V(nu1, nu2) cycles on lap(phi) = f (uniform periodic mesh);
+        f and phi are [n_leaves, N, N, N] float64 device tensors (phi: initial
+        guess in, mean-free result out).  Returns the residual norms (device
+        tensor of ncycles + 1) or None."""
+        shape = (self.nleaf, self.N, self.N, self.N)
+        for t in (f, phi):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device or tuple(t.shape) != shape:
+                raise ValueError("f and phi must be contiguous float64 [n_leaves, N, N, N] tensors on the device")
+        if work is None:
+            work = self.poisson_workspace()
+        r = torch.empty(ncycles + 1, dtype=torch.float64, device=self.device) if resid else None
+        check(lib().amr_poisson_solve(self._h, _ptr(f), _ptr(phi), int(ncycles), int(nu1), int(nu2),
+                                      _ptr(r) if r is not None else None, _ptr(work), _stream()))
+        return r
+
     # remesh -----------------------------------------------------------
     def indicator(self, U: torch.Tensor) -> torch.Tensor:
         """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""
