@@ -3,7 +3,10 @@
 // The gravity Method's geometric multigrid V-cycle (paper Sec. II-C; the
 // self-gravity solver of its uniform-mesh cosmology test, Sec. III): the
 // 7-point Laplacian of phi equals f on a uniform periodic mesh.  Each level
-// is one global array (x fastest); level l+1 halves every axis of level l
+// is one global grid stored split by colour: cell (i, j, k) of colour
+// c = (i + j + k) mod 2 sits at c n/2 + (k ny + j) nx/2 + i/2, so a colour
+// pass reads the other colour and writes its own with unit stride across
+// lanes and moves no line of the colour it skips.  Level l+1 halves every axis of level l
 // and exists while all of level l's axes are multiples of 4.  Red-black
 // Gauss-Seidel smoothing (red = (i + j + k) even first), residual restriction
 // by the mean of the 8 children, trilinear prolongation of the correction,
@@ -35,32 +38,43 @@ struct Lvl {
 __device__ __forceinline__ int wrap_dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_up(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 
+// Storage index of cell (i, j, k) (colour-split layout).
 __device__ __forceinline__ int64_t lidx(const Lvl& L, int i, int j, int k) {
-  return (int64_t(k) * L.ny + j) * L.nx + i;
+  const int64_t half = (int64_t(L.nx) * L.ny * L.nz) >> 1;
+  return ((i + j + k) & 1) * half + (int64_t(k) * L.ny + j) * (L.nx >> 1) + (i >> 1);
+}
+
+// Cell of storage index t: colour t / (n/2), then z, y, x/2.
+__device__ __forceinline__ void lcell(const Lvl& L, int64_t t, int& i, int& j, int& k) {
+  const int64_t half = (int64_t(L.nx) * L.ny * L.nz) >> 1;
+  const int c = t >= half ? 1 : 0;
+  const int64_t r = t - c * half;
+  const int hx = L.nx >> 1;
+  const int m = int(r % hx);
+  const int64_t q = r / hx;
+  j = int(q % L.ny);
+  k = int(q / L.ny);
+  i = 2 * m + ((j + k + c) & 1);
 }
 
 // ((W + E) + (S + N)) + (B + T) of phi around (i, j, k), periodic.
 __device__ __forceinline__ double nbr_sum(const Lvl& L, const double* p, int i, int j, int k) {
-  const int64_t row = int64_t(L.nx);
-  const int64_t pln = row * L.ny;
-  const int64_t c = lidx(L, i, j, k);
-  const double w = p[c - i + wrap_dn(i, L.nx)], e = p[c - i + wrap_up(i, L.nx)];
-  const double s = p[c + (wrap_dn(j, L.ny) - j) * row], n = p[c + (wrap_up(j, L.ny) - j) * row];
-  const double b = p[c + (wrap_dn(k, L.nz) - k) * pln], t = p[c + (wrap_up(k, L.nz) - k) * pln];
+  const double w = p[lidx(L, wrap_dn(i, L.nx), j, k)], e = p[lidx(L, wrap_up(i, L.nx), j, k)];
+  const double s = p[lidx(L, i, wrap_dn(j, L.ny), k)], n = p[lidx(L, i, wrap_up(j, L.ny), k)];
+  const double b = p[lidx(L, i, j, wrap_dn(k, L.nz))], t = p[lidx(L, i, j, wrap_up(k, L.nz))];
   return ((w + e) + (s + n)) + (b + t);
 }
 
-// One colour of a red-black sweep: thread -> (m, j, k), i = 2m + parity.
+// One colour of a red-black sweep: thread t updates the colour's cell of
+// storage index color n/2 + t.
 __global__ void __launch_bounds__(256) mg_rbgs(Lvl L, int color) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int hx = L.nx >> 1;
-  if (t >= int64_t(hx) * L.ny * L.nz) return;
-  const int m = int(t % hx);
-  const int64_t r = t / hx;
-  const int j = int(r % L.ny), k = int(r / L.ny);
-  const int i = 2 * m + ((j + k + color) & 1);
+  const int64_t half = (int64_t(L.nx) * L.ny * L.nz) >> 1;
+  if (t >= half) return;
+  const int64_t c = color * half + t;
+  int i, j, k;
+  lcell(L, c, i, j, k);
   const double h2 = L.h * L.h, sixth = 1.0 / 6.0;
-  const int64_t c = lidx(L, i, j, k);
   L.phi[c] = (nbr_sum(L, L.phi, i, j, k) - h2 * L.f[c]) * sixth;
 }
 
@@ -72,6 +86,8 @@ __device__ __forceinline__ double residual_at(const Lvl& L, int i, int j, int k)
 
 // Coarse right-hand side = mean of the 8 children's residuals (x fastest,
 // then y, then z, in pairs); the coarse correction starts from 0.
+// Threads run over coarse cells in natural order (x fastest), so that the
+// children's reads are contiguous across lanes in the fine colour arrays.
 __global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(C.nx) * C.ny * C.nz) return;
@@ -81,29 +97,43 @@ __global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
   double r[8];
 #pragma unroll
   for (int o = 0; o < 8; o++) r[o] = residual_at(F, 2 * i + (o & 1), 2 * j + ((o >> 1) & 1), 2 * k + (o >> 2));
-  C.f[t] = (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * 0.125;
-  C.phi[t] = 0.0;
+  const int64_t c = lidx(C, i, j, k);
+  C.f[c] = (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * 0.125;
+  C.phi[c] = 0.0;
 }
 
-// Trilinear prolongation of the coarse correction, added to the fine phi.
+// Trilinear prolongation of the coarse correction, added to the fine phi:
+// one thread per coarse cell (natural order) reads its 27 coarse neighbours
+// once and updates its 8 children.
 __global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(F.nx) * F.ny * F.nz) return;
-  const int i = int(t % F.nx);
-  const int64_t q = t / F.nx;
-  const int j = int(q % F.ny), k = int(q / F.ny);
-  const int I = i >> 1, J = j >> 1, K = k >> 1;
-  const int I2 = (i & 1) ? wrap_up(I, C.nx) : wrap_dn(I, C.nx);
-  const int J2 = (j & 1) ? wrap_up(J, C.ny) : wrap_dn(J, C.ny);
-  const int K2 = (k & 1) ? wrap_up(K, C.nz) : wrap_dn(K, C.nz);
-  const double* p = C.phi;
-  const double c0 = p[lidx(C, I, J, K)];
-  const double cx = p[lidx(C, I2, J, K)], cy = p[lidx(C, I, J2, K)], cz = p[lidx(C, I, J, K2)];
-  const double cxy = p[lidx(C, I2, J2, K)], cxz = p[lidx(C, I2, J, K2)], cyz = p[lidx(C, I, J2, K2)];
-  const double cxyz = p[lidx(C, I2, J2, K2)];
+  if (t >= int64_t(C.nx) * C.ny * C.nz) return;
+  const int I = int(t % C.nx);
+  const int64_t q = t / C.nx;
+  const int J = int(q % C.ny), K = int(q / C.ny);
+  const int xs[3] = {wrap_dn(I, C.nx), I, wrap_up(I, C.nx)};
+  const int ys[3] = {wrap_dn(J, C.ny), J, wrap_up(J, C.ny)};
+  const int zs[3] = {wrap_dn(K, C.nz), K, wrap_up(K, C.nz)};
+  double cv[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) cv[a][b][d] = C.phi[lidx(C, xs[d], ys[b], zs[a])];
   const double w64 = 1.0 / 64.0;
-  const double v = ((27.0 * c0 + 9.0 * ((cx + cy) + cz)) + (3.0 * ((cxy + cxz) + cyz) + cxyz)) * w64;
-  F.phi[t] = F.phi[t] + v;
+#pragma unroll
+  for (int o = 0; o < 8; o++) {
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+    const int sx = ox ? 2 : 0, sy = oy ? 2 : 0, sz = oz ? 2 : 0;  // neighbour towards the child's corner
+    const double c0 = cv[1][1][1];
+    const double cx = cv[1][1][sx], cy = cv[1][sy][1], cz = cv[sz][1][1];
+    const double cxy = cv[1][sy][sx], cxz = cv[sz][1][sx], cyz = cv[sz][sy][1];
+    const double cxyz = cv[sz][sy][sx];
+    const double v = ((27.0 * c0 + 9.0 * ((cx + cy) + cz)) + (3.0 * ((cxy + cxz) + cyz) + cxyz)) * w64;
+    const int64_t fidx = lidx(F, 2 * I + ox, 2 * J + oy, 2 * K + oz);
+    F.phi[fidx] = F.phi[fidx] + v;
+  }
 }
 
 // Coarsest level: 64 red-black sweeps in one workgroup's LDS (at most
@@ -112,25 +142,31 @@ __global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F) {
 __global__ void __launch_bounds__(kCoarseThreads) mg_coarse_solve(Lvl L) {
   __shared__ double ph[kMgCoarseMax];
   __shared__ double rhs[kMgCoarseMax];
-  const int n = L.nx * L.ny * L.nz;
+  const int n = L.nx * L.ny * L.nz;  // LDS in natural order (x fastest)
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    ph[c] = L.phi[c];
-    rhs[c] = L.f[c];
+    const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    ph[c] = L.phi[lidx(L, i, j, k)];
+    rhs[c] = L.f[lidx(L, i, j, k)];
   }
   __syncthreads();
-  Lvl S = L;
-  S.phi = ph;
   const double h2 = L.h * L.h, sixth = 1.0 / 6.0;
   for (int sweep = 0; sweep < kMgCoarseSweeps; sweep++)
     for (int color = 0; color < 2; color++) {
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
         const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
         if (((i + j + k) & 1) != color) continue;
-        ph[c] = (nbr_sum(S, ph, i, j, k) - h2 * rhs[c]) * sixth;
+        const int row = L.nx, pln = L.nx * L.ny;
+        const double w = ph[c - i + wrap_dn(i, L.nx)], e = ph[c - i + wrap_up(i, L.nx)];
+        const double s = ph[c + (wrap_dn(j, L.ny) - j) * row], nn = ph[c + (wrap_up(j, L.ny) - j) * row];
+        const double b = ph[c + (wrap_dn(k, L.nz) - k) * pln], t = ph[c + (wrap_up(k, L.nz) - k) * pln];
+        ph[c] = ((((w + e) + (s + nn)) + (b + t)) - h2 * rhs[c]) * sixth;
       }
       __syncthreads();
     }
-  for (int c = threadIdx.x; c < n; c += blockDim.x) L.phi[c] = ph[c];
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    L.phi[lidx(L, i, j, k)] = ph[c];
+  }
 }
 
 // Level 0 from the block layout (per leaf N^3 active cells, x fastest).
@@ -190,9 +226,9 @@ __global__ void __launch_bounds__(kRedBlock) mg_sum_parts(const double* __restri
     if (MODE == 0) {
       s += a[t];
     } else {
-      const int i = int(t % L.nx);
-      const int64_t q = t / L.nx;
-      const double r = residual_at(L, i, int(q % L.ny), int(q / L.ny));
+      int i, j, k;
+      lcell(L, t, i, j, k);
+      const double r = residual_at(L, i, j, k);
       s += r * r;
     }
   }
@@ -281,7 +317,7 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
     }
     hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
     for (int l = nl - 2; l >= 0; l--) {
-      const int64_t ncell = int64_t(Ls[l].nx) * Ls[l].ny * Ls[l].nz;
+      const int64_t ncell = int64_t(Ls[l + 1].nx) * Ls[l + 1].ny * Ls[l + 1].nz;  // coarse cells
       hipLaunchKernelGGL(mg_prolong_add, dim3(grid_for(ncell, 256)), b, 0, st, Ls[l + 1], Ls[l]);
       smooth(Ls[l], nu2);
     }
