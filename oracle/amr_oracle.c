@@ -1079,6 +1079,103 @@ double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, d
 }
 
 /* ------------------------------------------------------------------ */
+/* Self-gravity on a uniform mesh (Sec. II-C: the gravity Method with    */
+/* the mg0 solver; Sec. III: self-gravity on a uniform mesh)             */
+/* ------------------------------------------------------------------ */
+/* Readings: the potential solves lap(phi) = 4 pi G (rho - mean rho) with
+ * mg0 on the level-0 grid (warm-started from the caller's phi); the
+ * acceleration is g = -grad(phi) by central differences, g_a = (phi(a-1) -
+ * phi(a+1)) (1 / (2 dx)); a step is kick-drift-kick: a half kick with the
+ * start-of-step phi, the hydro step (dt from the CFL condition), phi from
+ * the new density, a half kick with it.  A kick changes the momentum by
+ * (dt/2) rho g and the total energy by the change of the kinetic energy
+ * (ke = (0.5 rho)((ux ux + uy uy) + uz uz), u = m (1/rho)), so it leaves the
+ * internal energy (and rho e) unchanged; G = 0 leaves every bit unchanged. */
+
+static int gravity_grid(const orc_mesh* m, int n[3]) {
+  for (int64_t s = 0; s < m->nleaf; s++)
+    if (m->key[4 * s] != 0) return fail("self-gravity needs a uniform mesh");
+  for (int a = 0; a < 3; a++) {
+    if (m->d.bc[a] != ORC_BC_PERIODIC) return fail("self-gravity needs periodic boundaries");
+    n[a] = m->d.root[a] * m->N;
+  }
+  return 0;
+}
+
+static void density_source(const orc_mesh* m, const int n[3], double four_pi_G, double* f) {
+  const int N = m->N, M = m->M;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double* B = block_ptr(m, s);
+    const int32_t* kk = m->key + 4 * s;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          const int64_t g = ((int64_t)(kk[3] * N + c) * n[1] + (kk[2] * N + b)) * n[0] + (kk[1] * N + a);
+          f[g] = four_pi_G * B[cell(M, 0, a + G, b + G, c + G)];
+        }
+  }
+}
+
+static void kick(orc_mesh* m, const int n[3], const double* phi, double hdt) {
+  const int N = m->N, M = m->M;
+  const double inv2h = 1.0 / (2.0 * dx_level(m, 0));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    double* B = block_ptr(m, s);
+    const int32_t* kk = m->key + 4 * s;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          const int p[3] = {kk[1] * N + a, kk[2] * N + b, kk[3] * N + c};
+          double gv[3];
+          for (int ax = 0; ax < 3; ax++) {
+            int lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
+            lo[ax] = (p[ax] + n[ax] - 1) % n[ax];
+            hi[ax] = (p[ax] + 1) % n[ax];
+            const double pl = phi[((int64_t)lo[2] * n[1] + lo[1]) * n[0] + lo[0]];
+            const double ph = phi[((int64_t)hi[2] * n[1] + hi[1]) * n[0] + hi[0]];
+            gv[ax] = (pl - ph) * inv2h;
+          }
+          double* rho = &B[cell(M, 0, a + G, b + G, c + G)];
+          double* mom[3] = {&B[cell(M, 1, a + G, b + G, c + G)], &B[cell(M, 2, a + G, b + G, c + G)],
+                            &B[cell(M, 3, a + G, b + G, c + G)]};
+          double* E = &B[cell(M, 4, a + G, b + G, c + G)];
+          const double ir = 1.0 / *rho;
+          double u[3], u2[3];
+          for (int ax = 0; ax < 3; ax++) u[ax] = *mom[ax] * ir;
+          const double ke = (0.5 * *rho) * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+          for (int ax = 0; ax < 3; ax++) {
+            const double g = (g_debug & ORC_DEBUG_GRAVITY_SIGN) ? -gv[ax] : gv[ax];
+            *mom[ax] = *mom[ax] + hdt * (*rho * g);
+            u2[ax] = *mom[ax] * ir;
+          }
+          const double ke2 = (0.5 * *rho) * ((u2[0] * u2[0] + u2[1] * u2[1]) + u2[2] * u2[2]);
+          *E = *E + (ke2 - ke);
+        }
+  }
+}
+
+double orc_step_gravity(orc_mesh* m, int64_t step_index, double four_pi_G, double* phi, int phi_current,
+                        int ncycles, int nu1, int nu2) {
+  int n[3];
+  if (gravity_grid(m, n) != 0) return -1.0;
+  const double h = dx_level(m, 0);
+  double* f = (double*)malloc((size_t)n[0] * n[1] * n[2] * sizeof(double));
+  if (!phi_current) {
+    density_source(m, n, four_pi_G, f);
+    orc_mg_solve(n[0], n[1], n[2], h, f, phi, ncycles, nu1, nu2, NULL);
+  }
+  const double dt = orc_cfl_dt(m);
+  kick(m, n, phi, 0.5 * dt);
+  orc_step_dt(m, step_index, dt);
+  density_source(m, n, four_pi_G, f);
+  orc_mg_solve(n[0], n[1], n[2], h, f, phi, ncycles, nu1, nu2, NULL);
+  kick(m, n, phi, 0.5 * dt);
+  free(f);
+  return dt;
+}
+
+/* ------------------------------------------------------------------ */
 /* Test hooks                                                          */
 /* ------------------------------------------------------------------ */
 

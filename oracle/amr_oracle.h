@@ -94,11 +94,22 @@ int64_t orc_tracers_drift(const orc_mesh* m, double dt, int64_t n, double* X, do
 double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, double* Y, double* Z,
                         int32_t* alive);
 
-/* Test hooks on the building blocks. *//* Test hooks on the building blocks. */
+/* Self-gravity step on a uniform periodic mesh (all leaves at level 0):
+ * kick-drift-kick with g = -grad(phi), lap(phi) = 4 pi G (rho - mean rho) by
+ * mg0 (ncycles V(nu1, nu2) cycles warm-started from phi, a global
+ * (root[0] N) x (root[1] N) x (root[2] N) grid, x fastest); phi_current = 1
+ * says phi already belongs to the current density (the previous step's
+ * output), 0 solves it first.  On return phi belongs to the new density.
+ * Returns dt, or -1 for a refined or non-periodic mesh. */
+double orc_step_gravity(orc_mesh* m, int64_t step_index, double four_pi_G, double* phi, int phi_current,
+                        int ncycles, int nu1, int nu2);
+
+/* Test hooks on the building blocks. */
 #define ORC_DEBUG_SKIP_REFLUX 1
 #define ORC_DEBUG_DE_PDV_SIGN 2   /* rho e takes +p div(v) */
 #define ORC_DEBUG_DE_ENTHALPY 4   /* rho e flux with gamma / (gamma - 1) */
 #define ORC_DEBUG_DE_ETA1_FLIP 8  /* pressure source selection reversed */
+#define ORC_DEBUG_GRAVITY_SIGN 16 /* g = +grad(phi) */
 void orc_set_debug(int flags);
 void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
                  const double* WL /* rho,u,v,w,p */, const double* WR,

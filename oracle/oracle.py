@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
         L.orc_tracers_drift.restype = I64
         L.orc_step_tracers.argtypes = [P, I64, I64, P, P, P, P]
         L.orc_step_tracers.restype = D
+        L.orc_step_gravity.argtypes = [P, I64, D, P, I32, I32, I32, I32]
+        L.orc_step_gravity.restype = D
         L.orc_mg_set_debug.argtypes = [I32]
         L.orc_mg_prolong_add.argtypes = [I32, I32, I32, P, P]
         L.orc_mg_restrict_residual.argtypes = [I32, I32, I32, D, P, P, P]
@@ -217,6 +219,17 @@ class OracleMesh:
         sources over dt with H = hubble (a and H at the step's mid time)."""
         lib().orc_step_comoving(self._h, int(k), float(dt), float(a), float(hubble))
 
+    def step_gravity(self, k: int, four_pi_G: float, phi: np.ndarray, phi_current: bool, ncycles: int = 2,
+                     nu1: int = 2, nu2: int = 2) -> float:
+        """Self-gravity step (uniform periodic mesh): kick-drift-kick with the
+        mg0 potential; phi is the global [nz, ny, nx] grid, updated in place."""
+        assert phi.dtype == np.float64 and phi.flags.c_contiguous
+        dt = float(lib().orc_step_gravity(self._h, int(k), float(four_pi_G), _ptr(phi), int(bool(phi_current)),
+                                          int(ncycles), int(nu1), int(nu2)))
+        if dt < 0:
+            raise ValueError("oracle gravity: " + lib().orc_last_error().decode())
+        return dt
+
     def indicator(self) -> np.ndarray:
         out = np.zeros(self.nleaf)
         lib().orc_indicator(self._h, _ptr(out))
@@ -273,6 +286,7 @@ DEBUG_SKIP_REFLUX = 1
 DEBUG_DE_PDV_SIGN = 2
 DEBUG_DE_ENTHALPY = 4
 DEBUG_DE_ETA1_FLIP = 8
+DEBUG_GRAVITY_SIGN = 16
 
 
 def num_threads() -> int:
