@@ -457,6 +457,62 @@ def mg0_compare(cycles: int = 10):
     return out
 
 
+def gravity_compare(steps: int = 10, ncycles: int = 2):
+    """Self-gravity steps (kick-drift-kick with the mg0 potential, ncycles
+    V(2,2) cycles per solve warm-started from the previous potential) on a
+    uniform periodic mesh of 8^3 root octrees x 32^3 cells (256^3): a
+    Jeans-unstable gas (4 pi G rho0 = 60, density 1 + 0.1 cos cos, adiabatic
+    pressure).  Reports the time per step, the hydro and gravity shares, and
+    the same mesh's plain step."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    gamma = 5.0 / 3.0
+    spec = I.MeshSpec(root=(8, 8, 8), block_cells=32, gamma=gamma)
+    m = Mesh(**spec.kwargs())
+
+    def act(keys):
+        x, y, z = I.cell_centres(spec, keys)
+        rho = 1.0 + 0.1 * np.cos(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        return I.conserved(gamma, rho, 0.0, 0.0, 0.0, rho ** gamma)
+
+    U = m.state_from_blocks(act)
+    phi = torch.zeros((m.nleaf, m.N, m.N, m.N), dtype=torch.float64, device=m.device)
+    work = m.poisson_workspace()
+    dt = torch.zeros(1, dtype=torch.float64, device=m.device)
+    m.step_gravity(U, dt, 0, 60.0, phi, False, ncycles, work=work)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        m.step_gravity(U, dt, k, 60.0, phi, True, ncycles, work=work)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = m.profile_read()
+    m.profile(False)
+    cells = m.nleaf * m.N ** 3
+    grav = prof["poisson"][0] / steps
+    hydro = sum(v[0] for p, v in prof.items() if p != "poisson") / steps
+    U2 = m.state_from_blocks(act)
+    m.step(U2, dt, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        m.step(U2, dt, k)
+    torch.cuda.synchronize()
+    plain = (time.perf_counter() - t0) * 1e3 / steps
+    out = {"workload": "uniform periodic mesh, 8^3 root octrees x 32^3 cells (256^3), Jeans-unstable gas, "
+                       f"4 pi G rho0 = 60, {ncycles} V(2,2) cycles per solve",
+           "steps": steps, "ms_per_step": wall * 1e3 / steps, "cell_updates_per_s": cells * steps / wall,
+           "gravity_ms_per_step": grav, "hydro_ms_per_step": hydro, "plain_step_ms": plain}
+    del U, U2, phi, work, m
+    torch.cuda.empty_cache()
+    return out
+
+
 def step_bytes_per_block(N: int) -> int:
     """Algorithmic HBM bytes of one step of one block in a run of steps:
     refresh and three sweeps (the CFL candidates are taken from the values
@@ -603,6 +659,8 @@ def main():
                     help="steps of the dual-energy measurement (0: skip)")
     ap.add_argument("--mg-cycles", type=int, default=10,
                     help="V-cycles of the mg0 Poisson measurement (0: skip)")
+    ap.add_argument("--gravity-steps", type=int, default=10,
+                    help="steps of the self-gravity measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -725,6 +783,8 @@ def main():
         out["dual_energy"] = dual_energy_compare(args.dual_steps)
     if args.mg_cycles > 0:
         out["mg0"] = mg0_compare(args.mg_cycles)
+    if args.gravity_steps > 0:
+        out["self_gravity"] = gravity_compare(args.gravity_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -418,6 +418,26 @@ amr_status amr_poisson_workspace_bytes(const amr_mesh* mesh, int64_t* bytes);
 amr_status amr_poisson_solve(amr_mesh* mesh, const double* f_dev, double* phi_dev, int32_t ncycles, int32_t nu1,
                              int32_t nu2, double* resid_dev, void* work_dev, void* stream);
 
+/* Self-gravity step on the same meshes as amr_poisson_solve (the gravity
+ * Method coupled to ppm, Sec. II-C; the self-gravitating gas of Sec. III):
+ * kick-drift-kick.  phi solves lap(phi) = four_pi_G (rho - mean rho) with
+ * ncycles V(nu1, nu2) cycles warm-started from phi_dev; a half kick with
+ * g = -grad(phi) (central differences (phi(a-1) - phi(a+1)) / (2 dx),
+ * periodic) changes the momentum by (dt/2) rho g and the total energy by the
+ * kinetic-energy change, so it changes no internal energy (nor the
+ * dual-energy field); then the hydro step (as amr_hydro_step: dt_dev
+ * receives the CFL dt), phi of the new density, the second half kick.
+ *   phi_dev: n_leaves x N^3 doubles (the amr_poisson_solve layout), the
+ *     mean-free potential; phi_current = 1 says it belongs to U's density
+ *     (the previous call's output), 0 makes the call solve it first.  On
+ *     return it belongs to the new density.
+ *   work_dev: amr_poisson_workspace_bytes bytes.
+ * four_pi_G = 0 (with phi_dev zero) gives amr_hydro_step bit for bit.
+ * Errors: those of amr_poisson_solve, and of amr_hydro_step. */
+amr_status amr_hydro_step_gravity(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t step_index,
+                                  double four_pi_G, double* phi_dev, int32_t phi_current, int32_t ncycles,
+                                  int32_t nu1, int32_t nu2, void* work_dev, void* stream);
+
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
 /* Waits for the recorded events, then writes per phase the summed kernel

@@ -944,9 +944,45 @@ amr_status amr_poisson_solve(amr_mesh* h, const double* f, double* phi, int32_t 
   const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = timed(h, AMR_PHASE_POISSON, st, [&] {
-    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, phi, ncycles, nu1, nu2, resid, work, st);
+    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, nullptr, 0.0, phi, ncycles, nu1, nu2, resid, work, st);
   });
   return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
+}
+
+amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t step_index, double four_pi_G,
+                                  double* phi, int32_t phi_current, int32_t ncycles, int32_t nu1, int32_t nu2,
+                                  void* work, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !phi || !work) return fail(AMR_E_INVALID, "null argument");
+  if (!std::isfinite(four_pi_G)) return fail(AMR_E_INVALID, "four_pi_G must be finite");
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
+    return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
+  int n[3];
+  rc = poisson_grid(h, n);
+  if (rc != AMR_OK) return rc;
+  const Plan& p = h->plan;
+  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  auto solve = [&] {
+    return timed(h, AMR_PHASE_POISSON, st, [&] {
+      return mg_solve(P, n[0], n[1], n[2], dx, nullptr, U, four_pi_G, phi, ncycles, nu1, nu2, nullptr, work, st);
+    });
+  };
+  auto kick = [&] {
+    return timed(h, AMR_PHASE_POISSON, st, [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, work, st); });
+  };
+  hipError_t e = hipSuccess;
+  if (!phi_current) e = solve();
+  if (e == hipSuccess) e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dt, h->cfg, st); });
+  if (e == hipSuccess) e = kick();
+  if (e != hipSuccess) return hip_fail(e, "gravity");
+  rc = run_step(h, U, dt, step_index, st);
+  if (rc != AMR_OK) return rc;
+  e = solve();
+  if (e == hipSuccess) e = kick();
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
 }
 
 amr_status amr_arith_selftest(uint64_t seed, int64_t n, uint64_t* counts, void* stream) {

@@ -169,19 +169,72 @@ __global__ void __launch_bounds__(kCoarseThreads) mg_coarse_solve(Lvl L) {
   }
 }
 
-// Level 0 from the block layout (per leaf N^3 active cells, x fastest).
-template <int N>
-__global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, const double* __restrict__ pb,
-                                                 Lvl L, DevPlan P) {
+// Level 0 from the block layout (per leaf N^3 active cells, x fastest): phi
+// from pb; f from fb (SRC 0), from fpg times the density of the state U
+// (SRC 1: padded blocks of P.nf fields), or left alone (SRC 2).
+template <int N, int SRC>
+__global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, const double* __restrict__ U,
+                                                 double fpg, const double* __restrict__ pb, Lvl L, DevPlan P) {
   constexpr int N3 = N * N * N;
+  constexpr int M = N + 2 * kGhost;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= P.nleaf * N3) return;
   const int s = int(t / N3);
   const int q = int(t - int64_t(s) * N3);
+  const int a = q % N, b = (q / N) % N, c = q / (N * N);
   const BlockInfo bi = P.blocks[s];
-  const int64_t g = lidx(L, bi.i * N + q % N, bi.j * N + (q / N) % N, bi.k * N + q / (N * N));
-  L.f[g] = fb[t];
+  const int64_t g = lidx(L, bi.i * N + a, bi.j * N + b, bi.k * N + c);
+  if (SRC == 0) L.f[g] = fb[t];
+  if (SRC == 1)
+    L.f[g] = fpg * U[int64_t(s) * P.nf * M * M * M + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost)];
   L.phi[g] = pb[t];
+}
+
+// Half kick of the active cells with g = -grad(phi) (central differences of
+// level 0's phi, which holds a mean-free potential): momentum + (dt/2) rho g,
+// energy + (ke' - ke).
+template <int N>
+__global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, DevPlan P,
+                                               const double* __restrict__ dtv) {
+  constexpr int N3 = N * N * N;
+  constexpr int M = N + 2 * kGhost;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const int a = q % N, b = (q / N) % N, c = q / (N * N);
+  const BlockInfo bi = P.blocks[s];
+  const int p[3] = {bi.i * N + a, bi.j * N + b, bi.k * N + c};
+  const int n[3] = {L.nx, L.ny, L.nz};
+  const double inv2h = 1.0 / (2.0 * L.h);
+  double gv[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    int lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
+    lo[ax] = wrap_dn(p[ax], n[ax]);
+    hi[ax] = wrap_up(p[ax], n[ax]);
+    gv[ax] = (L.phi[lidx(L, lo[0], lo[1], lo[2])] - L.phi[lidx(L, hi[0], hi[1], hi[2])]) * inv2h;
+  }
+  double* B = U + int64_t(s) * P.nf * M3 + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost);
+  const double hdt = 0.5 * dtv[0];
+  const double rho = B[0];
+  const double ir = 1.0 / rho;
+  double mo[3], u[3], u2[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    mo[ax] = B[(1 + ax) * M3];
+    u[ax] = mo[ax] * ir;
+  }
+  const double ke = (0.5 * rho) * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    mo[ax] = mo[ax] + hdt * (rho * gv[ax]);
+    u2[ax] = mo[ax] * ir;
+    B[(1 + ax) * M3] = mo[ax];
+  }
+  const double ke2 = (0.5 * rho) * ((u2[0] * u2[0] + u2[1] * u2[1]) + u2[2] * u2[2]);
+  B[4 * M3] = B[4 * M3] + (ke2 - ke);
 }
 
 // Block layout from level 0, minus the mean held at *mean.
@@ -270,11 +323,11 @@ int64_t mg_workspace_bytes(int nx, int ny, int nz) {
   return o + (kRedParts + 64) * 8;
 }
 
-hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, double* phi_blocks,
-                    int ncycles, int nu1, int nu2, double* resid, void* work, hipStream_t st) {
+namespace {
+
+void levels_in(void* work, int nx, int ny, int nz, double h, Lvl* Ls, int& nl, double*& parts) {
   int sz[kMgMaxLevels][3];
-  const int nl = mg_levels(nx, ny, nz, sz);
-  Lvl Ls[kMgMaxLevels];
+  nl = mg_levels(nx, ny, nz, sz);
   unsigned char* w = static_cast<unsigned char*>(work);
   double hl = h;
   for (int l = 0; l < nl; l++) {
@@ -283,17 +336,50 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
     w += 2 * bytes;
     hl = 2.0 * hl;
   }
-  double* parts = reinterpret_cast<double*>(w);
+  parts = reinterpret_cast<double*>(w);
+}
+
+template <int SRC>
+void gather_n(const DevPlan& P, const double* fb, const double* U, double fpg, const double* pb, const Lvl& L0,
+              hipStream_t st) {
+  const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
+  const dim3 g(grid_for(nb, 256)), b(256);
+  if (P.N == 8) hipLaunchKernelGGL((mg_gather<8, SRC>), g, b, 0, st, fb, U, fpg, pb, L0, P);
+  else if (P.N == 16) hipLaunchKernelGGL((mg_gather<16, SRC>), g, b, 0, st, fb, U, fpg, pb, L0, P);
+  else hipLaunchKernelGGL((mg_gather<32, SRC>), g, b, 0, st, fb, U, fpg, pb, L0, P);
+}
+
+}  // namespace
+
+hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
+                   const double* dt, void* work, hipStream_t st) {
+  Lvl Ls[kMgMaxLevels];
+  int nl;
+  double* parts;
+  levels_in(work, nx, ny, nz, h, Ls, nl, parts);
+  gather_n<2>(P, nullptr, nullptr, 0.0, phi_blocks, Ls[0], st);
+  const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
+  const dim3 g(grid_for(nb, 256)), b(256);
+  if (P.N == 8) hipLaunchKernelGGL(mg_kick<8>, g, b, 0, st, U, Ls[0], P, dt);
+  else if (P.N == 16) hipLaunchKernelGGL(mg_kick<16>, g, b, 0, st, U, Ls[0], P, dt);
+  else hipLaunchKernelGGL(mg_kick<32>, g, b, 0, st, U, Ls[0], P, dt);
+  return hipGetLastError();
+}
+
+hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, const double* U,
+                    double fpg, double* phi_blocks, int ncycles, int nu1, int nu2, double* resid, void* work,
+                    hipStream_t st) {
+  Lvl Ls[kMgMaxLevels];
+  int nl;
+  double* parts;
+  levels_in(work, nx, ny, nz, h, Ls, nl, parts);
   double* scal = parts + kRedParts;  // [0] mean of f, [1] mean of phi
   const int64_t n0 = int64_t(nx) * ny * nz;
   const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
   const dim3 b(256);
-  switch (P.N) {
-    case 8: hipLaunchKernelGGL(mg_gather<8>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
-    case 16: hipLaunchKernelGGL(mg_gather<16>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
-    case 32: hipLaunchKernelGGL(mg_gather<32>, dim3(grid_for(nb, 256)), b, 0, st, f_blocks, phi_blocks, Ls[0], P); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (P.N != 8 && P.N != 16 && P.N != 32) return hipErrorInvalidValue;
+  if (f_blocks) gather_n<0>(P, f_blocks, nullptr, 0.0, phi_blocks, Ls[0], st);
+  else gather_n<1>(P, nullptr, U, fpg, phi_blocks, Ls[0], st);
   hipLaunchKernelGGL(mg_sum_parts<0>, dim3(kRedParts), dim3(kRedBlock), 0, st, Ls[0].f, Ls[0], n0, parts);
   hipLaunchKernelGGL(mg_sum_final<0>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0 / double(n0), scal);
   hipLaunchKernelGGL(mg_sub_mean, dim3(grid_for(n0, 256)), b, 0, st, Ls[0].f, n0, scal);

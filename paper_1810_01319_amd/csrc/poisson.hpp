@@ -21,7 +21,14 @@ int64_t mg_workspace_bytes(int nx, int ny, int nz);
 // ncycles V(nu1, nu2) cycles on the uniform periodic grid of the plan's
 // level-0 leaves (spacing h), f and phi in the block layout (per leaf N^3
 // active cells, x fastest); resid (device, ncycles + 1 doubles) or null.
-hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, double* phi_blocks,
-                    int ncycles, int nu1, int nu2, double* resid, void* work, hipStream_t st);
+// f from f_blocks, or (f_blocks null) fpg times the density of the state U.
+hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, const double* U,
+                    double fpg, double* phi_blocks, int ncycles, int nu1, int nu2, double* resid, void* work,
+                    hipStream_t st);
+// Half kick of U's active cells with g = -grad(phi) of the mean-free
+// potential phi_blocks (block layout), dt from the device: momentum
+// + (dt/2) rho g, energy + the kinetic-energy change.
+hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
+                   const double* dt, void* work, hipStream_t st);
 
 }  // namespace amr

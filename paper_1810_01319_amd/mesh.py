@@ -263,6 +263,22 @@ class Mesh:
                                       _ptr(r) if r is not None else None, _ptr(work), _stream()))
         return r
 
+    def step_gravity(self, U: torch.Tensor, dt: torch.Tensor, k: int, four_pi_G: float, phi: torch.Tensor,
+                     phi_current: bool, ncycles: int = 2, nu1: int = 2, nu2: int = 2,
+                     work: torch.Tensor = None) -> None:
+        """Self-gravity step (kick-drift-kick with the mg0 potential of
+        four_pi_G (rho - mean rho)); phi: [n_leaves, N, N, N] mean-free
+        potential, current for U's density if phi_current, updated to the new
+        density."""
+        self._check_state(U)
+        if phi.dtype != torch.float64 or not phi.is_contiguous() or phi.numel() != self.nleaf * self.N ** 3:
+            raise ValueError("phi must be a contiguous float64 [n_leaves, N, N, N] tensor")
+        if work is None:
+            work = self.poisson_workspace()
+        check(lib().amr_hydro_step_gravity(self._h, _ptr(U), _ptr(dt), int(k), ctypes.c_double(four_pi_G),
+                                           _ptr(phi), int(bool(phi_current)), int(ncycles), int(nu1), int(nu2),
+                                           _ptr(work), _stream()))
+
     # remesh -----------------------------------------------------------
     def indicator(self, U: torch.Tensor) -> torch.Tensor:
         """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""
