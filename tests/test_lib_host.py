@@ -259,3 +259,32 @@ def test_batch_leaf_sets_equal_single_meshes():
     descs[1] = d2
     h = ctypes.c_void_p()
     assert L.amr_batch_create(descs, 2, ctypes.byref(h)) == -1
+
+
+def _poisson_bytes(**kw):
+    L = _lib.lib()
+    refine = kw.pop("refine", ())
+    d, keep = _lib.make_desc(refine=refine, **kw)
+    h = ctypes.c_void_p()
+    assert L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h)) == 0
+    n = ctypes.c_int64(-1)
+    rc = L.amr_poisson_workspace_bytes(h, ctypes.byref(n))
+    L.amr_mesh_destroy(h)
+    return rc, n.value
+
+
+def test_poisson_workspace_and_refusals_on_the_host():
+    """The mg0 workspace holds phi and f of every level (each 256-byte
+    rounded) and the reduction scratch; refined meshes, outflow axes and
+    coarsest levels above 4096 cells are refused before any GPU work."""
+    rc, nbytes = _poisson_bytes(root=(2, 2, 2), block_cells=16)  # 32^3: levels 32, 16, 8, 4, 2
+    assert rc == 0
+    levels = [32 ** 3, 16 ** 3, 8 ** 3, 4 ** 3, 2 ** 3]
+    want = sum(2 * ((c * 8 + 255) // 256 * 256) for c in levels) + (1024 + 64) * 8
+    assert nbytes == want
+    assert _poisson_bytes(root=(2, 2, 2), block_cells=8, max_level=1, refine=[(0, 0, 0, 0)])[0] == -1
+    assert _poisson_bytes(root=(2, 2, 2), block_cells=8, bc="outflow")[0] == -1
+    # 9^3 roots of 32^3: 288 -> 144 -> 72 -> 36 -> 18 (not a multiple of 4): coarsest 18^3 = 5832 cells
+    assert _poisson_bytes(root=(9, 9, 9), block_cells=32)[0] == -1
+    assert _poisson_bytes(root=(7, 7, 7), block_cells=32)[0] == 0  # coarsest 14^3 = 2744 cells
+    assert _poisson_bytes(root=(3, 2, 1), block_cells=16)[0] == 0  # coarsest 6 x 4 x 2
