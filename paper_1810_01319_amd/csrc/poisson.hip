@@ -65,15 +65,16 @@ __device__ __forceinline__ double nbr_sum(const Lvl& L, const double* p, int i, 
   return ((w + e) + (s + n)) + (b + t);
 }
 
-// One colour of a red-black sweep: thread t updates the colour's cell of
-// storage index color n/2 + t.
+// One colour of a red-black sweep: grid (x/2 chunks, y, z); thread m of row
+// (j, k) updates the colour's cell i = 2m + parity (no index division).
 __global__ void __launch_bounds__(256) mg_rbgs(Lvl L, int color) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int hx = L.nx >> 1;
+  const int m = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (m >= hx) return;
+  const int j = int(blockIdx.y), k = int(blockIdx.z);
+  const int i = 2 * m + ((j + k + color) & 1);
   const int64_t half = (int64_t(L.nx) * L.ny * L.nz) >> 1;
-  if (t >= half) return;
-  const int64_t c = color * half + t;
-  int i, j, k;
-  lcell(L, c, i, j, k);
+  const int64_t c = color * half + (int64_t(k) * L.ny + j) * hx + m;
   const double h2 = L.h * L.h, sixth = 1.0 / 6.0;
   L.phi[c] = (nbr_sum(L, L.phi, i, j, k) - h2 * L.f[c]) * sixth;
 }
@@ -89,11 +90,9 @@ __device__ __forceinline__ double residual_at(const Lvl& L, int i, int j, int k)
 // Threads run over coarse cells in natural order (x fastest), so that the
 // children's reads are contiguous across lanes in the fine colour arrays.
 __global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(C.nx) * C.ny * C.nz) return;
-  const int i = int(t % C.nx);
-  const int64_t q = t / C.nx;
-  const int j = int(q % C.ny), k = int(q / C.ny);
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x);  // grid (x chunks, y, z) of the coarse level
+  if (i >= C.nx) return;
+  const int j = int(blockIdx.y), k = int(blockIdx.z);
   double r[8];
 #pragma unroll
   for (int o = 0; o < 8; o++) r[o] = residual_at(F, 2 * i + (o & 1), 2 * j + ((o >> 1) & 1), 2 * k + (o >> 2));
@@ -106,11 +105,9 @@ __global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
 // one thread per coarse cell (natural order) reads its 27 coarse neighbours
 // once and updates its 8 children.
 __global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(C.nx) * C.ny * C.nz) return;
-  const int I = int(t % C.nx);
-  const int64_t q = t / C.nx;
-  const int J = int(q % C.ny), K = int(q / C.ny);
+  const int I = int(blockIdx.x * blockDim.x + threadIdx.x);  // grid (x chunks, y, z) of the coarse level
+  if (I >= C.nx) return;
+  const int J = int(blockIdx.y), K = int(blockIdx.z);
   const int xs[3] = {wrap_dn(I, C.nx), I, wrap_up(I, C.nx)};
   const int ys[3] = {wrap_dn(J, C.ny), J, wrap_up(J, C.ny)};
   const int zs[3] = {wrap_dn(K, C.nz), K, wrap_up(K, C.nz)};
@@ -388,23 +385,31 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
     hipLaunchKernelGGL(mg_sum_parts<1>, dim3(kRedParts), dim3(kRedBlock), 0, st, nullptr, Ls[0], n0, parts);
     hipLaunchKernelGGL(mg_sum_final<1>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0, resid + c);
   };
+  // rows of n cells: workgroups of up to 256 lanes along x, one grid row per (y, z)
+  auto rows = [](int n, int ny, int nz, dim3& g, dim3& blk) {
+    const int bs = n >= 256 ? 256 : (n + 63) / 64 * 64;
+    blk = dim3(bs);
+    g = dim3(unsigned((n + bs - 1) / bs), unsigned(ny), unsigned(nz));
+  };
   auto smooth = [&](const Lvl& L, int sweeps) {
-    const int64_t half = int64_t(L.nx / 2) * L.ny * L.nz;
+    dim3 g, blk;
+    rows(L.nx / 2, L.ny, L.nz, g, blk);
     for (int s = 0; s < sweeps; s++)
-      for (int color = 0; color < 2; color++)
-        hipLaunchKernelGGL(mg_rbgs, dim3(grid_for(half, 256)), b, 0, st, L, color);
+      for (int color = 0; color < 2; color++) hipLaunchKernelGGL(mg_rbgs, g, blk, 0, st, L, color);
   };
   norm(0);
   for (int c = 0; c < ncycles; c++) {
     for (int l = 0; l < nl - 1; l++) {
       smooth(Ls[l], nu1);
-      const int64_t ncell = int64_t(Ls[l + 1].nx) * Ls[l + 1].ny * Ls[l + 1].nz;
-      hipLaunchKernelGGL(mg_restrict, dim3(grid_for(ncell, 256)), b, 0, st, Ls[l], Ls[l + 1]);
+      dim3 g, blk;
+      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk);
+      hipLaunchKernelGGL(mg_restrict, g, blk, 0, st, Ls[l], Ls[l + 1]);
     }
     hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
     for (int l = nl - 2; l >= 0; l--) {
-      const int64_t ncell = int64_t(Ls[l + 1].nx) * Ls[l + 1].ny * Ls[l + 1].nz;  // coarse cells
-      hipLaunchKernelGGL(mg_prolong_add, dim3(grid_for(ncell, 256)), b, 0, st, Ls[l + 1], Ls[l]);
+      dim3 g, blk;
+      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk);  // coarse cells
+      hipLaunchKernelGGL(mg_prolong_add, g, blk, 0, st, Ls[l + 1], Ls[l]);
       smooth(Ls[l], nu2);
     }
     norm(c + 1);
