@@ -87,17 +87,20 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(spec, act_fn, steps):
-    """The oracle as it stands, on this host's cores, for `steps` steps of the
-    same workload after one warm-up step."""
+def cpu_baseline(spec, act_fn, min_seconds, max_steps=200):
+    """The oracle as it stands, on this host's cores: whole steps of the same
+    workload after one warm-up step, until at least `min_seconds` have passed
+    (a bounded sample of the timed workload)."""
     from oracle import oracle as O
 
     m = O.OracleMesh(**spec.kwargs())
     m.set_active(act_fn(spec, m.keys))
     m.step(0)
     t0 = time.perf_counter()
-    for k in range(1, steps + 1):
-        m.step(k)
+    steps = 0
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
+        steps += 1
+        m.step(steps)
     t = time.perf_counter() - t0
     cells = m.nleaf * spec.block_cells ** 3
     return {"value": cells * steps / t, "unit": "cell-updates/s", "cores": O.num_threads(),
@@ -646,7 +649,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sedov")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum length of the oracle's timed sample (whole steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the sweep launch shapes first")
     ap.add_argument("--batch-steps", type=int, default=100,
@@ -786,7 +790,7 @@ def main():
     if args.gravity_steps > 0:
         out["self_gravity"] = gravity_compare(args.gravity_steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
