@@ -1175,6 +1175,41 @@ double orc_step_gravity(orc_mesh* m, int64_t step_index, double four_pi_G, doubl
   return dt;
 }
 
+/* Comoving self-gravity (Bryan et al. 1995): with the comoving density the
+ * momentum source is -(rho / a^2) grad(phi), phi solving lap(phi) =
+ * 4 pi G (rho - mean rho) (free of a, so a potential carried from one step
+ * to the next stays exact).  A step with the caller's dt (the comoving CFL
+ * dt), a at its start, middle and end and H at its middle: a half kick with
+ * (dt/2) / a0^2, the expansion sources over dt/2, the hydro step with
+ * dt / a_mid, the expansion sources over dt/2 (both halves with H; the
+ * symmetric split keeps the step second order, where sources after the
+ * drift made the growth of a perturbation first order in dt), phi of the
+ * new density, a half kick with (dt/2) / a1^2.  With a = 1 everywhere and
+ * H = 0 it is the plain self-gravity step with that dt. */
+int orc_step_gravity_comoving(orc_mesh* m, int64_t step_index, double dt, double a0, double a_mid, double a1,
+                              double hubble, double four_pi_G, double* phi, int phi_current, int ncycles, int nu1,
+                              int nu2) {
+  int n[3];
+  if (gravity_grid(m, n) != 0) return -1;
+  const double h = dx_level(m, 0);
+  const int no_a = (g_debug & ORC_DEBUG_GRAVITY_NO_A) != 0;
+  const double s0 = no_a ? 1.0 : 1.0 / (a0 * a0), s1 = no_a ? 1.0 : 1.0 / (a1 * a1);
+  double* f = (double*)malloc((size_t)n[0] * n[1] * n[2] * sizeof(double));
+  if (!phi_current) {
+    density_source(m, n, four_pi_G, f);
+    orc_mg_solve(n[0], n[1], n[2], h, f, phi, ncycles, nu1, nu2, NULL);
+  }
+  kick(m, n, phi, (0.5 * dt) * s0);
+  expansion(m, 0.5 * dt, hubble);
+  orc_step_dt(m, step_index, dt / a_mid);
+  expansion(m, 0.5 * dt, hubble);
+  density_source(m, n, four_pi_G, f);
+  orc_mg_solve(n[0], n[1], n[2], h, f, phi, ncycles, nu1, nu2, NULL);
+  kick(m, n, phi, (0.5 * dt) * s1);
+  free(f);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Test hooks                                                          */
 /* ------------------------------------------------------------------ */

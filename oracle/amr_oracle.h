@@ -104,12 +104,22 @@ double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, d
 double orc_step_gravity(orc_mesh* m, int64_t step_index, double four_pi_G, double* phi, int phi_current,
                         int ncycles, int nu1, int nu2);
 
+/* Comoving self-gravity step with the caller's dt, a at the step's start,
+ * middle and end, H at its middle: half kick (dt/2) / a0^2 with phi of
+ * lap(phi) = four_pi_G (rho - mean rho), the comoving hydro step, phi of the
+ * new density, half kick (dt/2) / a1^2.  Returns 0, or -1 for a refined or
+ * non-periodic mesh. */
+int orc_step_gravity_comoving(orc_mesh* m, int64_t step_index, double dt, double a0, double a_mid, double a1,
+                              double hubble, double four_pi_G, double* phi, int phi_current, int ncycles, int nu1,
+                              int nu2);
+
 /* Test hooks on the building blocks. */
 #define ORC_DEBUG_SKIP_REFLUX 1
 #define ORC_DEBUG_DE_PDV_SIGN 2   /* rho e takes +p div(v) */
 #define ORC_DEBUG_DE_ENTHALPY 4   /* rho e flux with gamma / (gamma - 1) */
 #define ORC_DEBUG_DE_ETA1_FLIP 8  /* pressure source selection reversed */
 #define ORC_DEBUG_GRAVITY_SIGN 16 /* g = +grad(phi) */
+#define ORC_DEBUG_GRAVITY_NO_A 32 /* comoving kicks without the 1/a^2 */
 void orc_set_debug(int flags);
 void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
                  const double* WL /* rho,u,v,w,p */, const double* WR,

@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
         L.orc_step_tracers.restype = D
         L.orc_step_gravity.argtypes = [P, I64, D, P, I32, I32, I32, I32]
         L.orc_step_gravity.restype = D
+        L.orc_step_gravity_comoving.argtypes = [P, I64, D, D, D, D, D, D, P, I32, I32, I32, I32]
+        L.orc_step_gravity_comoving.restype = I32
         L.orc_mg_set_debug.argtypes = [I32]
         L.orc_mg_prolong_add.argtypes = [I32, I32, I32, P, P]
         L.orc_mg_restrict_residual.argtypes = [I32, I32, I32, D, P, P, P]
@@ -230,6 +232,18 @@ class OracleMesh:
             raise ValueError("oracle gravity: " + lib().orc_last_error().decode())
         return dt
 
+    def step_gravity_comoving(self, k: int, dt: float, a0: float, a_mid: float, a1: float, hubble: float,
+                              four_pi_G: float, phi: np.ndarray, phi_current: bool, ncycles: int = 2, nu1: int = 2,
+                              nu2: int = 2) -> None:
+        """Comoving self-gravity step with the given dt, a at the step's start,
+        middle and end, and H at its middle."""
+        assert phi.dtype == np.float64 and phi.flags.c_contiguous
+        rc = lib().orc_step_gravity_comoving(self._h, int(k), float(dt), float(a0), float(a_mid), float(a1),
+                                             float(hubble), float(four_pi_G), _ptr(phi), int(bool(phi_current)),
+                                             int(ncycles), int(nu1), int(nu2))
+        if rc != 0:
+            raise ValueError("oracle gravity: " + lib().orc_last_error().decode())
+
     def indicator(self) -> np.ndarray:
         out = np.zeros(self.nleaf)
         lib().orc_indicator(self._h, _ptr(out))
@@ -287,6 +301,7 @@ DEBUG_DE_PDV_SIGN = 2
 DEBUG_DE_ENTHALPY = 4
 DEBUG_DE_ETA1_FLIP = 8
 DEBUG_GRAVITY_SIGN = 16
+DEBUG_GRAVITY_NO_A = 32
 
 
 def num_threads() -> int:
