@@ -382,9 +382,9 @@ amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 #define AMR_PHASE_ADJ_REFRESH 12
 /* tracer drift and migration (amr_hydro_step_tracers, amr_tracers_advance) */
 #define AMR_PHASE_TRACERS 13
-/* expansion sources of amr_hydro_step_comoving */
+/* expansion sources of amr_hydro_step_comoving and amr_hydro_step_gravity_comoving */
 #define AMR_PHASE_EXPANSION 14
-/* amr_poisson_solve (one record per solve) */
+/* amr_poisson_solve (one record per solve), and the gravity steps' solves and kicks */
 #define AMR_PHASE_POISSON 15
 #define AMR_NPHASE 16
 /* mg0 Poisson solver: the gravity Method's geometric multigrid V-cycle
@@ -437,6 +437,32 @@ amr_status amr_poisson_solve(amr_mesh* mesh, const double* f_dev, double* phi_de
 amr_status amr_hydro_step_gravity(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t step_index,
                                   double four_pi_G, double* phi_dev, int32_t phi_current, int32_t ncycles,
                                   int32_t nu1, int32_t nu2, void* work_dev, void* stream);
+
+/* Comoving self-gravity step (the gravity Method with the comoving ppm
+ * Method, Sec. II-C; the comoving terms of Bryan et al. 1995), on the same
+ * meshes as amr_poisson_solve.  phi is the comoving potential, free of a:
+ * lap(phi) = four_pi_G (rho - mean rho) (the comoving density; four_pi_G
+ * carries the cosmology, e.g. 3/2 Omega_m H0^2 for code units in which
+ * mean rho = 1), and the peculiar acceleration is -grad(phi) / a^2 at the
+ * time of each kick.  With dt given on the device (e.g. from
+ * amr_cfl_dt_comoving) and a0, a_mid, a1 the expansion factors at the
+ * step's start, middle and end, H = adot / a at the middle:
+ *   half kick (dt/2) / a0^2 with phi of U's density (solved first unless
+ *     phi_current);
+ *   expansion sources over dt/2 (the Crank-Nicolson factors of
+ *     amr_hydro_step_comoving with c = (dt/4) H);
+ *   the plain refresh, sweeps and reflux with dt / a_mid;
+ *   expansion sources over dt/2;
+ *   phi of the new density, half kick (dt/2) / a1^2.
+ * a0 = a_mid = a1 = 1, H = 0 gives amr_hydro_step_gravity with the same dt
+ * bit for bit.  Layouts, phi_current and work_dev as amr_hydro_step_gravity;
+ * dt_dev is read only.  Errors: those of amr_hydro_step_gravity, and
+ * AMR_E_INVALID for an expansion factor <= 0 or not finite, or a non-finite
+ * H or four_pi_G. */
+amr_status amr_hydro_step_gravity_comoving(amr_mesh* mesh, double* U_dev, const double* dt_dev, int64_t step_index,
+                                           double a0, double a_mid, double a1, double hubble, double four_pi_G,
+                                           double* phi_dev, int32_t phi_current, int32_t ncycles, int32_t nu1,
+                                           int32_t nu2, void* work_dev, void* stream);
 
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);

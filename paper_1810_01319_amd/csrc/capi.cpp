@@ -971,7 +971,8 @@ amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t st
     });
   };
   auto kick = [&] {
-    return timed(h, AMR_PHASE_POISSON, st, [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, work, st); });
+    return timed(h, AMR_PHASE_POISSON, st,
+                 [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, 1.0, work, st); });
   };
   hipError_t e = hipSuccess;
   if (!phi_current) e = solve();
@@ -982,6 +983,55 @@ amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t st
   if (rc != AMR_OK) return rc;
   e = solve();
   if (e == hipSuccess) e = kick();
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
+}
+
+amr_status amr_hydro_step_gravity_comoving(amr_mesh* h, double* U, const double* dt, int64_t step_index, double a0,
+                                           double a_mid, double a1, double hubble, double four_pi_G, double* phi,
+                                           int32_t phi_current, int32_t ncycles, int32_t nu1, int32_t nu2,
+                                           void* work, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !phi || !work) return fail(AMR_E_INVALID, "null argument");
+  for (double a : {a0, a_mid, a1})
+    if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factors must be positive and finite");
+  if (!std::isfinite(hubble) || !std::isfinite(four_pi_G))
+    return fail(AMR_E_INVALID, "expansion rate and four_pi_G must be finite");
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
+    return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
+  int n[3];
+  rc = poisson_grid(h, n);
+  if (rc != AMR_OK) return rc;
+  const Plan& p = h->plan;
+  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  auto solve = [&] {
+    return timed(h, AMR_PHASE_POISSON, st, [&] {
+      return mg_solve(P, n[0], n[1], n[2], dx, nullptr, U, four_pi_G, phi, ncycles, nu1, nu2, nullptr, work, st);
+    });
+  };
+  auto kick = [&](double a) {
+    const double scale = 1.0 / (a * a);
+    return timed(h, AMR_PHASE_POISSON, st,
+                 [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, scale, work, st); });
+  };
+  hipError_t e = hipSuccess;
+  if (!phi_current) e = solve();
+  if (e == hipSuccess) e = kick(a0);
+  double* half = nullptr;
+  if (e == hipSuccess) {
+    half = mg_half_dt(dt, work, n[0], n[1], n[2], st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, half, hubble, st); });
+  if (e == hipSuccess) e = launch_scale_dt(P, dt, a_mid, st);
+  if (e != hipSuccess) return hip_fail(e, "gravity");
+  rc = run_step(h, U, P.dte, step_index, st);
+  if (rc != AMR_OK) return rc;
+  e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, half, hubble, st); });
+  if (e == hipSuccess) e = solve();
+  if (e == hipSuccess) e = kick(a1);
   return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
 }
 

@@ -188,11 +188,11 @@ __global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, 
 }
 
 // Half kick of the active cells with g = -grad(phi) (central differences of
-// level 0's phi, which holds a mean-free potential): momentum + (dt/2) rho g,
-// energy + (ke' - ke).
+// level 0's phi, which holds a mean-free potential): momentum + hdt rho g,
+// energy + (ke' - ke), hdt = (dt/2) scale (scale 1/a^2 in comoving steps).
 template <int N>
 __global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, DevPlan P,
-                                               const double* __restrict__ dtv) {
+                                               const double* __restrict__ dtv, double scale) {
   constexpr int N3 = N * N * N;
   constexpr int M = N + 2 * kGhost;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, De
     gv[ax] = (L.phi[lidx(L, lo[0], lo[1], lo[2])] - L.phi[lidx(L, hi[0], hi[1], hi[2])]) * inv2h;
   }
   double* B = U + int64_t(s) * P.nf * M3 + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost);
-  const double hdt = 0.5 * dtv[0];
+  const double hdt = (0.5 * dtv[0]) * scale;
   const double rho = B[0];
   const double ir = 1.0 / rho;
   double mo[3], u[3], u2[3];
@@ -246,6 +246,11 @@ __global__ void __launch_bounds__(256) mg_scatter(Lvl L, DevPlan P, const double
   const BlockInfo bi = P.blocks[s];
   const int64_t g = lidx(L, bi.i * N + q % N, bi.j * N + (q / N) % N, bi.k * N + q / (N * N));
   pb[t] = L.phi[g] - *mean;
+}
+
+// dst[0] = factor src[0] (one lane).
+__global__ void mg_scale_scalar(const double* __restrict__ src, double* __restrict__ dst, double factor) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) dst[0] = factor * src[0];
 }
 
 __global__ void __launch_bounds__(256) mg_sub_mean(double* __restrict__ a, int64_t n, const double* __restrict__ mean) {
@@ -349,7 +354,7 @@ void gather_n(const DevPlan& P, const double* fb, const double* U, double fpg, c
 }  // namespace
 
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
-                   const double* dt, void* work, hipStream_t st) {
+                   const double* dt, double scale, void* work, hipStream_t st) {
   Lvl Ls[kMgMaxLevels];
   int nl;
   double* parts;
@@ -357,10 +362,20 @@ hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U
   gather_n<2>(P, nullptr, nullptr, 0.0, phi_blocks, Ls[0], st);
   const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
   const dim3 g(grid_for(nb, 256)), b(256);
-  if (P.N == 8) hipLaunchKernelGGL(mg_kick<8>, g, b, 0, st, U, Ls[0], P, dt);
-  else if (P.N == 16) hipLaunchKernelGGL(mg_kick<16>, g, b, 0, st, U, Ls[0], P, dt);
-  else hipLaunchKernelGGL(mg_kick<32>, g, b, 0, st, U, Ls[0], P, dt);
+  if (P.N == 8) hipLaunchKernelGGL(mg_kick<8>, g, b, 0, st, U, Ls[0], P, dt, scale);
+  else if (P.N == 16) hipLaunchKernelGGL(mg_kick<16>, g, b, 0, st, U, Ls[0], P, dt, scale);
+  else hipLaunchKernelGGL(mg_kick<32>, g, b, 0, st, U, Ls[0], P, dt, scale);
   return hipGetLastError();
+}
+
+double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStream_t st) {
+  Lvl Ls[kMgMaxLevels];
+  int nl;
+  double* parts;
+  levels_in(work, nx, ny, nz, 1.0, Ls, nl, parts);
+  double* slot = parts + kRedParts + 8;
+  hipLaunchKernelGGL(mg_scale_scalar, dim3(1), dim3(64), 0, st, dt, slot, 0.5);
+  return slot;
 }
 
 hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, const double* U,

@@ -29,6 +29,9 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
 // potential phi_blocks (block layout), dt from the device: momentum
 // + (dt/2) rho g, energy + the kinetic-energy change.
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
-                   const double* dt, void* work, hipStream_t st);
+                   const double* dt, double scale, void* work, hipStream_t st);
+// Enqueues dt/2 (exact) into a slot of the workspace's scratch and returns
+// the slot's device address.
+double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStream_t st);
 
 }  // namespace amr

@@ -369,7 +369,7 @@ def gaussian_random_field(n: int, seed: int, slope: float = -3.0) -> np.ndarray:
     amp = np.zeros_like(k2)
     nz = k2 > 0
     amp[nz] = k2[nz] ** (slope / 4.0)
-    f = np.fft.irfftn(fk * amp, s=(n, n, n))
+    f = np.fft.irfftn(fk * amp, s=(n, n, n), axes=(0, 1, 2))
     f -= f.mean()
     return f / np.sqrt(np.mean(f * f))
 

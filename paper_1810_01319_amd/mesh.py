@@ -279,6 +279,24 @@ class Mesh:
                                            _ptr(phi), int(bool(phi_current)), int(ncycles), int(nu1), int(nu2),
                                            _ptr(work), _stream()))
 
+    def step_gravity_comoving(self, U: torch.Tensor, dt: torch.Tensor, k: int, a0: float, a_mid: float, a1: float,
+                              hubble: float, four_pi_G: float, phi: torch.Tensor, phi_current: bool,
+                              ncycles: int = 2, nu1: int = 2, nu2: int = 2, work: torch.Tensor = None) -> None:
+        """Comoving self-gravity step with the given dt (device): kicks
+        (dt/2)/a^2 at the start (a0) and end (a1) with the a-free potential
+        of four_pi_G (rho - mean rho), expansion sources over dt/2 on both
+        sides of the hydro step, which runs with dt / a_mid; H = hubble at
+        the mid time."""
+        self._check_state(U)
+        if phi.dtype != torch.float64 or not phi.is_contiguous() or phi.numel() != self.nleaf * self.N ** 3:
+            raise ValueError("phi must be a contiguous float64 [n_leaves, N, N, N] tensor")
+        if work is None:
+            work = self.poisson_workspace()
+        d = ctypes.c_double
+        check(lib().amr_hydro_step_gravity_comoving(self._h, _ptr(U), _ptr(dt), int(k), d(a0), d(a_mid), d(a1),
+                                                    d(hubble), d(four_pi_G), _ptr(phi), int(bool(phi_current)),
+                                                    int(ncycles), int(nu1), int(nu2), _ptr(work), _stream()))
+
     # remesh -----------------------------------------------------------
     def indicator(self, U: torch.Tensor) -> torch.Tensor:
         """Per-leaf density-slope indicator (ghosts of U must be refreshed)."""

@@ -8,7 +8,9 @@ only round-off and weak coupling fill, m_z here at 1e-4 of |m|, has no scale
 of its own; its differences are one rounding unit of |m|); dt within 1e-12.
 The differences come from the potential's means, two-stage sums on the GPU
 and sequential ones in the oracle.  G = 0 equals the plain GPU step bit for
-bit."""
+bit.  The comoving step: the same bar against the oracle over an
+Einstein-de Sitter expansion; a = 1, H = 0 equals the GPU gravity step bit for
+bit; bad expansion factors are refused."""
 import sys
 
 import numpy as np
@@ -17,6 +19,7 @@ import torch
 
 from oracle import oracle as O
 from paper_1810_01319_amd import inputs as I
+from paper_1810_01319_amd._lib import AmrError
 from paper_1810_01319_amd.mesh import Mesh
 
 from test_gpu_mg import to_blocks, to_global
@@ -81,3 +84,68 @@ def test_zero_G_is_the_plain_step_bitwise():
         assert torch.equal(da, db)
     assert np.array_equal(gm.active(Ua), gm.active(Ub))
     assert torch.count_nonzero(phi).item() == 0
+
+
+def compare(gm, om, U, perm, phi_g, phi_o, de):
+    a, b = gm.active(U), om.active()[perm]
+    groups = [[0], [1, 2, 3], [4]] + ([[5]] if de else [])
+    err = max(np.max(np.abs(a[:, g] - b[:, g])) / np.max(np.abs(b[:, g])) for g in groups)
+    pg = to_global(gm, phi_g.cpu().numpy())
+    perr = np.max(np.abs(pg - phi_o)) / np.max(np.abs(phi_o))
+    return err, perr, float(np.mean(a == b))
+
+
+@pytest.mark.parametrize("root,N,de", [((2, 2, 2), 16, False), ((4, 2, 2), 8, True)])
+def test_comoving_gravity_steps_match_oracle(root, N, de):
+    """Einstein-de Sitter: a = t^(2/3), H = 2 / (3 t) at the mid time, from
+    t = 1; four_pi_G = 6 (Jeans-unstable at this sound speed)."""
+    spec = I.MeshSpec(root=root, block_cells=N, gamma=GAMMA, dual_energy=de, eta1=1e-3, eta2=0.1)
+    say(f"comoving gravity root={root} N={N} dual_energy={de}")
+    om, gm, perm = pair(spec)
+    U = load(om, gm, perm, state(spec, gm.keys, N + 1))
+    shape = (root[2] * N, root[1] * N, root[0] * N)
+    phi_o = np.zeros(shape)
+    phi_g = torch.zeros((gm.nleaf, N, N, N), dtype=torch.float64, device="cuda")
+    work = gm.poisson_workspace()
+    dtv, t = 0.004, 1.0
+    dt = torch.full((1,), dtv, dtype=torch.float64, device="cuda")
+    for k in range(4):
+        tm, t1 = t + 0.5 * dtv, t + dtv
+        args = (t ** (2 / 3), tm ** (2 / 3), t1 ** (2 / 3), 2.0 / (3.0 * tm), 6.0)
+        gm.step_gravity_comoving(U, dt, k, *args, phi_g, k > 0, ncycles=3, work=work)
+        om.step_gravity_comoving(k, dtv, *args, phi_o, k > 0, ncycles=3)
+        err, perr, bw = compare(gm, om, U, perm, phi_g, phi_o, de)
+        say(f"step {k}: a={args[2]:.5f} state rel err {err:.2e} (bitwise {bw:.4f}), phi rel err {perr:.2e}")
+        assert err <= TOL and perr <= TOL
+        t = t1
+    assert float(dt.cpu()[0]) == dtv  # dt is read only
+
+
+def test_comoving_gravity_with_a_one_is_the_gravity_step_bitwise():
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=16, gamma=GAMMA)
+    gm = Mesh(**spec.kwargs())
+    act = state(spec, gm.keys, 4)
+    Ua, Ub = gm.state_from_active(act), gm.state_from_active(act)
+    pa = torch.zeros((gm.nleaf, 16, 16, 16), dtype=torch.float64, device="cuda")
+    pb = torch.zeros_like(pa)
+    work = gm.poisson_workspace()
+    da = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        gm.step_gravity(Ua, da, k, 30.0, pa, k > 0, work=work)
+        gm.step_gravity_comoving(Ub, da, k, 1.0, 1.0, 1.0, 0.0, 30.0, pb, k > 0, work=work)
+        assert torch.equal(Ua, Ub) and torch.equal(pa, pb)
+
+
+def test_comoving_gravity_refusals():
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, gamma=GAMMA)
+    gm = Mesh(**spec.kwargs())
+    U = gm.state_from_active(state(spec, gm.keys, 2))
+    phi = torch.zeros((gm.nleaf, 8, 8, 8), dtype=torch.float64, device="cuda")
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    before = U.clone()
+    for a0, am, a1, H, g in [(0.0, 1.0, 1.0, 0.0, 1.0), (1.0, -1.0, 1.0, 0.0, 1.0), (1.0, 1.0, float("inf"), 0.0, 1.0),
+                             (1.0, 1.0, 1.0, float("nan"), 1.0), (1.0, 1.0, 1.0, 0.0, float("inf"))]:
+        with pytest.raises(AmrError):
+            gm.step_gravity_comoving(U, dt, 0, a0, am, a1, H, g, phi, False)
+    torch.cuda.synchronize()
+    assert torch.equal(U, before)
