@@ -507,11 +507,37 @@ def gravity_compare(steps: int = 10, ncycles: int = 2):
         m.step(U2, dt, k)
     torch.cuda.synchronize()
     plain = (time.perf_counter() - t0) * 1e3 / steps
+    # the comoving step on the same gas in an Einstein-de Sitter universe
+    # (a = t^(2/3) from t = 1, H = 2 / (3 t), 4 pi G mean rho = 2/3 with mean
+    # rho = 1): dt from the comoving CFL, read back each step for a(t)
+    U3 = m.state_from_blocks(act)
+    phi.zero_()
+    t = 1.0
+
+    def co_step(k, current):
+        nonlocal t
+        m.cfl_dt_comoving(U3, t ** (2.0 / 3.0), dt)
+        d = float(dt.cpu()[0])
+        tm = t + 0.5 * d
+        m.step_gravity_comoving(U3, dt, k, t ** (2.0 / 3.0), tm ** (2.0 / 3.0), (t + d) ** (2.0 / 3.0),
+                                2.0 / (3.0 * tm), 2.0 / 3.0, phi, current, ncycles, work=work)
+        t += d
+
+    co_step(0, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        co_step(k, True)
+    torch.cuda.synchronize()
+    co_wall = time.perf_counter() - t0
     out = {"workload": "uniform periodic mesh, 8^3 root octrees x 32^3 cells (256^3), Jeans-unstable gas, "
                        f"4 pi G rho0 = 60, {ncycles} V(2,2) cycles per solve",
            "steps": steps, "ms_per_step": wall * 1e3 / steps, "cell_updates_per_s": cells * steps / wall,
-           "gravity_ms_per_step": grav, "hydro_ms_per_step": hydro, "plain_step_ms": plain}
-    del U, U2, phi, work, m
+           "gravity_ms_per_step": grav, "hydro_ms_per_step": hydro, "plain_step_ms": plain,
+           "comoving": {"workload": "the same gas and mesh, comoving, Einstein-de Sitter from a = 1, "
+                                    "4 pi G mean rho = 2/3, dt from the comoving CFL read back each step",
+                        "ms_per_step": co_wall * 1e3 / steps, "a_end": t ** (2.0 / 3.0)}}
+    del U, U2, U3, phi, work, m
     torch.cuda.empty_cache()
     return out
 

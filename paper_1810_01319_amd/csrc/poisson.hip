@@ -65,13 +65,36 @@ __device__ __forceinline__ double nbr_sum(const Lvl& L, const double* p, int i, 
   return ((w + e) + (s + n)) + (b + t);
 }
 
-// One colour of a red-black sweep: grid (x/2 chunks, y, z); thread m of row
-// (j, k) updates the colour's cell i = 2m + parity (no index division).
-__global__ void __launch_bounds__(256) mg_rbgs(Lvl L, int color) {
+// Workgroup -> (x chunk bx of gx, row j, plane k) over a (gx, ny, nz) grid.
+// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8, x fastest),
+// each XCD with its own L2.  When ny is a multiple of 8, XCD x takes the band
+// of rows j in [x ny/8, (x+1) ny/8), plane after plane: the rows j +- 1 and
+// planes k +- 1 that a workgroup reads were then fetched into that XCD's L2
+// by its neighbours in the band (with the natural order, row j went to XCD
+// j mod 8 and its y neighbours to two other XCDs).
+__device__ __forceinline__ void block_row(int gx, int ny, int& bx, int& j, int& k) {
+  const unsigned b = blockIdx.x + unsigned(gx) * (blockIdx.y + unsigned(ny) * blockIdx.z);
+  if ((ny & 7) == 0) {
+    const unsigned x = b & 7u, q = b >> 3, band = unsigned(ny) >> 3;
+    bx = int(q % unsigned(gx));
+    const unsigned r = q / unsigned(gx);
+    j = int(x * band + r % band);
+    k = int(r / band);
+  } else {
+    bx = int(blockIdx.x);
+    j = int(blockIdx.y);
+    k = int(blockIdx.z);
+  }
+}
+
+// One colour of a red-black sweep: thread m of row (j, k) updates the
+// colour's cell i = 2m + parity.
+__global__ void __launch_bounds__(256) mg_rbgs(Lvl L, int color, int gx) {
   const int hx = L.nx >> 1;
-  const int m = int(blockIdx.x * blockDim.x + threadIdx.x);
+  int bx, j, k;
+  block_row(gx, L.ny, bx, j, k);
+  const int m = int(bx * blockDim.x + threadIdx.x);
   if (m >= hx) return;
-  const int j = int(blockIdx.y), k = int(blockIdx.z);
   const int i = 2 * m + ((j + k + color) & 1);
   const int64_t half = (int64_t(L.nx) * L.ny * L.nz) >> 1;
   const int64_t c = color * half + (int64_t(k) * L.ny + j) * hx + m;
@@ -89,10 +112,11 @@ __device__ __forceinline__ double residual_at(const Lvl& L, int i, int j, int k)
 // then y, then z, in pairs); the coarse correction starts from 0.
 // Threads run over coarse cells in natural order (x fastest), so that the
 // children's reads are contiguous across lanes in the fine colour arrays.
-__global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
-  const int i = int(blockIdx.x * blockDim.x + threadIdx.x);  // grid (x chunks, y, z) of the coarse level
+__global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C, int gx) {
+  int bx, j, k;
+  block_row(gx, C.ny, bx, j, k);  // rows of the coarse level
+  const int i = int(bx * blockDim.x + threadIdx.x);
   if (i >= C.nx) return;
-  const int j = int(blockIdx.y), k = int(blockIdx.z);
   double r[8];
 #pragma unroll
   for (int o = 0; o < 8; o++) r[o] = residual_at(F, 2 * i + (o & 1), 2 * j + ((o >> 1) & 1), 2 * k + (o >> 2));
@@ -104,10 +128,11 @@ __global__ void __launch_bounds__(256) mg_restrict(Lvl F, Lvl C) {
 // Trilinear prolongation of the coarse correction, added to the fine phi:
 // one thread per coarse cell (natural order) reads its 27 coarse neighbours
 // once and updates its 8 children.
-__global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F) {
-  const int I = int(blockIdx.x * blockDim.x + threadIdx.x);  // grid (x chunks, y, z) of the coarse level
+__global__ void __launch_bounds__(256) mg_prolong_add(Lvl C, Lvl F, int gx) {
+  int bx, J, K;
+  block_row(gx, C.ny, bx, J, K);  // rows of the coarse level
+  const int I = int(bx * blockDim.x + threadIdx.x);
   if (I >= C.nx) return;
-  const int J = int(blockIdx.y), K = int(blockIdx.z);
   const int xs[3] = {wrap_dn(I, C.nx), I, wrap_up(I, C.nx)};
   const int ys[3] = {wrap_dn(J, C.ny), J, wrap_up(J, C.ny)};
   const int zs[3] = {wrap_dn(K, C.nz), K, wrap_up(K, C.nz)};
@@ -400,31 +425,36 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
     hipLaunchKernelGGL(mg_sum_parts<1>, dim3(kRedParts), dim3(kRedBlock), 0, st, nullptr, Ls[0], n0, parts);
     hipLaunchKernelGGL(mg_sum_final<1>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0, resid + c);
   };
-  // rows of n cells: workgroups of up to 256 lanes along x, one grid row per (y, z)
-  auto rows = [](int n, int ny, int nz, dim3& g, dim3& blk) {
+  // rows of n cells: workgroups of up to 256 lanes along x, gx of them per
+  // (y, z) row (block_row maps them to rows)
+  auto rows = [](int n, int ny, int nz, dim3& g, dim3& blk, int& gx) {
     const int bs = n >= 256 ? 256 : (n + 63) / 64 * 64;
     blk = dim3(bs);
-    g = dim3(unsigned((n + bs - 1) / bs), unsigned(ny), unsigned(nz));
+    gx = (n + bs - 1) / bs;
+    g = dim3(unsigned(gx), unsigned(ny), unsigned(nz));
   };
   auto smooth = [&](const Lvl& L, int sweeps) {
     dim3 g, blk;
-    rows(L.nx / 2, L.ny, L.nz, g, blk);
+    int gx;
+    rows(L.nx / 2, L.ny, L.nz, g, blk, gx);
     for (int s = 0; s < sweeps; s++)
-      for (int color = 0; color < 2; color++) hipLaunchKernelGGL(mg_rbgs, g, blk, 0, st, L, color);
+      for (int color = 0; color < 2; color++) hipLaunchKernelGGL(mg_rbgs, g, blk, 0, st, L, color, gx);
   };
   norm(0);
   for (int c = 0; c < ncycles; c++) {
     for (int l = 0; l < nl - 1; l++) {
       smooth(Ls[l], nu1);
       dim3 g, blk;
-      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk);
-      hipLaunchKernelGGL(mg_restrict, g, blk, 0, st, Ls[l], Ls[l + 1]);
+      int gx;
+      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);
+      hipLaunchKernelGGL(mg_restrict, g, blk, 0, st, Ls[l], Ls[l + 1], gx);
     }
     hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
     for (int l = nl - 2; l >= 0; l--) {
       dim3 g, blk;
-      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk);  // coarse cells
-      hipLaunchKernelGGL(mg_prolong_add, g, blk, 0, st, Ls[l + 1], Ls[l]);
+      int gx;
+      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);  // coarse cells
+      hipLaunchKernelGGL(mg_prolong_add, g, blk, 0, st, Ls[l + 1], Ls[l], gx);
       smooth(Ls[l], nu2);
     }
     norm(c + 1);
