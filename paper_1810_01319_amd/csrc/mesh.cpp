@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <stdexcept>
 
 namespace amr {
 
@@ -44,8 +45,8 @@ Octree::Octree(const MeshDesc& d) : d_(d) {
 }
 
 uint8_t Octree::state(int l, int i, int j, int k) const {
-  auto it = node_.find(pack(l, i, j, k));
-  return it == node_.end() ? ABSENT : it->second;
+  const uint8_t* v = node_.find(pack(l, i, j, k));
+  return v ? *v : ABSENT;
 }
 
 bool Octree::wrap(int l, int ax, int& v) const {
@@ -91,11 +92,10 @@ std::string Octree::refine_list(const int32_t* keys, int64_t n) {
 void Octree::balance() {
   for (int l = d_.max_level; l >= 2; l--) {
     std::vector<Key> level_leaves;
-    for (const auto& kv : node_) {
-      if (kv.second != LEAF || int(kv.first >> 60) != l) continue;
-      const uint64_t p = kv.first;
-      level_leaves.push_back({l, int(p & 0xFFFFF), int((p >> 20) & 0xFFFFF), int((p >> 40) & 0xFFFFF)});
-    }
+    node_.for_each([&](uint64_t p, uint8_t st) {
+      if (st == LEAF && int(p >> 60) == l)
+        level_leaves.push_back({l, int(p & 0xFFFFF), int((p >> 20) & 0xFFFFF), int((p >> 40) & 0xFFFFF)});
+    });
     for (const Key& lf : level_leaves) {
       for (int dz = -1; dz <= 1; dz++)
         for (int dy = -1; dy <= 1; dy++)
@@ -117,11 +117,12 @@ void Octree::balance() {
 }
 
 std::string Octree::check_balance() const {
-  for (const auto& kv : node_) {
-    if (kv.second != LEAF) continue;
-    const int l = int(kv.first >> 60);
-    if (l < 2) continue;
-    const int i = int(kv.first & 0xFFFFF), j = int((kv.first >> 20) & 0xFFFFF), k = int((kv.first >> 40) & 0xFFFFF);
+  bool ok = true;
+  node_.for_each([&](uint64_t p, uint8_t st) {
+    if (!ok || st != LEAF) return;
+    const int l = int(p >> 60);
+    if (l < 2) return;
+    const int i = int(p & 0xFFFFF), j = int((p >> 20) & 0xFFFFF), k = int((p >> 40) & 0xFFFFF);
     for (int dz = -1; dz <= 1; dz++)
       for (int dy = -1; dy <= 1; dy++)
         for (int dx = -1; dx <= 1; dx++) {
@@ -130,10 +131,10 @@ std::string Octree::check_balance() const {
           bool in = true;
           for (int a = 0; a < 3; a++) in = in && wrap(l, a, q[a]);
           if (!in) continue;
-          if (state(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1) == ABSENT) return "leaves violate 2:1 balance";
+          if (state(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1) == ABSENT) ok = false;
         }
-  }
-  return "";
+  });
+  return ok ? "" : "leaves violate 2:1 balance";
 }
 
 std::string Octree::from_leaves(const int32_t* keys, int64_t n) {
@@ -158,15 +159,22 @@ std::string Octree::from_leaves(const int32_t* keys, int64_t n) {
     for (int j = 0; j < d_.root[1]; j++)
       for (int i = 0; i < d_.root[0]; i++)
         if (state(0, i, j, k) == ABSENT) return "leaves do not cover the domain";
-  for (const auto& kv : node_) {
-    if (kv.second != REFINED) continue;
-    const int l = int(kv.first >> 60);
-    const int i = int(kv.first & 0xFFFFF), j = int((kv.first >> 20) & 0xFFFFF), k = int((kv.first >> 40) & 0xFFFFF);
-    if (l + 1 > d_.max_level) return "refined node at the deepest level";
+  const char* err = nullptr;
+  node_.for_each([&](uint64_t p, uint8_t st) {
+    if (err || st != REFINED) return;
+    const int l = int(p >> 60);
+    const int i = int(p & 0xFFFFF), j = int((p >> 20) & 0xFFFFF), k = int((p >> 40) & 0xFFFFF);
+    if (l + 1 > d_.max_level) {
+      err = "refined node at the deepest level";
+      return;
+    }
     for (int c = 0; c < 8; c++)
-      if (state(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2)) == ABSENT)
-        return "leaves do not tile the domain";
-  }
+      if (state(l + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2)) == ABSENT) {
+        err = "leaves do not tile the domain";
+        return;
+      }
+  });
+  if (err) return err;
   return check_balance();
 }
 
@@ -219,7 +227,8 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   }
   nleaf = int64_t(blocks.size());
   // leaf id lookup per instance
-  std::vector<std::unordered_map<uint64_t, int32_t>> id(meshes.size());
+  std::vector<FlatMap<int32_t>> id(meshes.size());
+  for (size_t m = 0; m < meshes.size(); m++) id[m].reserve(size_t(inst[m].n_leaf));
   auto pk = [](int l, int i, int j, int k) {
     return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
   };
@@ -235,6 +244,8 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
     const int l = b.level;
     const int key[3] = {b.i, b.j, b.k};
     bool coarse_nbr = false;
+    uint8_t nst[27];  // state of the node at each neighbour position (outflow: this leaf)
+    nst[13] = Octree::LEAF;
     for (int code = 0; code < 27; code++) {
       if (code == 13) continue;
       const int sd[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
@@ -244,17 +255,20 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
         if (!T.wrap(l, a, q[a])) q[a] = key[a];  // outflow: clamp to this block's slab
       }
       const uint8_t st = T.state(l, q[0], q[1], q[2]);
+      nst[code] = st;
       Nbr& e = nbr[size_t(27 * s + code)];
       if (st == Octree::LEAF) {
         e.kind = NBR_COPY;
-        e.id = id[b.inst].at(pk(l, q[0], q[1], q[2]));
+        const int32_t* it = id[b.inst].find(pk(l, q[0], q[1], q[2]));
+        if (!it) return "leaf without a storage slot";
+        e.id = *it;
       } else if (st == Octree::REFINED) {
         e.kind = NBR_FINE;
         e.id = int32_t(fine.size() / 8);
         for (int c = 0; c < 8; c++) {
           const int co[3] = {c & 1, (c >> 1) & 1, c >> 2};
-          auto it = id[b.inst].find(pk(l + 1, 2 * q[0] + co[0], 2 * q[1] + co[1], 2 * q[2] + co[2]));
-          fine.push_back(it == id[b.inst].end() ? -1 : it->second);
+          const int32_t* it = id[b.inst].find(pk(l + 1, 2 * q[0] + co[0], 2 * q[1] + co[1], 2 * q[2] + co[2]));
+          fine.push_back(it ? *it : -1);
           // The ghost box of direction sd reads the children on the near
           // side along each axis with sd != 0 and both along sd == 0: those
           // touch this leaf, so balance makes them leaves.  Checked here
@@ -264,21 +278,20 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
           if (read && fine.back() < 0) return "restriction source is not a leaf: mesh not balanced";
         }
       } else {
-        auto it = l > 0 ? id[b.inst].find(pk(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1)) : id[b.inst].end();
-        if (it == id[b.inst].end()) return "neighbour two levels coarser: mesh not balanced";
+        const int32_t* it = l > 0 ? id[b.inst].find(pk(l - 1, q[0] >> 1, q[1] >> 1, q[2] >> 1)) : nullptr;
+        if (!it) return "neighbour two levels coarser: mesh not balanced";
         e.kind = NBR_COARSE;
-        e.id = it->second;
+        e.id = *it;
         coarse_nbr = true;
       }
     }
     if (coarse_nbr) p2list.push_back(int32_t(s));
-    // coarse-fine faces get flux slots
+    // coarse-fine faces get flux slots (a face on an outflow boundary saw
+    // this leaf itself above, a leaf: no slot)
     for (int dir = 0; dir < 3; dir++)
       for (int side = 0; side < 2; side++) {
-        int q[3] = {key[0], key[1], key[2]};
-        q[dir] += side ? 1 : -1;
-        if (!T.wrap(l, dir, q[dir])) continue;
-        if (T.state(l, q[0], q[1], q[2]) != Octree::LEAF) faceslot[size_t(6 * s + 2 * dir + side)] = int32_t(nslots++);
+        const int code = 13 + (side ? 1 : -1) * (dir == 0 ? 1 : (dir == 1 ? 3 : 9));
+        if (nst[code] != Octree::LEAF) faceslot[size_t(6 * s + 2 * dir + side)] = int32_t(nslots++);
       }
   }
   has_p2 = !p2list.empty();
@@ -307,9 +320,9 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
             c[dir] = 2 * q[dir] + (side ? 0 : 1);
             c[A] = 2 * key[A] + hA;
             c[B] = 2 * key[B] + hB;
-            auto it = id[b.inst].find(pk(l + 1, c[0], c[1], c[2]));
-            if (it == id[b.inst].end()) return "refined face neighbour without leaf children";
-            const int32_t fslot = faceslot[size_t(6 * it->second + 2 * dir + (1 - side))];
+            const int32_t* it = id[b.inst].find(pk(l + 1, c[0], c[1], c[2]));
+            if (!it) return "refined face neighbour without leaf children";
+            const int32_t fslot = faceslot[size_t(6 * *it + 2 * dir + (1 - side))];
             if (fslot < 0) return "fine face without a flux slot";
             t.slot_f[hA + 2 * hB] = fslot;
           }
@@ -385,7 +398,8 @@ RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<
   res.tree.reset(new Octree(old));
   Octree& T = *res.tree;
   const MeshDesc& d = old.desc();
-  std::unordered_map<uint64_t, int32_t> old_id;
+  FlatMap<int32_t> old_id;
+  old_id.reserve(size_t(op.nleaf));
   for (int64_t s = 0; s < op.nleaf; s++) {
     const Key& k = op.keys[size_t(s)];
     old_id[pk4(k.l, k.i, k.j, k.k)] = int32_t(s);
@@ -461,9 +475,9 @@ RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<
     bool ok = true;
     for (int ch = 0; ch < 8 && ok; ch++) {
       const int ci = 2 * P.i + (ch & 1), cj = 2 * P.j + ((ch >> 1) & 1), ck = 2 * P.k + (ch >> 2);
-      auto it = old_id.find(pk4(P.l + 1, ci, cj, ck));
-      if (it == old_id.end() || T.state(P.l + 1, ci, cj, ck) != Octree::LEAF) ok = false;
-      else if (!(S[size_t(it->second)] < coarsen_slope)) ok = false;
+      const int32_t* it = old_id.find(pk4(P.l + 1, ci, cj, ck));
+      if (!it || T.state(P.l + 1, ci, cj, ck) != Octree::LEAF) ok = false;
+      else if (!(S[size_t(*it)] < coarsen_slope)) ok = false;
     }
     if (ok) par.push_back(P);
   }
@@ -494,18 +508,22 @@ RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<
   for (const Key& k : T.leaves()) {
     MigrTask t{};
     for (int q = 0; q < 8; q++) t.src[q] = -1;
-    auto it = old_id.find(pk4(k.l, k.i, k.j, k.k));
-    if (it != old_id.end()) {
+    const int32_t* it = old_id.find(pk4(k.l, k.i, k.j, k.k));
+    const int32_t* par = k.l > 0 ? old_id.find(pk4(k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1)) : nullptr;
+    if (it) {
       t.kind = MIGR_COPY;
-      t.src[0] = it->second;
-    } else if (k.l > 0 && old_id.count(pk4(k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1))) {
+      t.src[0] = *it;
+    } else if (par) {
       t.kind = MIGR_PROLONG;
-      t.src[0] = old_id.at(pk4(k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1));
+      t.src[0] = *par;
       t.co = (k.i & 1) | ((k.j & 1) << 1) | ((k.k & 1) << 2);
     } else {
       t.kind = MIGR_RESTRICT;
-      for (int ch = 0; ch < 8; ch++)
-        t.src[ch] = old_id.at(pk4(k.l + 1, 2 * k.i + (ch & 1), 2 * k.j + ((ch >> 1) & 1), 2 * k.k + (ch >> 2)));
+      for (int ch = 0; ch < 8; ch++) {
+        const int32_t* c = old_id.find(pk4(k.l + 1, 2 * k.i + (ch & 1), 2 * k.j + ((ch >> 1) & 1), 2 * k.k + (ch >> 2)));
+        if (!c) throw std::logic_error("a merged leaf's children were not all leaves");
+        t.src[ch] = *c;
+      }
     }
     res.migr.push_back(t);
   }

@@ -2,10 +2,10 @@
 // nodes in a hash map, level-by-level 2:1 balance, Morton leaf order, and
 // the plan tables the kernels walk.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <memory>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "layout.hpp"
@@ -27,6 +27,90 @@ struct MeshDesc {
 
 struct Key {
   int32_t l, i, j, k;
+};
+
+// Hash table from packed node keys (level << 60 | k << 40 | j << 20 | i; the
+// all-ones key never occurs, level <= 8) to small values: open addressing
+// with linear probing in one flat array (load <= 1/2, Fibonacci hashing),
+// deletion by backward shift.  The plan build and the remesh decisions look
+// up every leaf's 26 neighbours; a node-based map made those lookups most of
+// the host's remesh time.
+template <class V>
+class FlatMap {
+ public:
+  static constexpr uint64_t kEmpty = ~uint64_t(0);
+  FlatMap() { rehash(16); }
+  size_t size() const { return n_; }
+  void clear() {
+    std::fill(key_.begin(), key_.end(), kEmpty);
+    n_ = 0;
+  }
+  void reserve(size_t n) {
+    size_t c = 16;
+    while (c < 2 * n) c <<= 1;
+    if (c > key_.size()) rehash(c);
+  }
+  const V* find(uint64_t k) const {
+    for (size_t s = home(k);; s = (s + 1) & mask_) {
+      if (key_[s] == k) return &val_[s];
+      if (key_[s] == kEmpty) return nullptr;
+    }
+  }
+  V* find(uint64_t k) { return const_cast<V*>(static_cast<const FlatMap*>(this)->find(k)); }
+  // The value of k, inserted as V{} if absent.
+  V& operator[](uint64_t k) {
+    if (2 * (n_ + 1) > key_.size()) rehash(2 * key_.size());
+    size_t s = home(k);
+    for (; key_[s] != kEmpty; s = (s + 1) & mask_)
+      if (key_[s] == k) return val_[s];
+    key_[s] = k;
+    val_[s] = V{};
+    n_++;
+    return val_[s];
+  }
+  void erase(uint64_t k) {
+    size_t i = home(k);
+    for (; key_[i] != k; i = (i + 1) & mask_)
+      if (key_[i] == kEmpty) return;
+    // backward shift: move each later entry of the run whose home does not
+    // lie cyclically in (i, j] into the hole
+    for (size_t j = (i + 1) & mask_; key_[j] != kEmpty; j = (j + 1) & mask_) {
+      const size_t h = home(key_[j]);
+      const bool stays = i <= j ? (i < h && h <= j) : (i < h || h <= j);
+      if (stays) continue;
+      key_[i] = key_[j];
+      val_[i] = val_[j];
+      i = j;
+    }
+    key_[i] = kEmpty;
+    n_--;
+  }
+  // f(key, value) for every entry, in table order.
+  template <class F>
+  void for_each(F&& f) const {
+    for (size_t s = 0; s < key_.size(); s++)
+      if (key_[s] != kEmpty) f(key_[s], val_[s]);
+  }
+
+ private:
+  size_t home(uint64_t k) const { return size_t((k * 0x9E3779B97F4A7C15ull) >> shift_); }
+  void rehash(size_t cap) {
+    std::vector<uint64_t> ok = std::move(key_);
+    std::vector<V> ov = std::move(val_);
+    key_.assign(cap, kEmpty);
+    val_.assign(cap, V{});
+    mask_ = cap - 1;
+    int bits = 0;
+    while ((size_t(1) << bits) < cap) bits++;
+    shift_ = 64 - bits;
+    n_ = 0;
+    for (size_t s = 0; s < ok.size(); s++)
+      if (ok[s] != kEmpty) (*this)[ok[s]] = ov[s];
+  }
+  std::vector<uint64_t> key_;
+  std::vector<V> val_;
+  size_t n_ = 0, mask_ = 0;
+  int shift_ = 64;
 };
 
 class Octree {
@@ -59,7 +143,7 @@ class Octree {
   }
   void dfs(int l, int i, int j, int k, std::vector<Key>& out) const;
   MeshDesc d_;
-  std::unordered_map<uint64_t, uint8_t> node_;
+  FlatMap<uint8_t> node_;
 };
 
 // Flattened tables of one or more meshes.
