@@ -619,6 +619,7 @@ def run_adaptive(args, spec, desc):
     dts = torch.zeros(4, 1, dtype=torch.float64, device=m.device)
     k, end = args.warmup, args.warmup + args.steps
     while k < end:
+        fresh = False
         if k > 0 and k % 4 == 0:
             torch.cuda.synchronize()
             tr = time.perf_counter()
@@ -627,13 +628,15 @@ def run_adaptive(args, spec, desc):
                 pool.swap()
                 collect(m)
                 new.profile(True)
+            else:
+                fresh = True  # the remesh refreshed u's ghosts and changed nothing
             m, u = new, un
             stats.append(st)
             torch.cuda.synchronize()
             t_remesh += time.perf_counter() - tr
         # the steps up to the next remesh in one multi-step call
         n = min(end, (k // 4 + 1) * 4) - k
-        m.steps(u, dts, n, k)
+        m.steps(u, dts, n, k, ghosts_fresh=fresh)
         for j in range(n):
             cells_per_step.append(m.nleaf * N ** 3)
             bytes_per_step.append(m.nleaf * step_bytes_per_block(N))

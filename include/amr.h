@@ -193,6 +193,15 @@ amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* 
  * Stream-ordered; AMR_E_INVALID for nsteps < 0 or a null dt_dev. */
 amr_status amr_hydro_steps(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps, int64_t first_step,
                            void* stream);
+/* amr_hydro_steps for a state whose ghosts are current: the first step
+ * skips its ghost refresh (the later ones refresh as usual).  The caller
+ * guarantees that U_dev's ghost cells hold what a refresh would write, i.e.
+ * that no active cell changed since the last amr_refresh_ghosts on this mesh
+ * or since an amr_remesh_plan that refined and coarsened nothing (which
+ * refreshes U_dev itself); then the results equal amr_hydro_steps bit for
+ * bit.  For adaptive runs, whose remesh already refreshed the state. */
+amr_status amr_hydro_steps_fresh(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps, int64_t first_step,
+                                 void* stream);
 
 /* The same step with dt given on the device (no CFL reduction). */
 amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,

@@ -207,9 +207,10 @@ hipError_t refresh_timed(amr_mesh* h, const DevPlan& P, double* U, hipStream_t s
 // candidates (last sweep, then the refluxed cells) into the instance
 // accumulators, for cfl_finalize.
 amr_status run_step_into(amr_mesh* h, double* U, double* const out[3], const double* dt, int64_t step_index,
-                         hipStream_t st, const TracerDev* tracers = nullptr, int cfl_next = 0) {
+                         hipStream_t st, const TracerDev* tracers = nullptr, int cfl_next = 0,
+                         bool ghosts_fresh = false) {
   const DevPlan P = dev_plan(h);
-  hipError_t e = refresh_timed(h, P, U, st);
+  hipError_t e = ghosts_fresh ? hipSuccess : refresh_timed(h, P, U, st);
   if (e != hipSuccess) return hip_fail(e, "refresh");
   if (tracers) {  // drift with the refreshed start-of-step state, then migrate
     e = timed(h, AMR_PHASE_TRACERS, st, [&] { return launch_tracers_advance(P, U, dt, *tracers, st); });
@@ -476,7 +477,9 @@ amr_status amr_hydro_step(amr_mesh* h, double* U, double* dt, int64_t step_index
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
 }
 
-amr_status amr_hydro_steps(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step, void* stream) {
+namespace {
+amr_status hydro_steps(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step, void* stream,
+                       bool ghosts_fresh) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
   if (!dt) return fail(AMR_E_INVALID, "null dt pointer");
@@ -493,10 +496,20 @@ amr_status amr_hydro_steps(amr_mesh* h, double* U, double* dt, int64_t nsteps, i
       e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl_finalize(P, dti, st); });
       if (e != hipSuccess) return hip_fail(e, "cfl");
     }
-    rc = run_step_into(h, U, out, dti, first_step + i, st, nullptr, i + 1 < nsteps ? 1 : 0);
+    rc = run_step_into(h, U, out, dti, first_step + i, st, nullptr, i + 1 < nsteps ? 1 : 0, ghosts_fresh && i == 0);
     if (rc != AMR_OK) return rc;
   }
   return AMR_OK;
+}
+}  // namespace
+
+amr_status amr_hydro_steps(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step, void* stream) {
+  return hydro_steps(h, U, dt, nsteps, first_step, stream, false);
+}
+
+amr_status amr_hydro_steps_fresh(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step,
+                                 void* stream) {
+  return hydro_steps(h, U, dt, nsteps, first_step, stream, true);
 }
 
 amr_status amr_hydro_step_dt(amr_mesh* h, double* U, const double* dt, int64_t step_index, void* stream) {

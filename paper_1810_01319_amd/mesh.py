@@ -142,14 +142,17 @@ class Mesh:
         self._check_state(U)
         check(lib().amr_hydro_step(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
 
-    def steps(self, U: torch.Tensor, dt: torch.Tensor, n: int, first: int = 0) -> None:
+    def steps(self, U: torch.Tensor, dt: torch.Tensor, n: int, first: int = 0, ghosts_fresh: bool = False) -> None:
         """n consecutive steps in one call (the same results as n step calls);
         dt holds n * n_instances doubles, step i's in row i.  Each step's CFL
-        reduction is fused into its predecessor."""
+        reduction is fused into its predecessor.  ghosts_fresh: U's ghosts
+        are current (no active cell changed since the last refresh, or since
+        a remesh that changed nothing), so the first step skips its refresh."""
         self._check_state(U)
         if dt.numel() < n * self.n_instances:
             raise ValueError("dt holds fewer than n * n_instances values")
-        check(lib().amr_hydro_steps(self._h, _ptr(U), _ptr(dt), int(n), int(first), _stream()))
+        fn = lib().amr_hydro_steps_fresh if ghosts_fresh else lib().amr_hydro_steps
+        check(fn(self._h, _ptr(U), _ptr(dt), int(n), int(first), _stream()))
 
     def step_dt(self, U: torch.Tensor, dt: torch.Tensor, k: int) -> None:
         self._check_state(U)

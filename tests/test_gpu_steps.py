@@ -88,3 +88,40 @@ def test_steps_on_batched_instances():
     torch.cuda.synchronize()
     assert torch.equal(dts, torch.stack(seq))
     assert torch.equal(Ua, Ub)
+
+
+def test_fresh_steps_after_a_refresh_equal_steps():
+    """amr_hydro_steps_fresh skips the first step's refresh: after an explicit
+    refresh it gives amr_hydro_steps' dt sequence and state bit for bit."""
+    spec = I.sedov_spec(root=2, block_cells=16, levels=2)
+    gm = Mesh(**spec.kwargs())
+    act = I.sedov_state(spec, gm.keys)
+    Ua, Ub = gm.state_from_active(act), gm.state_from_active(act)
+    da = torch.zeros(4, 1, dtype=torch.float64, device="cuda")
+    db = torch.zeros_like(da)
+    gm.refresh(Ua)
+    gm.steps(Ua, da, 4, 0, ghosts_fresh=True)
+    gm.steps(Ub, db, 4, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(da, db) and torch.equal(Ua, Ub)
+
+
+def test_fresh_steps_after_an_unchanged_remesh_equal_steps():
+    """A remesh that refines and coarsens nothing returns the same mesh and
+    state with the ghosts refreshed: the next run of steps may skip its first
+    refresh (as the adaptive benchmark does) and matches plain steps bit for
+    bit."""
+    spec = I.blasts_spec(root=2, block_cells=16, levels=2)
+    gm = Mesh(**spec.kwargs())
+    U = gm.state_from_active(I.blasts_state(spec, gm.keys))
+    d = torch.zeros(4, 1, dtype=torch.float64, device="cuda")
+    gm.steps(U, d, 4, 0)
+    Ub = U.clone()
+    new, Un, st = gm.remesh(U, 1e300, 0.0, gm.nleaf + 100)
+    assert new is gm and Un is U and st["refined"] == 0 and st["coarsened"] == 0
+    da = torch.zeros(4, 1, dtype=torch.float64, device="cuda")
+    db = torch.zeros_like(da)
+    gm.steps(U, da, 4, 4, ghosts_fresh=True)
+    gm.steps(Ub, db, 4, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(da, db) and torch.equal(U, Ub)
