@@ -42,10 +42,15 @@ class StatePool:
 def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope=0.1, interval=4,
         max_blocks=None, start=0, on_remesh=None, pool: StatePool = None):
     """Advance `steps` steps from step index `start`, remeshing before every
-    step index that is a positive multiple of `interval`.  Returns
-    (mesh, U, dt list (device tensors), remesh stats list)."""
+    step index that is a positive multiple of `interval`.  The steps between
+    two remeshes run as one multi-step call; after a remesh that changed
+    nothing (which refreshed the state's ghosts) that call skips its first
+    refresh.  Returns (mesh, U, dt list (device tensors of n_instances
+    doubles, one per step), remesh stats list)."""
     dts, stats = [], []
-    for k in range(start, start + steps):
+    k, end = start, start + steps
+    while k < end:
+        fresh = False
         if interval and k > 0 and k % interval == 0:
             cap = max_blocks if max_blocks is not None else capacity_from_memory(mesh)
             if pool is not None:
@@ -55,11 +60,14 @@ def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope
                     pool.swap()
             else:
                 new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap)
+            fresh = new is mesh
             mesh, U = new, Un
             stats.append(st)
             if on_remesh is not None:
                 on_remesh(k, mesh, U, st)
-        dt = torch.zeros(1, dtype=torch.float64, device=mesh.device)
-        mesh.step(U, dt, k)
-        dts.append(dt)
+        n = min(end, (k // interval + 1) * interval) - k if interval else end - k
+        seg = torch.zeros(n, mesh.n_instances, dtype=torch.float64, device=mesh.device)
+        mesh.steps(U, seg, n, k, ghosts_fresh=fresh)
+        dts.extend(seg[i] for i in range(n))
+        k += n
     return mesh, U, dts, stats
