@@ -344,12 +344,16 @@ typedef struct {
 /* Refreshes U_dev's ghosts, evaluates the indicator on the GPU, copies it to
  * the host (synchronises the stream) and builds the new mesh (host-owned,
  * destroy with amr_mesh_destroy).  U_dev must not change before
- * amr_remesh_apply. */
+ * amr_remesh_apply.  When nothing is refined or coarsened (every candidate
+ * refused, or none), *new_mesh_out is NULL: the mesh and U_dev stay as they
+ * are (U_dev's ghosts now refreshed, see amr_hydro_steps_fresh), and stats
+ * still count the refusals. */
 amr_status amr_remesh_plan(amr_mesh* mesh, double* U_dev, const amr_remesh_params* params,
                            amr_mesh** new_mesh_out, amr_remesh_stats* stats, void* stream);
 /* The same decisions from a caller-supplied indicator (S_host: n_leaves
  * doubles in host memory, storage order); no GPU work.  The returned mesh
- * can be uploaded and migrated with amr_remesh_apply like the one above. */
+ * (NULL when nothing changed) can be uploaded and migrated with
+ * amr_remesh_apply like the one above. */
 amr_status amr_remesh_plan_host(amr_mesh* mesh, const double* S_host, const amr_remesh_params* params,
                                 amr_mesh** new_mesh_out, amr_remesh_stats* stats);
 /* Fill the active cells of U_new_dev (new mesh layout) from U_old_dev (the

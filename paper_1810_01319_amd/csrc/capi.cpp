@@ -284,6 +284,14 @@ bool adjoint_iters_ok(const Plan& p) {
 amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_params* prm, amr_mesh** out,
                   amr_remesh_stats* stats) {
   RemeshResult r = remesh_decide(*h->tree, h->plan, S, prm->refine_slope, prm->coarsen_slope, prm->max_blocks);
+  if (r.refined == 0 && r.coarsened == 0) {  // the same leaves in the same order: no new mesh
+    *out = nullptr;
+    stats->refined = 0;
+    stats->coarsened = 0;
+    stats->refused = r.refused;
+    stats->n_leaves = h->plan.nleaf;
+    return AMR_OK;
+  }
   amr_mesh* nh = new (std::nothrow) amr_mesh();
   if (!nh) return fail(AMR_E_NOMEM, "out of host memory");
   nh->trees.push_back(std::move(r.tree));

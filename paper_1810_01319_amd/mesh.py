@@ -323,8 +323,7 @@ class Mesh:
                                     _stream()))
         stats = {"refined": int(st.refined), "coarsened": int(st.coarsened), "refused": int(st.refused),
                  "n_leaves": int(st.n_leaves)}
-        if stats["refined"] == 0 and stats["coarsened"] == 0:
-            lib().amr_mesh_destroy(h)
+        if not h.value:  # nothing refined or coarsened: no new mesh
             return self, U, stats
         new = Mesh(device=self.device, _handle=h, **self.params)
         new.set_launch(**self.get_launch())

@@ -151,6 +151,42 @@ def _blast_oracle(root, N, levels, seed, steps=4):
     return spec, m
 
 
+def _new_leaves(L, h, h2, st):
+    """Leaf keys of the remeshed mesh h2; a remesh that changed nothing
+    returns no mesh, and the leaves are h's."""
+    src = h2 if h2.value else h
+    if not h2.value:
+        assert st.refined == 0 and st.coarsened == 0
+    info = _lib.MeshInfo()
+    L.amr_mesh_info(src, ctypes.byref(info))
+    assert info.n_leaves == st.n_leaves
+    k2 = np.zeros((info.n_leaves, 4), dtype=np.int32)
+    L.amr_mesh_blocks(src, k2.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+    return k2
+
+
+def test_remesh_that_changes_nothing_returns_no_mesh():
+    L = _lib.lib()
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=2, gamma=1.4,
+                      refine=I.random_refine_list((2, 2, 2), 2, 4, 1))
+    d, keep = _lib.make_desc(**spec.kwargs())
+    h = ctypes.c_void_p()
+    assert L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h)) == 0
+    info = _lib.MeshInfo()
+    L.amr_mesh_info(h, ctypes.byref(info))
+    n = int(info.n_leaves)
+    S = np.full(n, 0.5)
+    for prm, refused in [(_lib.RemeshParams(1e300, 0.0, n), 0),  # nothing is a candidate
+                         (_lib.RemeshParams(0.3, 0.0, n + 6), None)]:  # every candidate refused at the cap
+        st = _lib.RemeshStats()
+        h2 = ctypes.c_void_p(1)
+        assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
+                                      ctypes.byref(st)) == 0
+        assert not h2.value and st.refined == 0 and st.coarsened == 0 and st.n_leaves == n
+        assert st.refused > 0 if refused is None else st.refused == refused
+    L.amr_mesh_destroy(h)
+
+
 @pytest.mark.parametrize("seed,cap_extra,levels", [(5, 10 ** 6, 2), (6, 40, 2), (7, 10 ** 6, 3), (8, 90, 3)])
 def test_host_remesh_decisions_match_oracle(seed, cap_extra, levels):
     """Same indicator in, same leaf set and counters out: the library's local
@@ -179,9 +215,7 @@ def test_host_remesh_decisions_match_oracle(seed, cap_extra, levels):
         h2 = ctypes.c_void_p()
         assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
                                       ctypes.byref(st)) == 0
-        L.amr_mesh_info(h2, ctypes.byref(info))
-        k2 = np.zeros((info.n_leaves, 4), dtype=np.int32)
-        L.amr_mesh_blocks(h2, k2.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+        k2 = _new_leaves(L, h, h2, st)
         m2, ost = m.remesh(0.3, 0.1 if rnd else 0.0, cap)
         assert sorted(map(tuple, k2)) == sorted(map(tuple, m2.keys))
         assert (st.refined, st.coarsened, st.refused) == tuple(int(v) for v in ost)
@@ -218,9 +252,7 @@ def test_host_coarsening_decisions_match_oracle(seed):
         h2 = ctypes.c_void_p()
         assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
                                       ctypes.byref(st)) == 0
-        L.amr_mesh_info(h2, ctypes.byref(info))
-        k2 = np.zeros((info.n_leaves, 4), dtype=np.int32)
-        L.amr_mesh_blocks(h2, k2.ctypes.data_as(ctypes.c_void_p), info.n_leaves)
+        k2 = _new_leaves(L, h, h2, st)
         m2, ost = m.remesh(rs, thr, 10 ** 6)
         assert st.coarsened > 0
         assert sorted(map(tuple, k2)) == sorted(map(tuple, m2.keys))
