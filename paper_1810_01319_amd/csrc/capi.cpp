@@ -1032,27 +1032,30 @@ amr_status amr_hydro_step_gravity_comoving(amr_mesh* h, double* U, const double*
       return mg_solve(P, n[0], n[1], n[2], dx, nullptr, U, four_pi_G, phi, ncycles, nu1, nu2, nullptr, work, st);
     });
   };
-  auto kick = [&](double a) {
+  // the kicks carry the expansion sources in the same pass: the first kick
+  // is followed by the first half of the sources, the last kick preceded by
+  // the second half (the solve between them reads only the density, which
+  // the sources leave alone)
+  double* half = nullptr;
+  auto kick = [&](double a, int exp) {
     const double scale = 1.0 / (a * a);
-    return timed(h, AMR_PHASE_POISSON, st,
-                 [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, scale, work, st); });
+    return timed(h, AMR_PHASE_POISSON, st, [&] {
+      return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, scale, work, st, exp, half, hubble);
+    });
   };
   hipError_t e = hipSuccess;
   if (!phi_current) e = solve();
-  if (e == hipSuccess) e = kick(a0);
-  double* half = nullptr;
   if (e == hipSuccess) {
     half = mg_half_dt(dt, work, n[0], n[1], n[2], st);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, half, hubble, st); });
+  if (e == hipSuccess) e = kick(a0, 1);
   if (e == hipSuccess) e = launch_scale_dt(P, dt, a_mid, st);
   if (e != hipSuccess) return hip_fail(e, "gravity");
   rc = run_step(h, U, P.dte, step_index, st);
   if (rc != AMR_OK) return rc;
-  e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, half, hubble, st); });
-  if (e == hipSuccess) e = solve();
-  if (e == hipSuccess) e = kick(a1);
+  e = solve();
+  if (e == hipSuccess) e = kick(a1, 2);
   return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
 }
 

@@ -14,6 +14,7 @@
 // energy below the pressure floor it is raised to it and counted.
 #include <hip/hip_runtime.h>
 
+#include "expansion_cell.hpp"
 #include "kernels.hpp"
 #include "ppm_core.hpp"
 
@@ -42,33 +43,17 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   const BlockInfo bi = P.blocks[s];
   const InstParams ip = P.inst[bi.inst];
   const double c = (0.5 * dtv[bi.inst]) * hubble;
-  const double g3 = 3.0 * ip.gm1;
-  const double fv = (1.0 - c) / (1.0 + c);
-  const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
   double* const B = U + int64_t(s) * P.nf * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
-  const double rho = B[0], mx = B[M3], my = B[2 * M3], mz = B[3 * M3], E = B[4 * M3];
-  const double ir = rcp_pos(rho);
-  const double u = mx * ir, v = my * ir, w = mz * ir;
-  const double ke = (0.5 * rho) * ((u * u + v * v) + w * w);
-  const double ie = E - ke;
-  double ie2 = ie * fe;
-  const bool fl = ie2 < ie && ip.gm1 * ie2 < ip.p_floor;
-  if (fl) ie2 = ip.p_floor * ip.inv_gm1;
-  B[M3] = mx * fv;
-  B[2 * M3] = my * fv;
-  B[3 * M3] = mz * fv;
-  B[4 * M3] = E + ((ie2 - ie) + ke * (fv * fv - 1.0));
-  unsigned long long nfl = fl ? 1ull : 0ull;
-  if (P.nf == kFieldsDE) {  // the dual-energy field: the same factor and floor rule
-    const double ge = B[5 * M3];
-    double ge2 = ge * fe;
-    if (ge2 < ge && ip.gm1 * ge2 < ip.p_floor) {
-      ge2 = ip.p_floor * ip.inv_gm1;
-      nfl++;
-    }
-    B[5 * M3] = ge2;
-  }
-  if (nfl) atomicAdd(P.counters, nfl);
+  const bool de = P.nf == kFieldsDE;
+  const double rho = B[0];
+  double mx = B[M3], my = B[2 * M3], mz = B[3 * M3], E = B[4 * M3], ge = de ? B[5 * M3] : 0.0;
+  const unsigned nfl = expansion_cell(ip, c, de, rho, mx, my, mz, E, ge);
+  B[M3] = mx;
+  B[2 * M3] = my;
+  B[3 * M3] = mz;
+  B[4 * M3] = E;
+  if (de) B[5 * M3] = ge;
+  if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
 template <int N>

@@ -20,6 +20,8 @@
 
 #include "poisson.hpp"
 
+#include "expansion_cell.hpp"
+
 namespace amr {
 
 namespace {
@@ -215,9 +217,13 @@ __global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, 
 // Half kick of the active cells with g = -grad(phi) (central differences of
 // level 0's phi, which holds a mean-free potential): momentum + hdt rho g,
 // energy + (ke' - ke), hdt = (dt/2) scale (scale 1/a^2 in comoving steps).
-template <int N>
+// EXP 1: the expansion sources over dt/2 follow the kick in the same pass
+// (c = (halfdt/2) H, halfdt = dt/2 on the device); EXP 2: they precede it.
+// Each cell's arithmetic is that of the separate kick and expansion kernels.
+template <int N, int EXP>
 __global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, DevPlan P,
-                                               const double* __restrict__ dtv, double scale) {
+                                               const double* __restrict__ dtv, double scale,
+                                               const double* __restrict__ halfdt, double hubble) {
   constexpr int N3 = N * N * N;
   constexpr int M = N + 2 * kGhost;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -240,23 +246,39 @@ __global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, De
   }
   double* B = U + int64_t(s) * P.nf * M3 + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost);
   const double hdt = (0.5 * dtv[0]) * scale;
+  const bool de = P.nf == kFieldsDE;
   const double rho = B[0];
-  const double ir = 1.0 / rho;
-  double mo[3], u[3], u2[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ax++) {
-    mo[ax] = B[(1 + ax) * M3];
-    u[ax] = mo[ax] * ir;
+  double mo[3] = {B[M3], B[2 * M3], B[3 * M3]};
+  double E = B[4 * M3];
+  double ge = EXP != 0 && de ? B[5 * M3] : 0.0;
+  unsigned nfl = 0;
+  InstParams ip;
+  double cexp = 0.0;
+  if (EXP != 0) {
+    ip = P.inst[bi.inst];
+    cexp = (0.5 * halfdt[0]) * hubble;
   }
-  const double ke = (0.5 * rho) * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+  if (EXP == 2) nfl += expansion_cell(ip, cexp, de, rho, mo[0], mo[1], mo[2], E, ge);
+  {
+    const double ir = 1.0 / rho;
+    double u[3], u2[3];
 #pragma unroll
-  for (int ax = 0; ax < 3; ax++) {
-    mo[ax] = mo[ax] + hdt * (rho * gv[ax]);
-    u2[ax] = mo[ax] * ir;
-    B[(1 + ax) * M3] = mo[ax];
+    for (int ax = 0; ax < 3; ax++) u[ax] = mo[ax] * ir;
+    const double ke = (0.5 * rho) * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+      mo[ax] = mo[ax] + hdt * (rho * gv[ax]);
+      u2[ax] = mo[ax] * ir;
+    }
+    const double ke2 = (0.5 * rho) * ((u2[0] * u2[0] + u2[1] * u2[1]) + u2[2] * u2[2]);
+    E = E + (ke2 - ke);
   }
-  const double ke2 = (0.5 * rho) * ((u2[0] * u2[0] + u2[1] * u2[1]) + u2[2] * u2[2]);
-  B[4 * M3] = B[4 * M3] + (ke2 - ke);
+  if (EXP == 1) nfl += expansion_cell(ip, cexp, de, rho, mo[0], mo[1], mo[2], E, ge);
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) B[(1 + ax) * M3] = mo[ax];
+  B[4 * M3] = E;
+  if (EXP != 0 && de) B[5 * M3] = ge;
+  if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
 // Block layout from level 0, minus the mean held at *mean.
@@ -378,8 +400,19 @@ void gather_n(const DevPlan& P, const double* fb, const double* U, double fpg, c
 
 }  // namespace
 
+namespace {
+template <int N>
+void kick_n(int exp, dim3 g, dim3 b, hipStream_t st, double* U, const Lvl& L0, const DevPlan& P, const double* dt,
+            double scale, const double* halfdt, double hubble) {
+  if (exp == 1) hipLaunchKernelGGL((mg_kick<N, 1>), g, b, 0, st, U, L0, P, dt, scale, halfdt, hubble);
+  else if (exp == 2) hipLaunchKernelGGL((mg_kick<N, 2>), g, b, 0, st, U, L0, P, dt, scale, halfdt, hubble);
+  else hipLaunchKernelGGL((mg_kick<N, 0>), g, b, 0, st, U, L0, P, dt, scale, halfdt, hubble);
+}
+}  // namespace
+
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
-                   const double* dt, double scale, void* work, hipStream_t st) {
+                   const double* dt, double scale, void* work, hipStream_t st, int exp, const double* halfdt,
+                   double hubble) {
   Lvl Ls[kMgMaxLevels];
   int nl;
   double* parts;
@@ -387,9 +420,9 @@ hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U
   gather_n<2>(P, nullptr, nullptr, 0.0, phi_blocks, Ls[0], st);
   const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
   const dim3 g(grid_for(nb, 256)), b(256);
-  if (P.N == 8) hipLaunchKernelGGL(mg_kick<8>, g, b, 0, st, U, Ls[0], P, dt, scale);
-  else if (P.N == 16) hipLaunchKernelGGL(mg_kick<16>, g, b, 0, st, U, Ls[0], P, dt, scale);
-  else hipLaunchKernelGGL(mg_kick<32>, g, b, 0, st, U, Ls[0], P, dt, scale);
+  if (P.N == 8) kick_n<8>(exp, g, b, st, U, Ls[0], P, dt, scale, halfdt, hubble);
+  else if (P.N == 16) kick_n<16>(exp, g, b, st, U, Ls[0], P, dt, scale, halfdt, hubble);
+  else kick_n<32>(exp, g, b, st, U, Ls[0], P, dt, scale, halfdt, hubble);
   return hipGetLastError();
 }
 

@@ -28,8 +28,12 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
 // Half kick of U's active cells with g = -grad(phi) of the mean-free
 // potential phi_blocks (block layout), dt from the device: momentum
 // + (dt/2) rho g, energy + the kinetic-energy change.
+// exp 0: the kick alone; 1: the kick, then the comoving expansion sources
+// over *halfdt with expansion rate hubble, in the same pass; 2: the sources,
+// then the kick.
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
-                   const double* dt, double scale, void* work, hipStream_t st);
+                   const double* dt, double scale, void* work, hipStream_t st, int exp = 0,
+                   const double* halfdt = nullptr, double hubble = 0.0);
 // Enqueues dt/2 (exact) into a slot of the workspace's scratch and returns
 // the slot's device address.
 double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStream_t st);
