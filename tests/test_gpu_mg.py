@@ -106,3 +106,33 @@ def test_mg_refusals():
     bm = Mesh.batch([I.MeshSpec(root=(2, 2, 2), block_cells=8).kwargs()] * 2)
     with pytest.raises(AmrError):
         bm.poisson_workspace()
+
+
+def test_mg_full_size_eigenmode():
+    """The benchmark's grid (16^3 roots x 32^3 cells = 512^3, 8 levels, the
+    XCD row bands in use at every level with ny >= 8): a discrete eigenmode of
+    the 7-point operator, built on the GPU in the block layout, is solved to
+    round-off, and the mean stays zero."""
+    spec = I.MeshSpec(root=(16, 16, 16), block_cells=32)
+    m = Mesh(**spec.kwargs())
+    N, h = 32, spec.dx(0)
+    say(f"mg full size 512^3, {m.nleaf} leaves")
+    keys = torch.as_tensor(np.asarray(m.keys), device=m.device)
+    r = (torch.arange(N, device=m.device, dtype=torch.float64) + 0.5)
+    x = ((keys[:, 1, None] * N).double() + r[None, :]) * h  # [leaf, N] along x
+    y = ((keys[:, 2, None] * N).double() + r[None, :]) * h
+    z = ((keys[:, 3, None] * N).double() + r[None, :]) * h
+    kx, ky, kz = 2 * np.pi, 4 * np.pi, 6 * np.pi
+    s = (torch.cos(kz * z)[:, :, None, None] * torch.sin(ky * y)[:, None, :, None]
+         * torch.sin(kx * x)[:, None, None, :]).contiguous()
+    lam = -(4.0 / h ** 2) * (np.sin(0.5 * kx * h) ** 2 + np.sin(0.5 * ky * h) ** 2 + np.sin(0.5 * kz * h) ** 2)
+    f = (lam * s).contiguous()
+    phi = torch.zeros_like(s)
+    res = m.poisson_solve(f, phi, 20)
+    torch.cuda.synchronize()
+    err = float((phi - s).abs().max())
+    rr = res.cpu().numpy()
+    say(f"mg full size: max |phi - s| {err:.2e}, residual {rr[0]:.3e} -> {rr[-1]:.3e}, mean {float(phi.mean()):.1e}")
+    assert err < 1e-10
+    assert rr[-1] < 1e-9 * rr[0]
+    assert abs(float(phi.mean())) < 1e-13
