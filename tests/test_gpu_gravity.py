@@ -149,3 +149,33 @@ def test_comoving_gravity_refusals():
             gm.step_gravity_comoving(U, dt, 0, a0, am, a1, H, g, phi, False)
     torch.cuda.synchronize()
     assert torch.equal(U, before)
+
+
+def test_gravity_full_size_step_matches_oracle():
+    """The benchmark's self-gravity workload at its full size (8^3 roots of
+    32^3 cells = 256^3, 4 pi G rho0 = 60, 2 V(2,2) cycles per solve): the
+    first step (potential solved first), then a comoving step from a = 1,
+    against the oracle on every cell, to the bar above."""
+    spec = I.MeshSpec(root=(8, 8, 8), block_cells=32, gamma=GAMMA)
+    say("gravity full size 256^3")
+    om, gm, perm = pair(spec)
+    U = load(om, gm, perm, state(spec, gm.keys, 1))
+    phi_o = np.zeros((256, 256, 256))
+    phi_g = torch.zeros((gm.nleaf, 32, 32, 32), dtype=torch.float64, device="cuda")
+    work = gm.poisson_workspace()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gm.step_gravity(U, dt, 0, 60.0, phi_g, False, ncycles=2, work=work)
+    dto = om.step_gravity(0, 60.0, phi_o, False, ncycles=2)
+    dtg = float(dt.cpu()[0])
+    assert abs(dtg - dto) <= 1e-12 * dto, (dtg, dto)
+    err, perr, bw = compare(gm, om, U, perm, phi_g, phi_o, False)
+    say(f"full size gravity step: state rel err {err:.2e} (bitwise {bw:.4f}), phi rel err {perr:.2e}")
+    assert err <= TOL and perr <= TOL
+    d, tm = 0.5 * dtg, 1.0 + 0.25 * dtg
+    args = (1.0, tm ** (2 / 3), (1.0 + d) ** (2 / 3), 2.0 / (3.0 * tm), 60.0)
+    dt.fill_(d)
+    gm.step_gravity_comoving(U, dt, 1, *args, phi_g, True, ncycles=2, work=work)
+    om.step_gravity_comoving(1, d, *args, phi_o, True, ncycles=2)
+    err, perr, bw = compare(gm, om, U, perm, phi_g, phi_o, False)
+    say(f"full size comoving gravity step: state rel err {err:.2e} (bitwise {bw:.4f}), phi rel err {perr:.2e}")
+    assert err <= TOL and perr <= TOL
