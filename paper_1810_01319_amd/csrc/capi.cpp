@@ -991,19 +991,20 @@ amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t st
       return mg_solve(P, n[0], n[1], n[2], dx, nullptr, U, four_pi_G, phi, ncycles, nu1, nu2, nullptr, work, st);
     });
   };
-  auto kick = [&] {
-    return timed(h, AMR_PHASE_POISSON, st,
-                 [&] { return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, 1.0, work, st); });
+  auto kick = [&](bool after_solve) {
+    return timed(h, AMR_PHASE_POISSON, st, [&] {
+      return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, 1.0, work, st, 0, nullptr, 0.0, after_solve);
+    });
   };
   hipError_t e = hipSuccess;
   if (!phi_current) e = solve();
   if (e == hipSuccess) e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dt, h->cfg, st); });
-  if (e == hipSuccess) e = kick();
+  if (e == hipSuccess) e = kick(!phi_current);
   if (e != hipSuccess) return hip_fail(e, "gravity");
   rc = run_step(h, U, dt, step_index, st);
   if (rc != AMR_OK) return rc;
   e = solve();
-  if (e == hipSuccess) e = kick();
+  if (e == hipSuccess) e = kick(true);
   return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
 }
 
@@ -1037,10 +1038,10 @@ amr_status amr_hydro_step_gravity_comoving(amr_mesh* h, double* U, const double*
   // the second half (the solve between them reads only the density, which
   // the sources leave alone)
   double* half = nullptr;
-  auto kick = [&](double a, int exp) {
+  auto kick = [&](double a, int exp, bool after_solve) {
     const double scale = 1.0 / (a * a);
     return timed(h, AMR_PHASE_POISSON, st, [&] {
-      return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, scale, work, st, exp, half, hubble);
+      return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, scale, work, st, exp, half, hubble, after_solve);
     });
   };
   hipError_t e = hipSuccess;
@@ -1049,13 +1050,13 @@ amr_status amr_hydro_step_gravity_comoving(amr_mesh* h, double* U, const double*
     half = mg_half_dt(dt, work, n[0], n[1], n[2], st);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = kick(a0, 1);
+  if (e == hipSuccess) e = kick(a0, 1, !phi_current);
   if (e == hipSuccess) e = launch_scale_dt(P, dt, a_mid, st);
   if (e != hipSuccess) return hip_fail(e, "gravity");
   rc = run_step(h, U, P.dte, step_index, st);
   if (rc != AMR_OK) return rc;
   e = solve();
-  if (e == hipSuccess) e = kick(a1, 2);
+  if (e == hipSuccess) e = kick(a1, 2, true);
   return e == hipSuccess ? AMR_OK : hip_fail(e, "gravity");
 }
 

@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(256) mg_kick(double* __restrict__ U, Lvl L, De
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
-// Block layout from level 0, minus the mean held at *mean.
+// Block layout from level 0, minus the mean held at *mean; level 0 keeps the
+// same mean-free values, so a kick right after the solve needs no gather.
 template <int N>
 __global__ void __launch_bounds__(256) mg_scatter(Lvl L, DevPlan P, const double* __restrict__ mean,
                                                   double* __restrict__ pb) {
@@ -292,7 +293,9 @@ __global__ void __launch_bounds__(256) mg_scatter(Lvl L, DevPlan P, const double
   const int q = int(t - int64_t(s) * N3);
   const BlockInfo bi = P.blocks[s];
   const int64_t g = lidx(L, bi.i * N + q % N, bi.j * N + (q / N) % N, bi.k * N + q / (N * N));
-  pb[t] = L.phi[g] - *mean;
+  const double v = L.phi[g] - *mean;
+  pb[t] = v;
+  L.phi[g] = v;
 }
 
 // dst[0] = factor src[0] (one lane).
@@ -412,12 +415,12 @@ void kick_n(int exp, dim3 g, dim3 b, hipStream_t st, double* U, const Lvl& L0, c
 
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
                    const double* dt, double scale, void* work, hipStream_t st, int exp, const double* halfdt,
-                   double hubble) {
+                   double hubble, bool level0_current) {
   Lvl Ls[kMgMaxLevels];
   int nl;
   double* parts;
   levels_in(work, nx, ny, nz, h, Ls, nl, parts);
-  gather_n<2>(P, nullptr, nullptr, 0.0, phi_blocks, Ls[0], st);
+  if (!level0_current) gather_n<2>(P, nullptr, nullptr, 0.0, phi_blocks, Ls[0], st);
   const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
   const dim3 g(grid_for(nb, 256)), b(256);
   if (P.N == 8) kick_n<8>(exp, g, b, st, U, Ls[0], P, dt, scale, halfdt, hubble);

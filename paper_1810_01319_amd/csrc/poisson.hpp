@@ -30,10 +30,12 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
 // + (dt/2) rho g, energy + the kinetic-energy change.
 // exp 0: the kick alone; 1: the kick, then the comoving expansion sources
 // over *halfdt with expansion rate hubble, in the same pass; 2: the sources,
-// then the kick.
+// then the kick.  level0_current: the workspace's finest level still holds
+// phi_blocks' values (the last operation on it was the mg_solve that wrote
+// them), so the gather is skipped.
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
                    const double* dt, double scale, void* work, hipStream_t st, int exp = 0,
-                   const double* halfdt = nullptr, double hubble = 0.0);
+                   const double* halfdt = nullptr, double hubble = 0.0, bool level0_current = false);
 // Enqueues dt/2 (exact) into a slot of the workspace's scratch and returns
 // the slot's device address.
 double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStream_t st);
