@@ -497,7 +497,8 @@ static double cfl_min(const orc_mesh* m) {
                                    K.de ? B[cell(M, 5, a, b, c)] : 0.0);
           p = p < K.p_floor ? K.p_floor : p;
           double cs = sqrt((K.gamma * p) * ir);
-          double vm = dmax(dmax(fabs(u), fabs(v)), fabs(w));
+          double vm = (g_debug & ORC_DEBUG_CFL_SUM) ? (fabs(u) + fabs(v)) + fabs(w)
+                                                    : dmax(dmax(fabs(u), fabs(v)), fabs(w));
           double t = dx / (vm + cs);
           best = t < best ? t : best;
         }
@@ -618,6 +619,7 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
     WR[3] = Im(K, &par[3], s0);
   }
   /* positivity floors on the edge states */
+  if (g_debug & ORC_DEBUG_EDGE_NO_FLOOR) return;
   WL[0] = WL[0] < K->rho_floor ? K->rho_floor : WL[0];
   WL[4] = WL[4] < K->p_floor ? K->p_floor : WL[4];
   WR[0] = WR[0] < K->rho_floor ? K->rho_floor : WR[0];
@@ -800,18 +802,29 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
             Un[5] = (g_debug & ORC_DEBUG_DE_PDV_SIGN) ? Un[5] + nu * work : Un[5] - nu * work;
           }
           /* post-update floors (counted: they break conservation) */
-          if (Un[0] < K->rho_floor) { Un[0] = K->rho_floor; nfl++; }
+          if (Un[0] < K->rho_floor) {
+            if (g_debug & ORC_DEBUG_FLOOR_KEEP_VEL)
+              for (int d = 1; d <= 3; d++) Un[d] = Un[d] * (K->rho_floor / Un[0]);
+            Un[0] = K->rho_floor;
+            if (!(g_debug & ORC_DEBUG_FLOOR_NO_COUNT)) nfl++;
+          }
           double ir = 1.0 / Un[0];
           double u = Un[1] * ir, v = Un[2] * ir, w = Un[3] * ir;
           double ke = (0.5 * Un[0]) * ((u * u + v * v) + w * w);
           double p = K->gm1 * (Un[4] - ke);
-          if (p < K->p_floor) { Un[4] = K->p_floor * K->inv_gm1 + ke; nfl++; }
+          if (p < K->p_floor) {
+            Un[4] = (g_debug & ORC_DEBUG_FLOOR_E_NO_KE) ? K->p_floor * K->inv_gm1 : K->p_floor * K->inv_gm1 + ke;
+            nfl++;
+          }
           if (K->de) {
             /* resynchronise rho e from the total energy where E - ke > eta2 E,
              * then its own floor (counted) */
             const double ie = Un[4] - ke;
             if (ie > K->eta2 * Un[4]) Un[5] = ie;
-            if (K->gm1 * Un[5] < K->p_floor) { Un[5] = K->p_floor * K->inv_gm1; nfl++; }
+            if (K->gm1 * Un[5] < K->p_floor) {
+              Un[5] = (g_debug & ORC_DEBUG_DE_FLOOR_NO_IG) ? K->p_floor : K->p_floor * K->inv_gm1;
+              nfl++;
+            }
           }
           pos[dir] = j;
           for (int vv = 0; vv < nv; vv++) B[cell(M, fmap[vv], pos[0], pos[1], pos[2])] = Un[vv];
@@ -949,7 +962,7 @@ static void expansion(orc_mesh* m, double dt, double hubble) {
           const double ie = *E - ke;
           double ie2 = ie * fe;
           if (ie2 < ie && K.gm1 * ie2 < K.p_floor) {
-            ie2 = K.p_floor * K.inv_gm1;
+            ie2 = (g_debug & ORC_DEBUG_EXP_FLOOR_NO_IG) ? K.p_floor : K.p_floor * K.inv_gm1;
             nfl++;
           }
           *mx = *mx * fv;

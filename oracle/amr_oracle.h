@@ -120,6 +120,13 @@ int orc_step_gravity_comoving(orc_mesh* m, int64_t step_index, double dt, double
 #define ORC_DEBUG_DE_ETA1_FLIP 8  /* pressure source selection reversed */
 #define ORC_DEBUG_GRAVITY_SIGN 16 /* g = +grad(phi) */
 #define ORC_DEBUG_GRAVITY_NO_A 32 /* comoving kicks without the 1/a^2 */
+#define ORC_DEBUG_FLOOR_E_NO_KE 64     /* pressure floor resets E to p_floor/(gamma-1) alone */
+#define ORC_DEBUG_FLOOR_KEEP_VEL 128   /* density floor keeps the velocity (momenta rescaled) */
+#define ORC_DEBUG_DE_FLOOR_NO_IG 256   /* rho e floor set to p_floor, not p_floor/(gamma-1) */
+#define ORC_DEBUG_EDGE_NO_FLOOR 512    /* traced edge states left unfloored */
+#define ORC_DEBUG_CFL_SUM 1024         /* CFL signal speed |u|+|v|+|w|+c instead of max_d |u_d|+c */
+#define ORC_DEBUG_EXP_FLOOR_NO_IG 2048 /* expansion raises E - ke to p_floor, not p_floor/(gamma-1) */
+#define ORC_DEBUG_FLOOR_NO_COUNT 4096  /* density floor resets not counted */
 void orc_set_debug(int flags);
 void orc_riemann(const double* gas /* gamma,p_floor */, int iters,
                  const double* WL /* rho,u,v,w,p */, const double* WR,

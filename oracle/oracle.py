@@ -302,6 +302,13 @@ DEBUG_DE_ENTHALPY = 4
 DEBUG_DE_ETA1_FLIP = 8
 DEBUG_GRAVITY_SIGN = 16
 DEBUG_GRAVITY_NO_A = 32
+DEBUG_FLOOR_E_NO_KE = 64
+DEBUG_FLOOR_KEEP_VEL = 128
+DEBUG_DE_FLOOR_NO_IG = 256
+DEBUG_EDGE_NO_FLOOR = 512
+DEBUG_CFL_SUM = 1024
+DEBUG_EXP_FLOOR_NO_IG = 2048
+DEBUG_FLOOR_NO_COUNT = 4096
 
 
 def num_threads() -> int:

@@ -45,7 +45,9 @@ def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope
     step index that is a positive multiple of `interval`.  The steps between
     two remeshes run as one multi-step call; after a remesh that changed
     nothing (which refreshed the state's ghosts) that call skips its first
-    refresh.  Returns (mesh, U, dt list (device tensors of n_instances
+    refresh, unless `on_remesh` is given: the callback may write U's
+    active cells (sources, re-seeding), so its ghosts are refreshed again.
+    Returns (mesh, U, dt list (device tensors of n_instances
     doubles, one per step), remesh stats list)."""
     dts, stats = [], []
     k, end = start, start + steps
@@ -60,7 +62,7 @@ def run(mesh: Mesh, U: torch.Tensor, steps: int, refine_slope=0.3, coarsen_slope
                     pool.swap()
             else:
                 new, Un, st = mesh.remesh(U, refine_slope, coarsen_slope, cap)
-            fresh = new is mesh
+            fresh = new is mesh and on_remesh is None
             mesh, U = new, Un
             stats.append(st)
             if on_remesh is not None:
