@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the AMR hydro step on one MI355X.
 
-Workload: the static two-level Sedov blast on an 8^3 array of octrees of
-32^3-cell blocks (624 leaves, 20.4M cells), FP64, periodic, gamma = 5/3,
-refined around the domain centre.  One step = CFL reduction + two-phase ghost
-refresh + three PPM sweeps + reflux over every leaf; the steps run through the
-multi-step entry, which takes each step's CFL reduction inside its
-predecessor (last sweep and refluxed cells).  Inputs are generated on
-the host, uploaded once, and resident in HBM for the timed region.
+Headline workload (the default): the large adaptive blast array, one GPU's
+share of the paper's weak-scaling shape -- 24^3 root octrees of 32^3-cell
+blocks (453M cells at start), one Sedov blast per octree at a seeded offset,
+up to 3 levels by density slope (refine > 0.3, coarsen < 0.1), remesh every
+4 steps, gamma 5/3, FP64, periodic.  One step = CFL reduction + two-phase
+ghost refresh + three PPM sweeps + reflux over every leaf; the remesh
+(indicator, host decisions, migration) is inside the timed region.  Inputs
+are generated on the host, uploaded once and resident in HBM before timing.
 
 Prints one JSON line: cell-updates/s, the dominant kernel's roofline (live
-HIP-event timing of every kernel over the timed region) and the FP64 CPU
-oracle's throughput on a bounded sample on the host cores.
+HIP-event timing of every kernel over the timed region, HBM and FP64
+fractions, the higher one binding), the FP64 CPU oracle on a bounded tile
+of the same workload, and sub-objects for the other workloads: the static
+two-level Sedov mesh, the batched uneven meshes, the adjoint, tracers,
+comoving and dual-energy steps, mg0 and self-gravity.
 """
 from __future__ import annotations
 
@@ -85,6 +89,68 @@ def workload(name):
         spec = I.sod_spec()
         return spec, I.sod_state, "sod-uniform: 4^3 x 16^3 cells, outflow, gamma 1.4"
     raise SystemExit(f"unknown workload {name}")
+
+
+def sweep_roofline(prof, step_leaves, N, nf, launch, workload_name, iters=5):
+    """Roofline of the three sweep kernels over a timed region.
+
+    step_leaves: (step index, leaf count) of every timed step; a sweep's
+    pencils per leaf depend on its place in that step's order (x, y, z on
+    even steps, z, y, x on odd ones).  Per launch: algorithmic bytes (read
+    the pencil's M cells and write its N cells, 5 fields of 8 B) and
+    algorithmic flops (the cost model's count per pencil), divided by the
+    kernel's mean launch time from the library's HIP events.  Returns
+    (per-axis table, dominant axis)."""
+    from paper_1810_01319_amd import costs
+
+    pen = costs.sweep_pencils_per_block(N)
+    fpp = costs.sweep_flops_per_pencil(N, iters)
+    bpp = costs.sweep_bytes_per_pencil(N)
+    axes = ("x", "y", "z")
+    per_axis = {}
+    for a in range(3):
+        pencils = 0
+        for k, leaves in step_leaves:
+            order = (0, 1, 2) if k % 2 == 0 else (2, 1, 0)
+            pencils += leaves * (pen["first"], pen["second"], pen["third"])[order.index(a)]
+        ms, n = prof["sweep_" + axes[a]]
+        sec = ms / n * 1e-3
+        flops = fpp * pencils / n
+        byts = bpp * pencils / n
+        kname = ("sweep_staged" if launch["sweep_mode"][a] == 1 else "sweep_kernel") + f"<{N},{a},{nf}>"
+        per_axis[axes[a]] = {"kernel": kname, "avg_launch_ms": ms / n, "launches": n,
+                             "flops_per_launch": flops, "TFLOP/s": flops / sec / 1e12,
+                             "fp64_frac": flops / sec / 1e12 / PEAK_FP64_TFLOPS,
+                             "algorithmic_bytes_per_launch": byts, "GB/s": byts / sec / 1e9,
+                             "hbm_frac": byts / sec / 1e9 / PEAK_HBM_GBS}
+    dom = max(per_axis, key=lambda a: per_axis[a]["avg_launch_ms"])
+    return per_axis, dom
+
+
+def roofline_object(d: dict, workload_name: str) -> dict:
+    """The dominant kernel's roofline: its algorithmic HBM rate and its
+    algorithmic FP64 rate against the published peaks; the binding roof is
+    the one with the higher fraction.  `traffic` is the committed rocprofv3
+    FETCH_SIZE + WRITE_SIZE per launch (scaled by a plain copy's reading),
+    or None once the kernel sources have changed since it was taken."""
+    traffic = measured_traffic(d["kernel"], workload_name)
+    hbm = {"bound": "hbm", "achieved": d["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["hbm_frac"]}
+    alu = {"bound": "alu", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+           "frac": d["fp64_frac"]}
+    top, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
+    out = dict(top)
+    out.update({"traffic": traffic, "kernel": d["kernel"], "avg_launch_ms": d["avg_launch_ms"],
+                "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                "flops_per_launch": d["flops_per_launch"],
+                "other_roof": other})
+    if traffic is not None:
+        out["traffic_over_algorithmic"] = traffic / d["algorithmic_bytes_per_launch"]
+    valu = committed_counters(d["kernel"], workload_name, "valu")
+    if valu:
+        out["valu_busy"] = float(valu["valu_busy"])
+        out["valu_issue_frac"] = (float(valu["valu_insts_per_launch"]) * 4
+                                  / (d["avg_launch_ms"] * 1e-3 * 1024 * 2.4e9))
+    return out
 
 
 def cpu_baseline(spec, act_fn, min_seconds, max_steps=200):
@@ -552,25 +618,29 @@ def step_bytes_per_block(N: int) -> int:
     return costs.refresh_bytes_per_block(N) + costs.sweep_bytes_per_block_step(N)
 
 
-def cpu_baseline_adaptive(spec_tile, steps: int = 9):
+def cpu_baseline_adaptive(spec_tile, min_seconds: float):
     """The oracle on a 4^3-octree tile of the adaptive workload (same block
-    size, levels, thresholds and interval; remesh before steps 4 and 8)."""
+    size, levels, thresholds and interval, remesh before every fourth step),
+    whole steps until at least `min_seconds` have passed."""
     from oracle import oracle as O
     from paper_1810_01319_amd import inputs as I
 
     m = O.OracleMesh(**spec_tile.kwargs())
     m.set_active(I.blasts_state(spec_tile, m.keys))
     cells = 0
+    k = remeshes = 0
     t0 = time.perf_counter()
-    for k in range(steps):
+    while k < 200 and (k < 9 or time.perf_counter() - t0 < min_seconds):
         if k > 0 and k % 4 == 0:
             m, _ = m.remesh(0.3, 0.1, 10 ** 9)
+            remeshes += 1
         m.step(k)
         cells += m.nleaf * spec_tile.block_cells ** 3
+        k += 1
     t = time.perf_counter() - t0
     return {"value": cells / t, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} steps incl. 2 remeshes of a 4^3-octree tile of the same workload "
-                      f"({cells} cell-updates), {t:.1f} s"}
+            "sample": f"{k} steps incl. {remeshes} remeshes of a 4^3-octree tile of the same workload "
+                      f"({m.nleaf} leaves at the end, {cells} cell-updates), {t:.1f} s"}
 
 
 def run_adaptive(args, spec, desc):
@@ -591,16 +661,16 @@ def run_adaptive(args, spec, desc):
     mesh, U, _, _ = adaptive.run(mesh, U, args.warmup, max_blocks=cap, pool=pool)
     torch.cuda.synchronize()
     leaves_start = int(mesh.nleaf)
-    cells_per_step = []
-    bytes_per_step = []
+    step_leaves = []
     stats = []
-    phases = {p: 0.0 for p in _lib.PHASES if not p.startswith("adj_")}
+    phases = {p: [0.0, 0] for p in _lib.PHASES if not p.startswith("adj_")}
 
     def collect(mm):
         prof = mm.profile_read()
         mm.profile(False)
         for p in phases:
-            phases[p] += prof[p][0]
+            phases[p][0] += prof[p][0]
+            phases[p][1] += prof[p][1]
 
     def total_mass(mm, uu):
         # sum over leaves of the cell volumes (root-cell units) times rho
@@ -638,46 +708,110 @@ def run_adaptive(args, spec, desc):
         n = min(end, (k // 4 + 1) * 4) - k
         m.steps(u, dts, n, k, ghosts_fresh=fresh)
         for j in range(n):
-            cells_per_step.append(m.nleaf * N ** 3)
-            bytes_per_step.append(m.nleaf * step_bytes_per_block(N))
+            step_leaves.append((k + j, int(m.nleaf)))
             if (k + j - args.warmup) % 10 == 0:
                 print(f"[bench] step {k + j} leaves {m.nleaf}", file=sys.stderr, flush=True)
         k += n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     collect(m)
+    if m.floor_count() != 0:
+        print("warning: floors triggered", file=sys.stderr)
     mass1 = total_mass(m, u)
-    total = float(sum(cells_per_step))
+    total = float(sum(l for _, l in step_leaves)) * N ** 3
     hydro_s = wall - t_remesh
+    step_bytes = sum(l for _, l in step_leaves) * step_bytes_per_block(N)
+    prof = {p: (v[0], v[1]) for p, v in phases.items()}
+    per_axis, dom = sweep_roofline(prof, step_leaves, N, m.nf, m.get_launch(), "blasts", spec.riemann_iters)
     out = {
         "metric": METRIC, "value": total / wall, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "leaves_start": leaves_start, "leaves_end": int(m.nleaf),
-                   "max_blocks": cap, "parallelism": "single GPU"},
+                   "cells_end": int(m.nleaf) * N ** 3, "block_cells": N, "max_blocks": cap,
+                   "timed_steps": f"{args.warmup}..{end - 1}", "parallelism": "single GPU"},
+        "roofline": roofline_object(per_axis[dom], "blasts"),
+        "sweeps": per_axis,
         "without_remesh": total / hydro_s,
         "remesh_s": t_remesh,
         "remeshes": len(stats),
         "remesh_stats_last": stats[-1] if stats else None,
         "refused_total": int(sum(s["refused"] for s in stats)),
         "mass_relative_change": (mass1 - mass0) / mass0,
-        "phases_ms_per_step": {p: round(v / args.steps, 3) for p, v in phases.items()},
-        "step_hbm_algorithmic": {"GB/s": sum(bytes_per_step) / hydro_s / 1e9, "peak": PEAK_HBM_GBS,
-                                 "frac": sum(bytes_per_step) / hydro_s / 1e9 / PEAK_HBM_GBS},
+        "phases_ms_per_step": {p: round(v[0] / args.steps, 3) for p, v in phases.items() if v[1] > 0},
+        "step_hbm_algorithmic": {"bytes_per_cell_update": step_bytes_per_block(N) / N ** 3,
+                                 "GB/s": step_bytes / hydro_s / 1e9, "peak": PEAK_HBM_GBS,
+                                 "frac": step_bytes / hydro_s / 1e9 / PEAK_HBM_GBS},
+        "launch": m.get_launch(),
     }
-    if not args.no_cpu_baseline:
-        del u, pool
-        tile = I.blasts_spec(root=4, block_cells=spec.block_cells, levels=spec.max_level)
-        out["cpu_baseline"] = cpu_baseline_adaptive(tile)
+    del m, u, pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_static(args, spec, act_fn, desc, workload_name):
+    """A static mesh (the two-level Sedov blast by default): runs of steps
+    through the multi-step entry (each step's CFL reduction fused into its
+    predecessor; the same results as single steps)."""
+    import torch
+
+    from paper_1810_01319_amd import _lib, costs
+    from paper_1810_01319_amd.mesh import Mesh
+
+    mesh = Mesh(**spec.kwargs())
+    N = spec.block_cells
+    U = mesh.state_from_active(act_fn(spec, mesh.keys))
+    tuned = None
+    if args.tune:
+        from paper_1810_01319_amd import autotune
+
+        tuned = autotune.tune(mesh, U, use_cache=False)
+    steps, warmup = args.static_steps, 2
+    dts = torch.zeros(max(warmup, steps), mesh.n_instances, dtype=torch.float64, device=mesh.device)
+    mesh.steps(U, dts, warmup, 0)
+    torch.cuda.synchronize()
+    mesh.profile(True)
+    t0 = time.perf_counter()
+    mesh.steps(U, dts, steps, warmup)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = mesh.profile_read()
+    mesh.profile(False)
+    if mesh.floor_count() != 0:
+        print("warning: floors triggered", file=sys.stderr)
+    cells = mesh.nleaf * N ** 3
+    per_axis, dom = sweep_roofline(prof, [(k, mesh.nleaf) for k in range(warmup, warmup + steps)], N, mesh.nf,
+                                   mesh.get_launch(), workload_name, spec.riemann_iters)
+    refresh_bytes = mesh.nleaf * costs.refresh_bytes_per_block(N)
+    refresh_ms = (prof["refresh1"][0] + prof["refresh2"][0]) / steps
+    out = {
+        "workload": desc, "leaves": mesh.nleaf, "cells": cells, "steps": steps, "warmup": warmup,
+        "value": cells * steps / wall, "unit": "cell-updates/s", "ms_per_step": wall * 1e3 / steps,
+        "roofline": roofline_object(per_axis[dom], workload_name),
+        "sweeps": per_axis,
+        "phases_ms_per_step": {p: round(prof[p][0] / steps, 4) for p in _lib.PHASES
+                               if not p.startswith("adj_") and prof[p][1] > 0},
+        "launch": mesh.get_launch(),
+        "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
+                        "peak": PEAK_HBM_GBS},
+    }
+    if tuned is not None:
+        out["autotune"] = tuned
+    del U, mesh
+    torch.cuda.empty_cache()
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sedov")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before them (remeshes included)")
+    ap.add_argument("--workload", default="blasts", choices=["blasts", "sedov", "sod"],
+                    help="headline workload: the large adaptive blast array (default), the static "
+                         "two-level Sedov mesh or the uniform Sod tube")
+    ap.add_argument("--static-steps", type=int, default=50,
+                    help="steps of the static Sedov sub-measurement (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum length of the oracle's timed sample (whole steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -694,6 +828,8 @@ def main():
                     help="V-cycles of the mg0 Poisson measurement (0: skip)")
     ap.add_argument("--gravity-steps", type=int, default=10,
                     help="steps of the self-gravity measurement (0: skip)")
+    ap.add_argument("--subs-only", action="store_true",
+                    help="skip the headline workload (profiling runs of the sub-measurements)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -704,107 +840,33 @@ def main():
 
     import torch
 
-    from paper_1810_01319_amd import _lib, costs
-    from paper_1810_01319_amd.mesh import Mesh
-
-    spec, act_fn, desc = workload(args.workload)
-    if args.workload == "blasts":
-        print(json.dumps(run_adaptive(args, spec, desc)), flush=True)
-        return
-    mesh = Mesh(**spec.kwargs())
-    N = spec.block_cells
-    U = mesh.state_from_active(act_fn(spec, mesh.keys))
-    dt = torch.zeros(1, dtype=torch.float64, device=mesh.device)
     if args.calibrate_copy:
-        a = torch.ones(1 << 27, dtype=torch.float64, device=mesh.device)
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    tuned = None
-    if args.tune:
-        from paper_1810_01319_amd import autotune
 
-        tuned = autotune.tune(mesh, U, use_cache=False)
-    # runs of steps through the multi-step entry (each step's CFL reduction
-    # fused into its predecessor; the same results as single steps)
-    dts = torch.zeros(max(args.warmup, args.steps), mesh.n_instances, dtype=torch.float64, device=mesh.device)
-    if args.warmup:
-        mesh.steps(U, dts, args.warmup, 0)
-    torch.cuda.synchronize()
-
-    mesh.profile(True)
-    t0 = time.perf_counter()
-    mesh.steps(U, dts, args.steps, args.warmup)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = mesh.profile_read()
-    mesh.profile(False)
-    if mesh.floor_count() != 0:
-        print("warning: floors triggered", file=sys.stderr)
-
-    cells = mesh.nleaf * N ** 3
-    K = args.steps
-    value = cells * K / wall
-    # dominant kernel: the sweep axis with the most kernel time (FP64 ALU
-    # bound).  Its pencils per block depend on its place in the step's sweep
-    # order (x, y, z on even steps, z, y, x on odd ones).
-    launch = mesh.get_launch()
-    pen = costs.sweep_pencils_per_block(N)
-    fpp = costs.sweep_flops_per_pencil(N, spec.riemann_iters)
-    axes = ("x", "y", "z")
-    per_axis = {}
-    for a in range(3):
-        pencils = 0
-        for k in range(args.warmup, args.warmup + K):
-            order = (0, 1, 2) if k % 2 == 0 else (2, 1, 0)
-            pencils += (pen["first"], pen["second"], pen["third"])[order.index(a)]
-        ms, n = prof["sweep_" + axes[a]]
-        flops_launch = mesh.nleaf * fpp * pencils / K
-        kname = ("sweep_staged" if launch["sweep_mode"][a] == 1 else "sweep_kernel") + f"<{N},{a},{mesh.nf}>"
-        per_axis[axes[a]] = {"kernel": kname, "avg_launch_ms": ms / n, "flops_per_launch": flops_launch,
-                             "TFLOP/s": flops_launch / (ms / n * 1e-3) / 1e12}
-    dom = max(per_axis, key=lambda a: per_axis[a]["avg_launch_ms"])
-    achieved = per_axis[dom]["TFLOP/s"]
-    traffic = measured_traffic(per_axis[dom]["kernel"], args.workload)
-    valu = committed_counters(per_axis[dom]["kernel"], args.workload, "valu")
-    phases = {p: round(prof[p][0] / K, 4) for p in _lib.PHASES if not p.startswith("adj_")}
-    refresh_bytes = mesh.nleaf * costs.refresh_bytes_per_block(N)
-    refresh_ms = (prof["refresh1"][0] + prof["refresh2"][0]) / K
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": desc, "leaves": mesh.nleaf, "cells": cells, "block_cells": N,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": per_axis[dom]["kernel"], "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": traffic, "flops_per_launch": per_axis[dom]["flops_per_launch"],
-                     "avg_launch_ms": per_axis[dom]["avg_launch_ms"],
-                     # rocprofv3 VALUBusy and VALU instructions of the same kernel (committed
-                     # counter summary; None once the kernel sources change)
-                     "valu_busy": float(valu["valu_busy"]) if valu else None,
-                     "valu_issue_frac": (float(valu["valu_insts_per_launch"]) * 4
-                                         / (per_axis[dom]["avg_launch_ms"] * 1e-3 * 1024 * 2.4e9)) if valu else None},
-        "sweeps": per_axis,
-        "phases_ms_per_step": phases,
-        "launch": launch,
-        "refresh_hbm": {"GB/s": refresh_bytes / (refresh_ms * 1e-3) / 1e9 if refresh_ms > 0 else None,
-                        "peak": PEAK_HBM_GBS},
-    }
-    if tuned is not None:
-        out["autotune"] = tuned
+    spec, act_fn, desc = workload(args.workload)
+    out = {}
+    if not args.subs_only:
+        if args.workload == "blasts":
+            out = run_adaptive(args, spec, desc)
+        else:
+            st = run_static(argparse.Namespace(**{**vars(args), "static_steps": args.steps}), spec, act_fn, desc,
+                            args.workload)
+            out = {"metric": METRIC, "value": st["value"], "unit": "cell-updates/s", "n_gpus": 1,
+                   "steps": args.steps, "warmup": 2, "ms_per_step": st["ms_per_step"], "higher_is_better": True,
+                   "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                   "config": {"workload": desc, "leaves": st["leaves"], "cells": st["cells"],
+                              "block_cells": spec.block_cells, "parallelism": "single GPU"},
+                   "roofline": st["roofline"], "sweeps": st["sweeps"],
+                   "phases_ms_per_step": st["phases_ms_per_step"], "launch": st["launch"]}
+    if args.workload == "blasts" and args.static_steps > 0:
+        sspec, sfn, sdesc = workload("sedov")
+        out["static_amr"] = run_static(argparse.Namespace(**{**vars(args), "tune": False}), sspec, sfn, sdesc,
+                                       "sedov")
     if args.batch_steps > 0:
-        del U
         out["batched"] = batched_compare(args.batch_steps)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_compare(args.adjoint_steps)
@@ -818,8 +880,14 @@ def main():
         out["mg0"] = mg0_compare(args.mg_cycles)
     if args.gravity_steps > 0:
         out["self_gravity"] = gravity_compare(args.gravity_steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_seconds)
+    if not args.no_cpu_baseline and not args.subs_only:
+        if args.workload == "blasts":
+            from paper_1810_01319_amd import inputs as I
+
+            tile = I.blasts_spec(root=4, block_cells=spec.block_cells, levels=spec.max_level)
+            out["cpu_baseline"] = cpu_baseline_adaptive(tile, args.cpu_seconds)
+        else:
+            out["cpu_baseline"] = cpu_baseline(spec, act_fn, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
