@@ -431,6 +431,21 @@ amr_status amr_poisson_workspace_bytes(const amr_mesh* mesh, int64_t* bytes);
 amr_status amr_poisson_solve(amr_mesh* mesh, const double* f_dev, double* phi_dev, int32_t ncycles, int32_t nu1,
                              int32_t nu2, double* resid_dev, void* work_dev, void* stream);
 
+/* amr_poisson_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, fixed-memory serving
+ * loops, harnesses that forbid allocation): the solver's level arrays and
+ * reduction scratch live in a fixed 64 MiB device buffer of the library,
+ * one per GPU, held until the process ends.  Grids whose workspace
+ * (amr_poisson_workspace_bytes) exceeds 64 MiB are refused with
+ * AMR_E_CAPACITY; 128^3 cells (38.4 MB) fit.  The call allocates nothing.
+ * Every call on one GPU shares that GPU's buffer: calls that overlap on one
+ * GPU (concurrent streams or threads) race and must be serialised by the
+ * caller.  The buffer's contents are ignored on entry, as work_dev's are.
+ * Arguments, results and other errors as amr_poisson_solve; its results are
+ * bit for bit those of amr_poisson_solve. */
+amr_status amr_poisson_solve_static(amr_mesh* mesh, const double* f_dev, double* phi_dev, int32_t ncycles,
+                                    int32_t nu1, int32_t nu2, double* resid_dev, void* stream);
+
 /* Self-gravity step on the same meshes as amr_poisson_solve (the gravity
  * Method coupled to ppm, Sec. II-C; the self-gravitating gas of Sec. III):
  * kick-drift-kick.  phi solves lap(phi) = four_pi_G (rho - mean rho) with

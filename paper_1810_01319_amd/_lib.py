@@ -129,6 +129,7 @@ SIGNATURES = {
     "amr_arith_selftest": (_I32, [ctypes.c_uint64, _I64, _P, _P]),
     "amr_poisson_workspace_bytes": (_I32, [_P, ctypes.POINTER(_I64)]),
     "amr_poisson_solve": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P]),
+    "amr_poisson_solve_static": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "amr_hydro_step_gravity": (_I32, [_P, _P, _P, _I64, ctypes.c_double, _P, _I32, _I32, _I32, _I32, _P, _P]),
     "amr_hydro_step_gravity_comoving": (_I32, [_P, _P, _P, _I64] + [ctypes.c_double] * 5
                                         + [_P, _I32, _I32, _I32, _I32, _P, _P]),

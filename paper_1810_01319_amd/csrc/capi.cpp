@@ -970,6 +970,34 @@ amr_status amr_poisson_solve(amr_mesh* h, const double* f, double* phi, int32_t 
   return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
 }
 
+amr_status amr_poisson_solve_static(amr_mesh* h, const double* f, double* phi, int32_t ncycles, int32_t nu1,
+                                    int32_t nu2, double* resid, void* stream) {
+  if (!h) return fail(AMR_E_INVALID, "null mesh");
+  if (!h->ws) return fail(AMR_E_STATE, "no workspace uploaded");
+  if (!f || !phi) return fail(AMR_E_INVALID, "null argument");
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
+    return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
+  int n[3];
+  amr_status rc = poisson_grid(h, n);
+  if (rc != AMR_OK) return rc;
+  const int64_t need = mg_workspace_bytes(n[0], n[1], n[2]);
+  if (need > kMgStaticScratchBytes)
+    return fail(AMR_E_CAPACITY, "grid of " + std::to_string(n[0]) + "x" + std::to_string(n[1]) + "x" +
+                                    std::to_string(n[2]) + " needs a " + std::to_string(need) +
+                                    "-byte workspace, above the fixed buffer's " +
+                                    std::to_string(kMgStaticScratchBytes) + " bytes (use amr_poisson_solve)");
+  void* work = nullptr;
+  hipError_t e = mg_static_scratch(&work);
+  if (e != hipSuccess) return hip_fail(e, "poisson fixed workspace");
+  const Plan& p = h->plan;
+  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  e = timed(h, AMR_PHASE_POISSON, st, [&] {
+    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, nullptr, 0.0, phi, ncycles, nu1, nu2, resid, work, st);
+  });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
+}
+
 amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t step_index, double four_pi_G,
                                   double* phi, int32_t phi_current, int32_t ncycles, int32_t nu1, int32_t nu2,
                                   void* work, void* stream) {

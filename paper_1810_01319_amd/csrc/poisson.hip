@@ -18,6 +18,8 @@
 // Built with -ffp-contract=off: each formula rounds exactly as written.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "poisson.hpp"
 
 #include "expansion_cell.hpp"
@@ -365,6 +367,31 @@ int mg_levels(int nx, int ny, int nz, int sizes[][3]) {
     for (int a = 0; a < 3; a++) n[a] /= 2;
   }
   return nl;
+}
+
+// The solver's workspace for callers that cannot allocate device memory
+// (amr_poisson_solve_static).  Host code never names it: its name on the host
+// is a stand-in, not a device address; mg_static_scratch returns the address
+// of the current device's copy.
+static __device__ __align__(256) unsigned char scratch[kMgStaticScratchBytes];
+
+hipError_t mg_static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 int64_t mg_workspace_bytes(int nx, int ny, int nz) {

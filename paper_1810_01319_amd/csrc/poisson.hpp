@@ -11,6 +11,10 @@ namespace amr {
 constexpr int kMgMaxLevels = 24;
 constexpr int kMgCoarseMax = 4096;  // cells of the coarsest level (one workgroup's LDS)
 constexpr int kMgCoarseSweeps = 64;
+// Size of the fixed device buffer that serves as mg_solve's workspace in the
+// entry point that allocates nothing: enough for a 128^3 grid (its workspace
+// is 38.4 MB).
+constexpr int64_t kMgStaticScratchBytes = int64_t(64) << 20;
 
 // Level sizes (x, y, z) of a uniform nx x ny x nz grid: level l+1 halves
 // level l while every axis of level l is a multiple of 4.  Returns the count.
@@ -36,6 +40,10 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
 hipError_t mg_kick(const DevPlan& P, int nx, int ny, int nz, double h, double* U, const double* phi_blocks,
                    const double* dt, double scale, void* work, hipStream_t st, int exp = 0,
                    const double* halfdt = nullptr, double hubble = 0.0, bool level0_current = false);
+// Device address of the fixed workspace buffer (kMgStaticScratchBytes) on
+// the current device, looked up once per device.  Every call on one device
+// shares it, so calls that overlap on one device race.
+hipError_t mg_static_scratch(void** out);
 // Enqueues dt/2 (exact) into a slot of the workspace's scratch and returns
 // the slot's device address.
 double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStream_t st);

@@ -266,6 +266,21 @@ class Mesh:
                                       _ptr(r) if r is not None else None, _ptr(work), _stream()))
         return r
 
+    def poisson_solve_static(self, f: torch.Tensor, phi: torch.Tensor, ncycles: int, nu1: int = 2, nu2: int = 2,
+                             resid: torch.Tensor = None) -> None:
+        """poisson_solve with the library's fixed device buffer as workspace
+        (the entry point that allocates nothing; grids up to 128^3).  resid:
+        None or a caller-allocated float64 device tensor of ncycles + 1."""
+        shape = (self.nleaf, self.N, self.N, self.N)
+        for t in (f, phi):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device or tuple(t.shape) != shape:
+                raise ValueError("f and phi must be contiguous float64 [n_leaves, N, N, N] tensors on the device")
+        if resid is not None and (resid.dtype != torch.float64 or resid.numel() < ncycles + 1
+                                  or resid.device != self.device):
+            raise ValueError("resid must be a float64 device tensor of ncycles + 1 entries")
+        check(lib().amr_poisson_solve_static(self._h, _ptr(f), _ptr(phi), int(ncycles), int(nu1), int(nu2),
+                                             _ptr(resid) if resid is not None else None, _stream()))
+
     def step_gravity(self, U: torch.Tensor, dt: torch.Tensor, k: int, four_pi_G: float, phi: torch.Tensor,
                      phi_current: bool, ncycles: int = 2, nu1: int = 2, nu2: int = 2,
                      work: torch.Tensor = None) -> None:
