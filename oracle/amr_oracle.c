@@ -108,8 +108,51 @@ static consts_t mesh_consts(const orc_mesh* m) {
   return K;
 }
 
-static inline double dmax(double a, double b) { return a < b ? b : a; }
-static inline double dmin(double a, double b) { return a < b ? a : b; }
+/* ------------------------------------------------------------------ */
+/* Frozen-branch forward (the adjoint's reading: every discrete choice    */
+/* held at the forward run's)                                             */
+/* ------------------------------------------------------------------ */
+/* A step's discrete choices -- limiter selections, the signs of |x|, the
+ * parabola cases, the flattening switch and clamps, the wave-speed gates of
+ * the tracing, the Riemann solver's floors, side, wave type and sampling
+ * region, the prolongation's minmod, the positivity floors -- pass through
+ * BR().  With no tape BR() returns its argument.  A recording tape stores
+ * each choice in order; a replaying tape returns the stored choices instead,
+ * so a perturbed run evaluates the same smooth branch of the scheme as the
+ * recorded one and its central differences converge to the derivative the
+ * adjoint takes.  While a tape is attached the step's loops run serially,
+ * so the choices occur in one fixed order. */
+typedef struct {
+  unsigned char* b;
+  int64_t n, cap, pos;
+  int replay, overrun;
+} tape_t;
+static _Thread_local tape_t* t_tape = NULL;
+
+static int BR(int c) {
+  tape_t* t = t_tape;
+  if (!t) return c;
+  if (t->replay) {
+    if (t->pos < t->n) return t->b[t->pos++];
+    t->overrun = 1;
+    return c;
+  }
+  if (t->n == t->cap) {
+    int64_t cap = t->cap ? 2 * t->cap : (int64_t)1 << 20;
+    unsigned char* nb = (unsigned char*)realloc(t->b, (size_t)cap);
+    if (!nb) { t->overrun = 1; return c; }
+    t->b = nb;
+    t->cap = cap;
+  }
+  t->b[t->n++] = (unsigned char)(c != 0);
+  return c;
+}
+/* |x| with its sign choice recorded (the same value as fabs) */
+static inline double babs(double x) { return BR(signbit(x) != 0) ? -x : x; }
+#define SERIAL_IF_TAPED if (t_tape == NULL)
+
+static inline double dmax(double a, double b) { return BR(a < b) ? b : a; }
+static inline double dmin(double a, double b) { return BR(a < b) ? a : b; }
 
 /* ------------------------------------------------------------------ */
 /* Mesh: dense per-level node state, 2:1 balance                       */
@@ -390,13 +433,17 @@ static inline int is_active(int N, int a, int b, int c) {
 
 /* Value of the cell at level-l global index q inside the leaf that holds it
  * (q's block must be a leaf at level l). */
-static inline double leaf_value(const orc_mesh* m, int l, const int64_t q[3], int f) {
+static inline double leaf_value_of(const orc_mesh* m, const double* data, int nf, int l, const int64_t q[3],
+                                   int f) {
   int N = m->N;
   int bx = (int)(q[0] / N), by = (int)(q[1] / N), bz = (int)(q[2] / N);
   int32_t s = m->leaf_at[l][nidx(m, l, bx, by, bz)];
-  const double* B = block_ptr(m, s);
+  const double* B = data + s * (int64_t)nf * m->M * m->M * m->M;
   return B[cell(m->M, f, (int)(q[0] - (int64_t)bx * N) + G, (int)(q[1] - (int64_t)by * N) + G,
                 (int)(q[2] - (int64_t)bz * N) + G)];
+}
+static inline double leaf_value(const orc_mesh* m, int l, const int64_t q[3], int f) {
+  return leaf_value_of(m, m->U, m->nf, l, q, f);
 }
 
 /* Restrict (Sec. II-B): the coarse value is the mean of its 8 children,
@@ -408,16 +455,20 @@ static double restrict8(const double v[8]) {
 /* minmod(a,b): the smaller-magnitude argument if both have the same sign,
  * else 0 (ties take b). */
 static inline double minmod(double a, double b) {
-  return (a * b > 0.0) ? (fabs(a) < fabs(b) ? a : b) : 0.0;
+  return BR(a * b > 0.0) ? (BR(babs(a) < babs(b)) ? a : b) : 0.0;
 }
 
-static void refresh_phase(orc_mesh* m, int phase) {
+/* Ghost refresh of nf fields stored like the state (per leaf nf x M^3).
+ * linear = 0: the minmod-limited prolongation above (hydro); linear = 1:
+ * unlimited central slopes s_d = 0.5 (U_{P+e_d} - U_{P-e_d}), the linear
+ * interpolation of the composite Poisson operator. */
+static void refresh_fields(const orc_mesh* m, double* data, int nf, int phase, int linear) {
   const int N = m->N, M = m->M;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) SERIAL_IF_TAPED
   for (int64_t s = 0; s < m->nleaf; s++) {
     const int32_t* kk = m->key + 4 * s;
     const int l = kk[0];
-    double* B = block_ptr(m, s);
+    double* B = data + s * (int64_t)nf * M * M * M;
     for (int c = 0; c < M; c++)
       for (int b = 0; b < M; b++)
         for (int a = 0; a < M; a++) {
@@ -427,13 +478,13 @@ static void refresh_phase(orc_mesh* m, int phase) {
           int bp[3] = {(int)(p[0] / N), (int)(p[1] / N), (int)(p[2] / N)};
           unsigned char st = m->state[l][nidx(m, l, bp[0], bp[1], bp[2])];
           if (phase == 1 && st == LEAF) {
-            for (int f = 0; f < m->nf; f++) B[cell(M, f, a, b, c)] = leaf_value(m, l, p, f);
+            for (int f = 0; f < nf; f++) B[cell(M, f, a, b, c)] = leaf_value_of(m, data, nf, l, p, f);
           } else if (phase == 1 && st == REFINED) {
-            for (int f = 0; f < m->nf; f++) {
+            for (int f = 0; f < nf; f++) {
               double v[8];
               for (int o = 0; o < 8; o++) {
                 int64_t q[3] = {2 * p[0] + (o & 1), 2 * p[1] + ((o >> 1) & 1), 2 * p[2] + (o >> 2)};
-                v[o] = leaf_value(m, l + 1, q, f);
+                v[o] = leaf_value_of(m, data, nf, l + 1, q, f);
               }
               B[cell(M, f, a, b, c)] = restrict8(v);
             }
@@ -445,19 +496,25 @@ static void refresh_phase(orc_mesh* m, int phase) {
             int64_t pc[3] = {p[0] >> 1, p[1] >> 1, p[2] >> 1};
             int cb[3] = {(int)(pc[0] / N), (int)(pc[1] / N), (int)(pc[2] / N)};
             int32_t sc = m->leaf_at[l - 1][nidx(m, l - 1, cb[0], cb[1], cb[2])];
-            const double* C = block_ptr(m, sc);
+            const double* C = data + sc * (int64_t)nf * M * M * M;
             int lc[3];
             double o[3];
             for (int ax = 0; ax < 3; ax++) {
               lc[ax] = (int)(pc[ax] - (int64_t)cb[ax] * N) + G;
               o[ax] = (p[ax] & 1) ? 1.0 : -1.0;
             }
-            for (int f = 0; f < m->nf; f++) {
+            for (int f = 0; f < nf; f++) {
               double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
               double sl[3];
-              sl[0] = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
-              sl[1] = minmod(C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - u0, u0 - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
-              sl[2] = minmod(C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - u0, u0 - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
+              if (linear) {
+                sl[0] = 0.5 * (C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
+                sl[1] = 0.5 * (C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
+                sl[2] = 0.5 * (C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
+              } else {
+                sl[0] = minmod(C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - u0, u0 - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
+                sl[1] = minmod(C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - u0, u0 - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
+                sl[2] = minmod(C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - u0, u0 - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
+              }
               B[cell(M, f, a, b, c)] =
                   ((u0 + (0.25 * o[0]) * sl[0]) + (0.25 * o[1]) * sl[1]) + (0.25 * o[2]) * sl[2];
             }
@@ -465,6 +522,8 @@ static void refresh_phase(orc_mesh* m, int phase) {
         }
   }
 }
+
+static void refresh_phase(orc_mesh* m, int phase) { refresh_fields(m, m->U, m->nf, phase, 0); }
 
 void orc_refresh(orc_mesh* m) {
   refresh_phase(m, 1);
@@ -531,7 +590,7 @@ static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, doub
   double ir = 1.0 / rho;
   double u = mn * ir, v = mt1 * ir, w = mt2 * ir;
   double p = cell_pressure(K, rho, u, v, w, E, ge);
-  p = p < K->p_floor ? K->p_floor : p;
+  p = BR(p < K->p_floor) ? K->p_floor : p;
   P.q[0] = rho; P.q[1] = u; P.q[2] = v; P.q[3] = w; P.q[4] = p;
   P.c = sqrt((K->gamma * p) * ir);
   P.ir = ir;
@@ -541,9 +600,9 @@ static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, doub
 /* Limited (monotonised central) slope of cell j from q[j-1], q[j], q[j+1]. */
 static double mc_slope(double qm, double q0, double qp) {
   double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
-  if (!(dl * dr > 0.0)) return 0.0;
-  double mlim = dmin(dmin(fabs(dc), 2.0 * fabs(dl)), 2.0 * fabs(dr));
-  return dc > 0.0 ? mlim : -mlim;
+  if (!BR(dl * dr > 0.0)) return 0.0;
+  double mlim = dmin(dmin(babs(dc), 2.0 * babs(dl)), 2.0 * babs(dr));
+  return BR(dc > 0.0) ? mlim : -mlim;
 }
 
 /* Parabola of one cell after flattening and the monotonicity constraint. */
@@ -553,14 +612,14 @@ static para_t make_parabola(const consts_t* K, double q, double qL, double qR, d
   para_t P;
   qL = f * q + (1.0 - f) * qL;
   qR = f * q + (1.0 - f) * qR;
-  if ((qR - q) * (q - qL) <= 0.0) {
+  if (BR((qR - q) * (q - qL) <= 0.0)) {
     qL = q;
     qR = q;
   } else {
     double D = qR - qL, mm = q - 0.5 * (qL + qR);
-    if (D * mm > (D * D) * K->sixth)
+    if (BR(D * mm > (D * D) * K->sixth))
       qL = 3.0 * q - 2.0 * qR;
-    else if (-((D * D) * K->sixth) > D * mm)
+    else if (BR(-((D * D) * K->sixth) > D * mm))
       qR = 3.0 * q - 2.0 * qL;
   }
   P.qL = qL;
@@ -596,10 +655,11 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
   const double cor = c * C->ir;         /* c / rho */
   /* right edge: waves with positive speed */
   {
-    double sm = (lm > 0.0 ? lm : 0.0) * nu, s0 = (l0 > 0.0 ? l0 : 0.0) * nu, sp = (lp > 0.0 ? lp : 0.0) * nu;
+    const int gm = BR(lm > 0.0), g0 = BR(l0 > 0.0), gp = BR(lp > 0.0);
+    double sm = (gm ? lm : 0.0) * nu, s0 = (g0 ? l0 : 0.0) * nu, sp = (gp ? lp : 0.0) * nu;
     double rr = Ip(K, &par[0], sp), ur = Ip(K, &par[1], sp), pr = Ip(K, &par[4], sp);
-    double am = (lm > 0.0) ? Ac * ((pr - Ip(K, &par[4], sm)) * Bc - (ur - Ip(K, &par[1], sm))) : 0.0;
-    double a0 = (l0 > 0.0) ? (rr - Ip(K, &par[0], s0)) - (pr - Ip(K, &par[4], s0)) * ic2 : 0.0;
+    double am = gm ? Ac * ((pr - Ip(K, &par[4], sm)) * Bc - (ur - Ip(K, &par[1], sm))) : 0.0;
+    double a0 = g0 ? (rr - Ip(K, &par[0], s0)) - (pr - Ip(K, &par[4], s0)) * ic2 : 0.0;
     WL[0] = (rr - am) - a0;
     WL[1] = ur + cor * am;
     WL[4] = pr - cc * am;
@@ -608,10 +668,11 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
   }
   /* left edge: waves with negative speed */
   {
-    double sm = (lm < 0.0 ? -lm : 0.0) * nu, s0 = (l0 < 0.0 ? -l0 : 0.0) * nu, sp = (lp < 0.0 ? -lp : 0.0) * nu;
+    const int gm = BR(lm < 0.0), g0 = BR(l0 < 0.0), gp = BR(lp < 0.0);
+    double sm = (gm ? -lm : 0.0) * nu, s0 = (g0 ? -l0 : 0.0) * nu, sp = (gp ? -lp : 0.0) * nu;
     double rr = Im(K, &par[0], sm), ur = Im(K, &par[1], sm), pr = Im(K, &par[4], sm);
-    double ap = (lp < 0.0) ? Ac * ((pr - Im(K, &par[4], sp)) * Bc + (ur - Im(K, &par[1], sp))) : 0.0;
-    double a0 = (l0 < 0.0) ? (rr - Im(K, &par[0], s0)) - (pr - Im(K, &par[4], s0)) * ic2 : 0.0;
+    double ap = gp ? Ac * ((pr - Im(K, &par[4], sp)) * Bc + (ur - Im(K, &par[1], sp))) : 0.0;
+    double a0 = g0 ? (rr - Im(K, &par[0], s0)) - (pr - Im(K, &par[4], s0)) * ic2 : 0.0;
     WR[0] = (rr - ap) - a0;
     WR[1] = ur - cor * ap;
     WR[4] = pr - cc * ap;
@@ -620,10 +681,10 @@ static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], 
   }
   /* positivity floors on the edge states */
   if (g_debug & ORC_DEBUG_EDGE_NO_FLOOR) return;
-  WL[0] = WL[0] < K->rho_floor ? K->rho_floor : WL[0];
-  WL[4] = WL[4] < K->p_floor ? K->p_floor : WL[4];
-  WR[0] = WR[0] < K->rho_floor ? K->rho_floor : WR[0];
-  WR[4] = WR[4] < K->p_floor ? K->p_floor : WR[4];
+  WL[0] = BR(WL[0] < K->rho_floor) ? K->rho_floor : WL[0];
+  WL[4] = BR(WL[4] < K->p_floor) ? K->p_floor : WL[4];
+  WR[0] = BR(WR[0] < K->rho_floor) ? K->rho_floor : WR[0];
+  WR[4] = BR(WR[4] < K->p_floor) ? K->p_floor : WR[4];
 }
 
 /* Two-shock approximate Riemann solver (the PPM approximation of Colella &
@@ -648,7 +709,7 @@ static void riemann(const consts_t* K, const double WLs[5], const double WRs[5],
   const double CL = sqrt((K->gamma * pL) * rL), CR = sqrt((K->gamma * pR) * rR);
   const double ipL = 1.0 / pL, ipR = 1.0 / pR;
   double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
-  ps = ps < K->p_floor ? K->p_floor : ps;
+  ps = BR(ps < K->p_floor) ? K->p_floor : ps;
   double iWL = 0.0, iWR = 0.0, iZL = 0.0, iZR = 0.0, usL = 0.0, usR = 0.0, WLw = 0.0, WRw = 0.0;
   for (int it = 0; it <= K->iters; it++) {
     WLw = CL * sqrt(1.0 + K->g1 * (ps * ipL - 1.0));
@@ -662,11 +723,11 @@ static void riemann(const consts_t* K, const double WLs[5], const double WRs[5],
     iZR = (0.5 * iWR) * (1.0 + qR * qR);
     if (it == K->iters) break; /* final pass: wave speeds at the last p* */
     ps = ps - (usR - usL) / (iZL + iZR);
-    ps = ps < K->p_floor ? K->p_floor : ps;
+    ps = BR(ps < K->p_floor) ? K->p_floor : ps;
   }
   const double us = (iZR * usL + iZL * usR) / (iZL + iZR);
   /* side of the contact the interface lies on; a tie takes the left side */
-  const int left = us >= 0.0;
+  const int left = BR(us >= 0.0);
   const double s = left ? 1.0 : -1.0;
   const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
   const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
@@ -674,17 +735,17 @@ static void riemann(const consts_t* K, const double WLs[5], const double WRs[5],
   const double vs = irK - (ps - pK) * (iWK * iWK); /* 1/rho* on side K */
   const double rs = 1.0 / vs;
   double rg, ug, pg;
-  if (ps > pK) {
+  if (BR(ps > pK)) {
     /* shock: S = u_K - s W_K / rho_K */
     double S = uK - s * (WK * irK);
-    if (s * S >= 0.0) { rg = rK; ug = uK; pg = pK; }
+    if (BR(s * S >= 0.0)) { rg = rK; ug = uK; pg = pK; }
     else { rg = rs; ug = us; pg = ps; }
   } else {
     double cK = sqrt((K->gamma * pK) * irK);
     double cs = sqrt((K->gamma * ps) * vs);
     double lh = uK - s * cK, lt = us - s * cs;
-    if (s * lh >= 0.0) { rg = rK; ug = uK; pg = pK; }
-    else if (s * lt <= 0.0) { rg = rs; ug = us; pg = ps; }
+    if (BR(s * lh >= 0.0)) { rg = rK; ug = uK; pg = pK; }
+    else if (BR(s * lt <= 0.0)) { rg = rs; ug = us; pg = ps; }
     else {
       double xi = lh / (lh - lt);
       rg = rK + xi * (rs - rK);
@@ -730,13 +791,13 @@ static void pencil(const consts_t* K, double nu, int n, const double* const U[],
      * fourth ghost cell) */
     double pp = P[j + 1].q[4], pm = P[j - 1].q[4];
     double dp1 = pp - pm;
-    double pmin = pp < pm ? pp : pm;
-    int shock = (fabs(dp1) > EPS_S * pmin) && (P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
+    double pmin = BR(pp < pm) ? pp : pm;
+    int shock = BR(babs(dp1) > EPS_S * pmin) && BR(P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
     double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
-    double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    double r = BR(dp2 != 0.0) ? dp1 / dp2 : 0.0;
     double ft = OMEGA2 * (r - OMEGA1);
-    ft = ft < 1.0 ? ft : 1.0;
-    ft = ft > 0.0 ? ft : 0.0;
+    ft = BR(ft < 1.0) ? ft : 1.0;
+    ft = BR(ft > 0.0) ? ft : 0.0;
     double f = shock ? ft : 0.0;
     para_t par[5];
     for (int v = 0; v < 5; v++) par[v] = make_parabola(K, P[j].q[v], fa[j - 1][v], fa[j][v], f);
@@ -764,7 +825,7 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
     hi[a] = act ? G + N : M;
   }
   int64_t nfl_total = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl_total)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl_total) SERIAL_IF_TAPED
   for (int64_t s = 0; s < m->nleaf; s++) {
     double* B = block_ptr(m, s);
     const double nu = dt / dx_level(m, m->key[4 * s]);
@@ -802,7 +863,7 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
             Un[5] = (g_debug & ORC_DEBUG_DE_PDV_SIGN) ? Un[5] + nu * work : Un[5] - nu * work;
           }
           /* post-update floors (counted: they break conservation) */
-          if (Un[0] < K->rho_floor) {
+          if (BR(Un[0] < K->rho_floor)) {
             if (g_debug & ORC_DEBUG_FLOOR_KEEP_VEL)
               for (int d = 1; d <= 3; d++) Un[d] = Un[d] * (K->rho_floor / Un[0]);
             Un[0] = K->rho_floor;
@@ -812,7 +873,7 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
           double u = Un[1] * ir, v = Un[2] * ir, w = Un[3] * ir;
           double ke = (0.5 * Un[0]) * ((u * u + v * v) + w * w);
           double p = K->gm1 * (Un[4] - ke);
-          if (p < K->p_floor) {
+          if (BR(p < K->p_floor)) {
             Un[4] = (g_debug & ORC_DEBUG_FLOOR_E_NO_KE) ? K->p_floor * K->inv_gm1 : K->p_floor * K->inv_gm1 + ke;
             nfl++;
           }
@@ -820,8 +881,8 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
             /* resynchronise rho e from the total energy where E - ke > eta2 E,
              * then its own floor (counted) */
             const double ie = Un[4] - ke;
-            if (ie > K->eta2 * Un[4]) Un[5] = ie;
-            if (K->gm1 * Un[5] < K->p_floor) {
+            if (BR(ie > K->eta2 * Un[4])) Un[5] = ie;
+            if (BR(K->gm1 * Un[5] < K->p_floor)) {
               Un[5] = (g_debug & ORC_DEBUG_DE_FLOOR_NO_IG) ? K->p_floor : K->p_floor * K->inv_gm1;
               nfl++;
             }
@@ -856,7 +917,7 @@ static void reflux(orc_mesh* m, double dt) {
   const int N = m->N, M = m->M;
   for (int dir = 0; dir < 3; dir++) {
     const int a1 = dir == 0 ? 1 : 0, a2 = dir == 2 ? 1 : 2;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) SERIAL_IF_TAPED
     for (int64_t s = 0; s < m->nleaf; s++) {
       const int32_t* kk = m->key + 4 * s;
       const int l = kk[0];
@@ -909,6 +970,120 @@ void orc_step_dt(orc_mesh* m, int64_t step_index, double dt) {
     swept[order[s]] = 1;
   }
   if (!(g_debug & ORC_DEBUG_SKIP_REFLUX)) reflux(m, dt);
+}
+
+/* Density misfit of the config-4 loss: sum over active leaf cells of
+ * (V_c / V_root) (rho_c - target_c)^2, V_c / V_root = 8^-level, summed
+ * leaf by leaf, cells z, y, x. */
+static double density_misfit(const orc_mesh* m, const double* target) {
+  const int N = m->N, M = m->M;
+  const int64_t N3 = (int64_t)N * N * N;
+  double L = 0.0;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double* B = block_ptr(m, s);
+    const double w = ldexp(1.0, -3 * m->key[4 * s]);
+    const double* T = target + s * N3;
+    double ls = 0.0;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          const double d = B[cell(M, 0, a + G, b + G, c + G)] - T[((int64_t)c * N + b) * N + a];
+          ls = ls + d * d;
+        }
+    L = L + w * ls;
+  }
+  return L;
+}
+
+static orc_mesh* clone_mesh(const orc_mesh* m0) {
+  orc_mesh* m = NULL;
+  if (orc_create_from_leaves(&m0->d, m0->nleaf, m0->key, &m)) return NULL;
+  memcpy(m->U, m0->U, (size_t)m0->nleaf * m0->nf * m0->M * m0->M * m0->M * sizeof(double));
+  return m;
+}
+
+static void run_steps_dt(orc_mesh* m, int64_t first_step, int nsteps, const double* dts) {
+  for (int k = 0; k < nsteps; k++) orc_step_dt(m, first_step + k, dts[k]);
+}
+
+/* Difference of the misfit between two states a and b of the same mesh,
+ * L(a) - L(b) = sum 8^-level (rho_a - rho_b)(rho_a + rho_b - 2 target),
+ * written so that L's own size does not cancel. */
+static double misfit_difference(const orc_mesh* m, const double* rho_a, const orc_mesh* b, const double* target) {
+  const int N = m->N, M = m->M;
+  const int64_t N3 = (int64_t)N * N * N;
+  double D = 0.0;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double* B = block_ptr(b, s);
+    const double w = ldexp(1.0, -3 * m->key[4 * s]);
+    double ds = 0.0;
+    for (int c = 0; c < N; c++)
+      for (int y = 0; y < N; y++)
+        for (int a = 0; a < N; a++) {
+          const int64_t q = s * N3 + ((int64_t)c * N + y) * N + a;
+          const double ra = rho_a[q], rb = B[cell(M, 0, a + G, y + G, c + G)];
+          ds = ds + (ra - rb) * ((ra + rb) - 2.0 * target[q]);
+        }
+    D = D + w * ds;
+  }
+  return D;
+}
+
+int orc_frozen_fd_density_grad(const orc_mesh* m0, int64_t first_step, int nsteps, const double* dts,
+                               const double* target, double eps, const int64_t* idx, int64_t nidx,
+                               double* grad_out, double* loss_out) {
+  if (m0->nf != 5) return fail("frozen-branch differences need a five-field mesh");
+  if (nsteps < 0 || !(eps > 0.0)) return fail("nsteps must be >= 0 and eps > 0");
+  const int N = m0->N, M = m0->M;
+  const int64_t N3 = (int64_t)N * N * N;
+  for (int64_t q = 0; q < nidx; q++)
+    if (idx[q] < 0 || idx[q] >= m0->nleaf * N3) return fail("density index out of range");
+  /* record the base run's choices */
+  tape_t rec = {0};
+  orc_mesh* base = clone_mesh(m0);
+  if (!base) return -1;
+  t_tape = &rec;
+  run_steps_dt(base, first_step, nsteps, dts);
+  t_tape = NULL;
+  if (loss_out) *loss_out = density_misfit(base, target);
+  orc_destroy(base);
+  if (rec.overrun) { free(rec.b); return fail("branch tape allocation failed"); }
+  int bad = 0;
+#pragma omp parallel reduction(| : bad)
+  {
+    orc_mesh* m = clone_mesh(m0);
+    double* rho_p = (double*)malloc((size_t)(m0->nleaf * N3) * sizeof(double));
+    tape_t rep = {rec.b, rec.n, rec.cap, 0, 1, 0};
+    if (!m || !rho_p) bad = 1;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nidx; q++) {
+      if (!m || !rho_p) continue;
+      const int64_t s = idx[q] / N3, r = idx[q] - s * N3;
+      const int a = (int)(r % N) + G, b = (int)((r / N) % N) + G, c = (int)(r / ((int64_t)N * N)) + G;
+      for (int side = 0; side < 2; side++) {
+        memcpy(m->U, m0->U, (size_t)m0->nleaf * 5 * M * M * M * sizeof(double));
+        double* rho = &block_ptr(m, s)[cell(M, 0, a, b, c)];
+        *rho = side ? *rho - eps : *rho + eps;
+        rep.pos = 0;
+        t_tape = &rep;
+        run_steps_dt(m, first_step, nsteps, dts);
+        t_tape = NULL;
+        if (rep.overrun || rep.pos != rep.n) bad = 1;
+        if (side == 0) {
+          for (int64_t t = 0; t < m->nleaf; t++)
+            for (int cz = 0; cz < N; cz++)
+              for (int y = 0; y < N; y++)
+                for (int x = 0; x < N; x++)
+                  rho_p[t * N3 + ((int64_t)cz * N + y) * N + x] = block_ptr(m, t)[cell(M, 0, x + G, y + G, cz + G)];
+        }
+      }
+      grad_out[q] = misfit_difference(m, rho_p, m, target) / (2.0 * eps);
+    }
+    if (m) orc_destroy(m);
+    free(rho_p);
+  }
+  free(rec.b);
+  return bad ? fail("a replay did not consume the recorded choices exactly") : 0;
 }
 
 double orc_step(orc_mesh* m, int64_t step_index) {

@@ -113,6 +113,20 @@ int orc_step_gravity_comoving(orc_mesh* m, int64_t step_index, double dt, double
                               double hubble, double four_pi_G, double* phi, int phi_current, int ncycles, int nu1,
                               int nu2);
 
+/* Frozen-branch central differences of the density misfit (reading R17 of
+ * the adjoint: dt sequence and every discrete choice held at the base
+ * run's).  From m's state (unchanged), nsteps steps of indices first_step,
+ * first_step + 1, ... with the given dts; L = sum over active leaf cells of
+ * 8^-level (rho - target)^2 (target: nleaf x N^3, x fastest).  The base
+ * run records its choices; for each of the nidx flat density indices
+ * (leaf * N^3 + (z N + y) N + x) the runs with rho +- eps replay them, and
+ * grad_out[q] = (L(+eps) - L(-eps)) / (2 eps).  loss_out (may be NULL)
+ * receives the base run's L.  Returns 0, or -1 (five fields only; a replay
+ * that does not consume the recorded choices exactly). */
+int orc_frozen_fd_density_grad(const orc_mesh* m, int64_t first_step, int nsteps, const double* dts,
+                               const double* target, double eps, const int64_t* idx, int64_t nidx,
+                               double* grad_out, double* loss_out);
+
 /* Test hooks on the building blocks. */
 #define ORC_DEBUG_SKIP_REFLUX 1
 #define ORC_DEBUG_DE_PDV_SIGN 2   /* rho e takes +p div(v) */
@@ -156,6 +170,24 @@ void orc_mg_restrict_residual(int nx, int ny, int nz, double h, const double* f,
                               double* coarse_f);
 int orc_mg_solve(int nx, int ny, int nz, double h, const double* f, double* phi, int ncycles, int nu1, int nu2,
                  double* resid);
+
+int orc_mg_vcycle_from_zero(int nx, int ny, int nz, double h, const double* f, double* phi, int nu1, int nu2);
+
+/* mg0 on the octree (Sec. II-C gravity solver on the Sec. II-B array of
+ * octrees): the composite-grid Poisson problem on the leaves of a periodic
+ * 2:1-balanced mesh and its multigrid V-cycle; readings in amr_oracle.c.
+ * Arrays are per leaf N^3 doubles (x fastest), leaves in m's order.
+ * orc_mgc_apply: L phi.  orc_mgc_solve: f made mean-free (volume-weighted),
+ * ncycles composite V(nu1, nu2) cycles from phi, phi returned with zero
+ * volume-weighted mean, resid (ncycles + 1, may be NULL) the volume-weighted
+ * residual L2 norms; an unrefined mesh takes orc_mg_solve's path exactly.
+ * Return 0 (apply) or the number of levels (solve), -1 for a non-periodic
+ * mesh or a coarsest level above 4096 cells. */
+#define ORC_MGC_DEBUG_NO_MATCH 1  /* coarse side of a coarse-fine face keeps its own flux */
+#define ORC_MGC_DEBUG_FLAT 2      /* coarse-fine ghosts without slopes (constant) */
+void orc_mgc_set_debug(int flags);
+int orc_mgc_apply(const orc_mesh* m, const double* phi, double* out);
+int orc_mgc_solve(const orc_mesh* m, const double* f, double* phi, int ncycles, int nu1, int nu2, double* resid);
 
 /* Remesh (density-slope criterion).  Evaluates the per-leaf indicator on
  * refreshed data, applies refine/coarsen with 2:1 balance and the capacity

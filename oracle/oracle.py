@@ -59,15 +59,27 @@ class _Desc(ctypes.Structure):
     ]
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (abort on the first report) into `path`, for the CPU suite's sanitizer
+    run; loaded in place of the plain build when AMR_ORACLE_LIBRARY names it."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", *CFLAGS[1:], "-o", path, *_SRCS, "-lm"])
+    return path
+
+
 _lib = None
 
 
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
-            build()
-        L = ctypes.CDLL(_SO)
+        so = os.environ.get("AMR_ORACLE_LIBRARY", "")
+        if not so:
+            so = _SO
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
+                build()
+        L = ctypes.CDLL(so)
         P, D, I64, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
         L.orc_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(P)]
         L.orc_create.restype = I32
@@ -90,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.orc_step.argtypes = [P, I64]
         L.orc_step.restype = D
         L.orc_step_dt.argtypes = [P, I64, D]
+        L.orc_frozen_fd_density_grad.argtypes = [P, I64, I32, P, P, D, P, I64, P, P]
+        L.orc_frozen_fd_density_grad.restype = I32
         L.orc_cfl_dt_comoving.argtypes = [P, D]
         L.orc_cfl_dt_comoving.restype = D
         L.orc_step_comoving.argtypes = [P, I64, D, D, D]
@@ -211,6 +225,27 @@ class OracleMesh:
 
     def step_dt(self, k: int, dt: float) -> None:
         lib().orc_step_dt(self._h, int(k), float(dt))
+
+    def frozen_fd_density_grad(self, first_step: int, dts, target: np.ndarray, eps: float, idx=None):
+        """Central differences of the density misfit after len(dts) steps
+        from this mesh's state (left unchanged), with the dt sequence and
+        every discrete choice of the scheme frozen at the unperturbed run's:
+        returns (gradient at the flat density indices idx, default all
+        active cells, leaf * N^3 + (z N + y) N + x; the unperturbed loss)."""
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        target = np.ascontiguousarray(target, dtype=np.float64).reshape(self.nleaf, -1)
+        if target.shape[1] != self.N ** 3:
+            raise ValueError("target must hold N^3 densities per leaf")
+        if idx is None:
+            idx = np.arange(self.nleaf * self.N ** 3, dtype=np.int64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        grad = np.zeros(idx.size)
+        loss = ctypes.c_double()
+        rc = lib().orc_frozen_fd_density_grad(self._h, int(first_step), int(dts.size), _ptr(dts), _ptr(target),
+                                              float(eps), _ptr(idx), int(idx.size), _ptr(grad), ctypes.byref(loss))
+        if rc != 0:
+            raise ValueError("oracle frozen-branch differences: " + lib().orc_last_error().decode())
+        return grad, float(loss.value)
 
     def cfl_dt_comoving(self, a: float) -> float:
         """CFL dt in comoving coordinates with expansion factor a."""
