@@ -61,5 +61,35 @@ def build(force: bool = True) -> str:
     return SO
 
 
+def build_host_sanitized(path: str) -> str:
+    """The library with its host half (mesh.cpp, capi.cpp) compiled by g++
+    with AddressSanitizer and UndefinedBehaviorSanitizer (abort on the first
+    report) and linked with the device objects of the last build(): for the
+    CPU suite's sanitizer run, loaded in place of libamr.so when AMR_LIBRARY
+    names it (with the sanitizer runtimes preloaded).  Nothing in the device
+    code is sanitized."""
+    objs = [os.path.join(BUILD, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"device objects missing (run build() first): {missing}")
+    san = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    out_dir = os.path.dirname(os.path.abspath(path))
+    host = []
+    for src in ("mesh.cpp", "capi.cpp"):
+        obj = os.path.join(out_dir, src + ".san.o")
+        r = subprocess.run(["g++", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", *san,
+                            "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                            "-I" + os.path.join(HERE, "..", "include"), "-c", os.path.join(SRC, src), "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"g++ failed on {src}:\n{r.stderr}")
+        host.append(obj)
+    r = subprocess.run(["g++", "-shared", "-fsanitize=address,undefined", "-o", path, *host, *objs,
+                        "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr)
+    return path
+
+
 if __name__ == "__main__":
     print(build())
