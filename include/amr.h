@@ -42,6 +42,10 @@ extern "C" {
 #endif
 
 typedef struct amr_mesh amr_mesh;
+/* A batch of independent meshes is a mesh handle whose leaves form one flat
+ * worklist of several instances (amr_batch_create); every entry point that
+ * takes an amr_mesh* also takes a batch. */
+typedef struct amr_mesh amr_batch;
 typedef struct amr_graph amr_graph;
 
 typedef int32_t amr_status;
@@ -114,8 +118,9 @@ typedef struct {
 amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out);
 
 /* Build from an explicit leaf set (n x (level,i,j,k), borrowed for the
- * call).  Errors: AMR_E_BALANCE if the leaves do not tile the domain or
- * violate the 2:1 rule. */
+ * call): the octree of Sec. II-B given by its leaves (checkpoint restart,
+ * meshes made elsewhere).  Errors: AMR_E_BALANCE if the leaves do not tile
+ * the domain or violate the 2:1 rule. */
 amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n,
                                        const int32_t* keys, amr_mesh** out);
 
@@ -127,21 +132,37 @@ amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n,
  * dt_dev holds n doubles.  This is the paper's "agglomerating work units"
  * (Sec. IV) applied to many small meshes on one GPU.  Remesh is for
  * single meshes. */
-amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_mesh** out);
+amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_batch** out);
+/* One step of every instance of a batch (Sec. II-C ppm Method on every
+ * Block of every instance, Sec. IV agglomerated work units): amr_hydro_step
+ * on the batch handle -- each instance's refresh, its own CFL dt (dt_dev:
+ * n_instances doubles, written), sweeps and reflux, all instances in the same
+ * launches.  Errors as amr_hydro_step. */
+amr_status amr_batch_step(amr_batch* batch, double* U_dev, double* dt_dev, int64_t step_index, void* stream);
 /* first_leaf[m] = index of instance m's first leaf, first_leaf[n] =
- * n_leaves (host memory, cap >= n_instances + 1). */
+ * n_leaves (host memory, cap >= n_instances + 1).  Not in the paper (the
+ * batch's leaf layout, reading of Sec. IV's agglomeration). */
 amr_status amr_mesh_instance_offsets(const amr_mesh* mesh, int64_t* first_leaf, int64_t cap);
 
+/* Release the host tables of a mesh or batch (Sec. II-B: the mesh object;
+ * the device memory is the caller's). */
 amr_status amr_mesh_destroy(amr_mesh* mesh);
+/* Sizes of the storage the caller allocates for a mesh: leaves per level,
+ * field layout, workspace and scratch bytes (Sec. II-B: Data of the Blocks,
+ * Field layout). */
 amr_status amr_mesh_info(const amr_mesh* mesh, amr_mesh_info_t* out);
 
 /* Leaf keys (level, i, j, k) in storage order (roots x-fastest, Morton order
- * inside each octree).  keys_out holds cap x 4 int32 (host memory). */
+ * inside each octree; Sec. II-B array of octrees, one Block per node), for
+ * initial conditions (Sec. II-B Initial).  keys_out holds cap x 4 int32
+ * (host memory). */
 amr_status amr_mesh_blocks(const amr_mesh* mesh, int32_t* keys_out, int64_t cap);
 
 /* Copy the mesh tables into caller-owned device memory of workspace_bytes
  * (amr_mesh_info) and bind it to the mesh.  The copy is enqueued on the
- * stream; the workspace must outlive every later call on this mesh. */
+ * stream; the workspace must outlive every later call on this mesh.  Not in
+ * the paper (the device copy of the Sec. II-B neighbour and refresh
+ * relations). */
 amr_status amr_mesh_upload(amr_mesh* mesh, void* workspace_dev, void* stream);
 
 /* Ghost refresh (Sec. II-B): fill the width-3 ghost shell of all fields of
@@ -151,8 +172,10 @@ amr_status amr_mesh_upload(amr_mesh* mesh, void* workspace_dev, void* stream);
  * prolongation into ghosts covered by a coarser leaf. */
 amr_status amr_refresh_ghosts(amr_mesh* mesh, double* U_dev, void* stream);
 
-/* CFL dt (device, 1 double): C_cfl * min over active leaf cells of
- * dx_l / (max_d |u_d| + c).  Exact minimum, order independent. */
+/* CFL dt (device, 1 double per instance): C_cfl * min over active leaf
+ * cells of dx_l / (max_d |u_d| + c).  Exact minimum, order independent.
+ * Not in the paper (reading: one global dt per mesh, the step's stability
+ * limit for the Sec. II-C ppm Method). */
 amr_status amr_cfl_dt(amr_mesh* mesh, const double* U_dev, double* dt_dev, void* stream);
 
 /* One hydro step (Sec. II-C "ppm" Method on every Block, after the refresh
@@ -181,7 +204,9 @@ amr_status amr_cfl_dt_comoving(amr_mesh* mesh, const double* U_dev, double a, do
 amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* dt_dev, int64_t step_index,
                                    double a, double hubble, void* stream);
 
-/* nsteps consecutive hydro steps (step indices first_step, first_step + 1,
+/* Sec. II-C ppm Method on every Block, repeated; the fused CFL is not in
+ * the paper (reading: a step's dt needs only its predecessor's output).
+ * nsteps consecutive hydro steps (step indices first_step, first_step + 1,
  * ...; U_dev updated in place): the same results as that many
  * amr_hydro_step calls, bit for bit, with step i's dt (one per instance) in
  * dt_dev[i * n_instances ...] (device, nsteps * n_instances doubles).  Only
@@ -193,7 +218,9 @@ amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* 
  * Stream-ordered; AMR_E_INVALID for nsteps < 0 or a null dt_dev. */
 amr_status amr_hydro_steps(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps, int64_t first_step,
                            void* stream);
-/* amr_hydro_steps for a state whose ghosts are current: the first step
+/* Sec. II-B refresh skipped where it would rewrite what is there (not in the
+ * paper: the remesh of Sec. II-B Refine has just refreshed).
+ * amr_hydro_steps for a state whose ghosts are current: the first step
  * skips its ghost refresh (the later ones refresh as usual).  The caller
  * guarantees that U_dev's ghost cells hold what a refresh would write, i.e.
  * that no active cell changed since the last amr_refresh_ghosts on this mesh
@@ -203,11 +230,14 @@ amr_status amr_hydro_steps(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_
 amr_status amr_hydro_steps_fresh(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps, int64_t first_step,
                                  void* stream);
 
-/* The same step with dt given on the device (no CFL reduction). */
+/* The same step (Sec. II-C ppm Method after the Sec. II-B refresh) with dt
+ * given on the device (no CFL reduction). */
 amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev,
                              int64_t step_index, void* stream);
 
-/* HIP graph of two consecutive steps (first_step and first_step+1, so one
+/* Not in the paper (a launch-overhead reading of Sec. IV's agglomeration:
+ * the fixed kernel sequence of two steps recorded once).
+ * HIP graph of two consecutive steps (first_step and first_step+1, so one
  * even and one odd sweep order) bound to U_dev and dt_dev, captured on a
  * non-null stream; each launch advances the state by two steps.  The
  * second step's CFL reduction is fused into the first step, as in
@@ -216,10 +246,15 @@ amr_status amr_hydro_step_dt(amr_mesh* mesh, double* U_dev, const double* dt_dev
  * write the same buffers every launch. */
 amr_status amr_graph_create(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t first_step, void* stream,
                             amr_graph** out);
+/* Replay the two captured steps on the stream. */
 amr_status amr_graph_launch(amr_graph* graph, void* stream);
+/* Release the graph (its captured buffers stay the caller's). */
 amr_status amr_graph_destroy(amr_graph* graph);
 
-/* The recording step and the three adjoint entries below need a five-field
+/* Differentiation is not in the paper (reading R17: the exact vector-
+ * Jacobian product of the Sec. II-C ppm step and the Sec. II-B refresh with
+ * every discrete choice frozen).
+ * The recording step and the three adjoint entries below need a five-field
  * mesh: they return AMR_E_INVALID for a mesh with the dual-energy field.
  *
  * One hydro step (as amr_hydro_step, bitwise the same result) that keeps
@@ -317,7 +352,7 @@ amr_status amr_tracer_counters(amr_mesh* mesh, void* scratch_dev, int64_t capaci
                                void* stream);
 
 /* Number of post-update floor resets since upload (synchronises the
- * stream). */
+ * stream).  Not in the paper (the positivity floors of the ppm reading). */
 amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
 
 /* Remesh (Sec. II-B "Refine"; the paper's blast test refines adaptively).
@@ -363,8 +398,9 @@ amr_status amr_remesh_apply(amr_mesh* new_mesh, const double* U_old_dev, double*
  * must be refreshed. */
 amr_status amr_indicator(amr_mesh* mesh, const double* U_dev, double* ind_dev, void* stream);
 
-/* Launch shapes.  Every choice computes bitwise-identical results (each
- * cell's arithmetic is the same; only the thread mapping changes). */
+/* Launch shapes (not in the paper: Sec. IV's multiple kernel versions, one
+ * per hardware choice).  Every choice computes bitwise-identical results
+ * (each cell's arithmetic is the same; only the thread mapping changes). */
 typedef struct {
   int32_t sweep_mode[3];  /* per axis x,y,z: 0 = one lane walks one pencil with
                              a register window; 1 = LDS-staged tile of whole
@@ -377,7 +413,8 @@ amr_status amr_mesh_set_launch(amr_mesh* mesh, const amr_launch_t* cfg);
 amr_status amr_mesh_get_launch(const amr_mesh* mesh, amr_launch_t* cfg);
 
 /* Per-phase kernel timing with HIP events recorded on the launch stream
- * around every kernel of refresh, CFL, sweeps and reflux.  Phases: */
+ * around every kernel of refresh, CFL, sweeps and reflux (not in the paper:
+ * measurement).  Phases: */
 #define AMR_PHASE_CFL 0
 #define AMR_PHASE_REFRESH1 1
 #define AMR_PHASE_REFRESH2 2
@@ -499,7 +536,8 @@ amr_status amr_profile_enable(amr_mesh* mesh, int32_t on);
  * AMR_NPHASE entries (host memory), and clears the records. */
 amr_status amr_profile_read(amr_mesh* mesh, double* ms_out, int64_t* launches_out);
 
-/* Device arithmetic self-test.  The kernels take reciprocals and square
+/* Not in the paper (a check of this build's arithmetic).
+ * Device arithmetic self-test.  The kernels take reciprocals and square
  * roots of positive operands in [2^-767, 2^1022] (densities, pressures,
  * sound speeds, shock mass fluxes: within that range for floors >= 1e-100
  * and states <= 1e100) with the IEEE sequences minus their operand scaling
@@ -510,6 +548,7 @@ amr_status amr_profile_read(amr_mesh* mesh, double* ms_out, int64_t* launches_ou
  * counts[1] (device memory, 2 x uint64, not cleared).  Stream-ordered. */
 amr_status amr_arith_selftest(uint64_t seed, int64_t n, uint64_t* counts_dev, void* stream);
 
+/* Message of the last failing call on this thread (not in the paper). */
 const char* amr_last_error(void);
 
 #ifdef __cplusplus

@@ -105,6 +105,7 @@ SIGNATURES = {
     "amr_refresh_ghosts": (_I32, [_P, _P, _P]),
     "amr_cfl_dt": (_I32, [_P, _P, _P, _P]),
     "amr_hydro_step": (_I32, [_P, _P, _P, _I64, _P]),
+    "amr_batch_step": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_dt": (_I32, [_P, _P, _P, _I64, _P]),
     "amr_hydro_step_adjoint": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
     "amr_hydro_step_record": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I64, _P]),
@@ -144,11 +145,14 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
+    """The HIP library; AMR_LIBRARY may name another build of the same
+    sources (the sanitizer build of the CPU suite)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(SO):
-            raise ImportError(f"HIP library {SO} is not built; run python -m paper_1810_01319_amd._build")
-        L = ctypes.CDLL(SO)
+        so = os.environ.get("AMR_LIBRARY", "") or SO
+        if not os.path.exists(so):
+            raise ImportError(f"HIP library {so} is not built; run python -m paper_1810_01319_amd._build")
+        L = ctypes.CDLL(so)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
             fn.restype = res

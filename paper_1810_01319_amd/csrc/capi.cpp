@@ -378,7 +378,7 @@ amr_status amr_mesh_create_from_leaves(const amr_mesh_desc* desc, int64_t n, con
   return finish(h, out);
 }
 
-amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_mesh** out) {
+amr_status amr_batch_create(const amr_mesh_desc* descs, int32_t n, amr_batch** out) {
   if (!out || !descs || n < 1) return fail(AMR_E_INVALID, "need at least one descriptor");
   *out = nullptr;
   amr_mesh* h = new (std::nothrow) amr_mesh();
@@ -483,6 +483,10 @@ amr_status amr_hydro_step(amr_mesh* h, double* U, double* dt, int64_t step_index
   amr_status rc = amr_cfl_dt(h, U, dt, stream);
   if (rc != AMR_OK) return rc;
   return run_step(h, U, dt, step_index, static_cast<hipStream_t>(stream));
+}
+
+amr_status amr_batch_step(amr_batch* b, double* U, double* dt, int64_t step_index, void* stream) {
+  return amr_hydro_step(b, U, dt, step_index, stream);
 }
 
 namespace {

@@ -138,9 +138,13 @@ class Mesh:
         check(lib().amr_cfl_dt(self._h, _ptr(U), _ptr(dt), _stream()))
 
     def step(self, U: torch.Tensor, dt: torch.Tensor, k: int) -> None:
-        """One hydro step; dt (1 double on the device) receives the CFL dt."""
+        """One hydro step; dt (n_instances doubles on the device) receives the
+        CFL dt of each instance.  A batch steps through amr_batch_step."""
         self._check_state(U)
-        check(lib().amr_hydro_step(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
+        if dt.numel() < self.n_instances:
+            raise ValueError("dt needs one double per instance")
+        fn = lib().amr_batch_step if self.n_instances > 1 else lib().amr_hydro_step
+        check(fn(self._h, _ptr(U), _ptr(dt), int(k), _stream()))
 
     def steps(self, U: torch.Tensor, dt: torch.Tensor, n: int, first: int = 0, ghosts_fresh: bool = False) -> None:
         """n consecutive steps in one call (the same results as n step calls);
