@@ -506,7 +506,9 @@ static void refresh_fields(const orc_mesh* m, double* data, int nf, int phase, i
             for (int f = 0; f < nf; f++) {
               double u0 = C[cell(M, f, lc[0], lc[1], lc[2])];
               double sl[3];
-              if (linear) {
+              if (linear == 2) {
+                sl[0] = sl[1] = sl[2] = 0.0;
+              } else if (linear) {
                 sl[0] = 0.5 * (C[cell(M, f, lc[0] + 1, lc[1], lc[2])] - C[cell(M, f, lc[0] - 1, lc[1], lc[2])]);
                 sl[1] = 0.5 * (C[cell(M, f, lc[0], lc[1] + 1, lc[2])] - C[cell(M, f, lc[0], lc[1] - 1, lc[2])]);
                 sl[2] = 0.5 * (C[cell(M, f, lc[0], lc[1], lc[2] + 1)] - C[cell(M, f, lc[0], lc[1], lc[2] - 1)]);
@@ -1264,6 +1266,428 @@ double orc_step_tracers(orc_mesh* m, int64_t step_index, int64_t n, double* X, d
   orc_tracers_drift(m, dt, n, X, Y, Z, alive);
   orc_step_dt(m, step_index, dt);  /* refreshes again: the same ghosts */
   return dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* mg0 on the octree (Sec. II-C: the gravity Method's multigrid solver;  */
+/* Sec. II-B: the array of octrees it runs on)                           */
+/* ------------------------------------------------------------------ */
+/* Readings (the paper names mg0 and the octree, not the discretisation):
+ *  - unknowns: one value per active leaf cell.  The operator is the
+ *    finite-volume Laplacian -- per cell, the sum over its 6 faces of the
+ *    outward difference quotient, divided by h -- written as the 7-point sum
+ *    on ghost-filled blocks plus a correction at coarse-fine faces:
+ *    L = (S - 6 phi) (1/h^2), S = ((W + E) + (S + N)) + (B + T) from the
+ *    block's ghosts, which hold same-level copies, the mean of the 8
+ *    children over finer leaves, and over a coarser leaf its linear
+ *    interpolation with central slopes,
+ *    g = ((phi_P + 0.25 o_x s_x) + 0.25 o_y s_y) + 0.25 o_z s_z,
+ *    s_d = 0.5 (phi_{P+e_d} - phi_{P-e_d});
+ *    at a coarse cell's face onto finer leaves the coarse quotient
+ *    F_c = (g_c - phi_c) (1/h) (g_c the restricted ghost) is replaced by the
+ *    mean of the four fine cells' quotients across that face, taken outward
+ *    from the coarse cell, F_k = (phi_k - g_k) (1/h_f):
+ *    L += ((((F00 + F10) + (F01 + F11)) 0.25) - F_c) (1/h), axes x, y, z in
+ *    turn (first index along the lower transverse axis).  The fluxes through
+ *    a coarse-fine face then agree on both sides, so the volume-weighted sum
+ *    of L phi over a periodic mesh vanishes.
+ *  - hierarchy: Omega_l = the leaves coarser than l and every octree node of
+ *    level l, for l = L_max (the mesh itself) down to 1, then Omega_0 = the
+ *    root blocks, a uniform periodic grid.
+ *  - V-cycle on Omega_l (l >= 1; correction form): nu1 red-black passes, the
+ *    residual, its restriction to Omega_{l-1} (a level-(l-1) node's cell is
+ *    the mean of its 8 children's residuals, summed as the refresh's
+ *    restriction; unchanged cells copy), the correction on Omega_{l-1} from
+ *    zero, then added back: the copy on unchanged cells, on a level-l cell
+ *    the interpolation formula above from its parent (correction ghosts
+ *    refreshed the same way), then nu2 red-black passes.  On Omega_0: one
+ *    uniform mg0 V-cycle from zero (the uniform solver's own levels below).
+ *  - red-black pass of colour c ((i + j + k) even first, global indices at
+ *    the cell's level): refresh, then for every leaf cell of colour c,
+ *    r = f - L phi from the values before the pass, then phi -= r / D,
+ *    D = (6 + n_cf) (1/h^2) (minus L's diagonal coefficient), n_cf = the
+ *    cell's coarse-side coarse-fine faces (each such face doubles its
+ *    diagonal coefficient).
+ *  - a solve: f minus its volume-weighted mean; ncycles V-cycles from the
+ *    caller's phi; phi minus its volume-weighted mean.  A cell weighs 8^-level;
+ *    sums run leaf by leaf, cells z, y, x.  An unrefined mesh takes the
+ *    uniform solver's path exactly. */
+
+static int g_mgc_debug = 0;
+void orc_mgc_set_debug(int flags) { g_mgc_debug = flags; }
+
+typedef struct {
+  const orc_mesh* m;
+  orc_mesh* own;
+  double* x; /* nleaf x M^3, ghost-filled on use */
+  double* b; /* nleaf x N^3 */
+  double* L; /* nleaf x N^3 */
+  unsigned char* ncf; /* nleaf x N^3 */
+} mgc_stage;
+
+static inline int64_t acell(int N, int64_t s, int a, int b, int c) {
+  return (s * N + c) * (int64_t)N * N + (int64_t)b * N + a;
+}
+
+static void mgc_refresh(const orc_mesh* m, double* x) {
+  const int lin = (g_mgc_debug & ORC_MGC_DEBUG_FLAT) ? 2 : 1;
+  refresh_fields(m, x, 1, 1, lin);
+  refresh_fields(m, x, 1, 2, lin);
+}
+
+/* L phi (and the coarse-side coarse-fine face counts) on the cells of
+ * colour col (-1: all), from the ghost-filled x. */
+static void mgc_lap(const orc_mesh* m, const double* x, double* Lout, unsigned char* ncf, int col) {
+  const int N = m->N, M = m->M;
+  const int64_t M3 = (int64_t)M * M * M;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const int32_t* kk = m->key + 4 * s;
+    const int l = kk[0];
+    const double h = dx_level(m, l), ih = 1.0 / h, ih2 = 1.0 / (h * h);
+    const double ihf = 1.0 / dx_level(m, l + 1);
+    const double* X = x + s * M3;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          if (col >= 0 && ((a + b + c) & 1) != col) continue;
+          const int A = a + G, B = b + G, C = c + G;
+          const double xc = X[cell(M, 0, A, B, C)];
+          const double S = ((X[cell(M, 0, A - 1, B, C)] + X[cell(M, 0, A + 1, B, C)]) +
+                            (X[cell(M, 0, A, B - 1, C)] + X[cell(M, 0, A, B + 1, C)])) +
+                           (X[cell(M, 0, A, B, C - 1)] + X[cell(M, 0, A, B, C + 1)]);
+          double L = (S - 6.0 * xc) * ih2;
+          int n = 0;
+          const int loc[3] = {a, b, c};
+          for (int dir = 0; dir < 3 && !(g_mgc_debug & ORC_MGC_DEBUG_NO_MATCH); dir++) {
+            const int side = loc[dir] == 0 ? 0 : (loc[dir] == N - 1 ? 1 : -1);
+            if (side < 0) continue;
+            int nb[3] = {kk[1], kk[2], kk[3]};
+            nb[dir] += side ? 1 : -1;
+            if (!wrap_block(m, l, dir, &nb[dir])) continue;
+            if (m->state[l][nidx(m, l, nb[0], nb[1], nb[2])] != REFINED) continue;
+            const int a1 = dir == 0 ? 1 : 0, a2 = dir == 2 ? 1 : 2;
+            int gp[3] = {A, B, C};
+            gp[dir] += side ? 1 : -1;
+            const double Fc = (X[cell(M, 0, gp[0], gp[1], gp[2])] - xc) * ih;
+            /* the four fine cells across the face, global level-(l+1) indices */
+            const int64_t P[3] = {(int64_t)kk[1] * N + a, (int64_t)kk[2] * N + b, (int64_t)kk[3] * N + c};
+            double F[2][2];
+            for (int q2 = 0; q2 < 2; q2++)
+              for (int q1 = 0; q1 < 2; q1++) {
+                int64_t fq[3];
+                fq[dir] = side ? 2 * P[dir] + 2 : 2 * P[dir] - 1;
+                fq[a1] = 2 * P[a1] + q1;
+                fq[a2] = 2 * P[a2] + q2;
+                for (int ax = 0; ax < 3; ax++) fq[ax] = bc_cell(m, l + 1, ax, fq[ax]);
+                const int fb[3] = {(int)(fq[0] / N), (int)(fq[1] / N), (int)(fq[2] / N)};
+                const int32_t fs = m->leaf_at[l + 1][nidx(m, l + 1, fb[0], fb[1], fb[2])];
+                const double* XF = x + fs * M3;
+                int fl[3];
+                for (int ax = 0; ax < 3; ax++) fl[ax] = (int)(fq[ax] - (int64_t)fb[ax] * N) + G;
+                const double xf = XF[cell(M, 0, fl[0], fl[1], fl[2])];
+                fl[dir] += side ? -1 : 1; /* the fine cell's ghost inside the coarse cell */
+                const double gf = XF[cell(M, 0, fl[0], fl[1], fl[2])];
+                F[q1][q2] = (xf - gf) * ihf;
+              }
+            const double Fbar = ((F[0][0] + F[1][0]) + (F[0][1] + F[1][1])) * 0.25;
+            L = L + (Fbar - Fc) * ih;
+            n++;
+          }
+          Lout[acell(N, s, a, b, c)] = L;
+          if (ncf) ncf[acell(N, s, a, b, c)] = (unsigned char)n;
+        }
+  }
+}
+
+static void mgc_pass(mgc_stage* st, int col) {
+  const orc_mesh* m = st->m;
+  const int N = m->N, M = m->M;
+  const int64_t M3 = (int64_t)M * M * M;
+  mgc_refresh(m, st->x);
+  mgc_lap(m, st->x, st->L, st->ncf, col);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double h = dx_level(m, m->key[4 * s]), ih2 = 1.0 / (h * h);
+    double* X = st->x + s * M3;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          if (((a + b + c) & 1) != col) continue;
+          const int64_t q = acell(N, s, a, b, c);
+          const double r = st->b[q] - st->L[q];
+          const double D = (double)(6 + st->ncf[q]) * ih2;
+          double* xc = &X[cell(M, 0, a + G, b + G, c + G)];
+          *xc = *xc - r / D;
+        }
+  }
+}
+
+/* r = f - L phi on every cell into st->L (overwritten). */
+static void mgc_residual(mgc_stage* st) {
+  const int64_t n = st->m->nleaf * (int64_t)st->m->N * st->m->N * st->m->N;
+  mgc_refresh(st->m, st->x);
+  mgc_lap(st->m, st->x, st->L, NULL, -1);
+  for (int64_t q = 0; q < n; q++) st->L[q] = st->b[q] - st->L[q];
+}
+
+static int32_t leaf_of(const orc_mesh* m, int l, int i, int j, int k) {
+  if (l >= m->nlev) return -1;
+  const int64_t q = nidx(m, l, i, j, k);
+  return m->state[l][q] == LEAF ? m->leaf_at[l][q] : -1;
+}
+
+/* Omega_l's residual (in F->L) restricted into C->b (Omega_{l-1}). */
+static void mgc_restrict(const mgc_stage* F, mgc_stage* C) {
+  const orc_mesh* fm = F->m;
+  const orc_mesh* cm = C->m;
+  const int N = cm->N;
+  for (int64_t t = 0; t < cm->nleaf; t++) {
+    const int32_t* kk = cm->key + 4 * t;
+    const int32_t same = leaf_of(fm, kk[0], kk[1], kk[2], kk[3]);
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          double v;
+          if (same >= 0) {
+            v = F->L[acell(N, same, a, b, c)];
+          } else {
+            double w8[8];
+            for (int o = 0; o < 8; o++) {
+              const int fa = 2 * a + (o & 1), fb = 2 * b + ((o >> 1) & 1), fc = 2 * c + (o >> 2);
+              const int32_t fs = leaf_of(fm, kk[0] + 1, 2 * kk[1] + fa / N, 2 * kk[2] + fb / N, 2 * kk[3] + fc / N);
+              w8[o] = F->L[acell(N, fs, fa % N, fb % N, fc % N)];
+            }
+            v = restrict8(w8);
+          }
+          C->b[acell(N, t, a, b, c)] = v;
+        }
+  }
+}
+
+/* Omega_l's x += the interpolation of Omega_{l-1}'s correction (C->x,
+ * refreshed here). */
+static void mgc_prolong_add(mgc_stage* C, mgc_stage* F) {
+  const orc_mesh* cm = C->m;
+  const orc_mesh* fm = F->m;
+  const int N = fm->N, M = fm->M;
+  const int64_t M3 = (int64_t)M * M * M;
+  mgc_refresh(cm, C->x);
+  for (int64_t s = 0; s < fm->nleaf; s++) {
+    const int32_t* kk = fm->key + 4 * s;
+    double* X = F->x + s * M3;
+    const int32_t same = leaf_of(cm, kk[0], kk[1], kk[2], kk[3]);
+    const int32_t par = same >= 0 ? -1 : leaf_of(cm, kk[0] - 1, kk[1] >> 1, kk[2] >> 1, kk[3] >> 1);
+    const double* E = C->x + (same >= 0 ? same : par) * M3;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          double v;
+          if (same >= 0) {
+            v = E[cell(M, 0, a + G, b + G, c + G)];
+          } else {
+            const int g[3] = {(kk[1] & 1) * N + a, (kk[2] & 1) * N + b, (kk[3] & 1) * N + c};
+            const int lc[3] = {g[0] / 2 + G, g[1] / 2 + G, g[2] / 2 + G};
+            double o[3], sl[3];
+            for (int ax = 0; ax < 3; ax++) o[ax] = (g[ax] & 1) ? 1.0 : -1.0;
+            const double u0 = E[cell(M, 0, lc[0], lc[1], lc[2])];
+            if (g_mgc_debug & ORC_MGC_DEBUG_FLAT) {
+              sl[0] = sl[1] = sl[2] = 0.0;
+            } else {
+              sl[0] = 0.5 * (E[cell(M, 0, lc[0] + 1, lc[1], lc[2])] - E[cell(M, 0, lc[0] - 1, lc[1], lc[2])]);
+              sl[1] = 0.5 * (E[cell(M, 0, lc[0], lc[1] + 1, lc[2])] - E[cell(M, 0, lc[0], lc[1] - 1, lc[2])]);
+              sl[2] = 0.5 * (E[cell(M, 0, lc[0], lc[1], lc[2] + 1)] - E[cell(M, 0, lc[0], lc[1], lc[2] - 1)]);
+            }
+            v = ((u0 + (0.25 * o[0]) * sl[0]) + (0.25 * o[1]) * sl[1]) + (0.25 * o[2]) * sl[2];
+          }
+          double* xc = &X[cell(M, 0, a + G, b + G, c + G)];
+          *xc = *xc + v;
+        }
+  }
+}
+
+/* Block storage (per leaf N^3 at level 0) <-> the global root grid. */
+static void root_gather(const orc_mesh* m, const double* blocks, int64_t stride, int off, double* g) {
+  const int N = m->N, n0 = m->d.root[0] * N, n1 = m->d.root[1] * N;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const int32_t* kk = m->key + 4 * s;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          const int64_t q = stride ? s * stride + cell(m->M, 0, a + off, b + off, c + off) : acell(N, s, a, b, c);
+          g[((int64_t)(kk[3] * N + c) * n1 + (kk[2] * N + b)) * n0 + (kk[1] * N + a)] = blocks[q];
+        }
+  }
+}
+static void root_scatter(const orc_mesh* m, const double* g, double* blocks, int64_t stride, int off) {
+  const int N = m->N, n0 = m->d.root[0] * N, n1 = m->d.root[1] * N;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const int32_t* kk = m->key + 4 * s;
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) {
+          const int64_t q = stride ? s * stride + cell(m->M, 0, a + off, b + off, c + off) : acell(N, s, a, b, c);
+          blocks[q] = g[((int64_t)(kk[3] * N + c) * n1 + (kk[2] * N + b)) * n0 + (kk[1] * N + a)];
+        }
+  }
+}
+
+static void mgc_vcycle(mgc_stage* st, int l, int nu1, int nu2) {
+  mgc_stage* S = &st[l];
+  const orc_mesh* m = S->m;
+  const int N = m->N, M = m->M;
+  if (l == 0) {
+    const int n[3] = {m->d.root[0] * N, m->d.root[1] * N, m->d.root[2] * N};
+    const int64_t cnt = (int64_t)n[0] * n[1] * n[2];
+    double* f = (double*)malloc((size_t)cnt * sizeof(double));
+    double* e = (double*)malloc((size_t)cnt * sizeof(double));
+    root_gather(m, S->b, 0, 0, f);
+    orc_mg_vcycle_from_zero(n[0], n[1], n[2], dx_level(m, 0), f, e, nu1, nu2);
+    memset(S->x, 0, (size_t)m->nleaf * M * M * M * sizeof(double));
+    root_scatter(m, e, S->x, (int64_t)M * M * M, G);
+    free(f);
+    free(e);
+    return;
+  }
+  for (int k = 0; k < nu1; k++) {
+    mgc_pass(S, 0);
+    mgc_pass(S, 1);
+  }
+  mgc_residual(S);
+  mgc_restrict(S, &st[l - 1]);
+  /* the correction on the coarser hierarchy level starts from zero */
+  memset(st[l - 1].x, 0, (size_t)st[l - 1].m->nleaf * M * M * M * sizeof(double));
+  mgc_vcycle(st, l - 1, nu1, nu2);
+  mgc_prolong_add(&st[l - 1], S);
+  for (int k = 0; k < nu2; k++) {
+    mgc_pass(S, 0);
+    mgc_pass(S, 1);
+  }
+}
+
+static double weighted_sum(const orc_mesh* m, const double* v, int sq, double* vol) {
+  const int64_t N3 = (int64_t)m->N * m->N * m->N;
+  double tot = 0.0, vv = 0.0;
+  for (int64_t s = 0; s < m->nleaf; s++) {
+    const double w = ldexp(1.0, -3 * m->key[4 * s]);
+    double ls = 0.0;
+    for (int64_t q = 0; q < N3; q++) ls = ls + (sq ? v[s * N3 + q] * v[s * N3 + q] : v[s * N3 + q]);
+    tot = tot + w * ls;
+    vv = vv + w * (double)N3;
+  }
+  if (vol) *vol = vv;
+  return tot;
+}
+
+int orc_mgc_apply(const orc_mesh* m, const double* phi, double* out) {
+  for (int a = 0; a < 3; a++)
+    if (m->d.bc[a] != ORC_BC_PERIODIC) return fail("mg0 on the octree needs periodic boundaries");
+  const int N = m->N, M = m->M;
+  double* x = (double*)calloc((size_t)m->nleaf * M * M * M, sizeof(double));
+  for (int64_t s = 0; s < m->nleaf; s++)
+    for (int c = 0; c < N; c++)
+      for (int b = 0; b < N; b++)
+        for (int a = 0; a < N; a++) x[s * (int64_t)M * M * M + cell(M, 0, a + G, b + G, c + G)] = phi[acell(N, s, a, b, c)];
+  mgc_refresh(m, x);
+  mgc_lap(m, x, out, NULL, -1);
+  free(x);
+  return 0;
+}
+
+int orc_mgc_solve(const orc_mesh* m, const double* f, double* phi, int ncycles, int nu1, int nu2, double* resid) {
+  const int N = m->N, M = m->M;
+  const int64_t M3 = (int64_t)M * M * M, N3 = (int64_t)N * N * N;
+  int n[3];
+  for (int a = 0; a < 3; a++) {
+    if (m->d.bc[a] != ORC_BC_PERIODIC) return fail("mg0 on the octree needs periodic boundaries");
+    n[a] = m->d.root[a] * N;
+  }
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0) return fail("ncycles, nu1 and nu2 must be >= 0");
+  int lmax = 0;
+  for (int64_t s = 0; s < m->nleaf; s++) lmax = m->key[4 * s] > lmax ? m->key[4 * s] : lmax;
+  if (lmax == 0) {
+    /* the uniform solver exactly */
+    const int64_t cnt = (int64_t)n[0] * n[1] * n[2];
+    double* fg = (double*)malloc((size_t)cnt * sizeof(double));
+    double* pg = (double*)malloc((size_t)cnt * sizeof(double));
+    root_gather(m, f, 0, 0, fg);
+    root_gather(m, phi, 0, 0, pg);
+    const int nl = orc_mg_solve(n[0], n[1], n[2], dx_level(m, 0), fg, pg, ncycles, nu1, nu2, resid);
+    root_scatter(m, pg, phi, 0, 0);
+    free(fg);
+    free(pg);
+    return nl;
+  }
+  mgc_stage st[ORC_MAXLEV];
+  memset(st, 0, sizeof st);
+  int rc = 0;
+  for (int l = lmax; l >= 0 && !rc; l--) {
+    if (l == lmax) {
+      st[l].m = m;
+    } else {
+      /* leaves coarser than l and every node of level l */
+      int64_t cnt = 0;
+      for (int64_t s = 0; s < m->nleaf; s++) cnt += m->key[4 * s] < l;
+      const int64_t nl = (int64_t)m->ext[l][0] * m->ext[l][1] * m->ext[l][2];
+      int32_t* keys = (int32_t*)malloc((size_t)(cnt + nl) * 4 * sizeof(int32_t));
+      int64_t k = 0;
+      for (int64_t s = 0; s < m->nleaf; s++)
+        if (m->key[4 * s] < l) memcpy(keys + 4 * k++, m->key + 4 * s, 4 * sizeof(int32_t));
+      for (int kz = 0; kz < m->ext[l][2]; kz++)
+        for (int ky = 0; ky < m->ext[l][1]; ky++)
+          for (int kx = 0; kx < m->ext[l][0]; kx++)
+            if (m->state[l][nidx(m, l, kx, ky, kz)] != ABSENT) {
+              int32_t* e = keys + 4 * k++;
+              e[0] = l; e[1] = kx; e[2] = ky; e[3] = kz;
+            }
+      rc = orc_create_from_leaves(&m->d, k, keys, &st[l].own);
+      free(keys);
+      st[l].m = st[l].own;
+    }
+    if (rc) break;
+    const int64_t nb = st[l].m->nleaf;
+    st[l].x = (double*)calloc((size_t)(nb * M3), sizeof(double));
+    st[l].b = (double*)calloc((size_t)(nb * N3), sizeof(double));
+    st[l].L = (double*)calloc((size_t)(nb * N3), sizeof(double));
+    st[l].ncf = (unsigned char*)calloc((size_t)(nb * N3), 1);
+  }
+  int nlev = -1;
+  if (!rc) {
+    mgc_stage* T = &st[lmax];
+    double vol;
+    const double fm = weighted_sum(m, f, 0, &vol) / vol;
+    for (int64_t q = 0; q < m->nleaf * N3; q++) T->b[q] = f[q] - fm;
+    for (int64_t s = 0; s < m->nleaf; s++)
+      for (int c = 0; c < N; c++)
+        for (int b = 0; b < N; b++)
+          for (int a = 0; a < N; a++) T->x[s * M3 + cell(M, 0, a + G, b + G, c + G)] = phi[acell(N, s, a, b, c)];
+    if (resid) {
+      mgc_residual(T);
+      resid[0] = sqrt(weighted_sum(m, T->L, 1, NULL));
+    }
+    for (int cyc = 0; cyc < ncycles; cyc++) {
+      mgc_vcycle(st, lmax, nu1, nu2);
+      if (resid) {
+        mgc_residual(T);
+        resid[cyc + 1] = sqrt(weighted_sum(m, T->L, 1, NULL));
+      }
+    }
+    for (int64_t s = 0; s < m->nleaf; s++)
+      for (int c = 0; c < N; c++)
+        for (int b = 0; b < N; b++)
+          for (int a = 0; a < N; a++) T->L[acell(N, s, a, b, c)] = T->x[s * M3 + cell(M, 0, a + G, b + G, c + G)];
+    const double pm = weighted_sum(m, T->L, 0, &vol) / vol;
+    for (int64_t q = 0; q < m->nleaf * N3; q++) phi[q] = T->L[q] - pm;
+    nlev = lmax + orc_mg_levels(n[0], n[1], n[2]);
+  }
+  for (int l = 0; l <= lmax; l++) {
+    if (st[l].own) orc_destroy(st[l].own);
+    free(st[l].x);
+    free(st[l].b);
+    free(st[l].L);
+    free(st[l].ncf);
+  }
+  return rc ? -1 : nlev;
 }
 
 /* ------------------------------------------------------------------ */

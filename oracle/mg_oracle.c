@@ -192,6 +192,34 @@ int orc_mg_solve(int nx, int ny, int nz, double h, const double* f, double* phi,
   return nl;
 }
 
+/* One V(nu1, nu2) cycle from phi = 0 on f as given (no mean handling): the
+ * coarse-grid correction the composite solver takes on its root level. */
+int orc_mg_vcycle_from_zero(int nx, int ny, int nz, double h, const double* f, double* phi, int nu1, int nu2) {
+  if (nx < 2 || ny < 2 || nz < 2 || nx % 2 || ny % 2 || nz % 2 || !(h > 0.0)) return -1;
+  const int nl = orc_mg_levels(nx, ny, nz);
+  level_t Ls[MG_MAXLEV];
+  int n[3] = {nx, ny, nz};
+  double hl = h;
+  for (int l = 0; l < nl; l++) {
+    const int64_t cnt = (int64_t)n[0] * n[1] * n[2];
+    memcpy(Ls[l].n, n, sizeof n);
+    Ls[l].h = hl;
+    Ls[l].phi = (double*)calloc((size_t)cnt, sizeof(double));
+    Ls[l].f = (double*)calloc((size_t)cnt, sizeof(double));
+    for (int a = 0; a < 3; a++) n[a] /= 2;
+    hl = 2.0 * hl;
+  }
+  const int64_t n0 = (int64_t)nx * ny * nz;
+  memcpy(Ls[0].f, f, (size_t)n0 * sizeof(double));
+  vcycle(Ls, 0, nl, nu1, nu2);
+  memcpy(phi, Ls[0].phi, (size_t)n0 * sizeof(double));
+  for (int l = 0; l < nl; l++) {
+    free(Ls[l].phi);
+    free(Ls[l].f);
+  }
+  return nl;
+}
+
 /* Test hooks on the building blocks. */
 void orc_mg_prolong_add(int nxc, int nyc, int nzc, const double* coarse, double* fine) {
   level_t C = {{nxc, nyc, nzc}, 1.0, (double*)coarse, NULL};

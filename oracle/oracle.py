@@ -131,6 +131,11 @@ def lib() -> ctypes.CDLL:
         L.orc_mg_levels.argtypes = [I32, I32, I32]
         L.orc_mg_levels.restype = I32
         L.orc_mg_solve.argtypes = [I32, I32, I32, D, P, P, I32, I32, I32, P]
+        L.orc_mgc_set_debug.argtypes = [I32]
+        L.orc_mgc_apply.argtypes = [P, P, P]
+        L.orc_mgc_apply.restype = I32
+        L.orc_mgc_solve.argtypes = [P, P, P, I32, I32, I32, P]
+        L.orc_mgc_solve.restype = I32
         L.orc_mg_solve.restype = I32
         _lib = L
     return _lib
@@ -399,6 +404,41 @@ def mg_solve(f, h, ncycles, nu1=2, nu2=2, phi0=None):
 MG_DEBUG_INJECT = 1
 MG_DEBUG_RESTRICT_SUM = 2
 MG_DEBUG_SMOOTH_SIGN = 4
+MGC_DEBUG_NO_MATCH = 1
+MGC_DEBUG_FLAT = 2
+
+
+def mgc_set_debug(flags: int) -> None:
+    """Plant a known mistake in the composite mg0 oracle (tests of the pins' power only)."""
+    lib().orc_mgc_set_debug(int(flags))
+
+
+def _blocks(om, a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (om.nleaf, om.N, om.N, om.N):
+        raise ValueError("expected [n_leaves, N, N, N] (x fastest)")
+    return a
+
+
+def mgc_apply(om, phi):
+    """The composite-grid Laplacian of phi ([n_leaves, N, N, N], om's leaf
+    order) on om's leaves."""
+    phi = _blocks(om, phi)
+    out = np.zeros_like(phi)
+    if lib().orc_mgc_apply(om._h, _ptr(phi), _ptr(out)) != 0:
+        raise ValueError("composite mg0: " + lib().orc_last_error().decode())
+    return out
+
+
+def mgc_solve(om, f, ncycles, nu1=2, nu2=2, phi0=None):
+    """mg0 on the octree: ncycles composite V(nu1, nu2) cycles for
+    L phi = f on om's leaves; returns (phi, residual norms)."""
+    f = _blocks(om, f)
+    phi = np.zeros_like(f) if phi0 is None else _blocks(om, phi0).copy()
+    res = np.zeros(ncycles + 1)
+    if lib().orc_mgc_solve(om._h, _ptr(f), _ptr(phi), int(ncycles), int(nu1), int(nu2), _ptr(res)) < 0:
+        raise ValueError("composite mg0: " + lib().orc_last_error().decode())
+    return phi, res
 
 
 def mg_set_debug(flags: int) -> None:
