@@ -189,6 +189,12 @@ void orc_mgc_set_debug(int flags);
 int orc_mgc_apply(const orc_mesh* m, const double* phi, double* out);
 int orc_mgc_solve(const orc_mesh* m, const double* f, double* phi, int ncycles, int nu1, int nu2, double* resid);
 
+/* Self-gravity step on any periodic mesh (mg0 on the octree): phi on the
+ * leaves (per leaf N^3, m's leaf order), otherwise as orc_step_gravity,
+ * which it equals bit for bit on an unrefined mesh.  Returns dt, or -1. */
+double orc_step_gravity_amr(orc_mesh* m, int64_t step_index, double four_pi_G, double* phi, int phi_current,
+                            int ncycles, int nu1, int nu2);
+
 /* Remesh (density-slope criterion).  Evaluates the per-leaf indicator on
  * refreshed data, applies refine/coarsen with 2:1 balance and the capacity
  * policy, and returns a new mesh holding the migrated state.  Counters:

@@ -131,6 +131,8 @@ def lib() -> ctypes.CDLL:
         L.orc_mg_levels.argtypes = [I32, I32, I32]
         L.orc_mg_levels.restype = I32
         L.orc_mg_solve.argtypes = [I32, I32, I32, D, P, P, I32, I32, I32, P]
+        L.orc_step_gravity_amr.argtypes = [P, I64, D, P, I32, I32, I32, I32]
+        L.orc_step_gravity_amr.restype = D
         L.orc_mgc_set_debug.argtypes = [I32]
         L.orc_mgc_apply.argtypes = [P, P, P]
         L.orc_mgc_apply.restype = I32
@@ -270,6 +272,18 @@ class OracleMesh:
                                           int(ncycles), int(nu1), int(nu2)))
         if dt < 0:
             raise ValueError("oracle gravity: " + lib().orc_last_error().decode())
+        return dt
+
+    def step_gravity_amr(self, k: int, four_pi_G: float, phi: np.ndarray, phi_current: bool, ncycles: int = 2,
+                         nu1: int = 2, nu2: int = 2) -> float:
+        """Self-gravity step on any periodic mesh, phi [n_leaves, N, N, N]
+        (updated in place) from mg0 on the octree; returns dt."""
+        if phi.dtype != np.float64 or not phi.flags.c_contiguous or phi.shape != (self.nleaf,) + (self.N,) * 3:
+            raise ValueError("phi must be a contiguous float64 [n_leaves, N, N, N] array")
+        dt = lib().orc_step_gravity_amr(self._h, int(k), float(four_pi_G), _ptr(phi), int(bool(phi_current)),
+                                        int(ncycles), int(nu1), int(nu2))
+        if dt < 0:
+            raise ValueError("oracle gravity step: " + lib().orc_last_error().decode())
         return dt
 
     def step_gravity_comoving(self, k: int, dt: float, a0: float, a_mid: float, a1: float, hubble: float,
