@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libamr.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "tracers.hip", "comoving.hip", "poisson.hip", "mesh.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "tracers.hip", "comoving.hip", "poisson.hip", "composite.hip", "mesh.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

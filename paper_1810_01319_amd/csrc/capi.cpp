@@ -3,11 +3,13 @@
 
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 
 #include "../../include/amr.h"
 #include "adjoint.hpp"
+#include "composite.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
 #include "poisson.hpp"
@@ -47,6 +49,24 @@ struct Profiler {
   }
 };
 
+// mg0 on the octree: the hierarchy of coarsened meshes of a refined mesh and
+// the layout of the solver's workspace (tables of the coarser stages, per
+// stage the padded correction x, right-hand side b and operator values L,
+// the transfer tasks between neighbouring stages, the uniform solver's
+// levels of the root grid, reduction scratch).
+struct CompositeMg {
+  int lmax = 0;
+  std::vector<std::unique_ptr<Octree>> trees;  // stages 0 .. lmax-1 (stage lmax is the mesh)
+  std::vector<Plan> plans;                     // stages 0 .. lmax-1
+  std::vector<std::vector<MigrTask>> rtask;    // stage l < lmax: per leaf, from stage l+1
+  std::vector<std::vector<MigrTask>> ptask;    // stage l >= 1: per leaf, from stage l-1
+  std::vector<int64_t> nleaf;                  // stages 0 .. lmax
+  std::vector<int64_t> off_plan, off_x, off_b, off_L, off_r, off_p;
+  int64_t off_mg = 0, off_parts = 0, off_scal = 0, total = 0, tables = 0;
+  double volume = 0.0;                         // volume-weighted cell count of the mesh
+  std::vector<unsigned char> staging;          // bytes [0, tables) of the workspace
+};
+
 struct amr_mesh {
   std::vector<std::unique_ptr<Octree>> trees;  // one per instance
   Octree* tree = nullptr;                      // trees[0]
@@ -54,6 +74,7 @@ struct amr_mesh {
   unsigned char* ws = nullptr;  // caller-owned device workspace
   LaunchCfg cfg;
   Profiler prof;
+  std::unique_ptr<CompositeMg> comp;  // built on first use by the Poisson entries on a refined mesh
 };
 
 namespace {
@@ -139,10 +160,8 @@ int64_t adjoint_scratch(const Plan& p) {
   return adjoint_face_bytes(p) + 3 * field + 256;
 }
 
-DevPlan dev_plan(const amr_mesh* h) {
-  const Plan& p = h->plan;
+DevPlan dev_plan_at(const Plan& p, unsigned char* w) {
   DevPlan P{};
-  unsigned char* w = h->ws;
   P.inst = reinterpret_cast<const InstParams*>(w + p.off.inst);
   P.blocks = reinterpret_cast<const BlockInfo*>(w + p.off.blocks);
   P.nbr = reinterpret_cast<const Nbr*>(w + p.off.nbr);
@@ -169,6 +188,8 @@ DevPlan dev_plan(const amr_mesh* h) {
   P.nf = p.nf;
   return P;
 }
+
+DevPlan dev_plan(const amr_mesh* h) { return dev_plan_at(h->plan, h->ws); }
 
 amr_status check_ready(const amr_mesh* h, const void* U) {
   if (!h) return fail(AMR_E_INVALID, "null mesh");
@@ -946,13 +967,352 @@ amr_status poisson_grid(const amr_mesh* h, int n[3]) {
 
 }  // namespace
 
+namespace {
+
+// The root grid of a single periodic mesh (refined or not) for the Poisson
+// entries; *refined says whether any leaf lies below level 0.
+amr_status poisson_root(const amr_mesh* h, int n[3], bool* refined) {
+  const Plan& p = h->plan;
+  if (p.inst.size() != 1) return fail(AMR_E_INVALID, "the Poisson solver takes one mesh, not a batch");
+  *refined = false;
+  for (const Key& k : p.keys) *refined = *refined || k.l != 0;
+  const InstParams& ip = p.inst[0];
+  for (int a = 0; a < 3; a++) {
+    if (ip.bc[a] != AMR_BC_PERIODIC) return fail(AMR_E_INVALID, "the Poisson solver needs periodic boundaries");
+    n[a] = ip.root[a] * p.N;
+  }
+  int sz[kMgMaxLevels][3];
+  const int nl = mg_levels(n[0], n[1], n[2], sz);
+  if (int64_t(sz[nl - 1][0]) * sz[nl - 1][1] * sz[nl - 1][2] > kMgCoarseMax)
+    return fail(AMR_E_INVALID, "the Poisson solver's coarsest level exceeds 4096 cells (odd parts of the root extents too large)");
+  return AMR_OK;
+}
+
+inline uint64_t pack_key(int l, int i, int j, int k) {
+  return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
+}
+
+// The hierarchy of mg0 on the octree: stage l (0 <= l < lmax) = the leaves
+// coarser than l and every node of level l; stage lmax = the mesh.
+amr_status build_composite(amr_mesh* h, const int n[3]) {
+  if (h->comp) return AMR_OK;
+  std::unique_ptr<CompositeMg> C(new (std::nothrow) CompositeMg());
+  if (!C) return fail(AMR_E_NOMEM, "out of host memory");
+  const Plan& top = h->plan;
+  const Octree& T = *h->tree;
+  const int N = top.N, M = N + 2 * kGhost;
+  int lmax = 0;
+  for (const Key& k : top.keys) lmax = std::max(lmax, int(k.l));
+  C->lmax = lmax;
+  C->plans.resize(size_t(lmax));
+  C->nleaf.assign(size_t(lmax + 1), 0);
+  std::vector<FlatMap<int32_t>> index(size_t(lmax + 1));
+  for (int l = 0; l < lmax; l++) {
+    std::vector<int32_t> keys;
+    for (const Key& k : top.keys)
+      if (k.l < l) keys.insert(keys.end(), {k.l, k.i, k.j, k.k});
+    for (int kz = 0; kz < T.ext(l, 2); kz++)
+      for (int ky = 0; ky < T.ext(l, 1); ky++)
+        for (int kx = 0; kx < T.ext(l, 0); kx++)
+          if (T.state(l, kx, ky, kz) != Octree::ABSENT) keys.insert(keys.end(), {int32_t(l), kx, ky, kz});
+    C->trees.emplace_back(new Octree(T.desc()));
+    std::string e = C->trees.back()->from_leaves(keys.data(), int64_t(keys.size() / 4));
+    if (e.empty()) e = C->plans[size_t(l)].build({C->trees.back().get()});
+    if (!e.empty()) return fail(AMR_E_BALANCE, "mg0 hierarchy stage " + std::to_string(l) + ": " + e);
+  }
+  for (int l = 0; l <= lmax; l++) {
+    const Plan& P = l == lmax ? top : C->plans[size_t(l)];
+    C->nleaf[size_t(l)] = P.nleaf;
+    index[size_t(l)].reserve(size_t(P.nleaf));
+    for (int64_t s = 0; s < P.nleaf; s++) {
+      const Key& k = P.keys[size_t(s)];
+      index[size_t(l)][pack_key(k.l, k.i, k.j, k.k)] = int32_t(s);
+    }
+  }
+  auto find = [&](int stage, int l, int i, int j, int k) -> int32_t {
+    const int32_t* v = index[size_t(stage)].find(pack_key(l, i, j, k));
+    return v ? *v : -1;
+  };
+  C->rtask.resize(size_t(lmax));
+  C->ptask.resize(size_t(lmax + 1));
+  for (int l = 0; l < lmax; l++) {
+    const Plan& P = C->plans[size_t(l)];
+    for (int64_t s = 0; s < P.nleaf; s++) {
+      const Key& k = P.keys[size_t(s)];
+      MigrTask t{};
+      const int32_t same = find(l + 1, k.l, k.i, k.j, k.k);
+      if (same >= 0) {
+        t.kind = MIGR_COPY;
+        t.src[0] = same;
+      } else {
+        t.kind = MIGR_RESTRICT;
+        for (int o = 0; o < 8; o++) {
+          t.src[o] = find(l + 1, k.l + 1, 2 * k.i + (o & 1), 2 * k.j + ((o >> 1) & 1), 2 * k.k + (o >> 2));
+          if (t.src[o] < 0) return fail(AMR_E_BALANCE, "mg0 hierarchy: missing child");
+        }
+      }
+      C->rtask[size_t(l)].push_back(t);
+    }
+  }
+  for (int l = 1; l <= lmax; l++) {
+    const Plan& P = l == lmax ? top : C->plans[size_t(l)];
+    for (int64_t s = 0; s < P.nleaf; s++) {
+      const Key& k = P.keys[size_t(s)];
+      MigrTask t{};
+      const int32_t same = find(l - 1, k.l, k.i, k.j, k.k);
+      if (same >= 0) {
+        t.kind = MIGR_COPY;
+        t.src[0] = same;
+      } else {
+        t.kind = MIGR_PROLONG;
+        t.co = (k.i & 1) + 2 * (k.j & 1) + 4 * (k.k & 1);
+        t.src[0] = find(l - 1, k.l - 1, k.i >> 1, k.j >> 1, k.k >> 1);
+        if (t.src[0] < 0) return fail(AMR_E_BALANCE, "mg0 hierarchy: missing parent");
+      }
+      C->ptask[size_t(l)].push_back(t);
+    }
+  }
+  auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
+  const int64_t M3 = int64_t(M) * M * M, N3 = int64_t(N) * N * N;
+  int64_t o = 0;
+  C->off_plan.assign(size_t(lmax + 1), 0);
+  C->off_r.assign(size_t(lmax + 1), 0);
+  C->off_p.assign(size_t(lmax + 1), 0);
+  for (int l = 0; l < lmax; l++) {
+    C->off_plan[size_t(l)] = o;
+    o = al(o + C->plans[size_t(l)].off.total);
+  }
+  for (int l = 0; l <= lmax; l++) {
+    C->off_r[size_t(l)] = o;
+    if (l < lmax) o = al(o + int64_t(C->rtask[size_t(l)].size() * sizeof(MigrTask)));
+    C->off_p[size_t(l)] = o;
+    if (l >= 1) o = al(o + int64_t(C->ptask[size_t(l)].size() * sizeof(MigrTask)));
+  }
+  C->tables = o;
+  C->off_x.assign(size_t(lmax + 1), 0);
+  C->off_b.assign(size_t(lmax + 1), 0);
+  C->off_L.assign(size_t(lmax + 1), 0);
+  for (int l = 0; l <= lmax; l++) {
+    const int64_t nb = C->nleaf[size_t(l)];
+    C->off_x[size_t(l)] = o; o = al(o + nb * M3 * 8);
+    C->off_b[size_t(l)] = o; o = al(o + nb * N3 * 8);
+    C->off_L[size_t(l)] = o; o = al(o + nb * N3 * 8);
+  }
+  C->off_mg = o; o = al(o + mg_workspace_bytes(n[0], n[1], n[2]));
+  C->off_parts = o; o = al(o + top.nleaf * 8);
+  C->off_scal = o; o = al(o + 8 * 8);
+  C->total = o;
+  C->staging.assign(size_t(C->tables), 0);
+  for (int l = 0; l < lmax; l++) {
+    const Plan& P = C->plans[size_t(l)];
+    std::memcpy(C->staging.data() + C->off_plan[size_t(l)], P.staging.data(), P.staging.size());
+    std::memcpy(C->staging.data() + C->off_r[size_t(l)], C->rtask[size_t(l)].data(),
+                C->rtask[size_t(l)].size() * sizeof(MigrTask));
+  }
+  for (int l = 1; l <= lmax; l++)
+    std::memcpy(C->staging.data() + C->off_p[size_t(l)], C->ptask[size_t(l)].data(),
+                C->ptask[size_t(l)].size() * sizeof(MigrTask));
+  C->volume = 0.0;
+  for (const Key& k : top.keys) C->volume += std::ldexp(double(N3), -3 * k.l);
+  h->comp = std::move(C);
+  return AMR_OK;
+}
+
+amr_status poisson_bytes(amr_mesh* h, int64_t* bytes) {
+  int n[3];
+  bool refined = false;
+  amr_status rc = poisson_root(h, n, &refined);
+  if (rc != AMR_OK) return rc;
+  if (!refined) {
+    *bytes = mg_workspace_bytes(n[0], n[1], n[2]);
+    return AMR_OK;
+  }
+  rc = build_composite(h, n);
+  if (rc != AMR_OK) return rc;
+  *bytes = h->comp->total;
+  return AMR_OK;
+}
+
+// The composite V-cycles (the hierarchy and its workspace layout built).
+hipError_t composite_solve(amr_mesh* h, const int n[3], const double* f, double* phi, int ncycles, int nu1, int nu2,
+                           double* resid, unsigned char* work, hipStream_t st) {
+  const CompositeMg& C = *h->comp;
+  const int lmax = C.lmax;
+  const int N = h->plan.N;
+  const int64_t N3 = int64_t(N) * N * N;
+  hipError_t e = hipMemcpyAsync(work, C.staging.data(), size_t(C.tables), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  std::vector<DevPlan> SP(size_t(lmax + 1));
+  std::vector<double*> X(size_t(lmax + 1)), B(size_t(lmax + 1)), L(size_t(lmax + 1));
+  for (int l = 0; l <= lmax; l++) {
+    SP[size_t(l)] = l == lmax ? dev_plan(h) : dev_plan_at(C.plans[size_t(l)], work + C.off_plan[size_t(l)]);
+    X[size_t(l)] = reinterpret_cast<double*>(work + C.off_x[size_t(l)]);
+    B[size_t(l)] = reinterpret_cast<double*>(work + C.off_b[size_t(l)]);
+    L[size_t(l)] = reinterpret_cast<double*>(work + C.off_L[size_t(l)]);
+  }
+  double* parts = reinterpret_cast<double*>(work + C.off_parts);
+  double* scal = reinterpret_cast<double*>(work + C.off_scal);
+  auto op = [&](int kind, int l) {
+    CzOp o;
+    o.kind = kind;
+    o.P = SP[size_t(l)];
+    o.x = X[size_t(l)];
+    o.b = B[size_t(l)];
+    o.L = L[size_t(l)];
+    o.parts = parts;
+    o.scal = scal;
+    return o;
+  };
+  auto operator_on = [&](int l, int col) {
+    hipError_t r = launch_refresh_scalar(SP[size_t(l)], X[size_t(l)], st);
+    if (r != hipSuccess) return r;
+    CzOp o = op(CZ_OPERATOR, l);
+    o.col = col;
+    return cz_launch(o, st);
+  };
+  auto pass = [&](int l, int col) {
+    hipError_t r = operator_on(l, col);
+    if (r != hipSuccess) return r;
+    CzOp o = op(CZ_UPDATE, l);
+    o.col = col;
+    return cz_launch(o, st);
+  };
+  auto residual = [&](int l) {
+    hipError_t r = operator_on(l, -1);
+    return r != hipSuccess ? r : cz_launch(op(CZ_RESID, l), st);
+  };
+  const double dx0 = 1.0 / double(int64_t(h->plan.inst[0].root[0]) * N);
+  std::function<hipError_t(int)> vcycle = [&](int l) -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (l == 0)
+      return mg_vcycle_blocks(SP[0], n[0], n[1], n[2], dx0, B[0], X[0], nu1, nu2, work + C.off_mg, st);
+    for (int k = 0; k < nu1 && r == hipSuccess; k++) {
+      r = pass(l, 0);
+      if (r == hipSuccess) r = pass(l, 1);
+    }
+    if (r == hipSuccess) r = residual(l);
+    if (r == hipSuccess) {
+      CzOp o = op(CZ_RESTRICT, l - 1);
+      o.L = L[size_t(l)];
+      o.tasks = reinterpret_cast<const MigrTask*>(work + C.off_r[size_t(l - 1)]);
+      r = cz_launch(o, st);
+    }
+    if (r == hipSuccess) r = cz_launch(op(CZ_ZERO, l - 1), st);
+    if (r == hipSuccess) r = vcycle(l - 1);
+    if (r == hipSuccess) r = launch_refresh_scalar(SP[size_t(l - 1)], X[size_t(l - 1)], st);
+    if (r == hipSuccess) {
+      CzOp o = op(CZ_PROLONG, l);
+      o.e = X[size_t(l - 1)];
+      o.tasks = reinterpret_cast<const MigrTask*>(work + C.off_p[size_t(l)]);
+      r = cz_launch(o, st);
+    }
+    for (int k = 0; k < nu2 && r == hipSuccess; k++) {
+      r = pass(l, 0);
+      if (r == hipSuccess) r = pass(l, 1);
+    }
+    return r;
+  };
+  if (f != B[size_t(lmax)]) {
+    e = hipMemcpyAsync(B[size_t(lmax)], f, size_t(h->plan.nleaf * N3 * 8), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  CzOp mo = op(CZ_MEAN_SUB, lmax);
+  mo.scale = 1.0 / C.volume;
+  if ((e = cz_launch(mo, st)) != hipSuccess) return e;
+  if ((e = cz_launch(op(CZ_ZERO, lmax), st)) != hipSuccess) return e;
+  CzOp ci = op(CZ_COPY_IN, lmax);
+  ci.src = phi;
+  if ((e = cz_launch(ci, st)) != hipSuccess) return e;
+  auto norm = [&](int c) {
+    if (!resid) return hipSuccess;
+    hipError_t r = residual(lmax);
+    if (r != hipSuccess) return r;
+    CzOp o = op(CZ_NORM, lmax);
+    o.scal = resid + c;
+    return cz_launch(o, st);
+  };
+  if ((e = norm(0)) != hipSuccess) return e;
+  for (int c = 0; c < ncycles; c++) {
+    if ((e = vcycle(lmax)) != hipSuccess) return e;
+    if ((e = norm(c + 1)) != hipSuccess) return e;
+  }
+  CzOp mp = op(CZ_MEAN_PADDED, lmax);
+  mp.scale = 1.0 / C.volume;
+  mp.scal = scal + 1;
+  if ((e = cz_launch(mp, st)) != hipSuccess) return e;
+  CzOp co = op(CZ_COPY_OUT, lmax);
+  co.dst = phi;
+  co.scal = scal + 1;
+  return cz_launch(co, st);
+}
+
+amr_status poisson_run(amr_mesh* h, const double* f, double* phi, int32_t ncycles, int32_t nu1, int32_t nu2,
+                       double* resid, void* work, int64_t work_cap, void* stream) {
+  int n[3];
+  bool refined = false;
+  amr_status rc = poisson_root(h, n, &refined);
+  if (rc != AMR_OK) return rc;
+  int64_t need = 0;
+  rc = poisson_bytes(h, &need);
+  if (rc != AMR_OK) return rc;
+  if (work_cap >= 0 && need > work_cap)
+    return fail(AMR_E_CAPACITY, "grid of " + std::to_string(n[0]) + "x" + std::to_string(n[1]) + "x" +
+                                    std::to_string(n[2]) + " needs a " + std::to_string(need) +
+                                    "-byte workspace, above the fixed buffer's " + std::to_string(work_cap) +
+                                    " bytes (use amr_poisson_solve)");
+  const Plan& p = h->plan;
+  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = timed(h, AMR_PHASE_POISSON, st, [&] {
+    if (refined)
+      return composite_solve(h, n, f, phi, ncycles, nu1, nu2, resid, static_cast<unsigned char*>(work), st);
+    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, nullptr, 0.0, phi, ncycles, nu1, nu2, resid, work, st);
+  });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
+}
+
+// Self-gravity pieces on a refined mesh (composite layout of work): the
+// solve for four_pi_G times U's density, and a half kick with -grad(phi).
+hipError_t composite_gravity_solve(amr_mesh* h, const int n[3], const double* U, double four_pi_G, double* phi,
+                                   int ncycles, int nu1, int nu2, unsigned char* work, hipStream_t st) {
+  const CompositeMg& C = *h->comp;
+  double* b = reinterpret_cast<double*>(work + C.off_b[size_t(C.lmax)]);
+  CzOp o;
+  o.kind = CZ_DENSITY;
+  o.P = dev_plan(h);
+  o.U = const_cast<double*>(U);
+  o.b = b;
+  o.fpg = four_pi_G;
+  hipError_t e = cz_launch(o, st);
+  if (e != hipSuccess) return e;
+  return composite_solve(h, n, b, phi, ncycles, nu1, nu2, nullptr, work, st);
+}
+
+hipError_t composite_kick(amr_mesh* h, double* U, const double* phi, const double* dt, double scale,
+                          unsigned char* work, hipStream_t st) {
+  const CompositeMg& C = *h->comp;
+  CzOp o;
+  o.P = dev_plan(h);
+  o.x = reinterpret_cast<double*>(work + C.off_x[size_t(C.lmax)]);
+  o.kind = CZ_ZERO;
+  hipError_t e = cz_launch(o, st);
+  o.kind = CZ_COPY_IN;
+  o.src = phi;
+  if (e == hipSuccess) e = cz_launch(o, st);
+  if (e == hipSuccess) e = launch_refresh_scalar(o.P, o.x, st);
+  o.kind = CZ_KICK;
+  o.U = U;
+  o.dt = dt;
+  o.scale = scale;
+  if (e == hipSuccess) e = cz_launch(o, st);
+  return e;
+}
+
+}  // namespace
+
 amr_status amr_poisson_workspace_bytes(const amr_mesh* h, int64_t* bytes) {
   if (!h || !bytes) return fail(AMR_E_INVALID, "null argument");
-  int n[3];
-  amr_status rc = poisson_grid(h, n);
-  if (rc != AMR_OK) return rc;
-  *bytes = mg_workspace_bytes(n[0], n[1], n[2]);
-  return AMR_OK;
+  return poisson_bytes(const_cast<amr_mesh*>(h), bytes);
 }
 
 amr_status amr_poisson_solve(amr_mesh* h, const double* f, double* phi, int32_t ncycles, int32_t nu1, int32_t nu2,
@@ -962,16 +1322,7 @@ amr_status amr_poisson_solve(amr_mesh* h, const double* f, double* phi, int32_t 
   if (!f || !phi || !work) return fail(AMR_E_INVALID, "null argument");
   if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
     return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
-  int n[3];
-  amr_status rc = poisson_grid(h, n);
-  if (rc != AMR_OK) return rc;
-  const Plan& p = h->plan;
-  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = timed(h, AMR_PHASE_POISSON, st, [&] {
-    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, nullptr, 0.0, phi, ncycles, nu1, nu2, resid, work, st);
-  });
-  return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
+  return poisson_run(h, f, phi, ncycles, nu1, nu2, resid, work, -1, stream);
 }
 
 amr_status amr_poisson_solve_static(amr_mesh* h, const double* f, double* phi, int32_t ncycles, int32_t nu1,
@@ -981,25 +1332,15 @@ amr_status amr_poisson_solve_static(amr_mesh* h, const double* f, double* phi, i
   if (!f || !phi) return fail(AMR_E_INVALID, "null argument");
   if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
     return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
-  int n[3];
-  amr_status rc = poisson_grid(h, n);
+  int64_t need = 0;
+  amr_status rc = poisson_bytes(h, &need);
   if (rc != AMR_OK) return rc;
-  const int64_t need = mg_workspace_bytes(n[0], n[1], n[2]);
-  if (need > kMgStaticScratchBytes)
-    return fail(AMR_E_CAPACITY, "grid of " + std::to_string(n[0]) + "x" + std::to_string(n[1]) + "x" +
-                                    std::to_string(n[2]) + " needs a " + std::to_string(need) +
-                                    "-byte workspace, above the fixed buffer's " +
-                                    std::to_string(kMgStaticScratchBytes) + " bytes (use amr_poisson_solve)");
+  if (need > kMgStaticScratchBytes) return poisson_run(h, f, phi, ncycles, nu1, nu2, resid, nullptr,
+                                                       kMgStaticScratchBytes, stream);
   void* work = nullptr;
   hipError_t e = mg_static_scratch(&work);
   if (e != hipSuccess) return hip_fail(e, "poisson fixed workspace");
-  const Plan& p = h->plan;
-  const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  e = timed(h, AMR_PHASE_POISSON, st, [&] {
-    return mg_solve(dev_plan(h), n[0], n[1], n[2], dx, f, nullptr, 0.0, phi, ncycles, nu1, nu2, resid, work, st);
-  });
-  return e == hipSuccess ? AMR_OK : hip_fail(e, "poisson");
+  return poisson_run(h, f, phi, ncycles, nu1, nu2, resid, work, kMgStaticScratchBytes, stream);
 }
 
 amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t step_index, double four_pi_G,
@@ -1012,19 +1353,28 @@ amr_status amr_hydro_step_gravity(amr_mesh* h, double* U, double* dt, int64_t st
   if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu1 > 64 || nu2 > 64)
     return fail(AMR_E_INVALID, "ncycles must be >= 0 and nu1, nu2 in [0, 64]");
   int n[3];
-  rc = poisson_grid(h, n);
+  bool refined = false;
+  rc = poisson_root(h, n, &refined);
   if (rc != AMR_OK) return rc;
+  if (refined) {
+    int64_t need = 0;
+    rc = poisson_bytes(h, &need);
+    if (rc != AMR_OK) return rc;
+  }
   const Plan& p = h->plan;
   const double dx = 1.0 / double(int64_t(p.inst[0].root[0]) * p.N);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevPlan P = dev_plan(h);
+  unsigned char* wb = static_cast<unsigned char*>(work);
   auto solve = [&] {
     return timed(h, AMR_PHASE_POISSON, st, [&] {
+      if (refined) return composite_gravity_solve(h, n, U, four_pi_G, phi, ncycles, nu1, nu2, wb, st);
       return mg_solve(P, n[0], n[1], n[2], dx, nullptr, U, four_pi_G, phi, ncycles, nu1, nu2, nullptr, work, st);
     });
   };
   auto kick = [&](bool after_solve) {
     return timed(h, AMR_PHASE_POISSON, st, [&] {
+      if (refined) return composite_kick(h, U, phi, dt, 1.0, wb, st);
       return mg_kick(P, n[0], n[1], n[2], dx, U, phi, dt, 1.0, work, st, 0, nullptr, 0.0, after_solve);
     });
   };

@@ -76,8 +76,9 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 }
 
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
-// and phase-1 ghost cells are complete.
-template <int N, int NF>
+// and phase-1 ghost cells are complete.  LIN: unlimited central slopes
+// 0.5 (u(+1) - u(-1)) (the composite Poisson operator's interpolation).
+template <int N, int NF, bool LIN = false>
 __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -108,9 +109,16 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
   for (int f = 0; f < NF; f++) {
     const double* q = src + f * M3;
     const double u0 = q[0];
-    const double sx = minmod(q[1] - u0, u0 - q[-1]);
-    const double sy = minmod(q[M] - u0, u0 - q[-M]);
-    const double sz = minmod(q[M * M] - u0, u0 - q[-M * M]);
+    double sx, sy, sz;
+    if (LIN) {
+      sx = 0.5 * (q[1] - q[-1]);
+      sy = 0.5 * (q[M] - q[-M]);
+      sz = 0.5 * (q[M * M] - q[-M * M]);
+    } else {
+      sx = minmod(q[1] - u0, u0 - q[-1]);
+      sy = minmod(q[M] - u0, u0 - q[-M]);
+      sz = minmod(q[M * M] - u0, u0 - q[-M * M]);
+    }
     dst[f * M3] = ((u0 + ox * sx) + oy * sy) + oz * sz;
   }
 }
@@ -975,6 +983,25 @@ hipError_t reflux_n(const DevPlan& P, double* U, const double* dt, int dir, cons
 
 }  // namespace
 
+
+template <int N>
+hipError_t refresh_scalar_n(const DevPlan& P, double* x, hipStream_t st) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
+  if (P.nleaf > 0) hipLaunchKernelGGL((refresh_phase1<N, 1>), dim3(grid_for(P.nleaf * GC, 256)), dim3(256), 0, st, x, P);
+  if (P.np2 > 0)
+    hipLaunchKernelGGL((refresh_phase2<N, 1, true>), dim3(grid_for(P.np2 * GC, 256)), dim3(256), 0, st, x, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_scalar(const DevPlan& P, double* x, hipStream_t st) {
+  switch (P.N) {
+    case 8: return refresh_scalar_n<8>(P, x, st);
+    case 16: return refresh_scalar_n<16>(P, x, st);
+    case 32: return refresh_scalar_n<32>(P, x, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
   switch (P.N) {

@@ -40,6 +40,10 @@ struct LaunchCfg {
 };
 
 hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st);
+// Refresh of one padded field (per leaf M^3) with unlimited linear
+// prolongation into ghosts over a coarser leaf (the composite Poisson
+// operator's ghosts).
+hipError_t launch_refresh_scalar(const DevPlan& P, double* x, hipStream_t st);
 // dt = (C_cfl * a) * min ...; a = 1 outside comoving steps
 hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st,
                       double a = 1.0);

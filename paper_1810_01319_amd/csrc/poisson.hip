@@ -210,10 +210,26 @@ __global__ void __launch_bounds__(256) mg_gather(const double* __restrict__ fb, 
   const int a = q % N, b = (q / N) % N, c = q / (N * N);
   const BlockInfo bi = P.blocks[s];
   const int64_t g = lidx(L, bi.i * N + a, bi.j * N + b, bi.k * N + c);
-  if (SRC == 0) L.f[g] = fb[t];
+  if (SRC == 0 || SRC == 3) L.f[g] = fb[t];
   if (SRC == 1)
     L.f[g] = fpg * U[int64_t(s) * P.nf * M * M * M + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost)];
-  L.phi[g] = pb[t];
+  L.phi[g] = SRC == 3 ? 0.0 : pb[t];
+}
+
+// Level 0's phi into the active cells of a padded one-field block layout
+// (per leaf M^3), as it is.
+template <int N>
+__global__ void __launch_bounds__(256) mg_scatter_padded(Lvl L, DevPlan P, double* __restrict__ x) {
+  constexpr int N3 = N * N * N;
+  constexpr int M = N + 2 * kGhost;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const int a = q % N, b = (q / N) % N, c = q / (N * N);
+  const BlockInfo bi = P.blocks[s];
+  x[int64_t(s) * M * M * M + (int64_t(c + kGhost) * M + (b + kGhost)) * M + (a + kGhost)] =
+      L.phi[lidx(L, bi.i * N + a, bi.j * N + b, bi.k * N + c)];
 }
 
 // Half kick of the active cells with g = -grad(phi) (central differences of
@@ -466,6 +482,61 @@ double* mg_half_dt(const double* dt, void* work, int nx, int ny, int nz, hipStre
   return slot;
 }
 
+namespace {
+
+// One V(nu1, nu2) cycle on the levels Ls (level 0 holds f and the initial phi).
+void vcycle(const Lvl* Ls, int nl, int nu1, int nu2, hipStream_t st) {
+  // rows of n cells: workgroups of up to 256 lanes along x, gx of them per
+  // (y, z) row (block_row maps them to rows)
+  auto rows = [](int n, int ny, int nz, dim3& g, dim3& blk, int& gx) {
+    const int bs = n >= 256 ? 256 : (n + 63) / 64 * 64;
+    blk = dim3(bs);
+    gx = (n + bs - 1) / bs;
+    g = dim3(unsigned(gx), unsigned(ny), unsigned(nz));
+  };
+  auto smooth = [&](const Lvl& L, int sweeps) {
+    dim3 g, blk;
+    int gx;
+    rows(L.nx / 2, L.ny, L.nz, g, blk, gx);
+    for (int s = 0; s < sweeps; s++)
+      for (int color = 0; color < 2; color++) hipLaunchKernelGGL(mg_rbgs, g, blk, 0, st, L, color, gx);
+  };
+  for (int l = 0; l < nl - 1; l++) {
+    smooth(Ls[l], nu1);
+    dim3 g, blk;
+    int gx;
+    rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);
+    hipLaunchKernelGGL(mg_restrict, g, blk, 0, st, Ls[l], Ls[l + 1], gx);
+  }
+  hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
+  for (int l = nl - 2; l >= 0; l--) {
+    dim3 g, blk;
+    int gx;
+    rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);  // coarse cells
+    hipLaunchKernelGGL(mg_prolong_add, g, blk, 0, st, Ls[l + 1], Ls[l], gx);
+    smooth(Ls[l], nu2);
+  }
+}
+
+}  // namespace
+
+hipError_t mg_vcycle_blocks(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks,
+                            double* x_padded, int nu1, int nu2, void* work, hipStream_t st) {
+  Lvl Ls[kMgMaxLevels];
+  int nl;
+  double* parts;
+  levels_in(work, nx, ny, nz, h, Ls, nl, parts);
+  if (P.N != 8 && P.N != 16 && P.N != 32) return hipErrorInvalidValue;
+  gather_n<3>(P, f_blocks, nullptr, 0.0, nullptr, Ls[0], st);
+  vcycle(Ls, nl, nu1, nu2, st);
+  const int64_t nb = P.nleaf * int64_t(P.N) * P.N * P.N;
+  const dim3 g(grid_for(nb, 256)), b(256);
+  if (P.N == 8) hipLaunchKernelGGL(mg_scatter_padded<8>, g, b, 0, st, Ls[0], P, x_padded);
+  else if (P.N == 16) hipLaunchKernelGGL(mg_scatter_padded<16>, g, b, 0, st, Ls[0], P, x_padded);
+  else hipLaunchKernelGGL(mg_scatter_padded<32>, g, b, 0, st, Ls[0], P, x_padded);
+  return hipGetLastError();
+}
+
 hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, const double* U,
                     double fpg, double* phi_blocks, int ncycles, int nu1, int nu2, double* resid, void* work,
                     hipStream_t st) {
@@ -488,38 +559,9 @@ hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const do
     hipLaunchKernelGGL(mg_sum_parts<1>, dim3(kRedParts), dim3(kRedBlock), 0, st, nullptr, Ls[0], n0, parts);
     hipLaunchKernelGGL(mg_sum_final<1>, dim3(1), dim3(kRedBlock), 0, st, parts, 1.0, resid + c);
   };
-  // rows of n cells: workgroups of up to 256 lanes along x, gx of them per
-  // (y, z) row (block_row maps them to rows)
-  auto rows = [](int n, int ny, int nz, dim3& g, dim3& blk, int& gx) {
-    const int bs = n >= 256 ? 256 : (n + 63) / 64 * 64;
-    blk = dim3(bs);
-    gx = (n + bs - 1) / bs;
-    g = dim3(unsigned(gx), unsigned(ny), unsigned(nz));
-  };
-  auto smooth = [&](const Lvl& L, int sweeps) {
-    dim3 g, blk;
-    int gx;
-    rows(L.nx / 2, L.ny, L.nz, g, blk, gx);
-    for (int s = 0; s < sweeps; s++)
-      for (int color = 0; color < 2; color++) hipLaunchKernelGGL(mg_rbgs, g, blk, 0, st, L, color, gx);
-  };
   norm(0);
   for (int c = 0; c < ncycles; c++) {
-    for (int l = 0; l < nl - 1; l++) {
-      smooth(Ls[l], nu1);
-      dim3 g, blk;
-      int gx;
-      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);
-      hipLaunchKernelGGL(mg_restrict, g, blk, 0, st, Ls[l], Ls[l + 1], gx);
-    }
-    hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kCoarseThreads), 0, st, Ls[nl - 1]);
-    for (int l = nl - 2; l >= 0; l--) {
-      dim3 g, blk;
-      int gx;
-      rows(Ls[l + 1].nx, Ls[l + 1].ny, Ls[l + 1].nz, g, blk, gx);  // coarse cells
-      hipLaunchKernelGGL(mg_prolong_add, g, blk, 0, st, Ls[l + 1], Ls[l], gx);
-      smooth(Ls[l], nu2);
-    }
+    vcycle(Ls, nl, nu1, nu2, st);
     norm(c + 1);
   }
   hipLaunchKernelGGL(mg_sum_parts<0>, dim3(kRedParts), dim3(kRedBlock), 0, st, Ls[0].phi, Ls[0], n0, parts);

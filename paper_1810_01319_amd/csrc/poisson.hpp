@@ -29,6 +29,11 @@ int64_t mg_workspace_bytes(int nx, int ny, int nz);
 hipError_t mg_solve(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks, const double* U,
                     double fpg, double* phi_blocks, int ncycles, int nu1, int nu2, double* resid, void* work,
                     hipStream_t st);
+// One V(nu1, nu2) cycle from phi = 0 on f (block layout of P's level-0
+// leaves), no mean handling; phi into the active cells of x_padded (per leaf
+// M^3, one field).  The composite solver's root-level correction.
+hipError_t mg_vcycle_blocks(const DevPlan& P, int nx, int ny, int nz, double h, const double* f_blocks,
+                            double* x_padded, int nu1, int nu2, void* work, hipStream_t st);
 // Half kick of U's active cells with g = -grad(phi) of the mean-free
 // potential phi_blocks (block layout), dt from the device: momentum
 // + (dt/2) rho g, energy + the kinetic-energy change.

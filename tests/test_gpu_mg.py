@@ -6,7 +6,8 @@ oracle relative to max |phi| (the solver's means and norms are fixed-order
 two-stage sums, the oracle's sequential ones, so the last bits may differ);
 residual histories within 1e-10 of the initial residual.  Also: a discrete
 eigenmode solved to round-off on the GPU alone, bitwise repeatability, and
-the refusals (batch, refined mesh, outflow)."""
+the refusals (batch, outflow; refined meshes take mg0 on the octree,
+test_gpu_mgc.py)."""
 import sys
 
 import numpy as np
@@ -97,8 +98,7 @@ def test_mg_is_repeatable_bitwise():
 
 
 def test_mg_refusals():
-    bad = [I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=1, refine=[(0, 0, 0, 0)]),
-           I.MeshSpec(root=(2, 2, 2), block_cells=8, bc="outflow")]
+    bad = [I.MeshSpec(root=(2, 2, 2), block_cells=8, bc="outflow")]
     for spec in bad:
         m = Mesh(**spec.kwargs())
         with pytest.raises(AmrError):

@@ -307,14 +307,18 @@ def _poisson_bytes(**kw):
 
 def test_poisson_workspace_and_refusals_on_the_host():
     """The mg0 workspace holds phi and f of every level (each 256-byte
-    rounded) and the reduction scratch; refined meshes, outflow axes and
-    coarsest levels above 4096 cells are refused before any GPU work."""
+    rounded) and the reduction scratch; on a refined mesh (mg0 on the
+    octree) it also holds the hierarchy of coarsened meshes and their
+    arrays, so it is larger than the root grid's; outflow axes and coarsest
+    levels above 4096 cells are refused before any GPU work."""
     rc, nbytes = _poisson_bytes(root=(2, 2, 2), block_cells=16)  # 32^3: levels 32, 16, 8, 4, 2
     assert rc == 0
     levels = [32 ** 3, 16 ** 3, 8 ** 3, 4 ** 3, 2 ** 3]
     want = sum(2 * ((c * 8 + 255) // 256 * 256) for c in levels) + (1024 + 64) * 8
     assert nbytes == want
-    assert _poisson_bytes(root=(2, 2, 2), block_cells=8, max_level=1, refine=[(0, 0, 0, 0)])[0] == -1
+    rc, refined = _poisson_bytes(root=(4, 4, 4), block_cells=8, max_level=2, refine=[(0, 1, 1, 1), (1, 2, 2, 2)])
+    _, root_only = _poisson_bytes(root=(4, 4, 4), block_cells=8)
+    assert rc == 0 and refined > 3 * root_only
     assert _poisson_bytes(root=(2, 2, 2), block_cells=8, bc="outflow")[0] == -1
     # 9^3 roots of 32^3: 288 -> 144 -> 72 -> 36 -> 18 (not a multiple of 4): coarsest 18^3 = 5832 cells
     assert _poisson_bytes(root=(9, 9, 9), block_cells=32)[0] == -1
