@@ -267,15 +267,21 @@ __device__ __forceinline__ void cfl_commit(unsigned long long* acc, double best)
 // PPM sweep: one lane walks one pencil along the sweep axis with a sliding
 // register window; the next cell is prefetched one step ahead, and each cell
 // is updated three cells behind the read front (the stencil of a cell update
-// is 7 cells wide), re-read from cache for its conserved values.
+// is 7 cells wide).  The conserved values of the last three cells read wait
+// in a per-lane ring in LDS (3 cells x NF fields, lane-minor, dynamic shared
+// memory of 3 NF blockDim.x doubles), so the update takes them from there
+// instead of reading HBM a second time.
 // ---------------------------------------------------------------------------
+
+constexpr int kWalkLanes = 256;  // workgroup size bound of the walk kernels
 
 // cfl_next (the last sweep of a step in a run of steps): every updated cell
 // that no reflux will change adds its CFL candidate for the next step to the
 // instance's accumulator.
 template <int N, int DIR, bool OOP, int NF>
 __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout, const double* __restrict__ dtv,
-                                                const DevPlan& P, int loA, int nA, int loB, int nB, int cfl_next) {
+                                                const DevPlan& P, int loA, int nA, int loB, int nB, int cfl_next,
+                                                double* __restrict__ ring) {
   constexpr bool DE = NF == kFieldsDE;  // dual-energy field rho e (field 5)
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -347,15 +353,22 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   // issues the same loads and stores (so that waiting for the prefetched cell
   // never waits for the previous cell's stores) and the last cell (the upper
   // face flux).
+  // ring slot of cell c: c mod 3, rotating with the walk; field stride L
+  const int L = int(blockDim.x);
+  double* const rl = ring + threadIdx.x;
+  int rs = 0;
   auto cell = [&](const int c, auto phase) __attribute__((always_inline)) {
     constexpr int PH = decltype(phase)::value;
     double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
-    if (PH > 0) {  // the cell updated here, c-3, loaded ahead of the prefetch
-      const int64_t o = int64_t(c - 3) * SD;
-      h0 = pr_[o]; h1 = pn_[o]; h2 = p1_[o]; h3 = p2_[o]; h4 = pe_[o];
-      if constexpr (DE) h5 = pg_[o];
+    double* const slot = rl + rs * (NF * L);
+    if (PH > 0) {  // the cell updated here, c-3: its values left the ring's slot c mod 3
+      h0 = slot[0]; h1 = slot[L]; h2 = slot[2 * L]; h3 = slot[3 * L]; h4 = slot[4 * L];
+      if constexpr (DE) h5 = slot[5 * L];
     }
     const double U0 = nx0, U1 = nx1, U2 = nx2, U3 = nx3, U4 = nx4, U5 = nx5;
+    slot[0] = U0; slot[L] = U1; slot[2 * L] = U2; slot[3 * L] = U3; slot[4 * L] = U4;
+    if constexpr (DE) slot[5 * L] = U5;
+    rs = rs == 2 ? 0 : rs + 1;
     if (PH < 2) {
       const int64_t o = int64_t(c + 1) * SD;
       nx0 = pr_[o]; nx1 = pn_[o]; nx2 = p1_[o]; nx3 = p2_[o]; nx4 = pe_[o];
@@ -491,18 +504,21 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
 }
 
 template <int N, int DIR, int NF>
-__global__ void __launch_bounds__(256) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
-                                                    DevPlan P, int loA, int nA, int loB, int nB, int cfl_next) {
-  sweep_walk_body<N, DIR, false, NF>(U, U, dtv, P, loA, nA, loB, nB, cfl_next);
+__global__ void __launch_bounds__(kWalkLanes) sweep_kernel(double* __restrict__ U, const double* __restrict__ dtv,
+                                                           DevPlan P, int loA, int nA, int loB, int nB, int cfl_next) {
+  extern __shared__ double walk_ring[];
+  sweep_walk_body<N, DIR, false, NF>(U, U, dtv, P, loA, nA, loB, nB, cfl_next, walk_ring);
 }
 
 // Out of place: every cell of the swept pencils is written to Uout (updated
 // or passed through); Uin is not modified.
 template <int N, int DIR, int NF>
-__global__ void __launch_bounds__(256) sweep_kernel_oop(const double* __restrict__ Uin, double* __restrict__ Uout,
-                                                        const double* __restrict__ dtv, DevPlan P, int loA, int nA,
-                                                        int loB, int nB) {
-  sweep_walk_body<N, DIR, true, NF>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0);
+__global__ void __launch_bounds__(kWalkLanes) sweep_kernel_oop(const double* __restrict__ Uin,
+                                                               double* __restrict__ Uout,
+                                                               const double* __restrict__ dtv, DevPlan P, int loA,
+                                                               int nA, int loB, int nB) {
+  extern __shared__ double walk_ring[];
+  sweep_walk_body<N, DIR, true, NF>(Uin, Uout, dtv, P, loA, nA, loB, nB, 0, walk_ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -844,6 +860,9 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
+// dynamic LDS of a walk launch: the per-lane ring of 3 cells x nf fields
+inline size_t walk_ring_bytes(int nf, int block) { return size_t(3) * nf * block * sizeof(double); }
+
 template <int N, int NF>
 hipError_t refresh_nf(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
   constexpr int M = N + 2 * G;
@@ -895,10 +914,11 @@ hipError_t sweep_ndf(const DevPlan& P, const double* Uin, double* Uout, const do
   } else {
     const int64_t n = P.nleaf * ((int64_t(nA) * nB + 63) / 64) * 64;  // whole waves per leaf
     const dim3 g(grid_for(n, L.sweep_block)), b(L.sweep_block);
+    const size_t ring = walk_ring_bytes(NF, L.sweep_block);
     if (oop)
-      hipLaunchKernelGGL((sweep_kernel_oop<N, DIR, NF>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
+      hipLaunchKernelGGL((sweep_kernel_oop<N, DIR, NF>), g, b, ring, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
-      hipLaunchKernelGGL((sweep_kernel<N, DIR, NF>), g, b, 0, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
+      hipLaunchKernelGGL((sweep_kernel<N, DIR, NF>), g, b, ring, st, Uout, dt, P, loA, nA, loB, nB, cfl_next);
   }
   return hipGetLastError();
 }
