@@ -10,6 +10,7 @@
 
 #include "adjoint.hpp"
 #include "ghost.hpp"
+#include "xcd.hpp"
 #include "ppm_adjoint.hpp"
 
 namespace amr {
@@ -118,11 +119,12 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   // along A, then B), so only the leaf's last tile is partial
   const int npen = nA * nB;
   const int tpl = (npen + R - 1) / R;
-  const int s = int(blockIdx.x / unsigned(tpl));
+  const unsigned bx = xcd_block();
+  const int s = int(bx / unsigned(tpl));
   const int i = threadIdx.x;
   const int r = DIR == 0 ? i / M : i % R;
   const int c = DIR == 0 ? i - r * M : i / R;
-  const int pp = (int(blockIdx.x) - s * tpl) * R + r;
+  const int pp = (int(bx) - s * tpl) * R + r;
   const bool live = i < T && pp < npen;
   const int iB = loB + pp / nA;
   const BlockInfo bi = P.blocks[s];

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "ppm_core.hpp"
 #include "ghost.hpp"
+#include "xcd.hpp"
 
 namespace amr {
 
@@ -37,7 +38,7 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int GC = M * M * M - N * N * N;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = int64_t(xcd_block()) * blockDim.x + threadIdx.x;
   if (t >= P.nleaf * GC) return;
   const int s = int(t / GC);
   const int g = int(t - int64_t(s) * GC);
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int GC = M * M * M - N * N * N;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = int64_t(xcd_block()) * blockDim.x + threadIdx.x;
   if (t >= P.np2 * GC) return;
   const int w = int(t / GC);
   const int g = int(t - int64_t(w) * GC);
@@ -295,7 +296,7 @@ __device__ __forceinline__ void sweep_walk_body(const double* Uin, double* Uout,
   // leaf's and the instance's parameters are scalar loads
   const int npen = nA * nB;
   const unsigned wpl = unsigned(npen + 63) / 64u;
-  const unsigned w = blockIdx.x * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
   const int s = int(w / wpl);
   const int pp = int(w - unsigned(s) * wpl) * 64 + int(threadIdx.x & 63u);
   if (s >= P.nleaf || pp >= npen) return;
@@ -560,7 +561,7 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   __shared__ double Fg[DE ? T : 1];     // DE: rho e flux at j+1/2
   __shared__ double Ug[DE ? T : 1];     // DE: Godunov velocity at j+1/2
   const int tilesA = (nA + R - 1) / R;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_block();
   const int s = int(tile / (int64_t(nB) * tilesA));
   const int rem = int(tile - int64_t(s) * nB * tilesA);
   const int iB = loB + rem / tilesA;
