@@ -286,11 +286,16 @@ amr_status amr_hydro_step_adjoint(amr_mesh* mesh, const double* U_in_dev, const 
 
 /* The same adjoint from what amr_hydro_step_record kept: S0_dev (its U_dev
  * after the call), S1_dev, S2_dev, dt_dev and floors_dev (zero resets lets
- * the sweeps' transposes skip the floors).  scratch_dev: adjoint_face_bytes
- * of amr_mesh_info.  Nothing is recomputed. */
+ * the sweeps' transposes skip the floors).  floors_host: the value of
+ * *floors_dev if the caller has read it (then only the matching transpose
+ * kernels are launched; a value that differs from *floors_dev gives a wrong
+ * result), or -1 (the kernels read the count on the device).  scratch_dev:
+ * adjoint_face_bytes of amr_mesh_info.  Nothing is recomputed.
+ * Errors: AMR_E_INVALID for floors_host < -1. */
 amr_status amr_hydro_step_adjoint_recorded(amr_mesh* mesh, const double* S0_dev, const double* S1_dev,
                                            const double* S2_dev, const double* dt_dev, const uint64_t* floors_dev,
-                                           double* lam_dev, void* scratch_dev, int64_t step_index, void* stream);
+                                           int64_t floors_host, double* lam_dev, void* scratch_dev,
+                                           int64_t step_index, void* stream);
 
 /* Transpose of amr_refresh_ghosts at the refreshed state U_ref_dev (its
  * minmod slope choices): on entry lam_dev holds an adjoint on every cell,

@@ -49,13 +49,17 @@ class HydroSteps(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gU):
         mesh = ctx.mesh
-        lam = gU.detach().clone().contiguous()
-        lam[:, :, ~active_mask(mesh)] = 0.0  # ghost values of U_K influence nothing
+        # ghost values of U_K influence nothing
+        lam = torch.where(active_mask(mesh), gU.detach(), torch.zeros((), dtype=gU.dtype, device=gU.device))
         if ctx.record:
             scratch = mesh.adjoint_face_scratch()
+            # every step's floor-reset count in one read: each sweep transpose
+            # then launches only the kernel variant its step needs
+            counts = torch.cat([s[3] for s in ctx.saved]).cpu().tolist()
             for i in range(len(ctx.saved) - 1, -1, -1):
                 S0, S1, S2, floors = ctx.saved[i]
-                mesh.step_adjoint_recorded(S0, S1, S2, ctx.dts[i], floors, lam, scratch, ctx.start + i)
+                mesh.step_adjoint_recorded(S0, S1, S2, ctx.dts[i], floors, lam, scratch, ctx.start + i,
+                                           floors_host=int(counts[i]))
         else:
             scratch = mesh.adjoint_scratch()
             for i in range(len(ctx.saved) - 1, -1, -1):

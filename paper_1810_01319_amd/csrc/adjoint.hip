@@ -87,8 +87,10 @@ struct AdjShape {
 };
 
 // FLOORS: the variant with the post-update floors' products (and the flux
-// recompute that detects them).  Both variants are launched; each returns at
-// once unless the forward step's floor-reset count (null: unknown) selects it.
+// recompute that detects them).  When the host knows the forward step's
+// floor-reset count (sel >= 0: whether it is non-zero) only the matching
+// variant is launched; otherwise both are, and each returns at once unless
+// the count on the device (null: unknown, the floors variant) selects it.
 // Registers are capped for 3 waves per SIMD (a few bytes of spill cost less
 // than the lost occupancy).  The cell's state and adjoint are read together
 // at the start (the adjoint parked in LDS until the reverse pass) and again
@@ -96,8 +98,8 @@ struct AdjShape {
 template <int N, int DIR, bool FLOORS>
 __global__ void __launch_bounds__((AdjShape<N, DIR>::WG)) __attribute__((amdgpu_waves_per_eu(3)))
 sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const double* __restrict__ dtv, DevPlan P,
-              const double* __restrict__ gfaces, const unsigned long long* __restrict__ floors, int loA, int nA,
-              int loB, int nB) {
+              const double* __restrict__ gfaces, const unsigned long long* __restrict__ floors, int sel, int loA,
+              int nA, int loB, int nB) {
   using S = AdjShape<N, DIR>;
   constexpr int M = S::M, R = S::R, T = S::T;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -138,7 +140,9 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   const bool traced = live && c >= 2 && c <= M - 3;
   const bool faced = live && c >= 2 && c <= M - 4;
   const bool active = live && c >= G && c < G + N;
-  if ((floors == nullptr || *floors != 0) != FLOORS) return;  // uniform over the grid
+  // sel < 0: the device count selects (uniform over the grid); else the host's choice
+  const bool with_floors = sel < 0 ? (floors == nullptr || *floors != 0) : sel != 0;
+  if (with_floors != FLOORS) return;
 
   // ---- forward recompute ----
   // Between phases only adjoint accumulators stay in registers: primitives
@@ -499,7 +503,7 @@ inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 template <int N, int DIR>
 hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
-                        const unsigned long long* floors, const int swept[3], hipStream_t st) {
+                        const unsigned long long* floors, int64_t floors_host, const int swept[3], hipStream_t st) {
   using S = AdjShape<N, DIR>;
   constexpr int A = DIR == 0 ? 1 : 0, B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
@@ -507,18 +511,23 @@ hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const 
   const int64_t tiles = P.nleaf * ((int64_t(nA) * nB + S::R - 1) / S::R);
   if (tiles == 0) return hipSuccess;
   const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
-  if (floors != nullptr)
-    hipLaunchKernelGGL((sweep_adjoint<N, DIR, false>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, loA, nA, loB, nB);
-  hipLaunchKernelGGL((sweep_adjoint<N, DIR, true>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, loA, nA, loB, nB);
+  const int sel = floors == nullptr ? 1 : (floors_host < 0 ? -1 : (floors_host > 0 ? 1 : 0));
+  if (sel <= 0)
+    hipLaunchKernelGGL((sweep_adjoint<N, DIR, false>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, sel, loA, nA, loB,
+                       nB);
+  if (sel != 0)
+    hipLaunchKernelGGL((sweep_adjoint<N, DIR, true>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, sel, loA, nA, loB,
+                       nB);
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const double* dt, const double* gfaces,
-                       const unsigned long long* floors, int dir, const int swept[3], hipStream_t st) {
-  if (dir == 0) return sweep_adj_nd<N, 0>(P, Uin, lam, dt, gfaces, floors, swept, st);
-  if (dir == 1) return sweep_adj_nd<N, 1>(P, Uin, lam, dt, gfaces, floors, swept, st);
-  return sweep_adj_nd<N, 2>(P, Uin, lam, dt, gfaces, floors, swept, st);
+                       const unsigned long long* floors, int64_t floors_host, int dir, const int swept[3],
+                       hipStream_t st) {
+  if (dir == 0) return sweep_adj_nd<N, 0>(P, Uin, lam, dt, gfaces, floors, floors_host, swept, st);
+  if (dir == 1) return sweep_adj_nd<N, 1>(P, Uin, lam, dt, gfaces, floors, floors_host, swept, st);
+  return sweep_adj_nd<N, 2>(P, Uin, lam, dt, gfaces, floors, floors_host, swept, st);
 }
 
 template <int N>
@@ -564,12 +573,12 @@ hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const doub
 }
 
 hipError_t launch_sweep_adjoint(const DevPlan& P, const double* Uin, double* lam, const double* dt,
-                                const double* gfaces, const unsigned long long* floors, int dir, const int swept[3],
-                                hipStream_t st) {
+                                const double* gfaces, const unsigned long long* floors, int64_t floors_host, int dir,
+                                const int swept[3], hipStream_t st) {
   switch (P.N) {
-    case 8: return sweep_adj_n<8>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
-    case 16: return sweep_adj_n<16>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
-    case 32: return sweep_adj_n<32>(P, Uin, lam, dt, gfaces, floors, dir, swept, st);
+    case 8: return sweep_adj_n<8>(P, Uin, lam, dt, gfaces, floors, floors_host, dir, swept, st);
+    case 16: return sweep_adj_n<16>(P, Uin, lam, dt, gfaces, floors, floors_host, dir, swept, st);
+    case 32: return sweep_adj_n<32>(P, Uin, lam, dt, gfaces, floors, floors_host, dir, swept, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,10 +16,11 @@ hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const doub
                                  hipStream_t st);
 // transpose of the sweep along dir whose input state was Uin; floors (device,
 // nullable) = post-update floor resets of the forward step: 0 lets the
-// kernel skip the floors' products
+// kernel skip the floors' products; floors_host = the same count read by the
+// host (only the matching kernel is launched), or -1 (not read)
 hipError_t launch_sweep_adjoint(const DevPlan& P, const double* Uin, double* lam, const double* dt,
-                                const double* gfaces, const unsigned long long* floors, int dir, const int swept[3],
-                                hipStream_t st);
+                                const double* gfaces, const unsigned long long* floors, int64_t floors_host, int dir,
+                                const int swept[3], hipStream_t st);
 // transpose of the refresh; Uref = the refreshed state (for the frozen
 // prolongation slopes)
 hipError_t launch_refresh_adjoint(const DevPlan& P, double* lam, const double* Uref, hipStream_t st);

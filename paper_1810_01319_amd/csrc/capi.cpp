@@ -272,8 +272,8 @@ amr_status run_step(amr_mesh* h, double* U, const double* dt, int64_t step_index
 // The transposes of one step in reverse order, given the inputs S[k] of its
 // three sweeps (S[0] the refreshed input state).
 hipError_t adjoint_transposes(amr_mesh* h, const DevPlan& P, const double* const S[3], const double* dt,
-                              const unsigned long long* floors, double* lam, double* gfaces, int64_t step_index,
-                              hipStream_t st) {
+                              const unsigned long long* floors, int64_t floors_host, double* lam, double* gfaces,
+                              int64_t step_index, hipStream_t st) {
   const Plan& p = h->plan;
   int order[3] = {0, 1, 2};
   if (step_index & 1) {
@@ -289,7 +289,7 @@ hipError_t adjoint_transposes(amr_mesh* h, const DevPlan& P, const double* const
     int sw[3] = {0, 0, 0};
     for (int q = 0; q < k; q++) sw[order[q]] = 1;
     e = timed(h, AMR_PHASE_ADJ_SWEEP_X + order[k], st,
-              [&] { return launch_sweep_adjoint(P, S[k], lam, dt, gfaces, floors, order[k], sw, st); });
+              [&] { return launch_sweep_adjoint(P, S[k], lam, dt, gfaces, floors, floors_host, order[k], sw, st); });
   }
   if (e == hipSuccess)
     e = timed(h, AMR_PHASE_ADJ_REFRESH, st, [&] { return launch_refresh_adjoint(P, lam, S[0], st); });
@@ -639,21 +639,23 @@ amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* 
   });
   if (e != hipSuccess) return hip_fail(e, "adjoint recompute");
   const double* const Sc[3] = {S[0], S[1], S[2]};
-  e = adjoint_transposes(h, P, Sc, dt, nullptr, lam, gfaces, step_index, st);
+  e = adjoint_transposes(h, P, Sc, dt, nullptr, -1, lam, gfaces, step_index, st);
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
 }
 
 amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const double* S1, const double* S2,
-                                           const double* dt, const uint64_t* floors, double* lam, void* scratch,
-                                           int64_t step_index, void* stream) {
+                                           const double* dt, const uint64_t* floors, int64_t floors_host,
+                                           double* lam, void* scratch, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, S0);
   if (rc != AMR_OK) return rc;
   if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!S1 || !S2 || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
+  if (floors_host < -1) return fail(AMR_E_INVALID, "floors_host must be a count or -1");
   if (!adjoint_iters_ok(h->plan)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
   const double* const S[3] = {S0, S1, S2};
-  hipError_t e = adjoint_transposes(h, dev_plan(h), S, dt, reinterpret_cast<const unsigned long long*>(floors), lam,
-                                    static_cast<double*>(scratch), step_index, static_cast<hipStream_t>(stream));
+  hipError_t e = adjoint_transposes(h, dev_plan(h), S, dt, reinterpret_cast<const unsigned long long*>(floors),
+                                    floors ? floors_host : -1, lam, static_cast<double*>(scratch), step_index,
+                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
 }
 

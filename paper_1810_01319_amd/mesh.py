@@ -233,13 +233,17 @@ class Mesh:
                                           _ptr(floors), int(k), _stream()))
 
     def step_adjoint_recorded(self, S0: torch.Tensor, S1: torch.Tensor, S2: torch.Tensor, dt: torch.Tensor,
-                              floors: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor, k: int) -> None:
-        """lam <- (d step_k / d U)^T lam from what step_record kept."""
+                              floors: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor, k: int,
+                              floors_host: int = -1) -> None:
+        """lam <- (d step_k / d U)^T lam from what step_record kept;
+        floors_host: the recorded floor-reset count if already read on the
+        host (only the matching transpose kernels run), else -1."""
         for X in (S0, S1, S2, lam):
             self._check_state(X)
         self._check_scratch(scratch, int(self.info.adjoint_face_bytes))
         check(lib().amr_hydro_step_adjoint_recorded(self._h, _ptr(S0), _ptr(S1), _ptr(S2), _ptr(dt),
-                                                    _ptr(floors), _ptr(lam), _ptr(scratch), int(k), _stream()))
+                                                    _ptr(floors), int(floors_host), _ptr(lam), _ptr(scratch),
+                                                    int(k), _stream()))
 
     def refresh_adjoint(self, U_ref: torch.Tensor, lam: torch.Tensor) -> None:
         self._check_state(U_ref)
