@@ -560,12 +560,15 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   __shared__ double Ys[5][T];           // face values at j+1/2, then fluxes
   __shared__ double Fg[DE ? T : 1];     // DE: rho e flux at j+1/2
   __shared__ double Ug[DE ? T : 1];     // DE: Godunov velocity at j+1/2
-  const int tilesA = (nA + R - 1) / R;
-  const int64_t tile = xcd_block();
-  const int s = int(tile / (int64_t(nB) * tilesA));
-  const int rem = int(tile - int64_t(s) * nB * tilesA);
-  const int iB = loB + rem / tilesA;
-  const int a0 = (rem % tilesA) * R;
+  // tile -> (leaf, B row, first A pencil): 32-bit unsigned arithmetic on the
+  // uniform tile index (a grid has fewer than 2^32 workgroups)
+  const unsigned tilesA = unsigned(nA + R - 1) / unsigned(R);
+  const unsigned per_leaf = unsigned(nB) * tilesA;
+  const unsigned tile = xcd_block();
+  const int s = int(tile / per_leaf);
+  const unsigned rem = tile - unsigned(s) * per_leaf;
+  const int iB = loB + int(rem / tilesA);
+  const int a0 = int(rem % tilesA) * R;
   const int i = threadIdx.x;
   const int r = DIR == 0 ? i / M : i % R;
   const int c = DIR == 0 ? i - r * M : i / R;
