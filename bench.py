@@ -38,7 +38,7 @@ def kernel_source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kernels.hip", "ppm_core.hpp", "layout.hpp", "ghost.hpp"):
+    for f in ("kernels.hip", "ppm_core.hpp", "layout.hpp", "ghost.hpp", "xcd.hpp"):
         with open(os.path.join(ROOT, "paper_1810_01319_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -285,9 +285,7 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
 
         def fwd():
             r = base[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N].clone().requires_grad_(True)
-            U = base.clone()
-            U[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N] = r
-            L = A.density_misfit(m, A.run_steps(U, m, steps, record=record), target)
+            L = A.density_misfit(m, A.run_steps(A.with_density(base, r), m, steps, record=record), target)
             state["L"], state["r"] = L, r
             return L
 

@@ -71,10 +71,54 @@ def run_steps(U0: torch.Tensor, mesh, steps: int, start: int = 0, record: bool =
     return HydroSteps.apply(U0, mesh, steps, start, record)
 
 
+class DensityMisfit(torch.autograd.Function):
+    """L = sum over leaf cells of w (rho - rho_target)^2; its backward writes
+    dL/dU (2 w (rho - rho_target) on the active densities, zero elsewhere,
+    ghosts included) in one pass instead of autograd's chain of slices."""
+
+    @staticmethod
+    def forward(ctx, U, w, target_rho):
+        g = GHOST
+        N = target_rho.shape[-1]
+        d = U[:, 0, g:g + N, g:g + N, g:g + N] - target_rho
+        ctx.save_for_backward(d, w)
+        ctx.shape = U.shape
+        return (w * d * d).sum()
+
+    @staticmethod
+    def backward(ctx, gL):
+        d, w = ctx.saved_tensors
+        g, N = GHOST, d.shape[-1]
+        gU = torch.zeros(ctx.shape, dtype=d.dtype, device=d.device)
+        gU[:, 0, g:g + N, g:g + N, g:g + N] = (2.0 * gL) * (w * d)
+        return gU, None, None
+
+
 def density_misfit(mesh, U: torch.Tensor, target_rho: torch.Tensor) -> torch.Tensor:
     """sum over leaf cells of (V_c / V_root) (rho_c - rho_target_c)^2."""
-    g, N = GHOST, mesh.N
-    rho = U[:, 0, g:g + N, g:g + N, g:g + N]
     lev = torch.as_tensor(mesh.keys[:, 0], device=U.device, dtype=torch.float64)
     w = torch.pow(0.125, lev)[:, None, None, None]
-    return (w * (rho - target_rho) ** 2).sum()
+    return DensityMisfit.apply(U, w, target_rho)
+
+
+class WithDensity(torch.autograd.Function):
+    """A copy of the state U with the active densities replaced by rho; the
+    gradient flows to rho only (U is data), without materialising a gradient
+    for the rest of the state."""
+
+    @staticmethod
+    def forward(ctx, U, rho):
+        g, N = GHOST, rho.shape[-1]
+        out = U.detach().clone()
+        out[:, 0, g:g + N, g:g + N, g:g + N] = rho
+        return out
+
+    @staticmethod
+    def backward(ctx, gU):
+        g = GHOST
+        N = gU.shape[-1] - 2 * g
+        return None, gU[:, 0, g:g + N, g:g + N, g:g + N].contiguous()
+
+
+def with_density(U: torch.Tensor, rho: torch.Tensor) -> torch.Tensor:
+    return WithDensity.apply(U, rho)

@@ -388,6 +388,10 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
 // Refresh transpose, phase 2 (prolongation): a prolonged ghost's adjoint
 // goes to the coarse parent cell and, through the frozen minmod slopes, to
 // its face neighbours; then the ghost entry is cleared.
+// One thread per ghost cell of every leaf with a coarser neighbour (the
+// threads of other neighbours return at once: spreading the prolonged cells
+// over the grid keeps fewer waves adding to one coarse cell at a time than
+// the forward's compact task list would).
 template <int N>
 __global__ void __launch_bounds__(256) refresh2_adjoint(double* __restrict__ lam, const double* __restrict__ Uref,
                                                         DevPlan P) {

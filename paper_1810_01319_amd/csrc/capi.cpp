@@ -167,6 +167,7 @@ DevPlan dev_plan_at(const Plan& p, unsigned char* w) {
   P.nbr = reinterpret_cast<const Nbr*>(w + p.off.nbr);
   P.fine = reinterpret_cast<const int32_t*>(w + p.off.fine);
   P.p2list = reinterpret_cast<const int32_t*>(w + p.off.p2list);
+  P.p2task = reinterpret_cast<const int32_t*>(w + p.off.p2task);
   P.faceslot = reinterpret_cast<const int32_t*>(w + p.off.faceslot);
   for (int d = 0; d < 3; d++) {
     P.reflux[d] = reinterpret_cast<const RefluxTask*>(w + p.off.reflux[d]);
@@ -183,6 +184,7 @@ DevPlan dev_plan_at(const Plan& p, unsigned char* w) {
   P.faces = reinterpret_cast<double*>(w + p.off.faces);
   P.nleaf = p.nleaf;
   P.np2 = int64_t(p.p2list.size());
+  for (int k = 0; k < 3; k++) P.np2t[k] = p.np2t[k];
   P.ninst = int32_t(p.inst.size());
   P.N = p.N;
   P.nf = p.nf;

@@ -63,6 +63,28 @@ __device__ inline int dir_code(int a, int b, int c) {
   return sx + 3 * sy + 9 * sz;
 }
 
+// Phase-2 tasks of kind K (0: faces, 1: edges, 2: corners): a task is the
+// ghost region of one direction (neighbour code) of one leaf, SIZE cells.
+template <int N, int K>
+struct P2Region {
+  static constexpr int SIZE = K == 0 ? 3 * N * N : (K == 1 ? 9 * N : 27);
+  static constexpr int WAVES = (SIZE + 63) / 64;  // a task takes whole waves
+};
+
+// Cell r (x fastest) of the ghost region of direction code -> padded (a, b, c).
+template <int N>
+__device__ inline void p2_cell(int code, int r, int& a, int& b, int& c) {
+  static_assert((N & (N - 1)) == 0, "N is a power of two");
+  const int cx = code % 3, cy = (code / 3) % 3, cz = code / 9;
+  const int ia = cx == 1 ? (r & (N - 1)) : r % kGhost;
+  const int q = cx == 1 ? r / N : r / kGhost;
+  const int ib = cy == 1 ? (q & (N - 1)) : q % kGhost;
+  const int ic = cy == 1 ? q / N : q / kGhost;
+  a = (cx == 0 ? 0 : (cx == 1 ? kGhost : N + kGhost)) + ia;
+  b = (cy == 0 ? 0 : (cy == 1 ? kGhost : N + kGhost)) + ib;
+  c = (cz == 0 ? 0 : (cz == 1 ? kGhost : N + kGhost)) + ic;
+}
+
 // Global level-l index of a ghost cell after the physical boundary: periodic
 // wraps, outflow clamps to the nearest domain cell.
 template <int N>

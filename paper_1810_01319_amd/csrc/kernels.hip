@@ -77,24 +77,28 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 }
 
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
-// and phase-1 ghost cells are complete.  LIN: unlimited central slopes
-// 0.5 (u(+1) - u(-1)) (the composite Poisson operator's interpolation).
-template <int N, int NF, bool LIN = false>
+// and phase-1 ghost cells are complete; one thread per cell of the ghost
+// regions of kind K (faces, edges, corners) whose neighbour position a
+// coarser leaf covers.  Each task takes whole waves, so the task, its leaves
+// and their instance are wave-uniform: scalar loads, off the latency chain
+// of the stencil loads.  LIN: unlimited central slopes 0.5 (u(+1) - u(-1))
+// (the composite Poisson operator's interpolation).
+template <int N, int NF, bool LIN, int K>
 __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
-  constexpr int GC = M * M * M - N * N * N;
-  const int64_t t = int64_t(xcd_block()) * blockDim.x + threadIdx.x;
-  if (t >= P.np2 * GC) return;
-  const int w = int(t / GC);
-  const int g = int(t - int64_t(w) * GC);
-  const int s = P.p2list[w];
+  constexpr unsigned RS = P2Region<N, K>::SIZE, WV = P2Region<N, K>::WAVES;
+  const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  const unsigned task = w / WV;
+  const int r = int((w - task * WV) * 64 + (threadIdx.x & 63u));
+  if (task >= unsigned(P.np2t[K]) || r >= int(RS)) return;
+  const int64_t row = 2 * ((K == 0 ? 0 : (K == 1 ? P.np2t[0] : P.np2t[0] + P.np2t[1])) + task);
+  const int s = P.p2task[row], code = P.p2task[row + 1];
   int a, b, c;
-  ghost_decode<N>(g, a, b, c);
-  const Nbr e = P.nbr[27 * int64_t(s) + dir_code<N>(a, b, c)];
-  if (e.kind != NBR_COARSE) return;
+  p2_cell<N>(code, r, a, b, c);
+  const Nbr e = P.nbr[27 * int64_t(s) + code];  // a coarser leaf, by construction
   const BlockInfo bi = P.blocks[s];
-  const InstParams& ip = P.inst[bi.inst];
+  const InstParams ip = P.inst[bi.inst];  // by value: read once, before the store
   const int l = bi.level;
   const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
   const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
@@ -864,6 +868,19 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
+// the phase-2 launches, one per task kind (faces, edges, corners)
+template <int N, int NF, bool LIN>
+hipError_t launch_phase2(const DevPlan& P, double* U, int block, hipStream_t st) {
+  // whole waves per task; wave indices are 32-bit
+  const int64_t n0 = P.np2t[0] * P2Region<N, 0>::WAVES * 64, n1 = P.np2t[1] * P2Region<N, 1>::WAVES * 64,
+                n2 = P.np2t[2] * P2Region<N, 2>::WAVES * 64;
+  if (n0 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  if (n0 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 0>), dim3(grid_for(n0, block)), dim3(block), 0, st, U, P);
+  if (n1 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 1>), dim3(grid_for(n1, block)), dim3(block), 0, st, U, P);
+  if (n2 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 2>), dim3(grid_for(n2, block)), dim3(block), 0, st, U, P);
+  return hipSuccess;
+}
+
 // dynamic LDS of a walk launch: the per-lane ring of 3 cells x nf fields
 inline size_t walk_ring_bytes(int nf, int block) { return size_t(3) * nf * block * sizeof(double); }
 
@@ -873,8 +890,10 @@ hipError_t refresh_nf(const DevPlan& P, double* U, const LaunchCfg& L, hipStream
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
   if (P.nleaf > 0)
     hipLaunchKernelGGL((refresh_phase1<N, NF>), dim3(grid_for(P.nleaf * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
-  if (P.np2 > 0)
-    hipLaunchKernelGGL((refresh_phase2<N, NF>), dim3(grid_for(P.np2 * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+  if (P.np2 > 0) {
+    const hipError_t e = launch_phase2<N, NF, false>(P, U, L.refresh_block, st);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
@@ -1013,8 +1032,10 @@ hipError_t refresh_scalar_n(const DevPlan& P, double* x, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
   if (P.nleaf > 0) hipLaunchKernelGGL((refresh_phase1<N, 1>), dim3(grid_for(P.nleaf * GC, 256)), dim3(256), 0, st, x, P);
-  if (P.np2 > 0)
-    hipLaunchKernelGGL((refresh_phase2<N, 1, true>), dim3(grid_for(P.np2 * GC, 256)), dim3(256), 0, st, x, P);
+  if (P.np2 > 0) {
+    const hipError_t e = launch_phase2<N, 1, true>(P, x, 256, st);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ struct Reloc {
 };
 
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, faceslot, reflux[3], acc, lacc, dte, counters, ind, migr, reloc,
+  int64_t inst, blocks, nbr, fine, p2list, p2task, faceslot, reflux[3], acc, lacc, dte, counters, ind, migr, reloc,
       reloc_child, faces, total;
 };
 

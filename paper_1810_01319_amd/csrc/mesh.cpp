@@ -204,7 +204,9 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   N = meshes[0]->desc().N;
   M = N + 2 * kGhost;
   nf = meshes[0]->desc().de ? kFieldsDE : kFields;
-  inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); faceslot.clear(); keys.clear();
+  inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); p2task.clear(); faceslot.clear();
+  keys.clear();
+  std::vector<int32_t> p2k[3];  // phase-2 tasks by kind, merged below
   if (!migr.empty() && meshes.size() != 1) return "migration tables belong to single-mesh plans";
   for (auto& r : reflux) r.clear();
   nslots = 0;
@@ -283,6 +285,9 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
         e.kind = NBR_COARSE;
         e.id = *it;
         coarse_nbr = true;
+        const int kind = (sd[0] != 0) + (sd[1] != 0) + (sd[2] != 0) - 1;  // 0 face, 1 edge, 2 corner
+        p2k[kind].push_back(int32_t(s));
+        p2k[kind].push_back(int32_t(code));
       }
     }
     if (coarse_nbr) p2list.push_back(int32_t(s));
@@ -295,6 +300,10 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
       }
   }
   has_p2 = !p2list.empty();
+  for (int k = 0; k < 3; k++) {
+    np2t[k] = int64_t(p2k[k].size() / 2);
+    p2task.insert(p2task.end(), p2k[k].begin(), p2k[k].end());
+  }
   // reflux tasks: coarse side of each coarse-fine face
   for (int64_t s = 0; s < nleaf; s++) {
     const BlockInfo& b = blocks[s];
@@ -339,6 +348,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   off.nbr = o; o = align256(o + int64_t(nbr.size() * sizeof(Nbr)));
   off.fine = o; o = align256(o + int64_t(fine.size() * sizeof(int32_t)));
   off.p2list = o; o = align256(o + int64_t(p2list.size() * sizeof(int32_t)));
+  off.p2task = o; o = align256(o + int64_t(p2task.size() * sizeof(int32_t)));
   off.faceslot = o; o = align256(o + int64_t(faceslot.size() * sizeof(int32_t)));
   for (int d = 0; d < 3; d++) {
     off.reflux[d] = o;
@@ -363,6 +373,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   put(off.nbr, nbr.data(), nbr.size() * sizeof(Nbr));
   put(off.fine, fine.data(), fine.size() * sizeof(int32_t));
   put(off.p2list, p2list.data(), p2list.size() * sizeof(int32_t));
+  put(off.p2task, p2task.data(), p2task.size() * sizeof(int32_t));
   put(off.faceslot, faceslot.data(), faceslot.size() * sizeof(int32_t));
   for (int d = 0; d < 3; d++) put(off.reflux[d], reflux[d].data(), reflux[d].size() * sizeof(RefluxTask));
   put(off.migr, migr.data(), migr.size() * sizeof(MigrTask));

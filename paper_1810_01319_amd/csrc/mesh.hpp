@@ -156,6 +156,10 @@ struct Plan {
   std::vector<Nbr> nbr;          // 27 per leaf
   std::vector<int32_t> fine;     // 8 per FINE entry
   std::vector<int32_t> p2list;   // leaves with a coarser neighbour
+  // phase-2 tasks: (leaf, neighbour code) pairs whose neighbour position is
+  // covered by a coarser leaf, faces first, then edges, then corners
+  std::vector<int32_t> p2task;
+  int64_t np2t[3] = {0, 0, 0};   // tasks of each kind (faces, edges, corners)
   std::vector<int32_t> faceslot; // 6 per leaf
   std::vector<RefluxTask> reflux[3];
   std::vector<MigrTask> migr;    // set before build() by a remesh
