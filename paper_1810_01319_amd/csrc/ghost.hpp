@@ -68,21 +68,29 @@ __device__ inline int dir_code(int a, int b, int c) {
 template <int N, int K>
 struct P2Region {
   static constexpr int SIZE = K == 0 ? 3 * N * N : (K == 1 ? 9 * N : 27);
-  static constexpr int WAVES = (SIZE + 63) / 64;  // a task takes whole waves
+  // cells sharing one coarse parent: along a ghost axis the 3 cells form the
+  // groups {1 cell, 2 cells} (low side) or {2, 1} (high side), along an
+  // interior axis N / 2 pairs; GROUPS per region
+  static constexpr int GROUPS = K == 0 ? 2 * (N / 2) * (N / 2) : (K == 1 ? 4 * (N / 2) : 8);
+  static constexpr int WAVES = (GROUPS + 63) / 64;  // a task takes whole waves
 };
 
-// Cell r (x fastest) of the ghost region of direction code -> padded (a, b, c).
+// Group j along an axis of region class cl (0: low ghost slab, 1: interior,
+// 2: high ghost slab): its first padded index and its number of cells.  The
+// padded index a is the global index i N - 3 + a (N even), so the cells
+// 2 p + 1, 2 p + 2 of the padded range share the coarse parent.
 template <int N>
-__device__ inline void p2_cell(int code, int r, int& a, int& b, int& c) {
-  static_assert((N & (N - 1)) == 0, "N is a power of two");
-  const int cx = code % 3, cy = (code / 3) % 3, cz = code / 9;
-  const int ia = cx == 1 ? (r & (N - 1)) : r % kGhost;
-  const int q = cx == 1 ? r / N : r / kGhost;
-  const int ib = cy == 1 ? (q & (N - 1)) : q % kGhost;
-  const int ic = cy == 1 ? q / N : q / kGhost;
-  a = (cx == 0 ? 0 : (cx == 1 ? kGhost : N + kGhost)) + ia;
-  b = (cy == 0 ? 0 : (cy == 1 ? kGhost : N + kGhost)) + ib;
-  c = (cz == 0 ? 0 : (cz == 1 ? kGhost : N + kGhost)) + ic;
+__device__ inline void p2_group(int cl, int j, int& first, int& n) {
+  if (cl == 1) {
+    first = kGhost + 2 * j;
+    n = 2;
+  } else if (cl == 0) {
+    first = j == 0 ? 0 : 1;
+    n = j == 0 ? 1 : 2;
+  } else {
+    first = j == 0 ? N + kGhost : N + kGhost + 2;
+    n = j == 0 ? 2 : 1;
+  }
 }
 
 // Global level-l index of a ghost cell after the physical boundary: periodic

@@ -77,54 +77,76 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 }
 
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
-// and phase-1 ghost cells are complete; one thread per cell of the ghost
-// regions of kind K (faces, edges, corners) whose neighbour position a
-// coarser leaf covers.  Each task takes whole waves, so the task, its leaves
-// and their instance are wave-uniform: scalar loads, off the latency chain
-// of the stencil loads.  LIN: unlimited central slopes 0.5 (u(+1) - u(-1))
-// (the composite Poisson operator's interpolation).
+// and phase-1 ghost cells are complete, over the ghost regions of kind K
+// (faces, edges, corners) whose neighbour position a coarser leaf covers.
+// One thread per group of ghost cells that share a coarse parent (up to
+// 2 x 2 x 2): the parent's stencil is loaded and its slopes computed once,
+// then each cell of the group takes its own offset.  Each task takes whole
+// waves, so the task, its leaves and their instance are wave-uniform: scalar
+// loads, off the latency chain of the stencil loads.  LIN: unlimited central
+// slopes 0.5 (u(+1) - u(-1)) (the composite Poisson operator's
+// interpolation).
 template <int N, int NF, bool LIN, int K>
 __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
-  constexpr unsigned RS = P2Region<N, K>::SIZE, WV = P2Region<N, K>::WAVES;
+  constexpr unsigned RG = P2Region<N, K>::GROUPS, WV = P2Region<N, K>::WAVES;
   const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
   const unsigned task = w / WV;
   const int r = int((w - task * WV) * 64 + (threadIdx.x & 63u));
-  if (task >= unsigned(P.np2t[K]) || r >= int(RS)) return;
+  if (task >= unsigned(P.np2t[K]) || r >= int(RG)) return;
   const int64_t row = 2 * ((K == 0 ? 0 : (K == 1 ? P.np2t[0] : P.np2t[0] + P.np2t[1])) + task);
   const int s = P.p2task[row], code = P.p2task[row + 1];
-  int a, b, c;
-  p2_cell<N>(code, r, a, b, c);
+  // group -> its cells' padded ranges along x, y, z (x fastest)
+  const int cl[3] = {code % 3, (code / 3) % 3, code / 9};
+  int first[3], cnt[3], j = r;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int ng = cl[d] == 1 ? N / 2 : 2;  // a power of two
+    p2_group<N>(cl[d], j & (ng - 1), first[d], cnt[d]);
+    j /= ng;
+  }
   const Nbr e = P.nbr[27 * int64_t(s) + code];  // a coarser leaf, by construction
   const BlockInfo bi = P.blocks[s];
-  const InstParams ip = P.inst[bi.inst];  // by value: read once, before the store
+  const InstParams ip = P.inst[bi.inst];  // by value: read once, before the stores
   const int l = bi.level;
-  const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
-  const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
-  const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
   const BlockInfo cb = P.blocks[e.id];
-  const int la = (px >> 1) - cb.i * N + G, lb = (py >> 1) - cb.j * N + G, lc = (pz >> 1) - cb.k * N + G;
-  const double ox = (px & 1) ? 0.25 : -0.25;
-  const double oy = (py & 1) ? 0.25 : -0.25;
-  const double oz = (pz & 1) ? 0.25 : -0.25;
+  // the parent (the same for every cell of the group)
+  const int px0 = bc_index<N>(ip, l, 0, bi.i * N + first[0] - G);
+  const int py0 = bc_index<N>(ip, l, 1, bi.j * N + first[1] - G);
+  const int pz0 = bc_index<N>(ip, l, 2, bi.k * N + first[2] - G);
+  const int la = (px0 >> 1) - cb.i * N + G, lb = (py0 >> 1) - cb.j * N + G, lc = (pz0 >> 1) - cb.k * N + G;
   const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
-  double* dst = U + int64_t(s) * NF * M3 + (int64_t(c) * M + b) * M + a;
+  double u0[NF], sx[NF], sy[NF], sz[NF];
 #pragma unroll
   for (int f = 0; f < NF; f++) {
     const double* q = src + f * M3;
-    const double u0 = q[0];
-    double sx, sy, sz;
+    u0[f] = q[0];
     if (LIN) {
-      sx = 0.5 * (q[1] - q[-1]);
-      sy = 0.5 * (q[M] - q[-M]);
-      sz = 0.5 * (q[M * M] - q[-M * M]);
+      sx[f] = 0.5 * (q[1] - q[-1]);
+      sy[f] = 0.5 * (q[M] - q[-M]);
+      sz[f] = 0.5 * (q[M * M] - q[-M * M]);
     } else {
-      sx = minmod(q[1] - u0, u0 - q[-1]);
-      sy = minmod(q[M] - u0, u0 - q[-M]);
-      sz = minmod(q[M * M] - u0, u0 - q[-M * M]);
+      sx[f] = minmod(q[1] - u0[f], u0[f] - q[-1]);
+      sy[f] = minmod(q[M] - u0[f], u0[f] - q[-M]);
+      sz[f] = minmod(q[M * M] - u0[f], u0[f] - q[-M * M]);
     }
-    dst[f * M3] = ((u0 + ox * sx) + oy * sy) + oz * sz;
+  }
+  double* const dst0 = U + int64_t(s) * NF * M3;
+  for (int dc = 0; dc < cnt[2]; dc++) {
+    const int c = first[2] + dc;
+    const double oz = (bc_index<N>(ip, l, 2, bi.k * N + c - G) & 1) ? 0.25 : -0.25;
+    for (int db = 0; db < cnt[1]; db++) {
+      const int b = first[1] + db;
+      const double oy = (bc_index<N>(ip, l, 1, bi.j * N + b - G) & 1) ? 0.25 : -0.25;
+      for (int da = 0; da < cnt[0]; da++) {
+        const int a = first[0] + da;
+        const double ox = (bc_index<N>(ip, l, 0, bi.i * N + a - G) & 1) ? 0.25 : -0.25;
+        double* const dst = dst0 + (int64_t(c) * M + b) * M + a;
+#pragma unroll
+        for (int f = 0; f < NF; f++) dst[f * M3] = ((u0[f] + ox * sx[f]) + oy * sy[f]) + oz * sz[f];
+      }
+    }
   }
 }
 
@@ -873,7 +895,7 @@ template <int N, int NF, bool LIN>
 hipError_t launch_phase2(const DevPlan& P, double* U, int block, hipStream_t st) {
   // whole waves per task; wave indices are 32-bit
   const int64_t n0 = P.np2t[0] * P2Region<N, 0>::WAVES * 64, n1 = P.np2t[1] * P2Region<N, 1>::WAVES * 64,
-                n2 = P.np2t[2] * P2Region<N, 2>::WAVES * 64;
+                n2 = P.np2t[2] * P2Region<N, 2>::WAVES * 64;  // threads (groups padded to whole waves)
   if (n0 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
   if (n0 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 0>), dim3(grid_for(n0, block)), dim3(block), 0, st, U, P);
   if (n1 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 1>), dim3(grid_for(n1, block)), dim3(block), 0, st, U, P);
