@@ -372,11 +372,13 @@ def tracer_compare(steps: int = 20):
 
 def comoving_compare(steps: int = 20):
     """Comoving steps on the Sedov workload in an Einstein-de Sitter expansion
-    (a = t^(2/3), H = 2 / (3 t), from t = 1e-3, a = 0.01): each step takes its dt from the
-    comoving CFL (read back to the host, as a cosmology code does to place
-    a and H at the step's mid time), then runs the step.  Reports the time per
-    step and the expansion-source kernel's HBM rate (per active cell: 5
-    fields read, 4 written)."""
+    (a = t^(2/3), H = 2 / (3 t), from t = 1e-3, a = 0.01), two ways: (1) the
+    device-resident run (amr_hydro_steps_comoving: a(t), the comoving CFL dt,
+    a and H at the step's mid time all on the device, nothing read back);
+    (2) host-driven steps, each reading its CFL dt back to place a and H at
+    the step's mid time.  Reports the time per step of both and the
+    expansion-source kernel's HBM rate (per active cell: 5 fields read, 4
+    written)."""
     import torch
 
     from paper_1810_01319_amd import inputs as I
@@ -384,9 +386,29 @@ def comoving_compare(steps: int = 20):
 
     spec = I.sedov_spec(root=8, block_cells=32, levels=2)
     m = Mesh(**spec.kwargs())
-    U = m.state_from_active(I.sedov_state(spec, m.keys))
-    dt = m.dt_tensor()
+    U0 = m.state_from_active(I.sedov_state(spec, m.keys))
     cells = m.nleaf * spec.block_cells ** 3
+    H0, t_start = 2.0 / 3.0, 1e-3  # a = (3/2 H0 t)^(2/3) = t^(2/3)
+
+    # (1) device-resident
+    U = U0.clone()
+    cosmo = torch.tensor([t_start, 0.0, 0.0, 0.0], dtype=torch.float64, device=m.device)
+    dts = torch.zeros(max(steps, 2), dtype=torch.float64, device=m.device)
+    m.steps_comoving(U, dts, 2, 0, cosmo, H0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.steps_comoving(U, dts, steps, 2, cosmo, H0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_end = float(cosmo.cpu()[0])
+    m.profile(True)  # per-phase times from one more run
+    m.steps_comoving(U, dts, steps, 2 + steps, cosmo, H0)
+    prof = m.profile_read()
+    m.profile(False)
+
+    # (2) host-driven
+    U = U0.clone()
+    dt = m.dt_tensor()
 
     def run(k0, n, t):
         for k in range(k0, k0 + n):
@@ -398,20 +420,18 @@ def comoving_compare(steps: int = 20):
             t += d
         return t
 
-    t = run(0, 2, 1e-3)
+    t = run(0, 2, t_start)
     torch.cuda.synchronize()
-    m.profile(True)
     t0 = time.perf_counter()
-    t = run(2, steps, t)
+    run(2, steps, t)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = m.profile_read()
-    m.profile(False)
+    wall_host = time.perf_counter() - t0
     ex_ms = prof["expansion"][0] / steps
     bytes_pc = 72
     return {"workload": "sedov-static-amr, comoving, Einstein-de Sitter expansion from a = 0.01",
-            "steps": steps, "a_end": t ** (2.0 / 3.0), "ms_per_step": wall * 1e3 / steps,
-            "cell_updates_per_s": cells * steps / wall, "expansion_ms_per_step": ex_ms,
+            "steps": steps, "a_end": t_end ** (2.0 / 3.0), "ms_per_step": wall * 1e3 / steps,
+            "cell_updates_per_s": cells * steps / wall, "host_driven_ms_per_step": wall_host * 1e3 / steps,
+            "expansion_ms_per_step": ex_ms,
             "expansion_hbm": {"algorithmic_bytes_per_cell": bytes_pc,
                               "GB/s": cells * bytes_pc / (ex_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS},
             "phases_ms_per_step": {p: round(v[0] / steps, 4) for p, v in prof.items() if v[1] > 0}}

@@ -204,6 +204,22 @@ amr_status amr_cfl_dt_comoving(amr_mesh* mesh, const double* U_dev, double a, do
 amr_status amr_hydro_step_comoving(amr_mesh* mesh, double* U_dev, const double* dt_dev, int64_t step_index,
                                    double a, double hubble, void* stream);
 
+/* A run of comoving steps with the expansion history evaluated on the
+ * device (not in the paper: a flat matter + Lambda background,
+ * H(a) = H0 sqrt(omega_m / a^3 + omega_l), omega_m + omega_l = 1, for which
+ * a(t) has a closed form; radiation neglected).  cosmo_dev: 4 doubles on the
+ * device, [0] the time t (in: at the first step; out: after the last),
+ * [1] a(t) at the last step's start, [2] a and [3] H at its mid time.  Each
+ * step: a(t); the comoving CFL dt into dt_dev[k] (nsteps doubles); a and H
+ * at t + dt / 2; amr_hydro_step_comoving with them (step index
+ * first_step + k); t += dt.  Nothing is read back to the host, so the run
+ * can be captured in a graph.  Single meshes only (AMR_E_INVALID for a
+ * batch); AMR_E_INVALID for H0 <= 0, omega_m <= 0, omega_l < 0 or
+ * |omega_m + omega_l - 1| > 1e-12. */
+amr_status amr_hydro_steps_comoving(amr_mesh* mesh, double* U_dev, double* dt_dev, int64_t nsteps,
+                                    int64_t first_step, double H0, double omega_m, double omega_l,
+                                    double* cosmo_dev, void* stream);
+
 /* Sec. II-C ppm Method on every Block, repeated; the fused CFL is not in
  * the paper (reading: a step's dt needs only its predecessor's output).
  * nsteps consecutive hydro steps (step indices first_step, first_step + 1,

@@ -114,6 +114,7 @@ SIGNATURES = {
     "amr_hydro_step_tracers": (_I32, [_P, _P, _P, _P, _P, _I64, _P, _I64, _P]),
     "amr_tracer_counters": (_I32, [_P, _P, _I64, _P, _I32, _P]),
     "amr_tracers_remesh": (_I32, [_P, _I64, _P, _P, _I64, _P, _P]),
+    "amr_hydro_steps_comoving": (_I32, [_P, _P, _P, _I64, _I64] + [ctypes.c_double] * 3 + [_P, _P]),
     "amr_hydro_step_adjoint_recorded": (_I32, [_P, _P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P]),
     "amr_refresh_ghosts_adjoint": (_I32, [_P, _P, _P, _P]),
     "amr_floor_count": (_I32, [_P, ctypes.POINTER(_I64), _P]),

@@ -582,6 +582,34 @@ amr_status amr_hydro_step_comoving(amr_mesh* h, double* U, const double* dt, int
   return e == hipSuccess ? AMR_OK : hip_fail(e, "expansion");
 }
 
+amr_status amr_hydro_steps_comoving(amr_mesh* h, double* U, double* dt, int64_t nsteps, int64_t first_step,
+                                    double H0, double omega_m, double omega_l, double* cosmo, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (!dt || !cosmo) return fail(AMR_E_INVALID, "null argument");
+  if (nsteps < 0) return fail(AMR_E_INVALID, "nsteps < 0");
+  if (h->plan.inst.size() != 1) return fail(AMR_E_INVALID, "a run of comoving steps needs a single mesh");
+  if (!(H0 > 0.0) || !std::isfinite(H0) || !(omega_m > 0.0) || !(omega_l >= 0.0) ||
+      !(std::fabs(omega_m + omega_l - 1.0) <= 1e-12))
+    return fail(AMR_E_INVALID, "cosmology: H0 > 0, omega_m > 0, omega_l >= 0, omega_m + omega_l = 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  for (int64_t k = 0; k < nsteps; k++) {
+    double* const dk = dt + k;
+    hipError_t e = launch_cosmology(0, H0, omega_m, omega_l, dk, cosmo, st);
+    if (e == hipSuccess)
+      e = timed(h, AMR_PHASE_CFL, st, [&] { return launch_cfl(P, U, dk, h->cfg, st, 1.0, cosmo + 1); });
+    if (e == hipSuccess) e = launch_cosmology(1, H0, omega_m, omega_l, dk, cosmo, st);
+    if (e == hipSuccess) e = launch_scale_dt(P, dk, 1.0, st, cosmo + 2);
+    if (e != hipSuccess) return hip_fail(e, "comoving dt");
+    rc = run_step(h, U, P.dte, first_step + k, st);
+    if (rc != AMR_OK) return rc;
+    e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, U, dk, 0.0, st, cosmo + 3); });
+    if (e != hipSuccess) return hip_fail(e, "expansion");
+  }
+  return AMR_OK;
+}
+
 amr_status amr_hydro_step_record(amr_mesh* h, double* U, double* dt, double* S1, double* S2, double* Uout,
                                  uint64_t* floors, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, U);

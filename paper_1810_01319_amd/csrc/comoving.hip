@@ -23,15 +23,41 @@ namespace {
 
 constexpr int G = kGhost;
 
-__global__ void scale_dt_kernel(const double* __restrict__ dt, double a, double* __restrict__ dte, int64_t ninst) {
+__global__ void scale_dt_kernel(const double* __restrict__ dt, double a, const double* __restrict__ a_dev,
+                                double* __restrict__ dte, int64_t ninst) {
   const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m < ninst) dte[m] = dt[m] / a;
+  if (m < ninst) dte[m] = dt[m] / (a_dev ? *a_dev : a);
+}
+
+// Flat matter + Lambda expansion (radiation neglected): from
+// (adot / a)^2 = H0^2 (om / a^3 + ol) with a(0) = 0,
+//   a(t) = (om / ol)^(1/3) sinh(3/2 sqrt(ol) H0 t)^(2/3)   (ol > 0),
+//   a(t) = (3/2 H0 t)^(2/3)                                 (ol = 0).
+__device__ double cosmo_a(double H0, double om, double ol, double t) {
+  if (ol > 0.0) return cbrt(om / ol) * pow(sinh(1.5 * sqrt(ol) * H0 * t), 2.0 / 3.0);
+  return pow(1.5 * H0 * t, 2.0 / 3.0);
+}
+
+__global__ void cosmology_kernel(int stage, double H0, double om, double ol, const double* __restrict__ dt,
+                                 double* __restrict__ cs) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double t = cs[0];
+  if (stage == 0) {
+    cs[1] = cosmo_a(H0, om, ol, t);
+    return;
+  }
+  const double d = dt[0];
+  const double am = cosmo_a(H0, om, ol, t + 0.5 * d);
+  cs[2] = am;
+  cs[3] = H0 * sqrt(om / (am * am * am) + ol);
+  cs[0] = t + d;
 }
 
 // One thread per active cell.
 template <int N>
 __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, const double* __restrict__ dtv,
-                                                        double hubble, DevPlan P) {
+                                                        double hubble, const double* __restrict__ hubble_dev,
+                                                        DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int N3 = N * N * N;
@@ -42,7 +68,7 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   const int x = q % N, y = (q / N) % N, z = q / (N * N);
   const BlockInfo bi = P.blocks[s];
   const InstParams ip = P.inst[bi.inst];
-  const double c = (0.5 * dtv[bi.inst]) * hubble;
+  const double c = (0.5 * dtv[bi.inst]) * (hubble_dev ? *hubble_dev : hubble);
   double* const B = U + int64_t(s) * P.nf * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
   const bool de = P.nf == kFieldsDE;
   const double rho = B[0];
@@ -57,30 +83,38 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
 }
 
 template <int N>
-hipError_t expansion_n(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st) {
+hipError_t expansion_n(const DevPlan& P, double* U, const double* dt, double hubble, const double* hubble_dev,
+                       hipStream_t st) {
   const int64_t n = P.nleaf * int64_t(N) * N * N;
   if (n > 0)
     hipLaunchKernelGGL(expansion_kernel<N>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, U, dt,
-                       hubble, P);
+                       hubble, hubble_dev, P);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStream_t st) {
+hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStream_t st, const double* a_dev) {
   if (P.ninst > 0)
     hipLaunchKernelGGL(scale_dt_kernel, dim3(static_cast<unsigned>((P.ninst + 63) / 64)), dim3(64), 0, st, dt, a,
-                       P.dte, P.ninst);
+                       a_dev, P.dte, P.ninst);
   return hipGetLastError();
 }
 
-hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st) {
+hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st,
+                            const double* hubble_dev) {
   switch (P.N) {
-    case 8: return expansion_n<8>(P, U, dt, hubble, st);
-    case 16: return expansion_n<16>(P, U, dt, hubble, st);
-    case 32: return expansion_n<32>(P, U, dt, hubble, st);
+    case 8: return expansion_n<8>(P, U, dt, hubble, hubble_dev, st);
+    case 16: return expansion_n<16>(P, U, dt, hubble, hubble_dev, st);
+    case 32: return expansion_n<32>(P, U, dt, hubble, hubble_dev, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_cosmology(int stage, double H0, double om, double ol, const double* dt, double* cs,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(cosmology_kernel, dim3(1), dim3(64), 0, st, stage, H0, om, ol, dt, cs);
+  return hipGetLastError();
 }
 
 }  // namespace amr

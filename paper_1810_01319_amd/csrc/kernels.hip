@@ -208,11 +208,13 @@ __global__ void floor_mark(DevPlan P, unsigned long long* __restrict__ mark, int
   else P.counters[threadIdx.x] = mark[threadIdx.x];
 }
 
-__global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a) {
+// a_dev (nullable): the expansion factor on the device, in place of a
+__global__ void cfl_finalize(DevPlan P, double* __restrict__ dt, double a, const double* __restrict__ a_dev) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= P.ninst) return;
   const double mn = __longlong_as_double((long long)P.acc[m]);
-  dt[m] = (P.inst[m].cfl * a) * mn;  // a = 1 leaves cfl * mn bit for bit
+  const double av = a_dev ? *a_dev : a;
+  dt[m] = (P.inst[m].cfl * av) * mn;  // a = 1 leaves cfl * mn bit for bit
   P.acc[m] = 0x7FF0000000000000ull;
 }
 
@@ -925,7 +927,8 @@ hipError_t refresh_n(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_
 }
 
 template <int N>
-hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a) {
+hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a,
+                 const double* a_dev) {
   constexpr int N3 = N * N * N;
   int chunks = N3 / (8 * 256);
   if (chunks < 1) chunks = 1;
@@ -935,7 +938,7 @@ hipError_t cfl_n(const DevPlan& P, const double* U, double* dt, const LaunchCfg&
     else
       hipLaunchKernelGGL((cfl_kernel<N, kFields>), dim3(unsigned(P.nleaf * chunks)), dim3(256), 0, st, U, P, chunks);
   }
-  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt, a);
+  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt, a, a_dev);
   return hipGetLastError();
 }
 
@@ -1079,11 +1082,12 @@ hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipSt
   }
 }
 
-hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a) {
+hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st, double a,
+                      const double* a_dev) {
   switch (P.N) {
-    case 8: return cfl_n<8>(P, U, dt, L, st, a);
-    case 16: return cfl_n<16>(P, U, dt, L, st, a);
-    case 32: return cfl_n<32>(P, U, dt, L, st, a);
+    case 8: return cfl_n<8>(P, U, dt, L, st, a, a_dev);
+    case 16: return cfl_n<16>(P, U, dt, L, st, a, a_dev);
+    case 32: return cfl_n<32>(P, U, dt, L, st, a, a_dev);
     default: return hipErrorInvalidValue;
   }
 }

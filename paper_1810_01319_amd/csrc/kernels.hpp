@@ -46,12 +46,22 @@ hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipSt
 // prolongation into ghosts over a coarser leaf (the composite Poisson
 // operator's ghosts).
 hipError_t launch_refresh_scalar(const DevPlan& P, double* x, hipStream_t st);
-// dt = (C_cfl * a) * min ...; a = 1 outside comoving steps
+// dt = (C_cfl * a) * min ...; a = 1 outside comoving steps; a_dev (nullable):
+// a read on the device instead
 hipError_t launch_cfl(const DevPlan& P, const double* U, double* dt, const LaunchCfg& L, hipStream_t st,
-                      double a = 1.0);
-// comoving steps (comoving.hip): P.dte = dt / a; the expansion sources
-hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStream_t st);
-hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st);
+                      double a = 1.0, const double* a_dev = nullptr);
+// comoving steps (comoving.hip): P.dte = dt / a; the expansion sources with
+// rate hubble; a_dev, hubble_dev (nullable): the same read on the device
+hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStream_t st,
+                           const double* a_dev = nullptr);
+hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st,
+                            const double* hubble_dev = nullptr);
+// expansion history on the device (comoving.hip): flat matter + Lambda,
+// H(a) = H0 sqrt(om / a^3 + ol), om + ol = 1.  cs = {t, a(t), a(t_mid),
+// H(t_mid)}: stage 0 sets cs[1] = a(cs[0]); stage 1, with the step's dt,
+// sets t_mid = t + dt / 2, cs[2] = a(t_mid), cs[3] = H(cs[2]), cs[0] = t + dt
+hipError_t launch_cosmology(int stage, double H0, double om, double ol, const double* dt, double* cs,
+                            hipStream_t st);
 // sweep along dir; swept[a] = axis a already swept this step
 hipError_t launch_sweep(const DevPlan& P, double* U, const double* dt, int dir, const int swept[3],
                         const LaunchCfg& L, hipStream_t st);

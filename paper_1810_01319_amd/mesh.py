@@ -174,6 +174,21 @@ class Mesh:
         check(lib().amr_hydro_step_comoving(self._h, _ptr(U), _ptr(dt), int(k), ctypes.c_double(a),
                                             ctypes.c_double(hubble), _stream()))
 
+    def steps_comoving(self, U: torch.Tensor, dts: torch.Tensor, n: int, first: int, cosmo: torch.Tensor,
+                       H0: float, omega_m: float = 1.0, omega_l: float = 0.0) -> None:
+        """n comoving steps with the expansion history of a flat matter +
+        Lambda background evaluated on the device: cosmo is a float64 device
+        tensor of 4 ([0] the time t in and out; [1] a(t) at the last step's
+        start; [2], [3] a and H at its mid time), dts receives the n dts."""
+        self._check_state(U)
+        if dts.dtype != torch.float64 or dts.device != U.device or dts.numel() < n or not dts.is_contiguous():
+            raise ValueError("dts must be a contiguous float64 device tensor of at least n entries")
+        if cosmo.dtype != torch.float64 or cosmo.device != U.device or cosmo.numel() != 4:
+            raise ValueError("cosmo must be a float64 device tensor of 4 entries")
+        check(lib().amr_hydro_steps_comoving(self._h, _ptr(U), _ptr(dts), int(n), int(first), ctypes.c_double(H0),
+                                             ctypes.c_double(omega_m), ctypes.c_double(omega_l), _ptr(cosmo),
+                                             _stream()))
+
     def floor_count(self) -> int:
         out = ctypes.c_int64()
         check(lib().amr_floor_count(self._h, ctypes.byref(out), _stream()))

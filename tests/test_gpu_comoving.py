@@ -128,3 +128,41 @@ def test_comoving_batched_instances_match_oracle():
             om.step_comoving(k, float(dts[i]), a, h)
             got = act[gm.first_leaf[i]:gm.first_leaf[i + 1]]
             assert np.array_equal(got, om.active()[perm]), f"instance {i} step {k}"
+
+
+@pytest.mark.parametrize("omega_m,omega_l", [(1.0, 0.0), (0.3, 0.7)])
+def test_device_resident_comoving_run_matches_oracle(omega_m, omega_l):
+    """amr_hydro_steps_comoving (the expansion history evaluated on the
+    device, nothing read back) against the oracle stepping with a and H from
+    the closed form on the host at the same times: dt within 1e-14, every
+    active cell within 1e-12, and the device's time, a and H after the run."""
+    from test_cosmology_background import flat_lcdm
+
+    root = (2, 2, 2)
+    spec = I.MeshSpec(root=root, block_cells=16, max_level=2, gamma=5.0 / 3.0,
+                      refine=I.random_refine_list(root, 2, 4, 9))
+    say(f"device-resident comoving run, omega_m {omega_m}, omega_l {omega_l}")
+    orc, gm, perm = pair(spec)
+    U = load(orc, gm, perm, I.smooth_state(spec, gm.keys, seed=31, amp=0.2, vel=0.6))
+    H0, t0, n = 2.0 / 3.0, 1.0, 6
+    cosmo = torch.tensor([t0, 0.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
+    dts = torch.zeros(n, dtype=torch.float64, device="cuda")
+    gm.steps_comoving(U, dts, n, 0, cosmo, H0, omega_m, omega_l)
+    d = dts.cpu().numpy()
+    t = t0
+    for k in range(n):
+        a, _ = flat_lcdm(t, H0, omega_m, omega_l)
+        dto = orc.cfl_dt_comoving(a)
+        assert abs(d[k] - dto) <= 1e-14 * dto, (k, d[k], dto)
+        tm = t + 0.5 * d[k]
+        am, hm = flat_lcdm(tm, H0, omega_m, omega_l)
+        orc.step_comoving(k, float(d[k]), am, hm)
+        t += d[k]
+    err, bw = compare_active(gm, U, orc, perm)
+    say(f"after {n} steps: rel err {err:.3e}, bitwise fraction {bw:.6f}")
+    assert err <= TOL
+    c = cosmo.cpu().numpy()
+    a_last = flat_lcdm(t - d[-1], H0, omega_m, omega_l)[0]
+    assert abs(c[0] - t) <= 1e-14 * t
+    assert abs(c[1] - a_last) <= 1e-14 * a_last
+    assert abs(c[2] - am) <= 1e-14 * am and abs(c[3] - hm) <= 1e-14 * hm

@@ -60,7 +60,7 @@ def compare_active(gm, U, om, perm, tol=TOL):
     return float(np.max(err)), float(bitwise)
 
 
-def run_case(name, spec, act_fn, steps, fixed_dt=None):
+def run_case(name, spec, act_fn, steps, fixed_dt=None, compare_every=1):
     say(f"case {name}: root={spec.root} N={spec.block_cells} levels={spec.max_level} steps={steps}")
     om, gm, perm = pair(spec)
     U = load(om, gm, perm, act_fn(spec, gm.keys))
@@ -77,8 +77,11 @@ def run_case(name, spec, act_fn, steps, fixed_dt=None):
             gm.step_dt(U, dt, k)
             om.step_dt(k, fixed_dt)
         torch.cuda.synchronize()
+        if (k + 1) % compare_every and k + 1 < steps:
+            continue
         err, bw = compare_active(gm, U, om, perm)
         worst = max(worst, err)
+        say(f"case {name}: step {k}, rel err {err:.3e}, bitwise fraction {bw:.6f}")
         assert err <= TOL, f"{name}: step {k} rel err {err:.3e}"
     assert gm.floor_count() == om.floors, f"{name}: floor counts differ"
     say(f"case {name}: worst rel err {worst:.3e}, bitwise fraction {bw:.6f}")
@@ -171,9 +174,10 @@ def test_floor_triggers_match():
 
 def test_sedov_full_size_parity():
     """The static two-level Sedov workload at its full size (8^3 roots of
-    32^3 cells, 624 leaves, 20.4M cells), two steps against the oracle."""
+    32^3 cells, 624 leaves, 20.4M cells) for its 50 steps against the
+    oracle: every step's dt exactly, every field every 10 steps."""
     spec = I.sedov_spec(root=8, block_cells=32, levels=2)
-    run_case("sedov full 8^3 x 32^3", spec, I.sedov_state, 2)
+    run_case("sedov full 8^3 x 32^3", spec, I.sedov_state, 50, compare_every=10)
 
 
 def test_repeat_runs_are_bitwise_identical():
@@ -288,7 +292,8 @@ def test_indicator_bitwise():
 
 def test_batched_instances_match_oracle_bitwise():
     """16 uneven instances of the batched workload in one worklist: every
-    instance's dt sequence and state equal its own oracle run bitwise."""
+    instance's dt sequence and state equal its own oracle run bitwise over
+    10 steps."""
     specs, cents = zip(*[I.batch_instance(i) for i in range(16)])
     gm = Mesh.batch([s.kwargs() for s in specs])
     say(f"batch of 16: {gm.nleaf} leaves")
@@ -306,7 +311,7 @@ def test_batched_instances_match_oracle_bitwise():
         oms.append((om, perm))
     U = gm.state_from_active(np.concatenate(acts))
     dt = gm.dt_tensor()
-    for k in range(4):
+    for k in range(10):
         gm.step(U, dt, k)
         dts = dt.cpu().numpy()
         for i, (om, perm) in enumerate(oms):
