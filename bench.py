@@ -143,13 +143,19 @@ def roofline_object(d: dict, workload_name: str) -> dict:
                 "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
                 "flops_per_launch": d["flops_per_launch"],
                 "other_roof": other})
+    sec = d["avg_launch_ms"] * 1e-3
     if traffic is not None:
         out["traffic_over_algorithmic"] = traffic / d["algorithmic_bytes_per_launch"]
+        out["traffic_hbm_frac"] = traffic / sec / 1e9 / PEAK_HBM_GBS  # measured bytes, not algorithmic
     valu = committed_counters(d["kernel"], workload_name, "valu")
     if valu:
         out["valu_busy"] = float(valu["valu_busy"])
-        out["valu_issue_frac"] = (float(valu["valu_insts_per_launch"]) * 4
-                                  / (d["avg_launch_ms"] * 1e-3 * 1024 * 2.4e9))
+        out["valu_issue_frac"] = float(valu["valu_insts_per_launch"]) * 4 / (sec * 1024 * 2.4e9)
+        if "fp64_flops_executed_per_launch" in valu:
+            # executed FP64 operations (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes): divisions and square
+            # roots as their Newton-Raphson / Goldschmidt sequences, divergent branches both arms
+            ex = float(valu["fp64_flops_executed_per_launch"]) / sec / 1e12
+            out["fp64_executed"] = {"TFLOP/s": ex, "frac": ex / PEAK_FP64_TFLOPS}
     return out
 
 
