@@ -98,13 +98,14 @@ def sweep_roofline(prof, step_leaves, N, nf, launch, workload_name, iters=5):
     pencils per leaf depend on its place in that step's order (x, y, z on
     even steps, z, y, x on odd ones).  Per launch: algorithmic bytes (read
     the pencil's M cells and write its N cells, 5 fields of 8 B) and
-    algorithmic flops (the cost model's count per pencil), divided by the
+    algorithmic flops (the oracle's mean executed operations per pencil on
+    this workload, else the cost model's longest-path count), divided by the
     kernel's mean launch time from the library's HIP events.  Returns
     (per-axis table, dominant axis)."""
     from paper_1810_01319_amd import costs
 
     pen = costs.sweep_pencils_per_block(N)
-    fpp = costs.sweep_flops_per_pencil(N, iters)
+    fpp = costs.sweep_ops_per_pencil(workload_name, N, iters)
     bpp = costs.sweep_bytes_per_pencil(N)
     axes = ("x", "y", "z")
     per_axis = {}

@@ -44,10 +44,6 @@
 
 enum { ABSENT = 0, LEAF = 1, REFINED = 2 };
 
-/* Published PPM flattening constants (Colella & Woodward 1984): shock
- * detection threshold and the ramp of the flattening coefficient. */
-static const double EPS_S = 0.33, OMEGA1 = 0.75, OMEGA2 = 10.0;
-
 struct orc_mesh {
   orc_desc d;
   int N, M, nlev;
@@ -62,13 +58,6 @@ struct orc_mesh {
   int64_t floors;
 };
 
-typedef struct {
-  double gamma, gm1, inv_gm1, g_gm1, g1, rho_floor, p_floor, sixth, two3;
-  int iters;
-  int de;             /* dual-energy field present */
-  double eta1, eta2;  /* its pressure-selection and resynchronisation thresholds */
-} consts_t;
-
 static char g_err[256];
 /* Test-only switches that plant a known mistake, to show that a pin fails
  * without the piece it checks (ORC_DEBUG_*). */
@@ -77,35 +66,6 @@ const char* orc_last_error(void) { return g_err; }
 static int fail(const char* msg) {
   snprintf(g_err, sizeof g_err, "%s", msg);
   return -1;
-}
-
-/* Gas constants computed once in FP64, in the forms the formulas use. */
-static consts_t make_consts(double gamma, double rho_floor, double p_floor, int iters) {
-  consts_t K;
-  K.gamma = gamma;
-  K.gm1 = gamma - 1.0;
-  K.inv_gm1 = 1.0 / (gamma - 1.0);
-  K.g_gm1 = gamma / (gamma - 1.0);
-  K.g1 = (gamma + 1.0) / (2.0 * gamma);
-  K.rho_floor = rho_floor;
-  K.p_floor = p_floor;
-  K.sixth = 1.0 / 6.0;
-  K.two3 = 2.0 / 3.0;
-  K.iters = iters;
-  K.de = 0;
-  K.eta1 = 0.0;
-  K.eta2 = 0.0;
-  return K;
-}
-
-static double cell_pressure(const consts_t* K, double rho, double u, double v, double w, double E, double ge);
-
-static consts_t mesh_consts(const orc_mesh* m) {
-  consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
-  K.de = m->d.dual_energy != 0;
-  K.eta1 = m->d.eta1;
-  K.eta2 = m->d.eta2;
-  return K;
 }
 
 /* ------------------------------------------------------------------ */
@@ -153,6 +113,18 @@ static inline double babs(double x) { return BR(signbit(x) != 0) ? -x : x; }
 
 static inline double dmax(double a, double b) { return BR(a < b) ? b : a; }
 static inline double dmin(double a, double b) { return BR(a < b) ? a : b; }
+
+/* The PPM pencil, the cell update and the gas constants they use; compiled
+ * a second time with a counting number type by opcount.cpp. */
+#include "ppm_pencil.inc"
+
+static consts_t mesh_consts(const orc_mesh* m) {
+  consts_t K = make_consts(m->d.gamma, m->d.rho_floor, m->d.p_floor, m->d.riemann_iters);
+  K.de = m->d.dual_energy != 0;
+  K.eta1 = m->d.eta1;
+  K.eta2 = m->d.eta2;
+  return K;
+}
 
 /* ------------------------------------------------------------------ */
 /* Mesh: dense per-level node state, 2:1 balance                       */
@@ -569,251 +541,6 @@ static double cfl_min(const orc_mesh* m) {
 
 double orc_cfl_dt(const orc_mesh* m) { return m->d.cfl * cfl_min(m); }
 
-/* ------------------------------------------------------------------ */
-/* PPM pencil (Sec. II-C, "ppm"; Colella & Woodward 1984 as modified)  */
-/* ------------------------------------------------------------------ */
-
-/* Primitive state of one cell; normal/transverse momenta are the sweep's. */
-typedef struct { double q[5]; double c, ir; } prim_t;  /* q = rho,u,v,w,p */
-
-/* Pressure (before the floor) of a cell with density rho, velocity u, v, w,
- * total energy E and (dual energy) internal energy density ge.  Dual-energy
- * reading (Bryan et al. 1995): the internal energy is E - ke where it exceeds
- * eta1 E, else the separately advected rho e. */
-static double cell_pressure(const consts_t* K, double rho, double u, double v, double w, double E, double ge) {
-  const double ie = E - (0.5 * rho) * ((u * u + v * v) + w * w);
-  const int use_ge = (g_debug & ORC_DEBUG_DE_ETA1_FLIP) ? (ie > K->eta1 * E) : !(ie > K->eta1 * E);
-  if (K->de && use_ge) return K->gm1 * ge;
-  return K->gm1 * ie;
-}
-
-static prim_t to_prim(const consts_t* K, double rho, double mn, double mt1, double mt2, double E, double ge) {
-  prim_t P;
-  double ir = 1.0 / rho;
-  double u = mn * ir, v = mt1 * ir, w = mt2 * ir;
-  double p = cell_pressure(K, rho, u, v, w, E, ge);
-  p = BR(p < K->p_floor) ? K->p_floor : p;
-  P.q[0] = rho; P.q[1] = u; P.q[2] = v; P.q[3] = w; P.q[4] = p;
-  P.c = sqrt((K->gamma * p) * ir);
-  P.ir = ir;
-  return P;
-}
-
-/* Limited (monotonised central) slope of cell j from q[j-1], q[j], q[j+1]. */
-static double mc_slope(double qm, double q0, double qp) {
-  double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
-  if (!BR(dl * dr > 0.0)) return 0.0;
-  double mlim = dmin(dmin(babs(dc), 2.0 * babs(dl)), 2.0 * babs(dr));
-  return BR(dc > 0.0) ? mlim : -mlim;
-}
-
-/* Parabola of one cell after flattening and the monotonicity constraint. */
-typedef struct { double qL, qR, dq, q6; } para_t;
-
-static para_t make_parabola(const consts_t* K, double q, double qL, double qR, double f) {
-  para_t P;
-  qL = f * q + (1.0 - f) * qL;
-  qR = f * q + (1.0 - f) * qR;
-  if (BR((qR - q) * (q - qL) <= 0.0)) {
-    qL = q;
-    qR = q;
-  } else {
-    double D = qR - qL, mm = q - 0.5 * (qL + qR);
-    if (BR(D * mm > (D * D) * K->sixth))
-      qL = 3.0 * q - 2.0 * qR;
-    else if (BR(-((D * D) * K->sixth) > D * mm))
-      qR = 3.0 * q - 2.0 * qL;
-  }
-  P.qL = qL;
-  P.qR = qR;
-  P.dq = qR - qL;
-  P.q6 = 6.0 * (q - 0.5 * (qL + qR));
-  return P;
-}
-
-/* Mean of the parabola over the part of the cell a wave of Courant number s
- * sweeps through in dt, at the right edge (Ip) and at the left edge (Im). */
-static inline double Ip(const consts_t* K, const para_t* P, double s) {
-  return P->qR - (0.5 * s) * (P->dq - (1.0 - K->two3 * s) * P->q6);
-}
-static inline double Im(const consts_t* K, const para_t* P, double s) {
-  return P->qL + (0.5 * s) * (P->dq + (1.0 - K->two3 * s) * P->q6);
-}
-
-/* Characteristic tracing of cell j: the left state at j+1/2 (WL) and the
- * right state at j-1/2 (WR).  Reference state = the fastest wave towards the
- * edge; the other waves moving towards it subtract their projections on the
- * primitive eigenvectors (rho,u,p); v,w ride the contact. */
-static void trace_cell(const consts_t* K, const prim_t* C, const para_t par[5], double nu,
-                       double WL[5], double WR[5]) {
-  const double rho = C->q[0], u = C->q[1], c = C->c;
-  const double lm = u - c, l0 = u, lp = u + c;
-  /* one reciprocal of c serves the three eigenvector weights */
-  const double ic = 1.0 / c;
-  const double Ac = (0.5 * rho) * ic;   /* rho / (2c) */
-  const double Bc = C->ir * ic;         /* 1 / (rho c) */
-  const double cc = c * c;
-  const double ic2 = ic * ic;           /* 1 / c^2 */
-  const double cor = c * C->ir;         /* c / rho */
-  /* right edge: waves with positive speed */
-  {
-    const int gm = BR(lm > 0.0), g0 = BR(l0 > 0.0), gp = BR(lp > 0.0);
-    double sm = (gm ? lm : 0.0) * nu, s0 = (g0 ? l0 : 0.0) * nu, sp = (gp ? lp : 0.0) * nu;
-    double rr = Ip(K, &par[0], sp), ur = Ip(K, &par[1], sp), pr = Ip(K, &par[4], sp);
-    double am = gm ? Ac * ((pr - Ip(K, &par[4], sm)) * Bc - (ur - Ip(K, &par[1], sm))) : 0.0;
-    double a0 = g0 ? (rr - Ip(K, &par[0], s0)) - (pr - Ip(K, &par[4], s0)) * ic2 : 0.0;
-    WL[0] = (rr - am) - a0;
-    WL[1] = ur + cor * am;
-    WL[4] = pr - cc * am;
-    WL[2] = Ip(K, &par[2], s0);
-    WL[3] = Ip(K, &par[3], s0);
-  }
-  /* left edge: waves with negative speed */
-  {
-    const int gm = BR(lm < 0.0), g0 = BR(l0 < 0.0), gp = BR(lp < 0.0);
-    double sm = (gm ? -lm : 0.0) * nu, s0 = (g0 ? -l0 : 0.0) * nu, sp = (gp ? -lp : 0.0) * nu;
-    double rr = Im(K, &par[0], sm), ur = Im(K, &par[1], sm), pr = Im(K, &par[4], sm);
-    double ap = gp ? Ac * ((pr - Im(K, &par[4], sp)) * Bc + (ur - Im(K, &par[1], sp))) : 0.0;
-    double a0 = g0 ? (rr - Im(K, &par[0], s0)) - (pr - Im(K, &par[4], s0)) * ic2 : 0.0;
-    WR[0] = (rr - ap) - a0;
-    WR[1] = ur - cor * ap;
-    WR[4] = pr - cc * ap;
-    WR[2] = Im(K, &par[2], s0);
-    WR[3] = Im(K, &par[3], s0);
-  }
-  /* positivity floors on the edge states */
-  if (g_debug & ORC_DEBUG_EDGE_NO_FLOOR) return;
-  WL[0] = BR(WL[0] < K->rho_floor) ? K->rho_floor : WL[0];
-  WL[4] = BR(WL[4] < K->p_floor) ? K->p_floor : WL[4];
-  WR[0] = BR(WR[0] < K->rho_floor) ? K->rho_floor : WR[0];
-  WR[4] = BR(WR[4] < K->p_floor) ? K->p_floor : WR[4];
-}
-
-/* Two-shock approximate Riemann solver (the PPM approximation of Colella &
- * Woodward 1984): both waves treated as shocks, a fixed number of Newton
- * steps on p*, sampled at x/t = 0 with rarefaction fans interpolated linearly
- * between head and tail.  Written with reciprocals of the shock mass fluxes
- * W_K = C_K sqrt(1 + (gamma+1)/(2 gamma) (p* / p_K - 1)) and of the impedances
- * Z_K = 2 W_K^3 / (W_K^2 + C_K^2), so 1/Z_K = (1 + (C_K/W_K)^2) / (2 W_K):
- *   u*_L = u_L - (p* - p_L)/W_L,  u*_R = u_R + (p* - p_R)/W_R,
- *   p*  <- p* - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
- *   u*   = (u*_L/Z_R + u*_R/Z_L) / (1/Z_L + 1/Z_R)   (= Z-weighted mean).
- * Returns the Godunov state and its flux; with the dual-energy field also
- * the flux of rho e, the internal-energy flux of the Godunov state,
- * u_g p_g / (gamma - 1) (rho e and p are the same variable up to the factor
- * gamma - 1, so its interface value is the characteristic-traced p_g; a
- * value carried along the contact alone would miss the acoustic waves and
- * drop to first order in time). */
-static void riemann(const consts_t* K, const double WLs[5], const double WRs[5], double Wg[5],
-                    double F[], double* pstar, double* ustar) {
-  const double rL = WLs[0], uL = WLs[1], pL = WLs[4];
-  const double rR = WRs[0], uR = WRs[1], pR = WRs[4];
-  const double CL = sqrt((K->gamma * pL) * rL), CR = sqrt((K->gamma * pR) * rR);
-  const double ipL = 1.0 / pL, ipR = 1.0 / pR;
-  double ps = ((CR * pL + CL * pR) - (CL * CR) * (uR - uL)) / (CL + CR);
-  ps = BR(ps < K->p_floor) ? K->p_floor : ps;
-  double iWL = 0.0, iWR = 0.0, iZL = 0.0, iZR = 0.0, usL = 0.0, usR = 0.0, WLw = 0.0, WRw = 0.0;
-  for (int it = 0; it <= K->iters; it++) {
-    WLw = CL * sqrt(1.0 + K->g1 * (ps * ipL - 1.0));
-    WRw = CR * sqrt(1.0 + K->g1 * (ps * ipR - 1.0));
-    iWL = 1.0 / WLw;
-    iWR = 1.0 / WRw;
-    usL = uL - (ps - pL) * iWL;
-    usR = uR + (ps - pR) * iWR;
-    const double qL = CL * iWL, qR = CR * iWR;
-    iZL = (0.5 * iWL) * (1.0 + qL * qL);
-    iZR = (0.5 * iWR) * (1.0 + qR * qR);
-    if (it == K->iters) break; /* final pass: wave speeds at the last p* */
-    ps = ps - (usR - usL) / (iZL + iZR);
-    ps = BR(ps < K->p_floor) ? K->p_floor : ps;
-  }
-  const double us = (iZR * usL + iZL * usR) / (iZL + iZR);
-  /* side of the contact the interface lies on; a tie takes the left side */
-  const int left = BR(us >= 0.0);
-  const double s = left ? 1.0 : -1.0;
-  const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
-  const double WK = left ? WLw : WRw, iWK = left ? iWL : iWR;
-  const double irK = 1.0 / rK;
-  const double vs = irK - (ps - pK) * (iWK * iWK); /* 1/rho* on side K */
-  const double rs = 1.0 / vs;
-  double rg, ug, pg;
-  if (BR(ps > pK)) {
-    /* shock: S = u_K - s W_K / rho_K */
-    double S = uK - s * (WK * irK);
-    if (BR(s * S >= 0.0)) { rg = rK; ug = uK; pg = pK; }
-    else { rg = rs; ug = us; pg = ps; }
-  } else {
-    double cK = sqrt((K->gamma * pK) * irK);
-    double cs = sqrt((K->gamma * ps) * vs);
-    double lh = uK - s * cK, lt = us - s * cs;
-    if (BR(s * lh >= 0.0)) { rg = rK; ug = uK; pg = pK; }
-    else if (BR(s * lt <= 0.0)) { rg = rs; ug = us; pg = ps; }
-    else {
-      double xi = lh / (lh - lt);
-      rg = rK + xi * (rs - rK);
-      ug = uK + xi * (us - uK);
-      pg = pK + xi * (ps - pK);
-    }
-  }
-  const double vg = left ? WLs[2] : WRs[2], wg = left ? WLs[3] : WRs[3];
-  const double mf = rg * ug;
-  F[0] = mf;
-  F[1] = mf * ug + pg;
-  F[2] = mf * vg;
-  F[3] = mf * wg;
-  F[4] = ug * (pg * K->g_gm1 + (0.5 * rg) * ((ug * ug + vg * vg) + wg * wg));
-  if (K->de) F[5] = ug * (pg * ((g_debug & ORC_DEBUG_DE_ENTHALPY) ? K->g_gm1 : K->inv_gm1));
-  Wg[0] = rg; Wg[1] = ug; Wg[2] = vg; Wg[3] = wg; Wg[4] = pg;
-  if (pstar) *pstar = ps;
-  if (ustar) *ustar = us;
-}
-
-/* Fluxes at interfaces j+1/2, j = 2 .. n-4, of a pencil of n cells; U is
- * (rho, m_normal, m_t1, m_t2, E [, rho e]) x n, F is nv x (n-5) and, with the
- * dual-energy field, ug (n-5) the Godunov velocity at each interface.  Cell
- * j's update needs cells j-3 .. j+3, which a ghost width of 3 provides. */
-static void pencil(const consts_t* K, double nu, int n, const double* const U[], double* const F[], double* ug) {
-  const int nf = K->de ? 6 : 5;
-  prim_t* P = (prim_t*)malloc((size_t)n * sizeof(prim_t));
-  double(*dl)[5] = malloc((size_t)n * sizeof *dl);   /* slopes */
-  double(*fa)[5] = malloc((size_t)n * sizeof *fa);   /* face values at j+1/2 */
-  double(*WL)[5] = malloc((size_t)n * sizeof *WL);   /* left state at j+1/2 from cell j */
-  double(*WR)[5] = malloc((size_t)n * sizeof *WR);   /* right state at j-1/2 from cell j */
-  for (int j = 0; j < n; j++)
-    P[j] = to_prim(K, U[0][j], U[1][j], U[2][j], U[3][j], U[4][j], K->de ? U[5][j] : 0.0);
-  for (int j = 1; j <= n - 2; j++)
-    for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
-  /* interface value q_{j+1/2} = 0.5 (q_j + q_{j+1}) - (dq_{j+1} - dq_j) / 6 */
-  for (int j = 1; j <= n - 3; j++)
-    for (int v = 0; v < 5; v++)
-      fa[j][v] = 0.5 * (P[j].q[v] + P[j + 1].q[v]) - (dl[j + 1][v] - dl[j][v]) * K->sixth;
-  for (int j = 2; j <= n - 3; j++) {
-    /* local flattening: shock detector on p and u, ramp on the pressure
-     * ratio (the upwind max over neighbours is dropped: it would need a
-     * fourth ghost cell) */
-    double pp = P[j + 1].q[4], pm = P[j - 1].q[4];
-    double dp1 = pp - pm;
-    double pmin = BR(pp < pm) ? pp : pm;
-    int shock = BR(babs(dp1) > EPS_S * pmin) && BR(P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
-    double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
-    double r = BR(dp2 != 0.0) ? dp1 / dp2 : 0.0;
-    double ft = OMEGA2 * (r - OMEGA1);
-    ft = BR(ft < 1.0) ? ft : 1.0;
-    ft = BR(ft > 0.0) ? ft : 0.0;
-    double f = shock ? ft : 0.0;
-    para_t par[5];
-    for (int v = 0; v < 5; v++) par[v] = make_parabola(K, P[j].q[v], fa[j - 1][v], fa[j][v], f);
-    trace_cell(K, &P[j], par, nu, WL[j], WR[j]);
-  }
-  for (int j = 2; j <= n - 4; j++) {
-    double Wg[5], Fl[6];
-    riemann(K, WL[j], WR[j + 1], Wg, Fl, NULL, NULL);
-    for (int v = 0; v < nf; v++) F[v][j - 2] = Fl[v];
-    if (ug) ug[j - 2] = Wg[1];
-  }
-  free(P); free(dl); free(fa); free(WL); free(WR);
-}
-
 /* One directional sweep over every leaf.  swept[a] says whether axis a was
  * already swept this step (then only its active range is updated). */
 static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], double dt) {
@@ -855,40 +582,13 @@ static void sweep(orc_mesh* m, const consts_t* K, int dir, const int swept[3], d
         pencil(K, nu, M, (const double* const*)in, fl, ug);
         /* flux index k is interface (G-1+k)+1/2 */
         for (int j = G; j < G + N; j++) {
-          double Un[6];
-          for (int v = 0; v < nv; v++) Un[v] = in[v][j] - nu * (fl[v][j - G + 1] - fl[v][j - G]);
-          if (K->de) {
-            /* the -p div(v) work on rho e: the cell's pressure (as in its
-             * primitives) times the difference of the Godunov velocities */
-            const prim_t Pj = to_prim(K, in[0][j], in[1][j], in[2][j], in[3][j], in[4][j], in[5][j]);
-            const double work = Pj.q[4] * (ug[j - G + 1] - ug[j - G]);
-            Un[5] = (g_debug & ORC_DEBUG_DE_PDV_SIGN) ? Un[5] + nu * work : Un[5] - nu * work;
+          double Uc[6], Fm[6], Fp[6], Un[6];
+          for (int v = 0; v < nv; v++) {
+            Uc[v] = in[v][j];
+            Fm[v] = fl[v][j - G];
+            Fp[v] = fl[v][j - G + 1];
           }
-          /* post-update floors (counted: they break conservation) */
-          if (BR(Un[0] < K->rho_floor)) {
-            if (g_debug & ORC_DEBUG_FLOOR_KEEP_VEL)
-              for (int d = 1; d <= 3; d++) Un[d] = Un[d] * (K->rho_floor / Un[0]);
-            Un[0] = K->rho_floor;
-            if (!(g_debug & ORC_DEBUG_FLOOR_NO_COUNT)) nfl++;
-          }
-          double ir = 1.0 / Un[0];
-          double u = Un[1] * ir, v = Un[2] * ir, w = Un[3] * ir;
-          double ke = (0.5 * Un[0]) * ((u * u + v * v) + w * w);
-          double p = K->gm1 * (Un[4] - ke);
-          if (BR(p < K->p_floor)) {
-            Un[4] = (g_debug & ORC_DEBUG_FLOOR_E_NO_KE) ? K->p_floor * K->inv_gm1 : K->p_floor * K->inv_gm1 + ke;
-            nfl++;
-          }
-          if (K->de) {
-            /* resynchronise rho e from the total energy where E - ke > eta2 E,
-             * then its own floor (counted) */
-            const double ie = Un[4] - ke;
-            if (BR(ie > K->eta2 * Un[4])) Un[5] = ie;
-            if (BR(K->gm1 * Un[5] < K->p_floor)) {
-              Un[5] = (g_debug & ORC_DEBUG_DE_FLOOR_NO_IG) ? K->p_floor : K->p_floor * K->inv_gm1;
-              nfl++;
-            }
-          }
+          nfl += update_cell(K, nu, Uc, Fm, Fp, ug[j - G], ug[j - G + 1], Un);
           pos[dir] = j;
           for (int vv = 0; vv < nv; vv++) B[cell(M, fmap[vv], pos[0], pos[1], pos[2])] = Un[vv];
         }

@@ -22,6 +22,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amr_oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "mg_oracle.c")]
 _SO = os.path.join(_HERE, "libamr_oracle.so")
+_INC = os.path.join(_HERE, "ppm_pencil.inc")  # the pencil, included by amr_oracle.c and opcount.cpp
+_COUNT_SRC = os.path.join(_HERE, "opcount.cpp")
+_COUNT_SO = os.path.join(_HERE, "liborc_opcount.so")
 GHOST = 3
 NFIELD = 5
 BC = {"periodic": 0, "outflow": 1}
@@ -32,11 +35,17 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into ``oracle/libamr_oracle.so``."""
+    """Compile the oracle with gcc into ``oracle/libamr_oracle.so`` and its
+    operation counter with g++ into ``oracle/liborc_opcount.so``."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _SO)
+    if force or not os.path.exists(_COUNT_SO):
+        tmp = _COUNT_SO + ".tmp"
+        subprocess.check_call(["g++", "-std=c++20", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+                               "-o", tmp, _COUNT_SRC])
+        os.replace(tmp, _COUNT_SO)
     return _SO
 
 
@@ -77,7 +86,7 @@ def lib() -> ctypes.CDLL:
         so = os.environ.get("AMR_ORACLE_LIBRARY", "")
         if not so:
             so = _SO
-            if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS + [_INC]):
                 build()
         L = ctypes.CDLL(so)
         P, D, I64, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
@@ -393,6 +402,78 @@ def pencil_flux(U, nu, gamma=1.4, rho_floor=1e-20, p_floor=1e-20, iters=5):
     out = np.zeros((5, n - 5))
     gas = np.array([gamma, rho_floor, p_floor])
     lib().orc_pencil_flux(_ptr(gas), int(iters), float(nu), int(n), _ptr(U), _ptr(out))
+    return out
+
+
+_count_lib = None
+
+
+def _counter() -> ctypes.CDLL:
+    global _count_lib
+    if _count_lib is None:
+        if not os.path.exists(_COUNT_SO) or os.path.getmtime(_COUNT_SO) < max(
+                os.path.getmtime(f) for f in (_COUNT_SRC, _INC)):
+            build()
+        L = ctypes.CDLL(_COUNT_SO)
+        P, D, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+        L.orc_count_sweep_ops.argtypes = [P, I32, D, I32, P, P]
+        L.orc_count_sweep_ops.restype = I32
+        L.orc_count_riemann_ops.argtypes = [P, I32, P, P, P, P]
+        L.orc_count_block_ops.argtypes = [I32, P, D, P, P]
+        L.orc_count_block_ops.restype = I32
+        _count_lib = L
+    return _count_lib
+
+
+OPS = ("add", "sub", "mul", "div", "sqrt")
+
+
+def count_sweep_ops(U, nu, gamma=1.4, rho_floor=1e-20, p_floor=1e-20, iters=5):
+    """FP64 operations the oracle executes for one sweep of the pencil U[5, n]
+    (fluxes at the n - 5 interfaces, then the update and floors of the n - 6
+    cells between the ghost layers): dict of add, sub, mul, div, sqrt and
+    their total, plus the floor resets."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = U.shape[1]
+    gas = np.array([gamma, rho_floor, p_floor])
+    c = np.zeros(5, dtype=np.int64)
+    nfl = _counter().orc_count_sweep_ops(_ptr(gas), int(iters), float(nu), int(n), _ptr(U), _ptr(c))
+    if nfl < 0:
+        raise ValueError("a pencil needs at least 7 cells")
+    out = dict(zip(OPS, map(int, c)))
+    out["total"] = int(c.sum())
+    out["floors"] = int(nfl)
+    return out
+
+
+def count_riemann_ops(WL, WR, gamma=1.4, p_floor=1e-20, iters=5):
+    """FP64 operations of one two-shock Riemann solve (dict as above, with
+    the flux the counting build computed under "flux")."""
+    gas = np.array([gamma, p_floor])
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    c = np.zeros(5, dtype=np.int64)
+    fl = np.zeros(5)
+    _counter().orc_count_riemann_ops(_ptr(gas), int(iters), _ptr(WL), _ptr(WR), _ptr(c), _ptr(fl))
+    out = dict(zip(OPS, map(int, c)))
+    out["total"] = int(c.sum())
+    out["flux"] = fl
+    return out
+
+
+BLOCKS = {"primitives": 0, "slope": 1, "parabola": 2, "trace": 3, "update": 4}
+
+
+def count_block_ops(block, values, nu=0.0, gamma=1.4, rho_floor=1e-20, p_floor=1e-20):
+    """FP64 operations of one building block of the oracle's sweep (see
+    ``orc_count_block_ops`` for the layout of ``values``)."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    gas = np.array([gamma, rho_floor, p_floor])
+    c = np.zeros(5, dtype=np.int64)
+    if _counter().orc_count_block_ops(BLOCKS[block], _ptr(gas), float(nu), _ptr(v), _ptr(c)) != 0:
+        raise ValueError(block)
+    out = dict(zip(OPS, map(int, c)))
+    out["total"] = int(c.sum())
     return out
 
 
