@@ -220,6 +220,34 @@ amr_status amr_hydro_steps_comoving(amr_mesh* mesh, double* U_dev, double* dt_de
                                     int64_t first_step, double H0, double omega_m, double omega_l,
                                     double* cosmo_dev, void* stream);
 
+/* Adjoint of the comoving step (Sec. II-C comoving terms; the adjoint itself
+ * is not in the paper: reading R17, every step's dt, a and H frozen at the
+ * forward's values).  amr_hydro_step_comoving_record runs
+ * amr_hydro_step_comoving (dt_dev given, a and H at the mid time) from U_dev
+ * as amr_hydro_step_record does from a plain step: U_dev is refreshed in
+ * place (it becomes S0), S1_dev and S2_dev receive the second and third
+ * sweeps' inputs, U_pre_dev the state after the reflux and before the
+ * expansion sources, U_out_dev the step's result, floors_dev the sweeps'
+ * floor-reset count (the expansion's own resets are counted in
+ * amr_floor_count only).  amr_hydro_step_comoving_adjoint_recorded: on entry
+ * lam_dev holds dL/dU after the step (ghost entries zero), on exit dL/dU
+ * before it: the transpose of the expansion sources at U_pre_dev (each
+ * cell's floor decision held), then the plain step's transposes with dt / a
+ * (floors_host as for amr_hydro_step_adjoint_recorded; scratch_dev:
+ * adjoint_face_bytes of amr_mesh_info).  Five-field meshes only.
+ * Errors: AMR_E_INVALID for a dual-energy mesh, a null or aliased buffer,
+ * a <= 0 or non-finite a, H, floors_host < -1, riemann_iters > 8. */
+amr_status amr_hydro_step_comoving_record(amr_mesh* mesh, double* U_dev, const double* dt_dev, double a,
+                                          double hubble, double* S1_dev, double* S2_dev, double* U_pre_dev,
+                                          double* U_out_dev, uint64_t* floors_dev, int64_t step_index,
+                                          void* stream);
+amr_status amr_hydro_step_comoving_adjoint_recorded(amr_mesh* mesh, const double* S0_dev, const double* S1_dev,
+                                                    const double* S2_dev, const double* U_pre_dev,
+                                                    const double* dt_dev, double a, double hubble,
+                                                    const uint64_t* floors_dev, int64_t floors_host,
+                                                    double* lam_dev, void* scratch_dev, int64_t step_index,
+                                                    void* stream);
+
 /* Sec. II-C ppm Method on every Block, repeated; the fused CFL is not in
  * the paper (reading: a step's dt needs only its predecessor's output).
  * nsteps consecutive hydro steps (step indices first_step, first_step + 1,

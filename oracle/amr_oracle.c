@@ -731,6 +731,32 @@ static double misfit_difference(const orc_mesh* m, const double* rho_a, const or
   return D;
 }
 
+/* A branch tape driven by the caller, for frozen-branch runs of any
+ * sequence of oracle calls (comoving steps, say) on the calling thread:
+ * orc_tape_record() starts recording the choices of the calls that follow,
+ * orc_tape_replay() makes them return the recorded choices from the first,
+ * orc_tape_stop() detaches the tape; it returns -1 if the recording ran out
+ * of memory or a replay did not consume the recorded choices exactly (the
+ * replayed calls were not the recorded ones), else 0. */
+static tape_t g_user_tape;
+void orc_tape_record(void) {
+  free(g_user_tape.b);
+  memset(&g_user_tape, 0, sizeof g_user_tape);
+  t_tape = &g_user_tape;
+}
+void orc_tape_replay(void) {
+  g_user_tape.pos = 0;
+  g_user_tape.replay = 1;
+  g_user_tape.overrun = 0;
+  t_tape = &g_user_tape;
+}
+int orc_tape_stop(void) {
+  t_tape = NULL;
+  if (g_user_tape.overrun || (g_user_tape.replay && g_user_tape.pos != g_user_tape.n))
+    return fail("the branch tape was not replayed exactly");
+  return 0;
+}
+
 int orc_frozen_fd_density_grad(const orc_mesh* m0, int64_t first_step, int nsteps, const double* dts,
                                const double* target, double eps, const int64_t* idx, int64_t nidx,
                                double* grad_out, double* loss_out) {
@@ -822,7 +848,7 @@ static void expansion(orc_mesh* m, double dt, double hubble) {
   const double fv = (1.0 - c) / (1.0 + c);
   const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
   int64_t nfl = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl) SERIAL_IF_TAPED
   for (int64_t s = 0; s < m->nleaf; s++) {
     double* B = block_ptr(m, s);
     for (int z = G; z < G + N; z++)
@@ -838,7 +864,7 @@ static void expansion(orc_mesh* m, double dt, double hubble) {
           const double ke = (0.5 * *rho) * ((u * u + v * v) + w * w);
           const double ie = *E - ke;
           double ie2 = ie * fe;
-          if (ie2 < ie && K.gm1 * ie2 < K.p_floor) {
+          if (BR(ie2 < ie && K.gm1 * ie2 < K.p_floor)) {
             ie2 = (g_debug & ORC_DEBUG_EXP_FLOOR_NO_IG) ? K.p_floor : K.p_floor * K.inv_gm1;
             nfl++;
           }

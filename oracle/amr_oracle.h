@@ -113,6 +113,13 @@ int orc_step_gravity_comoving(orc_mesh* m, int64_t step_index, double dt, double
                               double hubble, double four_pi_G, double* phi, int phi_current, int ncycles, int nu1,
                               int nu2);
 
+/* Caller-driven branch tape (frozen-branch runs of any sequence of oracle
+ * calls on this thread): record, then replay the recorded choices; stop
+ * returns -1 if a replay did not consume them exactly, else 0. */
+void orc_tape_record(void);
+void orc_tape_replay(void);
+int orc_tape_stop(void);
+
 /* Frozen-branch central differences of the density misfit (reading R17 of
  * the adjoint: dt sequence and every discrete choice held at the base
  * run's).  From m's state (unchanged), nsteps steps of indices first_step,

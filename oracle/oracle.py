@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         L.orc_step_dt.argtypes = [P, I64, D]
         L.orc_frozen_fd_density_grad.argtypes = [P, I64, I32, P, P, D, P, I64, P, P]
         L.orc_frozen_fd_density_grad.restype = I32
+        L.orc_tape_stop.restype = I32
         L.orc_cfl_dt_comoving.argtypes = [P, D]
         L.orc_cfl_dt_comoving.restype = D
         L.orc_step_comoving.argtypes = [P, I64, D, D, D]
@@ -381,6 +382,22 @@ def num_threads() -> int:
 def set_debug(flags: int) -> None:
     """Plant a known mistake in the oracle (tests of the pins' power only)."""
     lib().orc_set_debug(int(flags))
+
+
+def tape_record() -> None:
+    """Record the discrete choices of the oracle calls that follow (this
+    thread), until tape_stop(); loops over blocks run serially meanwhile."""
+    lib().orc_tape_record()
+
+
+def tape_replay() -> None:
+    """Make the oracle calls that follow take the recorded choices."""
+    lib().orc_tape_replay()
+
+
+def tape_stop() -> None:
+    if lib().orc_tape_stop() != 0:
+        raise RuntimeError(lib().orc_last_error().decode())
 
 
 def riemann(WL, WR, gamma=1.4, p_floor=1e-20, iters=5):

@@ -139,6 +139,10 @@ SIGNATURES = {
     "amr_hydro_steps": (_I32, [_P, _P, _P, _I64, _I64, _P]),
     "amr_hydro_steps_fresh": (_I32, [_P, _P, _P, _I64, _I64, _P]),
     "amr_hydro_step_comoving": (_I32, [_P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, _P]),
+    "amr_hydro_step_comoving_record": (_I32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
+                                              _I64, _P]),
+    "amr_hydro_step_comoving_adjoint_recorded": (_I32, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double,
+                                                        _P, _I64, _P, _P, _I64, _P]),
     "amr_last_error": (ctypes.c_char_p, []),
 }
 

@@ -71,6 +71,45 @@ def run_steps(U0: torch.Tensor, mesh, steps: int, start: int = 0, record: bool =
     return HydroSteps.apply(U0, mesh, steps, start, record)
 
 
+class ComovingSteps(torch.autograd.Function):
+    """Comoving steps with given (dt, a, H) per step (dt a float64 device
+    tensor of one element, a and H at the step's mid time), all frozen in the
+    backward; every step keeps its refreshed input, its second and third
+    sweeps' inputs, its state before the expansion sources and its floor
+    count (four states per step)."""
+
+    @staticmethod
+    def forward(ctx, U0, mesh, schedule, start: int = 0):
+        U = U0.detach().clone()
+        saved = []
+        for i, (dt, a, hubble) in enumerate(schedule):
+            S1, S2, Up, Uo = (torch.empty_like(U) for _ in range(4))
+            floors = torch.empty(1, dtype=torch.int64, device=U.device)
+            mesh.step_comoving_record(U, dt, a, hubble, S1, S2, Up, Uo, floors, start + i)
+            saved.append((U, S1, S2, Up, floors))
+            U = Uo
+        ctx.mesh, ctx.saved, ctx.schedule, ctx.start = mesh, saved, list(schedule), start
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        mesh = ctx.mesh
+        lam = torch.where(active_mask(mesh), gU.detach(), torch.zeros((), dtype=gU.dtype, device=gU.device))
+        scratch = mesh.adjoint_face_scratch()
+        counts = torch.cat([s[4] for s in ctx.saved]).cpu().tolist()
+        for i in range(len(ctx.saved) - 1, -1, -1):
+            S0, S1, S2, Up, floors = ctx.saved[i]
+            dt, a, hubble = ctx.schedule[i]
+            mesh.step_comoving_adjoint_recorded(S0, S1, S2, Up, dt, a, hubble, floors, lam, scratch, ctx.start + i,
+                                                floors_host=int(counts[i]))
+        return lam, None, None, None
+
+
+def run_comoving_steps(U0: torch.Tensor, mesh, schedule, start: int = 0) -> torch.Tensor:
+    """schedule: one (dt device tensor, a, H) per step."""
+    return ComovingSteps.apply(U0, mesh, schedule, start)
+
+
 class DensityMisfit(torch.autograd.Function):
     """L = sum over leaf cells of w (rho - rho_target)^2; its backward writes
     dL/dU (2 w (rho - rho_target) on the active densities, zero elsewhere,

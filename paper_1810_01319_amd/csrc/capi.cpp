@@ -689,6 +689,61 @@ amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const 
   return e == hipSuccess ? AMR_OK : hip_fail(e, "adjoint");
 }
 
+amr_status amr_hydro_step_comoving_record(amr_mesh* h, double* U, const double* dt, double a, double hubble,
+                                          double* S1, double* S2, double* Upre, double* Uout, uint64_t* floors,
+                                          int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, U);
+  if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
+  if (!dt || !S1 || !S2 || !Upre || !Uout || !floors) return fail(AMR_E_INVALID, "null argument");
+  const double* const bufs[5] = {U, S1, S2, Upre, Uout};
+  for (int i = 0; i < 5; i++)
+    for (int j = i + 1; j < 5; j++)
+      if (bufs[i] == bufs[j]) return fail(AMR_E_INVALID, "U, S1, S2, U_pre and U_out must be distinct buffers");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factor must be positive and finite");
+  if (!std::isfinite(hubble)) return fail(AMR_E_INVALID, "expansion rate must be finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  unsigned long long* mark = reinterpret_cast<unsigned long long*>(floors);
+  hipError_t e = launch_floor_mark(P, mark, 0, st);
+  if (e == hipSuccess) e = launch_scale_dt(P, dt, a, st);
+  if (e != hipSuccess) return hip_fail(e, "comoving record");
+  double* const out[3] = {S1, S2, Upre};
+  rc = run_step_into(h, U, out, P.dte, step_index, st);
+  if (rc != AMR_OK) return rc;
+  // the sweeps' resets only: the adjoint's floor transposes depend on them
+  e = launch_floor_mark(P, mark, 1, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(Uout, Upre, size_t(h->plan.nleaf) * kFields * size_t(h->plan.M) * h->plan.M * h->plan.M *
+                                       sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, Uout, dt, hubble, st); });
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "comoving record");
+}
+
+amr_status amr_hydro_step_comoving_adjoint_recorded(amr_mesh* h, const double* S0, const double* S1,
+                                                    const double* S2, const double* Upre, const double* dt, double a,
+                                                    double hubble, const uint64_t* floors, int64_t floors_host,
+                                                    double* lam, void* scratch, int64_t step_index, void* stream) {
+  amr_status rc = check_ready(h, S0);
+  if (rc != AMR_OK) return rc;
+  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
+  if (!S1 || !S2 || !Upre || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
+  if (floors_host < -1) return fail(AMR_E_INVALID, "floors_host must be a count or -1");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factor must be positive and finite");
+  if (!std::isfinite(hubble)) return fail(AMR_E_INVALID, "expansion rate must be finite");
+  if (!adjoint_iters_ok(h->plan)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevPlan P = dev_plan(h);
+  hipError_t e = launch_expansion_adjoint(P, Upre, lam, dt, hubble, st);
+  if (e == hipSuccess) e = launch_scale_dt(P, dt, a, st);
+  if (e != hipSuccess) return hip_fail(e, "comoving adjoint");
+  const double* const S[3] = {S0, S1, S2};
+  e = adjoint_transposes(h, P, S, P.dte, reinterpret_cast<const unsigned long long*>(floors),
+                         floors ? floors_host : -1, lam, static_cast<double*>(scratch), step_index, st);
+  return e == hipSuccess ? AMR_OK : hip_fail(e, "comoving adjoint");
+}
+
 // ---- tracer particles ------------------------------------------------------
 
 amr_status tracer_dev(amr_mesh* h, const amr_tracer_set_t* in, amr_tracer_set_t* out, int64_t cap, void* scratch,

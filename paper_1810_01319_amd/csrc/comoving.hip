@@ -82,6 +82,47 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
+// Transpose of expansion_kernel (five fields): lam holds dL/dU after the
+// sources on entry and dL/dU before them on exit, at the state U they were
+// applied to.  One thread per active cell.
+template <int N>
+__global__ void __launch_bounds__(256) expansion_adjoint_kernel(const double* __restrict__ U,
+                                                                double* __restrict__ lam,
+                                                                const double* __restrict__ dtv, double hubble,
+                                                                DevPlan P) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int N3 = N * N * N;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * N3) return;
+  const int s = int(t / N3);
+  const int q = int(t - int64_t(s) * N3);
+  const int x = q % N, y = (q / N) % N, z = q / (N * N);
+  const BlockInfo bi = P.blocks[s];
+  const InstParams ip = P.inst[bi.inst];
+  const double c = (0.5 * dtv[bi.inst]) * hubble;
+  const int64_t o = int64_t(s) * kFields * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
+  const double* const B = U + o;
+  double* const L = lam + o;
+  double lr = L[0], lmx = L[M3], lmy = L[2 * M3], lmz = L[3 * M3], lE = L[4 * M3];
+  expansion_cell_vjp(ip, c, B[0], B[M3], B[2 * M3], B[3 * M3], B[4 * M3], lr, lmx, lmy, lmz, lE);
+  L[0] = lr;
+  L[M3] = lmx;
+  L[2 * M3] = lmy;
+  L[3 * M3] = lmz;
+  L[4 * M3] = lE;
+}
+
+template <int N>
+hipError_t expansion_adjoint_n(const DevPlan& P, const double* U, double* lam, const double* dt, double hubble,
+                               hipStream_t st) {
+  const int64_t n = P.nleaf * int64_t(N) * N * N;
+  if (n > 0)
+    hipLaunchKernelGGL(expansion_adjoint_kernel<N>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                       U, lam, dt, hubble, P);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t expansion_n(const DevPlan& P, double* U, const double* dt, double hubble, const double* hubble_dev,
                        hipStream_t st) {
@@ -107,6 +148,16 @@ hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, doubl
     case 8: return expansion_n<8>(P, U, dt, hubble, hubble_dev, st);
     case 16: return expansion_n<16>(P, U, dt, hubble, hubble_dev, st);
     case 32: return expansion_n<32>(P, U, dt, hubble, hubble_dev, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_expansion_adjoint(const DevPlan& P, const double* U, double* lam, const double* dt, double hubble,
+                                   hipStream_t st) {
+  switch (P.N) {
+    case 8: return expansion_adjoint_n<8>(P, U, lam, dt, hubble, st);
+    case 16: return expansion_adjoint_n<16>(P, U, lam, dt, hubble, st);
+    case 32: return expansion_adjoint_n<32>(P, U, lam, dt, hubble, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -45,4 +45,31 @@ __device__ __forceinline__ unsigned expansion_cell(const InstParams& ip, double 
   return n;
 }
 
+// Vector-Jacobian product of expansion_cell (five fields) at the cell's
+// state before it, with the floor decision held at the forward's (the same
+// arithmetic decides it): on entry lr, lm*, lE are the adjoints of rho, the
+// momenta and E after the sources, on exit before them.  With ie = E - ke and
+// ke = |m|^2 / (2 rho):
+//   E' = fe E + (fv^2 - fe) ke   (not floored),   E' = const + fv^2 ke  (floored),
+//   m' = fv m,  rho' = rho,  d ke / d m = u,  d ke / d rho = -|u|^2 / 2.
+__device__ __forceinline__ void expansion_cell_vjp(const InstParams& ip, double c, double rho, double mx, double my,
+                                                   double mz, double E, double& lr, double& lmx, double& lmy,
+                                                   double& lmz, double& lE) {
+  const double g3 = 3.0 * ip.gm1;
+  const double fv = (1.0 - c) / (1.0 + c);
+  const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
+  const double ir = rcp_pos(rho);
+  const double u = mx * ir, v = my * ir, w = mz * ir;
+  const double ke = (0.5 * rho) * ((u * u + v * v) + w * w);
+  const double ie = E - ke;
+  const double ie2 = ie * fe;
+  const bool fl = ie2 < ie && ip.gm1 * ie2 < ip.p_floor;
+  const double dk = lE * (fl ? fv * fv : fv * fv - fe);  // adjoint reaching ke
+  lr = lr - dk * (0.5 * ((u * u + v * v) + w * w));
+  lmx = lmx * fv + dk * u;
+  lmy = lmy * fv + dk * v;
+  lmz = lmz * fv + dk * w;
+  lE = fl ? 0.0 : lE * fe;
+}
+
 }  // namespace amr

@@ -56,6 +56,9 @@ hipError_t launch_scale_dt(const DevPlan& P, const double* dt, double a, hipStre
                            const double* a_dev = nullptr);
 hipError_t launch_expansion(const DevPlan& P, double* U, const double* dt, double hubble, hipStream_t st,
                             const double* hubble_dev = nullptr);
+// transpose of launch_expansion (five fields) at the state U it was applied to
+hipError_t launch_expansion_adjoint(const DevPlan& P, const double* U, double* lam, const double* dt, double hubble,
+                                   hipStream_t st);
 // expansion history on the device (comoving.hip): flat matter + Lambda,
 // H(a) = H0 sqrt(om / a^3 + ol), om + ol = 1.  cs = {t, a(t), a(t_mid),
 // H(t_mid)}: stage 0 sets cs[1] = a(cs[0]); stage 1, with the step's dt,

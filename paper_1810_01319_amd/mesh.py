@@ -260,6 +260,33 @@ class Mesh:
                                                     _ptr(floors), int(floors_host), _ptr(lam), _ptr(scratch),
                                                     int(k), _stream()))
 
+    def step_comoving_record(self, U: torch.Tensor, dt: torch.Tensor, a: float, hubble: float, S1: torch.Tensor,
+                             S2: torch.Tensor, U_pre: torch.Tensor, U_out: torch.Tensor, floors: torch.Tensor,
+                             k: int) -> None:
+        """Comoving step k (dt given on the device; a, H at the mid time) from
+        U into U_out as step_record does, keeping also the state before the
+        expansion sources in U_pre."""
+        for X in (U, S1, S2, U_pre, U_out):
+            self._check_state(X)
+        if floors.dtype != torch.int64 or floors.numel() < 1 or floors.device != self.device:
+            raise ValueError("floors must be an int64 device tensor")
+        check(lib().amr_hydro_step_comoving_record(self._h, _ptr(U), _ptr(dt), ctypes.c_double(a),
+                                                   ctypes.c_double(hubble), _ptr(S1), _ptr(S2), _ptr(U_pre),
+                                                   _ptr(U_out), _ptr(floors), int(k), _stream()))
+
+    def step_comoving_adjoint_recorded(self, S0: torch.Tensor, S1: torch.Tensor, S2: torch.Tensor,
+                                       U_pre: torch.Tensor, dt: torch.Tensor, a: float, hubble: float,
+                                       floors: torch.Tensor, lam: torch.Tensor, scratch: torch.Tensor, k: int,
+                                       floors_host: int = -1) -> None:
+        """lam <- (d comoving step_k / d U)^T lam from what
+        step_comoving_record kept."""
+        for X in (S0, S1, S2, U_pre, lam):
+            self._check_state(X)
+        self._check_scratch(scratch, int(self.info.adjoint_face_bytes))
+        check(lib().amr_hydro_step_comoving_adjoint_recorded(
+            self._h, _ptr(S0), _ptr(S1), _ptr(S2), _ptr(U_pre), _ptr(dt), ctypes.c_double(a),
+            ctypes.c_double(hubble), _ptr(floors), int(floors_host), _ptr(lam), _ptr(scratch), int(k), _stream()))
+
     def refresh_adjoint(self, U_ref: torch.Tensor, lam: torch.Tensor) -> None:
         self._check_state(U_ref)
         self._check_state(lam)
