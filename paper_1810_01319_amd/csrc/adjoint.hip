@@ -30,7 +30,7 @@ __global__ void fill_zero(double* __restrict__ p, int64_t n) {
 // Reflux transpose: each coarse face cell's correction
 // U_c += s nu_c (F_c - ((F00 + F10) + (F01 + F11)) / 4) sends s nu_c lam_c to
 // the coarse face flux and -s nu_c lam_c / 4 to each of its four fine fluxes.
-template <int N, int DIR>
+template <int N, int DIR, int NF>
 __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__ lam, const double* __restrict__ dtv,
                                                       DevPlan P, double* __restrict__ gfaces) {
   constexpr int M = N + 2 * G;
@@ -53,14 +53,14 @@ __global__ void __launch_bounds__(256) reflux_adjoint(const double* __restrict__
   const int fs = T.slot_f[hA + 2 * hB];
   const int fA = 2 * tA - hA * N, fB = 2 * tB - hB * N;
   const int d = T.side ? N + G - 1 : G;
-  const double* cellp = lam + int64_t(T.leaf) * kFields * M3 + int64_t(d) * SD + int64_t(G + tA) * SA +
+  const double* cellp = lam + int64_t(T.leaf) * NF * M3 + int64_t(d) * SD + int64_t(G + tA) * SA +
                         int64_t(G + tB) * SB;
   const double s = T.side ? 1.0 : -1.0;
 #pragma unroll
-  for (int f = 0; f < kFields; f++) {
+  for (int f = 0; f < NF; f++) {
     const double g = s * nu * cellp[f * M3];
-    gfaces[(int64_t(T.slot_c) * kFields + f) * N * N + int64_t(tB) * N + tA] = g;
-    double* Q = gfaces + (int64_t(fs) * kFields + f) * N * N;
+    gfaces[(int64_t(T.slot_c) * NF + f) * N * N + int64_t(tB) * N + tA] = g;
+    double* Q = gfaces + (int64_t(fs) * NF + f) * N * N;
     const double gf = -0.25 * g;
     Q[fB * N + fA] = gf;
     Q[fB * N + fA + 1] = gf;
@@ -392,7 +392,7 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
 // threads of other neighbours return at once: spreading the prolonged cells
 // over the grid keeps fewer waves adding to one coarse cell at a time than
 // the forward's compact task list would).
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh2_adjoint(double* __restrict__ lam, const double* __restrict__ Uref,
                                                         DevPlan P) {
   constexpr int M = N + 2 * G;
@@ -416,11 +416,11 @@ __global__ void __launch_bounds__(256) refresh2_adjoint(double* __restrict__ lam
   const BlockInfo cb = P.blocks[e.id];
   const int la = (px >> 1) - cb.i * N + G, lb = (py >> 1) - cb.j * N + G, lc = (pz >> 1) - cb.k * N + G;
   const double o[3] = {(px & 1) ? 0.25 : -0.25, (py & 1) ? 0.25 : -0.25, (pz & 1) ? 0.25 : -0.25};
-  const int64_t cbase = int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
-  const int64_t gidx = int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  const int64_t cbase = int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
+  const int64_t gidx = int64_t(s) * NF * M3 + (int64_t(c) * M + b) * M + a;
   const int st[3] = {1, M, M * M};
 #pragma unroll
-  for (int f = 0; f < kFields; f++) {
+  for (int f = 0; f < NF; f++) {
     double* lg = lam + gidx + f * M3;
     const double gv = *lg;
     *lg = 0.0;
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(256) refresh2_adjoint(double* __restrict__ lam
 // Refresh transpose, phase 1 (copies and restriction): a ghost's adjoint goes
 // to its source cell (weight 1) or to its 8 children (weight 1/8); then the
 // ghost entry is cleared.
-template <int N>
+template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
@@ -467,13 +467,13 @@ __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam
   const int px = bc_index<N>(ip, l, 0, bi.i * N + a - G);
   const int py = bc_index<N>(ip, l, 1, bi.j * N + b - G);
   const int pz = bc_index<N>(ip, l, 2, bi.k * N + c - G);
-  double* dst = lam + int64_t(s) * kFields * M3 + (int64_t(c) * M + b) * M + a;
+  double* dst = lam + int64_t(s) * NF * M3 + (int64_t(c) * M + b) * M + a;
   if (e.kind == NBR_COPY) {
     const BlockInfo sb = P.blocks[e.id];
     const int la = px - sb.i * N + G, lb = py - sb.j * N + G, lc = pz - sb.k * N + G;
-    double* src = lam + int64_t(e.id) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    double* src = lam + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) {
+    for (int f = 0; f < NF; f++) {
       const double gv = dst[f * M3];
       dst[f * M3] = 0.0;
       if (gv != 0.0) atomicAdd(src + f * M3, gv);
@@ -483,9 +483,9 @@ __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam
     const int cidx = ((qx / N) & 1) + 2 * ((qy / N) & 1) + 4 * ((qz / N) & 1);
     const int fs = P.fine[8 * int64_t(e.id) + cidx];
     const int la = qx % N + G, lb = qy % N + G, lc = qz % N + G;
-    double* src = lam + int64_t(fs) * kFields * M3 + (int64_t(lc) * M + lb) * M + la;
+    double* src = lam + int64_t(fs) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < kFields; f++) {
+    for (int f = 0; f < NF; f++) {
       const double gv = dst[f * M3];
       dst[f * M3] = 0.0;
       if (gv == 0.0) continue;
@@ -503,6 +503,64 @@ __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam
   }
 }
 
+// Dual-energy sweep transpose: one thread per pencil, the pencil's six
+// fields and their adjoints in private arrays, and pencil_vjp_de (the
+// element products composed pencil by pencil, the reference form the host
+// tests check): a plain form for the six-field step, whose transpose is not
+// on the measured path.  The pencils are the forward sweep's.
+template <int N, int DIR>
+__global__ void __launch_bounds__(64) sweep_adjoint_de(const double* __restrict__ Uin, double* __restrict__ lam,
+                                                       const double* __restrict__ dtv, DevPlan P,
+                                                       const double* __restrict__ gfaces, int loA, int nA, int loB,
+                                                       int nB) {
+  constexpr int M = N + 2 * G;
+  constexpr int64_t M3 = int64_t(M) * M * M;
+  constexpr int NF = kFieldsDE;
+  constexpr int A = DIR == 0 ? 1 : 0;
+  constexpr int B = DIR == 2 ? 1 : 2;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
+  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
+  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
+  static_assert(M <= kMaxPencil, "pencil longer than the adjoint's arrays");
+  const int64_t npen = int64_t(nA) * nB;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P.nleaf * npen) return;
+  const int s = int(t / npen);
+  const int pp = int(t - int64_t(s) * npen);
+  const int iA = loA + pp % nA, iB = loB + pp / nA;
+  const BlockInfo bi = P.blocks[s];
+  const InstParams ip = P.inst[bi.inst];
+  const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
+  const int fmap[NF] = {0, 1 + DIR, 1 + T1, 1 + T2, 4, 5};
+  const int64_t boff = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
+  double U[NF * M], L[NF * M];
+  for (int v = 0; v < NF; v++)
+    for (int j = 0; j < M; j++) {
+      const int64_t o = boff + int64_t(fmap[v]) * M3 + int64_t(j) * SD;
+      U[v * M + j] = Uin[o];
+      L[v * M + j] = lam[o];
+    }
+  double glo[NF], ghi[NF];
+  const double* pl = nullptr;
+  const double* ph = nullptr;
+  if (iA >= G && iA < G + N && iB >= G && iB < G + N) {
+    const int64_t off = int64_t(iB - G) * N + (iA - G);
+    const int sl = P.faceslot[6 * int64_t(s) + 2 * DIR], sh = P.faceslot[6 * int64_t(s) + 2 * DIR + 1];
+    if (sl >= 0) {
+      for (int v = 0; v < NF; v++) glo[v] = gfaces[(int64_t(sl) * NF + fmap[v]) * N * N + off];
+      pl = glo;
+    }
+    if (sh >= 0) {
+      for (int v = 0; v < NF; v++) ghi[v] = gfaces[(int64_t(sh) * NF + fmap[v]) * N * N + off];
+      ph = ghi;
+    }
+  }
+  pencil_vjp_de(ip, nu, M, G, G + N, U, L, pl, ph);
+  for (int v = 0; v < NF; v++)
+    for (int j = 0; j < M; j++) lam[boff + int64_t(fmap[v]) * M3 + int64_t(j) * SD] = L[v * M + j];
+}
+
 inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 template <int N, int DIR>
@@ -512,6 +570,13 @@ hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const 
   constexpr int A = DIR == 0 ? 1 : 0, B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : S::M;
+  if (P.nf == kFieldsDE) {
+    const int64_t n = P.nleaf * int64_t(nA) * nB;
+    if (n > 0)
+      hipLaunchKernelGGL((sweep_adjoint_de<N, DIR>), dim3(gridn(n, 64)), dim3(64), 0, st, Uin, lam, dt, P, gfaces,
+                         loA, nA, loB, nB);
+    return hipGetLastError();
+  }
   const int64_t tiles = P.nleaf * ((int64_t(nA) * nB + S::R - 1) / S::R);
   if (tiles == 0) return hipSuccess;
   const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
@@ -534,28 +599,39 @@ hipError_t sweep_adj_n(const DevPlan& P, const double* Uin, double* lam, const d
   return sweep_adj_nd<N, 2>(P, Uin, lam, dt, gfaces, floors, floors_host, swept, st);
 }
 
-template <int N>
-hipError_t reflux_adj_n(const DevPlan& P, const double* lam, const double* dt, double* gfaces, hipStream_t st) {
+template <int N, int NF>
+hipError_t reflux_adj_nf(const DevPlan& P, const double* lam, const double* dt, double* gfaces, hipStream_t st) {
   for (int d = 0; d < 3; d++) {
     const int64_t n = P.nreflux[d] * N * N;
     if (n == 0) continue;
     const dim3 g(gridn(n, 256)), b(256);
-    if (d == 0) hipLaunchKernelGGL((reflux_adjoint<N, 0>), g, b, 0, st, lam, dt, P, gfaces);
-    else if (d == 1) hipLaunchKernelGGL((reflux_adjoint<N, 1>), g, b, 0, st, lam, dt, P, gfaces);
-    else hipLaunchKernelGGL((reflux_adjoint<N, 2>), g, b, 0, st, lam, dt, P, gfaces);
+    if (d == 0) hipLaunchKernelGGL((reflux_adjoint<N, 0, NF>), g, b, 0, st, lam, dt, P, gfaces);
+    else if (d == 1) hipLaunchKernelGGL((reflux_adjoint<N, 1, NF>), g, b, 0, st, lam, dt, P, gfaces);
+    else hipLaunchKernelGGL((reflux_adjoint<N, 2, NF>), g, b, 0, st, lam, dt, P, gfaces);
   }
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t refresh_adj_n(const DevPlan& P, double* lam, const double* Uref, hipStream_t st) {
+hipError_t reflux_adj_n(const DevPlan& P, const double* lam, const double* dt, double* gfaces, hipStream_t st) {
+  return P.nf == kFieldsDE ? reflux_adj_nf<N, kFieldsDE>(P, lam, dt, gfaces, st)
+                           : reflux_adj_nf<N, kFields>(P, lam, dt, gfaces, st);
+}
+
+template <int N, int NF>
+hipError_t refresh_adj_nf(const DevPlan& P, double* lam, const double* Uref, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
   if (P.np2 > 0)
-    hipLaunchKernelGGL(refresh2_adjoint<N>, dim3(gridn(P.np2 * GC, 256)), dim3(256), 0, st, lam, Uref, P);
+    hipLaunchKernelGGL((refresh2_adjoint<N, NF>), dim3(gridn(P.np2 * GC, 256)), dim3(256), 0, st, lam, Uref, P);
   if (P.nleaf > 0)
-    hipLaunchKernelGGL(refresh1_adjoint<N>, dim3(gridn(P.nleaf * GC, 256)), dim3(256), 0, st, lam, P);
+    hipLaunchKernelGGL((refresh1_adjoint<N, NF>), dim3(gridn(P.nleaf * GC, 256)), dim3(256), 0, st, lam, P);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t refresh_adj_n(const DevPlan& P, double* lam, const double* Uref, hipStream_t st) {
+  return P.nf == kFieldsDE ? refresh_adj_nf<N, kFieldsDE>(P, lam, Uref, st) : refresh_adj_nf<N, kFields>(P, lam, Uref, st);
 }
 
 }  // namespace

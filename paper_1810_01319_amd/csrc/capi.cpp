@@ -151,7 +151,7 @@ amr_status finish(amr_mesh* h, amr_mesh** out) {
 // Adjoint scratch: face-flux adjoints (256-B rounded), then for the
 // recomputing entry three states and one counter slot.
 int64_t adjoint_face_bytes(const Plan& p) {
-  const int64_t faces = p.nslots * kFields * int64_t(p.N) * p.N * 8;
+  const int64_t faces = p.nslots * p.nf * int64_t(p.N) * p.N * 8;
   return (faces + 255) / 256 * 256;
 }
 
@@ -283,7 +283,7 @@ hipError_t adjoint_transposes(amr_mesh* h, const DevPlan& P, const double* const
     order[2] = 0;
   }
   hipError_t e = timed(h, AMR_PHASE_ADJ_REFLUX, st, [&] {
-    hipError_t r = launch_fill_zero(gfaces, p.nslots * kFields * int64_t(p.N) * p.N, st);
+    hipError_t r = launch_fill_zero(gfaces, p.nslots * p.nf * int64_t(p.N) * p.N, st);
     if (r == hipSuccess) r = launch_reflux_adjoint(P, lam, dt, gfaces, st);
     return r;
   });
@@ -614,7 +614,6 @@ amr_status amr_hydro_step_record(amr_mesh* h, double* U, double* dt, double* S1,
                                  uint64_t* floors, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!dt || !S1 || !S2 || !Uout || !floors) return fail(AMR_E_INVALID, "null argument");
   if (S1 == U || S2 == U || Uout == U || S1 == S2 || S1 == Uout || S2 == Uout)
     return fail(AMR_E_INVALID, "U, S1, S2 and U_out must be distinct buffers");
@@ -678,7 +677,6 @@ amr_status amr_hydro_step_adjoint_recorded(amr_mesh* h, const double* S0, const 
                                            double* lam, void* scratch, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, S0);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!S1 || !S2 || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   if (floors_host < -1) return fail(AMR_E_INVALID, "floors_host must be a count or -1");
   if (!adjoint_iters_ok(h->plan)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
@@ -852,7 +850,6 @@ amr_status amr_tracer_counters(amr_mesh* h, void* scratch, int64_t capacity, int
 amr_status amr_refresh_ghosts_adjoint(amr_mesh* h, const double* Uref, double* lam, void* stream) {
   amr_status rc = check_ready(h, Uref);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!lam) return fail(AMR_E_INVALID, "null adjoint");
   hipError_t e = launch_refresh_adjoint(dev_plan(h), lam, Uref, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? AMR_OK : hip_fail(e, "refresh adjoint");

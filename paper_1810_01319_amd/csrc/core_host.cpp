@@ -23,6 +23,14 @@ static InstParams params(const double* gas, int iters) {
   return p;
 }
 
+// gas = (gamma, rho_floor, p_floor, eta1, eta2) for the dual-energy calls
+static InstParams params_de(const double* gas, int iters) {
+  InstParams p = params(gas, iters);
+  p.eta1 = gas[3];
+  p.eta2 = gas[4];
+  return p;
+}
+
 extern "C" {
 
 // Forward update of one pencil (cells [lo,hi) updated, then floored);
@@ -68,6 +76,69 @@ void core_pencil_update(const double* gas, int iters, double nu, int n, int lo, 
     faces_out[v] = F[lo - 1][v];
     faces_out[5 + v] = F[hi - 1][v];
   }
+}
+
+// Dual energy: the same update with the sixth field rho e (U, Uout: six
+// fields; faces_out[12]).
+void core_pencil_update_de(const double* gas, int iters, double nu, int n, int lo, int hi, const double* U,
+                           double* Uout, double* faces_out) {
+  const InstParams ip = params_de(gas, iters);
+  Prim P[kMaxPencil];
+  double dl[kMaxPencil][5], fa[kMaxPencil][5], WL[kMaxPencil][5], WR[kMaxPencil][5], F[kMaxPencil][6],
+      ug[kMaxPencil];
+  for (int j = 0; j < n; j++) {
+    double u6[6] = {U[j], U[n + j], U[2 * n + j], U[3 * n + j], U[4 * n + j], U[5 * n + j]};
+    P[j] = prim_fwd_de(ip, u6);
+  }
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++)
+      fa[j][v] = 0.5 * (P[j].q[v] + P[j + 1].q[v]) - (dl[j + 1][v] - dl[j][v]) * ip.sixth;
+  for (int j = 2; j <= n - 3; j++) {
+    const double pp1 = P[j + 1].q[4], pm1 = P[j - 1].q[4];
+    const double dp1 = pp1 - pm1;
+    const double pmin = pp1 < pm1 ? pp1 : pm1;
+    const bool shock = (fabs(dp1) > 0.33 * pmin) && (P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
+    const double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+    const double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    double ft = 10.0 * (r - 0.75);
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    const double f = shock ? ft : 0.0;
+    Par pa[5];
+    for (int v = 0; v < 5; v++) pa[v] = parabola(P[j].q[v], fa[j - 1][v], fa[j][v], f, ip.sixth);
+    trace(ip, P[j].q[0], P[j].q[1], P[j].c, P[j].ir, pa, nu, WL[j], WR[j]);
+  }
+  for (int j = lo - 1; j <= hi - 1; j++) riemann_flux<true>(ip, WL[j], WR[j + 1], F[j], &ug[j]);
+  std::memcpy(Uout, U, sizeof(double) * 6 * n);
+  for (int j = lo; j < hi; j++) {
+    double V[6], W[6];
+    for (int v = 0; v < 6; v++) V[v] = U[v * n + j] - nu * (F[j][v] - F[j - 1][v]);
+    V[5] = V[5] - nu * (P[j].q[4] * (ug[j] - ug[j - 1]));
+    floor_apply_de(ip, V, W);
+    for (int v = 0; v < 6; v++) Uout[v * n + j] = W[v];
+  }
+  for (int v = 0; v < 6; v++) {
+    faces_out[v] = F[lo - 1][v];
+    faces_out[6 + v] = F[hi - 1][v];
+  }
+}
+
+void core_pencil_vjp_de(const double* gas, int iters, double nu, int n, int lo, int hi, const double* U,
+                        double* lam, const double* gface /* 12 or null */) {
+  const InstParams ip = params_de(gas, iters);
+  pencil_vjp_de(ip, nu, n, lo, hi, U, lam, gface, gface ? gface + 6 : nullptr);
+}
+
+void core_floor_de(const double* gas, const double* V, double* out) {
+  const InstParams ip = params_de(gas, 5);
+  floor_apply_de(ip, V, out);
+}
+
+void core_floor_vjp_de(const double* gas, const double* V, const double* g, double* gV) {
+  const InstParams ip = params_de(gas, 5);
+  floor_vjp_de(ip, V, g, gV);
 }
 
 void core_pencil_vjp(const double* gas, int iters, double nu, int n, int lo, int hi, const double* U, double* lam,

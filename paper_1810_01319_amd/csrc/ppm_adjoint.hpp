@@ -17,6 +17,7 @@ struct Prim {
   double q[5];  // rho, u, v, w, p (floored)
   double c, ir, K;
   bool pfl;     // pressure floor active
+  bool sel;     // dual energy: p from the rho e field (E - ke <= eta1 E)
 };
 
 AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
@@ -29,12 +30,35 @@ AMR_HD inline Prim prim_fwd(const InstParams& ip, const double* U) {
   P.K = (P.q[1] * P.q[1] + P.q[2] * P.q[2]) + P.q[3] * P.q[3];
   const double p = ip.gm1 * (U[4] - (0.5 * U[0]) * P.K);
   P.pfl = p < ip.p_floor;
+  P.sel = false;
   P.q[4] = P.pfl ? ip.p_floor : p;
   P.c = sqrt_pos((ip.gamma * P.q[4]) * P.ir);
   return P;
 }
 
-// g_q[5], g_c, g_ir -> g_U[5] (accumulated)
+// Dual energy: U = (rho, m_n, m_t1, m_t2, E, rho e); the pressure is
+// (gamma - 1) rho e where E - ke <= eta1 E (the forward's selection, in its
+// arithmetic), else (gamma - 1)(E - ke).
+AMR_HD inline Prim prim_fwd_de(const InstParams& ip, const double* U) {
+  Prim P;
+  P.ir = rcp_pos(U[0]);
+  P.q[0] = U[0];
+  P.q[1] = U[1] * P.ir;
+  P.q[2] = U[2] * P.ir;
+  P.q[3] = U[3] * P.ir;
+  P.K = (P.q[1] * P.q[1] + P.q[2] * P.q[2]) + P.q[3] * P.q[3];
+  const double ie = U[4] - (0.5 * U[0]) * P.K;
+  P.sel = !(ie > ip.eta1 * U[4]);
+  const double p = P.sel ? ip.gm1 * U[5] : ip.gm1 * ie;
+  P.pfl = p < ip.p_floor;
+  P.q[4] = P.pfl ? ip.p_floor : p;
+  P.c = sqrt_pos((ip.gamma * P.q[4]) * P.ir);
+  return P;
+}
+
+// g_q[5], g_c, g_ir -> g_U[5] (accumulated); DE: g_U[6], and with the
+// selection (P.sel) the pressure's adjoint goes to g_U[5] (rho e) instead
+template <bool DE = false>
 AMR_HD inline void prim_vjp(const InstParams& ip, const double* U, const Prim& P, const double* gq, double gc,
                             double gir, double* gU) {
   // c = sqrt(gamma p / rho): dc = (gamma / 2c)(dp / rho + p d(1/rho))
@@ -42,7 +66,13 @@ AMR_HD inline void prim_vjp(const InstParams& ip, const double* U, const Prim& P
   double gp = gq[4] + h * P.ir;
   gir += h * P.q[4];
   if (P.pfl) gp = 0.0;
-  const double gpm = gp * ip.gm1;
+  double gpm = gp * ip.gm1;
+  if constexpr (DE) {
+    if (P.sel) {
+      gU[5] += gpm;
+      gpm = 0.0;
+    }
+  }
   gU[4] += gpm;
   const double gK = -gpm * (0.5 * U[0]);
   double g0 = gq[0] - gpm * (0.5 * P.K);
@@ -289,9 +319,11 @@ AMR_HD inline void trace_vjp(const InstParams& ip, double rho, double u, double 
 // terms.
 // FIXSTOP = false reverses every evaluation one by one (a host-side check of
 // the closed form used at a fixed point).
-template <int MAXIT, bool FIXSTOP = true>
+// DE: also the adjoints of the rho e flux F[5] = u_g p_g / (gamma - 1)
+// (gF5) and of the Godunov velocity u_g itself (gUg).
+template <int MAXIT, bool FIXSTOP = true, bool DE = false>
 AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const double* R, const double* gF, double* gL,
-                                 double* gR) {
+                                 double* gR, double gF5 = 0.0, double gUg = 0.0) {
   const double rL = L[0], uL = L[1], pL = L[4];
   const double rR = R[0], uR = R[1], pR = R[4];
   const double gam = ip.gamma, g1 = ip.g1, pfl = ip.p_floor;
@@ -382,6 +414,10 @@ AMR_HD inline void riemann_vjp_n(const InstParams& ip, const double* L, const do
   const double gwg = gF[3] * mf + gK2 * (2.0 * wg);
   grg += gmf * ug;
   gug += gmf * rg;
+  if constexpr (DE) {
+    gug += gF5 * (pg * ip.inv_gm1) + gUg;
+    gpg += (gF5 * ug) * ip.inv_gm1;
+  }
   if (left) { gL[2] += gvg; gL[3] += gwg; }
   else { gR[2] += gvg; gR[3] += gwg; }
   // ---- reverse: sampling ----
@@ -597,6 +633,57 @@ AMR_HD inline void floor_vjp(const InstParams& ip, const double* V, const double
   gV[0] = rfl ? 0.0 : gr;
 }
 
+// Dual energy: the update's floors and resynchronisation of one cell.  V
+// holds the pre-floor values (rho, m_n, m_t1, m_t2, E, rho e), rho e already
+// with its flux difference and work term.  Forward: the density and pressure
+// floors as floor_apply, then rho e takes E - ke where E - ke > eta2 E, then
+// its own floor (gamma - 1) rho e >= p_floor.
+AMR_HD inline void floor_apply_de(const InstParams& ip, const double* V, double* out) {
+  floor_apply(ip, V, out);
+  const double jr = rcp_pos(out[0]);
+  const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
+  const double ke = (0.5 * out[0]) * ((a1 * a1 + a2 * a2) + a3 * a3);
+  double ge = V[5];
+  const double ie = out[4] - ke;
+  if (ie > ip.eta2 * out[4]) ge = ie;
+  if (ip.gm1 * ge < ip.p_floor) ge = ip.p_floor * ip.inv_gm1;
+  out[5] = ge;
+}
+
+// g (adjoint of the six outputs) -> gV (adjoint of V); may alias g.
+AMR_HD inline void floor_vjp_de(const InstParams& ip, const double* V, const double* g, double* gV) {
+  const bool rfl = V[0] < ip.rho_floor;
+  const double r0 = rfl ? ip.rho_floor : V[0];
+  const double jr = rcp_pos(r0);
+  const double a1 = V[1] * jr, a2 = V[2] * jr, a3 = V[3] * jr;
+  const double K = (a1 * a1 + a2 * a2) + a3 * a3;
+  const double ke = (0.5 * r0) * K;
+  const bool pfl = ip.gm1 * (V[4] - ke) < ip.p_floor;
+  const double e = pfl ? ip.p_floor * ip.inv_gm1 + ke : V[4];
+  const double ie = e - ke;
+  const bool rsy = ie > ip.eta2 * e;
+  const double ge = rsy ? ie : V[5];
+  const bool gfl = ip.gm1 * ge < ip.p_floor;
+  const double g5 = gfl ? 0.0 : g[5];
+  // rho e = E - ke (resynchronised) passes g5 to E and -g5 to ke
+  const double gE = g[4] + (rsy ? g5 : 0.0);
+  double gke = rsy ? -g5 : 0.0;
+  gV[5] = rsy ? 0.0 : g5;
+  // the pressure floor: E = const + ke
+  if (pfl) {
+    gke += gE;
+    gV[4] = 0.0;
+  } else {
+    gV[4] = gE;
+  }
+  // ke = |m|^2 / (2 rho): d/dm = a, d/drho = -K / 2
+  const double gr = g[0] - (0.5 * K) * gke;
+  gV[1] = g[1] + gke * a1;
+  gV[2] = g[2] + gke * a2;
+  gV[3] = g[3] + gke * a3;
+  gV[0] = rfl ? 0.0 : gr;
+}
+
 // ---- one pencil ------------------------------------------------------------
 
 constexpr int kMaxPencil = 38;
@@ -709,6 +796,122 @@ AMR_HD inline void pencil_vjp(const InstParams& ip, double nu, int n, int lo, in
     double gU[5] = {0, 0, 0, 0, 0};
     prim_vjp(ip, u5, P[j], gq[j], gc[j], gir[j], gU);
     for (int v = 0; v < 5; v++) lam[v * n + j] += gU[v];
+  }
+}
+
+
+// Dual energy: the same with the sixth field rho e (U, lam and the face
+// adjoints carry six fields).  rho e enters the sweep through the pressure
+// selection of the primitives, its flux u_g p_g / (gamma - 1) and the work
+// term of the update; the update's floors and resynchronisation follow
+// floor_vjp_de.
+AMR_HD inline void pencil_vjp_de(const InstParams& ip, double nu, int n, int lo, int hi, const double* U, double* lam,
+                              const double* gface_lo, const double* gface_hi) {
+  Prim P[kMaxPencil];
+  double dl[kMaxPencil][5], fa[kMaxPencil][5], fl[kMaxPencil];
+  Par pa[kMaxPencil][5];
+  double WL[kMaxPencil][5], WR[kMaxPencil][5];
+  const double sixth = ip.sixth;
+  for (int j = 0; j < n; j++) {
+    double u6[6] = {U[j], U[n + j], U[2 * n + j], U[3 * n + j], U[4 * n + j], U[5 * n + j]};
+    P[j] = prim_fwd_de(ip, u6);
+  }
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++) dl[j][v] = mc_slope(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v]);
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++)
+      fa[j][v] = 0.5 * (P[j].q[v] + P[j + 1].q[v]) - (dl[j + 1][v] - dl[j][v]) * sixth;
+  bool shk[kMaxPencil], fact[kMaxPencil];
+  double rr_[kMaxPencil];
+  for (int j = 2; j <= n - 3; j++) {
+    const double pp1 = P[j + 1].q[4], pm1 = P[j - 1].q[4];
+    const double dp1 = pp1 - pm1;
+    const double pmin = pp1 < pm1 ? pp1 : pm1;
+    shk[j] = (fabs(dp1) > 0.33 * pmin) && (P[j - 1].q[1] - P[j + 1].q[1] > 0.0);
+    const double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+    const double r = (dp2 != 0.0) ? dp1 / dp2 : 0.0;
+    rr_[j] = r;
+    double ft = 10.0 * (r - 0.75);
+    fact[j] = shk[j] && dp2 != 0.0 && ft < 1.0 && ft > 0.0;
+    ft = ft < 1.0 ? ft : 1.0;
+    ft = ft > 0.0 ? ft : 0.0;
+    fl[j] = shk[j] ? ft : 0.0;
+    for (int v = 0; v < 5; v++) pa[j][v] = parabola(P[j].q[v], fa[j - 1][v], fa[j][v], fl[j], sixth);
+    trace(ip, P[j].q[0], P[j].q[1], P[j].c, P[j].ir, pa[j], nu, WL[j], WR[j]);
+  }
+  // adjoint accumulators
+  double gq[kMaxPencil][5] = {}, gc[kMaxPencil] = {}, gir[kMaxPencil] = {};
+  double gdl[kMaxPencil][5] = {}, gfa[kMaxPencil][5] = {}, gfl[kMaxPencil] = {};
+  double gWL[kMaxPencil][5] = {}, gWR[kMaxPencil][5] = {};
+  // fluxes and Godunov velocities at the faces j+1/2, j = lo-1 .. hi-1
+  double F[kMaxPencil][6], ugf[kMaxPencil], gug[kMaxPencil] = {};
+  for (int j = lo - 1; j <= hi - 1; j++) riemann_flux<true>(ip, WL[j], WR[j + 1], F[j], &ugf[j]);
+  // update U_j -= nu (F_{j+1/2} - F_{j-1/2}) on [lo, hi), rho e also less the
+  // work nu p_j (u_g(j+1/2) - u_g(j-1/2)), then floors and resynchronisation:
+  // the adjoint of the pre-floor values replaces lam there
+  for (int j = lo; j < hi; j++) {
+    double V[6], g[6];
+    for (int v = 0; v < 6; v++) {
+      V[v] = U[v * n + j] - nu * (F[j][v] - F[j - 1][v]);
+      g[v] = lam[v * n + j];
+    }
+    V[5] = V[5] - nu * (P[j].q[4] * (ugf[j] - ugf[j - 1]));
+    floor_vjp_de(ip, V, g, g);
+    for (int v = 0; v < 6; v++) lam[v * n + j] = g[v];
+    const double gw = -nu * g[5];
+    gq[j][4] += gw * (ugf[j] - ugf[j - 1]);
+    gug[j] += gw * P[j].q[4];
+    gug[j - 1] -= gw * P[j].q[4];
+  }
+  // faces for reflux
+  for (int j = lo - 1; j <= hi - 1; j++) {
+    double gF[6];
+    for (int v = 0; v < 6; v++) {
+      const double up = (j + 1 >= lo && j + 1 < hi) ? lam[v * n + j + 1] : 0.0;
+      const double dn = (j >= lo && j < hi) ? lam[v * n + j] : 0.0;
+      gF[v] = nu * (up - dn);
+    }
+    if (j == lo - 1 && gface_lo)
+      for (int v = 0; v < 6; v++) gF[v] += gface_lo[v];
+    if (j == hi - 1 && gface_hi)
+      for (int v = 0; v < 6; v++) gF[v] += gface_hi[v];
+    riemann_vjp_n<64, true, true>(ip, WL[j], WR[j + 1], gF, gWL[j], gWR[j + 1], gF[5], gug[j]);
+  }
+  for (int j = 2; j <= n - 3; j++) {
+    ParGrad G[5] = {};
+    double grho = 0, gu = 0;
+    trace_vjp(ip, P[j].q[0], P[j].q[1], P[j].c, P[j].ir, pa[j], nu, gWL[j], gWR[j], G, &grho, &gu, &gc[j], &gir[j]);
+    gq[j][0] += grho;
+    gq[j][1] += gu;
+    for (int v = 0; v < 5; v++)
+      parabola_vjp(P[j].q[v], fa[j - 1][v], fa[j][v], fl[j], sixth, G[v], &gq[j][v], &gfa[j - 1][v], &gfa[j][v],
+                   &gfl[j]);
+    if (fact[j]) {
+      const double gr = 10.0 * gfl[j];
+      const double dp2 = P[j + 2].q[4] - P[j - 2].q[4];
+      const double gdp1 = gr / dp2, gdp2 = -gr * rr_[j] / dp2;
+      gq[j + 1][4] += gdp1;
+      gq[j - 1][4] -= gdp1;
+      gq[j + 2][4] += gdp2;
+      gq[j - 2][4] -= gdp2;
+    }
+  }
+  for (int j = 1; j <= n - 3; j++)
+    for (int v = 0; v < 5; v++) {
+      const double g = gfa[j][v];
+      gq[j][v] += 0.5 * g;
+      gq[j + 1][v] += 0.5 * g;
+      gdl[j + 1][v] -= sixth * g;
+      gdl[j][v] += sixth * g;
+    }
+  for (int j = 1; j <= n - 2; j++)
+    for (int v = 0; v < 5; v++)
+      slope_vjp(P[j - 1].q[v], P[j].q[v], P[j + 1].q[v], gdl[j][v], &gq[j - 1][v], &gq[j][v], &gq[j + 1][v]);
+  for (int j = 0; j < n; j++) {
+    double u6[6] = {U[j], U[n + j], U[2 * n + j], U[3 * n + j], U[4 * n + j], U[5 * n + j]};
+    double gU[6] = {0, 0, 0, 0, 0, 0};
+    prim_vjp<true>(ip, u6, P[j], gq[j], gc[j], gir[j], gU);
+    for (int v = 0; v < 6; v++) lam[v * n + j] += gU[v];
   }
 }
 
