@@ -168,6 +168,8 @@ DevPlan dev_plan_at(const Plan& p, unsigned char* w) {
   P.fine = reinterpret_cast<const int32_t*>(w + p.off.fine);
   P.p2list = reinterpret_cast<const int32_t*>(w + p.off.p2list);
   P.p2task = reinterpret_cast<const int32_t*>(w + p.off.p2task);
+  P.p2wave = reinterpret_cast<const int32_t*>(w + p.off.p2wave);
+  P.np2w = int64_t(p.p2wave.size());
   P.faceslot = reinterpret_cast<const int32_t*>(w + p.off.faceslot);
   for (int d = 0; d < 3; d++) {
     P.reflux[d] = reinterpret_cast<const RefluxTask*>(w + p.off.reflux[d]);

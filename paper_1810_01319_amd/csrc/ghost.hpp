@@ -71,8 +71,9 @@ struct P2Region {
   // cells sharing one coarse parent: along a ghost axis the 3 cells form the
   // groups {1 cell, 2 cells} (low side) or {2, 1} (high side), along an
   // interior axis N / 2 pairs; GROUPS per region
-  static constexpr int GROUPS = K == 0 ? 2 * (N / 2) * (N / 2) : (K == 1 ? 4 * (N / 2) : 8);
-  static constexpr int WAVES = (GROUPS + 63) / 64;  // a task takes whole waves
+  static constexpr int GROUPS = p2_groups(N, K);
+  static constexpr int WAVES = p2_waves(N, K);  // a task takes whole waves
+  static_assert(WAVES <= (1 << kP2SubBits), "wave-in-task index does not fit its bits");
 };
 
 // Group j along an axis of region class cl (0: low ghost slab, 1: interior,

@@ -77,26 +77,22 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 }
 
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
-// and phase-1 ghost cells are complete, over the ghost regions of kind K
-// (faces, edges, corners) whose neighbour position a coarser leaf covers.
-// One thread per group of ghost cells that share a coarse parent (up to
+// and phase-1 ghost cells are complete, over the ghost regions (faces,
+// edges, corners) whose neighbour position a coarser leaf covers.  One
+// thread per group of ghost cells that share a coarse parent (up to
 // 2 x 2 x 2): the parent's stencil is loaded and its slopes computed once,
-// then each cell of the group takes its own offset.  Each task takes whole
-// waves, so the task, its leaves and their instance are wave-uniform: scalar
-// loads, off the latency chain of the stencil loads.  LIN: unlimited central
-// slopes 0.5 (u(+1) - u(-1)) (the composite Poisson operator's
-// interpolation).
+// then each cell of the group takes its own offset.  One launch covers every
+// region, in leaf order, so that a leaf's face, edge and corner regions run
+// together and share the coarse cells and output lines they touch in L2.
+// Each task takes whole waves, so the task, its leaves and their instance
+// are wave-uniform: scalar loads, off the latency chain of the stencil loads.
+// LIN: unlimited central slopes 0.5 (u(+1) - u(-1)) (the composite Poisson
+// operator's interpolation).
 template <int N, int NF, bool LIN, int K>
-__global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
+__device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPlan& P, int s, int code, int r) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
-  constexpr unsigned RG = P2Region<N, K>::GROUPS, WV = P2Region<N, K>::WAVES;
-  const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
-  const unsigned task = w / WV;
-  const int r = int((w - task * WV) * 64 + (threadIdx.x & 63u));
-  if (task >= unsigned(P.np2t[K]) || r >= int(RG)) return;
-  const int64_t row = 2 * ((K == 0 ? 0 : (K == 1 ? P.np2t[0] : P.np2t[0] + P.np2t[1])) + task);
-  const int s = P.p2task[row], code = P.p2task[row + 1];
+  if (r >= P2Region<N, K>::GROUPS) return;
   // group -> its cells' padded ranges along x, y, z (x fastest)
   const int cl[3] = {code % 3, (code / 3) % 3, code / 9};
   int first[3], cnt[3], j = r;
@@ -148,6 +144,21 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
       }
     }
   }
+}
+
+template <int N, int NF, bool LIN>
+__global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
+  const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  if (w >= unsigned(P.np2w)) return;
+  const int e = P.p2wave[w];
+  const int row = e >> kP2SubBits;
+  const int r = (e & ((1 << kP2SubBits) - 1)) * 64 + int(threadIdx.x & 63u);
+  const int s = P.p2task[2 * int64_t(row)], code = P.p2task[2 * int64_t(row) + 1];
+  // the region's kind from its direction: a face has two interior axes
+  const int nin = (code % 3 == 1) + ((code / 3) % 3 == 1) + (code / 9 == 1);
+  if (nin == 2) phase2_group<N, NF, LIN, 0>(U, P, s, code, r);
+  else if (nin == 1) phase2_group<N, NF, LIN, 1>(U, P, s, code, r);
+  else phase2_group<N, NF, LIN, 2>(U, P, s, code, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -892,16 +903,13 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
-// the phase-2 launches, one per task kind (faces, edges, corners)
+// the phase-2 launch: whole waves per task, in leaf order (wave indices are
+// 32-bit)
 template <int N, int NF, bool LIN>
 hipError_t launch_phase2(const DevPlan& P, double* U, int block, hipStream_t st) {
-  // whole waves per task; wave indices are 32-bit
-  const int64_t n0 = P.np2t[0] * P2Region<N, 0>::WAVES * 64, n1 = P.np2t[1] * P2Region<N, 1>::WAVES * 64,
-                n2 = P.np2t[2] * P2Region<N, 2>::WAVES * 64;  // threads (groups padded to whole waves)
-  if (n0 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
-  if (n0 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 0>), dim3(grid_for(n0, block)), dim3(block), 0, st, U, P);
-  if (n1 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 1>), dim3(grid_for(n1, block)), dim3(block), 0, st, U, P);
-  if (n2 > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN, 2>), dim3(grid_for(n2, block)), dim3(block), 0, st, U, P);
+  const int64_t n = P.np2w * 64;  // threads
+  if (n >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  if (n > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN>), dim3(grid_for(n, block)), dim3(block), 0, st, U, P);
   return hipSuccess;
 }
 

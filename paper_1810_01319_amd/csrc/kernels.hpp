@@ -16,6 +16,7 @@ struct DevPlan {
   const int32_t* fine;
   const int32_t* p2list;
   const int32_t* p2task;  // (leaf, neighbour code) pairs of phase 2: faces, edges, corners
+  const int32_t* p2wave;  // phase-2 waves in leaf order: (task row << kP2SubBits) | wave in task
   const int32_t* faceslot;
   const RefluxTask* reflux[3];
   unsigned long long* acc;
@@ -29,6 +30,7 @@ struct DevPlan {
   double* faces;
   int64_t nleaf, np2, nreflux[3];
   int64_t np2t[3];  // phase-2 tasks per kind (faces, edges, corners)
+  int64_t np2w;     // phase-2 waves
   int32_t ninst, N;
   int32_t nf;  // fields per cell: kFields, or kFieldsDE with the dual-energy field
 };

@@ -15,6 +15,12 @@ constexpr int kFieldsDE = 6;  // with the dual-energy field rho e
 // slots per leaf of the next-step signal-speed maxima of a run of steps (spread
 // so that a leaf's waves do not all update one word)
 constexpr int kCflSlots = 16;
+// Phase-2 refresh: groups of ghost cells sharing one coarse parent in a ghost
+// region of kind K (0: face, 1: edge, 2: corner) of an N^3 block, and the
+// whole waves a region's task takes
+constexpr int p2_groups(int N, int K) { return K == 0 ? 2 * (N / 2) * (N / 2) : (K == 1 ? 4 * (N / 2) : 8); }
+constexpr int p2_waves(int N, int K) { return (p2_groups(N, K) + 63) / 64; }
+constexpr int kP2SubBits = 3;  // wave-in-task bits of a phase-2 wave entry (at most 8 waves per task)
 
 // Per mesh instance: gas constants in the exact forms the formulas use
 // (computed once on the host in FP64) and the geometry.
@@ -76,7 +82,7 @@ struct Reloc {
 };
 
 struct PlanOffsets {
-  int64_t inst, blocks, nbr, fine, p2list, p2task, faceslot, reflux[3], acc, lacc, dte, counters, ind, migr, reloc,
+  int64_t inst, blocks, nbr, fine, p2list, p2task, p2wave, faceslot, reflux[3], acc, lacc, dte, counters, ind, migr, reloc,
       reloc_child, faces, total;
 };
 

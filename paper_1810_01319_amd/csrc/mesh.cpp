@@ -204,7 +204,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   N = meshes[0]->desc().N;
   M = N + 2 * kGhost;
   nf = meshes[0]->desc().de ? kFieldsDE : kFields;
-  inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); p2task.clear(); faceslot.clear();
+  inst.clear(); blocks.clear(); nbr.clear(); fine.clear(); p2list.clear(); p2task.clear(); p2wave.clear(); faceslot.clear();
   keys.clear();
   std::vector<int32_t> p2k[3];  // phase-2 tasks by kind, merged below
   if (!migr.empty() && meshes.size() != 1) return "migration tables belong to single-mesh plans";
@@ -304,6 +304,19 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
     np2t[k] = int64_t(p2k[k].size() / 2);
     p2task.insert(p2task.end(), p2k[k].begin(), p2k[k].end());
   }
+  // the waves in leaf order (each kind's list is in leaf order: merge them)
+  {
+    int64_t first[3] = {0, np2t[0], np2t[0] + np2t[1]}, at[3] = {0, 0, 0};
+    for (;;) {
+      int k = -1;
+      for (int q = 0; q < 3; q++)
+        if (at[q] < np2t[q] && (k < 0 || p2k[q][size_t(2 * at[q])] < p2k[k][size_t(2 * at[k])])) k = q;
+      if (k < 0) break;
+      const int64_t row = first[k] + at[k]++;
+      if (row >= (int64_t(1) << (31 - kP2SubBits))) return "too many phase-2 tasks";
+      for (int w = 0; w < p2_waves(N, k); w++) p2wave.push_back(int32_t((row << kP2SubBits) | w));
+    }
+  }
   // reflux tasks: coarse side of each coarse-fine face
   for (int64_t s = 0; s < nleaf; s++) {
     const BlockInfo& b = blocks[s];
@@ -349,6 +362,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   off.fine = o; o = align256(o + int64_t(fine.size() * sizeof(int32_t)));
   off.p2list = o; o = align256(o + int64_t(p2list.size() * sizeof(int32_t)));
   off.p2task = o; o = align256(o + int64_t(p2task.size() * sizeof(int32_t)));
+  off.p2wave = o; o = align256(o + int64_t(p2wave.size() * sizeof(int32_t)));
   off.faceslot = o; o = align256(o + int64_t(faceslot.size() * sizeof(int32_t)));
   for (int d = 0; d < 3; d++) {
     off.reflux[d] = o;
@@ -374,6 +388,7 @@ std::string Plan::build(const std::vector<const Octree*>& meshes) {
   put(off.fine, fine.data(), fine.size() * sizeof(int32_t));
   put(off.p2list, p2list.data(), p2list.size() * sizeof(int32_t));
   put(off.p2task, p2task.data(), p2task.size() * sizeof(int32_t));
+  put(off.p2wave, p2wave.data(), p2wave.size() * sizeof(int32_t));
   put(off.faceslot, faceslot.data(), faceslot.size() * sizeof(int32_t));
   for (int d = 0; d < 3; d++) put(off.reflux[d], reflux[d].data(), reflux[d].size() * sizeof(RefluxTask));
   put(off.migr, migr.data(), migr.size() * sizeof(MigrTask));

@@ -159,6 +159,9 @@ struct Plan {
   // phase-2 tasks: (leaf, neighbour code) pairs whose neighbour position is
   // covered by a coarser leaf, faces first, then edges, then corners
   std::vector<int32_t> p2task;
+  // phase-2 waves in leaf order: (task row << kP2SubBits) | wave in task, so
+  // that one launch covers a leaf's face, edge and corner regions together
+  std::vector<int32_t> p2wave;
   int64_t np2t[3] = {0, 0, 0};   // tasks of each kind (faces, edges, corners)
   std::vector<int32_t> faceslot; // 6 per leaf
   std::vector<RefluxTask> reflux[3];
