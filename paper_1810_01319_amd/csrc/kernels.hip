@@ -32,13 +32,17 @@ __device__ __forceinline__ double level_dx(const InstParams& ip, int N, int l) {
 // Ghost refresh
 // ---------------------------------------------------------------------------
 
-// Phase 1: same-level copies (incl. outflow clamps) and restriction.
+// Phase 1: same-level copies (incl. outflow clamps) and restriction.  On
+// large meshes the workgroups go to the XCDs in contiguous ranges (a leaf's
+// ghost cells and its neighbours' in one L2); on small ones in hardware
+// order, which spreads the leaves of a refined region, and their restriction
+// work, over all XCDs.
 template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int GC = M * M * M - N * N * N;
-  const int64_t t = int64_t(xcd_block()) * blockDim.x + threadIdx.x;
+  const int64_t t = int64_t(P.p1_xcd ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= P.nleaf * GC) return;
   const int s = int(t / GC);
   const int g = int(t - int64_t(s) * GC);
