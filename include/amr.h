@@ -234,9 +234,11 @@ amr_status amr_hydro_steps_comoving(amr_mesh* mesh, double* U_dev, double* dt_de
  * before it: the transpose of the expansion sources at U_pre_dev (each
  * cell's floor decision held), then the plain step's transposes with dt / a
  * (floors_host as for amr_hydro_step_adjoint_recorded; scratch_dev:
- * adjoint_face_bytes of amr_mesh_info).  Five-field meshes only.
- * Errors: AMR_E_INVALID for a dual-energy mesh, a null or aliased buffer,
- * a <= 0 or non-finite a, H, floors_host < -1, riemann_iters > 8. */
+ * adjoint_face_bytes of amr_mesh_info).  With the dual-energy field the
+ * sixth field's adjoint takes the internal-energy factor (zero where its
+ * floor was applied).
+ * Errors: AMR_E_INVALID for a null or aliased buffer, a <= 0 or non-finite
+ * a, H, floors_host < -1, riemann_iters > 8. */
 amr_status amr_hydro_step_comoving_record(amr_mesh* mesh, double* U_dev, const double* dt_dev, double a,
                                           double hubble, double* S1_dev, double* S2_dev, double* U_pre_dev,
                                           double* U_out_dev, uint64_t* floors_dev, int64_t step_index,

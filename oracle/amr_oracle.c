@@ -875,7 +875,7 @@ static void expansion(orc_mesh* m, double dt, double hubble) {
           if (K.de) { /* the dual-energy field takes the same factor and floor rule */
             double* ge = &B[cell(M, 5, x, y, z)];
             double ge2 = *ge * fe;
-            if (ge2 < *ge && K.gm1 * ge2 < K.p_floor) {
+            if (BR(ge2 < *ge && K.gm1 * ge2 < K.p_floor)) {
               ge2 = K.p_floor * K.inv_gm1;
               nfl++;
             }

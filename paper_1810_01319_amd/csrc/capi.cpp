@@ -695,7 +695,6 @@ amr_status amr_hydro_step_comoving_record(amr_mesh* h, double* U, const double* 
                                           int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, U);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!dt || !S1 || !S2 || !Upre || !Uout || !floors) return fail(AMR_E_INVALID, "null argument");
   const double* const bufs[5] = {U, S1, S2, Upre, Uout};
   for (int i = 0; i < 5; i++)
@@ -715,7 +714,7 @@ amr_status amr_hydro_step_comoving_record(amr_mesh* h, double* U, const double* 
   // the sweeps' resets only: the adjoint's floor transposes depend on them
   e = launch_floor_mark(P, mark, 1, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(Uout, Upre, size_t(h->plan.nleaf) * kFields * size_t(h->plan.M) * h->plan.M * h->plan.M *
+    e = hipMemcpyAsync(Uout, Upre, size_t(h->plan.nleaf) * h->plan.nf * size_t(h->plan.M) * h->plan.M * h->plan.M *
                                        sizeof(double),
                        hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = timed(h, AMR_PHASE_EXPANSION, st, [&] { return launch_expansion(P, Uout, dt, hubble, st); });
@@ -728,7 +727,6 @@ amr_status amr_hydro_step_comoving_adjoint_recorded(amr_mesh* h, const double* S
                                                     double* lam, void* scratch, int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, S0);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!S1 || !S2 || !Upre || !dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   if (floors_host < -1) return fail(AMR_E_INVALID, "floors_host must be a count or -1");
   if (!(a > 0.0) || !std::isfinite(a)) return fail(AMR_E_INVALID, "expansion factor must be positive and finite");

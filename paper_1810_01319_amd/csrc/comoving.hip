@@ -82,10 +82,10 @@ __global__ void __launch_bounds__(256) expansion_kernel(double* __restrict__ U, 
   if (nfl) atomicAdd(P.counters, (unsigned long long)nfl);
 }
 
-// Transpose of expansion_kernel (five fields): lam holds dL/dU after the
-// sources on entry and dL/dU before them on exit, at the state U they were
-// applied to.  One thread per active cell.
-template <int N>
+// Transpose of expansion_kernel: lam holds dL/dU after the sources on entry
+// and dL/dU before them on exit, at the state U they were applied to (NF = 5,
+// or 6 with the dual-energy field).  One thread per active cell.
+template <int N, int NF>
 __global__ void __launch_bounds__(256) expansion_adjoint_kernel(const double* __restrict__ U,
                                                                 double* __restrict__ lam,
                                                                 const double* __restrict__ dtv, double hubble,
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) expansion_adjoint_kernel(const double* __
   const BlockInfo bi = P.blocks[s];
   const InstParams ip = P.inst[bi.inst];
   const double c = (0.5 * dtv[bi.inst]) * hubble;
-  const int64_t o = int64_t(s) * kFields * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
+  const int64_t o = int64_t(s) * NF * M3 + (int64_t(z + G) * M + (y + G)) * M + (x + G);
   const double* const B = U + o;
   double* const L = lam + o;
   double lr = L[0], lmx = L[M3], lmy = L[2 * M3], lmz = L[3 * M3], lE = L[4 * M3];
@@ -111,15 +111,25 @@ __global__ void __launch_bounds__(256) expansion_adjoint_kernel(const double* __
   L[2 * M3] = lmy;
   L[3 * M3] = lmz;
   L[4 * M3] = lE;
+  if constexpr (NF == kFieldsDE) {
+    double lge = L[5 * M3];
+    expansion_ge_vjp(ip, c, B[5 * M3], lge);
+    L[5 * M3] = lge;
+  }
 }
 
 template <int N>
 hipError_t expansion_adjoint_n(const DevPlan& P, const double* U, double* lam, const double* dt, double hubble,
                                hipStream_t st) {
   const int64_t n = P.nleaf * int64_t(N) * N * N;
-  if (n > 0)
-    hipLaunchKernelGGL(expansion_adjoint_kernel<N>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
-                       U, lam, dt, hubble, P);
+  if (n > 0) {
+    if (P.nf == kFieldsDE)
+      hipLaunchKernelGGL((expansion_adjoint_kernel<N, kFieldsDE>), dim3(static_cast<unsigned>((n + 255) / 256)),
+                         dim3(256), 0, st, U, lam, dt, hubble, P);
+    else
+      hipLaunchKernelGGL((expansion_adjoint_kernel<N, kFields>), dim3(static_cast<unsigned>((n + 255) / 256)),
+                         dim3(256), 0, st, U, lam, dt, hubble, P);
+  }
   return hipGetLastError();
 }
 

@@ -72,4 +72,13 @@ __device__ __forceinline__ void expansion_cell_vjp(const InstParams& ip, double 
   lE = fl ? 0.0 : lE * fe;
 }
 
+// The dual-energy field's part: rho e' = fe rho e, or the floor where that
+// fell below it (held at the forward's decision).
+__device__ __forceinline__ void expansion_ge_vjp(const InstParams& ip, double c, double ge, double& lge) {
+  const double g3 = 3.0 * ip.gm1;
+  const double fe = (1.0 - g3 * c) / (1.0 + g3 * c);
+  const double ge2 = ge * fe;
+  lge = (ge2 < ge && ip.gm1 * ge2 < ip.p_floor) ? 0.0 : lge * fe;
+}
+
 }  // namespace amr

@@ -123,11 +123,19 @@ def test_static_universe_gradient_equals_the_plain_adjoint():
     assert diff <= 1e-13 * scale
 
 
-def test_tiny_mesh_gradient_against_oracle_differences():
-    spec = tiny_spec()
+@pytest.mark.parametrize("de", [False, True])
+def test_tiny_mesh_gradient_against_oracle_differences(de):
+    """With the dual-energy field (eta2 = 0.99, so that rho e keeps its own
+    evolution) the loss also takes the misfit of rho e, and the entries
+    sampled cover all six fields."""
+    spec = tiny_spec(dual_energy=True, eta1=1e-3, eta2=0.99) if de else tiny_spec()
     m = Mesh(**spec.kwargs())
     N, steps = 8, 2
     act0 = I.smooth_state(spec, m.keys, seed=83, amp=0.2, vel=0.3)
+    if de:
+        act0 = I.with_internal_energy(act0)
+        act0[:, 5] *= 1.0 + 0.01 * np.random.default_rng(88).standard_normal(act0[:, 5].shape)
+    nf = act0.shape[1]
     U0 = m.state_from_active(act0)
     lev = m.keys[:, 0]
     wn = 0.125 ** lev
@@ -147,10 +155,17 @@ def test_tiny_mesh_gradient_against_oracle_differences():
         return om.active()[perm]
 
     # targets near the oracle's own final state
-    target = targets(oracle_final(act0), 84, m.device)
+    fin = oracle_final(act0)
+    target = targets(fin, 84, m.device)
     tgt = [t.cpu().numpy() for t in target]
+    ge_t = fin[:, 5] * (1.0 + 0.001 * np.random.default_rng(89).standard_normal(fin[:, 5].shape)) if de else None
     Ug = U0.clone().requires_grad_(True)
-    loss_terms(A.run_comoving_steps(Ug, m, sched), N, w, target).backward()
+    Uc = A.run_comoving_steps(Ug, m, sched)
+    L = loss_terms(Uc, N, w, target)
+    if de:
+        dge = Uc[:, 5, G:G + N, G:G + N, G:G + N] - torch.from_numpy(ge_t).to(m.device)
+        L = L + 0.3 * (w * dge * dge).sum()
+    L.backward()
     g = Ug.grad.detach().cpu().numpy()[:, :, G:G + N, G:G + N, G:G + N]
     wb = wn[:, None, None, None]
 
@@ -162,14 +177,17 @@ def test_tiny_mesh_gradient_against_oracle_differences():
         O.tape_replay()
         a = oracle_final(act)
         O.tape_stop()
-        dr, dm, de = a[:, 0] - tgt[0], a[:, 1] - tgt[1], a[:, 4] - tgt[2]
-        return float(np.sum(wb * (dr * dr + 0.2 * (dm * dm) + 0.3 * (de * de))))
+        dr, dm, dE = a[:, 0] - tgt[0], a[:, 1] - tgt[1], a[:, 4] - tgt[2]
+        v = np.sum(wb * (dr * dr + 0.2 * (dm * dm) + 0.3 * (dE * dE)))
+        if de:
+            v += 0.3 * np.sum(wb * (a[:, 5] - ge_t) ** 2)
+        return float(v)
 
     rng = np.random.default_rng(85)
     scale = np.abs(g).max()
     worst = 0.0
     for e in range(100):
-        s, f = int(rng.integers(m.nleaf)), e % 5
+        s, f = int(rng.integers(m.nleaf)), e % nf
         z, y, x = (int(v) for v in rng.integers(N, size=3))
         h = 1e-5 * max(1.0, abs(act0[s, f, z, y, x]))
         ap, am_ = act0.copy(), act0.copy()
@@ -179,7 +197,8 @@ def test_tiny_mesh_gradient_against_oracle_differences():
         err = abs(fd - g[s, f, z, y, x]) / max(abs(fd), 1e-3 * scale)
         worst = max(worst, err)
         assert err <= 1e-6, ((s, f, z, y, x), g[s, f, z, y, x], fd)
-    say(f"tiny mesh: 100 frozen-branch oracle difference entries over all fields, worst relative error {worst:.3e}")
+    say(f"tiny mesh (dual energy {de}): 100 frozen-branch oracle difference entries over all fields, "
+        f"worst relative error {worst:.3e}")
 
 
 def test_expansion_floors_gradient_on_directions():
