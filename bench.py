@@ -330,7 +330,47 @@ def adjoint_compare(steps: int = 10, reps: int = 3):
         else:
             out["recomputing"] = res
         del state
+    out["dual_energy"] = adjoint_compare_de(steps)
     return out
+
+
+def adjoint_compare_de(steps: int):
+    """The same workload with the dual-energy field (eta1 1e-3, eta2 0.1):
+    plain forward, recording forward and adjoint (one timed pass after a
+    warm-up)."""
+    import dataclasses
+
+    import torch
+
+    from paper_1810_01319_amd import adjoint as A
+    from paper_1810_01319_amd import inputs as I
+    from paper_1810_01319_amd.mesh import Mesh
+
+    spec = dataclasses.replace(I.grf_spec(root=4, block_cells=32), dual_energy=True, eta1=1e-3, eta2=0.1)
+    m = Mesh(**spec.kwargs())
+    N, g3 = spec.block_cells, 3
+    base = m.state_from_active(I.with_internal_energy(I.grf_state(spec, m.keys, seed=4)))
+    target = torch.from_numpy(I.grf_density(spec, m.keys, seed=40)).to(m.device)
+    t = {}
+    for i in range(2):  # the first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U = base.clone()
+        for k in range(steps):
+            m.step(U, m.dt_tensor(), k)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = base[:, 0, g3:g3 + N, g3:g3 + N, g3:g3 + N].clone().requires_grad_(True)
+        L = A.density_misfit(m, A.run_steps(A.with_density(base, r), m, steps), target)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t = {"forward_ms": (t1 - t0) * 1e3, "recording_forward_ms": (t2 - t1) * 1e3, "adjoint_ms": (t3 - t2) * 1e3}
+    t["adjoint_over_forward"] = t["adjoint_ms"] / t["forward_ms"]
+    t["workload"] = "the same mesh and state with the dual-energy field (eta1 1e-3, eta2 0.1), recording mode"
+    return t
 
 
 def tracer_compare(steps: int = 20):

@@ -95,7 +95,7 @@ struct AdjShape {
 // than the lost occupancy).  The cell's state and adjoint are read together
 // at the start (the adjoint parked in LDS until the reverse pass) and again
 // one phase before the end, so that their latency overlaps computation.
-template <int N, int DIR, bool FLOORS>
+template <int N, int DIR, bool FLOORS, int NF = kFields>
 __global__ void __launch_bounds__((AdjShape<N, DIR>::WG)) __attribute__((amdgpu_waves_per_eu(3)))
 sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const double* __restrict__ dtv, DevPlan P,
               const double* __restrict__ gfaces, const unsigned long long* __restrict__ floors, int sel, int loA,
@@ -110,13 +110,16 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
   constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
   constexpr int NS = DIR == 0 ? 1 : R;  // item stride between neighbouring cells
-  constexpr int fmap[5] = {0, 1 + DIR, 1 + T1, 1 + T2, 4};
+  constexpr bool DE = NF == kFieldsDE;  // dual-energy field rho e (field 5); only with FLOORS
+  static_assert(!DE || FLOORS, "the dual-energy transpose recomputes the fluxes");
+  constexpr int fmap[6] = {0, 1 + DIR, 1 + T1, 1 + T2, 4, 5};
   __shared__ double Ps[5][T];  // primitives
   __shared__ double Xs[5][T];  // slopes; fluxes; adjoint sent to face c-1/2
   __shared__ double Ys[5][T];  // face values at c+1/2; adjoint sent to cell c-1
   __shared__ double Ws[5][T];  // right states at c-1/2 and their adjoint; adjoint sent to cell c+1
-  __shared__ double Ls[5][T];  // adjoint of the pre-floor update; adjoint sent to face c+1/2
+  __shared__ double Ls[NF][T];  // adjoint of the pre-floor update; adjoint sent to face c+1/2
   __shared__ double Fl[2][T];  // flattening adjoint sent to p of cells c+-1, c+-2
+  __shared__ double Gs[DE ? 2 : 1][DE ? T : 1];  // DE: rho e flux and Godunov velocity at c+1/2
   // a tile is R consecutive pencils of the leaf's nA x nB plane (numbered
   // along A, then B), so only the leaf's last tile is partial
   const int npen = nA * nB;
@@ -133,7 +136,7 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   const InstParams ip = P.inst[bi.inst];  // by value: read once, before any store
   const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
   const int iA = loA + pp % nA;
-  const int64_t off = int64_t(s) * kFields * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
+  const int64_t off = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
   const double* const ucell = Uin + off;
   double* const lcell = lam + off;
   const double sixth = ip.sixth;
@@ -153,18 +156,19 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   if (live) {
     // the cell's adjoint is read with its state (one memory round trip) and
     // waits in Ls, which the forward recompute does not use
-    double u5[5], l5[5];
+    double u5[NF], l5[NF];
 #pragma unroll
-    for (int v = 0; v < 5; v++) {
+    for (int v = 0; v < NF; v++) {
       u5[v] = ucell[fmap[v] * M3];
       l5[v] = lcell[fmap[v] * M3];
     }
-    const Prim Pr = prim_fwd(ip, u5);
+    Prim Pr;
+    if constexpr (DE) Pr = prim_fwd_de(ip, u5);
+    else Pr = prim_fwd(ip, u5);
 #pragma unroll
-    for (int v = 0; v < 5; v++) {
-      Ps[v][i] = Pr.q[v];
-      Ls[v][i] = l5[v];
-    }
+    for (int v = 0; v < 5; v++) Ps[v][i] = Pr.q[v];
+#pragma unroll
+    for (int v = 0; v < NF; v++) Ls[v][i] = l5[v];
     Fl[0][i] = Pr.c;
     Fl[1][i] = Pr.ir;
   }
@@ -214,12 +218,16 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   __syncthreads();
   if (FLOORS) {
     if (faced) {
-      double R5[5], F[5];
+      double R5[5], F[NF], ug = 0.0;
 #pragma unroll
       for (int v = 0; v < 5; v++) R5[v] = Ws[v][i + NS];
-      riemann_flux(ip, WL, R5, F);
+      riemann_flux<DE>(ip, WL, R5, F, &ug);
 #pragma unroll
       for (int v = 0; v < 5; v++) Xs[v][i] = F[v];
+      if constexpr (DE) {
+        Gs[0][i] = F[5];
+        Gs[1][i] = ug;
+      }
     }
     __syncthreads();
   }
@@ -228,19 +236,26 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   // update and floors: li is the adjoint of the cell's own input through the
   // identity part (pre-floor adjoint on active cells, unchanged elsewhere);
   // the floor-free variant rereads it from lam at the end
-  double li[5] = {0, 0, 0, 0, 0};
+  double li[NF] = {};
   if (live) {
     if (FLOORS) {
 #pragma unroll
-      for (int v = 0; v < 5; v++) li[v] = Ls[v][i];
+      for (int v = 0; v < NF; v++) li[v] = Ls[v][i];
       if (active) {
-        double V[5];
+        double V[NF];
 #pragma unroll
         for (int v = 0; v < 5; v++) V[v] = ucell[fmap[v] * M3] - nu * (Xs[v][i] - Xs[v][i - NS]);
-        floor_vjp(ip, V, li, li);
+        if constexpr (DE) {
+          // rho e: its flux difference, then the work of the cell's pressure
+          V[5] = ucell[fmap[5] * M3] - nu * (Gs[0][i] - Gs[0][i - NS]);
+          V[5] = V[5] - nu * (Ps[4][i] * (Gs[1][i] - Gs[1][i - NS]));
+          floor_vjp_de(ip, V, li, li);
+        } else {
+          floor_vjp(ip, V, li, li);
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 5; v++) Ls[v][i] = active ? li[v] : 0.0;
+      for (int v = 0; v < NF; v++) Ls[v][i] = active ? li[v] : 0.0;
     } else if (!active) {
 #pragma unroll
       for (int v = 0; v < 5; v++) Ls[v][i] = 0.0;
@@ -259,15 +274,23 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
       R5[v] = Ws[v][i + NS];
     }
     const bool faces_act = iA >= G && iA < G + N && iB >= G && iB < G + N;
+    double gF5 = 0.0, gug = 0.0;
+    if constexpr (DE) {
+      // rho e's flux, and the Godunov velocity through the work terms of the
+      // cells c (-nu p_c) and c+1 (+nu p_c+1)
+      gF5 = nu * (Ls[5][i + NS] - Ls[5][i]);
+      gug = nu * (Ps[4][i + NS] * Ls[5][i + NS] - Ps[4][i] * Ls[5][i]);
+    }
     if (faces_act && (c == G - 1 || c == N + G - 1)) {
       const int slot = P.faceslot[6 * int64_t(s) + 2 * DIR + (c == G - 1 ? 0 : 1)];
       if (slot >= 0) {
-        const double* gf = gfaces + int64_t(slot) * kFields * N * N + int64_t(iB - G) * N + (iA - G);
+        const double* gf = gfaces + int64_t(slot) * NF * N * N + int64_t(iB - G) * N + (iA - G);
 #pragma unroll
         for (int v = 0; v < 5; v++) gF[v] += gf[fmap[v] * N * N];
+        if constexpr (DE) gF5 += gf[5 * N * N];
       }
     }
-    riemann_vjp_n<kAdjMaxIters>(ip, L5, R5, gF, gWL, gR5);
+    riemann_vjp_n<kAdjMaxIters, true, DE>(ip, L5, R5, gF, gWL, gR5, gF5, gug);
 #pragma unroll
     for (int v = 0; v < 5; v++) Ws[v][i + NS] = gR5[v];
   }
@@ -341,10 +364,10 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
   // face values at c+-1/2, flattening, then the own slope; the state and
   // (floor-free variant) the adjoint of the cell, needed at the end, are
   // read here so that the two phases hide their latency
-  double u5e[5] = {0, 0, 0, 0, 0};
+  double u5e[NF] = {};
   if (live) {
 #pragma unroll
-    for (int v = 0; v < 5; v++) u5e[v] = ucell[fmap[v] * M3];
+    for (int v = 0; v < NF; v++) u5e[v] = ucell[fmap[v] * M3];
     if (!FLOORS) {
 #pragma unroll
       for (int v = 0; v < 5; v++) li[v] = lcell[fmap[v] * M3];
@@ -377,11 +400,18 @@ sweep_adjoint(const double* __restrict__ Uin, double* __restrict__ lam, const do
       if (c >= 1) gq[v] += Ws[v][i - NS];
       if (c + 1 < M) gq[v] += Ys[v][i + NS];
     }
-    double gU[5] = {0, 0, 0, 0, 0};
-    const Prim Pr = prim_fwd(ip, u5e);
-    prim_vjp(ip, u5e, Pr, gq, gc, gir, gU);
+    double gU[NF] = {};
+    if constexpr (DE) {
+      // the work term of the own update: -nu p (u_g(c+1/2) - u_g(c-1/2)) on rho e
+      if (active) gq[4] += -nu * (Gs[1][i] - Gs[1][i - NS]) * li[5];
+      const Prim Pr = prim_fwd_de(ip, u5e);
+      prim_vjp<true>(ip, u5e, Pr, gq, gc, gir, gU);
+    } else {
+      const Prim Pr = prim_fwd(ip, u5e);
+      prim_vjp(ip, u5e, Pr, gq, gc, gir, gU);
+    }
 #pragma unroll
-    for (int v = 0; v < 5; v++) lcell[fmap[v] * M3] = li[v] + gU[v];
+    for (int v = 0; v < NF; v++) lcell[fmap[v] * M3] = li[v] + gU[v];
   }
 }
 
@@ -503,64 +533,6 @@ __global__ void __launch_bounds__(256) refresh1_adjoint(double* __restrict__ lam
   }
 }
 
-// Dual-energy sweep transpose: one thread per pencil, the pencil's six
-// fields and their adjoints in private arrays, and pencil_vjp_de (the
-// element products composed pencil by pencil, the reference form the host
-// tests check): a plain form for the six-field step, whose transpose is not
-// on the measured path.  The pencils are the forward sweep's.
-template <int N, int DIR>
-__global__ void __launch_bounds__(64) sweep_adjoint_de(const double* __restrict__ Uin, double* __restrict__ lam,
-                                                       const double* __restrict__ dtv, DevPlan P,
-                                                       const double* __restrict__ gfaces, int loA, int nA, int loB,
-                                                       int nB) {
-  constexpr int M = N + 2 * G;
-  constexpr int64_t M3 = int64_t(M) * M * M;
-  constexpr int NF = kFieldsDE;
-  constexpr int A = DIR == 0 ? 1 : 0;
-  constexpr int B = DIR == 2 ? 1 : 2;
-  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
-  constexpr int SD = DIR == 0 ? 1 : (DIR == 1 ? M : M * M);
-  constexpr int SA = A == 0 ? 1 : (A == 1 ? M : M * M);
-  constexpr int SB = B == 0 ? 1 : (B == 1 ? M : M * M);
-  static_assert(M <= kMaxPencil, "pencil longer than the adjoint's arrays");
-  const int64_t npen = int64_t(nA) * nB;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= P.nleaf * npen) return;
-  const int s = int(t / npen);
-  const int pp = int(t - int64_t(s) * npen);
-  const int iA = loA + pp % nA, iB = loB + pp / nA;
-  const BlockInfo bi = P.blocks[s];
-  const InstParams ip = P.inst[bi.inst];
-  const double nu = dtv[bi.inst] / level_dx_a(ip, N, bi.level);
-  const int fmap[NF] = {0, 1 + DIR, 1 + T1, 1 + T2, 4, 5};
-  const int64_t boff = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB;
-  double U[NF * M], L[NF * M];
-  for (int v = 0; v < NF; v++)
-    for (int j = 0; j < M; j++) {
-      const int64_t o = boff + int64_t(fmap[v]) * M3 + int64_t(j) * SD;
-      U[v * M + j] = Uin[o];
-      L[v * M + j] = lam[o];
-    }
-  double glo[NF], ghi[NF];
-  const double* pl = nullptr;
-  const double* ph = nullptr;
-  if (iA >= G && iA < G + N && iB >= G && iB < G + N) {
-    const int64_t off = int64_t(iB - G) * N + (iA - G);
-    const int sl = P.faceslot[6 * int64_t(s) + 2 * DIR], sh = P.faceslot[6 * int64_t(s) + 2 * DIR + 1];
-    if (sl >= 0) {
-      for (int v = 0; v < NF; v++) glo[v] = gfaces[(int64_t(sl) * NF + fmap[v]) * N * N + off];
-      pl = glo;
-    }
-    if (sh >= 0) {
-      for (int v = 0; v < NF; v++) ghi[v] = gfaces[(int64_t(sh) * NF + fmap[v]) * N * N + off];
-      ph = ghi;
-    }
-  }
-  pencil_vjp_de(ip, nu, M, G, G + N, U, L, pl, ph);
-  for (int v = 0; v < NF; v++)
-    for (int j = 0; j < M; j++) lam[boff + int64_t(fmap[v]) * M3 + int64_t(j) * SD] = L[v * M + j];
-}
-
 inline unsigned gridn(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 template <int N, int DIR>
@@ -570,16 +542,14 @@ hipError_t sweep_adj_nd(const DevPlan& P, const double* Uin, double* lam, const 
   constexpr int A = DIR == 0 ? 1 : 0, B = DIR == 2 ? 1 : 2;
   const int loA = swept[A] ? G : 0, nA = swept[A] ? N : S::M;
   const int loB = swept[B] ? G : 0, nB = swept[B] ? N : S::M;
-  if (P.nf == kFieldsDE) {
-    const int64_t n = P.nleaf * int64_t(nA) * nB;
-    if (n > 0)
-      hipLaunchKernelGGL((sweep_adjoint_de<N, DIR>), dim3(gridn(n, 64)), dim3(64), 0, st, Uin, lam, dt, P, gfaces,
-                         loA, nA, loB, nB);
-    return hipGetLastError();
-  }
   const int64_t tiles = P.nleaf * ((int64_t(nA) * nB + S::R - 1) / S::R);
   if (tiles == 0) return hipSuccess;
   const dim3 g(static_cast<unsigned>(tiles)), b(S::WG);
+  if (P.nf == kFieldsDE) {  // one variant: the flux recompute the dual-energy transpose needs
+    hipLaunchKernelGGL((sweep_adjoint<N, DIR, true, kFieldsDE>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, 1, loA,
+                       nA, loB, nB);
+    return hipGetLastError();
+  }
   const int sel = floors == nullptr ? 1 : (floors_host < 0 ? -1 : (floors_host > 0 ? 1 : 0));
   if (sel <= 0)
     hipLaunchKernelGGL((sweep_adjoint<N, DIR, false>), g, b, 0, st, Uin, lam, dt, P, gfaces, floors, sel, loA, nA, loB,
