@@ -11,6 +11,9 @@ pressure from E - ke, rho e resynchronised from E almost everywhere); rho e
 carried by its own flux and work term (eta2 = 0.99); and a fast flow whose
 pressure comes from rho e (eta1 = 0.5).  Loss: misfits of the final density,
 x momentum, energy and rho e to targets near the oracle's final state.
+
+The same check at 32^3 blocks (2 roots, one refined: 9 leaves, one step, 24
+entries per regime), where the transposes run in their N = 32 tile shapes.
 """
 import sys
 
@@ -43,16 +46,12 @@ REGIMES = {
 }
 
 
-@pytest.mark.parametrize("regime", list(REGIMES))
-def test_tiny_mesh_gradient_against_frozen_branch_oracle(regime):
-    r = REGIMES[regime]
-    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=1, gamma=5 / 3, refine=[(0, 1, 0, 1)],
-                      dual_energy=True, eta1=r["eta1"], eta2=r["eta2"])
+def check_against_frozen_oracle(spec, steps, entries, seed, vel, label):
     m = Mesh(**spec.kwargs())
-    N, steps = 8, 2
-    act5 = I.smooth_state(spec, m.keys, seed=91, amp=0.2, vel=r["vel"])
+    N = spec.block_cells
+    act5 = I.smooth_state(spec, m.keys, seed=seed, amp=0.2, vel=vel)
     act0 = I.with_internal_energy(act5)
-    rng = np.random.default_rng(92)
+    rng = np.random.default_rng(seed + 1)
     act0[:, 5] *= 1.0 + 0.01 * rng.standard_normal(act0[:, 5].shape)  # rho e near, not at, E - ke
     U0 = m.state_from_active(act0)
     # the dt sequence of the forward (the oracle's is the same: the forward is bitwise equal)
@@ -89,7 +88,7 @@ def test_tiny_mesh_gradient_against_frozen_branch_oracle(regime):
     d = [a[:, 0] - tg[0], a[:, 1] - tg[1], a[:, 4] - tg[2], a[:, 5] - tg[3]]
     (w * (d[0] * d[0] + 0.2 * d[1] * d[1] + 0.3 * d[2] * d[2] + 0.3 * d[3] * d[3])).sum().backward()
     g = Ug.grad.detach().cpu().numpy()[:, :, G:G + N, G:G + N, G:G + N]
-    say(f"{regime}: adjoint gradient done")
+    say(f"{label}: adjoint gradient done ({m.nleaf} leaves of {N}^3)")
 
     O.tape_record()
     oracle_final(act0)
@@ -104,7 +103,7 @@ def test_tiny_mesh_gradient_against_frozen_branch_oracle(regime):
 
     scale = np.abs(g).max()
     worst = 0.0
-    for e in range(100):
+    for e in range(entries):
         s, f = int(rng.integers(m.nleaf)), e % 6
         z, y, x = (int(v) for v in rng.integers(N, size=3))
         h = 1e-5 * max(1.0, abs(act0[s, f, z, y, x]))
@@ -114,5 +113,22 @@ def test_tiny_mesh_gradient_against_frozen_branch_oracle(regime):
         fd = (oracle_loss(ap) - oracle_loss(am)) / (2 * h)
         err = abs(fd - g[s, f, z, y, x]) / max(abs(fd), 1e-3 * scale)
         worst = max(worst, err)
-        assert err <= 1e-6, (regime, (s, f, z, y, x), g[s, f, z, y, x], fd)
-    say(f"{regime}: 100 frozen-branch oracle difference entries over six fields, worst relative error {worst:.3e}")
+        assert err <= 1e-6, (label, (s, f, z, y, x), g[s, f, z, y, x], fd)
+    say(f"{label}: {entries} frozen-branch oracle difference entries over six fields, "
+        f"worst relative error {worst:.3e}")
+
+
+@pytest.mark.parametrize("regime", list(REGIMES))
+def test_tiny_mesh_gradient_against_frozen_branch_oracle(regime):
+    r = REGIMES[regime]
+    spec = I.MeshSpec(root=(2, 2, 2), block_cells=8, max_level=1, gamma=5 / 3, refine=[(0, 1, 0, 1)],
+                      dual_energy=True, eta1=r["eta1"], eta2=r["eta2"])
+    check_against_frozen_oracle(spec, steps=2, entries=100, seed=91, vel=r["vel"], label=regime)
+
+
+@pytest.mark.parametrize("regime", ["own rho e", "pressure from rho e"])
+def test_block32_gradient_against_frozen_branch_oracle(regime):
+    r = REGIMES[regime]
+    spec = I.MeshSpec(root=(2, 1, 1), block_cells=32, max_level=1, gamma=5 / 3, refine=[(0, 1, 0, 0)],
+                      dual_energy=True, eta1=r["eta1"], eta2=r["eta2"])
+    check_against_frozen_oracle(spec, steps=1, entries=24, seed=93, vel=r["vel"], label=f"N=32 {regime}")
