@@ -250,34 +250,39 @@ __device__ __forceinline__ double cfl_speed(const InstParams& ip, double rho, do
 }
 
 // dt of each instance from the per-leaf maximum signal speeds a run of steps
-// accumulated: min over leaves of dx / speed (one workgroup per instance;
-// exact), C_cfl times it; the speeds are reset to 0.
-__global__ void __launch_bounds__(256) cfl_finalize_leaves(DevPlan P, double* __restrict__ dt) {
-  const int m = blockIdx.x;
-  const InstParams& ip = P.inst[m];
-  unsigned long long best = 0x7FF0000000000000ull;
-  for (int64_t s = ip.first_leaf + threadIdx.x; s < ip.first_leaf + ip.n_leaf; s += blockDim.x) {
+// accumulated, over the whole grid: one thread per leaf takes its maximum
+// (and resets the slots to 0) and dx / speed, and the minimum goes into the
+// instance's accumulator (one atomic per wave whose leaves share an
+// instance, else lane by lane; positive doubles order like their bit
+// patterns, so the minimum is exact in any order); cfl_finalize then forms
+// C_cfl times it.
+__global__ void __launch_bounds__(256) cfl_leaf_min(DevPlan P) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long v = 0x7FF0000000000000ull;  // +inf
+  int inst = -1;
+  if (s < P.nleaf) {
+    const BlockInfo bi = P.blocks[s];
+    inst = bi.inst;
     unsigned long long sb = 0ull;
     for (int k = 0; k < kCflSlots; k++) {
-      const unsigned long long v = P.lacc[s * kCflSlots + k];
-      sb = v > sb ? v : sb;
+      const unsigned long long x = P.lacc[s * kCflSlots + k];
+      sb = x > sb ? x : sb;
       P.lacc[s * kCflSlots + k] = 0ull;
     }
-    const double sp = __longlong_as_double((long long)sb);
-    const double t = level_dx(ip, P.N, P.blocks[s].level) / sp;
-    const unsigned long long v = (unsigned long long)__double_as_longlong(t);
-    best = v < best ? v : best;
+    const double t = level_dx(P.inst[inst], P.N, bi.level) / __longlong_as_double((long long)sb);
+    v = (unsigned long long)__double_as_longlong(t);
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(best, off, 64);
-    best = o < best ? o : best;
-  }
-  __shared__ unsigned long long red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; w++) best = red[w] < best ? red[w] : best;
-    dt[m] = ip.cfl * __longlong_as_double((long long)best);
+  // lane 0 holds the wave's first leaf: a wave without leaves has inst -1 everywhere
+  const int i0 = __shfl(inst, 0, 64);
+  if (i0 < 0) return;
+  if (__ballot(inst == i0 || inst < 0) == __ballot(1)) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(v, off, 64);
+      v = o < v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(&P.acc[i0], v);
+  } else if (inst >= 0) {
+    atomicMin(&P.acc[inst], v);
   }
 }
 
@@ -1130,8 +1135,9 @@ hipError_t launch_reflux_cfl(const DevPlan& P, const double* U, hipStream_t st) 
 }
 
 hipError_t launch_cfl_finalize(const DevPlan& P, double* dt, hipStream_t st) {
-  if (P.ninst > 0)
-    hipLaunchKernelGGL(cfl_finalize_leaves, dim3(static_cast<unsigned>(P.ninst)), dim3(256), 0, st, P, dt);
+  if (P.ninst <= 0) return hipSuccess;
+  if (P.nleaf > 0) hipLaunchKernelGGL(cfl_leaf_min, dim3(grid_for(P.nleaf, 256)), dim3(256), 0, st, P);
+  hipLaunchKernelGGL(cfl_finalize, dim3(grid_for(P.ninst, 64)), dim3(64), 0, st, P, dt, 1.0, nullptr);
   return hipGetLastError();
 }
 
