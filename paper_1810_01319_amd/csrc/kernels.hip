@@ -83,17 +83,20 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
 // Phase 2: limited linear prolongation from the coarser leaf, whose active
 // and phase-1 ghost cells are complete, over the ghost regions (faces,
 // edges, corners) whose neighbour position a coarser leaf covers.  One
-// thread per group of ghost cells that share a coarse parent (up to
-// 2 x 2 x 2): the parent's stencil is loaded and its slopes computed once,
-// then each cell of the group takes its own offset.  One launch covers every
-// region, in leaf order, so that a leaf's face, edge and corner regions run
-// together and share the coarse cells and output lines they touch in L2.
-// Each task takes whole waves, so the task, its leaves and their instance
-// are wave-uniform: scalar loads, off the latency chain of the stencil loads.
+// thread per field of a group of ghost cells that share a coarse parent (up
+// to 2 x 2 x 2): the parent's stencil is loaded and its slopes computed
+// once, then each cell of the group takes its own offset.  One launch covers
+// every region, in leaf order, so that a leaf's face, edge and corner
+// regions run together and share the coarse cells and output lines they
+// touch in L2; each wave of the task table runs once per field (fields
+// innermost).  Each task takes whole waves, so the task, its leaves and
+// their instance are wave-uniform: scalar loads, off the latency chain of
+// the stencil loads.
 // LIN: unlimited central slopes 0.5 (u(+1) - u(-1)) (the composite Poisson
 // operator's interpolation).
 template <int N, int NF, bool LIN, int K>
-__device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPlan& P, int s, int code, int r) {
+__device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPlan& P, int s, int code, int r,
+                                             int f) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   if (r >= P2Region<N, K>::GROUPS) return;
@@ -116,23 +119,19 @@ __device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPl
   const int py0 = bc_index<N>(ip, l, 1, bi.j * N + first[1] - G);
   const int pz0 = bc_index<N>(ip, l, 2, bi.k * N + first[2] - G);
   const int la = (px0 >> 1) - cb.i * N + G, lb = (py0 >> 1) - cb.j * N + G, lc = (pz0 >> 1) - cb.k * N + G;
-  const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
-  double u0[NF], sx[NF], sy[NF], sz[NF];
-#pragma unroll
-  for (int f = 0; f < NF; f++) {
-    const double* q = src + f * M3;
-    u0[f] = q[0];
-    if (LIN) {
-      sx[f] = 0.5 * (q[1] - q[-1]);
-      sy[f] = 0.5 * (q[M] - q[-M]);
-      sz[f] = 0.5 * (q[M * M] - q[-M * M]);
-    } else {
-      sx[f] = minmod(q[1] - u0[f], u0[f] - q[-1]);
-      sy[f] = minmod(q[M] - u0[f], u0[f] - q[-M]);
-      sz[f] = minmod(q[M * M] - u0[f], u0[f] - q[-M * M]);
-    }
+  const double* q = U + (int64_t(e.id) * NF + f) * M3 + (int64_t(lc) * M + lb) * M + la;
+  const double u0 = q[0];
+  double sx, sy, sz;
+  if (LIN) {
+    sx = 0.5 * (q[1] - q[-1]);
+    sy = 0.5 * (q[M] - q[-M]);
+    sz = 0.5 * (q[M * M] - q[-M * M]);
+  } else {
+    sx = minmod(q[1] - u0, u0 - q[-1]);
+    sy = minmod(q[M] - u0, u0 - q[-M]);
+    sz = minmod(q[M * M] - u0, u0 - q[-M * M]);
   }
-  double* const dst0 = U + int64_t(s) * NF * M3;
+  double* const dst0 = U + (int64_t(s) * NF + f) * M3;
   for (int dc = 0; dc < cnt[2]; dc++) {
     const int c = first[2] + dc;
     const double oz = (bc_index<N>(ip, l, 2, bi.k * N + c - G) & 1) ? 0.25 : -0.25;
@@ -142,9 +141,7 @@ __device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPl
       for (int da = 0; da < cnt[0]; da++) {
         const int a = first[0] + da;
         const double ox = (bc_index<N>(ip, l, 0, bi.i * N + a - G) & 1) ? 0.25 : -0.25;
-        double* const dst = dst0 + (int64_t(c) * M + b) * M + a;
-#pragma unroll
-        for (int f = 0; f < NF; f++) dst[f * M3] = ((u0[f] + ox * sx[f]) + oy * sy[f]) + oz * sz[f];
+        dst0[(int64_t(c) * M + b) * M + a] = ((u0 + ox * sx) + oy * sy) + oz * sz;
       }
     }
   }
@@ -152,7 +149,9 @@ __device__ __forceinline__ void phase2_group(double* __restrict__ U, const DevPl
 
 template <int N, int NF, bool LIN>
 __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, DevPlan P) {
-  const unsigned w = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  const unsigned wf = xcd_block() * (blockDim.x >> 6) + unsigned(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+  const unsigned w = wf / unsigned(NF);  // table wave, then the field
+  const int f = int(wf - w * unsigned(NF));
   if (w >= unsigned(P.np2w)) return;
   const int e = P.p2wave[w];
   const int row = e >> kP2SubBits;
@@ -160,9 +159,9 @@ __global__ void __launch_bounds__(256) refresh_phase2(double* __restrict__ U, De
   const int s = P.p2task[2 * int64_t(row)], code = P.p2task[2 * int64_t(row) + 1];
   // the region's kind from its direction: a face has two interior axes
   const int nin = (code % 3 == 1) + ((code / 3) % 3 == 1) + (code / 9 == 1);
-  if (nin == 2) phase2_group<N, NF, LIN, 0>(U, P, s, code, r);
-  else if (nin == 1) phase2_group<N, NF, LIN, 1>(U, P, s, code, r);
-  else phase2_group<N, NF, LIN, 2>(U, P, s, code, r);
+  if (nin == 2) phase2_group<N, NF, LIN, 0>(U, P, s, code, r, f);
+  else if (nin == 1) phase2_group<N, NF, LIN, 1>(U, P, s, code, r, f);
+  else phase2_group<N, NF, LIN, 2>(U, P, s, code, r, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -912,11 +911,11 @@ __global__ void __launch_bounds__(256) migrate_kernel(const double* __restrict__
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
-// the phase-2 launch: whole waves per task, in leaf order (wave indices are
-// 32-bit)
+// the phase-2 launch: whole waves per task and field, in leaf order (wave
+// indices are 32-bit)
 template <int N, int NF, bool LIN>
 hipError_t launch_phase2(const DevPlan& P, double* U, int block, hipStream_t st) {
-  const int64_t n = P.np2w * 64;  // threads
+  const int64_t n = P.np2w * NF * 64;  // threads
   if (n >= (int64_t(1) << 32)) return hipErrorInvalidValue;
   if (n > 0) hipLaunchKernelGGL((refresh_phase2<N, NF, LIN>), dim3(grid_for(n, block)), dim3(block), 0, st, U, P);
   return hipSuccess;
