@@ -530,7 +530,9 @@ RemeshResult remesh_decide(const Octree& old, const Plan& op, const std::vector<
     T.unrefine(P.l, P.i, P.j, P.k);
     res.coarsened++;
   }
-  // migration tasks in the new storage order
+  // migration tasks in the new storage order (none when nothing changed:
+  // the caller keeps the mesh)
+  if (res.refined == 0 && res.coarsened == 0) return res;
   for (const Key& k : T.leaves()) {
     MigrTask t{};
     for (int q = 0; q < 8; q++) t.src[q] = -1;
