@@ -114,7 +114,10 @@ typedef struct {
  * no leaf touches (face, edge or corner, periodic wrap included) a leaf two
  * or more levels finer.  Sec. II-B (array-of-octrees, Refine).
  * Errors: AMR_E_INVALID for a bad descriptor (ghost != 3, N not in {8,16,32},
- * key out of range, outflow on a refined mesh). */
+ * key out of range, outflow on a refined mesh), or more leaves than one
+ * kernel launch over the leaves can cover (2^32 work items: 1,198,372 leaves
+ * of 8^3, 381,300 of 16^3, 67,923 of 32^3; also for the meshes of
+ * amr_mesh_create_from_leaves, amr_batch_create and a remesh). */
 amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out);
 
 /* Build from an explicit leaf set (n x (level,i,j,k), borrowed for the
@@ -358,8 +361,9 @@ amr_status amr_refresh_ghosts_adjoint(amr_mesh* mesh, const double* U_ref_dev, d
  * carries tracers).  Positions are in level-0 cell units: X in
  * [0, root[0] N), Y in [0, root[1] N), Z in [0, root[2] N); a particle belongs
  * to the leaf holding its level-l cell floor(X 2^l).  A set stores
- * `capacity` slots per leaf (a multiple of the 256-slot batch), device
- * memory owned by the caller:
+ * `capacity` slots per leaf (a multiple of the 256-slot batch; n_leaves x
+ * capacity below 2^32, the slots one kernel launch covers, else the calls
+ * return AMR_E_INVALID), device memory owned by the caller:
  *   pos   3 x n_leaves x capacity doubles: every slot's X, then Y, then Z
  *         (slot s of leaf b at b * capacity + s);
  *   id    n_leaves x capacity int64, carried along;
@@ -416,7 +420,9 @@ amr_status amr_floor_count(amr_mesh* mesh, int64_t* out, void* stream);
  * S_b > refine_slope below max_level are refined in (S_b descending, then
  * level, z, y, x) order, each with the minimal refinement that keeps 2:1
  * balance, accepted only if that refines pre-existing leaves only (one level
- * per remesh) and the leaf count stays <= max_blocks (refused otherwise);
+ * per remesh) and the leaf count stays <= max_blocks (refused otherwise; the
+ * library also refuses growth beyond the leaves one kernel launch can cover,
+ * as amr_mesh_create states);
  * then, finer first, octets of pre-existing leaves all below coarsen_slope
  * merge if balance allows.  Data: kept leaves copy, new children prolong
  * (the refresh prolongation), merged parents restrict. */

@@ -8,6 +8,8 @@
 // (ghost values of a state are overwritten by the next refresh).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "adjoint.hpp"
 #include "ghost.hpp"
 #include "xcd.hpp"
@@ -639,6 +641,20 @@ hipError_t launch_refresh_adjoint(const DevPlan& P, double* lam, const double* U
     case 16: return refresh_adj_n<16>(P, lam, Uref, st);
     case 32: return refresh_adj_n<32>(P, lam, Uref, st);
     default: return hipErrorInvalidValue;
+  }
+}
+
+// Work items per leaf of the largest sweep-transpose launch: ceil(M^2 / R)
+// tiles of WG lanes on each axis.
+int64_t adjoint_items_per_leaf(int N) {
+  auto items = [](auto shape) {
+    using S = decltype(shape);
+    return int64_t((S::M * S::M + S::R - 1) / S::R) * S::WG;
+  };
+  switch (N) {
+    case 8: return std::max({items(AdjShape<8, 0>{}), items(AdjShape<8, 1>{}), items(AdjShape<8, 2>{})});
+    case 16: return std::max({items(AdjShape<16, 0>{}), items(AdjShape<16, 1>{}), items(AdjShape<16, 2>{})});
+    default: return std::max({items(AdjShape<32, 0>{}), items(AdjShape<32, 1>{}), items(AdjShape<32, 2>{})});
   }
 }
 

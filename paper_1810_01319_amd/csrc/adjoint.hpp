@@ -18,6 +18,8 @@ hipError_t launch_reflux_adjoint(const DevPlan& P, const double* lam, const doub
 // nullable) = post-update floor resets of the forward step: 0 lets the
 // kernel skip the floors' products; floors_host = the same count read by the
 // host (only the matching kernel is launched), or -1 (not read)
+// Work items per leaf of the largest sweep-transpose launch.
+int64_t adjoint_items_per_leaf(int N);
 hipError_t launch_sweep_adjoint(const DevPlan& P, const double* Uin, double* lam, const double* dt,
                                 const double* gfaces, const unsigned long long* floors, int64_t floors_host, int dir,
                                 const int swept[3], hipStream_t st);

@@ -1,6 +1,7 @@
 // capi.cpp -- extern "C" entry points declared in include/amr.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -124,6 +125,15 @@ amr_status to_desc(const amr_mesh_desc* d, MeshDesc& m) {
   return AMR_OK;
 }
 
+// Leaves of N^3 that one launch over a plan's leaves can cover: a dispatch
+// counts its work items in 32 bits, and the largest launches (the staged
+// sweeps, their transposes, the cell-wise kernels) take a fixed number per
+// leaf.
+int64_t launch_leaf_limit(int N) {
+  const int64_t per = std::max(forward_items_per_leaf(N), adjoint_items_per_leaf(N));
+  return ((int64_t(1) << 32) - 1) / per;
+}
+
 amr_status finish(amr_mesh* h, amr_mesh** out) {
   std::vector<const Octree*> v;
   for (auto& t : h->trees) v.push_back(t.get());
@@ -132,6 +142,13 @@ amr_status finish(amr_mesh* h, amr_mesh** out) {
   if (!e.empty()) {
     delete h;
     return fail(AMR_E_BALANCE, e);
+  }
+  if (h->plan.nleaf > launch_leaf_limit(h->plan.N)) {
+    const std::string m = std::to_string(h->plan.nleaf) + " leaves of " + std::to_string(h->plan.N) +
+                          "^3: a launch over them would exceed 2^32 work items (at most " +
+                          std::to_string(launch_leaf_limit(h->plan.N)) + ")";
+    delete h;
+    return fail(AMR_E_INVALID, m);
   }
   for (size_t m = 0; m < h->trees.size(); m++) {
     bool outflow = false;
@@ -309,7 +326,9 @@ bool adjoint_iters_ok(const Plan& p) {
 
 amr_status decide(amr_mesh* h, const std::vector<double>& S, const amr_remesh_params* prm, amr_mesh** out,
                   amr_remesh_stats* stats) {
-  RemeshResult r = remesh_decide(*h->tree, h->plan, S, prm->refine_slope, prm->coarsen_slope, prm->max_blocks);
+  // refinements beyond what one launch can cover are refused like those beyond max_blocks
+  const int64_t cap = std::min<int64_t>(prm->max_blocks, launch_leaf_limit(h->plan.N));
+  RemeshResult r = remesh_decide(*h->tree, h->plan, S, prm->refine_slope, prm->coarsen_slope, cap);
   if (r.refined == 0 && r.coarsened == 0) {  // the same leaves in the same order: no new mesh
     *out = nullptr;
     stats->refined = 0;
@@ -757,6 +776,9 @@ amr_status tracer_dev(amr_mesh* h, const amr_tracer_set_t* in, amr_tracer_set_t*
       return fail(AMR_E_INVALID, "input and output tracer sets must be distinct");
   }
   const int64_t nleaf = h->plan.nleaf;
+  // the tracer kernels run one lane per slot of every leaf in one launch
+  if (nleaf * cap >= (int64_t(1) << 32))
+    return fail(AMR_E_INVALID, "leaves x capacity reach 2^32 slots: more than one launch can cover");
   const TracerScratch L = tracer_scratch_layout(nleaf, cap);
   unsigned char* sc = static_cast<unsigned char*>(scratch);
   T->pos_in = in->pos;

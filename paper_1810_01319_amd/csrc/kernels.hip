@@ -9,6 +9,7 @@
 // Storage: per leaf 5 fields of M^3 doubles, M = N + 6, x fastest.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1222,6 +1223,30 @@ hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir,
     case 16: return reflux_n<16>(P, U, dt, dir, L, st);
     case 32: return reflux_n<32>(P, U, dt, dir, L, st);
     default: return hipErrorInvalidValue;
+  }
+}
+
+// Work items per leaf of the largest forward launch over the leaves: the
+// staged sweep's tiles (M rows of ceil(M / R) tiles of WG lanes) or one item
+// per padded cell.  A dispatch counts its work items in 32 bits.
+namespace {
+template <int N, int DIR>
+int64_t staged_items() {
+  using S = StagedShape<N, DIR>;
+  return int64_t(S::M) * ((S::M + S::R - 1) / S::R) * S::WG;
+}
+template <int N>
+int64_t forward_items() {
+  constexpr int64_t M = N + 2 * G;
+  return std::max({M * M * M, staged_items<N, 0>(), staged_items<N, 1>(), staged_items<N, 2>()});
+}
+}  // namespace
+
+int64_t forward_items_per_leaf(int N) {
+  switch (N) {
+    case 8: return forward_items<8>();
+    case 16: return forward_items<16>();
+    default: return forward_items<32>();
   }
 }
 

@@ -45,6 +45,9 @@ struct LaunchCfg {
 };
 
 hipError_t launch_refresh(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st);
+// Work items per leaf of the largest forward launch over a plan's leaves
+// (a dispatch counts its work items in 32 bits).
+int64_t forward_items_per_leaf(int N);
 // Refresh of one padded field (per leaf M^3) with unlimited linear
 // prolongation into ghosts over a coarser leaf (the composite Poisson
 // operator's ghosts).

@@ -324,3 +324,34 @@ def test_poisson_workspace_and_refusals_on_the_host():
     assert _poisson_bytes(root=(9, 9, 9), block_cells=32)[0] == -1
     assert _poisson_bytes(root=(7, 7, 7), block_cells=32)[0] == 0  # coarsest 14^3 = 2744 cells
     assert _poisson_bytes(root=(3, 2, 1), block_cells=16)[0] == 0  # coarsest 6 x 4 x 2
+
+
+def test_launch_size_limit():
+    """A dispatch counts its work items in 32 bits: the library rejects a
+    mesh with more leaves than its largest launch over the leaves can cover
+    (at 32^3 the staged x sweep's 38 x 13 tiles of 128 lanes per leaf:
+    67,923 leaves), and a remesh refuses growth beyond it like growth beyond
+    max_blocks."""
+    L = _lib.lib()
+    per_leaf = 38 * 13 * 128
+    limit = (2 ** 32 - 1) // per_leaf
+    assert limit == 67923
+    for root, ok in (((40, 40, 42), True), ((41, 41, 41), False)):
+        d, keep = _lib.make_desc(refine=(), root=root, block_cells=32, max_level=1)
+        h = ctypes.c_void_p()
+        rc = L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h))
+        assert (rc == 0) == ok, (root, rc)
+        if not ok:
+            assert _lib.STATUS[rc] == "AMR_E_INVALID"
+            continue
+        n = 40 * 40 * 42
+        S = np.zeros(n)
+        S[:200] = 1.0  # 200 root refinements of 7 new leaves each (one level: no balancing)
+        prm = _lib.RemeshParams(0.3, 0.0, 10 ** 9)
+        h2, st = ctypes.c_void_p(), _lib.RemeshStats()
+        assert L.amr_remesh_plan_host(h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm), ctypes.byref(h2),
+                                      ctypes.byref(st)) == 0
+        assert st.n_leaves <= limit and st.refused > 0 and st.refined == (limit - n) // 7
+        assert st.n_leaves == n + 7 * st.refined
+        L.amr_mesh_destroy(h2)
+        L.amr_mesh_destroy(h)
