@@ -115,8 +115,8 @@ typedef struct {
  * or more levels finer.  Sec. II-B (array-of-octrees, Refine).
  * Errors: AMR_E_INVALID for a bad descriptor (ghost != 3, N not in {8,16,32},
  * key out of range, outflow on a refined mesh), or more leaves than one
- * kernel launch over the leaves can cover (2^32 work items: 1,198,372 leaves
- * of 8^3, 381,300 of 16^3, 67,923 of 32^3; also for the meshes of
+ * kernel launch over the leaves can cover (2^32 work items: 1,525,201 leaves
+ * of 8^3, 381,300 of 16^3, 69,615 of 32^3; also for the meshes of
  * amr_mesh_create_from_leaves, amr_batch_create and a remesh). */
 amr_status amr_mesh_create(const amr_mesh_desc* desc, amr_mesh** out);
 

@@ -608,23 +608,24 @@ __device__ __forceinline__ void sweep_staged_body(const double* Uin, double* Uou
   __shared__ double Ys[5][T];           // face values at j+1/2, then fluxes
   __shared__ double Fg[DE ? T : 1];     // DE: rho e flux at j+1/2
   __shared__ double Ug[DE ? T : 1];     // DE: Godunov velocity at j+1/2
-  // tile -> (leaf, B row, first A pencil): 32-bit unsigned arithmetic on the
-  // uniform tile index (a grid has fewer than 2^32 workgroups)
-  const unsigned tilesA = unsigned(nA + R - 1) / unsigned(R);
-  const unsigned per_leaf = unsigned(nB) * tilesA;
+  // tile -> (leaf, its first pencil): a tile is R consecutive pencils of the
+  // leaf's nA x nB plane (numbered along A, then B; the pencils are
+  // independent, so a tile may span two B rows and only the leaf's last tile
+  // is partial); 32-bit unsigned arithmetic on the uniform tile index (a grid
+  // has fewer than 2^32 workgroups)
+  const int npen = nA * nB;
+  const unsigned tpl = unsigned(npen + R - 1) / unsigned(R);
   const unsigned tile = xcd_block();
-  const int s = int(tile / per_leaf);
-  const unsigned rem = tile - unsigned(s) * per_leaf;
-  const int iB = loB + int(rem / tilesA);
-  const int a0 = int(rem % tilesA) * R;
+  const int s = int(tile / tpl);
   const int i = threadIdx.x;
   const int r = DIR == 0 ? i / M : i % R;
   const int c = DIR == 0 ? i - r * M : i / R;
-  const bool live = i < T && a0 + r < nA;
+  const int pp = int(tile - unsigned(s) * tpl) * R + r;
+  const bool live = i < T && pp < npen;
   const BlockInfo bi = P.blocks[s];
   const InstParams& ip = P.inst[bi.inst];
   const double nu = dtv[bi.inst] / level_dx(ip, N, bi.level);
-  const int iA = loA + a0 + r;
+  const int iA = loA + pp % nA, iB = loB + pp / nA;
   const int64_t coff = int64_t(s) * NF * M3 + int64_t(iA) * SA + int64_t(iB) * SB + int64_t(c) * SD;
   const double* const cellp = Uin + coff;
   double* const outp = Uout + coff;
@@ -971,7 +972,7 @@ hipError_t sweep_ndf(const DevPlan& P, const double* Uin, double* Uout, const do
   const bool oop = Uin != Uout;
   if (L.sweep_mode[DIR] == 1) {
     using S = StagedShape<N, DIR>;
-    const dim3 g(static_cast<unsigned>(P.nleaf * int64_t(nB) * ((nA + S::R - 1) / S::R))), b(S::WG);
+    const dim3 g(static_cast<unsigned>(P.nleaf * ((int64_t(nA) * nB + S::R - 1) / S::R))), b(S::WG);
     if (oop)
       hipLaunchKernelGGL((sweep_staged_oop<N, DIR, NF>), g, b, 0, st, Uin, Uout, dt, P, loA, nA, loB, nB);
     else
@@ -1227,13 +1228,13 @@ hipError_t launch_reflux(const DevPlan& P, double* U, const double* dt, int dir,
 }
 
 // Work items per leaf of the largest forward launch over the leaves: the
-// staged sweep's tiles (M rows of ceil(M / R) tiles of WG lanes) or one item
-// per padded cell.  A dispatch counts its work items in 32 bits.
+// staged sweep's tiles (ceil(M^2 / R) tiles of WG lanes) or one item per
+// padded cell.  A dispatch counts its work items in 32 bits.
 namespace {
 template <int N, int DIR>
 int64_t staged_items() {
   using S = StagedShape<N, DIR>;
-  return int64_t(S::M) * ((S::M + S::R - 1) / S::R) * S::WG;
+  return int64_t((S::M * S::M + S::R - 1) / S::R) * S::WG;
 }
 template <int N>
 int64_t forward_items() {

@@ -329,14 +329,14 @@ def test_poisson_workspace_and_refusals_on_the_host():
 def test_launch_size_limit():
     """A dispatch counts its work items in 32 bits: the library rejects a
     mesh with more leaves than its largest launch over the leaves can cover
-    (at 32^3 the staged x sweep's 38 x 13 tiles of 128 lanes per leaf:
-    67,923 leaves), and a remesh refuses growth beyond it like growth beyond
-    max_blocks."""
+    (at 32^3 the first x sweep's and the transposes' ceil(38^2 / 3) tiles of
+    128 lanes per leaf: 69,615 leaves), and a remesh refuses growth beyond it
+    like growth beyond max_blocks."""
     L = _lib.lib()
-    per_leaf = 38 * 13 * 128
+    per_leaf = -(-38 * 38 // 3) * 128
     limit = (2 ** 32 - 1) // per_leaf
-    assert limit == 67923
-    for root, ok in (((40, 40, 42), True), ((41, 41, 41), False)):
+    assert limit == 69615
+    for root, ok in (((40, 40, 43), True), ((41, 41, 42), False)):
         d, keep = _lib.make_desc(refine=(), root=root, block_cells=32, max_level=1)
         h = ctypes.c_void_p()
         rc = L.amr_mesh_create(ctypes.byref(d), ctypes.byref(h))
@@ -344,7 +344,7 @@ def test_launch_size_limit():
         if not ok:
             assert _lib.STATUS[rc] == "AMR_E_INVALID"
             continue
-        n = 40 * 40 * 42
+        n = 40 * 40 * 43
         S = np.zeros(n)
         S[:200] = 1.0  # 200 root refinements of 7 new leaves each (one level: no balancing)
         prm = _lib.RemeshParams(0.3, 0.0, 10 ** 9)
