@@ -572,8 +572,9 @@ __global__ void __launch_bounds__(kWalkLanes) sweep_kernel_oop(const double* __r
 
 // ---------------------------------------------------------------------------
 // PPM sweep, LDS-staged: a workgroup owns a tile of R whole pencils, loaded
-// with coalesced accesses (along x a tile is R consecutive rows, one
-// contiguous run; along y or z it is R consecutive x positions).  Each thread
+// with coalesced accesses (along x a tile is R consecutive rows, contiguous
+// unless it spans two z layers; along y or z it is R consecutive x
+// positions).  Each thread
 // owns one cell of the tile through six stages separated by barriers; its own
 // cell's state stays in registers and only neighbour values go through LDS.
 // ---------------------------------------------------------------------------

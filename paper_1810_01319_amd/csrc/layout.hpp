@@ -20,11 +20,11 @@ constexpr int kCflSlots = 16;
 // whole waves a region's task takes
 constexpr int p2_groups(int N, int K) { return K == 0 ? 2 * (N / 2) * (N / 2) : (K == 1 ? 4 * (N / 2) : 8); }
 constexpr int p2_waves(int N, int K) { return (p2_groups(N, K) + 63) / 64; }
-constexpr int kP2SubBits = 3;
+constexpr int kP2SubBits = 3;  // wave-in-task bits of a phase-2 wave entry (at most 8 waves per task)
 // leaves from which the phase-1 refresh takes the XCD-contiguous workgroup
 // order (measured on gfx950: 45.0 -> 40.6 ms at 64,567 leaves of 32^3, but
 // 0.380 -> 0.425 ms at 624)
-constexpr int64_t kP1XcdMinLeaves = 4096;  // wave-in-task bits of a phase-2 wave entry (at most 8 waves per task)
+constexpr int64_t kP1XcdMinLeaves = 4096;
 
 // Per mesh instance: gas constants in the exact forms the formulas use
 // (computed once on the host in FP64) and the geometry.
