@@ -304,11 +304,10 @@ amr_status amr_graph_destroy(amr_graph* graph);
  * Jacobian product of the Sec. II-C ppm step and the Sec. II-B refresh with
  * every discrete choice frozen).
  * The recording step, amr_hydro_step_adjoint_recorded and
- * amr_refresh_ghosts_adjoint also take a mesh with the dual-energy field (six
- * fields: the sixth field's adjoint passes through the pressure selection,
- * its flux, the work term and the resynchronisation and floors of the
- * update); amr_hydro_step_adjoint (recomputing) returns AMR_E_INVALID for
- * such a mesh.
+ * amr_refresh_ghosts_adjoint, and amr_hydro_step_adjoint (recomputing), also
+ * take a mesh with the dual-energy field (six fields: the sixth field's
+ * adjoint passes through the pressure selection, its flux, the work term and
+ * the resynchronisation and floors of the update).
  *
  * One hydro step (as amr_hydro_step, bitwise the same result) that keeps
  * what its adjoint needs, for reverse-mode differentiation without

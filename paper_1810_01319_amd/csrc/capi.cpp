@@ -173,7 +173,7 @@ int64_t adjoint_face_bytes(const Plan& p) {
 }
 
 int64_t adjoint_scratch(const Plan& p) {
-  const int64_t field = p.nleaf * kFields * int64_t(p.M) * p.M * p.M * 8;
+  const int64_t field = p.nleaf * p.nf * int64_t(p.M) * p.M * p.M * 8;
   return adjoint_face_bytes(p) + 3 * field + 256;
 }
 
@@ -657,12 +657,11 @@ amr_status amr_hydro_step_adjoint(amr_mesh* h, const double* Uin, const double* 
                                   int64_t step_index, void* stream) {
   amr_status rc = check_ready(h, Uin);
   if (rc != AMR_OK) return rc;
-  if (h->plan.nf != kFields) return fail(AMR_E_INVALID, "the adjoint needs a mesh without the dual-energy field");
   if (!dt || !lam || !scratch) return fail(AMR_E_INVALID, "null argument");
   const Plan& p = h->plan;
   if (!adjoint_iters_ok(p)) return fail(AMR_E_INVALID, "adjoint supports riemann_iters <= 8");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t nfield = p.nleaf * kFields * int64_t(p.M) * p.M * p.M;
+  const int64_t nfield = p.nleaf * p.nf * int64_t(p.M) * p.M * p.M;
   unsigned char* sc = static_cast<unsigned char*>(scratch);
   double* gfaces = reinterpret_cast<double*>(sc);
   double* S[3];
