@@ -187,7 +187,7 @@ DevPlan dev_plan_at(const Plan& p, unsigned char* w) {
   P.p2task = reinterpret_cast<const int32_t*>(w + p.off.p2task);
   P.p2wave = reinterpret_cast<const int32_t*>(w + p.off.p2wave);
   P.np2w = int64_t(p.p2wave.size());
-  P.p1_xcd = p.nleaf >= kP1XcdMinLeaves ? 1 : 0;
+  P.p1_large = p.nleaf >= kP1LargeMinLeaves ? 1 : 0;
   P.faceslot = reinterpret_cast<const int32_t*>(w + p.off.faceslot);
   for (int d = 0; d < 3; d++) {
     P.reflux[d] = reinterpret_cast<const RefluxTask*>(w + p.off.reflux[d]);

@@ -35,15 +35,17 @@ __device__ __forceinline__ double level_dx(const InstParams& ip, int N, int l) {
 
 // Phase 1: same-level copies (incl. outflow clamps) and restriction.  On
 // large meshes the workgroups go to the XCDs in contiguous ranges (a leaf's
-// ghost cells and its neighbours' in one L2); on small ones in hardware
-// order, which spreads the leaves of a refined region, and their restriction
-// work, over all XCDs.
+// ghost cells and its neighbours' in one L2) and the ghost cells are written
+// with non-temporal stores (the sweeps read them from HBM either way); on
+// small ones in hardware order, which spreads the leaves of a refined region,
+// and their restriction work, over all XCDs, with ordinary stores.
 template <int N, int NF>
 __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int GC = M * M * M - N * N * N;
-  const int64_t t = int64_t(P.p1_xcd ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool large = P.p1_large != 0;
+  const int64_t t = int64_t(large ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= P.nleaf * GC) return;
   const int s = int(t / GC);
   const int g = int(t - int64_t(s) * GC);
@@ -63,7 +65,10 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
     const int la = px - sb.i * N + G, lb = py - sb.j * N + G, lc = pz - sb.k * N + G;
     const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
-    for (int f = 0; f < NF; f++) dst[f * M3] = src[f * M3];
+    for (int f = 0; f < NF; f++) {
+      if (large) __builtin_nontemporal_store(src[f * M3], dst + f * M3);
+      else dst[f * M3] = src[f * M3];
+    }
   } else {
     // mean of the 8 children, summed x fastest then y then z
     const int qx = 2 * px, qy = 2 * py, qz = 2 * pz;
@@ -76,7 +81,9 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
       const double* q = src + f * M3;
       const double v0 = q[0], v1 = q[1], v2 = q[M], v3 = q[M + 1];
       const double v4 = q[M * M], v5 = q[M * M + 1], v6 = q[M * M + M], v7 = q[M * M + M + 1];
-      dst[f * M3] = (((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7))) * 0.125;
+      const double m = (((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7))) * 0.125;
+      if (large) __builtin_nontemporal_store(m, dst + f * M3);
+      else dst[f * M3] = m;
     }
   }
 }

@@ -31,7 +31,7 @@ struct DevPlan {
   int64_t nleaf, np2, nreflux[3];
   int64_t np2t[3];  // phase-2 tasks per kind (faces, edges, corners)
   int64_t np2w;     // phase-2 waves
-  int32_t p1_xcd;   // phase-1 refresh in XCD-contiguous order (large meshes)
+  int32_t p1_large;  // phase-1 refresh of a large mesh: XCD-contiguous order, non-temporal stores
   int32_t ninst, N;
   int32_t nf;  // fields per cell: kFields, or kFieldsDE with the dual-energy field
 };

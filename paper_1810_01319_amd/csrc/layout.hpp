@@ -22,9 +22,10 @@ constexpr int p2_groups(int N, int K) { return K == 0 ? 2 * (N / 2) * (N / 2) : 
 constexpr int p2_waves(int N, int K) { return (p2_groups(N, K) + 63) / 64; }
 constexpr int kP2SubBits = 3;  // wave-in-task bits of a phase-2 wave entry (at most 8 waves per task)
 // leaves from which the phase-1 refresh takes the XCD-contiguous workgroup
-// order (measured on gfx950: 45.0 -> 40.6 ms at 64,567 leaves of 32^3, but
-// 0.380 -> 0.425 ms at 624)
-constexpr int64_t kP1XcdMinLeaves = 4096;
+// order and writes the ghost cells with non-temporal stores (measured on
+// gfx950, 64,567 leaves of 32^3: order 45.0 -> 40.6 ms, stores 40.7 -> 37.0
+// ms; 624 leaves: 0.380 -> 0.425 and 0.374 -> 0.394 ms)
+constexpr int64_t kP1LargeMinLeaves = 4096;
 
 // Per mesh instance: gas constants in the exact forms the formulas use
 // (computed once on the host in FP64) and the geometry.

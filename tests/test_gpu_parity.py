@@ -107,6 +107,24 @@ def test_refresh_matches_oracle_bitwise(N, levels, seed):
     assert np.array_equal(a, b)
 
 
+def test_refresh_large_mesh_bitwise():
+    """A mesh above the large-mesh threshold of the phase-1 refresh (4,096
+    leaves and more: XCD-contiguous workgroup order, non-temporal ghost
+    stores): 16^3 roots of 8^3, two of them refined (4,110 leaves), every cell
+    bitwise against the oracle."""
+    root = (16, 16, 16)
+    spec = I.MeshSpec(root=root, block_cells=8, max_level=1, refine=[(0, 3, 4, 5), (0, 11, 7, 2)])
+    om, gm, perm = pair(spec)
+    assert gm.nleaf >= 4096
+    say(f"refresh large mesh: {gm.nleaf} leaves of 8^3")
+    rng = np.random.default_rng(17)
+    U = load(om, gm, perm, rng.uniform(0.5, 1.5, (gm.nleaf, 5, 8, 8, 8)))
+    gm.refresh(U)
+    om.refresh()
+    torch.cuda.synchronize()
+    assert np.array_equal(U.cpu().numpy(), om.U[perm])
+
+
 def test_refresh_outflow_uniform_bitwise():
     spec = I.MeshSpec(root=(3, 1, 2), block_cells=8, bc="outflow")
     om, gm, perm = pair(spec)
