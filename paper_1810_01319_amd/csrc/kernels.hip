@@ -39,13 +39,15 @@ __device__ __forceinline__ double level_dx(const InstParams& ip, int N, int l) {
 // with non-temporal stores (the sweeps read them from HBM either way); on
 // small ones in hardware order, which spreads the leaves of a refined region,
 // and their restriction work, over all XCDs, with ordinary stores.
-template <int N, int NF>
+// LARGE: the large-mesh instantiation (the two store kinds must be separate
+// kernels: under a run-time branch the compiler merges them into one plain
+// store).
+template <int N, int NF, bool LARGE>
 __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, DevPlan P) {
   constexpr int M = N + 2 * G;
   constexpr int64_t M3 = int64_t(M) * M * M;
   constexpr int GC = M * M * M - N * N * N;
-  const bool large = P.p1_large != 0;
-  const int64_t t = int64_t(large ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = int64_t(LARGE ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= P.nleaf * GC) return;
   const int s = int(t / GC);
   const int g = int(t - int64_t(s) * GC);
@@ -66,7 +68,7 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
     const double* src = U + int64_t(e.id) * NF * M3 + (int64_t(lc) * M + lb) * M + la;
 #pragma unroll
     for (int f = 0; f < NF; f++) {
-      if (large) __builtin_nontemporal_store(src[f * M3], dst + f * M3);
+      if constexpr (LARGE) __builtin_nontemporal_store(src[f * M3], dst + f * M3);
       else dst[f * M3] = src[f * M3];
     }
   } else {
@@ -82,7 +84,7 @@ __global__ void __launch_bounds__(256) refresh_phase1(double* __restrict__ U, De
       const double v0 = q[0], v1 = q[1], v2 = q[M], v3 = q[M + 1];
       const double v4 = q[M * M], v5 = q[M * M + 1], v6 = q[M * M + M], v7 = q[M * M + M + 1];
       const double m = (((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7))) * 0.125;
-      if (large) __builtin_nontemporal_store(m, dst + f * M3);
+      if constexpr (LARGE) __builtin_nontemporal_store(m, dst + f * M3);
       else dst[f * M3] = m;
     }
   }
@@ -938,8 +940,11 @@ template <int N, int NF>
 hipError_t refresh_nf(const DevPlan& P, double* U, const LaunchCfg& L, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
-  if (P.nleaf > 0)
-    hipLaunchKernelGGL((refresh_phase1<N, NF>), dim3(grid_for(P.nleaf * GC, L.refresh_block)), dim3(L.refresh_block), 0, st, U, P);
+  if (P.nleaf > 0) {
+    const dim3 g(grid_for(P.nleaf * GC, L.refresh_block)), b(L.refresh_block);
+    if (P.p1_large) hipLaunchKernelGGL((refresh_phase1<N, NF, true>), g, b, 0, st, U, P);
+    else hipLaunchKernelGGL((refresh_phase1<N, NF, false>), g, b, 0, st, U, P);
+  }
   if (P.np2 > 0) {
     const hipError_t e = launch_phase2<N, NF, false>(P, U, L.refresh_block, st);
     if (e != hipSuccess) return e;
@@ -1082,7 +1087,10 @@ template <int N>
 hipError_t refresh_scalar_n(const DevPlan& P, double* x, hipStream_t st) {
   constexpr int M = N + 2 * G;
   constexpr int64_t GC = int64_t(M) * M * M - int64_t(N) * N * N;
-  if (P.nleaf > 0) hipLaunchKernelGGL((refresh_phase1<N, 1>), dim3(grid_for(P.nleaf * GC, 256)), dim3(256), 0, st, x, P);
+  if (P.nleaf > 0 && P.p1_large)
+    hipLaunchKernelGGL((refresh_phase1<N, 1, true>), dim3(grid_for(P.nleaf * GC, 256)), dim3(256), 0, st, x, P);
+  else if (P.nleaf > 0)
+    hipLaunchKernelGGL((refresh_phase1<N, 1, false>), dim3(grid_for(P.nleaf * GC, 256)), dim3(256), 0, st, x, P);
   if (P.np2 > 0) {
     const hipError_t e = launch_phase2<N, 1, true>(P, x, 256, st);
     if (e != hipSuccess) return e;
